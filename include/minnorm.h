@@ -1,0 +1,186 @@
+/*
+ * minnorm.h -- C ABI of the MI355X (gfx950) randomized minimal-norm solver.
+ *
+ * Problem (Section 1; Section 4's setting): A is a full-rank m x n matrix with
+ * m < n, b an m-vector and eps in (0, 1).  The solver returns x with
+ * ||x - p|| <= eps ||p||, p being the minimal-Euclidean-norm solution of
+ * A p = b.  The method is the paper's five steps with Steps 2-3 folded into
+ * Step 4 (A c = b by Lemma 5.1, so Step 4's normal equations are A A* y = b):
+ *   Step 1  S = T A*, T = S F D the l x N subsampled randomized Fourier
+ *           transform (eqs. SRFT, SRFT2, randmat)          -> srft_sketch
+ *   Step 2  Householder QR S = Q_S R, R kept                 -> build_preconditioner
+ *   Step 4  preconditioned CG on A A* y = b, preconditioner R* R, stopped at
+ *           Step 4's relative precision eps^2 l / (alpha N)  -> minnorm_solve
+ *   Step 5  x = A* y (eq. output)                            -> minnorm_solve
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers (memory of the GPU current when
+ *     the handle was created), except where a comment says "host".  The
+ *     caller owns every buffer; the library never frees or keeps a caller
+ *     pointer after the call returns.
+ *   - Element types are selected by `dtype` (MN_C128 complex double,
+ *     MN_C64 complex float, MN_F64 double, MN_F32 float).  Complex numbers
+ *     are stored interleaved (re, im), as in C99 / C++ / numpy / torch.
+ *   - A is row-major: entry (i, j) at A[i*lda + j], lda >= n.  Vectors are
+ *     contiguous.  S and R are column-major: S(k, i) at S[k + i*lds].
+ *   - N is the transform length: a power of two with n <= N <= 2^22.  Rows of
+ *     A are zero-padded from n to N; this does not change the minimal-norm
+ *     solution (its last N - n entries are zero).
+ *   - d holds the N diagonal entries of D in FP64 whatever dtype is: complex
+ *     unit-modulus phases (complex128) for complex dtypes, +-1 (float64) for
+ *     real dtypes, where the transform F is the orthonormal discrete Hartley
+ *     transform cas(2 pi j k / N) / sqrt(N) (the paper's real analogue).
+ *     idx holds the l subsampled rows as int32: strictly increasing, in [0, N).
+ *     The library draws no random numbers of its own.
+ *   - Work is enqueued on the handle's stream.  Entry points that report a
+ *     data-dependent status (rank deficiency, convergence, invalid idx)
+ *     synchronise that stream before returning.
+ *
+ * Return values
+ *    0  success
+ *   -k  argument k (1-based position in the call) is invalid; nothing was
+ *       enqueued.  For idx, validity is checked on the device: -k is then
+ *       returned after a stream synchronisation, and no output is written.
+ *   +1  MN_RANK_DEFICIENT: the sketch S is numerically rank-deficient
+ *       (Remark 4.1): min_j |R_jj| <= tau max_i |R_ii|, tau = 16 sqrt(l) u
+ *       for an FP64 sketch and 4 u for an FP32 one (u the unit roundoff).
+ *       Redraw (d, idx) and call again; a persistent +1 means A is not full
+ *       rank.
+ *   +2  MN_NOT_CONVERGED: the iteration cap was reached; x holds the last
+ *       iterate and info the certificate reached.
+ *   +3  MN_HIP_ERROR: a HIP runtime call failed (mn_last_hip_error()).
+ *   +4  MN_NONFINITE: a non-finite value appeared (input or intermediate).
+ */
+#ifndef MINNORM_H
+#define MINNORM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MN_OK 0
+#define MN_RANK_DEFICIENT 1
+#define MN_NOT_CONVERGED 2
+#define MN_HIP_ERROR 3
+#define MN_NONFINITE 4
+
+enum mn_dtype { MN_C128 = 0, MN_C64 = 1, MN_F64 = 2, MN_F32 = 3 };
+
+typedef struct mn_handle_s* mn_handle;
+
+/* Options of minnorm_solve / minnorm_solve_batched.  A NULL pointer or a zero
+ * field selects the default given in brackets. */
+typedef struct {
+  double alpha;          /* alpha of Step 4's precision eps^2 l/(alpha N) [4]     */
+  int32_t stop_rule;     /* 0: the paper's rule: f(y) - f* <= eps^2 l/(alpha N) f*,
+                            certified from the CG scalars (the certificate rule
+                            is used when l = N, where f* = 0);
+                            1: the certificate rule ||x - p|| <= eps ||p||     [0] */
+  int32_t max_iter;      /* cap on CG iterations (per refinement step)      [1000] */
+  int32_t max_refine;    /* mixed precision: cap on FP64 refinement steps     [40] */
+  int32_t check_every;   /* iterations enqueued between host reads of the
+                            device stop flag                                  [8] */
+  int32_t inner_digits;  /* mixed precision: decimal digits each low-precision
+                            inner solve gains                                 [4] */
+  int32_t reserved[3];
+} mn_opts;
+
+/* Per-solve report (host struct written by the library). */
+typedef struct {
+  int32_t status;        /* return value of this system                         */
+  int32_t iters;         /* CG iterations, summed over refinement steps         */
+  int32_t refine_steps;  /* FP64 residual evaluations (0 in plain FP64 mode)    */
+  int32_t nrhs_done;     /* right-hand sides that met their stopping rule       */
+  double cert_rel;       /* sqrt(rho / xi): the certificate of ||x-p|| / ||x||  */
+  double rho0, rho, xi;  /* CG scalars at exit (see minnorm_solve)              */
+  float stage_ms[8];     /* sketch, qr, cg, final product, refine, -, -, total  */
+} mn_info;
+
+/* Handle: owns the stream binding and a device workspace reused across calls.
+ * stream is a hipStream_t (NULL = the default stream).  Returns 0 or +3. */
+int mn_create(mn_handle* h, void* stream);
+int mn_destroy(mn_handle h);
+int mn_set_stream(mn_handle h, void* stream);
+const char* mn_status_string(int status);
+const char* mn_last_hip_error(void);
+/* Bytes of device workspace the handle currently holds. */
+int64_t mn_workspace_bytes(mn_handle h);
+
+/* Step 1, eq. (randmat): S = T A*, T = S F D of size l x N (eqs. SRFT,
+ * SRFT2, with H = I), applied to every row of A:
+ *   S(k, i) = (F (d o conj(a_i, zero-padded to N)))[idx[k]],  k < l, i < m,
+ * F the unitary DFT of eq. (DFT) (real dtypes: the orthonormal Hartley
+ * transform, no conjugation).
+ *   A  [m x n, dtype, row-major, lda]      read
+ *   d  [N, complex128 or float64]          read
+ *   idx[l, int32]                          read
+ *   S  [l x m, dtype, column-major, lds]   written
+ * Errors: -3/-4 m, n < 1; -6 lda < n; -7 N not a power of two, N < n or
+ * N > 2^22; -8 l < 1 or l > N; -12 lds < l; -5/-9/-10/-11 NULL pointer;
+ * -10 (after a sync) idx not strictly increasing or out of [0, N). */
+int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                int64_t N, int64_t l, const void* d, const int32_t* idx,
+                void* S, int64_t lds);
+
+/* Step 2's factorisation: Householder QR of the l x m sketch, S = Q_S R
+ * (tiled, blocked Householder reflections; Q_S is not formed).
+ *   S [l x m, dtype, column-major, lds]  read
+ *   R [m x m, dtype, column-major, ldr]  written: upper triangle = R with a
+ *                                        real diagonal, strict lower = 0
+ * R is unique up to a diagonal unitary factor.  Returns +1 when S is
+ * numerically rank-deficient (Remark 4.1) -- R is still written.
+ * Errors: -3 l < m; -4 m < 1; -5 NULL; -6 lds < l; -7 NULL; -8 ldr < m. */
+int build_preconditioner(mn_handle h, int dtype, int64_t l, int64_t m,
+                         const void* S, int64_t lds, void* R, int64_t ldr);
+
+/* The whole method: x with ||x_j - p_j|| <= eps ||p_j|| for each of nrhs
+ * right-hand sides b_j (Theorem 5.4; Step 4 is preconditioned CG on
+ * A A* y = b stopped by opts->stop_rule; Step 5 x = A* y).
+ *   A    [m x n, dtype, row-major, lda]  the problem matrix, read
+ *   A_lo [m x n, row-major, lda_lo] optional copy of A in the single-precision
+ *        type of the same kind (MN_C64 for MN_C128, MN_F32 for MN_F64), or
+ *        NULL.  Given, the sketch, the QR and the bulk CG run on A_lo in FP32
+ *        and FP64 iterative refinement on A (residual b - A A* y) restores the
+ *        accuracy.  With dtype MN_C64 / MN_F32 the single-precision A is the
+ *        problem itself: the bulk runs on it and the refinement residuals
+ *        promote it exactly to FP64; A_lo must then be NULL.
+ *   b    [nrhs x m, FP64 (complex128 / float64), b_j at b + j*ldb]   read
+ *   N, l, d, idx: the SRFT's length and random quantities as in srft_sketch
+ *        (m < l <= N; l = min(4m, N) is the paper's choice).
+ *   x    [nrhs x n, FP64 (complex128 / float64), x_j at x + j*ldx]   written
+ *   info optional host struct.
+ * Errors: -2 dtype; -3 m < 1 or m >= n; -4 n; -5 A; -6 lda; -7 A_lo with a
+ * single-precision dtype; -8 lda_lo; -9 b; -10 ldb < m; -11 nrhs < 1 or > 64;
+ * -12 eps not in (0,1); -13 N; -14 l <= m or l > N; -15 d; -16 idx;
+ * -17 opts field out of range; -18 x; -19 ldx < n. */
+int minnorm_solve(mn_handle h, int dtype, int64_t m, int64_t n,
+                  const void* A, int64_t lda, const void* A_lo, int64_t lda_lo,
+                  const void* b, int64_t ldb, int64_t nrhs, double eps,
+                  int64_t N, int64_t l, const void* d, const int32_t* idx,
+                  const mn_opts* opts, void* x, int64_t ldx, mn_info* info);
+
+/* Many independent systems of uneven sizes in one call.  Every array argument
+ * below is a HOST array of `batch` entries; the pointers inside are device
+ * pointers with the meaning of minnorm_solve (A_lo may be NULL, or hold NULL
+ * entries).  b_i has m[i] entries, x_i has n[i] entries; lda[i] >= n[i].
+ * info, if not NULL, is a host array of `batch` reports.  Returns the largest
+ * status over the systems (each system's own status is in info[i].status).
+ * Errors: -3 batch < 1; -4..-16 the matching array is NULL or an entry of it
+ * is invalid as in minnorm_solve. */
+int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch,
+                          const int64_t* m, const int64_t* n,
+                          const void* const* A, const int64_t* lda,
+                          const void* const* A_lo,
+                          const void* const* b, const double* eps,
+                          const int64_t* N, const int64_t* l,
+                          const void* const* d, const int32_t* const* idx,
+                          const mn_opts* opts, void* const* x, mn_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MINNORM_H */

@@ -1,0 +1,202 @@
+"""Python entry points with the C ABI's names, taking torch tensors.
+
+torch supplies device memory and the current stream; every step of the
+method runs in the HIP library.  Layouts follow include/minnorm.h:
+A (m, n) row-major; S and R are returned as transposed views of row-major
+buffers, i.e. column-major l x m and m x m arrays.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_DT = {torch.complex128: L.MN_C128, torch.complex64: L.MN_C64,
+       torch.float64: L.MN_F64, torch.float32: L.MN_F32}
+_WIDE = {L.MN_C128: torch.complex128, L.MN_C64: torch.complex128,
+         L.MN_F64: torch.float64, L.MN_F32: torch.float64}
+_SINGLE_OF = {L.MN_C128: torch.complex64, L.MN_F64: torch.float32}
+
+
+class MinnormError(RuntimeError):
+    def __init__(self, fn, status):
+        lib = L.load()
+        msg = lib.mn_status_string(int(status)).decode()
+        if status == 3:
+            msg += ": " + lib.mn_last_hip_error().decode()
+        super().__init__(f"{fn} returned {status}: {msg}")
+        self.status = int(status)
+
+
+_handles = {}
+
+
+def _handle(device: torch.device):
+    lib = L.load()
+    dev = device.index if device.index is not None else torch.cuda.current_device()
+    h = _handles.get(dev)
+    if h is None:
+        with torch.cuda.device(dev):
+            hv = C.c_void_p()
+            st = lib.mn_create(C.byref(hv), C.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+            if st != 0:
+                raise MinnormError("mn_create", st)
+            h = hv
+            _handles[dev] = h
+    lib.mn_set_stream(h, C.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+    return h
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(None)
+
+
+def _check_matrix(A, name="A"):
+    if not A.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError(f"{name} must be 2-D with unit column stride (row-major)")
+    if A.dtype not in _DT:
+        raise ValueError(f"{name} dtype {A.dtype} not supported")
+    return _DT[A.dtype]
+
+
+def _d_tensor(d, dtype_code, device):
+    want = torch.complex128 if dtype_code in (L.MN_C128, L.MN_C64) else torch.float64
+    return torch.as_tensor(d, device=device).to(want).contiguous()
+
+
+def _idx_tensor(idx, device):
+    return torch.as_tensor(idx, device=device).to(torch.int32).contiguous()
+
+
+def srft_sketch(A, d, idx, N: int):
+    """S = T A* (Step 1, eq. randmat); returns an (l, m) column-major view."""
+    code = _check_matrix(A)
+    m, n = A.shape
+    dt = _d_tensor(d, code, A.device)
+    it = _idx_tensor(idx, A.device)
+    l = it.numel()
+    St = torch.empty((m, l), dtype=A.dtype, device=A.device)
+    st = L.load().srft_sketch(_handle(A.device), code, m, n, _ptr(A), A.stride(0), int(N), l,
+                              _ptr(dt), _ptr(it), _ptr(St), l)
+    if st != 0:
+        raise MinnormError("srft_sketch", st)
+    return St.t()
+
+
+def build_preconditioner(S, allow_rank_deficient: bool = False):
+    """R of the Householder QR of the (l, m) sketch; returns an (m, m) column-major view.
+
+    S must be column-major (e.g. the view srft_sketch returns).
+    """
+    l, m = S.shape
+    if S.stride(0) != 1:
+        raise ValueError("S must be column-major (stride(0) == 1)")
+    code = _DT[S.dtype]
+    Rt = torch.empty((m, m), dtype=S.dtype, device=S.device)
+    st = L.load().build_preconditioner(_handle(S.device), code, l, m, _ptr(S), S.stride(1), _ptr(Rt), m)
+    if st != 0 and not (st == 1 and allow_rank_deficient):
+        raise MinnormError("build_preconditioner", st)
+    return Rt.t()
+
+
+@dataclass
+class SolveOptions:
+    alpha: float = 4.0
+    stop_rule: int = 0
+    max_iter: int = 1000
+    max_refine: int = 40
+    check_every: int = 8
+    inner_digits: int = 4
+
+    def to_c(self):
+        o = L.MnOpts()
+        o.alpha = self.alpha
+        o.stop_rule = self.stop_rule
+        o.max_iter = self.max_iter
+        o.max_refine = self.max_refine
+        o.check_every = self.check_every
+        o.inner_digits = self.inner_digits
+        return o
+
+
+def minnorm_solve(A, b, eps: float, d, idx, N: int, A_lo=None, opts: SolveOptions | None = None,
+                  x=None, raise_on_status: bool = True):
+    """x approximating the minimal-norm solution of A x = b to relative precision eps.
+
+    b: (m,) or (nrhs, m) FP64 (complex128 / float64).  Returns (x, info).
+    """
+    code = _check_matrix(A)
+    m, n = A.shape
+    wide = _WIDE[code]
+    b2 = b.reshape(1, -1) if b.dim() == 1 else b
+    if b2.dtype != wide or not b2.is_cuda or b2.stride(1) != 1 or b2.shape[1] != m:
+        raise ValueError(f"b must be a device {wide} tensor with m={m} entries per row")
+    nrhs = b2.shape[0]
+    if A_lo is not None:
+        lo_code = _check_matrix(A_lo, "A_lo")
+        if A_lo.shape != A.shape or A_lo.dtype != _SINGLE_OF.get(code):
+            raise ValueError("A_lo must be the single-precision copy of A")
+    dt = _d_tensor(d, code, A.device)
+    it = _idx_tensor(idx, A.device)
+    l = it.numel()
+    if x is None:
+        x = torch.empty((nrhs, n), dtype=wide, device=A.device)
+    info = L.MnInfo()
+    o = (opts or SolveOptions()).to_c()
+    st = L.load().minnorm_solve(_handle(A.device), code, m, n, _ptr(A), A.stride(0), _ptr(A_lo),
+                                A_lo.stride(0) if A_lo is not None else 0, _ptr(b2), b2.stride(0), nrhs,
+                                float(eps), int(N), l, _ptr(dt), _ptr(it), C.byref(o), _ptr(x), x.stride(0),
+                                C.byref(info))
+    if st != 0 and raise_on_status:
+        raise MinnormError("minnorm_solve", st)
+    out = x[0] if b.dim() == 1 else x
+    return out, info.as_dict()
+
+
+def minnorm_solve_batched(As, bs, eps, ds, idxs, Ns, A_los=None, opts: SolveOptions | None = None,
+                          raise_on_status: bool = True):
+    """Independent systems of uneven sizes in one call; returns (xs, infos)."""
+    batch = len(As)
+    code = _check_matrix(As[0])
+    wide = _WIDE[code]
+    dev = As[0].device
+    xs, dts, its = [], [], []
+    for A in As:
+        if _check_matrix(A) != code:
+            raise ValueError("all systems must share one dtype")
+        xs.append(torch.empty(A.shape[1], dtype=wide, device=dev))
+    for d, idx in zip(ds, idxs):
+        dts.append(_d_tensor(d, code, dev))
+        its.append(_idx_tensor(idx, dev))
+    I64 = C.c_int64 * batch
+    PP = C.c_void_p * batch
+    m = I64(*[A.shape[0] for A in As])
+    n = I64(*[A.shape[1] for A in As])
+    lda = I64(*[A.stride(0) for A in As])
+    Ap = PP(*[A.data_ptr() for A in As])
+    Alo = PP(*[a.data_ptr() for a in A_los]) if A_los is not None else None
+    bp = PP(*[b.data_ptr() for b in bs])
+    epsa = (C.c_double * batch)(*([float(eps)] * batch if isinstance(eps, (int, float)) else list(eps)))
+    Na = I64(*[int(v) for v in Ns])
+    la = I64(*[t.numel() for t in its])
+    dp = PP(*[t.data_ptr() for t in dts])
+    ip = PP(*[t.data_ptr() for t in its])
+    xp = PP(*[t.data_ptr() for t in xs])
+    infos = (L.MnInfo * batch)()
+    o = (opts or SolveOptions()).to_c()
+    st = L.load().minnorm_solve_batched(_handle(dev), code, batch, m, n, Ap, lda, Alo, bp, epsa, Na, la, dp, ip,
+                                        C.byref(o), xp, infos)
+    if st != 0 and raise_on_status:
+        raise MinnormError("minnorm_solve_batched", st)
+    return xs, [i.as_dict() for i in infos]
+
+
+def workspace_bytes(device=None) -> int:
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    return int(L.load().mn_workspace_bytes(_handle(dev)))

@@ -1,0 +1,664 @@
+// C ABI of the solver (declared in include/minnorm.h): argument checks,
+// device workspace, and the host drivers that enqueue the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/minnorm.h"
+#include "kernels.hpp"
+
+using namespace mn;
+
+namespace {
+
+thread_local std::string g_last_hip_error;
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Twiddle {
+  int64_t N = 0;
+  void* p = nullptr;
+};
+
+}  // namespace
+
+struct mn_handle_s {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::map<std::string, Buf> bufs;
+  Twiddle tw[2];  // [0] complex double, [1] complex float
+  PcgState* host_state = nullptr;  // pinned
+  int32_t* host_flag = nullptr;    // pinned
+  double* host_diag = nullptr;     // pinned, 4 doubles
+  hipEvent_t ev[9] = {};
+  bool events = false;
+};
+
+namespace {
+
+struct HipFail {
+  hipError_t e;
+};
+
+inline void ck(hipError_t e) {
+  if (e != hipSuccess) throw HipFail{e};
+}
+
+void* ws(mn_handle h, const char* name, size_t bytes) {
+  Buf& b = h->bufs[name];
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return b.p;
+  if (b.p) {
+    ck(hipStreamSynchronize(h->stream));
+    ck(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  ck(hipMalloc(&b.p, bytes));
+  b.bytes = bytes;
+  return b.p;
+}
+
+bool is_pow2(int64_t N) { return N > 0 && (N & (N - 1)) == 0; }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+bool is_complex(int dtype) { return dtype == MN_C128 || dtype == MN_C64; }
+bool is_single(int dtype) { return dtype == MN_C64 || dtype == MN_F32; }
+int compute_cplx_dtype(int dtype) { return is_single(dtype) ? 1 : 0; }  // twiddle table slot
+
+// W_N^k = exp(-2 pi i k / N), k < N, computed in long double and rounded.
+const void* twiddles(mn_handle h, int64_t N, bool single) {
+  Twiddle& t = h->tw[single ? 1 : 0];
+  if (t.N == N && t.p) return t.p;
+  if (t.p) {
+    ck(hipStreamSynchronize(h->stream));
+    ck(hipFree(t.p));
+    t.p = nullptr;
+    t.N = 0;
+  }
+  const size_t es = single ? 8 : 16;
+  std::vector<unsigned char> host((size_t)N * es);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int64_t k = 0; k < N; ++k) {
+    const long double a = two_pi * (long double)k / (long double)N;
+    const long double c = cosl(a), s = -sinl(a);
+    if (single) {
+      float v[2] = {(float)c, (float)s};
+      memcpy(&host[(size_t)k * es], v, es);
+    } else {
+      double v[2] = {(double)c, (double)s};
+      memcpy(&host[(size_t)k * es], v, es);
+    }
+  }
+  ck(hipMalloc(&t.p, host.size()));
+  ck(hipMemcpy(t.p, host.data(), host.size(), hipMemcpyHostToDevice));
+  t.N = N;
+  return t.p;
+}
+
+int fail_hip(hipError_t e) {
+  g_last_hip_error = hipGetErrorString(e);
+  return MN_HIP_ERROR;
+}
+
+void ev_record(mn_handle h, int i) {
+  if (h->events) (void)hipEventRecord(h->ev[i], h->stream);
+}
+
+// ----------------------------------------------------------------------------
+// Step 1: sketch of the rows of A (dtype) into S (l x m, lds).  idx must
+// already be validated into the inverse map `inv`.
+void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, int64_t N, int64_t l,
+                const void* d, const int32_t* idx, const int32_t* inv, void* S, int64_t lds) {
+  const bool single = is_single(dtype);
+  const int64_t ces = single ? 8 : 16;
+  SketchArgs a{};
+  a.A = A;
+  a.lda = lda;
+  a.m = m;
+  a.n = n;
+  a.N = N;
+  a.l = l;
+  a.d = d;
+  a.idx = idx;
+  a.inv = inv;
+  a.S = S;
+  a.lds = lds;
+  a.twiddle = twiddles(h, N, single);
+  if (N > kFftMaxLds) {
+    // rows per four-step chunk: intermediate of about 64 MB, so it can stay
+    // in the 256 MB last-level cache between the two passes
+    int64_t chunk = (int64_t)(64ll << 20) / (N * ces);
+    if (chunk < 1) chunk = 1;
+    if (chunk > m) chunk = m;
+    a.chunk_rows = chunk;
+    a.work = ws(h, "fft_y", (size_t)(chunk * N * ces));
+  }
+  ck(launch_sketch(dtype, a, h->stream));
+}
+
+// Validate idx on the device and build the inverse subsample map.
+bool prepare_idx(mn_handle h, const int32_t* idx, int64_t l, int64_t N, int32_t** inv_out) {
+  int32_t* inv = (int32_t*)ws(h, "inv", (size_t)N * 4);
+  int32_t* bad = (int32_t*)ws(h, "bad", 16);
+  ck(launch_inverse_map(idx, l, N, inv, bad, h->stream));
+  ck(hipMemcpyAsync(h->host_flag, bad, 4, hipMemcpyDeviceToHost, h->stream));
+  ck(hipStreamSynchronize(h->stream));
+  *inv_out = inv;
+  return *h->host_flag == 0;
+}
+
+// Step 2's factorisation; returns 0 or MN_RANK_DEFICIENT / MN_NONFINITE.
+int run_qr(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t lds, void* R, int64_t ldr) {
+  QrArgs a{};
+  a.S = S;
+  a.lds = lds;
+  a.l = l;
+  a.m = m;
+  a.R = R;
+  a.ldr = ldr;
+  a.work = ws(h, "qr", (size_t)qr_work_bytes(dtype, l, m));
+  a.diag_out = (double*)ws(h, "qr_diag", 64);
+  ck(launch_qr(dtype, a, h->stream));
+  ck(hipMemcpyAsync(h->host_diag, a.diag_out, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  ck(hipStreamSynchronize(h->stream));
+  const double mx = h->host_diag[0], mn_ = h->host_diag[1], nonfin = h->host_diag[2];
+  if (nonfin != 0.0 || !std::isfinite(mx)) return MN_NONFINITE;
+  // numerical rank test on the pivots: min |R_ii| >= sigma_min(R) and
+  // max |R_ii| <= sigma_max(R), so a tiny ratio means a (nearly) singular
+  // sketch.  FP32 sketches of ill-conditioned A legitimately reach ratios
+  // near 1e-6, hence the tighter single-precision threshold.
+  const double tau = is_single(dtype) ? 4.0 * 5.96e-8 : 16.0 * std::sqrt((double)l) * 1.11e-16;
+  if (!(mn_ > tau * mx)) return MN_RANK_DEFICIENT;
+  return MN_OK;
+}
+
+int64_t wide_size(int dtype) { return is_complex(dtype) ? 16 : 8; }
+
+struct SolveCtx {
+  mn_handle h;
+  int dtype;      // problem dtype (A)
+  int bulk;       // dtype of the matrix the CG bulk runs on
+  bool mixed;     // FP64 refinement around a single-precision bulk
+  const void* A;  // problem matrix
+  int64_t lda;
+  const void* Ab;  // bulk matrix
+  int64_t ldab;
+  int64_t m, n, N, l;
+  double eps;
+  mn_opts o;
+  void* R;  // m x m, bulk dtype
+  void* X;  // inverted diagonal blocks, FP64
+};
+
+void init_state(mn_handle h, PcgState* dst, const SolveCtx& c, int rule, double eps, int max_iter) {
+  PcgState& s = *h->host_state;
+  memset(&s, 0, sizeof(s));
+  s.eps = eps;
+  s.alpha = c.o.alpha;
+  s.l = (double)c.l;
+  s.N = (double)c.N;
+  s.eps_outer = c.eps;
+  s.rule = rule;
+  s.max_iter = max_iter;
+  s.max_refine = c.o.max_refine;
+  ck(hipMemcpyAsync(dst, &s, sizeof(PcgState), hipMemcpyHostToDevice, h->stream));
+  // the staging struct is reused: wait until the copy has left it
+  ck(hipStreamSynchronize(h->stream));
+}
+
+void read_state(mn_handle h, PcgState* src) {
+  ck(hipMemcpyAsync(h->host_state, src, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
+  ck(hipStreamSynchronize(h->stream));
+}
+
+// CG iterations until the device flag is set (checked every check_every).
+void cg_loop(const SolveCtx& c, const PcgVecs& v, void* w, void* part, void* qpart, int max_iter) {
+  mn_handle h = c.h;
+  const int32_t* flag = &v.state->done;
+  int enqueued = 0;
+  while (true) {
+    for (int k = 0; k < c.o.check_every; ++k) {
+      AdjArgs aa{};
+      aa.A = c.Ab;
+      aa.lda = c.ldab;
+      aa.m = c.m;
+      aa.n = c.n;
+      aa.u = v.p;
+      aa.w = w;
+      aa.part = part;
+      aa.flag = flag;
+      ck(launch_gemv_adj(c.bulk, false, aa, h->stream));
+      FwdArgs fa{};
+      fa.A = c.Ab;
+      fa.lda = c.ldab;
+      fa.m = c.m;
+      fa.n = c.n;
+      fa.w = w;
+      fa.qpart = qpart;
+      fa.flag = flag;
+      int chunks = 1;
+      fa.chunks_out = &chunks;
+      ck(launch_gemv_fwd(c.bulk, false, fa, h->stream));
+      ck(launch_pcg_tail(c.bulk, v, qpart, chunks, h->stream));
+    }
+    enqueued += c.o.check_every;
+    read_state(h, v.state);
+    if (h->host_state->done) break;
+    if (enqueued > max_iter + 2 * c.o.check_every) break;  // cannot happen: the tail caps iterations
+  }
+}
+
+// One right-hand side; b and x FP64 device vectors.  Returns a status.
+int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
+  mn_handle h = c.h;
+  const int64_t W = wide_size(c.dtype);
+  const int64_t m = c.m, n = c.n;
+  PcgState* st = (PcgState*)ws(h, "state", sizeof(PcgState));
+  PcgVecs v{};
+  v.R = c.R;
+  v.ldr = m;
+  v.m = m;
+  v.X = c.X;
+  v.y = ws(h, "y", m * W);
+  v.r = ws(h, "r", m * W);
+  v.p = ws(h, "p", m * W);
+  v.z = ws(h, "z", m * W);
+  v.s = ws(h, "s", m * W);
+  v.q = ws(h, "q", m * W);
+  v.tv = ws(h, "tv", m * W);
+  v.state = st;
+  const int64_t bes = is_single(c.bulk) ? W / 2 : W;  // bulk compute element size
+  void* w = ws(h, "w", (size_t)(n * bes + 64));
+  void* part = ws(h, "adj_part", (size_t)(adj_part_elems(m, n) * W + 64));
+  void* qpart = ws(h, "qpart", (size_t)(kMaxChunks * m * W));
+  int status = MN_OK;
+  ev_record(h, 3);
+  if (!c.mixed) {
+    v.b = b;
+    init_state(h, st, c, c.o.stop_rule, c.eps, c.o.max_iter);
+    ck(launch_pcg_start(c.bulk, v, nullptr, 0, nullptr, h->stream));
+    cg_loop(c, v, w, part, qpart, c.o.max_iter);
+    ev_record(h, 4);
+    // Step 5: x = A* y
+    AdjArgs aa{};
+    aa.A = c.A;
+    aa.lda = c.lda;
+    aa.m = m;
+    aa.n = n;
+    aa.u = v.y;
+    aa.w = x;
+    aa.part = part;
+    ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
+    ev_record(h, 5);
+    read_state(h, st);
+  } else {
+    // FP64 refinement: r = b - A A* y_outer in FP64, inner CG in single
+    // precision on the bulk copy, y_outer += dy, until the FP64 certificate
+    // meets eps.
+    void* y_outer = ws(h, "y_outer", m * W);
+    void* w64 = ws(h, "w64", (size_t)(n * W + 64));
+    ck(hipMemsetAsync(y_outer, 0, m * W, h->stream));
+    v.b = b;
+    const double inner_eps = std::pow(10.0, -(double)c.o.inner_digits);
+    init_state(h, st, c, 2, inner_eps, c.o.max_iter);
+    for (int outer = 0; outer <= c.o.max_refine + 1; ++outer) {
+      AdjArgs aa{};
+      aa.A = c.A;
+      aa.lda = c.lda;
+      aa.m = m;
+      aa.n = n;
+      aa.u = y_outer;
+      aa.w = w64;
+      aa.part = part;
+      ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
+      FwdArgs fa{};
+      fa.A = c.A;
+      fa.lda = c.lda;
+      fa.m = m;
+      fa.n = n;
+      fa.w = w64;
+      fa.qpart = qpart;
+      int chunks = 1;
+      fa.chunks_out = &chunks;
+      ck(launch_gemv_fwd(c.dtype, true, fa, h->stream));
+      ck(launch_pcg_start(c.bulk, v, qpart, chunks, y_outer, h->stream));
+      read_state(h, st);
+      if (h->host_state->outer_done) break;
+      cg_loop(c, v, w, part, qpart, c.o.max_iter);
+      ck(launch_refine_update(is_complex(c.dtype), y_outer, v.y, m, st, h->stream));
+    }
+    ev_record(h, 4);
+    AdjArgs aa{};
+    aa.A = c.A;
+    aa.lda = c.lda;
+    aa.m = m;
+    aa.n = n;
+    aa.u = y_outer;
+    aa.w = x;
+    aa.part = part;
+    ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
+    ev_record(h, 5);
+    read_state(h, st);
+  }
+  const PcgState& s = *h->host_state;
+  status = s.status;
+  if (info) {
+    info->iters += s.iter_total;
+    info->refine_steps += s.refine_steps;
+    if (status == MN_OK) info->nrhs_done += 1;
+    const double rho = c.mixed ? s.outer_rho : s.rho;
+    const double xi = c.mixed ? s.outer_xi : s.xi;
+    const double cert = xi > 0 ? std::sqrt(rho / xi) : 0.0;
+    if (cert > info->cert_rel) info->cert_rel = cert;
+    info->rho0 = s.rho0;
+    info->rho = rho;
+    info->xi = xi;
+  }
+  return status;
+}
+
+mn_opts resolve_opts(const mn_opts* o) {
+  mn_opts r{};
+  if (o) r = *o;
+  if (r.alpha == 0.0) r.alpha = 4.0;
+  if (r.max_iter == 0) r.max_iter = 1000;
+  if (r.max_refine == 0) r.max_refine = 40;
+  if (r.check_every == 0) r.check_every = 8;
+  if (r.inner_digits == 0) r.inner_digits = 4;
+  return r;
+}
+
+bool opts_valid(const mn_opts& o) {
+  return o.alpha > 1.0 && (o.stop_rule == 0 || o.stop_rule == 1) && o.max_iter > 0 && o.max_refine > 0 &&
+         o.check_every > 0 && o.check_every <= 1024 && o.inner_digits > 0 && o.inner_digits <= 12;
+}
+
+int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const void* A_lo,
+               int64_t lda_lo, const void* b, int64_t ldb, int64_t nrhs, double eps, int64_t N, int64_t l,
+               const void* d, const int32_t* idx, const mn_opts& o, void* x, int64_t ldx, mn_info* info) {
+  SolveCtx c{};
+  c.h = h;
+  c.dtype = dtype;
+  c.A = A;
+  c.lda = lda;
+  c.m = m;
+  c.n = n;
+  c.N = N;
+  c.l = l;
+  c.eps = eps;
+  c.o = o;
+  if (A_lo) {
+    c.mixed = true;
+    c.bulk = dtype + 1;  // C128 -> C64, F64 -> F32
+    c.Ab = A_lo;
+    c.ldab = lda_lo;
+  } else if (is_single(dtype)) {
+    c.mixed = true;
+    c.bulk = dtype;
+    c.Ab = A;
+    c.ldab = lda;
+  } else {
+    c.mixed = false;
+    c.bulk = dtype;
+    c.Ab = A;
+    c.ldab = lda;
+  }
+  if (info) {
+    memset(info, 0, sizeof(*info));
+  }
+  h->events = info != nullptr;
+  ev_record(h, 0);
+  int32_t* inv = nullptr;
+  if (!prepare_idx(h, idx, l, N, &inv)) return -16;
+  const int64_t bes = dtype_size(c.bulk);
+  void* S = ws(h, "S", (size_t)(l * m * bes));
+  run_sketch(h, c.bulk, m, n, c.Ab, c.ldab, N, l, d, idx, inv, S, l);
+  ev_record(h, 1);
+  c.R = ws(h, "R", (size_t)(m * m * bes));
+  int st = run_qr(h, c.bulk, l, m, S, l, c.R, m);
+  ev_record(h, 2);
+  if (st != MN_OK) {
+    if (info) info->status = st;
+    return st;
+  }
+  c.X = ws(h, "Xinv", (size_t)(cdiv(m, 32) * 32 * 32 * wide_size(dtype)));
+  ck(launch_inv_diag(c.bulk, c.R, m, m, c.X, h->stream));
+  const int64_t W = wide_size(dtype);
+  int worst = MN_OK;
+  for (int64_t j = 0; j < nrhs; ++j) {
+    const void* bj = (const char*)b + j * ldb * W;
+    void* xj = (char*)x + j * ldx * W;
+    const int s = solve_one(c, bj, xj, info);
+    if (s > worst) worst = s;
+  }
+  ev_record(h, 8);
+  if (info) {
+    info->status = worst;
+    if (h->events) {
+      ck(hipEventSynchronize(h->ev[8]));
+      float t = 0;
+      (void)hipEventElapsedTime(&t, h->ev[0], h->ev[1]);
+      info->stage_ms[0] = t;
+      (void)hipEventElapsedTime(&t, h->ev[1], h->ev[2]);
+      info->stage_ms[1] = t;
+      (void)hipEventElapsedTime(&t, h->ev[3], h->ev[4]);
+      info->stage_ms[2] = t;
+      (void)hipEventElapsedTime(&t, h->ev[4], h->ev[5]);
+      info->stage_ms[3] = t;
+      (void)hipEventElapsedTime(&t, h->ev[0], h->ev[8]);
+      info->stage_ms[7] = t;
+    }
+  }
+  return worst;
+}
+
+int check_solve_args(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const void* A_lo,
+                     int64_t lda_lo, const void* b, int64_t ldb, int64_t nrhs, double eps, int64_t N, int64_t l,
+                     const void* d, const int32_t* idx, const mn_opts& o, void* x, int64_t ldx) {
+  if (!h) return -1;
+  if (dtype < 0 || dtype > 3) return -2;
+  if (m < 1 || m >= n) return -3;
+  if (n < 2) return -4;
+  if (!A) return -5;
+  if (lda < n) return -6;
+  if (A_lo && is_single(dtype)) return -7;
+  if (A_lo && lda_lo < n) return -8;
+  if (!b) return -9;
+  if (ldb < m) return -10;
+  if (nrhs < 1 || nrhs > 64) return -11;
+  if (!(eps > 0.0 && eps < 1.0)) return -12;
+  if (!is_pow2(N) || N < n || N > (1 << 22)) return -13;
+  if (l <= m || l > N) return -14;
+  if (!d) return -15;
+  if (!idx) return -16;
+  if (!opts_valid(o)) return -17;
+  if (!x) return -18;
+  if (ldx < n) return -19;
+  return 0;
+}
+
+}  // namespace
+
+// =============================================================================
+extern "C" {
+
+int mn_create(mn_handle* hp, void* stream) {
+  if (!hp) return -1;
+  *hp = nullptr;
+  mn_handle h = new mn_handle_s();
+  try {
+    h->stream = (hipStream_t)stream;
+    ck(hipGetDevice(&h->device));
+    ck(hipHostMalloc((void**)&h->host_state, sizeof(PcgState), hipHostMallocDefault));
+    ck(hipHostMalloc((void**)&h->host_flag, 64, hipHostMallocDefault));
+    ck(hipHostMalloc((void**)&h->host_diag, 64, hipHostMallocDefault));
+    for (auto& e : h->ev) ck(hipEventCreate(&e));
+  } catch (HipFail f) {
+    mn_destroy(h);
+    return fail_hip(f.e);
+  }
+  *hp = h;
+  return 0;
+}
+
+int mn_destroy(mn_handle h) {
+  if (!h) return -1;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto& kv : h->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  for (auto& t : h->tw)
+    if (t.p) (void)hipFree(t.p);
+  if (h->host_state) (void)hipHostFree(h->host_state);
+  if (h->host_flag) (void)hipHostFree(h->host_flag);
+  if (h->host_diag) (void)hipHostFree(h->host_diag);
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete h;
+  return 0;
+}
+
+int mn_set_stream(mn_handle h, void* stream) {
+  if (!h) return -1;
+  h->stream = (hipStream_t)stream;
+  return 0;
+}
+
+const char* mn_status_string(int status) {
+  switch (status) {
+    case MN_OK: return "success";
+    case MN_RANK_DEFICIENT: return "sketch numerically rank-deficient (redraw d, idx; A may not have full rank)";
+    case MN_NOT_CONVERGED: return "iteration cap reached before the stopping rule was met";
+    case MN_HIP_ERROR: return "HIP runtime error";
+    case MN_NONFINITE: return "non-finite value in the input or an intermediate";
+  }
+  if (status < 0) return "invalid argument (-status is its 1-based position)";
+  return "unknown status";
+}
+
+const char* mn_last_hip_error(void) { return g_last_hip_error.c_str(); }
+
+int64_t mn_workspace_bytes(mn_handle h) {
+  if (!h) return -1;
+  int64_t t = 0;
+  for (auto& kv : h->bufs) t += (int64_t)kv.second.bytes;
+  for (auto& tw : h->tw) t += tw.N * 16;
+  return t;
+}
+
+int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, int64_t N, int64_t l,
+                const void* d, const int32_t* idx, void* S, int64_t lds) {
+  if (!h) return -1;
+  if (dtype < 0 || dtype > 3) return -2;
+  if (m < 1) return -3;
+  if (n < 1) return -4;
+  if (!A) return -5;
+  if (lda < n) return -6;
+  if (!is_pow2(N) || N < n || N > (1 << 22)) return -7;
+  if (l < 1 || l > N) return -8;
+  if (!d) return -9;
+  if (!idx) return -10;
+  if (!S) return -11;
+  if (lds < l) return -12;
+  try {
+    int32_t* inv = nullptr;
+    if (!prepare_idx(h, idx, l, N, &inv)) return -10;
+    run_sketch(h, dtype, m, n, A, lda, N, l, d, idx, inv, S, lds);
+    ck(hipGetLastError());
+  } catch (HipFail f) {
+    return fail_hip(f.e);
+  }
+  return 0;
+}
+
+int build_preconditioner(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t lds, void* R,
+                         int64_t ldr) {
+  if (!h) return -1;
+  if (dtype < 0 || dtype > 3) return -2;
+  if (m < 1) return -4;
+  if (l < m) return -3;
+  if (!S) return -5;
+  if (lds < l) return -6;
+  if (!R) return -7;
+  if (ldr < m) return -8;
+  try {
+    return run_qr(h, dtype, l, m, S, lds, R, ldr);
+  } catch (HipFail f) {
+    return fail_hip(f.e);
+  }
+}
+
+int minnorm_solve(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const void* A_lo,
+                  int64_t lda_lo, const void* b, int64_t ldb, int64_t nrhs, double eps, int64_t N, int64_t l,
+                  const void* d, const int32_t* idx, const mn_opts* opts, void* x, int64_t ldx, mn_info* info) {
+  const mn_opts o = resolve_opts(opts);
+  const int bad = check_solve_args(h, dtype, m, n, A, lda, A_lo, lda_lo, b, ldb, nrhs, eps, N, l, d, idx, o, x, ldx);
+  if (bad) return bad;
+  try {
+    return solve_impl(h, dtype, m, n, A, lda, A_lo, lda_lo, b, ldb, nrhs, eps, N, l, d, idx, o, x, ldx, info);
+  } catch (HipFail f) {
+    if (info) info->status = MN_HIP_ERROR;
+    return fail_hip(f.e);
+  }
+}
+
+int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* m, const int64_t* n,
+                          const void* const* A, const int64_t* lda, const void* const* A_lo, const void* const* b,
+                          const double* eps, const int64_t* N, const int64_t* l, const void* const* d,
+                          const int32_t* const* idx, const mn_opts* opts, void* const* x, mn_info* info) {
+  if (!h) return -1;
+  if (dtype < 0 || dtype > 3) return -2;
+  if (batch < 1) return -3;
+  if (!m) return -4;
+  if (!n) return -5;
+  if (!A) return -6;
+  if (!lda) return -7;
+  if (!b) return -9;
+  if (!eps) return -10;
+  if (!N) return -11;
+  if (!l) return -12;
+  if (!d) return -13;
+  if (!idx) return -14;
+  if (!x) return -16;
+  const mn_opts o = resolve_opts(opts);
+  if (!opts_valid(o)) return -15;
+  // argument checks for every system before any work is enqueued
+  // minnorm_solve argument positions -> positions in this call
+  static const int remap[20] = {0, -1, -2, -4, -5, -6, -7, -8, -7, -9, -4, -3, -10, -11, -12, -13, -14, -15, -16, -5};
+  for (int32_t i = 0; i < batch; ++i) {
+    const void* alo = A_lo ? A_lo[i] : nullptr;
+    const int e = check_solve_args(h, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i],
+                                   l[i], d[i], idx[i], o, x[i], n[i]);
+    if (e) return remap[-e];
+  }
+  int worst = MN_OK;
+  int argerr = 0;
+  for (int32_t i = 0; i < batch; ++i) {
+    const void* alo = A_lo ? A_lo[i] : nullptr;
+    int s;
+    try {
+      s = solve_impl(h, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i], l[i], d[i],
+                     idx[i], o, x[i], n[i], info ? &info[i] : nullptr);
+    } catch (HipFail f) {
+      s = fail_hip(f.e);
+      if (info) info[i].status = s;
+    }
+    if (s == -16) {  // idx of this system failed the device-side check
+      argerr = -14;
+      if (info) info[i].status = -14;
+      continue;
+    }
+    if (s > worst) worst = s;
+  }
+  return argerr ? argerr : worst;
+}
+
+}  // extern "C"

@@ -1,0 +1,498 @@
+// Step 1 of the method (eq. randmat): S = T A*, T = S F D, applied to every
+// row of A with a radix-staged FFT in LDS.
+//
+//   row i:  v = d o conj(a_i) zero-padded to N;  V = F v;  S(k, i) = V[idx[k]]
+//
+// F is the unitary DFT of eq. (DFT), entries N^{-1/2} exp(-2 pi i j k / N).
+// For real data F is replaced by the orthonormal Hartley transform (the
+// paper's "real-valued version"): the row is transformed as a complex
+// sequence with zero imaginary part and Re(V) - Im(V) is kept.
+//
+// Two launch shapes:
+//   * N <= LDS limit: one workgroup transforms B whole rows in LDS.
+//   * larger N = N1 * N2 ("four-step"): pass 1 does the N2-point FFTs down
+//     the columns of the N2 x N1 view of each row and multiplies by the
+//     twiddles W_N^{n1 k2}; pass 2 does the N1-point FFTs along the rows of
+//     the intermediate and scatters the kept outputs into S through the
+//     inverse subsample map.
+// Both use the same batched Stockham FFT: 256 threads, 16 elements per
+// thread, radix-16/8/4/2 butterflies in registers, LDS between stages.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mn {
+
+// ---------------------------------------------------------------------------
+// in-register DFTs, forward sign:  X[k] = sum_r v[r] exp(-2 pi i r k / R)
+// ---------------------------------------------------------------------------
+template <typename C> __device__ inline void dft2(C& a, C& b) {
+  C t = a;
+  a = vadd(t, b);
+  b = vsub(t, b);
+}
+
+template <typename C> __device__ inline void dft4(C& v0, C& v1, C& v2, C& v3) {
+  C t0 = vadd(v0, v2), t1 = vsub(v0, v2);
+  C t2 = vadd(v1, v3), t3 = vmul_negi(vsub(v1, v3));
+  v0 = vadd(t0, t2);
+  v2 = vsub(t0, t2);
+  v1 = vadd(t1, t3);
+  v3 = vsub(t1, t3);
+}
+
+// multiply by W_16^e = exp(-2 pi i e / 16); e is a compile-time constant
+template <int E, typename C> __device__ inline C w16(C a) {
+  constexpr int e = E & 15;
+  if constexpr (e == 0) return a;
+  else if constexpr (e == 4) return vmul_negi(a);
+  else if constexpr (e == 8) return vscale(a, (typename VT<C>::real)(-1));
+  else if constexpr (e == 12) return C{-a.im, a.re};
+  else {
+    using R = typename VT<C>::real;
+    // cos(2 pi e/16) and sin(2 pi e/16) via quarter-wave symmetry
+    constexpr int q = e & 3;      // offset within the quadrant
+    constexpr int quad = e >> 2;  // quadrant
+    const R c0 = (R)(q == 1 ? 0.92387953251128675613 : q == 2 ? 0.70710678118654752440 : 0.38268343236508977173);
+    const R s0 = (R)(q == 1 ? 0.38268343236508977173 : q == 2 ? 0.70710678118654752440 : 0.92387953251128675613);
+    R c, s;
+    if constexpr (quad == 0) { c = c0; s = s0; }
+    else if constexpr (quad == 1) { c = -s0; s = c0; }
+    else if constexpr (quad == 2) { c = -c0; s = -s0; }
+    else { c = s0; s = -c0; }
+    // (a.re + i a.im) * (c - i s)
+    return C{a.re * c + a.im * s, a.im * c - a.re * s};
+  }
+}
+
+template <typename C> __device__ inline void dft8(C* v) {
+  // 8 = 2 x 4: r = r2 + 4 r1, k = k1 + 2 k2
+#pragma unroll
+  for (int r2 = 0; r2 < 4; ++r2) dft2(v[r2], v[r2 + 4]);
+  v[5] = w16<2>(v[5]);
+  v[6] = w16<4>(v[6]);
+  v[7] = w16<6>(v[7]);
+  C u[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) u[i] = v[i];
+  // k1 = 0 uses u[0..3], k1 = 1 uses u[4..7]
+  dft4(u[0], u[1], u[2], u[3]);
+  dft4(u[4], u[5], u[6], u[7]);
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    v[2 * k2] = u[k2];
+    v[2 * k2 + 1] = u[4 + k2];
+  }
+}
+
+template <typename C> __device__ inline void dft16(C* v) {
+  // 16 = 4 x 4: r = r2 + 4 r1, k = k1 + 4 k2
+#pragma unroll
+  for (int r2 = 0; r2 < 4; ++r2) dft4(v[r2], v[r2 + 4], v[r2 + 8], v[r2 + 12]);
+  // now v[r2 + 4 k1] holds u[r2][k1]; twiddle W16^{r2 k1}
+  v[5] = w16<1>(v[5]);
+  v[6] = w16<2>(v[6]);
+  v[7] = w16<3>(v[7]);
+  v[9] = w16<2>(v[9]);
+  v[10] = w16<4>(v[10]);
+  v[11] = w16<6>(v[11]);
+  v[13] = w16<3>(v[13]);
+  v[14] = w16<6>(v[14]);
+  v[15] = w16<9>(v[15]);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  // v[4 k1 + k2] holds X[k1 + 4 k2]; transpose into natural order
+  C u[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) u[i] = v[i];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = u[4 * k1 + k2];
+}
+
+template <int R, typename C> __device__ inline void dftR(C* v) {
+  if constexpr (R == 2) dft2(v[0], v[1]);
+  else if constexpr (R == 4) dft4(v[0], v[1], v[2], v[3]);
+  else if constexpr (R == 8) dft8(v);
+  else if constexpr (R == 16) dft16(v);
+}
+
+// LDS index with one padding element every 16 (breaks power-of-two strides)
+__device__ inline int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ inline int lds_stride(int L) { return L + (L >> 4) + 1; }
+
+// One Stockham stage of radix R for the FFT owned by this thread.
+//   L   transform length, Ns product of the radices already applied,
+//   tpf threads per FFT, tl this thread's index within its FFT,
+//   tw  table of W_Nt^k, k < Nt, twm = Nt / L.
+template <int R, typename C>
+__device__ inline void fft_stage(C* buf, int L, int Ns, int tpf, int tl, const C* __restrict__ tw, int twm) {
+  constexpr int SMAX = 16 / R;
+  const int slots = (L / R) / tpf;  // 16 / R when E = 16
+  C v[16];
+  const int LR = L / R;
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    if (s < slots && tl < tpf) {
+      const int j = tl + s * tpf;
+      const int jm = j % Ns;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        C x = buf[lpad(j + r * LR)];
+        if (r > 0 && jm > 0) {
+          // W_{Ns R}^{r jm} = W_Nt^{r jm Nt/(Ns R)}
+          const int e = r * jm * (L / (Ns * R)) * twm;
+          x = vmul(x, tw[e]);
+        }
+        v[s * R + r] = x;
+      }
+      dftR<R>(v + s * R);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    if (s < slots && tl < tpf) {
+      const int j = tl + s * tpf;
+      const int jm = j % Ns;
+      const int d0 = (j / Ns) * Ns * R + jm;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[lpad(d0 + r * Ns)] = v[s * R + r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full FFT of length L (power of two) on buf[lpad(0..L)), done by tpf threads.
+// Requires a __syncthreads() before the call (data in place).
+template <typename C>
+__device__ inline void fft_lds(C* buf, const FftPlan& pl, int tpf, int tl, const C* __restrict__ tw, int twm) {
+  int Ns = 1;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int R = pl.radix[s];
+    if (R == 16) fft_stage<16>(buf, pl.L, Ns, tpf, tl, tw, twm);
+    else if (R == 8) fft_stage<8>(buf, pl.L, Ns, tpf, tl, tw, twm);
+    else if (R == 4) fft_stage<4>(buf, pl.L, Ns, tpf, tl, tw, twm);
+    else fft_stage<2>(buf, pl.L, Ns, tpf, tl, tw, twm);
+    Ns *= R;
+  }
+}
+
+// value of the padded, phase-multiplied row entry: d_j conj(a_j) (complex)
+// or d_j a_j + 0i (real)
+template <typename V, typename C>
+__device__ inline C load_row_entry(const V* __restrict__ row, int64_t j, int64_t n, const void* __restrict__ dv) {
+  if (j >= n) return vzero<C>();
+  if constexpr (VT<V>::cplx) {
+    const cd dd = reinterpret_cast<const cd*>(dv)[j];
+    const C d = vmake<C>(dd.re, dd.im);
+    return vcmul(vconv<C>(row[j]), d);  // conj(a) * d
+  } else {
+    const double dd = reinterpret_cast<const double*>(dv)[j];
+    using R = typename VT<C>::real;
+    return C{(R)row[j] * (R)dd, (R)0};
+  }
+}
+
+template <typename V, typename C>
+__device__ inline V out_value(C x, typename VT<C>::real scale) {
+  if constexpr (VT<V>::cplx) return vconv<V>(vscale(x, scale));
+  else return (V)((x.re - x.im) * scale);
+}
+
+// --------------------------- whole rows in LDS ------------------------------
+// grid.x = ceil(m / B); B rows per workgroup, 256 threads.
+template <typename V, typename C>
+__global__ void __launch_bounds__(256) k_sketch_small(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                      FftPlan pl, int B, const void* __restrict__ d,
+                                                      const int32_t* __restrict__ idx, int64_t l,
+                                                      V* __restrict__ S, int64_t lds, const C* __restrict__ tw,
+                                                      typename VT<C>::real scale) {
+  extern __shared__ unsigned char smem_raw[];
+  C* sm = reinterpret_cast<C*>(smem_raw);
+  const int L = pl.L;
+  const int Lp = lds_stride(L);
+  const int E = L < 16 ? L : 16;
+  const int tpf = L / E;
+  const int64_t row0 = (int64_t)blockIdx.x * B;
+  // load: consecutive threads read consecutive entries of one row
+  for (int t = threadIdx.x; t < B * L; t += blockDim.x) {
+    const int b = t / L, pos = t % L;
+    const int64_t i = row0 + b;
+    C v = vzero<C>();
+    if (i < m) v = load_row_entry<V, C>(A + i * lda, pos, n, d);
+    sm[b * Lp + lpad(pos)] = v;
+  }
+  __syncthreads();
+  const int b = threadIdx.x / tpf, tl = threadIdx.x % tpf;
+  const bool active = b < B;
+  {
+    // every thread must reach the stage barriers: inactive threads work on a
+    // harmless private copy of FFT 0's index range but write nothing back
+    C* buf = sm + (active ? b : 0) * Lp;
+    int Ns = 1;
+    for (int s = 0; s < pl.nst; ++s) {
+      const int R = pl.radix[s];
+      const int tl_eff = active ? tl : tpf;  // tl = tpf -> no slots executed
+      if (R == 16) fft_stage<16>(buf, L, Ns, tpf, tl_eff, tw, 1);
+      else if (R == 8) fft_stage<8>(buf, L, Ns, tpf, tl_eff, tw, 1);
+      else if (R == 4) fft_stage<4>(buf, L, Ns, tpf, tl_eff, tw, 1);
+      else fft_stage<2>(buf, L, Ns, tpf, tl_eff, tw, 1);
+      Ns *= R;
+    }
+  }
+  // gather the kept outputs: column i of S
+  for (int bb = 0; bb < B; ++bb) {
+    const int64_t i = row0 + bb;
+    if (i >= m) break;
+    for (int64_t k = threadIdx.x; k < l; k += blockDim.x) {
+      const int pos = idx[k];
+      S[k + i * lds] = out_value<V, C>(sm[bb * Lp + lpad(pos)], scale);
+    }
+  }
+}
+
+// ----------------------- four-step, pass 1: columns -------------------------
+// Row i viewed as N2 x N1 (x[n1 + N1 n2]); FFT over n2 for B consecutive n1,
+// times W_N^{n1 k2}; writes Y[i][k2][n1].  grid = (N1 / B, rows in chunk).
+template <typename V, typename C>
+__global__ void __launch_bounds__(256) k_sketch_cols(const V* __restrict__ A, int64_t lda, int64_t row0, int64_t m,
+                                                     int64_t n, int N1, FftPlan pl2, int B,
+                                                     const void* __restrict__ d, C* __restrict__ Y,
+                                                     const C* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  C* sm = reinterpret_cast<C*>(smem_raw);
+  const int N2 = pl2.L;
+  const int Lp = lds_stride(N2);
+  const int64_t i = row0 + blockIdx.y;
+  const int c0 = blockIdx.x * B;
+  const int64_t N = (int64_t)N1 * N2;
+  const V* row = A + i * lda;
+  // load: consecutive threads take consecutive n1 (contiguous in memory)
+  for (int t = threadIdx.x; t < B * N2; t += blockDim.x) {
+    const int bb = t % B, n2 = t / B;
+    const int64_t j = (int64_t)c0 + bb + (int64_t)N1 * n2;
+    C v = vzero<C>();
+    if (i < m) v = load_row_entry<V, C>(row, j, n, d);
+    sm[bb * Lp + lpad(n2)] = v;
+  }
+  __syncthreads();
+  const int E = N2 < 16 ? N2 : 16;
+  const int tpf = N2 / E;
+  const int b = threadIdx.x / tpf, tl = threadIdx.x % tpf;
+  const bool active = b < B;
+  C* buf = sm + (active ? b : 0) * Lp;
+  {
+    int Ns = 1;
+    const int twm = N1;  // table of size N: W_N2^k = W_N^{k N1}
+    for (int s = 0; s < pl2.nst; ++s) {
+      const int R = pl2.radix[s];
+      const int tl_eff = active ? tl : tpf;
+      if (R == 16) fft_stage<16>(buf, N2, Ns, tpf, tl_eff, tw, twm);
+      else if (R == 8) fft_stage<8>(buf, N2, Ns, tpf, tl_eff, tw, twm);
+      else if (R == 4) fft_stage<4>(buf, N2, Ns, tpf, tl_eff, tw, twm);
+      else fft_stage<2>(buf, N2, Ns, tpf, tl_eff, tw, twm);
+      Ns *= R;
+    }
+  }
+  if (i >= m) return;
+  // twiddle W_N^{n1 k2} and store Y[i][k2][n1]: consecutive threads, consecutive n1
+  C* Yi = Y + (int64_t)blockIdx.y * N;
+  for (int t = threadIdx.x; t < B * N2; t += blockDim.x) {
+    const int bb = t % B, k2 = t / B;
+    const int n1 = c0 + bb;
+    C v = sm[bb * Lp + lpad(k2)];
+    const int64_t e = (int64_t)n1 * k2;  // < N
+    if (e) v = vmul(v, tw[e]);
+    Yi[(int64_t)k2 * N1 + n1] = v;
+  }
+}
+
+// ---------------------- four-step, pass 2: rows + gather ---------------------
+// FFT over n1 of Y[i][k2][:] for B consecutive k2; output index k = k2 + N2 k1
+// is kept when inv[k] >= 0, written to S(inv[k], i).  grid = (N2 / B, rows).
+template <typename V, typename C>
+__global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, int64_t row0, int64_t m, int N2,
+                                                     FftPlan pl1, int B, const int32_t* __restrict__ inv,
+                                                     V* __restrict__ S, int64_t lds, const C* __restrict__ tw,
+                                                     typename VT<C>::real scale) {
+  extern __shared__ unsigned char smem_raw[];
+  C* sm = reinterpret_cast<C*>(smem_raw);
+  const int N1 = pl1.L;
+  const int Lp = lds_stride(N1);
+  const int64_t N = (int64_t)N1 * N2;
+  const int64_t i = row0 + blockIdx.y;
+  const int c0 = blockIdx.x * B;
+  const C* Yi = Y + (int64_t)blockIdx.y * N;
+  for (int t = threadIdx.x; t < B * N1; t += blockDim.x) {
+    const int bb = t / N1, n1 = t % N1;
+    sm[bb * Lp + lpad(n1)] = (i < m) ? Yi[(int64_t)(c0 + bb) * N1 + n1] : vzero<C>();
+  }
+  __syncthreads();
+  const int E = N1 < 16 ? N1 : 16;
+  const int tpf = N1 / E;
+  const int b = threadIdx.x / tpf, tl = threadIdx.x % tpf;
+  const bool active = b < B;
+  C* buf = sm + (active ? b : 0) * Lp;
+  {
+    int Ns = 1;
+    const int twm = N2;
+    for (int s = 0; s < pl1.nst; ++s) {
+      const int R = pl1.radix[s];
+      const int tl_eff = active ? tl : tpf;
+      if (R == 16) fft_stage<16>(buf, N1, Ns, tpf, tl_eff, tw, twm);
+      else if (R == 8) fft_stage<8>(buf, N1, Ns, tpf, tl_eff, tw, twm);
+      else if (R == 4) fft_stage<4>(buf, N1, Ns, tpf, tl_eff, tw, twm);
+      else fft_stage<2>(buf, N1, Ns, tpf, tl_eff, tw, twm);
+      Ns *= R;
+    }
+  }
+  if (i >= m) return;
+  for (int t = threadIdx.x; t < B * N1; t += blockDim.x) {
+    const int bb = t / N1, k1 = t % N1;
+    const int64_t k = (int64_t)(c0 + bb) + (int64_t)N2 * k1;
+    const int32_t pos = inv[k];
+    if (pos >= 0) S[pos + i * lds] = out_value<V, C>(sm[bb * Lp + lpad(k1)], scale);
+  }
+}
+
+// ------------------------------ helpers -------------------------------------
+// inv[k] = position of k in idx, or -1; also flags invalid idx (out of range
+// or not strictly increasing) in *bad.  Writes stay inside inv[0, N).
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = v;
+}
+
+__global__ void k_inverse_map(const int32_t* __restrict__ idx, int64_t l, int64_t N, int32_t* __restrict__ inv,
+                              int32_t* __restrict__ bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= l) return;
+  const int32_t v = idx[k];
+  bool ok = v >= 0 && (int64_t)v < N;
+  if (k + 1 < l && !(idx[k + 1] > v)) ok = false;
+  if (ok) inv[v] = (int32_t)k;
+  else atomicOr(bad, 1);
+}
+
+// ------------------------------ launchers -----------------------------------
+FftPlan make_plan(int L) {
+  FftPlan p{};
+  p.L = L;
+  int k = 0;
+  while ((1 << k) < L) ++k;
+  p.nst = 0;
+  while (k >= 4) { p.radix[p.nst++] = 16; k -= 4; }
+  if (k > 0) p.radix[p.nst++] = 1 << k;
+  return p;
+}
+
+
+// Per-workgroup LDS limit of the current device (bytes).
+static int lds_limit() {
+  static int v = -1;
+  if (v < 0) {
+    int dev = 0, x = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && x > 0)
+      v = x;
+    else
+      v = 65536;
+  }
+  return v;
+}
+
+template <typename C> static int max_lds_fft_len() {
+  int L = kFftMaxLds;
+  while (L > 16 && (int64_t)lds_stride(L) * (int64_t)sizeof(C) > lds_limit()) L >>= 1;
+  return L;
+}
+
+template <typename K> static void allow_lds(K* kern, size_t bytes) {
+  if (bytes > 48 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
+// transforms per workgroup: up to 4096 elements (256 threads x 16) within LDS
+template <typename C> static int fft_batch(int L) {
+  int B = 4096 / L;
+  if (B > 256) B = 256;  // L < 16: one thread per transform
+  if (B < 1) B = 1;
+  while (B > 1 && (int64_t)B * lds_stride(L) * (int64_t)sizeof(C) > lds_limit()) B >>= 1;
+  return B;
+}
+
+template <typename V, typename C>
+static hipError_t sketch_impl(const SketchArgs& a, hipStream_t st) {
+  const int N = (int)a.N;
+  const C* tw = reinterpret_cast<const C*>(a.twiddle);
+  using R = typename VT<C>::real;
+  const R scale = (R)(1.0 / sqrt((double)N));
+  const V* A = reinterpret_cast<const V*>(a.A);
+  V* S = reinterpret_cast<V*>(a.S);
+  const int Lmax = max_lds_fft_len<C>();
+  if (N <= Lmax) {
+    FftPlan pl = make_plan(N);
+    const int B = fft_batch<C>(N);
+    const size_t sm = (size_t)B * lds_stride(N) * sizeof(C);
+    allow_lds(k_sketch_small<V, C>, sm);
+    dim3 grid((unsigned)ceil_div(a.m, B));
+    hipLaunchKernelGGL((k_sketch_small<V, C>), grid, dim3(256), sm, st, A, a.lda, a.m, a.n, pl, B, a.d, a.idx,
+                       a.l, S, a.lds, tw, scale);
+    return hipGetLastError();
+  }
+  // four-step: N = N1 * N2, N1 >= N2, both transformed whole in LDS
+  int k = 0;
+  while ((1 << k) < N) ++k;
+  const int N2 = 1 << (k / 2), N1 = N >> (k / 2);
+  if (N1 > Lmax) return hipErrorInvalidValue;
+  FftPlan pl1 = make_plan(N1), pl2 = make_plan(N2);
+  const int Bc = fft_batch<C>(N2);  // columns per workgroup, pass 1
+  const int Br = fft_batch<C>(N1);  // rows of the intermediate per workgroup, pass 2
+  const size_t smc = (size_t)Bc * lds_stride(N2) * sizeof(C);
+  const size_t smr = (size_t)Br * lds_stride(N1) * sizeof(C);
+  allow_lds(k_sketch_cols<V, C>, smc);
+  allow_lds(k_sketch_rows<V, C>, smr);
+  C* Y = reinterpret_cast<C*>(a.work);
+  for (int64_t r0 = 0; r0 < a.m; r0 += a.chunk_rows) {
+    const int64_t rows = (a.m - r0) < a.chunk_rows ? (a.m - r0) : a.chunk_rows;
+    dim3 g1((unsigned)(N1 / Bc), (unsigned)rows);
+    hipLaunchKernelGGL((k_sketch_cols<V, C>), g1, dim3(256), smc, st, A, a.lda, r0, a.m, a.n, N1, pl2, Bc, a.d, Y,
+                       tw);
+    dim3 g2((unsigned)(N2 / Br), (unsigned)rows);
+    hipLaunchKernelGGL((k_sketch_rows<V, C>), g2, dim3(256), smr, st, Y, r0, a.m, N2, pl1, Br, a.inv, S, a.lds, tw,
+                       scale);
+  }
+  return hipGetLastError();
+}
+
+int sketch_max_log2n(int dtype) {
+  const int L = (dtype == 1 || dtype == 3) ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>();
+  int k = 0;
+  while ((1 << k) < L) ++k;
+  return 2 * k;
+}
+
+hipError_t launch_inverse_map(const int32_t* idx, int64_t l, int64_t N, int32_t* inv, int32_t* bad, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, st, inv, N, -1);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, bad, 1, 0);
+  hipLaunchKernelGGL(k_inverse_map, dim3((unsigned)ceil_div(l, 256)), dim3(256), 0, st, idx, l, N, inv, bad);
+  return hipGetLastError();
+}
+
+int64_t sketch_work_elems(int64_t N, int64_t chunk_rows) {
+  return N * chunk_rows;
+}
+
+hipError_t launch_sketch(int dtype, const SketchArgs& a, hipStream_t st) {
+  switch (dtype) {
+    case 0: return sketch_impl<cd, cd>(a, st);
+    case 1: return sketch_impl<cf, cf>(a, st);
+    case 2: return sketch_impl<double, cd>(a, st);
+    case 3: return sketch_impl<float, cf>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mn

@@ -1,0 +1,260 @@
+// The passes over A that dominate the method's cost (Step 4's iterations and
+// Step 5, x = A* y, eq. output): bandwidth-bound products with a row-major A.
+//
+//   adj:  w = A* u    (w_j = sum_i conj(A_ij) u_i)   threads own columns,
+//                                                    rows split into RS slabs
+//   fwd:  q = A w     (q_i = sum_j A_ij w_j)          workgroups own RB rows x
+//                                                    a column chunk
+// Every load of A is a 16-byte vector load by consecutive threads along a row
+// (fully coalesced).  Partial results are combined in a fixed order, so runs
+// are bitwise reproducible.  u comes in FP64 (the iteration's vectors are kept
+// in FP64); A and w are in A's precision; partial sums of q are written in
+// FP64.  All kernels return at once when the iteration's stop flag is set.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mn {
+
+template <typename V> struct Vec16;
+template <> struct Vec16<cd> { static constexpr int n = 1; };
+template <> struct Vec16<cf> { static constexpr int n = 2; };
+template <> struct Vec16<double> { static constexpr int n = 2; };
+template <> struct Vec16<float> { static constexpr int n = 4; };
+
+template <typename V, int K> struct alignas(16) Pack { V v[K]; };
+
+template <typename V, int K>
+__device__ inline Pack<V, K> loadk(const V* p) {
+  return *reinterpret_cast<const Pack<V, K>*>(p);
+}
+
+__device__ inline bool stopped(const int32_t* flag) { return flag != nullptr && *(volatile const int32_t*)flag != 0; }
+
+// ---------------------------------------------------------------------------
+// w (or its RS partial slabs) = A* u.  grid (ceil(n / (256*VEC)), RS), 256 thr.
+// If RS == 1 the result goes straight to w, else to part[rs * n + j].
+template <typename V, typename C, typename U, int VEC>
+__global__ void __launch_bounds__(256) k_gemv_adj(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                  const U* __restrict__ u, int64_t rows_per_slab,
+                                                  C* __restrict__ out, const int32_t* __restrict__ flag) {
+  if (stopped(flag)) return;
+  __shared__ C su[1024];
+  const int64_t j0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * VEC;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_slab;
+  const int64_t r1 = (r0 + rows_per_slab) < m ? (r0 + rows_per_slab) : m;
+  C acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = vzero<C>();
+  const bool full = j0 + VEC <= n;
+  for (int64_t rb = r0; rb < r1; rb += 1024) {
+    const int64_t rn = (r1 - rb) < 1024 ? (r1 - rb) : 1024;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < rn; t += 256) su[t] = vconv<C>(u[rb + t]);
+    __syncthreads();
+    if (j0 < n) {
+      const V* a = A + rb * lda + j0;
+      int64_t i = 0;
+      if (full) {
+        for (; i + 8 <= rn; i += 8) {
+          Pack<V, VEC> x[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) x[k] = loadk<V, VEC>(a + (i + k) * lda);
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const C ui = su[i + k];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = vcfma(vconv<C>(x[k].v[v]), ui, acc[v]);
+          }
+        }
+        for (; i < rn; ++i) {
+          Pack<V, VEC> x = loadk<V, VEC>(a + i * lda);
+          const C ui = su[i];
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v] = vcfma(vconv<C>(x.v[v]), ui, acc[v]);
+        }
+      } else {
+        for (; i < rn; ++i) {
+          const C ui = su[i];
+          for (int v = 0; v < VEC; ++v)
+            if (j0 + v < n) acc[v] = vcfma(vconv<C>(a[i * lda + v]), ui, acc[v]);
+        }
+      }
+    }
+  }
+  if (j0 >= n) return;
+  C* o = out + (int64_t)blockIdx.y * n + j0;
+  if (full && ((uintptr_t)o % 16 == 0)) {
+    Pack<C, VEC> pk;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) pk.v[v] = acc[v];
+    *reinterpret_cast<Pack<C, VEC>*>(o) = pk;
+  } else {
+    for (int v = 0; v < VEC; ++v)
+      if (j0 + v < n) o[v] = acc[v];
+  }
+}
+
+// w[j] = sum_s part[s * n + j] in slab order; optionally also a wide copy.
+template <typename V, typename W>
+__global__ void k_sum_slabs(const V* __restrict__ part, int rs, int64_t n, V* __restrict__ w, W* __restrict__ wide,
+                            const int32_t* __restrict__ flag) {
+  if (stopped(flag)) return;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  V s = part[j];
+  for (int k = 1; k < rs; ++k) s = vadd(s, part[(int64_t)k * n + j]);
+  if (w) w[j] = s;
+  if (wide) wide[j] = vconv<W>(s);
+}
+
+// ---------------------------------------------------------------------------
+// qpart[cs * m + i] = sum_{j in chunk cs} A_ij w_j.  grid (CS, ceil(m / RB)).
+template <typename V, typename C, typename W, int RB, int VEC>
+__global__ void __launch_bounds__(256) k_gemv_fwd(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                  const C* __restrict__ w, int64_t chunk,
+                                                  W* __restrict__ qpart, const int32_t* __restrict__ flag) {
+  if (stopped(flag)) return;
+  __shared__ W red[RB][4];
+  const int64_t i0 = (int64_t)blockIdx.y * RB;
+  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t c1 = (c0 + chunk) < n ? (c0 + chunk) : n;
+  C acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = vzero<C>();
+  int64_t rows = m - i0;
+  if (rows > RB) rows = RB;
+  for (int64_t j = c0 + (int64_t)threadIdx.x * VEC; j < c1; j += 256 * VEC) {
+    if (j + VEC <= c1) {
+      C wv[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) wv[v] = w[j + v];
+      Pack<V, VEC> x[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r < rows) x[r] = loadk<V, VEC>(A + (i0 + r) * lda + j);
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r < rows)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[r] = vfma(vconv<C>(x[r].v[v]), wv[v], acc[r]);
+    } else {
+      for (int v = 0; v < VEC; ++v) {
+        if (j + v >= c1) break;
+        const C wj = w[j + v];
+        for (int r = 0; r < RB; ++r)
+          if (r < rows) acc[r] = vfma(vconv<C>(A[(i0 + r) * lda + j + v]), wj, acc[r]);
+      }
+    }
+  }
+  // reduce each row's accumulator over the workgroup (wave sums, then 4 waves)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    W s = vconv<W>(acc[r]);
+    s = wave_sum(s);
+    if (lane == 0) red[r][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < RB && threadIdx.x < rows) {
+    const int r = threadIdx.x;
+    W s = vadd(vadd(red[r][0], red[r][1]), vadd(red[r][2], red[r][3]));
+    qpart[(int64_t)blockIdx.x * m + i0 + r] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+static bool aligned16(const void* p, int64_t ld, int64_t es) {
+  return ((uintptr_t)p % 16 == 0) && ((ld * es) % 16 == 0);
+}
+
+static int64_t slabs_for(int64_t m, int64_t n, int vec) {
+  const int64_t nb = ceil_div(n, (int64_t)256 * vec);
+  // enough workgroups to fill the chip (~2048), slabs of at least 32 rows
+  int64_t rs = ceil_div(2048, nb);
+  if (rs > ceil_div(m, 32)) rs = ceil_div(m, 32);
+  if (rs < 1) rs = 1;
+  if (rs > kMaxSlabs) rs = kMaxSlabs;
+  const int64_t rps = ceil_div(m, rs);
+  return ceil_div(m, rps);
+}
+
+template <typename V, typename C, typename W, int VEC>
+static hipError_t adj_run(const AdjArgs& a, hipStream_t st) {
+  const int64_t nb = ceil_div(a.n, (int64_t)256 * VEC);
+  int64_t rs = slabs_for(a.m, a.n, VEC);
+  const int64_t rps = ceil_div(a.m, rs);
+  const V* A = reinterpret_cast<const V*>(a.A);
+  const W* u = reinterpret_cast<const W*>(a.u);
+  C* w = reinterpret_cast<C*>(a.w);
+  W* wide = reinterpret_cast<W*>(a.w_wide);
+  if (rs == 1 && wide == nullptr) {
+    hipLaunchKernelGGL((k_gemv_adj<V, C, W, VEC>), dim3((unsigned)nb, 1), dim3(256), 0, st, A, a.lda, a.m, a.n, u,
+                       rps, w, a.flag);
+    return hipGetLastError();
+  }
+  C* part = reinterpret_cast<C*>(a.part);
+  hipLaunchKernelGGL((k_gemv_adj<V, C, W, VEC>), dim3((unsigned)nb, (unsigned)rs), dim3(256), 0, st, A, a.lda, a.m,
+                     a.n, u, rps, part, a.flag);
+  hipLaunchKernelGGL((k_sum_slabs<C, W>), dim3((unsigned)ceil_div(a.n, 256)), dim3(256), 0, st, part, (int)rs, a.n,
+                     w, wide, a.flag);
+  return hipGetLastError();
+}
+
+template <typename V, typename C, typename W>
+static hipError_t adj_impl(const AdjArgs& a, hipStream_t st) {
+  if (aligned16(a.A, a.lda, sizeof(V))) return adj_run<V, C, W, Vec16<V>::n>(a, st);
+  return adj_run<V, C, W, 1>(a, st);
+}
+
+template <typename V, typename C, typename W, int VEC>
+static hipError_t fwd_run(const FwdArgs& a, hipStream_t st) {
+  constexpr int RB = 8;
+  const int64_t rb = ceil_div(a.m, RB);
+  int64_t cs = ceil_div(2048, rb);
+  const int64_t min_chunk = 256 * VEC * 2;
+  if (cs > ceil_div(a.n, min_chunk)) cs = ceil_div(a.n, min_chunk);
+  if (cs < 1) cs = 1;
+  if (cs > kMaxChunks) cs = kMaxChunks;
+  int64_t chunk = ceil_div(a.n, cs);
+  chunk = ceil_div(chunk, 256 * VEC) * (256 * VEC);
+  cs = ceil_div(a.n, chunk);
+  hipLaunchKernelGGL((k_gemv_fwd<V, C, W, RB, VEC>), dim3((unsigned)cs, (unsigned)rb), dim3(256), 0, st,
+                     reinterpret_cast<const V*>(a.A), a.lda, a.m, a.n, reinterpret_cast<const C*>(a.w), chunk,
+                     reinterpret_cast<W*>(a.qpart), a.flag);
+  if (a.chunks_out) *a.chunks_out = (int)cs;
+  return hipGetLastError();
+}
+
+template <typename V, typename C, typename W>
+static hipError_t fwd_impl(const FwdArgs& a, hipStream_t st) {
+  if (aligned16(a.A, a.lda, sizeof(V))) return fwd_run<V, C, W, Vec16<V>::n>(a, st);
+  return fwd_run<V, C, W, 1>(a, st);
+}
+
+// the widest vector (4 elements) gives the fewest column blocks and hence
+// the most slabs: size the partial buffer for that case
+int64_t adj_part_elems(int64_t m, int64_t n) { return slabs_for(m, n, 4) * n; }
+
+// dtype: storage of A; wide: accumulate in FP64 (w in FP64) even for
+// single-precision storage.
+hipError_t launch_gemv_adj(int dtype, bool wide, const AdjArgs& a, hipStream_t st) {
+  switch (dtype) {
+    case 0: return adj_impl<cd, cd, cd>(a, st);
+    case 1: return wide ? adj_impl<cf, cd, cd>(a, st) : adj_impl<cf, cf, cd>(a, st);
+    case 2: return adj_impl<double, double, double>(a, st);
+    case 3: return wide ? adj_impl<float, double, double>(a, st) : adj_impl<float, float, double>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemv_fwd(int dtype, bool wide, const FwdArgs& a, hipStream_t st) {
+  switch (dtype) {
+    case 0: return fwd_impl<cd, cd, cd>(a, st);
+    case 1: return wide ? fwd_impl<cf, cd, cd>(a, st) : fwd_impl<cf, cf, cd>(a, st);
+    case 2: return fwd_impl<double, double, double>(a, st);
+    case 3: return wide ? fwd_impl<float, double, double>(a, st) : fwd_impl<float, float, double>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mn

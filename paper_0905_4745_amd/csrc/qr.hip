@@ -1,0 +1,457 @@
+// Step 2's factorisation of the l x m sketch, S = Q_S R, by Householder
+// reflections (Section 4, Step 2), keeping only R -- the preconditioner of
+// Step 4.  Q_S is never formed.
+//
+// Tiled ("communication-avoiding") Householder QR on 32 x 32 tiles.  For
+// each tile column k:
+//   level 0   every tile (i, k), i >= k, is reduced to a triangle R_i by its
+//             own reflectors; the same reflectors update tiles (i, j), j > k;
+//   level s   the triangles are merged pairwise in a binary tree: [R_a; R_b]
+//             is reduced to one triangle by reflectors that touch only the
+//             pivot row of R_a and the upper triangle of R_b, and the same
+//             reflectors update the row-tile pair (a, j), (b, j), j > k.
+// Every workgroup (pair, j) recomputes the small factorisation it needs, so
+// one launch covers a whole level and no reflector is ever stored globally.
+// The triangles live in a ping-pong buffer; the final one of column k is R's
+// diagonal block k, and tile (k, j), j > k, ends as R's block (k, j).
+//
+// Reflector convention: H = I - tau v v^*, v[pivot] = 1, chosen so that
+// H^* x = beta e_pivot with beta real and of sign opposite to Re(x_pivot).
+// R is unique up to a diagonal unitary factor; its diagonal comes out real.
+//
+// Ragged sizes: the sketch is copied into an lp x mp tile-aligned matrix
+// [[S, 0], [0, 0], [0, I]] whose R is diag(R_S, +-I), so the leading m x m
+// block is exactly R_S.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mn {
+
+constexpr int NB = kQrTile;  // 32
+
+// Householder vector for x = [alpha; rest], |rest|^2 = xn2: returns beta,
+// tau and scal = 1 / (alpha - beta) (v_rest = rest * scal).
+template <typename V>
+__device__ inline void make_reflector(V alpha, typename VT<V>::real xn2, V& tau, typename VT<V>::real& beta,
+                                      V& scal) {
+  using R = typename VT<V>::real;
+  const R ar = vre(alpha), ai = vim(alpha);
+  if (xn2 == (R)0 && ai == (R)0) {
+    tau = vzero<V>();
+    beta = ar;
+    scal = vzero<V>();
+    return;
+  }
+  const R nrm = sqrt(ar * ar + ai * ai + xn2);
+  beta = ar >= (R)0 ? -nrm : nrm;
+  // tau = (beta - alpha) / beta
+  tau = vmake<V>((beta - ar) / beta, -ai / beta);
+  // scal = 1 / (alpha - beta)
+  const R dr = ar - beta, di = ai;
+  const R den = dr * dr + di * di;
+  scal = vmake<V>(dr / den, -di / den);
+}
+
+// ---------------------------------------------------------------------------
+// Reduce the NB x NB tile T (LDS, column-major, ld NB) to upper-triangular
+// form.  On exit T holds beta on the diagonal, v below it, tau[] the scalars.
+// All 256 threads take part.
+template <typename V>
+__device__ void geqrt_lds(V* T, V* tau, typename VT<V>::real* red) {
+  using R = typename VT<V>::real;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  __shared__ V s_scal;
+  __shared__ R s_beta;
+  for (int j = 0; j < NB; ++j) {
+    if (wv == 0) {
+      R p = (lane > j && lane < NB) ? vabs2(T[lane + j * NB]) : (R)0;
+      p = wave_sum(p);
+      if (lane == 0) {
+        V tj, sc;
+        R bt;
+        make_reflector<V>(T[j + j * NB], p, tj, bt, sc);
+        tau[j] = tj;
+        s_scal = sc;
+        s_beta = bt;
+      }
+    }
+    __syncthreads();
+    const V sc = s_scal;
+    const V tj = tau[j];
+    // trailing columns c > j: 8 lanes per column, 4 rows each
+    {
+      const int c = j + 1 + (t >> 3);
+      const int q0 = (t & 7) * 4;
+      V part = vzero<V>();
+      V vq[4], aq[4];
+      if (c < NB) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u;
+          vq[u] = (q == j) ? vmake<V>(1.0, 0.0) : (q > j ? vmul(T[q + j * NB], sc) : vzero<V>());
+          aq[u] = T[q + c * NB];
+          part = vcfma(vq[u], aq[u], part);
+        }
+      }
+      // reduce over the 8 lanes of this column (always executed by all lanes)
+#pragma unroll
+      for (int off = 1; off < 8; off <<= 1) {
+        if constexpr (VT<V>::cplx) {
+          part.re += __shfl_xor(part.re, off, 64);
+          part.im += __shfl_xor(part.im, off, 64);
+        } else {
+          part += __shfl_xor(part, off, 64);
+        }
+      }
+      if (c < NB) {
+        const V f = vmul(vconj(tj), part);  // conj(tau) w
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u;
+          if (q >= j) T[q + c * NB] = vsub(aq[u], vmul(vq[u], f));
+        }
+      }
+    }
+    __syncthreads();
+    if (t < NB) {
+      if (t > j) T[t + j * NB] = vmul(T[t + j * NB], sc);
+      else if (t == j) T[j + j * NB] = vmake<V>((double)s_beta, 0.0);
+    }
+    __syncthreads();
+  }
+}
+
+// Apply Q^* of a geqrt'd tile (reflectors in T, tau) to the tile C held in
+// registers: thread t owns column t/8, rows 4*(t%8) .. +3.
+template <typename V>
+__device__ inline void apply_geqrt(const V* T, const V* tau, V* c) {
+  const int t = threadIdx.x;
+  const int q0 = (t & 7) * 4;
+  for (int r = 0; r < NB; ++r) {
+    V part = vzero<V>();
+    V vq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u;
+      vq[u] = (q == r) ? vmake<V>(1.0, 0.0) : (q > r ? T[q + r * NB] : vzero<V>());
+      part = vcfma(vq[u], c[u], part);
+    }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      if constexpr (VT<V>::cplx) {
+        part.re += __shfl_xor(part.re, off, 64);
+        part.im += __shfl_xor(part.im, off, 64);
+      } else {
+        part += __shfl_xor(part, off, 64);
+      }
+    }
+    const V f = vmul(vconj(tau[r]), part);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = vsub(c[u], vmul(vq[u], f));
+  }
+}
+
+// Merge two triangles: [R1; R2] (LDS, column-major NB x NB each) -> R1 new
+// triangle, R2 upper part holds the reflector tails v2, tau[] the scalars.
+template <typename V>
+__device__ void ttqrt_lds(V* R1, V* R2, V* tau) {
+  using R = typename VT<V>::real;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  __shared__ V s_scal;
+  __shared__ R s_beta;
+  for (int j = 0; j < NB; ++j) {
+    if (wv == 0) {
+      R p = (lane <= j) ? vabs2(R2[lane + j * NB]) : (R)0;
+      p = wave_sum(p);
+      if (lane == 0) {
+        V tj, sc;
+        R bt;
+        make_reflector<V>(R1[j + j * NB], p, tj, bt, sc);
+        tau[j] = tj;
+        s_scal = sc;
+        s_beta = bt;
+      }
+    }
+    __syncthreads();
+    const V sc = s_scal;
+    const V tj = tau[j];
+    {
+      const int c = j + 1 + (t >> 3);
+      const int q0 = (t & 7) * 4;
+      V part = vzero<V>();
+      V vq[4], aq[4];
+      V top = vzero<V>();
+      if (c < NB) {
+        if ((t & 7) == 0) {
+          top = R1[j + c * NB];
+          part = top;  // conj(1) * R1[j, c]
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u;
+          vq[u] = (q <= j) ? vmul(R2[q + j * NB], sc) : vzero<V>();
+          aq[u] = R2[q + c * NB];
+          part = vcfma(vq[u], aq[u], part);
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < 8; off <<= 1) {
+        if constexpr (VT<V>::cplx) {
+          part.re += __shfl_xor(part.re, off, 64);
+          part.im += __shfl_xor(part.im, off, 64);
+        } else {
+          part += __shfl_xor(part, off, 64);
+        }
+      }
+      if (c < NB) {
+        const V f = vmul(vconj(tj), part);
+        if ((t & 7) == 0) R1[j + c * NB] = vsub(top, f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u;
+          if (q <= j) R2[q + c * NB] = vsub(aq[u], vmul(vq[u], f));
+        }
+      }
+    }
+    __syncthreads();
+    if (t < NB) {
+      if (t <= j) R2[t + j * NB] = vmul(R2[t + j * NB], sc);
+      if (t == j) R1[j + j * NB] = vmake<V>((double)s_beta, 0.0);
+    }
+    __syncthreads();
+  }
+}
+
+// Apply the merge's Q^* to the row-tile pair (C1 top, C2 bottom) held in
+// registers: thread t owns column t/8, rows 4*(t%8)..+3 of both tiles.
+template <typename V>
+__device__ inline void apply_ttqrt(const V* V2, const V* tau, V* c1, V* c2) {
+  const int t = threadIdx.x;
+  const int q0 = (t & 7) * 4;
+  for (int r = 0; r < NB; ++r) {
+    V part = vzero<V>();
+    const bool own_top = (r >> 2) == (t & 7);
+    V vq[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u;
+      vq[u] = (q <= r) ? V2[q + r * NB] : vzero<V>();
+      part = vcfma(vq[u], c2[u], part);
+      if (own_top && q == r) part = vadd(part, c1[u]);
+    }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      if constexpr (VT<V>::cplx) {
+        part.re += __shfl_xor(part.re, off, 64);
+        part.im += __shfl_xor(part.im, off, 64);
+      } else {
+        part += __shfl_xor(part, off, 64);
+      }
+    }
+    const V f = vmul(vconj(tau[r]), part);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u;
+      if (own_top && q == r) c1[u] = vsub(c1[u], f);
+      c2[u] = vsub(c2[u], vmul(vq[u], f));
+    }
+  }
+}
+
+// tile load / store (column-major, leading dimension ld), all 256 threads
+template <typename V> __device__ inline void tile_to_lds(V* dst, const V* src, int64_t ld) {
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) dst[e] = src[(e % NB) + (int64_t)(e / NB) * ld];
+}
+template <typename V> __device__ inline void tile_from_lds(V* dst, int64_t ld, const V* src) {
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) dst[(e % NB) + (int64_t)(e / NB) * ld] = src[e];
+}
+template <typename V> __device__ inline void triu_store(V* dst, const V* src) {
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int r = e % NB, c = e / NB;
+    dst[e] = r <= c ? src[e] : vzero<V>();
+  }
+}
+template <typename V> __device__ inline void regs_load(V* c, const V* tile, int64_t ld) {
+  const int col = threadIdx.x >> 3, q0 = (threadIdx.x & 7) * 4;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) c[u] = tile[(q0 + u) + (int64_t)col * ld];
+}
+template <typename V> __device__ inline void regs_store(V* tile, int64_t ld, const V* c) {
+  const int col = threadIdx.x >> 3, q0 = (threadIdx.x & 7) * 4;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) tile[(q0 + u) + (int64_t)col * ld] = c[u];
+}
+
+// ---------------------------------------------------------------------------
+// copy S (l x m, lds) into the tile-aligned Sp (lp x mp, ld lp)
+template <typename V>
+__global__ void k_qr_pad(const V* __restrict__ S, int64_t lds, int64_t l, int64_t m, V* __restrict__ Sp, int64_t lp,
+                         int64_t mp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= lp * mp) return;
+  const int64_t r = e % lp, c = e / lp;
+  V v = vzero<V>();
+  if (r < l && c < m) v = S[r + c * lds];
+  else if (c >= m && r == lp - (mp - m) + (c - m)) v = vmake<V>(1.0, 0.0);
+  Sp[e] = v;
+}
+
+// level 0 of tile column k: grid (MT - k, NT - k), 256 threads
+template <typename V>
+__global__ void __launch_bounds__(256) k_qr_level0(V* __restrict__ Sp, int64_t lp, int k, V* __restrict__ Rb,
+                                                   V* __restrict__ Rdiag, int write_diag) {
+  __shared__ V T[NB * NB];
+  __shared__ V tau[NB];
+  __shared__ typename VT<V>::real red[4];
+  const int i = k + blockIdx.x;
+  const int jj = blockIdx.y;
+  const V* tile_ik = Sp + (int64_t)i * NB + (int64_t)k * NB * lp;
+  tile_to_lds(T, tile_ik, lp);
+  __syncthreads();
+  geqrt_lds<V>(T, tau, red);
+  if (jj == 0) {
+    triu_store(Rb + (int64_t)i * NB * NB, T);
+    if (write_diag) triu_store(Rdiag + (int64_t)k * NB * NB, T);
+    return;
+  }
+  V* tile_ij = Sp + (int64_t)i * NB + (int64_t)(k + jj) * NB * lp;
+  V c[4];
+  regs_load(c, tile_ij, lp);
+  apply_geqrt<V>(T, tau, c);
+  regs_store(tile_ij, lp, c);
+}
+
+// tree level s of tile column k: grid (pairs, NT - k), 256 threads
+template <typename V>
+__global__ void __launch_bounds__(256) k_qr_tree(V* __restrict__ Sp, int64_t lp, int MT, int k, int s,
+                                                 const V* __restrict__ Rin, V* __restrict__ Rout,
+                                                 V* __restrict__ Rdiag, int final_level) {
+  __shared__ V R1[NB * NB];
+  __shared__ V R2[NB * NB];
+  __shared__ V tau[NB];
+  const int p = blockIdx.x;
+  const int jj = blockIdx.y;
+  const int i1 = k + p * (2 << s);
+  const int i2 = i1 + (1 << s);
+  if (i2 >= MT) {
+    if (jj == 0)
+      for (int e = threadIdx.x; e < NB * NB; e += blockDim.x)
+        Rout[(int64_t)i1 * NB * NB + e] = Rin[(int64_t)i1 * NB * NB + e];
+    return;
+  }
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    R1[e] = Rin[(int64_t)i1 * NB * NB + e];
+    R2[e] = Rin[(int64_t)i2 * NB * NB + e];
+  }
+  __syncthreads();
+  ttqrt_lds<V>(R1, R2, tau);
+  if (jj == 0) {
+    triu_store(Rout + (int64_t)i1 * NB * NB, R1);
+    if (final_level) triu_store(Rdiag + (int64_t)k * NB * NB, R1);
+    return;
+  }
+  V* t1 = Sp + (int64_t)i1 * NB + (int64_t)(k + jj) * NB * lp;
+  V* t2 = Sp + (int64_t)i2 * NB + (int64_t)(k + jj) * NB * lp;
+  V c1[4], c2[4];
+  regs_load(c1, t1, lp);
+  regs_load(c2, t2, lp);
+  apply_ttqrt<V>(R2, tau, c1, c2);
+  regs_store(t1, lp, c1);
+  regs_store(t2, lp, c2);
+}
+
+// R (m x m, ldr) from the diagonal triangles and the tiles (I, J), I < J;
+// also max and min of |R_ii| (i < m) into dmax[0], dmax[1] via a second kernel.
+template <typename V>
+__global__ void k_qr_extract(const V* __restrict__ Sp, int64_t lp, const V* __restrict__ Rdiag, int64_t m,
+                             V* __restrict__ Rout, int64_t ldr) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * m) return;
+  const int64_t r = e % m, c = e / m;
+  V v = vzero<V>();
+  if (r <= c) {
+    const int64_t I = r / NB, J = c / NB;
+    if (I == J) v = Rdiag[I * NB * NB + (r % NB) + (c % NB) * NB];
+    else v = Sp[r + c * lp];
+  }
+  Rout[r + c * ldr] = v;
+}
+
+template <typename V>
+__global__ void k_rdiag_range(const V* __restrict__ R, int64_t ldr, int64_t m, double* __restrict__ out) {
+  __shared__ double red[16];
+  double mx = 0.0, mn = 1.0e308;
+  bool fin = true;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+    const V d = R[i + i * ldr];
+    const double a = sqrt((double)vabs2(d));
+    fin = fin && vfinite(d);
+    mx = fmax(mx, a);
+    mn = fmin(mn, a);
+  }
+  mx = block_max(mx, red);
+  mn = -block_max(-mn, red);
+  double f = fin ? 0.0 : 1.0;
+  f = block_max(f, red);
+  if (threadIdx.x == 0) {
+    out[0] = mx;
+    out[1] = mn;
+    out[2] = f;
+  }
+}
+
+template <typename V>
+static hipError_t qr_impl(const QrArgs& a, hipStream_t st) {
+  const int64_t mp = ceil_div(a.m, NB) * NB;
+  const int64_t lp = ceil_div(a.l + (mp - a.m), NB) * NB;
+  const int MT = (int)(lp / NB), NT = (int)(mp / NB);
+  V* Sp = reinterpret_cast<V*>(a.work);
+  V* Rb0 = Sp + lp * mp;
+  V* Rb1 = Rb0 + (int64_t)MT * NB * NB;
+  V* Rdiag = Rb1 + (int64_t)MT * NB * NB;
+  hipLaunchKernelGGL((k_qr_pad<V>), dim3((unsigned)ceil_div(lp * mp, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const V*>(a.S), a.lds, a.l, a.m, Sp, lp, mp);
+  for (int k = 0; k < NT; ++k) {
+    const int span = MT - k;
+    hipLaunchKernelGGL((k_qr_level0<V>), dim3(span, NT - k), dim3(256), 0, st, Sp, lp, k, Rb0, Rdiag,
+                       span == 1 ? 1 : 0);
+    V* rin = Rb0;
+    V* rout = Rb1;
+    for (int s = 0; (1 << s) < span; ++s) {
+      const int pairs = (int)ceil_div(span, 2 << s);
+      const int fin = (2 << s) >= span ? 1 : 0;
+      hipLaunchKernelGGL((k_qr_tree<V>), dim3(pairs, NT - k), dim3(256), 0, st, Sp, lp, MT, k, s, rin, rout, Rdiag,
+                         fin);
+      V* tmp = rin;
+      rin = rout;
+      rout = tmp;
+    }
+  }
+  V* R = reinterpret_cast<V*>(a.R);
+  hipLaunchKernelGGL((k_qr_extract<V>), dim3((unsigned)ceil_div(a.m * a.m, 256)), dim3(256), 0, st, Sp, lp, Rdiag,
+                     a.m, R, a.ldr);
+  hipLaunchKernelGGL((k_rdiag_range<V>), dim3(1), dim3(1024), 0, st, R, a.ldr, a.m, a.diag_out);
+  return hipGetLastError();
+}
+
+int64_t qr_work_bytes(int dtype, int64_t l, int64_t m) {
+  const int64_t mp = ceil_div(m, NB) * NB;
+  const int64_t lp = ceil_div(l + (mp - m), NB) * NB;
+  const int64_t MT = lp / NB, NT = mp / NB;
+  const int64_t elems = lp * mp + 2 * MT * NB * NB + NT * NB * NB;
+  return elems * dtype_size(dtype);
+}
+
+hipError_t launch_qr(int dtype, const QrArgs& a, hipStream_t st) {
+  switch (dtype) {
+    case 0: return qr_impl<cd>(a, st);
+    case 1: return qr_impl<cf>(a, st);
+    case 2: return qr_impl<double>(a, st);
+    case 3: return qr_impl<float>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mn

@@ -1,0 +1,121 @@
+"""The C ABI library: loads on a CPU-only host, exports every symbol the
+header declares, and rejects invalid arguments with -k before touching the
+GPU (the checks run before any HIP call, so a dummy handle suffices)."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "minnorm.h")
+
+
+def _lib():
+    from paper_0905_4745_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libminnorm.so not built: run `python -m paper_0905_4745_amd.build`")
+    return L, L.load()
+
+
+def test_header_symbols_exported():
+    L, lib = _lib()
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(\w+)\s*\(", text, re.M))
+    assert declared == set(L.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+def test_status_strings():
+    _, lib = _lib()
+    for s in (0, 1, 2, 3, 4, -5):
+        assert len(lib.mn_status_string(s)) > 0
+
+
+class _Dummy:
+    """A non-null opaque handle that the argument checks never dereference."""
+    def __init__(self):
+        self.buf = C.create_string_buffer(64)
+        self.ptr = C.cast(self.buf, C.c_void_p)
+
+
+def test_sketch_argument_errors():
+    L, lib = _lib()
+    h = _Dummy().ptr
+    p = C.c_void_p(16)  # never dereferenced on these paths
+    ok = dict(dtype=0, m=4, n=10, A=p, lda=10, N=16, l=8, d=p, idx=p, S=p, lds=8)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.srft_sketch(h, a["dtype"], a["m"], a["n"], a["A"], a["lda"], a["N"], a["l"], a["d"],
+                               a["idx"], a["S"], a["lds"])
+
+    assert lib.srft_sketch(None, 0, 4, 10, p, 10, 16, 8, p, p, p, 8) == -1
+    assert call(dtype=7) == -2
+    assert call(m=0) == -3
+    assert call(n=0) == -4
+    assert call(A=None) == -5
+    assert call(lda=9) == -6
+    assert call(N=12) == -7          # not a power of two
+    assert call(N=8) == -7           # N < n
+    assert call(N=1 << 23) == -7     # too long
+    assert call(l=0) == -8
+    assert call(l=17) == -8
+    assert call(d=None) == -9
+    assert call(idx=None) == -10
+    assert call(S=None) == -11
+    assert call(lds=7) == -12
+
+
+def test_preconditioner_argument_errors():
+    L, lib = _lib()
+    h = _Dummy().ptr
+    p = C.c_void_p(16)
+    assert lib.build_preconditioner(None, 0, 8, 4, p, 8, p, 4) == -1
+    assert lib.build_preconditioner(h, 9, 8, 4, p, 8, p, 4) == -2
+    assert lib.build_preconditioner(h, 0, 3, 4, p, 8, p, 4) == -3
+    assert lib.build_preconditioner(h, 0, 8, 0, p, 8, p, 4) == -4
+    assert lib.build_preconditioner(h, 0, 8, 4, None, 8, p, 4) == -5
+    assert lib.build_preconditioner(h, 0, 8, 4, p, 7, p, 4) == -6
+    assert lib.build_preconditioner(h, 0, 8, 4, p, 8, None, 4) == -7
+    assert lib.build_preconditioner(h, 0, 8, 4, p, 8, p, 3) == -8
+
+
+def test_solve_argument_errors():
+    L, lib = _lib()
+    h = _Dummy().ptr
+    p = C.c_void_p(16)
+    base = dict(dtype=0, m=4, n=10, A=p, lda=10, Alo=None, ldalo=0, b=p, ldb=4, nrhs=1, eps=1e-8,
+                N=16, l=8, d=p, idx=p, opts=None, x=p, ldx=10)
+
+    def call(**kw):
+        a = dict(base, **kw)
+        return lib.minnorm_solve(h, a["dtype"], a["m"], a["n"], a["A"], a["lda"], a["Alo"], a["ldalo"],
+                                 a["b"], a["ldb"], a["nrhs"], a["eps"], a["N"], a["l"], a["d"], a["idx"],
+                                 a["opts"], a["x"], a["ldx"], None)
+
+    assert call(dtype=-1) == -2
+    assert call(m=10) == -3         # m >= n
+    assert call(m=0) == -3
+    assert call(A=None) == -5
+    assert call(lda=9) == -6
+    assert call(dtype=1, Alo=p, ldalo=10) == -7   # single-precision problem with a copy
+    assert call(Alo=p, ldalo=9) == -8
+    assert call(b=None) == -9
+    assert call(ldb=3) == -10
+    assert call(nrhs=0) == -11
+    assert call(nrhs=65) == -11
+    assert call(eps=0.0) == -12
+    assert call(eps=1.0) == -12
+    assert call(N=24) == -13
+    assert call(l=4) == -14         # l must exceed m
+    assert call(l=17) == -14
+    assert call(d=None) == -15
+    assert call(idx=None) == -16
+    bad = L.MnOpts()
+    bad.alpha = 0.5
+    assert call(opts=C.pointer(bad)) == -17
+    assert call(x=None) == -18
+    assert call(ldx=9) == -19

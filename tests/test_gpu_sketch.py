@@ -1,0 +1,82 @@
+"""GPU parity of Step 1 (srft_sketch) against the oracle's FFT sketch.
+
+Same (d, idx) on both sides.  Bar: per column of S, the relative error is
+at most 20 u log2(N) (u the unit roundoff of the kernel's precision): a
+radix-staged FFT with correctly rounded twiddles has error O(u log N).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, rel, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+U64, U32 = 1.11e-16, 5.96e-8
+
+CASES = [
+    # (m, n, N, l): tiny, ragged n, one-workgroup FFT, four-step FFT
+    (1, 2, 2, 2),
+    (3, 13, 16, 9),
+    (5, 50, 64, 20),
+    (64, 1000, 1024, 256),
+    (37, 1024, 1024, 148),
+    (33, 4096, 4096, 132),
+    (33, 5000, 8192, 132),
+    (17, 65536, 65536, 68),
+]
+
+
+def _colerr(Sg, Sr):
+    return max(float(np.linalg.norm(Sg[:, i] - Sr[:, i]) / max(np.linalg.norm(Sr[:, i]), 1e-300))
+               for i in range(Sr.shape[1]))
+
+
+@pytest.mark.parametrize("m,n,N,l", CASES)
+@pytest.mark.parametrize("kind", ["c128", "c64", "f64", "f32"])
+def test_sketch_parity(m, n, N, l, kind):
+    import torch
+    from paper_0905_4745_amd import api
+    say(f"sketch {kind} m={m} n={n} N={N} l={l}")
+    real = kind.startswith("f")
+    g = np.random.default_rng(m * 7 + n)
+    if real:
+        A = g.standard_normal((m, n))
+    else:
+        A = synth.complex_gaussian(g, (m, n))
+    d, idx = synth.draw_srft(N, l, seed=N + l, real=real)
+    tdt = {"c128": torch.complex128, "c64": torch.complex64, "f64": torch.float64, "f32": torch.float32}[kind]
+    At = to_dev(A, tdt)
+    A_used = to_np(At).astype(np.float64 if real else np.complex128)
+    S = to_np(api.srft_sketch(At, d, idx, N))
+    ref = oracle.sketch_real(A_used, d, idx, N) if real else oracle.sketch(A_used, d, idx, N)
+    u = U32 if kind in ("c64", "f32") else U64
+    err = _colerr(S.astype(ref.dtype), ref)
+    say(f"  col rel err {err:.2e}")
+    assert err <= 20 * u * max(np.log2(N), 1)
+
+
+def test_sketch_rows_of_identity_give_orthonormal_T():
+    """A = I (N x N): S = T, so S S^* = I_l through the GPU kernel."""
+    import torch
+    from paper_0905_4745_amd import api
+    N, l = 64, 24
+    d, idx = synth.draw_srft(N, l, seed=3)
+    T = to_np(api.srft_sketch(to_dev(np.eye(N, dtype=np.complex128)), d, idx, N))
+    assert np.allclose(T @ T.conj().T, np.eye(l), atol=1e-13)
+    assert np.allclose(T, oracle.srft_matrix(N, d, idx), atol=1e-14)
+
+
+def test_sketch_invalid_idx_rejected():
+    import torch
+    from paper_0905_4745_amd import api
+    A = to_dev(np.ones((2, 8), dtype=np.complex128))
+    d, idx = synth.draw_srft(8, 4, seed=1)
+    with pytest.raises(api.MinnormError) as e:
+        api.srft_sketch(A, d, np.array([0, 3, 3, 5], dtype=np.int32), 8)
+    assert e.value.status == -10
+    with pytest.raises(api.MinnormError) as e:
+        api.srft_sketch(A, d, np.array([0, 3, 5, 8], dtype=np.int32), 8)
+    assert e.value.status == -10

@@ -1,0 +1,222 @@
+"""GPU parity of the whole method (minnorm_solve) against the CPU oracle.
+
+Bars: the method guarantees ||x - p|| <= eps ||p|| (Theorem 5.4), so each
+GPU x must lie within eps of the oracle's p (classical FP64 QR, or the
+longdouble-refined solver where cond(A) u64 approaches eps).  With the same
+(d, idx) the GPU iteration must also track the CPU randomized oracle: equal
+iteration counts up to one (rounding can move the stopping test by one step).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, rel, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(A, b, eps, d, idx, N, **kw):
+    from paper_0905_4745_amd import api
+    At = to_dev(A)
+    bt = to_dev(b)
+    x, info = api.minnorm_solve(At, bt, eps, d, idx, N, **kw)
+    return to_np(x), info
+
+
+@pytest.mark.parametrize("m,n,seed", [(64, 1024, 0), (1, 40, 1), (31, 700, 2), (100, 3000, 3), (200, 2000, 4)])
+def test_gaussian_c128(m, n, seed):
+    """Plain complex128 method on Gaussian A (the 64 x 1024, eps = 1e-12 workload and ragged sizes)."""
+    say(f"solve gaussian c128 m={m} n={n}")
+    A, b = synth.make_gaussian(m, n, seed=seed)
+    N = synth.next_pow2(n)
+    l = synth.sketch_width(m, N)
+    d, idx = synth.draw_srft(N, l, seed=seed + 10)
+    eps = 1e-12
+    x, info = _solve(A, b, eps, d, idx, N)
+    p = oracle.classical_minnorm(A, b)
+    err = rel(x, p)
+    o = oracle.randomized_minnorm(A, b, eps, d, idx, N, with_steps23=False)
+    say(f"  err {err:.2e} iters gpu {info['iters']} cpu {o['info']['iters']}")
+    assert info["status"] == 0
+    assert err <= eps
+    assert abs(info["iters"] - o["info"]["iters"]) <= 1
+    assert rel(x, o["x"]) <= eps
+
+
+@pytest.mark.parametrize("m,n,kappa,seed", [(128, 8192, 1e3, 5), (96, 5000, 1e3, 6)])
+def test_svd_c128_kappa_1e3(m, n, kappa, seed):
+    say(f"solve svd c128 m={m} n={n} kappa={kappa}")
+    A, b, _ = synth.make_svd(m, n, kappa, seed=seed)
+    N = synth.next_pow2(n)
+    l = synth.sketch_width(m, N)
+    d, idx = synth.draw_srft(N, l, seed=seed)
+    eps = 1e-10
+    x, info = _solve(A, b, eps, d, idx, N)
+    p = oracle.classical_minnorm(A, b)
+    o = oracle.randomized_minnorm(A, b, eps, d, idx, N, with_steps23=False)
+    say(f"  err {rel(x, p):.2e} iters gpu {info['iters']} cpu {o['info']['iters']}")
+    assert info["status"] == 0
+    assert rel(x, p) <= eps
+    assert abs(info["iters"] - o["info"]["iters"]) <= 1
+
+
+def test_full_size_c128_512x65536():
+    """The 512 x 65536, cond 1e3, eps = 1e-10 workload at full size."""
+    say("solve svd c128 full size m=512 n=65536")
+    A, b, _ = synth.make_svd(512, 65536, 1e3, seed=2)
+    N = 65536
+    l = 2048
+    d, idx = synth.draw_srft(N, l, seed=7)
+    x, info = _solve(A, b, 1e-10, d, idx, N)
+    p = oracle.classical_minnorm(A, b)
+    say(f"  err {rel(x, p):.2e} iters {info['iters']} ms {info['stage_ms']}")
+    assert info["status"] == 0
+    assert rel(x, p) <= 1e-10
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_stop_rules(rule):
+    from paper_0905_4745_amd import api
+    A, b, _ = synth.make_svd(48, 1500, 1e2, seed=9)
+    N = synth.next_pow2(1500)
+    d, idx = synth.draw_srft(N, 192, seed=1)
+    x, info = _solve(A, b, 1e-9, d, idx, N, opts=api.SolveOptions(stop_rule=rule))
+    o = oracle.randomized_minnorm(A, b, 1e-9, d, idx, N, rule="PR"[rule], with_steps23=False)
+    assert rel(x, oracle.classical_minnorm(A, b)) <= 1e-9
+    assert abs(info["iters"] - o["info"]["iters"]) <= 1
+
+
+def test_l_equals_N_and_zero_rhs():
+    A, b = synth.make_gaussian(20, 60, seed=3)
+    N = 64
+    d, idx = synth.draw_srft(N, N, seed=2)
+    x, info = _solve(A, b, 1e-12, d, idx, N)
+    assert info["iters"] <= 2
+    assert rel(x, oracle.classical_minnorm(A, b)) <= 1e-12
+    x0, info0 = _solve(A, np.zeros(20, complex), 1e-12, d, idx, N)
+    assert info0["iters"] == 0 and np.all(x0 == 0)
+
+
+def test_orthonormal_rows_and_known_answer():
+    g = np.random.default_rng(1)
+    Q = np.linalg.qr(synth.complex_gaussian(g, (600, 30)))[0]
+    A = np.ascontiguousarray(Q.conj().T)
+    b = synth.complex_gaussian(g, 30)
+    N = 1024
+    d, idx = synth.draw_srft(N, 120, seed=4)
+    x, _ = _solve(A, b, 1e-12, d, idx, N)
+    assert rel(x, A.conj().T @ b) <= 1e-12
+    # the paper's Section 7 construction, cond 1e3
+    A, b, p, _ = synth.make_known_answer(64, 2048, seed=5, kappa=1e3)
+    d, idx = synth.draw_srft(2048, 256, seed=5)
+    x, _ = _solve(A, b, 1e-10, d, idx, 2048)
+    assert rel(x, p) <= 1e-10
+
+
+def test_multi_rhs_c128():
+    A, B = synth.make_gaussian(40, 900, seed=11, nrhs=3)
+    N = 1024
+    d, idx = synth.draw_srft(N, 160, seed=2)
+    X, info = _solve(A, B, 1e-11, d, idx, N)
+    P = oracle.classical_minnorm(A, B)
+    for k in range(3):
+        assert rel(X[k], P[k]) <= 1e-11
+    assert info["nrhs_done"] == 3
+
+
+def test_real_f64():
+    shapes = synth.make_batch_shapes(3, seed=2, m_lo=16, m_hi=80, n_lo=400, n_hi=3000)
+    for k, (A, b) in enumerate(synth.make_batch(shapes, seed=3, kappa=1e4)):
+        m, n = A.shape
+        N = synth.next_pow2(n)
+        d, idx = synth.draw_srft(N, synth.sketch_width(m, N), seed=k, real=True)
+        x, info = _solve(A, b, 1e-10, d, idx, N)
+        assert info["status"] == 0
+        assert rel(x, oracle.refined_minnorm(A, b)) <= 1e-10
+
+
+def test_mixed_c128_with_c64_copy_kappa_1e6():
+    """complex64 bulk + FP64 refinement at cond 1e6 reaches 1e-10 vs the refined oracle."""
+    import torch
+    from paper_0905_4745_amd import api
+    say("solve mixed c128/c64 kappa 1e6")
+    A, b, _ = synth.make_svd(64, 4096, 1e6, seed=3)
+    N = 4096
+    d, idx = synth.draw_srft(N, 256, seed=3)
+    At = to_dev(A)
+    x, info = api.minnorm_solve(At, to_dev(b), 1e-10, d, idx, N, A_lo=At.to(torch.complex64))
+    p = oracle.refined_minnorm(A, b)
+    say(f"  err {rel(to_np(x), p):.2e} iters {info['iters']} refine {info['refine_steps']}")
+    assert info["status"] == 0
+    assert rel(to_np(x), p) <= 1e-10
+
+
+def test_mixed_real_f64_with_f32_copy():
+    import torch
+    from paper_0905_4745_amd import api
+    A, b, _ = synth.make_svd(50, 3000, 1e4, seed=8, complex_=False)
+    N = 4096
+    d, idx = synth.draw_srft(N, 200, seed=8, real=True)
+    At = to_dev(A)
+    x, info = api.minnorm_solve(At, to_dev(b), 1e-10, d, idx, N, A_lo=At.to(torch.float32))
+    assert info["status"] == 0
+    assert rel(to_np(x), oracle.refined_minnorm(A, b)) <= 1e-10
+
+
+def test_single_precision_problem_c64():
+    """complex64 data is the problem: refinement promotes it exactly to FP64."""
+    from paper_0905_4745_amd import api
+    A64, B = synth.make_row_scaled(48, 2000, 2, seed=4)
+    N = 2048
+    d, idx = synth.draw_srft(N, 192, seed=4)
+    X, info = api.minnorm_solve(to_dev(A64), to_dev(B), 1e-10, d, idx, N)
+    P = oracle.refined_minnorm(A64.astype(np.complex128), B)
+    for k in range(2):
+        assert rel(to_np(X[k]), P[k]) <= 1e-10
+
+
+def test_batched_uneven_real():
+    import torch
+    from paper_0905_4745_amd import api
+    shapes = synth.make_batch_shapes(5, seed=7, m_lo=8, m_hi=64, n_lo=300, n_hi=2000)
+    systems = synth.make_batch(shapes, seed=8, kappa=1e4)
+    As = [to_dev(A) for A, _ in systems]
+    A_los = [a.to(torch.float32) for a in As]
+    bs = [to_dev(b) for _, b in systems]
+    ds, idxs, Ns = [], [], []
+    for k, (m, n) in enumerate(shapes):
+        N = synth.next_pow2(n)
+        d, idx = synth.draw_srft(N, synth.sketch_width(m, N), seed=k, real=True)
+        ds.append(d), idxs.append(idx), Ns.append(N)
+    xs, infos = api.minnorm_solve_batched(As, bs, 1e-10, ds, idxs, Ns, A_los=A_los)
+    for (A, b), x, info in zip(systems, xs, infos):
+        assert info["status"] == 0
+        assert rel(to_np(x), oracle.refined_minnorm(A, b)) <= 1e-10
+
+
+def test_failure_statuses():
+    from paper_0905_4745_amd import api
+    # iteration cap -> +2
+    A, b, _ = synth.make_svd(32, 1000, 1e3, seed=1)
+    N = 1024
+    d, idx = synth.draw_srft(N, 128, seed=1)
+    x, info = _solve(A, b, 1e-12, d, idx, N, opts=api.SolveOptions(max_iter=1), raise_on_status=False)
+    assert info["status"] == 2 and info["iters"] == 1
+    # duplicate rows: A not full rank -> sketch rank-deficient (+1)
+    A2 = A.copy()
+    A2[5] = A2[9]
+    with pytest.raises(api.MinnormError) as e:
+        _solve(A2, b, 1e-10, d, idx, N)
+    assert e.value.status == 1
+    # NaN input -> +4
+    A3 = A.copy()
+    A3[2, 7] = np.nan
+    with pytest.raises(api.MinnormError) as e:
+        _solve(A3, b, 1e-10, d, idx, N)
+    assert e.value.status == 4
+    # invalid idx -> -16
+    with pytest.raises(api.MinnormError) as e:
+        _solve(A, b, 1e-10, d, np.sort(np.concatenate([idx[:-1], idx[:1]])), N)
+    assert e.value.status == -16
