@@ -109,6 +109,17 @@ const char* mn_last_hip_error(void);
 /* Bytes of device workspace the handle currently holds. */
 int64_t mn_workspace_bytes(mn_handle h);
 
+/* Per-kernel timing for measurement (not part of the method).  With
+ * enable != 0, every later launch of the passes over A is bracketed by a
+ * pair of HIP events on the handle's stream; mn_profile_read synchronises the
+ * stream and returns how many launches of `kernel` ("gemv_adj": w = A* u,
+ * "gemv_fwd": q = A w, "gram": the fused q = A (A* p) used when m <= 512)
+ * were recorded since the last mn_profile call and their
+ * summed duration in milliseconds.  mn_profile clears the records.
+ * Errors: -1 NULL handle; -2 unknown kernel name; -3/-4 NULL output. */
+int mn_profile(mn_handle h, int enable);
+int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* total_ms);
+
 /* Step 1, eq. (randmat): S = T A*, T = S F D of size l x N (eqs. SRFT,
  * SRFT2, with H = I), applied to every row of A:
  *   S(k, i) = (F (d o conj(a_i, zero-padded to N)))[idx[k]],  k < l, i < m,
@@ -152,7 +163,7 @@ int build_preconditioner(mn_handle h, int dtype, int64_t l, int64_t m,
  *        (m < l <= N; l = min(4m, N) is the paper's choice).
  *   x    [nrhs x n, FP64 (complex128 / float64), x_j at x + j*ldx]   written
  *   info optional host struct.
- * Errors: -2 dtype; -3 m < 1 or m >= n; -4 n; -5 A; -6 lda; -7 A_lo with a
+ * Errors: -2 dtype; -3 m < 1, m >= n or m > 8192; -4 n; -5 A; -6 lda; -7 A_lo with a
  * single-precision dtype; -8 lda_lo; -9 b; -10 ldb < m; -11 nrhs < 1 or > 64;
  * -12 eps not in (0,1); -13 N; -14 l <= m or l > N; -15 d; -16 idx;
  * -17 opts field out of range; -18 x; -19 ldx < n. */

@@ -31,7 +31,7 @@ class MnInfo(C.Structure):
 
 
 EXPORTS = ["mn_create", "mn_destroy", "mn_set_stream", "mn_status_string", "mn_last_hip_error",
-           "mn_workspace_bytes", "srft_sketch", "build_preconditioner", "minnorm_solve",
+           "mn_workspace_bytes", "mn_profile", "mn_profile_read", "srft_sketch", "build_preconditioner", "minnorm_solve",
            "minnorm_solve_batched"]
 
 _lib = None
@@ -60,6 +60,10 @@ def load():
     lib.mn_last_hip_error.restype = C.c_char_p
     lib.mn_workspace_bytes.argtypes = [P]
     lib.mn_workspace_bytes.restype = I64
+    lib.mn_profile.argtypes = [P, I32]
+    lib.mn_profile.restype = I32
+    lib.mn_profile_read.argtypes = [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    lib.mn_profile_read.restype = I32
     lib.srft_sketch.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, P, I64]
     lib.srft_sketch.restype = I32
     lib.build_preconditioner.argtypes = [P, I32, I64, I64, P, I64, P, I64]

@@ -58,11 +58,16 @@ def _ptr(t):
 def _check_matrix(A, name="A"):
     if not A.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
-    if A.dim() != 2 or A.stride(1) != 1:
+    if A.dim() != 2 or (A.stride(1) != 1 and A.shape[1] > 1):
         raise ValueError(f"{name} must be 2-D with unit column stride (row-major)")
     if A.dtype not in _DT:
         raise ValueError(f"{name} dtype {A.dtype} not supported")
     return _DT[A.dtype]
+
+
+def _ld(t, dim_other, logical):
+    """Leading dimension of a 2-D tensor; a size-1 dimension's stride is arbitrary."""
+    return t.stride(dim_other) if t.shape[dim_other] > 1 else logical
 
 
 def _d_tensor(d, dtype_code, device):
@@ -82,7 +87,7 @@ def srft_sketch(A, d, idx, N: int):
     it = _idx_tensor(idx, A.device)
     l = it.numel()
     St = torch.empty((m, l), dtype=A.dtype, device=A.device)
-    st = L.load().srft_sketch(_handle(A.device), code, m, n, _ptr(A), A.stride(0), int(N), l,
+    st = L.load().srft_sketch(_handle(A.device), code, m, n, _ptr(A), _ld(A, 0, n), int(N), l,
                               _ptr(dt), _ptr(it), _ptr(St), l)
     if st != 0:
         raise MinnormError("srft_sketch", st)
@@ -95,11 +100,11 @@ def build_preconditioner(S, allow_rank_deficient: bool = False):
     S must be column-major (e.g. the view srft_sketch returns).
     """
     l, m = S.shape
-    if S.stride(0) != 1:
+    if S.stride(0) != 1 and l > 1:
         raise ValueError("S must be column-major (stride(0) == 1)")
     code = _DT[S.dtype]
     Rt = torch.empty((m, m), dtype=S.dtype, device=S.device)
-    st = L.load().build_preconditioner(_handle(S.device), code, l, m, _ptr(S), S.stride(1), _ptr(Rt), m)
+    st = L.load().build_preconditioner(_handle(S.device), code, l, m, _ptr(S), _ld(S, 1, l), _ptr(Rt), m)
     if st != 0 and not (st == 1 and allow_rank_deficient):
         raise MinnormError("build_preconditioner", st)
     return Rt.t()
@@ -135,7 +140,7 @@ def minnorm_solve(A, b, eps: float, d, idx, N: int, A_lo=None, opts: SolveOption
     m, n = A.shape
     wide = _WIDE[code]
     b2 = b.reshape(1, -1) if b.dim() == 1 else b
-    if b2.dtype != wide or not b2.is_cuda or b2.stride(1) != 1 or b2.shape[1] != m:
+    if b2.dtype != wide or not b2.is_cuda or (b2.stride(1) != 1 and m > 1) or b2.shape[1] != m:
         raise ValueError(f"b must be a device {wide} tensor with m={m} entries per row")
     nrhs = b2.shape[0]
     if A_lo is not None:
@@ -149,8 +154,8 @@ def minnorm_solve(A, b, eps: float, d, idx, N: int, A_lo=None, opts: SolveOption
         x = torch.empty((nrhs, n), dtype=wide, device=A.device)
     info = L.MnInfo()
     o = (opts or SolveOptions()).to_c()
-    st = L.load().minnorm_solve(_handle(A.device), code, m, n, _ptr(A), A.stride(0), _ptr(A_lo),
-                                A_lo.stride(0) if A_lo is not None else 0, _ptr(b2), b2.stride(0), nrhs,
+    st = L.load().minnorm_solve(_handle(A.device), code, m, n, _ptr(A), _ld(A, 0, n), _ptr(A_lo),
+                                _ld(A_lo, 0, n) if A_lo is not None else 0, _ptr(b2), _ld(b2, 0, m), nrhs,
                                 float(eps), int(N), l, _ptr(dt), _ptr(it), C.byref(o), _ptr(x), x.stride(0),
                                 C.byref(info))
     if st != 0 and raise_on_status:
@@ -178,7 +183,7 @@ def minnorm_solve_batched(As, bs, eps, ds, idxs, Ns, A_los=None, opts: SolveOpti
     PP = C.c_void_p * batch
     m = I64(*[A.shape[0] for A in As])
     n = I64(*[A.shape[1] for A in As])
-    lda = I64(*[A.stride(0) for A in As])
+    lda = I64(*[_ld(A, 0, A.shape[1]) for A in As])
     Ap = PP(*[A.data_ptr() for A in As])
     Alo = PP(*[a.data_ptr() for a in A_los]) if A_los is not None else None
     bp = PP(*[b.data_ptr() for b in bs])
@@ -200,3 +205,22 @@ def minnorm_solve_batched(As, bs, eps, ds, idxs, Ns, A_los=None, opts: SolveOpti
 def workspace_bytes(device=None) -> int:
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     return int(L.load().mn_workspace_bytes(_handle(dev)))
+
+
+def profile(enable: bool, device=None) -> None:
+    """Turn per-launch event timing of the passes over A on or off (clears records)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    st = L.load().mn_profile(_handle(dev), 1 if enable else 0)
+    if st != 0:
+        raise MinnormError("mn_profile", st)
+
+
+def profile_read(kernel: str, device=None):
+    """(launch count, summed milliseconds) of `kernel` since the last profile() call."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    cnt = C.c_int64()
+    ms = C.c_double()
+    st = L.load().mn_profile_read(_handle(dev), kernel.encode(), C.byref(cnt), C.byref(ms))
+    if st != 0:
+        raise MinnormError("mn_profile_read", st)
+    return int(cnt.value), float(ms.value)

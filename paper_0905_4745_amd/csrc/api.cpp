@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,11 @@ struct mn_handle_s {
   double* host_diag = nullptr;     // pinned, 4 doubles
   hipEvent_t ev[9] = {};
   bool events = false;
+  // per-kernel timing (mn_profile): event pairs recorded around launches
+  bool prof = false;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  std::vector<std::pair<int, size_t>> recs;  // (kernel id, index of begin event)
 };
 
 namespace {
@@ -107,6 +113,24 @@ const void* twiddles(mn_handle h, int64_t N, bool single) {
 int fail_hip(hipError_t e) {
   g_last_hip_error = hipGetErrorString(e);
   return MN_HIP_ERROR;
+}
+
+// kernel ids for mn_profile_read
+enum { K_ADJ = 0, K_FWD = 1, K_GRAM = 2 };
+const char* kKernelNames[] = {"gemv_adj", "gemv_fwd", "gram"};
+
+// a begin/end event pair for one timed launch, or nulls when not profiling
+std::pair<hipEvent_t, hipEvent_t> prof_pair(mn_handle h, int kid) {
+  if (!h->prof) return {nullptr, nullptr};
+  while (h->pool.size() < h->pool_used + 2) {
+    hipEvent_t e;
+    ck(hipEventCreate(&e));
+    h->pool.push_back(e);
+  }
+  const size_t i = h->pool_used;
+  h->pool_used += 2;
+  h->recs.push_back({kid, i});
+  return {h->pool[i], h->pool[i + 1]};
 }
 
 void ev_record(mn_handle h, int i) {
@@ -220,40 +244,110 @@ void read_state(mn_handle h, PcgState* src) {
   ck(hipStreamSynchronize(h->stream));
 }
 
+struct CgBufs {
+  void *y, *r[2], *p, *s, *w, *part, *qpart, *q;
+  PcgState* st;
+  int par = 0;
+};
+
+void cg_start(const SolveCtx& c, CgBufs& v, const void* b, const void* parts, int nparts, const void* y_outer) {
+  CgStep a{};
+  a.X = c.X;
+  a.m = c.m;
+  a.start = 1;
+  a.b = b;
+  a.parts = parts;
+  a.nparts = nparts;
+  a.p = v.p;
+  a.y = v.y;
+  a.r_in = nullptr;
+  a.r_out = v.r[v.par];
+  a.s = v.s;
+  a.y_outer = y_outer;
+  a.state = v.st;
+  ck(launch_cg_step(is_complex(c.dtype), a, c.h->stream));
+}
+
 // CG iterations until the device flag is set (checked every check_every).
-void cg_loop(const SolveCtx& c, const PcgVecs& v, void* w, void* part, void* qpart, int max_iter) {
+void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
   mn_handle h = c.h;
-  const int32_t* flag = &v.state->done;
+  const int32_t* flag = &v.st->done;
+  const bool fused = gram_supported(c.bulk, c.m, c.Ab, c.ldab);
   int enqueued = 0;
   while (true) {
     for (int k = 0; k < c.o.check_every; ++k) {
+      if (fused) {
+        GramArgs ga{};
+        ga.A = c.Ab;
+        ga.lda = c.ldab;
+        ga.m = c.m;
+        ga.n = c.n;
+        ga.p = v.p;
+        ga.qpart = v.qpart;
+        ga.q = v.q;
+        ga.flag = flag;
+        std::tie(ga.ev_begin, ga.ev_end) = prof_pair(h, K_GRAM);
+        ck(launch_gram(c.bulk, ga, h->stream));
+        CgStep a{};
+        a.X = c.X;
+        a.m = c.m;
+        a.start = 0;
+        a.b = b;
+        a.parts = v.q;
+        a.nparts = 1;
+        a.p = v.p;
+        a.y = v.y;
+        a.r_in = v.r[v.par];
+        a.r_out = v.r[v.par ^ 1];
+        a.s = v.s;
+        a.state = v.st;
+        ck(launch_cg_step(is_complex(c.dtype), a, h->stream));
+        v.par ^= 1;
+        continue;
+      }
       AdjArgs aa{};
       aa.A = c.Ab;
       aa.lda = c.ldab;
       aa.m = c.m;
       aa.n = c.n;
       aa.u = v.p;
-      aa.w = w;
-      aa.part = part;
+      aa.w = v.w;
+      aa.part = v.part;
       aa.flag = flag;
+      std::tie(aa.ev_begin, aa.ev_end) = prof_pair(h, K_ADJ);
       ck(launch_gemv_adj(c.bulk, false, aa, h->stream));
       FwdArgs fa{};
       fa.A = c.Ab;
       fa.lda = c.ldab;
       fa.m = c.m;
       fa.n = c.n;
-      fa.w = w;
-      fa.qpart = qpart;
+      fa.w = v.w;
+      fa.qpart = v.qpart;
       fa.flag = flag;
       int chunks = 1;
       fa.chunks_out = &chunks;
+      std::tie(fa.ev_begin, fa.ev_end) = prof_pair(h, K_FWD);
       ck(launch_gemv_fwd(c.bulk, false, fa, h->stream));
-      ck(launch_pcg_tail(c.bulk, v, qpart, chunks, h->stream));
+      CgStep a{};
+      a.X = c.X;
+      a.m = c.m;
+      a.start = 0;
+      a.b = b;
+      a.parts = v.qpart;
+      a.nparts = chunks;
+      a.p = v.p;
+      a.y = v.y;
+      a.r_in = v.r[v.par];
+      a.r_out = v.r[v.par ^ 1];
+      a.s = v.s;
+      a.state = v.st;
+      ck(launch_cg_step(is_complex(c.dtype), a, h->stream));
+      v.par ^= 1;
     }
     enqueued += c.o.check_every;
-    read_state(h, v.state);
+    read_state(h, v.st);
     if (h->host_state->done) break;
-    if (enqueued > max_iter + 2 * c.o.check_every) break;  // cannot happen: the tail caps iterations
+    if (enqueued > max_iter + 2 * c.o.check_every) break;  // cannot happen: the kernels cap iterations
   }
 }
 
@@ -262,31 +356,23 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
   mn_handle h = c.h;
   const int64_t W = wide_size(c.dtype);
   const int64_t m = c.m, n = c.n;
-  PcgState* st = (PcgState*)ws(h, "state", sizeof(PcgState));
-  PcgVecs v{};
-  v.R = c.R;
-  v.ldr = m;
-  v.m = m;
-  v.X = c.X;
+  CgBufs v;
+  v.st = (PcgState*)ws(h, "state", sizeof(PcgState));
   v.y = ws(h, "y", m * W);
-  v.r = ws(h, "r", m * W);
+  v.r[0] = ws(h, "r0", m * W);
+  v.r[1] = ws(h, "r1", m * W);
   v.p = ws(h, "p", m * W);
-  v.z = ws(h, "z", m * W);
   v.s = ws(h, "s", m * W);
-  v.q = ws(h, "q", m * W);
-  v.tv = ws(h, "tv", m * W);
-  v.state = st;
   const int64_t bes = is_single(c.bulk) ? W / 2 : W;  // bulk compute element size
-  void* w = ws(h, "w", (size_t)(n * bes + 64));
-  void* part = ws(h, "adj_part", (size_t)(adj_part_elems(m, n) * W + 64));
-  void* qpart = ws(h, "qpart", (size_t)(kMaxChunks * m * W));
-  int status = MN_OK;
+  v.w = ws(h, "w", (size_t)(n * bes + 64));
+  v.part = ws(h, "adj_part", (size_t)(adj_part_elems(m, n) * W + 64));
+  v.qpart = ws(h, "qpart", (size_t)((kMaxChunks > kGramMaxWg ? kMaxChunks : kGramMaxWg) * m * W));
+  v.q = ws(h, "q", m * W);
   ev_record(h, 3);
   if (!c.mixed) {
-    v.b = b;
-    init_state(h, st, c, c.o.stop_rule, c.eps, c.o.max_iter);
-    ck(launch_pcg_start(c.bulk, v, nullptr, 0, nullptr, h->stream));
-    cg_loop(c, v, w, part, qpart, c.o.max_iter);
+    init_state(h, v.st, c, c.o.stop_rule, c.eps, c.o.max_iter);
+    cg_start(c, v, b, nullptr, 0, nullptr);
+    cg_loop(c, v, b, c.o.max_iter);
     ev_record(h, 4);
     // Step 5: x = A* y
     AdjArgs aa{};
@@ -296,20 +382,19 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
     aa.n = n;
     aa.u = v.y;
     aa.w = x;
-    aa.part = part;
+    aa.part = v.part;
     ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
     ev_record(h, 5);
-    read_state(h, st);
+    read_state(h, v.st);
   } else {
     // FP64 refinement: r = b - A A* y_outer in FP64, inner CG in single
     // precision on the bulk copy, y_outer += dy, until the FP64 certificate
     // meets eps.
     void* y_outer = ws(h, "y_outer", m * W);
     void* w64 = ws(h, "w64", (size_t)(n * W + 64));
-    ck(hipMemsetAsync(y_outer, 0, m * W, h->stream));
-    v.b = b;
+    ck(launch_zero(is_complex(c.dtype), y_outer, m, h->stream));
     const double inner_eps = std::pow(10.0, -(double)c.o.inner_digits);
-    init_state(h, st, c, 2, inner_eps, c.o.max_iter);
+    init_state(h, v.st, c, 2, inner_eps, c.o.max_iter);
     for (int outer = 0; outer <= c.o.max_refine + 1; ++outer) {
       AdjArgs aa{};
       aa.A = c.A;
@@ -318,7 +403,7 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
       aa.n = n;
       aa.u = y_outer;
       aa.w = w64;
-      aa.part = part;
+      aa.part = v.part;
       ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
       FwdArgs fa{};
       fa.A = c.A;
@@ -326,15 +411,15 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
       fa.m = m;
       fa.n = n;
       fa.w = w64;
-      fa.qpart = qpart;
+      fa.qpart = v.qpart;
       int chunks = 1;
       fa.chunks_out = &chunks;
       ck(launch_gemv_fwd(c.dtype, true, fa, h->stream));
-      ck(launch_pcg_start(c.bulk, v, qpart, chunks, y_outer, h->stream));
-      read_state(h, st);
+      cg_start(c, v, b, v.qpart, chunks, y_outer);
+      read_state(h, v.st);
       if (h->host_state->outer_done) break;
-      cg_loop(c, v, w, part, qpart, c.o.max_iter);
-      ck(launch_refine_update(is_complex(c.dtype), y_outer, v.y, m, st, h->stream));
+      cg_loop(c, v, b, c.o.max_iter);
+      ck(launch_refine_update(is_complex(c.dtype), y_outer, v.y, m, v.st, h->stream));
     }
     ev_record(h, 4);
     AdjArgs aa{};
@@ -344,13 +429,13 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
     aa.n = n;
     aa.u = y_outer;
     aa.w = x;
-    aa.part = part;
+    aa.part = v.part;
     ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
     ev_record(h, 5);
-    read_state(h, st);
+    read_state(h, v.st);
   }
   const PcgState& s = *h->host_state;
-  status = s.status;
+  int status = s.status;
   if (info) {
     info->iters += s.iter_total;
     info->refine_steps += s.refine_steps;
@@ -430,8 +515,9 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     if (info) info->status = st;
     return st;
   }
-  c.X = ws(h, "Xinv", (size_t)(cdiv(m, 32) * 32 * 32 * wide_size(dtype)));
-  ck(launch_inv_diag(c.bulk, c.R, m, m, c.X, h->stream));
+  const int64_t ldxi = rinv_ld(m);
+  c.X = ws(h, "Xinv", (size_t)(ldxi * ldxi * wide_size(dtype)));
+  ck(launch_rinv(c.bulk, c.R, m, m, c.X, h->stream));
   const int64_t W = wide_size(dtype);
   int worst = MN_OK;
   for (int64_t j = 0; j < nrhs; ++j) {
@@ -466,7 +552,7 @@ int check_solve_args(mn_handle h, int dtype, int64_t m, int64_t n, const void* A
                      const void* d, const int32_t* idx, const mn_opts& o, void* x, int64_t ldx) {
   if (!h) return -1;
   if (dtype < 0 || dtype > 3) return -2;
-  if (m < 1 || m >= n) return -3;
+  if (m < 1 || m >= n || m > kMaxRows) return -3;
   if (n < 2) return -4;
   if (!A) return -5;
   if (lda < n) return -6;
@@ -522,6 +608,7 @@ int mn_destroy(mn_handle h) {
   if (h->host_diag) (void)hipHostFree(h->host_diag);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : h->pool) (void)hipEventDestroy(e);
   delete h;
   return 0;
 }
@@ -545,6 +632,45 @@ const char* mn_status_string(int status) {
 }
 
 const char* mn_last_hip_error(void) { return g_last_hip_error.c_str(); }
+
+int mn_profile(mn_handle h, int enable) {
+  if (!h) return -1;
+  try {
+    ck(hipStreamSynchronize(h->stream));
+  } catch (HipFail f) {
+    return fail_hip(f.e);
+  }
+  h->prof = enable != 0;
+  h->pool_used = 0;
+  h->recs.clear();
+  return 0;
+}
+
+int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* total_ms) {
+  if (!h) return -1;
+  if (!kernel) return -2;
+  if (!count) return -3;
+  if (!total_ms) return -4;
+  int kid = -1;
+  for (int i = 0; i < (int)(sizeof(kKernelNames) / sizeof(kKernelNames[0])); ++i)
+    if (strcmp(kernel, kKernelNames[i]) == 0) kid = i;
+  if (kid < 0) return -2;
+  *count = 0;
+  *total_ms = 0.0;
+  try {
+    ck(hipStreamSynchronize(h->stream));
+    for (auto& r : h->recs) {
+      if (r.first != kid) continue;
+      float t = 0.f;
+      ck(hipEventElapsedTime(&t, h->pool[r.second], h->pool[r.second + 1]));
+      *count += 1;
+      *total_ms += t;
+    }
+  } catch (HipFail f) {
+    return fail_hip(f.e);
+  }
+  return 0;
+}
 
 int64_t mn_workspace_bytes(mn_handle h) {
   if (!h) return -1;

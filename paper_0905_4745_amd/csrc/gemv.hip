@@ -163,6 +163,136 @@ __global__ void __launch_bounds__(256) k_gemv_fwd(const V* __restrict__ A, int64
 }
 
 // ---------------------------------------------------------------------------
+// Fused pass  q = A (A* p)  reading A once (m <= 32 * RPT).
+// Workgroup g (TPB threads) streams column strips of width Wd = 8 * CPT (256
+// bytes of each row).  Thread t owns columns cg*CPT .. +CPT-1 (cg = t % 8) of
+// the strip and rows rg + (TPB/8) k, k < RPT (rg = t / 8), in registers.
+// Per strip:
+//   t_c = sum_r conj(A_rc) p_r   (over rows: 3 shuffles, then the waves via LDS)
+//   qacc_r += sum_c A_rc t_c     (registers, reduced over column groups once
+//                                 per workgroup at the end)
+// Output: qpart[g * m + i], FP64; the strips of a workgroup are contiguous.
+template <typename V, typename C, typename U, int CPT, int RPT, int TPB>
+__global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                              const U* __restrict__ p, int64_t strips_per_wg, int64_t nstrips,
+                                              U* __restrict__ qpart, const int32_t* __restrict__ flag) {
+  if (stopped(flag)) return;
+  constexpr int WD = 8 * CPT;
+  constexpr int VEC = Vec16<V>::n;  // elements per 16-byte load
+  constexpr int LPR = CPT / VEC;    // 16-byte loads per row segment
+  constexpr int RG = TPB / 8;       // row groups
+  constexpr int NW = TPB / 64;      // waves
+  __shared__ C sp[RG * RPT];
+  __shared__ C red[2][NW][WD];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int cg = t & 7, rg = t >> 3;
+  for (int64_t i = t; i < RG * RPT; i += TPB) sp[i] = (i < m) ? vconv<C>(p[i]) : vzero<C>();
+  C qacc[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) qacc[k] = vzero<C>();
+  const int64_t s0 = (int64_t)blockIdx.x * strips_per_wg;
+  int64_t s1 = s0 + strips_per_wg;
+  if (s1 > nstrips) s1 = nstrips;
+  __syncthreads();
+  int slot = 0;
+  for (int64_t sidx = s0; sidx < s1; ++sidx) {
+    const int64_t cbase = sidx * WD + cg * CPT;
+    const bool full = cbase + CPT <= n;
+    V x[RPT][CPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int64_t r = rg + RG * k;
+      if (r < m && full) {
+#pragma unroll
+        for (int q = 0; q < LPR; ++q) {
+          const Pack<V, VEC> pk = loadk<V, VEC>(A + r * lda + cbase + q * VEC);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) x[k][q * VEC + v] = pk.v[v];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) x[k][u] = (r < m && cbase + u < n) ? A[r * lda + cbase + u] : vzero<V>();
+      }
+    }
+    C tp[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) tp[u] = vzero<C>();
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const C pr = sp[rg + RG * k];
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) tp[u] = vcfma(vconv<C>(x[k][u]), pr, tp[u]);
+    }
+    // reduce over the 8 row groups of this wave (lanes equal mod 8)
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+#pragma unroll
+      for (int off = 8; off < 64; off <<= 1) {
+        if constexpr (VT<C>::cplx) {
+          tp[u].re += __shfl_xor(tp[u].re, off, 64);
+          tp[u].im += __shfl_xor(tp[u].im, off, 64);
+        } else {
+          tp[u] += __shfl_xor(tp[u], off, 64);
+        }
+      }
+    }
+    if (lane < 8) {
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) red[slot][wv][lane * CPT + u] = tp[u];
+    }
+    __syncthreads();
+    C tc[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int c = cg * CPT + u;
+      C sum = red[slot][0][c];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) sum = vadd(sum, red[slot][w][c]);
+      tc[u] = sum;
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) qacc[k] = vfma(vconv<C>(x[k][u]), tc[u], qacc[k]);
+    slot ^= 1;
+  }
+  // reduce q over the 8 column groups (low 3 lane bits) and write this
+  // workgroup's partial
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    U v = vconv<U>(qacc[k]);
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      if constexpr (VT<U>::cplx) {
+        v.re += __shfl_xor(v.re, off, 64);
+        v.im += __shfl_xor(v.im, off, 64);
+      } else {
+        v += __shfl_xor(v, off, 64);
+      }
+    }
+    const int64_t r = rg + RG * k;
+    if (cg == 0 && r < m) qpart[(int64_t)blockIdx.x * m + r] = v;
+  }
+}
+
+// q[i] = sum_g qpart[g * m + i], g < G, in a fixed order.  grid = ceil(m/64),
+// 256 threads: four interleaved quarters of the partials, then combined.
+template <typename U>
+__global__ void __launch_bounds__(256) k_gram_reduce(const U* __restrict__ qpart, int G, int64_t m,
+                                                     U* __restrict__ q, const int32_t* __restrict__ flag) {
+  if (stopped(flag)) return;
+  __shared__ U red[4][64];
+  const int rr = threadIdx.x & 63, quarter = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + rr;
+  U acc = vzero<U>();
+  if (i < m)
+    for (int g = quarter; g < G; g += 4) acc = vadd(acc, qpart[(int64_t)g * m + i]);
+  red[quarter][rr] = acc;
+  __syncthreads();
+  if (quarter == 0 && i < m) q[i] = vadd(vadd(red[0][rr], red[1][rr]), vadd(red[2][rr], red[3][rr]));
+}
+
+// ---------------------------------------------------------------------------
 static bool aligned16(const void* p, int64_t ld, int64_t es) {
   return ((uintptr_t)p % 16 == 0) && ((ld * es) % 16 == 0);
 }
@@ -187,14 +317,17 @@ static hipError_t adj_run(const AdjArgs& a, hipStream_t st) {
   const W* u = reinterpret_cast<const W*>(a.u);
   C* w = reinterpret_cast<C*>(a.w);
   W* wide = reinterpret_cast<W*>(a.w_wide);
+  if (a.ev_begin) (void)hipEventRecord(a.ev_begin, st);
   if (rs == 1 && wide == nullptr) {
     hipLaunchKernelGGL((k_gemv_adj<V, C, W, VEC>), dim3((unsigned)nb, 1), dim3(256), 0, st, A, a.lda, a.m, a.n, u,
                        rps, w, a.flag);
+    if (a.ev_end) (void)hipEventRecord(a.ev_end, st);
     return hipGetLastError();
   }
   C* part = reinterpret_cast<C*>(a.part);
   hipLaunchKernelGGL((k_gemv_adj<V, C, W, VEC>), dim3((unsigned)nb, (unsigned)rs), dim3(256), 0, st, A, a.lda, a.m,
                      a.n, u, rps, part, a.flag);
+  if (a.ev_end) (void)hipEventRecord(a.ev_end, st);
   hipLaunchKernelGGL((k_sum_slabs<C, W>), dim3((unsigned)ceil_div(a.n, 256)), dim3(256), 0, st, part, (int)rs, a.n,
                      w, wide, a.flag);
   return hipGetLastError();
@@ -218,9 +351,11 @@ static hipError_t fwd_run(const FwdArgs& a, hipStream_t st) {
   int64_t chunk = ceil_div(a.n, cs);
   chunk = ceil_div(chunk, 256 * VEC) * (256 * VEC);
   cs = ceil_div(a.n, chunk);
+  if (a.ev_begin) (void)hipEventRecord(a.ev_begin, st);
   hipLaunchKernelGGL((k_gemv_fwd<V, C, W, RB, VEC>), dim3((unsigned)cs, (unsigned)rb), dim3(256), 0, st,
                      reinterpret_cast<const V*>(a.A), a.lda, a.m, a.n, reinterpret_cast<const C*>(a.w), chunk,
                      reinterpret_cast<W*>(a.qpart), a.flag);
+  if (a.ev_end) (void)hipEventRecord(a.ev_end, st);
   if (a.chunks_out) *a.chunks_out = (int)cs;
   return hipGetLastError();
 }
@@ -233,6 +368,51 @@ static hipError_t fwd_impl(const FwdArgs& a, hipStream_t st) {
 
 // the widest vector (4 elements) gives the fewest column blocks and hence
 // the most slabs: size the partial buffer for that case
+template <typename V, typename C, typename U>
+static hipError_t gram_impl(const GramArgs& a, hipStream_t st) {
+  constexpr int CPT = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;  // 32 bytes of a row per thread
+  constexpr int WD = 8 * CPT;
+  const int64_t nstrips = ceil_div(a.n, WD);
+  int64_t G = nstrips < kGramMaxWg ? nstrips : kGramMaxWg;
+  const int64_t spw = ceil_div(nstrips, G);
+  G = ceil_div(nstrips, spw);
+  const V* A = reinterpret_cast<const V*>(a.A);
+  const U* p = reinterpret_cast<const U*>(a.p);
+  U* qpart = reinterpret_cast<U*>(a.qpart);
+  if (a.ev_begin) (void)hipEventRecord(a.ev_begin, st);
+  // 512 threads: 64 row groups, RPT rows each
+  if (a.m <= 64)
+    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 1, 512>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
+                       spw, nstrips, qpart, a.flag);
+  else if (a.m <= 128)
+    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 2, 512>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
+                       spw, nstrips, qpart, a.flag);
+  else if (a.m <= 256)
+    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 4, 512>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
+                       spw, nstrips, qpart, a.flag);
+  else
+    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 8, 512>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
+                       spw, nstrips, qpart, a.flag);
+  if (a.ev_end) (void)hipEventRecord(a.ev_end, st);
+  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64)), dim3(256), 0, st, qpart, (int)G, a.m,
+                     reinterpret_cast<U*>(a.q), a.flag);
+  return hipGetLastError();
+}
+
+bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda) {
+  return m <= kGramMaxRows && aligned16(A, lda, dtype_size(dtype));
+}
+
+hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st) {
+  switch (dtype) {
+    case 0: return gram_impl<cd, cd, cd>(a, st);
+    case 1: return gram_impl<cf, cf, cd>(a, st);
+    case 2: return gram_impl<double, double, double>(a, st);
+    case 3: return gram_impl<float, float, double>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 int64_t adj_part_elems(int64_t m, int64_t n) { return slabs_for(m, n, 4) * n; }
 
 // dtype: storage of A; wide: accumulate in FP64 (w in FP64) even for

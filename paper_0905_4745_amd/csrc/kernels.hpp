@@ -10,6 +10,7 @@ constexpr int kQrTile = 32;      // QR tile edge
 constexpr int kFftMaxLds = 4096; // longest FFT done whole in one workgroup's LDS
 constexpr int kMaxSlabs = 64;    // row slabs of the A* pass
 constexpr int kMaxChunks = 256;  // column chunks of the A pass
+constexpr int kMaxRows = 8192;   // largest m (the CG kernels keep an m-vector in LDS)
 
 inline int64_t dtype_size(int dtype) {
   switch (dtype) {
@@ -63,6 +64,7 @@ struct AdjArgs {
   void* w_wide;    // optional FP64 copy of w
   void* part;      // adj_part_elems(m, n) entries of the compute type
   const int32_t* flag;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;  // optional timing of the main kernel
 };
 int64_t adj_part_elems(int64_t m, int64_t n);
 hipError_t launch_gemv_adj(int dtype, bool wide, const AdjArgs& a, hipStream_t st);
@@ -74,31 +76,59 @@ struct FwdArgs {
   void* qpart;     // FP64, kMaxChunks * m
   const int32_t* flag;
   int* chunks_out;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
 };
 hipError_t launch_gemv_fwd(int dtype, bool wide, const FwdArgs& a, hipStream_t st);
 
-// CG state in device memory, written by the single-workgroup kernels.
+// Fused q = A (A* p) in one read of A (m <= kGramMaxRows, 16-byte aligned rows).
+constexpr int kGramMaxRows = 512;
+constexpr int kGramMaxWg = 512;  // partial sums per row
+struct GramArgs {
+  const void* A;
+  int64_t lda, m, n;
+  const void* p;   // FP64, m entries
+  void* qpart;     // FP64, kGramMaxWg * m
+  void* q;         // FP64, m entries (result)
+  const int32_t* flag;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+};
+bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda);
+hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st);
+
+// CG state in device memory, written by workgroup 0 of the CG kernels.
 struct PcgState {
-  double rho0, rho, xi;
+  double rho0, rho, rho_prev, xi;
   double eps, alpha, l, N;
   double eps_outer, outer_rho, outer_xi;
   int32_t rule, max_iter, max_refine, status;
-  int32_t iter_local, iter_total, refine_steps, done;
-  int32_t outer_done, pad[3];
+  int32_t iter_local, iter_total, iter_snap, done;
+  int32_t refine_steps, refine_snap, outer_done, pad;
 };
 
-struct PcgVecs {
-  const void* R;  // m x m, column-major, ldr, R's storage type
-  int64_t ldr, m;
-  const void* X;  // inverted diagonal blocks, FP64
-  const void* b;  // right-hand side of the current solve (FP64)
-  void *y, *r, *p, *z, *s, *q, *tv;  // FP64 m-vectors
+// X = R^{-1} (FP64, column-major, leading dimension rinv_ld(m)).
+int64_t rinv_ld(int64_t m);
+hipError_t launch_rinv(int rdtype, const void* R, int64_t ldr, int64_t m, void* X, hipStream_t st);
+
+// One CG step (see pcg.hip): start = 1 begins a solve from y = 0 with
+// r = b - sum(parts) (parts may be null); start = 0 is an iteration with
+// parts = the partial products of q = A A* p.
+struct CgStep {
+  const void* X;
+  int64_t m;
+  int start;
+  const void* b;
+  const void* parts;
+  int nparts;
+  void *p, *y;
+  const void* r_in;
+  void* r_out;
+  void* s;
+  const void* y_outer;  // start of an FP64 refinement step: certificate test
   PcgState* state;
 };
-hipError_t launch_inv_diag(int rdtype, const void* R, int64_t ldr, int64_t m, void* X, hipStream_t st);
-hipError_t launch_pcg_start(int rdtype, const PcgVecs& v, const void* parts, int nparts, const void* y_outer,
-                            hipStream_t st);
-hipError_t launch_pcg_tail(int rdtype, const PcgVecs& v, const void* qpart, int nparts, hipStream_t st);
-hipError_t launch_refine_update(bool cplx, void* y_outer, const void* y, int64_t m, PcgState* state, hipStream_t st);
+hipError_t launch_cg_step(bool cplx, const CgStep& a, hipStream_t st);
+hipError_t launch_refine_update(bool cplx, void* y_outer, const void* y, int64_t m, const PcgState* state,
+                                hipStream_t st);
+hipError_t launch_zero(bool cplx, void* v, int64_t m, hipStream_t st);
 
 }  // namespace mn

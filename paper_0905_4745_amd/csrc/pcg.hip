@@ -4,11 +4,26 @@
 //
 // The m-vectors of the iteration (y, r, p, z, s, q) are FP64 whatever the
 // precision of A; their inner products and norms, and the stopping test,
-// are FP64 too.  The preconditioner solves R* s = r and R z = s run in FP64
-// on R promoted from its storage precision, blocked by 32 x 32 diagonal
-// blocks whose inverses are formed once (k_inv_diag); R stays in cache.
+// are FP64 too.
 //
-// Stopping rules, with rho = ||R^{-*} r||^2 and xi = Re(y^*(b - r)) = ||A* y||^2
+// Preconditioner.  The two triangular solves s = R^{-*} r and z = R^{-1} s are
+// applied through X = R^{-1}, formed once per factorisation by blocked
+// back substitution on 32 x 32 blocks (diagonal blocks inverted directly, then
+// X_ij = -X_ii sum_{i<k<=j} R_ik X_kj one block diagonal at a time), in FP64
+// from R promoted out of its storage precision.  Each solve is then one
+// triangular matrix-vector product spread over many workgroups, with X (at
+// most m^2 / 2 FP64 entries) resident in the last-level cache.
+//
+// One CG iteration after q = A (A* p) = sum of partial products:
+//   k_cg_s  (column blocks of X)  alpha = rho / p^* q; r' = r - alpha q;
+//                                 y += alpha p; s = X^* r'
+//   k_cg_p  (row bands of X)      rho' = ||s||^2; xi = Re(y^*(b - r'));
+//                                 stopping test; z = X s; p = z + (rho'/rho) p
+// Scalars every workgroup needs (alpha, rho', xi) are recomputed by each
+// workgroup in the same fixed order, so all take identical decisions; only
+// workgroup 0 writes the shared vectors y, r' and the state.
+//
+// Stopping rules, with rho = ||R^{-*} r||^2 and xi = ||A* y||^2
 // (||x - p||^2 <= rho since the SRFT has orthonormal rows):
 //   rule 0 -- the paper's precision for Step 4, f - f* <= delta f*,
 //             delta = eps^2 l / (alpha N): rho <= delta (rho0 - (sqrt xi + sqrt rho)^2)
@@ -20,107 +35,87 @@
 
 namespace mn {
 
-constexpr int TB = 32;        // triangular block
-constexpr int PT = 1024;      // threads of the single-workgroup kernels
+constexpr int TB = 32;  // block edge of X
 
-// X_k = inverse of the k-th 32 x 32 diagonal block of R (upper triangular),
-// in FP64.  Ragged last block padded with the identity.  grid = K blocks.
+// R entry (gi, gk) promoted to FP64, with R extended by the identity beyond m
 template <typename RV, typename W>
-__global__ void __launch_bounds__(256) k_inv_diag(const RV* __restrict__ R, int64_t ldr, int64_t m, W* __restrict__ X) {
+__device__ inline W r_at(const RV* R, int64_t ldr, int64_t m, int64_t gi, int64_t gk) {
+  if (gi < m && gk < m) return vconv<W>(R[gi + gk * ldr]);
+  return gi == gk ? vmake<W>(1.0, 0.0) : vzero<W>();
+}
+
+// Diagonal blocks X_ii = R_ii^{-1} (back substitution, one thread per
+// column of the block).  grid = K blocks, 256 threads.
+template <typename RV, typename W>
+__global__ void __launch_bounds__(256) k_inv_diag(const RV* __restrict__ R, int64_t ldr, int64_t m,
+                                                  W* __restrict__ X, int64_t ldx) {
   __shared__ W T[TB * TB];
   __shared__ W Xs[TB * TB];
   const int64_t c0 = (int64_t)blockIdx.x * TB;
   for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
     const int r = e % TB, c = e / TB;
-    W v = vzero<W>();
-    if (c0 + r < m && c0 + c < m) v = vconv<W>(R[(c0 + r) + (c0 + c) * ldr]);
-    else if (r == c) v = vmake<W>(1.0, 0.0);
-    T[e] = v;
+    T[e] = r_at<RV, W>(R, ldr, m, c0 + r, c0 + c);
     Xs[e] = vzero<W>();
   }
   __syncthreads();
-  // column c of X solves T x = e_c by back substitution (thread c)
   if (threadIdx.x < TB) {
     const int c = threadIdx.x;
     for (int i = c; i >= 0; --i) {
       W acc = (i == c) ? vmake<W>(1.0, 0.0) : vzero<W>();
       for (int j = i + 1; j <= c; ++j) acc = vsub(acc, vmul(T[i + j * TB], Xs[j + c * TB]));
-      // divide by T[i, i]
       const W d = T[i + i * TB];
-      const double den = vabs2(d);
-      Xs[i + c * TB] = vscale(vcmul(d, acc), 1.0 / den);  // conj(d) acc / |d|^2
+      Xs[i + c * TB] = vscale(vcmul(d, acc), 1.0 / vabs2(d));  // acc / d
     }
   }
   __syncthreads();
-  W* Xo = X + (int64_t)blockIdx.x * TB * TB;
-  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) Xo[e] = Xs[e];
-}
-
-// --------------------------- triangular solves ------------------------------
-// s = R^{-*} r.  All PT threads.  r, s in global memory (may alias? no).
-template <typename RV, typename W>
-__device__ void trsv_adj(const RV* __restrict__ R, int64_t ldr, const W* __restrict__ X, int64_t m,
-                         const W* __restrict__ r, W* __restrict__ s, W* acc_sh, W* tmp_sh) {
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int nw = PT / 64;
-  const int64_t K = ceil_div(m, TB);
-  for (int64_t kb = 0; kb < K; ++kb) {
-    const int64_t c0 = kb * TB;
-    const int nb = (int)((m - c0) < TB ? (m - c0) : TB);
-    // acc[c] = sum_{q < c0} conj(R[q, c0 + c]) s[q]
-    for (int c = wv; c < TB; c += nw) {
-      W part = vzero<W>();
-      if (c < nb) {
-        const RV* col = R + (c0 + c) * ldr;
-        for (int64_t q = lane; q < c0; q += 64) part = vcfma(vconv<W>(col[q]), s[q], part);
-      }
-      part = wave_sum(part);
-      if (lane == 0) acc_sh[c] = part;
-    }
-    __syncthreads();
-    if (t < TB) tmp_sh[t] = (t < nb) ? vsub(r[c0 + t], acc_sh[t]) : vzero<W>();
-    __syncthreads();
-    if (t < nb) {
-      const W* Xk = X + kb * TB * TB;
-      W v = vzero<W>();
-      for (int cp = 0; cp <= t; ++cp) v = vcfma(Xk[cp + t * TB], tmp_sh[cp], v);
-      s[c0 + t] = v;
-    }
-    __syncthreads();
+  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+    const int r = e % TB, c = e / TB;
+    X[(c0 + r) + (c0 + c) * ldx] = Xs[e];
   }
 }
 
-// z = R^{-1} s, using tv (global, m entries) as the running right-hand side.
+// Off-diagonal blocks at distance d: X_{i,i+d} = -X_ii sum_{k=i+1}^{i+d} R_ik X_{k,i+d}.
+// grid = K - d blocks, 256 threads; thread t owns row t%32, columns 4*(t/32)..+3.
 template <typename RV, typename W>
-__device__ void trsv_fwd(const RV* __restrict__ R, int64_t ldr, const W* __restrict__ X, int64_t m,
-                         const W* __restrict__ s, W* __restrict__ z, W* __restrict__ tv) {
-  const int t = threadIdx.x;
-  for (int64_t q = t; q < m; q += PT) tv[q] = s[q];
+__global__ void __launch_bounds__(256) k_trtri_step(const RV* __restrict__ R, int64_t ldr, int64_t m,
+                                                    W* __restrict__ X, int64_t ldx, int d) {
+  __shared__ W Rs[TB * TB];
+  __shared__ W Xs[TB * TB];
+  const int i = blockIdx.x, j = i + d;
+  const int64_t i0 = (int64_t)i * TB, j0 = (int64_t)j * TB;
+  const int r = threadIdx.x % TB, cg = (threadIdx.x / TB) * 4;
+  W acc[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
+  for (int k = i + 1; k <= j; ++k) {
+    const int64_t k0 = (int64_t)k * TB;
+    __syncthreads();
+    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+      const int rr = e % TB, cc = e / TB;
+      Rs[e] = r_at<RV, W>(R, ldr, m, i0 + rr, k0 + cc);
+      Xs[e] = X[(k0 + rr) + (j0 + cc) * ldx];
+    }
+    __syncthreads();
+    for (int q = 0; q < TB; ++q) {
+      const W a = Rs[r + q * TB];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = vfma(a, Xs[q + (cg + u) * TB], acc[u]);
+    }
+  }
   __syncthreads();
-  const int64_t K = ceil_div(m, TB);
-  for (int64_t kb = K - 1; kb >= 0; --kb) {
-    const int64_t c0 = kb * TB;
-    const int nb = (int)((m - c0) < TB ? (m - c0) : TB);
-    if (t < nb) {
-      const W* Xk = X + kb * TB * TB;
-      W v = vzero<W>();
-      for (int cp = t; cp < nb; ++cp) v = vfma(Xk[t + cp * TB], tv[c0 + cp], v);
-      z[c0 + t] = v;
-    }
-    __syncthreads();
-    for (int64_t q = t; q < c0; q += PT) {
-      W acc = vzero<W>();
-      for (int c = 0; c < nb; ++c) acc = vfma(vconv<W>(R[q + (c0 + c) * ldr]), z[c0 + c], acc);
-      tv[q] = vsub(tv[q], acc);
-    }
-    __syncthreads();
+  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+    const int rr = e % TB, cc = e / TB;
+    Rs[e] = X[(i0 + rr) + (i0 + cc) * ldx];  // X_ii
   }
-}
-
-template <typename W> __device__ inline double block_dot_re(const W* a, const W* b, int64_t m, double* red) {
-  double p = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += PT) p += vre(vcmul(a[i], b[i]));
-  return block_sum(p, red);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) Xs[r + (cg + u) * TB] = acc[u];
+  __syncthreads();
+  W o[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
+  for (int q = 0; q < TB; ++q) {
+    const W a = Rs[r + q * TB];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) o[u] = vfma(a, Xs[q + (cg + u) * TB], o[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) X[(i0 + r) + (j0 + cg + u) * ldx] = vsub(vzero<W>(), o[u]);
 }
 
 __device__ inline bool stop_test(const PcgState& st, double rho, double xi) {
@@ -134,226 +129,271 @@ __device__ inline bool stop_test(const PcgState& st, double rho, double xi) {
   return rho <= tol * tol * xi;
 }
 
-// Start (or restart) CG from y = 0 with residual r = rhs:
-//   r = rhs, s = R^{-*} r, z = R^{-1} s, p = z, rho0 = rho = ||s||^2.
-// If parts != nullptr, rhs = b - sum_c parts[c*m + i] (an FP64 residual
-// b - A A* y_outer), and the outer certificate test (rule 1 with eps_outer)
-// is evaluated on it first: when it passes, the solve is marked finished.
-template <typename RV, typename W>
-__global__ void __launch_bounds__(PT) k_pcg_start(const RV* __restrict__ R, int64_t ldr, const W* __restrict__ X,
-                                                  int64_t m, const W* __restrict__ b, const W* __restrict__ parts,
-                                                  int nparts, const W* __restrict__ y_outer, W* __restrict__ y,
-                                                  W* __restrict__ r, W* __restrict__ p, W* __restrict__ z,
-                                                  W* __restrict__ s, W* __restrict__ tv, PcgState* __restrict__ st_p) {
-  __shared__ W acc_sh[TB], tmp_sh[TB];
-  __shared__ double red[PT / 64];
-  __shared__ int s_done;
-  PcgState& st = *st_p;
-  if (st.outer_done) return;
-  for (int64_t i = threadIdx.x; i < m; i += PT) {
-    W v = b[i];
-    if (parts) {
+// ---------------------------------------------------------------------------
+// k_cg_s.  start: r' = b - sum(parts) (or b), y = 0.  iter: alpha, r', y.
+// Then s_j = sum_{i<=j} conj(X_ij) r'_i for this workgroup's 8 columns.
+// grid = ceil(m / 8), 256 threads, dynamic LDS = m FP64 entries (r').
+template <typename W>
+__global__ void __launch_bounds__(256) k_cg_s(const W* __restrict__ X, int64_t ldx, int64_t m, int start,
+                                              const W* __restrict__ b, const W* __restrict__ parts, int nparts,
+                                              W* __restrict__ p, W* __restrict__ y, const W* __restrict__ r_in,
+                                              W* __restrict__ r_out, W* __restrict__ s, PcgState* __restrict__ stp) {
+  extern __shared__ unsigned char smem_raw[];
+  W* rs = reinterpret_cast<W*>(smem_raw);
+  __shared__ double red[4];
+  PcgState& st = *stp;
+  const bool lead = blockIdx.x == 0;
+  if (start) {
+    if (st.outer_done) return;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+      W v = b[i];
+      if (parts) {
+        W q = parts[i];
+        for (int c = 1; c < nparts; ++c) q = vadd(q, parts[(int64_t)c * m + i]);
+        v = vsub(v, q);
+      }
+      rs[i] = v;
+      if (lead) {
+        r_out[i] = v;
+        y[i] = vzero<W>();
+      }
+    }
+    if (lead && threadIdx.x == 0) st.refine_snap = st.refine_steps + (parts ? 1 : 0);
+  } else {
+    if (st.done) return;
+    // q = sum of the partial products (kept in p-order), alpha = rho / p^* q
+    double pq = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
       W q = parts[i];
       for (int c = 1; c < nparts; ++c) q = vadd(q, parts[(int64_t)c * m + i]);
-      v = vsub(v, q);
+      rs[i] = q;
+      pq += vre(vcmul(p[i], q));
     }
-    r[i] = v;
-    y[i] = vzero<W>();
-  }
-  __syncthreads();
-  trsv_adj<RV, W>(R, ldr, X, m, r, s, acc_sh, tmp_sh);
-  double rho = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += PT) rho += vabs2(s[i]);
-  rho = block_sum(rho, red);
-  if (parts) {
-    // outer certificate on the FP64 residual: ||x - p|| <= sqrt(rho)/sigma,
-    // sigma >= ~0.9 for an R from single-precision data: test against eps/2
-    double xi = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += PT) xi += vre(vcmul(y_outer[i], vsub(b[i], r[i])));
-    xi = block_sum(xi, red);
-    const double e = 0.5 * st.eps_outer;
-    const double tol = e / (1.0 + e);
-    if (threadIdx.x == 0) {
-      st.outer_rho = rho;
-      st.outer_xi = xi;
-      st.refine_steps += 1;
-      if (!(isfinite(rho) && isfinite(xi))) {
-        st.outer_done = 1;
+    pq = block_sum(pq, red);
+    const double alpha = st.rho / pq;
+    if (!(isfinite(alpha) && pq > 0.0)) {
+      if (lead && threadIdx.x == 0) {
+        st.done = 1;
         st.status = 4;
-      } else if (rho <= tol * tol * xi || (rho == 0.0)) {
-        st.outer_done = 1;
-      } else if (st.refine_steps > st.max_refine) {
-        st.outer_done = 1;
-        st.status = 2;
       }
-      s_done = st.outer_done;
-    }
-    __syncthreads();
-    if (s_done) {
-      if (threadIdx.x == 0) st.done = 1;
       return;
     }
-  }
-  trsv_fwd<RV, W>(R, ldr, X, m, s, z, tv);
-  for (int64_t i = threadIdx.x; i < m; i += PT) p[i] = z[i];
-  if (threadIdx.x == 0) {
-    st.rho0 = rho;
-    st.rho = rho;
-    st.xi = 0.0;
-    st.iter_local = 0;
-    st.done = (rho == 0.0) ? 1 : 0;
-    if (!isfinite(rho)) {
-      st.done = 1;
-      st.status = 4;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+      const W v = vsub(r_in[i], vscale(rs[i], alpha));
+      rs[i] = v;
+      if (lead) {
+        r_out[i] = v;
+        y[i] = vadd(y[i], vscale(p[i], alpha));
+      }
     }
+    if (lead && threadIdx.x == 0) {
+      st.rho_prev = st.rho;
+      st.iter_snap = st.iter_local;
+    }
+  }
+  __syncthreads();
+  // s for columns c0 .. c0+7: wave w takes 2 columns, lanes run down each
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * 8 + 2 * wv;
+  W acc0 = vzero<W>(), acc1 = vzero<W>();
+  const int64_t j0 = c0, j1 = c0 + 1;
+  if (j0 < m) {
+    const W* col = X + j0 * ldx;
+    for (int64_t i = lane; i <= j0; i += 64) acc0 = vcfma(col[i], rs[i], acc0);
+  }
+  if (j1 < m) {
+    const W* col = X + j1 * ldx;
+    for (int64_t i = lane; i <= j1; i += 64) acc1 = vcfma(col[i], rs[i], acc1);
+  }
+  acc0 = wave_sum(acc0);
+  acc1 = wave_sum(acc1);
+  if (lane == 0) {
+    if (j0 < m) s[j0] = acc0;
+    if (j1 < m) s[j1] = acc1;
   }
 }
 
-// One CG iteration's tail, after q = A (A* p) was produced as partial sums.
-template <typename RV, typename W>
-__global__ void __launch_bounds__(PT) k_pcg_tail(const RV* __restrict__ R, int64_t ldr, const W* __restrict__ X,
-                                                 int64_t m, const W* __restrict__ b, const W* __restrict__ qpart,
-                                                 int nparts, W* __restrict__ y, W* __restrict__ r, W* __restrict__ p,
-                                                 W* __restrict__ z, W* __restrict__ s, W* __restrict__ q,
-                                                 W* __restrict__ tv, PcgState* __restrict__ st_p) {
-  __shared__ W acc_sh[TB], tmp_sh[TB];
-  __shared__ double red[PT / 64];
-  __shared__ int s_stop;
-  PcgState& st = *st_p;
-  if (st.done) return;
-  // q = sum of the partial products, and p^* q
-  double pq = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += PT) {
-    W v = qpart[i];
-    for (int c = 1; c < nparts; ++c) v = vadd(v, qpart[(int64_t)c * m + i]);
-    q[i] = v;
-    pq += vre(vcmul(p[i], v));
-  }
-  pq = block_sum(pq, red);
-  const double rho = st.rho;
-  const double alpha = rho / pq;
-  const bool bad = !(isfinite(alpha) && pq > 0.0);
-  if (bad) {
-    if (threadIdx.x == 0) {
-      st.done = 1;
-      st.status = 4;
-    }
-    return;
-  }
-  for (int64_t i = threadIdx.x; i < m; i += PT) {
-    y[i] = vadd(y[i], vscale(p[i], alpha));
-    r[i] = vsub(r[i], vscale(q[i], alpha));
-  }
-  __syncthreads();
-  trsv_adj<RV, W>(R, ldr, X, m, r, s, acc_sh, tmp_sh);
-  double rho_new = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += PT) rho_new += vabs2(s[i]);
-  rho_new = block_sum(rho_new, red);
-  double xi = 0.0;
-  if (st.rule != 2) {
-    for (int64_t i = threadIdx.x; i < m; i += PT) xi += vre(vcmul(y[i], vsub(b[i], r[i])));
-    xi = block_sum(xi, red);
-  }
-  if (threadIdx.x == 0) {
-    int stop = 0;
-    st.iter_local += 1;
-    st.iter_total += 1;
-    st.rho = rho_new;
-    st.xi = xi;
-    if (!isfinite(rho_new)) {
-      st.status = 4;
-      stop = 1;
-    } else if (stop_test(st, rho_new, xi)) {
-      stop = 1;
-    } else if (st.iter_local >= st.max_iter) {
-      stop = 1;
-      if (st.rule != 2) st.status = 2;
-    }
-    s_stop = stop;
-  }
-  __syncthreads();
-  if (s_stop) {
-    if (threadIdx.x == 0) st.done = 1;
-    return;
-  }
-  trsv_fwd<RV, W>(R, ldr, X, m, s, z, tv);
-  const double beta = rho_new / rho;
-  for (int64_t i = threadIdx.x; i < m; i += PT) p[i] = vadd(z[i], vscale(p[i], beta));
-}
-
-// y_outer += y (after an inner solve); re-arms the inner loop's flag.
+// ---------------------------------------------------------------------------
+// k_cg_p.  rho' = ||s||^2 (and xi, the stopping test); z = X s on this
+// workgroup's 16-row band; p = z + beta p (start: p = z, rho0 = rho').
+// With y_outer (start of an FP64 refinement step) the outer certificate is
+// tested first.  grid = ceil(m / 16), 256 threads.
 template <typename W>
-__global__ void k_refine_update(W* __restrict__ y_outer, const W* __restrict__ y, int64_t m, PcgState* st) {
+__global__ void __launch_bounds__(256) k_cg_p(const W* __restrict__ X, int64_t ldx, int64_t m, int start,
+                                              const W* __restrict__ b, const W* __restrict__ y,
+                                              const W* __restrict__ y_outer, const W* __restrict__ r,
+                                              const W* __restrict__ s, W* __restrict__ p,
+                                              PcgState* __restrict__ stp) {
+  constexpr int RB = 16;
+  extern __shared__ unsigned char smem_raw[];
+  W* ss = reinterpret_cast<W*>(smem_raw);  // s, m entries
+  __shared__ double red[4];
+  __shared__ W part[16][RB];
+  PcgState& st = *stp;
+  const bool lead = blockIdx.x == 0;
+  if (start ? (st.outer_done != 0) : (st.done != 0)) return;
+  double rho = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+    const W v = s[i];
+    ss[i] = v;
+    rho += vabs2(v);
+  }
+  rho = block_sum(rho, red);
+  double beta = 0.0;
+  if (start) {
+    if (y_outer) {
+      // FP64 certificate of the current outer iterate: ||x - p|| <= sqrt(rho)/sigma
+      // with sigma >= ~0.9 for an R from single-precision data: test eps/2
+      double xi = 0.0;
+      for (int64_t i = threadIdx.x; i < m; i += blockDim.x) xi += vre(vcmul(y_outer[i], vsub(b[i], r[i])));
+      xi = block_sum(xi, red);
+      const double e = 0.5 * st.eps_outer;
+      const double tol = e / (1.0 + e);
+      int od = 0, status = st.status;
+      if (!(isfinite(rho) && isfinite(xi))) {
+        od = 1;
+        status = 4;
+      } else if (rho <= tol * tol * xi || rho == 0.0) {
+        od = 1;
+      } else if (st.refine_snap > st.max_refine) {
+        od = 1;
+        status = 2;
+      }
+      if (lead && threadIdx.x == 0) {
+        st.outer_rho = rho;
+        st.outer_xi = xi;
+        st.refine_steps = st.refine_snap;
+        st.status = status;
+        if (od) {
+          st.outer_done = 1;
+          st.done = 1;
+        }
+      }
+      if (od) return;
+    }
+    if (lead && threadIdx.x == 0) {
+      st.rho0 = rho;
+      st.rho = rho;
+      st.xi = 0.0;
+      st.iter_local = 0;
+      st.done = (rho == 0.0) ? 1 : 0;
+      if (!isfinite(rho)) {
+        st.done = 1;
+        st.status = 4;
+      }
+    }
+    if (rho == 0.0 || !isfinite(rho)) return;
+  } else {
+    double xi = 0.0;
+    if (st.rule != 2) {
+      for (int64_t i = threadIdx.x; i < m; i += blockDim.x) xi += vre(vcmul(y[i], vsub(b[i], r[i])));
+      xi = block_sum(xi, red);
+    }
+    const int it = st.iter_snap + 1;
+    int stop = 0, status = st.status;
+    if (!isfinite(rho)) {
+      stop = 1;
+      status = 4;
+    } else if (stop_test(st, rho, xi)) {
+      stop = 1;
+    } else if (it >= st.max_iter) {
+      stop = 1;
+      if (st.rule != 2) status = 2;
+    }
+    if (lead && threadIdx.x == 0) {
+      st.iter_local = it;
+      st.iter_total += 1;
+      st.rho = rho;
+      st.xi = xi;
+      st.status = status;
+      if (stop) st.done = 1;
+    }
+    if (stop) return;
+    beta = rho / st.rho_prev;
+  }
+  // z = X s on rows i0 .. i0+15: thread t takes row t%16 and every 16th column
+  const int64_t i0 = (int64_t)blockIdx.x * RB;
+  const int rr = threadIdx.x % RB, cgrp = threadIdx.x / RB;  // 16 column groups
+  const int64_t i = i0 + rr;
+  W acc = vzero<W>();
+  if (i < m)
+    for (int64_t j = i0 + cgrp; j < m; j += 16)
+      if (j >= i) acc = vfma(X[i + j * ldx], ss[j], acc);
+  part[cgrp][rr] = acc;
+  __syncthreads();
+  if (threadIdx.x < RB && i0 + threadIdx.x < m) {
+    W z = part[0][threadIdx.x];
+    for (int c = 1; c < 16; ++c) z = vadd(z, part[c][threadIdx.x]);
+    const int64_t ii = i0 + threadIdx.x;
+    p[ii] = start ? z : vadd(z, vscale(p[ii], beta));
+  }
+}
+
+// y_outer += y (after an inner solve).
+template <typename W>
+__global__ void k_refine_update(W* __restrict__ y_outer, const W* __restrict__ y, int64_t m, const PcgState* st) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (st->outer_done) return;
   if (i < m) y_outer[i] = vadd(y_outer[i], y[i]);
 }
 
-template <typename W> __global__ void k_copy_vec(const W* __restrict__ a, W* __restrict__ b, int64_t m) {
+template <typename W> __global__ void k_zero_vec(W* __restrict__ v, int64_t m) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) b[i] = a[i];
+  if (i < m) v[i] = vzero<W>();
 }
 
 // ------------------------------ launchers -----------------------------------
 template <typename RV, typename W>
-static hipError_t inv_diag_impl(const void* R, int64_t ldr, int64_t m, void* X, hipStream_t st) {
-  hipLaunchKernelGGL((k_inv_diag<RV, W>), dim3((unsigned)ceil_div(m, TB)), dim3(256), 0, st,
-                     reinterpret_cast<const RV*>(R), ldr, m, reinterpret_cast<W*>(X));
+static hipError_t inverse_impl(const void* R, int64_t ldr, int64_t m, void* X, int64_t ldx, hipStream_t st) {
+  const int K = (int)ceil_div(m, TB);
+  hipLaunchKernelGGL((k_inv_diag<RV, W>), dim3(K), dim3(256), 0, st, reinterpret_cast<const RV*>(R), ldr, m,
+                     reinterpret_cast<W*>(X), ldx);
+  for (int d = 1; d < K; ++d)
+    hipLaunchKernelGGL((k_trtri_step<RV, W>), dim3(K - d), dim3(256), 0, st, reinterpret_cast<const RV*>(R), ldr,
+                       m, reinterpret_cast<W*>(X), ldx, d);
   return hipGetLastError();
 }
 
-hipError_t launch_inv_diag(int rdtype, const void* R, int64_t ldr, int64_t m, void* X, hipStream_t st) {
+int64_t rinv_ld(int64_t m) { return ceil_div(m, TB) * TB; }
+
+hipError_t launch_rinv(int rdtype, const void* R, int64_t ldr, int64_t m, void* X, hipStream_t st) {
+  const int64_t ldx = rinv_ld(m);
   switch (rdtype) {
-    case 0: return inv_diag_impl<cd, cd>(R, ldr, m, X, st);
-    case 1: return inv_diag_impl<cf, cd>(R, ldr, m, X, st);
-    case 2: return inv_diag_impl<double, double>(R, ldr, m, X, st);
-    case 3: return inv_diag_impl<float, double>(R, ldr, m, X, st);
+    case 0: return inverse_impl<cd, cd>(R, ldr, m, X, ldx, st);
+    case 1: return inverse_impl<cf, cd>(R, ldr, m, X, ldx, st);
+    case 2: return inverse_impl<double, double>(R, ldr, m, X, ldx, st);
+    case 3: return inverse_impl<float, double>(R, ldr, m, X, ldx, st);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename RV, typename W>
-static hipError_t start_impl(const PcgVecs& v, const void* parts, int nparts, const void* y_outer, hipStream_t st) {
-  hipLaunchKernelGGL((k_pcg_start<RV, W>), dim3(1), dim3(PT), 0, st, reinterpret_cast<const RV*>(v.R), v.ldr,
-                     reinterpret_cast<const W*>(v.X), v.m, reinterpret_cast<const W*>(v.b),
-                     reinterpret_cast<const W*>(parts), nparts, reinterpret_cast<const W*>(y_outer),
-                     reinterpret_cast<W*>(v.y), reinterpret_cast<W*>(v.r), reinterpret_cast<W*>(v.p),
-                     reinterpret_cast<W*>(v.z), reinterpret_cast<W*>(v.s), reinterpret_cast<W*>(v.tv), v.state);
+template <typename W>
+static hipError_t cg_step_impl(const CgStep& a, hipStream_t st) {
+  const W* X = reinterpret_cast<const W*>(a.X);
+  const int64_t ldx = rinv_ld(a.m);
+  const size_t sm = (size_t)a.m * sizeof(W);
+  if (sm > 48 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_s<W>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sm);
+  if (sm > 48 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_p<W>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sm);
+  hipLaunchKernelGGL((k_cg_s<W>), dim3((unsigned)ceil_div(a.m, 8)), dim3(256), sm, st, X, ldx, a.m, a.start,
+                     reinterpret_cast<const W*>(a.b), reinterpret_cast<const W*>(a.parts), a.nparts,
+                     reinterpret_cast<W*>(a.p), reinterpret_cast<W*>(a.y), reinterpret_cast<const W*>(a.r_in),
+                     reinterpret_cast<W*>(a.r_out), reinterpret_cast<W*>(a.s), a.state);
+  hipLaunchKernelGGL((k_cg_p<W>), dim3((unsigned)ceil_div(a.m, 16)), dim3(256), sm, st, X, ldx, a.m, a.start,
+                     reinterpret_cast<const W*>(a.b), reinterpret_cast<const W*>(a.y),
+                     reinterpret_cast<const W*>(a.y_outer), reinterpret_cast<const W*>(a.r_out),
+                     reinterpret_cast<const W*>(a.s), reinterpret_cast<W*>(a.p), a.state);
   return hipGetLastError();
 }
 
-template <typename RV, typename W>
-static hipError_t tail_impl(const PcgVecs& v, const void* qpart, int nparts, hipStream_t st) {
-  hipLaunchKernelGGL((k_pcg_tail<RV, W>), dim3(1), dim3(PT), 0, st, reinterpret_cast<const RV*>(v.R), v.ldr,
-                     reinterpret_cast<const W*>(v.X), v.m, reinterpret_cast<const W*>(v.b),
-                     reinterpret_cast<const W*>(qpart), nparts, reinterpret_cast<W*>(v.y),
-                     reinterpret_cast<W*>(v.r), reinterpret_cast<W*>(v.p), reinterpret_cast<W*>(v.z),
-                     reinterpret_cast<W*>(v.s), reinterpret_cast<W*>(v.q), reinterpret_cast<W*>(v.tv), v.state);
-  return hipGetLastError();
+hipError_t launch_cg_step(bool cplx, const CgStep& a, hipStream_t st) {
+  return cplx ? cg_step_impl<cd>(a, st) : cg_step_impl<double>(a, st);
 }
 
-hipError_t launch_pcg_start(int rdtype, const PcgVecs& v, const void* parts, int nparts, const void* y_outer,
-                            hipStream_t st) {
-  switch (rdtype) {
-    case 0: return start_impl<cd, cd>(v, parts, nparts, y_outer, st);
-    case 1: return start_impl<cf, cd>(v, parts, nparts, y_outer, st);
-    case 2: return start_impl<double, double>(v, parts, nparts, y_outer, st);
-    case 3: return start_impl<float, double>(v, parts, nparts, y_outer, st);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_pcg_tail(int rdtype, const PcgVecs& v, const void* qpart, int nparts, hipStream_t st) {
-  switch (rdtype) {
-    case 0: return tail_impl<cd, cd>(v, qpart, nparts, st);
-    case 1: return tail_impl<cf, cd>(v, qpart, nparts, st);
-    case 2: return tail_impl<double, double>(v, qpart, nparts, st);
-    case 3: return tail_impl<float, double>(v, qpart, nparts, st);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_refine_update(bool cplx, void* y_outer, const void* y, int64_t m, PcgState* state,
+hipError_t launch_refine_update(bool cplx, void* y_outer, const void* y, int64_t m, const PcgState* state,
                                 hipStream_t st) {
   if (cplx)
     hipLaunchKernelGGL(k_refine_update<cd>, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st,
@@ -361,6 +401,16 @@ hipError_t launch_refine_update(bool cplx, void* y_outer, const void* y, int64_t
   else
     hipLaunchKernelGGL(k_refine_update<double>, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st,
                        reinterpret_cast<double*>(y_outer), reinterpret_cast<const double*>(y), m, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(bool cplx, void* v, int64_t m, hipStream_t st) {
+  if (cplx)
+    hipLaunchKernelGGL(k_zero_vec<cd>, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, reinterpret_cast<cd*>(v),
+                       m);
+  else
+    hipLaunchKernelGGL(k_zero_vec<double>, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st,
+                       reinterpret_cast<double*>(v), m);
   return hipGetLastError();
 }
 

@@ -53,73 +53,134 @@ __device__ inline void make_reflector(V alpha, typename VT<V>::real xn2, V& tau,
 }
 
 // ---------------------------------------------------------------------------
-// Reduce the NB x NB tile T (LDS, column-major, ld NB) to upper-triangular
-// form.  On exit T holds beta on the diagonal, v below it, tau[] the scalars.
-// All 256 threads take part.
+// Tile factorisations in LDS by all four waves.  Wave w owns columns
+// 8w .. 8w+7; lane (cl = lane % 8, g = lane / 8) owns column 8w + cl and rows
+// 4g .. 4g+3.  Each wave recomputes the pivot column's reflector from LDS, so
+// one barrier per column step suffices.
+
+template <typename S> __device__ inline S sum_over_g(S v) {
+  // lanes with equal lane % 8 (the 8 row groups of a column)
+#pragma unroll
+  for (int off = 8; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline cd sum_over_g(cd v) { return cd{sum_over_g(v.re), sum_over_g(v.im)}; }
+__device__ inline cf sum_over_g(cf v) { return cf{sum_over_g(v.re), sum_over_g(v.im)}; }
+
+// Reduce the NB x NB tile T (LDS, ld NB) to upper-triangular form: on exit
+// beta on the diagonal, v below it, tau[] the scalars.  All 256 threads; the
+// tile must be in LDS and visible (barrier) before the call.
 template <typename V>
-__device__ void geqrt_lds(V* T, V* tau, typename VT<V>::real* red) {
+__device__ void geqrt_lds(V* T, V* tau) {
   using R = typename VT<V>::real;
-  const int t = threadIdx.x;
-  const int lane = t & 63, wv = t >> 6;
-  __shared__ V s_scal;
-  __shared__ R s_beta;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = 8 * w + (lane & 7), g = lane >> 3;
   for (int j = 0; j < NB; ++j) {
-    if (wv == 0) {
-      R p = (lane > j && lane < NB) ? vabs2(T[lane + j * NB]) : (R)0;
-      p = wave_sum(p);
-      if (lane == 0) {
-        V tj, sc;
-        R bt;
-        make_reflector<V>(T[j + j * NB], p, tj, bt, sc);
-        tau[j] = tj;
-        s_scal = sc;
-        s_beta = bt;
+    V pk[4];
+    R part = (R)0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = 4 * g + k;
+      pk[k] = T[r + j * NB];
+      if (r > j) part += vabs2(pk[k]);
+    }
+    const R xn2 = sum_over_g(part);
+    V tj, sc;
+    R bt;
+    make_reflector<V>(T[j + j * NB], xn2, tj, bt, sc);
+    V vk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = 4 * g + k;
+      vk[k] = (r == j) ? vmake<V>(1.0, 0.0) : (r > j ? vmul(pk[k], sc) : vzero<V>());
+    }
+    const bool upd = c > j;
+    V o[4];
+    V wsum = vzero<V>();
+    if (upd) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        o[k] = T[(4 * g + k) + c * NB];
+        wsum = vcfma(vk[k], o[k], wsum);
       }
     }
+    wsum = sum_over_g(wsum);
+    const V f = vmul(vconj(tj), wsum);
+    if (upd) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (4 * g + k >= j) T[(4 * g + k) + c * NB] = vsub(o[k], vmul(vk[k], f));
+    }
+    // every wave has read column j: its owner may now overwrite it; column
+    // j+1, read next, was finished above by its owner
     __syncthreads();
-    const V sc = s_scal;
-    const V tj = tau[j];
-    // trailing columns c > j: 8 lanes per column, 4 rows each
-    {
-      const int c = j + 1 + (t >> 3);
-      const int q0 = (t & 7) * 4;
-      V part = vzero<V>();
-      V vq[4], aq[4];
-      if (c < NB) {
+    if (c == j) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int q = q0 + u;
-          vq[u] = (q == j) ? vmake<V>(1.0, 0.0) : (q > j ? vmul(T[q + j * NB], sc) : vzero<V>());
-          aq[u] = T[q + c * NB];
-          part = vcfma(vq[u], aq[u], part);
-        }
-      }
-      // reduce over the 8 lanes of this column (always executed by all lanes)
-#pragma unroll
-      for (int off = 1; off < 8; off <<= 1) {
-        if constexpr (VT<V>::cplx) {
-          part.re += __shfl_xor(part.re, off, 64);
-          part.im += __shfl_xor(part.im, off, 64);
-        } else {
-          part += __shfl_xor(part, off, 64);
-        }
-      }
-      if (c < NB) {
-        const V f = vmul(vconj(tj), part);  // conj(tau) w
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int q = q0 + u;
-          if (q >= j) T[q + c * NB] = vsub(aq[u], vmul(vq[u], f));
-        }
+      for (int k = 0; k < 4; ++k) {
+        const int r = 4 * g + k;
+        if (r > j) T[r + j * NB] = vk[k];
+        else if (r == j) T[j + j * NB] = vmake<V>((double)bt, 0.0);
       }
     }
-    __syncthreads();
-    if (t < NB) {
-      if (t > j) T[t + j * NB] = vmul(T[t + j * NB], sc);
-      else if (t == j) T[j + j * NB] = vmake<V>((double)s_beta, 0.0);
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) tau[j] = tj;
   }
+  __syncthreads();
+}
+
+// Merge two triangles in LDS: [R1; R2] -> R1 new triangle, R2's upper part
+// the reflector tails v2, tau[] the scalars.  All 256 threads; inputs must be
+// in LDS and visible before the call.
+template <typename V>
+__device__ void ttqrt_lds(V* R1, V* R2, V* tau) {
+  using R = typename VT<V>::real;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = 8 * w + (lane & 7), g = lane >> 3;
+  for (int j = 0; j < NB; ++j) {
+    V pk[4];
+    R part = (R)0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = 4 * g + k;
+      pk[k] = (r <= j) ? R2[r + j * NB] : vzero<V>();
+      part += vabs2(pk[k]);
+    }
+    const R xn2 = sum_over_g(part);
+    V tj, sc;
+    R bt;
+    make_reflector<V>(R1[j + j * NB], xn2, tj, bt, sc);
+    V vk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) vk[k] = vmul(pk[k], sc);
+    V o[4];
+    V wsum = vzero<V>();
+    const bool upd = c > j;
+    if (upd) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        o[k] = R2[(4 * g + k) + c * NB];
+        wsum = vcfma(vk[k], o[k], wsum);
+      }
+      if (g == 0) wsum = vadd(wsum, R1[j + c * NB]);
+    }
+    wsum = sum_over_g(wsum);
+    const V f = vmul(vconj(tj), wsum);
+    if (upd) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (4 * g + k <= j) R2[(4 * g + k) + c * NB] = vsub(o[k], vmul(vk[k], f));
+      if (g == 0) R1[j + c * NB] = vsub(R1[j + c * NB], f);
+    }
+    // every wave has read column j: its owner may now overwrite it
+    __syncthreads();
+    if (c == j) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (4 * g + k <= j) R2[(4 * g + k) + j * NB] = vk[k];
+      if (g == 0) R1[j + j * NB] = vmake<V>((double)bt, 0.0);
+    }
+    if (threadIdx.x == 0) tau[j] = tj;
+  }
+  __syncthreads();
 }
 
 // Apply Q^* of a geqrt'd tile (reflectors in T, tau) to the tile C held in
@@ -149,78 +210,6 @@ __device__ inline void apply_geqrt(const V* T, const V* tau, V* c) {
     const V f = vmul(vconj(tau[r]), part);
 #pragma unroll
     for (int u = 0; u < 4; ++u) c[u] = vsub(c[u], vmul(vq[u], f));
-  }
-}
-
-// Merge two triangles: [R1; R2] (LDS, column-major NB x NB each) -> R1 new
-// triangle, R2 upper part holds the reflector tails v2, tau[] the scalars.
-template <typename V>
-__device__ void ttqrt_lds(V* R1, V* R2, V* tau) {
-  using R = typename VT<V>::real;
-  const int t = threadIdx.x;
-  const int lane = t & 63, wv = t >> 6;
-  __shared__ V s_scal;
-  __shared__ R s_beta;
-  for (int j = 0; j < NB; ++j) {
-    if (wv == 0) {
-      R p = (lane <= j) ? vabs2(R2[lane + j * NB]) : (R)0;
-      p = wave_sum(p);
-      if (lane == 0) {
-        V tj, sc;
-        R bt;
-        make_reflector<V>(R1[j + j * NB], p, tj, bt, sc);
-        tau[j] = tj;
-        s_scal = sc;
-        s_beta = bt;
-      }
-    }
-    __syncthreads();
-    const V sc = s_scal;
-    const V tj = tau[j];
-    {
-      const int c = j + 1 + (t >> 3);
-      const int q0 = (t & 7) * 4;
-      V part = vzero<V>();
-      V vq[4], aq[4];
-      V top = vzero<V>();
-      if (c < NB) {
-        if ((t & 7) == 0) {
-          top = R1[j + c * NB];
-          part = top;  // conj(1) * R1[j, c]
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int q = q0 + u;
-          vq[u] = (q <= j) ? vmul(R2[q + j * NB], sc) : vzero<V>();
-          aq[u] = R2[q + c * NB];
-          part = vcfma(vq[u], aq[u], part);
-        }
-      }
-#pragma unroll
-      for (int off = 1; off < 8; off <<= 1) {
-        if constexpr (VT<V>::cplx) {
-          part.re += __shfl_xor(part.re, off, 64);
-          part.im += __shfl_xor(part.im, off, 64);
-        } else {
-          part += __shfl_xor(part, off, 64);
-        }
-      }
-      if (c < NB) {
-        const V f = vmul(vconj(tj), part);
-        if ((t & 7) == 0) R1[j + c * NB] = vsub(top, f);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int q = q0 + u;
-          if (q <= j) R2[q + c * NB] = vsub(aq[u], vmul(vq[u], f));
-        }
-      }
-    }
-    __syncthreads();
-    if (t < NB) {
-      if (t <= j) R2[t + j * NB] = vmul(R2[t + j * NB], sc);
-      if (t == j) R1[j + j * NB] = vmake<V>((double)s_beta, 0.0);
-    }
-    __syncthreads();
   }
 }
 
@@ -304,13 +293,12 @@ __global__ void __launch_bounds__(256) k_qr_level0(V* __restrict__ Sp, int64_t l
                                                    V* __restrict__ Rdiag, int write_diag) {
   __shared__ V T[NB * NB];
   __shared__ V tau[NB];
-  __shared__ typename VT<V>::real red[4];
   const int i = k + blockIdx.x;
   const int jj = blockIdx.y;
   const V* tile_ik = Sp + (int64_t)i * NB + (int64_t)k * NB * lp;
   tile_to_lds(T, tile_ik, lp);
   __syncthreads();
-  geqrt_lds<V>(T, tau, red);
+  geqrt_lds<V>(T, tau);
   if (jj == 0) {
     triu_store(Rb + (int64_t)i * NB * NB, T);
     if (write_diag) triu_store(Rdiag + (int64_t)k * NB * NB, T);

@@ -220,3 +220,20 @@ def test_failure_statuses():
     with pytest.raises(api.MinnormError) as e:
         _solve(A, b, 1e-10, d, np.sort(np.concatenate([idx[:-1], idx[:1]])), N)
     assert e.value.status == -16
+
+
+@pytest.mark.parametrize("m,n,kind", [(640, 6000, "c128"), (700, 5001, "f64"), (96, 3001, "c128")])
+def test_unfused_and_unaligned_paths(m, n, kind):
+    """m > 512 (separate A* p and A w passes) and rows that are not 16-byte
+    aligned (odd n for real data) go through the unfused kernels."""
+    say(f"solve {kind} m={m} n={n}")
+    real = kind == "f64"
+    A, b, _ = synth.make_svd(m, n, 1e2, seed=m, complex_=not real)
+    N = synth.next_pow2(n)
+    l = synth.sketch_width(m, N)
+    d, idx = synth.draw_srft(N, l, seed=m, real=real)
+    x, info = _solve(A, b, 1e-10, d, idx, N)
+    p = oracle.classical_minnorm(A, b)
+    say(f"  err {rel(x, p):.2e} iters {info['iters']}")
+    assert info["status"] == 0
+    assert rel(x, p) <= 1e-10
