@@ -294,7 +294,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
         a.start = 0;
         a.b = b;
         a.parts = v.q;
-        a.nparts = 1;
+        a.nparts = kGramParts;
         a.p = v.p;
         a.y = v.y;
         a.r_in = v.r[v.par];
@@ -367,7 +367,7 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
   v.w = ws(h, "w", (size_t)(n * bes + 64));
   v.part = ws(h, "adj_part", (size_t)(adj_part_elems(m, n) * W + 64));
   v.qpart = ws(h, "qpart", (size_t)((kMaxChunks > kGramMaxWg ? kMaxChunks : kGramMaxWg) * m * W));
-  v.q = ws(h, "q", m * W);
+  v.q = ws(h, "q", kGramParts * m * W);
   ev_record(h, 3);
   if (!c.mixed) {
     init_state(h, v.st, c, c.o.stop_rule, c.eps, c.o.max_iter);

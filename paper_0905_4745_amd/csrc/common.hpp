@@ -120,15 +120,44 @@ __host__ __device__ inline bool vfinite(cf a) { return isfinite(a.re) && isfinit
 __device__ inline cd vmul_negi(cd a) { return cd{a.im, -a.re}; }
 __device__ inline cf vmul_negi(cf a) { return cf{a.im, -a.re}; }
 
+// ---- DPP lane exchanges (VALU, no LDS traffic) ------------------------------
+// quad_perm xor 1, quad_perm xor 2, mirror within 8 lanes, mirror within 16,
+// rotation by 8 within 16.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+constexpr int kDppRor8 = 0x128;  // rotate right by 8 within 16-lane rows (= lane ^ 8)
+template <int CTRL> __device__ inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ inline float dpp(float v) { return __int_as_float(dpp_i<CTRL>(__float_as_int(v))); }
+template <int CTRL> __device__ inline double dpp(double v) {
+  const int lo = dpp_i<CTRL>(__double2loint(v)), hi = dpp_i<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL> __device__ inline cd dpp(cd v) { return cd{dpp<CTRL>(v.re), dpp<CTRL>(v.im)}; }
+template <int CTRL> __device__ inline cf dpp(cf v) { return cf{dpp<CTRL>(v.re), dpp<CTRL>(v.im)}; }
+
+// Sum over aligned groups of 8 (16) consecutive lanes; every lane of the
+// group receives the sum.  The combination order is fixed.
+template <typename S> __device__ inline S sum8(S v) {
+  v = vadd(v, dpp<kDppXor1>(v));
+  v = vadd(v, dpp<kDppXor2>(v));
+  v = vadd(v, dpp<kDppHalfMirror>(v));
+  return v;
+}
+template <typename S> __device__ inline S sum16(S v) { return vadd(sum8(v), dpp<kDppMirror>(sum8(v))); }
+
 // ---- wave / workgroup reductions (fixed order: deterministic) -------------
+// Sum over the 64-lane wave: DPP within 16-lane rows, then two shuffles.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  v = sum16(v);
+  v += __shfl_xor(v, 16, kWave);
+  v += __shfl_xor(v, 32, kWave);
   return v;
 }
 __device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  v = sum16(v);
+  v += __shfl_xor(v, 16, kWave);
+  v += __shfl_xor(v, 32, kWave);
   return v;
 }
 __device__ inline cd wave_sum(cd v) { return cd{wave_sum(v.re), wave_sum(v.im)}; }

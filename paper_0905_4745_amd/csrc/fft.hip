@@ -64,28 +64,21 @@ template <int E, typename C> __device__ inline C w16(C a) {
   }
 }
 
+// 8 = 2 x 4: r = r2 + 4 r1, k = k1 + 2 k2.  Output X[k] is left in
+// v[perm8(k)] = v[4 (k % 2) + k / 2].
 template <typename C> __device__ inline void dft8(C* v) {
-  // 8 = 2 x 4: r = r2 + 4 r1, k = k1 + 2 k2
 #pragma unroll
   for (int r2 = 0; r2 < 4; ++r2) dft2(v[r2], v[r2 + 4]);
   v[5] = w16<2>(v[5]);
   v[6] = w16<4>(v[6]);
   v[7] = w16<6>(v[7]);
-  C u[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) u[i] = v[i];
-  // k1 = 0 uses u[0..3], k1 = 1 uses u[4..7]
-  dft4(u[0], u[1], u[2], u[3]);
-  dft4(u[4], u[5], u[6], u[7]);
-#pragma unroll
-  for (int k2 = 0; k2 < 4; ++k2) {
-    v[2 * k2] = u[k2];
-    v[2 * k2 + 1] = u[4 + k2];
-  }
+  dft4(v[0], v[1], v[2], v[3]);
+  dft4(v[4], v[5], v[6], v[7]);
 }
 
+// 16 = 4 x 4: r = r2 + 4 r1, k = k1 + 4 k2.  Output X[k] is left in
+// v[perm16(k)] = v[4 (k % 4) + k / 4].
 template <typename C> __device__ inline void dft16(C* v) {
-  // 16 = 4 x 4: r = r2 + 4 r1, k = k1 + 4 k2
 #pragma unroll
   for (int r2 = 0; r2 < 4; ++r2) dft4(v[r2], v[r2 + 4], v[r2 + 8], v[r2 + 12]);
   // now v[r2 + 4 k1] holds u[r2][k1]; twiddle W16^{r2 k1}
@@ -100,14 +93,11 @@ template <typename C> __device__ inline void dft16(C* v) {
   v[15] = w16<9>(v[15]);
 #pragma unroll
   for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
-  // v[4 k1 + k2] holds X[k1 + 4 k2]; transpose into natural order
-  C u[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) u[i] = v[i];
-#pragma unroll
-  for (int k1 = 0; k1 < 4; ++k1)
-#pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = u[4 * k1 + k2];
+}
+
+// register slot holding output k of a radix-R butterfly
+template <int R> __host__ __device__ constexpr int out_slot(int k) {
+  return R == 16 ? 4 * (k % 4) + k / 4 : (R == 8 ? 4 * (k % 2) + k / 2 : k);
 }
 
 template <int R, typename C> __device__ inline void dftR(C* v) {
@@ -157,7 +147,7 @@ __device__ inline void fft_stage(C* buf, int L, int Ns, int tpf, int tl, const C
       const int jm = j % Ns;
       const int d0 = (j / Ns) * Ns * R + jm;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lpad(d0 + r * Ns)] = v[s * R + r];
+      for (int r = 0; r < R; ++r) buf[lpad(d0 + r * Ns)] = v[s * R + out_slot<R>(r)];
     }
   }
   __syncthreads();
@@ -215,13 +205,22 @@ __global__ void __launch_bounds__(256) k_sketch_small(const V* __restrict__ A, i
   const int E = L < 16 ? L : 16;
   const int tpf = L / E;
   const int64_t row0 = (int64_t)blockIdx.x * B;
-  // load: consecutive threads read consecutive entries of one row
-  for (int t = threadIdx.x; t < B * L; t += blockDim.x) {
-    const int b = t / L, pos = t % L;
-    const int64_t i = row0 + b;
-    C v = vzero<C>();
-    if (i < m) v = load_row_entry<V, C>(A + i * lda, pos, n, d);
-    sm[b * Lp + lpad(pos)] = v;
+  // load: consecutive threads read consecutive entries of one row; all of a
+  // thread's loads are issued before any is used
+  {
+    C v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = threadIdx.x + u * 256;
+      const int b = t / L, pos = t % L;
+      const int64_t i = row0 + b;
+      v[u] = (t < B * L && i < m) ? load_row_entry<V, C>(A + i * lda, pos, n, d) : vzero<C>();
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = threadIdx.x + u * 256;
+      if (t < B * L) sm[(t / L) * Lp + lpad(t % L)] = v[u];
+    }
   }
   __syncthreads();
   const int b = threadIdx.x / tpf, tl = threadIdx.x % tpf;
@@ -268,13 +267,22 @@ __global__ void __launch_bounds__(256) k_sketch_cols(const V* __restrict__ A, in
   const int c0 = blockIdx.x * B;
   const int64_t N = (int64_t)N1 * N2;
   const V* row = A + i * lda;
-  // load: consecutive threads take consecutive n1 (contiguous in memory)
-  for (int t = threadIdx.x; t < B * N2; t += blockDim.x) {
-    const int bb = t % B, n2 = t / B;
-    const int64_t j = (int64_t)c0 + bb + (int64_t)N1 * n2;
-    C v = vzero<C>();
-    if (i < m) v = load_row_entry<V, C>(row, j, n, d);
-    sm[bb * Lp + lpad(n2)] = v;
+  // load: consecutive threads take consecutive n1 (contiguous in memory);
+  // B * N2 <= 4096 = 16 per thread, all issued before use
+  {
+    C v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = threadIdx.x + u * 256;
+      const int bb = t % B, n2 = t / B;
+      const int64_t j = (int64_t)c0 + bb + (int64_t)N1 * n2;
+      v[u] = (t < B * N2 && i < m) ? load_row_entry<V, C>(row, j, n, d) : vzero<C>();
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = threadIdx.x + u * 256;
+      if (t < B * N2) sm[(t % B) * Lp + lpad(t / B)] = v[u];
+    }
   }
   __syncthreads();
   const int E = N2 < 16 ? N2 : 16;
@@ -298,13 +306,20 @@ __global__ void __launch_bounds__(256) k_sketch_cols(const V* __restrict__ A, in
   if (i >= m) return;
   // twiddle W_N^{n1 k2} and store Y[i][k2][n1]: consecutive threads, consecutive n1
   C* Yi = Y + (int64_t)blockIdx.y * N;
-  for (int t = threadIdx.x; t < B * N2; t += blockDim.x) {
-    const int bb = t % B, k2 = t / B;
-    const int n1 = c0 + bb;
-    C v = sm[bb * Lp + lpad(k2)];
-    const int64_t e = (int64_t)n1 * k2;  // < N
-    if (e) v = vmul(v, tw[e]);
-    Yi[(int64_t)k2 * N1 + n1] = v;
+  C wv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int t = threadIdx.x + u * 256;
+    const int64_t e = (int64_t)(c0 + t % B) * (t / B);  // n1 k2 < N
+    wv[u] = (t < B * N2) ? tw[e] : vzero<C>();
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int t = threadIdx.x + u * 256;
+    if (t < B * N2) {
+      const int bb = t % B, k2 = t / B;
+      Yi[(int64_t)k2 * N1 + c0 + bb] = vmul(sm[bb * Lp + lpad(k2)], wv[u]);
+    }
   }
 }
 
@@ -324,9 +339,18 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, in
   const int64_t i = row0 + blockIdx.y;
   const int c0 = blockIdx.x * B;
   const C* Yi = Y + (int64_t)blockIdx.y * N;
-  for (int t = threadIdx.x; t < B * N1; t += blockDim.x) {
-    const int bb = t / N1, n1 = t % N1;
-    sm[bb * Lp + lpad(n1)] = (i < m) ? Yi[(int64_t)(c0 + bb) * N1 + n1] : vzero<C>();
+  {
+    C v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = threadIdx.x + u * 256;
+      v[u] = (t < B * N1 && i < m) ? Yi[(int64_t)(c0 + t / N1) * N1 + t % N1] : vzero<C>();
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = threadIdx.x + u * 256;
+      if (t < B * N1) sm[(t / N1) * Lp + lpad(t % N1)] = v[u];
+    }
   }
   __syncthreads();
   const int E = N1 < 16 ? N1 : 16;
@@ -348,11 +372,16 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, in
     }
   }
   if (i >= m) return;
-  for (int t = threadIdx.x; t < B * N1; t += blockDim.x) {
-    const int bb = t / N1, k1 = t % N1;
-    const int64_t k = (int64_t)(c0 + bb) + (int64_t)N2 * k1;
-    const int32_t pos = inv[k];
-    if (pos >= 0) S[pos + i * lds] = out_value<V, C>(sm[bb * Lp + lpad(k1)], scale);
+  int32_t pos[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int t = threadIdx.x + u * 256;
+    pos[u] = (t < B * N1) ? inv[(int64_t)(c0 + t / N1) + (int64_t)N2 * (t % N1)] : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int t = threadIdx.x + u * 256;
+    if (pos[u] >= 0) S[pos[u] + i * lds] = out_value<V, C>(sm[(t / N1) * Lp + lpad(t % N1)], scale);
   }
 }
 

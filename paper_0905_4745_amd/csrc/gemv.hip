@@ -166,9 +166,10 @@ __global__ void __launch_bounds__(256) k_gemv_fwd(const V* __restrict__ A, int64
 // Fused pass  q = A (A* p)  reading A once (m <= 32 * RPT).
 // Workgroup g (TPB threads) streams column strips of width Wd = 8 * CPT (256
 // bytes of each row).  Thread t owns columns cg*CPT .. +CPT-1 (cg = t % 8) of
-// the strip and rows rg + (TPB/8) k, k < RPT (rg = t / 8), in registers.
-// Per strip:
-//   t_c = sum_r conj(A_rc) p_r   (over rows: 3 shuffles, then the waves via LDS)
+// the strip and rows rg + (TPB/8) k, k < RPT (rg = t / 8), in registers, so
+// 8 adjacent lanes read one contiguous 256-byte row segment.  Per strip:
+//   t_c = sum_r conj(A_rc) p_r   (over rows: lane distances 8, 16, 32, then
+//                                 the waves via LDS)
 //   qacc_r += sum_c A_rc t_c     (registers, reduced over column groups once
 //                                 per workgroup at the end)
 // Output: qpart[g * m + i], FP64; the strips of a workgroup are contiguous.
@@ -194,11 +195,11 @@ __global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t l
   int64_t s1 = s0 + strips_per_wg;
   if (s1 > nstrips) s1 = nstrips;
   __syncthreads();
-  int slot = 0;
-  for (int64_t sidx = s0; sidx < s1; ++sidx) {
+  // strip loads into registers; two register sets so that the next strip's
+  // loads are in flight while the current one is reduced
+  auto load_strip = [&](V (&x)[RPT][CPT], int64_t sidx) {
     const int64_t cbase = sidx * WD + cg * CPT;
     const bool full = cbase + CPT <= n;
-    V x[RPT][CPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
       const int64_t r = rg + RG * k;
@@ -214,6 +215,9 @@ __global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t l
         for (int u = 0; u < CPT; ++u) x[k][u] = (r < m && cbase + u < n) ? A[r * lda + cbase + u] : vzero<V>();
       }
     }
+  };
+  int slot = 0;
+  auto process = [&](const V (&x)[RPT][CPT]) {
     C tp[CPT];
 #pragma unroll
     for (int u = 0; u < CPT; ++u) tp[u] = vzero<C>();
@@ -223,17 +227,19 @@ __global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t l
 #pragma unroll
       for (int u = 0; u < CPT; ++u) tp[u] = vcfma(vconv<C>(x[k][u]), pr, tp[u]);
     }
-    // reduce over the 8 row groups of this wave (lanes equal mod 8)
+    // reduce over the 8 row groups of this wave (lanes equal mod 8): lane
+    // distance 8 by a DPP rotation within 16-lane rows, then 16 and 32
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
-#pragma unroll
-      for (int off = 8; off < 64; off <<= 1) {
-        if constexpr (VT<C>::cplx) {
-          tp[u].re += __shfl_xor(tp[u].re, off, 64);
-          tp[u].im += __shfl_xor(tp[u].im, off, 64);
-        } else {
-          tp[u] += __shfl_xor(tp[u], off, 64);
-        }
+      tp[u] = vadd(tp[u], dpp<kDppRor8>(tp[u]));
+      if constexpr (VT<C>::cplx) {
+        tp[u].re += __shfl_xor(tp[u].re, 16, 64);
+        tp[u].im += __shfl_xor(tp[u].im, 16, 64);
+        tp[u].re += __shfl_xor(tp[u].re, 32, 64);
+        tp[u].im += __shfl_xor(tp[u].im, 32, 64);
+      } else {
+        tp[u] += __shfl_xor(tp[u], 16, 64);
+        tp[u] += __shfl_xor(tp[u], 32, 64);
       }
     }
     if (lane < 8) {
@@ -255,6 +261,16 @@ __global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t l
 #pragma unroll
       for (int u = 0; u < CPT; ++u) qacc[k] = vfma(vconv<C>(x[k][u]), tc[u], qacc[k]);
     slot ^= 1;
+  };
+  V xa[RPT][CPT], xb[RPT][CPT];
+  if (s0 < s1) load_strip(xa, s0);
+  for (int64_t sidx = s0; sidx < s1; sidx += 2) {
+    if (sidx + 1 < s1) load_strip(xb, sidx + 1);
+    process(xa);
+    if (sidx + 1 < s1) {
+      if (sidx + 2 < s1) load_strip(xa, sidx + 2);
+      process(xb);
+    }
   }
   // reduce q over the 8 column groups (low 3 lane bits) and write this
   // workgroup's partial
@@ -275,21 +291,25 @@ __global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t l
   }
 }
 
-// q[i] = sum_g qpart[g * m + i], g < G, in a fixed order.  grid = ceil(m/64),
-// 256 threads: four interleaved quarters of the partials, then combined.
+// First level of the sum over workgroup partials: q8[gr * m + i] = sum of
+// qpart[g * m + i] over the gr-th eighth of g, in a fixed order.
+// grid = (ceil(m/64), 8), 256 threads (64 rows x 4 interleaved quarters).
 template <typename U>
 __global__ void __launch_bounds__(256) k_gram_reduce(const U* __restrict__ qpart, int G, int64_t m,
-                                                     U* __restrict__ q, const int32_t* __restrict__ flag) {
+                                                     U* __restrict__ q8, const int32_t* __restrict__ flag) {
   if (stopped(flag)) return;
   __shared__ U red[4][64];
   const int rr = threadIdx.x & 63, quarter = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + rr;
+  const int per = (G + 7) / 8;
+  const int g0 = blockIdx.y * per, g1 = (g0 + per) < G ? (g0 + per) : G;
   U acc = vzero<U>();
   if (i < m)
-    for (int g = quarter; g < G; g += 4) acc = vadd(acc, qpart[(int64_t)g * m + i]);
+    for (int g = g0 + quarter; g < g1; g += 4) acc = vadd(acc, qpart[(int64_t)g * m + i]);
   red[quarter][rr] = acc;
   __syncthreads();
-  if (quarter == 0 && i < m) q[i] = vadd(vadd(red[0][rr], red[1][rr]), vadd(red[2][rr], red[3][rr]));
+  if (quarter == 0 && i < m)
+    q8[(int64_t)blockIdx.y * m + i] = vadd(vadd(red[0][rr], red[1][rr]), vadd(red[2][rr], red[3][rr]));
 }
 
 // ---------------------------------------------------------------------------
@@ -394,8 +414,8 @@ static hipError_t gram_impl(const GramArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_gram<V, C, U, CPT, 8, 512>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
                        spw, nstrips, qpart, a.flag);
   if (a.ev_end) (void)hipEventRecord(a.ev_end, st);
-  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64)), dim3(256), 0, st, qpart, (int)G, a.m,
-                     reinterpret_cast<U*>(a.q), a.flag);
+  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64), 8), dim3(256), 0, st, qpart, (int)G,
+                     a.m, reinterpret_cast<U*>(a.q), a.flag);
   return hipGetLastError();
 }
 

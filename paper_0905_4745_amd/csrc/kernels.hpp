@@ -83,12 +83,13 @@ hipError_t launch_gemv_fwd(int dtype, bool wide, const FwdArgs& a, hipStream_t s
 // Fused q = A (A* p) in one read of A (m <= kGramMaxRows, 16-byte aligned rows).
 constexpr int kGramMaxRows = 512;
 constexpr int kGramMaxWg = 512;  // partial sums per row
+constexpr int kGramParts = 8;    // slices of q left for the CG kernel to add
 struct GramArgs {
   const void* A;
   int64_t lda, m, n;
   const void* p;   // FP64, m entries
   void* qpart;     // FP64, kGramMaxWg * m
-  void* q;         // FP64, m entries (result)
+  void* q;         // FP64, kGramParts * m: q = sum of the kGramParts slices
   const int32_t* flag;
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
 };

@@ -315,10 +315,19 @@ __global__ void __launch_bounds__(256) k_cg_p(const W* __restrict__ X, int64_t l
   const int64_t i0 = (int64_t)blockIdx.x * RB;
   const int rr = threadIdx.x % RB, cgrp = threadIdx.x / RB;  // 16 column groups
   const int64_t i = i0 + rr;
-  W acc = vzero<W>();
-  if (i < m)
-    for (int64_t j = i0 + cgrp; j < m; j += 16)
-      if (j >= i) acc = vfma(X[i + j * ldx], ss[j], acc);
+  // X is zero below the diagonal inside the diagonal block, so the band can
+  // be read from column i0 on; four independent accumulators keep the loads
+  // of a thread in flight together
+  W a4[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
+  if (i < m) {
+    int64_t j = i0 + cgrp;
+    for (; j + 48 < m; j += 64) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] = vfma(X[i + (j + 16 * u) * ldx], ss[j + 16 * u], a4[u]);
+    }
+    for (; j < m; j += 16) a4[0] = vfma(X[i + j * ldx], ss[j], a4[0]);
+  }
+  W acc = vadd(vadd(a4[0], a4[1]), vadd(a4[2], a4[3]));
   part[cgrp][rr] = acc;
   __syncthreads();
   if (threadIdx.x < RB && i0 + threadIdx.x < m) {

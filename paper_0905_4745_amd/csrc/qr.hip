@@ -28,6 +28,20 @@
 namespace mn {
 
 constexpr int NB = kQrTile;  // 32
+constexpr int LDT = NB + 1;  // LDS column stride of a tile (breaks bank conflicts)
+
+// 1/x: hardware reciprocal estimate plus two Newton-Raphson steps
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ inline float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  r = fmaf(r, fmaf(-x, r, 1.0f), r);
+  return r;
+}
 
 // Householder vector for x = [alpha; rest], |rest|^2 = xn2: returns beta,
 // tau and scal = 1 / (alpha - beta) (v_rest = rest * scal).
@@ -44,72 +58,64 @@ __device__ inline void make_reflector(V alpha, typename VT<V>::real xn2, V& tau,
   }
   const R nrm = sqrt(ar * ar + ai * ai + xn2);
   beta = ar >= (R)0 ? -nrm : nrm;
-  // tau = (beta - alpha) / beta
-  tau = vmake<V>((beta - ar) / beta, -ai / beta);
-  // scal = 1 / (alpha - beta)
+  // tau = (beta - alpha) / beta, scal = 1 / (alpha - beta); the reciprocals
+  // are hardware estimates refined by two Newton steps (the arguments are
+  // positive and far from the range limits: beta is a norm, den >= beta^2)
+  const R ib = recip(beta);
+  tau = vmake<V>((beta - ar) * ib, -ai * ib);
   const R dr = ar - beta, di = ai;
-  const R den = dr * dr + di * di;
-  scal = vmake<V>(dr / den, -di / den);
+  const R iden = recip(dr * dr + di * di);
+  scal = vmake<V>(dr * iden, -di * iden);
 }
 
 // ---------------------------------------------------------------------------
-// Tile factorisations in LDS by all four waves.  Wave w owns columns
-// 8w .. 8w+7; lane (cl = lane % 8, g = lane / 8) owns column 8w + cl and rows
-// 4g .. 4g+3.  Each wave recomputes the pivot column's reflector from LDS, so
-// one barrier per column step suffices.
+// Tile factorisations in LDS (column stride LDT) by all four waves.  Wave w
+// owns columns 8w .. 8w+7; lane (g = lane % 8, cl = lane / 8) owns column
+// 8w + cl and rows 4g .. 4g+3, so the sums over a column's rows are DPP
+// reductions over 8 adjacent lanes.  Each wave recomputes the pivot column's
+// reflector from LDS (bitwise identical in every lane), so one barrier per
+// column step suffices.
 
-template <typename S> __device__ inline S sum_over_g(S v) {
-  // lanes with equal lane % 8 (the 8 row groups of a column)
-#pragma unroll
-  for (int off = 8; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-__device__ inline cd sum_over_g(cd v) { return cd{sum_over_g(v.re), sum_over_g(v.im)}; }
-__device__ inline cf sum_over_g(cf v) { return cf{sum_over_g(v.re), sum_over_g(v.im)}; }
-
-// Reduce the NB x NB tile T (LDS, ld NB) to upper-triangular form: on exit
-// beta on the diagonal, v below it, tau[] the scalars.  All 256 threads; the
-// tile must be in LDS and visible (barrier) before the call.
+// Reduce the NB x NB tile T (LDS) to upper-triangular form: on exit beta on
+// the diagonal, v below it, tau[] the scalars.  All 256 threads; the tile
+// must be in LDS and visible (barrier) before the call.
 template <typename V>
 __device__ void geqrt_lds(V* T, V* tau) {
   using R = typename VT<V>::real;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int c = 8 * w + (lane & 7), g = lane >> 3;
+  const int g = lane & 7, c = 8 * w + (lane >> 3);
   for (int j = 0; j < NB; ++j) {
-    V pk[4];
+    // all of this step's LDS reads first: pivot column, alpha, own column
+    V pk[4], o[4];
+    const bool upd = c > j;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pk[k] = T[(4 * g + k) + j * LDT];
+    const V alpha = T[j + j * LDT];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = upd ? T[(4 * g + k) + c * LDT] : vzero<V>();
     R part = (R)0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = 4 * g + k;
-      pk[k] = T[r + j * NB];
-      if (r > j) part += vabs2(pk[k]);
-    }
-    const R xn2 = sum_over_g(part);
+    for (int k = 0; k < 4; ++k)
+      if (4 * g + k > j) part += vabs2(pk[k]);
+    const R xn2 = sum8(part);
     V tj, sc;
     R bt;
-    make_reflector<V>(T[j + j * NB], xn2, tj, bt, sc);
+    make_reflector<V>(alpha, xn2, tj, bt, sc);
     V vk[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int r = 4 * g + k;
       vk[k] = (r == j) ? vmake<V>(1.0, 0.0) : (r > j ? vmul(pk[k], sc) : vzero<V>());
     }
-    const bool upd = c > j;
-    V o[4];
     V wsum = vzero<V>();
-    if (upd) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        o[k] = T[(4 * g + k) + c * NB];
-        wsum = vcfma(vk[k], o[k], wsum);
-      }
-    }
-    wsum = sum_over_g(wsum);
+    for (int k = 0; k < 4; ++k) wsum = vcfma(vk[k], o[k], wsum);
+    wsum = sum8(wsum);
     const V f = vmul(vconj(tj), wsum);
     if (upd) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (4 * g + k >= j) T[(4 * g + k) + c * NB] = vsub(o[k], vmul(vk[k], f));
+        if (4 * g + k >= j) T[(4 * g + k) + c * LDT] = vsub(o[k], vmul(vk[k], f));
     }
     // every wave has read column j: its owner may now overwrite it; column
     // j+1, read next, was finished above by its owner
@@ -118,8 +124,8 @@ __device__ void geqrt_lds(V* T, V* tau) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int r = 4 * g + k;
-        if (r > j) T[r + j * NB] = vk[k];
-        else if (r == j) T[j + j * NB] = vmake<V>((double)bt, 0.0);
+        if (r > j) T[r + j * LDT] = vk[k];
+        else if (r == j) T[j + j * LDT] = vmake<V>((double)bt, 0.0);
       }
     }
     if (threadIdx.x == 0) tau[j] = tj;
@@ -134,49 +140,45 @@ template <typename V>
 __device__ void ttqrt_lds(V* R1, V* R2, V* tau) {
   using R = typename VT<V>::real;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int c = 8 * w + (lane & 7), g = lane >> 3;
+  const int g = lane & 7, c = 8 * w + (lane >> 3);
   for (int j = 0; j < NB; ++j) {
-    V pk[4];
+    // all of this step's LDS reads first: pivot column, alpha, own column
+    V pk[4], o[4];
+    const bool upd = c > j;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pk[k] = (4 * g + k <= j) ? R2[(4 * g + k) + j * LDT] : vzero<V>();
+    const V alpha = R1[j + j * LDT];
+    const V top = (upd && g == 0) ? R1[j + c * LDT] : vzero<V>();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = upd ? R2[(4 * g + k) + c * LDT] : vzero<V>();
     R part = (R)0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = 4 * g + k;
-      pk[k] = (r <= j) ? R2[r + j * NB] : vzero<V>();
-      part += vabs2(pk[k]);
-    }
-    const R xn2 = sum_over_g(part);
+    for (int k = 0; k < 4; ++k) part += vabs2(pk[k]);
+    const R xn2 = sum8(part);
     V tj, sc;
     R bt;
-    make_reflector<V>(R1[j + j * NB], xn2, tj, bt, sc);
+    make_reflector<V>(alpha, xn2, tj, bt, sc);
     V vk[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) vk[k] = vmul(pk[k], sc);
-    V o[4];
-    V wsum = vzero<V>();
-    const bool upd = c > j;
-    if (upd) {
+    V wsum = top;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        o[k] = R2[(4 * g + k) + c * NB];
-        wsum = vcfma(vk[k], o[k], wsum);
-      }
-      if (g == 0) wsum = vadd(wsum, R1[j + c * NB]);
-    }
-    wsum = sum_over_g(wsum);
+    for (int k = 0; k < 4; ++k) wsum = vcfma(vk[k], o[k], wsum);
+    wsum = sum8(wsum);
     const V f = vmul(vconj(tj), wsum);
     if (upd) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (4 * g + k <= j) R2[(4 * g + k) + c * NB] = vsub(o[k], vmul(vk[k], f));
-      if (g == 0) R1[j + c * NB] = vsub(R1[j + c * NB], f);
+        if (4 * g + k <= j) R2[(4 * g + k) + c * LDT] = vsub(o[k], vmul(vk[k], f));
+      if (g == 0) R1[j + c * LDT] = vsub(top, f);
     }
     // every wave has read column j: its owner may now overwrite it
     __syncthreads();
     if (c == j) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (4 * g + k <= j) R2[(4 * g + k) + j * NB] = vk[k];
-      if (g == 0) R1[j + j * NB] = vmake<V>((double)bt, 0.0);
+        if (4 * g + k <= j) R2[(4 * g + k) + j * LDT] = vk[k];
+      if (g == 0) R1[j + j * LDT] = vmake<V>((double)bt, 0.0);
     }
     if (threadIdx.x == 0) tau[j] = tj;
   }
@@ -195,18 +197,10 @@ __device__ inline void apply_geqrt(const V* T, const V* tau, V* c) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int q = q0 + u;
-      vq[u] = (q == r) ? vmake<V>(1.0, 0.0) : (q > r ? T[q + r * NB] : vzero<V>());
+      vq[u] = (q == r) ? vmake<V>(1.0, 0.0) : (q > r ? T[q + r * LDT] : vzero<V>());
       part = vcfma(vq[u], c[u], part);
     }
-#pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
-      if constexpr (VT<V>::cplx) {
-        part.re += __shfl_xor(part.re, off, 64);
-        part.im += __shfl_xor(part.im, off, 64);
-      } else {
-        part += __shfl_xor(part, off, 64);
-      }
-    }
+    part = sum8(part);
     const V f = vmul(vconj(tau[r]), part);
 #pragma unroll
     for (int u = 0; u < 4; ++u) c[u] = vsub(c[u], vmul(vq[u], f));
@@ -226,19 +220,11 @@ __device__ inline void apply_ttqrt(const V* V2, const V* tau, V* c1, V* c2) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int q = q0 + u;
-      vq[u] = (q <= r) ? V2[q + r * NB] : vzero<V>();
+      vq[u] = (q <= r) ? V2[q + r * LDT] : vzero<V>();
       part = vcfma(vq[u], c2[u], part);
       if (own_top && q == r) part = vadd(part, c1[u]);
     }
-#pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
-      if constexpr (VT<V>::cplx) {
-        part.re += __shfl_xor(part.re, off, 64);
-        part.im += __shfl_xor(part.im, off, 64);
-      } else {
-        part += __shfl_xor(part, off, 64);
-      }
-    }
+    part = sum8(part);
     const V f = vmul(vconj(tau[r]), part);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -251,15 +237,16 @@ __device__ inline void apply_ttqrt(const V* V2, const V* tau, V* c1, V* c2) {
 
 // tile load / store (column-major, leading dimension ld), all 256 threads
 template <typename V> __device__ inline void tile_to_lds(V* dst, const V* src, int64_t ld) {
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) dst[e] = src[(e % NB) + (int64_t)(e / NB) * ld];
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) dst[(e % NB) + (e / NB) * LDT] = src[(e % NB) + (int64_t)(e / NB) * ld];
 }
 template <typename V> __device__ inline void tile_from_lds(V* dst, int64_t ld, const V* src) {
   for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) dst[(e % NB) + (int64_t)(e / NB) * ld] = src[e];
 }
+// LDS tile (stride LDT) -> contiguous NB x NB upper triangle in global memory
 template <typename V> __device__ inline void triu_store(V* dst, const V* src) {
   for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
     const int r = e % NB, c = e / NB;
-    dst[e] = r <= c ? src[e] : vzero<V>();
+    dst[e] = r <= c ? src[r + c * LDT] : vzero<V>();
   }
 }
 template <typename V> __device__ inline void regs_load(V* c, const V* tile, int64_t ld) {
@@ -291,11 +278,14 @@ __global__ void k_qr_pad(const V* __restrict__ S, int64_t lds, int64_t l, int64_
 template <typename V>
 __global__ void __launch_bounds__(256) k_qr_level0(V* __restrict__ Sp, int64_t lp, int k, V* __restrict__ Rb,
                                                    V* __restrict__ Rdiag, int write_diag) {
-  __shared__ V T[NB * NB];
+  __shared__ V T[LDT * NB];
   __shared__ V tau[NB];
   const int i = k + blockIdx.x;
   const int jj = blockIdx.y;
   const V* tile_ik = Sp + (int64_t)i * NB + (int64_t)k * NB * lp;
+  V* tile_ij = Sp + (int64_t)i * NB + (int64_t)(k + jj) * NB * lp;
+  V c[4];
+  if (jj != 0) regs_load(c, tile_ij, lp);  // in flight during the factorisation
   tile_to_lds(T, tile_ik, lp);
   __syncthreads();
   geqrt_lds<V>(T, tau);
@@ -304,9 +294,6 @@ __global__ void __launch_bounds__(256) k_qr_level0(V* __restrict__ Sp, int64_t l
     if (write_diag) triu_store(Rdiag + (int64_t)k * NB * NB, T);
     return;
   }
-  V* tile_ij = Sp + (int64_t)i * NB + (int64_t)(k + jj) * NB * lp;
-  V c[4];
-  regs_load(c, tile_ij, lp);
   apply_geqrt<V>(T, tau, c);
   regs_store(tile_ij, lp, c);
 }
@@ -316,8 +303,8 @@ template <typename V>
 __global__ void __launch_bounds__(256) k_qr_tree(V* __restrict__ Sp, int64_t lp, int MT, int k, int s,
                                                  const V* __restrict__ Rin, V* __restrict__ Rout,
                                                  V* __restrict__ Rdiag, int final_level) {
-  __shared__ V R1[NB * NB];
-  __shared__ V R2[NB * NB];
+  __shared__ V R1[LDT * NB];
+  __shared__ V R2[LDT * NB];
   __shared__ V tau[NB];
   const int p = blockIdx.x;
   const int jj = blockIdx.y;
@@ -329,9 +316,16 @@ __global__ void __launch_bounds__(256) k_qr_tree(V* __restrict__ Sp, int64_t lp,
         Rout[(int64_t)i1 * NB * NB + e] = Rin[(int64_t)i1 * NB * NB + e];
     return;
   }
+  V* t1 = Sp + (int64_t)i1 * NB + (int64_t)(k + jj) * NB * lp;
+  V* t2 = Sp + (int64_t)i2 * NB + (int64_t)(k + jj) * NB * lp;
+  V c1[4], c2[4];
+  if (jj != 0) {  // in flight during the factorisation
+    regs_load(c1, t1, lp);
+    regs_load(c2, t2, lp);
+  }
   for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    R1[e] = Rin[(int64_t)i1 * NB * NB + e];
-    R2[e] = Rin[(int64_t)i2 * NB * NB + e];
+    R1[(e % NB) + (e / NB) * LDT] = Rin[(int64_t)i1 * NB * NB + e];
+    R2[(e % NB) + (e / NB) * LDT] = Rin[(int64_t)i2 * NB * NB + e];
   }
   __syncthreads();
   ttqrt_lds<V>(R1, R2, tau);
@@ -340,11 +334,6 @@ __global__ void __launch_bounds__(256) k_qr_tree(V* __restrict__ Sp, int64_t lp,
     if (final_level) triu_store(Rdiag + (int64_t)k * NB * NB, R1);
     return;
   }
-  V* t1 = Sp + (int64_t)i1 * NB + (int64_t)(k + jj) * NB * lp;
-  V* t2 = Sp + (int64_t)i2 * NB + (int64_t)(k + jj) * NB * lp;
-  V c1[4], c2[4];
-  regs_load(c1, t1, lp);
-  regs_load(c2, t2, lp);
   apply_ttqrt<V>(R2, tau, c1, c2);
   regs_store(t1, lp, c1);
   regs_store(t2, lp, c2);
