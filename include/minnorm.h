@@ -115,7 +115,9 @@ int64_t mn_workspace_bytes(mn_handle h);
  * stream and returns how many launches of `kernel` ("gemv_adj": w = A* u,
  * "gemv_fwd": q = A w, "gram": the fused q = A (A* p) used when m <= 512)
  * were recorded since the last mn_profile call and their
- * summed duration in milliseconds.  mn_profile clears the records.
+ * summed duration in milliseconds.  Launches enqueued after the iteration
+ * had already stopped (they return at once) are not counted.  mn_profile
+ * clears the records.
  * Errors: -1 NULL handle; -2 unknown kernel name; -3/-4 NULL output. */
 int mn_profile(mn_handle h, int enable);
 int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* total_ms);

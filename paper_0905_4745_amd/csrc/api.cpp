@@ -269,8 +269,23 @@ void cg_start(const SolveCtx& c, CgBufs& v, const void* b, const void* parts, in
 }
 
 // CG iterations until the device flag is set (checked every check_every).
+// Drop timing records of launches that found the stop flag set and returned
+// at once: only the first `iters` launches of each kernel since `begin` did
+// an iteration's work.
+void prune_records(mn_handle h, size_t begin, int iters) {
+  if (!h->prof) return;
+  std::vector<std::pair<int, size_t>> kept(h->recs.begin(), h->recs.begin() + begin);
+  int seen[8] = {0};
+  for (size_t r = begin; r < h->recs.size(); ++r) {
+    const int kid = h->recs[r].first;
+    if (seen[kid]++ < iters) kept.push_back(h->recs[r]);
+  }
+  h->recs.swap(kept);
+}
+
 void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
   mn_handle h = c.h;
+  const size_t rec_begin = h->recs.size();
   const int32_t* flag = &v.st->done;
   const bool fused = gram_supported(c.bulk, c.m, c.Ab, c.ldab);
   int enqueued = 0;
@@ -349,6 +364,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
     if (h->host_state->done) break;
     if (enqueued > max_iter + 2 * c.o.check_every) break;  // cannot happen: the kernels cap iterations
   }
+  prune_records(h, rec_begin, h->host_state->iter_local);
 }
 
 // One right-hand side; b and x FP64 device vectors.  Returns a status.
