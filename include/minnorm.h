@@ -85,7 +85,15 @@ typedef struct {
                             device stop flag                                  [8] */
   int32_t inner_digits;  /* mixed precision: decimal digits each low-precision
                             inner solve gains                                 [4] */
-  int32_t reserved[3];
+  int32_t block;         /* several right-hand sides: 0 = automatic (block form
+                            when nrhs >= 2 and the bulk runs in single
+                            precision), 1 = one right-hand side at a time,
+                            2 = block form.  The block form runs the k CG
+                            recurrences together: both products of an
+                            iteration are split-BF16 matrix-core products
+                            over all k columns (FP32 accumulation) and every
+                            column is certified by FP64 refinement         [0] */
+  int32_t reserved[2];
 } mn_opts;
 
 /* Per-solve report (host struct written by the library). */

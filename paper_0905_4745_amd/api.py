@@ -118,6 +118,7 @@ class SolveOptions:
     max_refine: int = 40
     check_every: int = 8
     inner_digits: int = 4
+    block: int = 0  # several RHS: 0 automatic, 1 one at a time, 2 block form
 
     def to_c(self):
         o = L.MnOpts()
@@ -127,6 +128,7 @@ class SolveOptions:
         o.max_refine = self.max_refine
         o.check_every = self.check_every
         o.inner_digits = self.inner_digits
+        o.block = self.block
         return o
 
 

@@ -38,6 +38,7 @@ struct mn_handle_s {
   std::map<std::string, Buf> bufs;
   Twiddle tw[2];  // [0] complex double, [1] complex float
   PcgState* host_state = nullptr;  // pinned
+  BlkState* host_blk = nullptr;    // pinned
   int32_t* host_flag = nullptr;    // pinned
   double* host_diag = nullptr;     // pinned, 4 doubles
   hipEvent_t ev[9] = {};
@@ -116,8 +117,8 @@ int fail_hip(hipError_t e) {
 }
 
 // kernel ids for mn_profile_read
-enum { K_ADJ = 0, K_FWD = 1, K_GRAM = 2 };
-const char* kKernelNames[] = {"gemv_adj", "gemv_fwd", "gram"};
+enum { K_ADJ = 0, K_FWD = 1, K_GRAM = 2, K_BADJ = 3, K_BFWD = 4, K_DRES = 5 };
+const char* kKernelNames[] = {"gemv_adj", "gemv_fwd", "gram", "block_adj", "block_fwd", "block_residual"};
 
 // a begin/end event pair for one timed launch, or nulls when not profiling
 std::pair<hipEvent_t, hipEvent_t> prof_pair(mn_handle h, int kid) {
@@ -467,6 +468,249 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
   return status;
 }
 
+// ----------------------------------------------------------------------------
+// Multi-right-hand-side block path (see block.hip).  Columns are k
+// independent CG recurrences on (A A*) y = b_j that share every pass over A:
+// bulk products in split BF16, refinement residuals and the certificate in
+// FP64, per-column stopping masks.  b, x FP64 (complex or real), ld ldb/ldx.
+int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+struct BlockPlan {
+  int64_t Kp1, Kp2;          // K' extents of A* P (over rows) and A W (over columns)
+  int s_fwd, s_d, s_res;     // splits of A W, of the X products, of A U
+  int64_t ks_fwd, ks_d, ks_res;
+  int64_t ldc;               // rows of a partial (m rounded to 4)
+  int ncol;                  // real output columns
+};
+
+BlockPlan plan_block(bool cplx, int64_t m, int64_t n, int kc) {
+  BlockPlan p{};
+  const int64_t E = cplx ? 2 : 1;
+  const int64_t kt = bf_ktile();
+  p.Kp1 = round_up(E * m, kt);
+  p.Kp2 = round_up(E * n, kt);
+  p.ldc = round_up(m, 4);
+  p.ncol = gemm_ncol(cplx, kc);
+  const int64_t tiles = cdiv(m, 128);
+  // about 1024 workgroups for the bulk product, 512 for the FP64 ones
+  int64_t s = cdiv(1024, tiles);
+  s = std::min<int64_t>(std::max<int64_t>(s, 1), p.Kp2 / kt);
+  p.ks_fwd = round_up(cdiv(p.Kp2, s), kt);
+  p.s_fwd = (int)cdiv(p.Kp2, p.ks_fwd);
+  s = std::min<int64_t>(std::max<int64_t>(cdiv(512, tiles), 1), cdiv(m, 16));
+  p.ks_d = round_up(cdiv(m, s), 16);
+  p.s_d = (int)cdiv(m, p.ks_d);
+  s = std::min<int64_t>(std::max<int64_t>(cdiv(512, tiles), 1), cdiv(n, 16));
+  p.ks_res = round_up(cdiv(n, s), 16);
+  p.s_res = (int)cdiv(n, p.ks_res);
+  return p;
+}
+
+void read_blk(mn_handle h, BlkState* src) {
+  ck(hipMemcpyAsync(h->host_blk, src, sizeof(BlkState), hipMemcpyDeviceToHost, h->stream));
+  ck(hipStreamSynchronize(h->stream));
+}
+
+int solve_block(const SolveCtx& c, const void* b, int64_t ldb, int kc, void* x, int64_t ldx, mn_info* info) {
+  mn_handle h = c.h;
+  hipStream_t st = h->stream;
+  const bool cplx = is_complex(c.dtype);
+  const int64_t W = wide_size(c.dtype);
+  const int64_t m = c.m, n = c.n;
+  const BlockPlan pl = plan_block(cplx, m, n, kc);
+  const int64_t ldx_pre = rinv_ld(m);
+  // bulk planes: A (m x Kp2) and its transpose (n x Kp1)
+  uint16_t* a_hi = (uint16_t*)ws(h, "blk_a_hi", (size_t)(m * pl.Kp2 * 2));
+  uint16_t* a_lo = (uint16_t*)ws(h, "blk_a_lo", (size_t)(m * pl.Kp2 * 2));
+  uint16_t* t_hi = (uint16_t*)ws(h, "blk_t_hi", (size_t)(n * pl.Kp1 * 2));
+  uint16_t* t_lo = (uint16_t*)ws(h, "blk_t_lo", (size_t)(n * pl.Kp1 * 2));
+  ck(launch_planes(c.bulk, c.Ab, c.ldab, m, n, false, a_hi, a_lo, pl.Kp2, st));
+  ck(launch_planes(c.bulk, c.Ab, c.ldab, m, n, true, t_hi, t_lo, pl.Kp1, st));
+  // right-operand planes (zero where the products never write)
+  const size_t p_bytes = (size_t)(kc * pl.Kp1 * 2), w_bytes = (size_t)(kc * pl.Kp2 * 2);
+  uint16_t* p_hi = (uint16_t*)ws(h, "blk_p_hi", p_bytes);
+  uint16_t* p_lo = (uint16_t*)ws(h, "blk_p_lo", p_bytes);
+  uint16_t* w_hi = (uint16_t*)ws(h, "blk_w_hi", w_bytes);
+  uint16_t* w_lo = (uint16_t*)ws(h, "blk_w_lo", w_bytes);
+  ck(launch_fill0(p_hi, (int64_t)p_bytes, st));
+  ck(launch_fill0(p_lo, (int64_t)p_bytes, st));
+  ck(launch_fill0(w_hi, (int64_t)w_bytes, st));
+  ck(launch_fill0(w_lo, (int64_t)w_bytes, st));
+  // block vectors, column-major with ld m
+  const size_t vb = (size_t)round_up(kc * m * W, 16);
+  void* yo = ws(h, "blk_yo", vb);
+  void* y = ws(h, "blk_y", vb);
+  void* rr = ws(h, "blk_rr", vb);
+  void* r = ws(h, "blk_r", vb);
+  void* p = ws(h, "blk_p", vb);
+  void* q = ws(h, "blk_q", vb);
+  void* s = ws(h, "blk_s", vb);
+  void* z = ws(h, "blk_z", vb);
+  float* qp = (float*)ws(h, "blk_qp", (size_t)pl.s_fwd * pl.ncol * pl.ldc * 4);
+  const int sd_max = std::max(pl.s_d, pl.s_res);
+  double* dp = (double*)ws(h, "blk_dp", (size_t)sd_max * pl.ncol * pl.ldc * 8);
+  BlkState* bst = (BlkState*)ws(h, "blk_state", sizeof(BlkState));
+  ck(launch_fill0(yo, (int64_t)vb, st));
+  for (int j = 0; j < kc; ++j) ck(hipMemsetAsync((char*)x + j * ldx * W, 0, (size_t)(n * W), st));
+  {
+    BlkState& hs = *h->host_blk;
+    memset(&hs, 0, sizeof(hs));
+    hs.eps_inner = std::pow(10.0, -(double)c.o.inner_digits);
+    hs.eps_outer = c.eps;
+    hs.kc = kc;
+    hs.max_iter = c.o.max_iter;
+    hs.max_refine = c.o.max_refine;
+    ck(hipMemcpyAsync(bst, &hs, sizeof(BlkState), hipMemcpyHostToDevice, st));
+    ck(hipStreamSynchronize(st));
+  }
+  const int32_t* inner_flag = &bst->all_inner_done;
+  const int xdt = cplx ? MN_C128 : MN_F64;  // dtype of X = R^{-1} (FP64)
+
+  // FP64 products with X: S = X* src (tri lower) or Z = X src (tri upper)
+  auto x_product = [&](bool adjoint, const void* src, void* out, const int32_t* flag) {
+    DGemmArgs g{};
+    g.A = c.X;
+    g.lda = ldx_pre;
+    g.M = m;
+    g.K = m;
+    g.B = src;
+    g.ldb = m;
+    g.kc = kc;
+    g.ks = pl.ks_d;
+    g.tri = adjoint ? 2 : 1;
+    g.Cp = dp;
+    g.ldc = pl.ldc;
+    g.flag = flag;
+    // rows of X* are the stored columns of X; rows of X are read across them
+    ck(launch_gemm_d(xdt, !adjoint, adjoint, 0, g, pl.s_d, st));
+    ck(launch_blk_reduce(cplx, false, dp, pl.s_d, pl.ldc, pl.ncol, m, kc, nullptr, 0, out, m, flag, st));
+  };
+
+  ev_record(h, 3);
+  for (int outer = 0; outer <= c.o.max_refine + 1; ++outer) {
+    // FP64 residual of the current y_out: U = A* y_out (= x), rr = b - A U
+    if (outer == 0) {
+      ck(launch_blk_reduce(cplx, false, dp, 0, pl.ldc, pl.ncol, m, kc, b, ldb, rr, m, nullptr, st));
+    } else {
+      DGemmArgs g{};
+      g.A = c.A;
+      g.lda = c.lda;
+      g.M = n;
+      g.K = m;
+      g.B = yo;
+      g.ldb = m;
+      g.kc = kc;
+      g.ks = round_up(m, 16);
+      g.O = x;
+      g.ldo = ldx;
+      auto ev = prof_pair(h, K_DRES);
+      if (ev.first) ck(hipEventRecord(ev.first, st));
+      ck(launch_gemm_d(c.dtype, true, true, 1, g, 1, st));
+      if (ev.second) ck(hipEventRecord(ev.second, st));
+      DGemmArgs f{};
+      f.A = c.A;
+      f.lda = c.lda;
+      f.M = m;
+      f.K = n;
+      f.B = x;
+      f.ldb = ldx;
+      f.kc = kc;
+      f.ks = pl.ks_res;
+      f.Cp = dp;
+      f.ldc = pl.ldc;
+      ev = prof_pair(h, K_DRES);
+      if (ev.first) ck(hipEventRecord(ev.first, st));
+      ck(launch_gemm_d(c.dtype, false, false, 0, f, pl.s_res, st));
+      if (ev.second) ck(hipEventRecord(ev.second, st));
+      ck(launch_blk_reduce(cplx, false, dp, pl.s_res, pl.ldc, pl.ncol, m, kc, b, ldb, rr, m, nullptr, st));
+    }
+    x_product(true, rr, s, nullptr);
+    ck(launch_blk_outer(cplx, kc, m, b, ldb, rr, s, yo, y, r, bst, st));
+    ck(launch_blk_flag(bst, st));
+    read_blk(h, bst);
+    if (h->host_blk->all_outer_done) break;
+    x_product(false, s, z, nullptr);
+    ck(launch_blk_beta(cplx, kc, m, 1, s, z, p, p_hi, p_lo, pl.Kp1, bst, st));
+    const size_t rec_begin = h->recs.size();
+    while (true) {
+      for (int it = 0; it < c.o.check_every; ++it) {
+        BfGemmArgs g1{};  // W = A* P (transposed planes, conjugated)
+        g1.Ahi = t_hi;
+        g1.Alo = t_lo;
+        g1.lda = pl.Kp1;
+        g1.M = n;
+        g1.Bhi = p_hi;
+        g1.Blo = p_lo;
+        g1.ldb = pl.Kp1;
+        g1.kc = kc;
+        g1.Kp = pl.Kp1;
+        g1.ks = pl.Kp1;
+        g1.Ohi = w_hi;
+        g1.Olo = w_lo;
+        g1.ldo = pl.Kp2;
+        g1.flag = inner_flag;
+        auto ev = prof_pair(h, K_BADJ);
+        if (ev.first) ck(hipEventRecord(ev.first, st));
+        ck(launch_gemm_bf(cplx, true, 1, g1, 1, st));
+        if (ev.second) ck(hipEventRecord(ev.second, st));
+        BfGemmArgs g2{};  // Q = A W
+        g2.Ahi = a_hi;
+        g2.Alo = a_lo;
+        g2.lda = pl.Kp2;
+        g2.M = m;
+        g2.Bhi = w_hi;
+        g2.Blo = w_lo;
+        g2.ldb = pl.Kp2;
+        g2.kc = kc;
+        g2.Kp = pl.Kp2;
+        g2.ks = pl.ks_fwd;
+        g2.Cp = qp;
+        g2.ldc = pl.ldc;
+        g2.flag = inner_flag;
+        ev = prof_pair(h, K_BFWD);
+        if (ev.first) ck(hipEventRecord(ev.first, st));
+        ck(launch_gemm_bf(cplx, false, 0, g2, pl.s_fwd, st));
+        if (ev.second) ck(hipEventRecord(ev.second, st));
+        ck(launch_blk_reduce(cplx, true, qp, pl.s_fwd, pl.ldc, pl.ncol, m, kc, nullptr, 0, q, m, inner_flag, st));
+        ck(launch_blk_alpha(cplx, kc, m, p, q, y, r, bst, st));
+        x_product(true, r, s, inner_flag);
+        x_product(false, s, z, inner_flag);
+        ck(launch_blk_beta(cplx, kc, m, 0, s, z, p, p_hi, p_lo, pl.Kp1, bst, st));
+      }
+      read_blk(h, bst);
+      if (h->host_blk->all_inner_done) break;
+    }
+    int live = 0;
+    for (int j = 0; j < kc; ++j) live = std::max(live, h->host_blk->col[j].inner_it);
+    prune_records(h, rec_begin, live);
+    ck(launch_blk_refine(cplx, kc, m, yo, y, bst, st));
+  }
+  ev_record(h, 4);
+  ev_record(h, 5);
+  read_blk(h, bst);
+  const BlkState& hs = *h->host_blk;
+  int worst = MN_OK;
+  for (int j = 0; j < kc; ++j) {
+    const BlkCol& col = hs.col[j];
+    int status = col.status;
+    if (!col.outer_done && status == MN_OK) status = MN_NOT_CONVERGED;
+    worst = std::max(worst, status);
+    if (info) {
+      info->iters += col.iters;
+      info->refine_steps += col.refine;
+      if (status == MN_OK) info->nrhs_done += 1;
+      const double cert = col.outer_xi > 0 ? std::sqrt(col.outer_rho / col.outer_xi) : 0.0;
+      if (cert >= info->cert_rel) {
+        info->cert_rel = cert;
+        info->rho0 = col.rho0;
+        info->rho = col.outer_rho;
+        info->xi = col.outer_xi;
+      }
+    }
+  }
+  return worst;
+}
+
 mn_opts resolve_opts(const mn_opts* o) {
   mn_opts r{};
   if (o) r = *o;
@@ -480,6 +724,7 @@ mn_opts resolve_opts(const mn_opts* o) {
 
 bool opts_valid(const mn_opts& o) {
   return o.alpha > 1.0 && (o.stop_rule == 0 || o.stop_rule == 1) && o.max_iter > 0 && o.max_refine > 0 &&
+         o.block >= 0 && o.block <= 2 &&
          o.check_every > 0 && o.check_every <= 1024 && o.inner_digits > 0 && o.inner_digits <= 12;
 }
 
@@ -533,10 +778,14 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   }
   const int64_t ldxi = rinv_ld(m);
   c.X = ws(h, "Xinv", (size_t)(ldxi * ldxi * wide_size(dtype)));
+  const bool block = o.block == 2 || (o.block == 0 && nrhs >= 2 && c.mixed);
+  // the block products read whole tiles of X, so its strict lower part must be zero
+  if (block) ck(launch_fill0(c.X, ldxi * ldxi * wide_size(dtype), h->stream));
   ck(launch_rinv(c.bulk, c.R, m, m, c.X, h->stream));
   const int64_t W = wide_size(dtype);
   int worst = MN_OK;
-  for (int64_t j = 0; j < nrhs; ++j) {
+  if (block) worst = solve_block(c, b, ldb, (int)nrhs, x, ldx, info);
+  for (int64_t j = 0; j < (block ? 0 : nrhs); ++j) {
     const void* bj = (const char*)b + j * ldb * W;
     void* xj = (char*)x + j * ldx * W;
     const int s = solve_one(c, bj, xj, info);
@@ -601,6 +850,7 @@ int mn_create(mn_handle* hp, void* stream) {
     h->stream = (hipStream_t)stream;
     ck(hipGetDevice(&h->device));
     ck(hipHostMalloc((void**)&h->host_state, sizeof(PcgState), hipHostMallocDefault));
+    ck(hipHostMalloc((void**)&h->host_blk, sizeof(BlkState), hipHostMallocDefault));
     ck(hipHostMalloc((void**)&h->host_flag, 64, hipHostMallocDefault));
     ck(hipHostMalloc((void**)&h->host_diag, 64, hipHostMallocDefault));
     for (auto& e : h->ev) ck(hipEventCreate(&e));
@@ -620,6 +870,7 @@ int mn_destroy(mn_handle h) {
   for (auto& t : h->tw)
     if (t.p) (void)hipFree(t.p);
   if (h->host_state) (void)hipHostFree(h->host_state);
+  if (h->host_blk) (void)hipHostFree(h->host_blk);
   if (h->host_flag) (void)hipHostFree(h->host_flag);
   if (h->host_diag) (void)hipHostFree(h->host_diag);
   for (auto& e : h->ev)

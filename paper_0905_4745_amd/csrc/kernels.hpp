@@ -132,4 +132,67 @@ hipError_t launch_refine_update(bool cplx, void* y_outer, const void* y, int64_t
                                 hipStream_t st);
 hipError_t launch_zero(bool cplx, void* v, int64_t m, hipStream_t st);
 
+// ---- multi-right-hand-side block path (block.hip) ---------------------------
+// Split-BF16 product C = L B^ (see block.hip): L as hi/lo planes (row-major,
+// ld lda, Kp columns, Kp a multiple of bf_ktile()), B as compact hi/lo
+// columns (kc of them, ld ldb).  mode 0: FP32 partials per split, mode 1:
+// compact BF16 planes of C (one split).
+struct BfGemmArgs {
+  const uint16_t *Ahi, *Alo;
+  int64_t lda, M;
+  const uint16_t *Bhi, *Blo;
+  int64_t ldb;
+  int kc;
+  int64_t Kp, ks;
+  float* Cp;
+  int64_t ldc;
+  uint16_t *Ohi, *Olo;
+  int64_t ldo;
+  const int32_t* flag;
+};
+// FP64 product C = op(L) B^ with L of any dtype (see block.hip).
+struct DGemmArgs {
+  const void* A;
+  int64_t lda, M, K;
+  const void* B;
+  int64_t ldb;
+  int kc;
+  int64_t ks;
+  int tri;
+  double* Cp;
+  int64_t ldc;
+  void* O;
+  int64_t ldo;
+  const int32_t* flag;
+};
+struct BlkCol {
+  double rho0, rho, rho_prev, outer_rho, outer_xi;
+  int32_t inner_done, outer_done, status, iters, refine, inner_it;
+};
+constexpr int kBlkMaxCols = 64;
+struct BlkState {
+  double eps_inner, eps_outer;
+  int32_t kc, max_iter, max_refine, all_inner_done, all_outer_done, pad;
+  BlkCol col[kBlkMaxCols];
+};
+int64_t bf_ktile();
+int gemm_ncol(bool cplx, int kc);  // real output columns of a product with kc right-hand columns
+hipError_t launch_planes(int dtype, const void* A, int64_t lda, int64_t M, int64_t K, bool trans, uint16_t* hi,
+                         uint16_t* lo, int64_t ldp, hipStream_t st);
+hipError_t launch_gemm_bf(bool cplx, bool conj, int mode, const BfGemmArgs& a, int splits, hipStream_t st);
+hipError_t launch_gemm_d(int dtype, bool trans, bool conj, int mode, const DGemmArgs& a, int splits, hipStream_t st);
+hipError_t launch_blk_reduce(bool cplx, bool f32, const void* Cp, int splits, int64_t ldc, int ncol, int64_t M,
+                             int kc, const void* src, int64_t lds, void* out, int64_t ldo, const int32_t* flag,
+                             hipStream_t st);
+hipError_t launch_blk_outer(bool cplx, int kc, int64_t m, const void* b, int64_t ldb, const void* rr, const void* s,
+                            const void* y_out, void* y, void* r, BlkState* state, hipStream_t st);
+hipError_t launch_blk_alpha(bool cplx, int kc, int64_t m, const void* p, const void* q, void* y, void* r,
+                            BlkState* state, hipStream_t st);
+hipError_t launch_blk_beta(bool cplx, int kc, int64_t m, int start, const void* s, const void* z, void* p,
+                           uint16_t* phi, uint16_t* plo, int64_t ldp, BlkState* state, hipStream_t st);
+hipError_t launch_blk_flag(BlkState* state, hipStream_t st);
+hipError_t launch_blk_refine(bool cplx, int kc, int64_t m, void* y_out, const void* y, BlkState* state,
+                             hipStream_t st);
+hipError_t launch_fill0(void* p, int64_t bytes, hipStream_t st);
+
 }  // namespace mn
