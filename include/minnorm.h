@@ -93,7 +93,9 @@ typedef struct {
                             iteration are split-BF16 matrix-core products
                             over all k columns (FP32 accumulation) and every
                             column is certified by FP64 refinement         [0] */
-  int32_t reserved[2];
+  int32_t streams;       /* minnorm_solve_batched: systems solved concurrently,
+                            each on its own stream and host thread          [8] */
+  int32_t reserved[1];
 } mn_opts;
 
 /* Per-solve report (host struct written by the library). */

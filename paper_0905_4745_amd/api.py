@@ -119,6 +119,7 @@ class SolveOptions:
     check_every: int = 8
     inner_digits: int = 4
     block: int = 0  # several RHS: 0 automatic, 1 one at a time, 2 block form
+    streams: int = 8  # batched: systems solved concurrently
 
     def to_c(self):
         o = L.MnOpts()
@@ -129,6 +130,7 @@ class SolveOptions:
         o.check_every = self.check_every
         o.inner_digits = self.inner_digits
         o.block = self.block
+        o.streams = self.streams
         return o
 
 

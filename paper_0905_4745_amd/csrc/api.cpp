@@ -6,7 +6,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <atomic>
 #include <map>
+#include <numeric>
+#include <thread>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -48,6 +52,9 @@ struct mn_handle_s {
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
   std::vector<std::pair<int, size_t>> recs;  // (kernel id, index of begin event)
+  // concurrent lanes of minnorm_solve_batched: child handles on their own streams
+  bool owns_stream = false;
+  std::vector<mn_handle> lanes;
 };
 
 namespace {
@@ -719,12 +726,13 @@ mn_opts resolve_opts(const mn_opts* o) {
   if (r.max_refine == 0) r.max_refine = 40;
   if (r.check_every == 0) r.check_every = 8;
   if (r.inner_digits == 0) r.inner_digits = 4;
+  if (r.streams == 0) r.streams = 8;
   return r;
 }
 
 bool opts_valid(const mn_opts& o) {
   return o.alpha > 1.0 && (o.stop_rule == 0 || o.stop_rule == 1) && o.max_iter > 0 && o.max_refine > 0 &&
-         o.block >= 0 && o.block <= 2 &&
+         o.block >= 0 && o.block <= 2 && o.streams > 0 && o.streams <= 64 &&
          o.check_every > 0 && o.check_every <= 1024 && o.inner_digits > 0 && o.inner_digits <= 12;
 }
 
@@ -864,6 +872,8 @@ int mn_create(mn_handle* hp, void* stream) {
 
 int mn_destroy(mn_handle h) {
   if (!h) return -1;
+  for (mn_handle c : h->lanes) mn_destroy(c);
+  h->lanes.clear();
   (void)hipStreamSynchronize(h->stream);
   for (auto& kv : h->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
@@ -876,6 +886,7 @@ int mn_destroy(mn_handle h) {
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : h->pool) (void)hipEventDestroy(e);
+  if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return 0;
 }
@@ -1032,24 +1043,70 @@ int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* 
                                    l[i], d[i], idx[i], o, x[i], n[i]);
     if (e) return remap[-e];
   }
+  // Systems run concurrently on `streams` lanes (child handles, each with its
+  // own stream, workspace and host thread), longest first; each lane solves
+  // its systems one after another.  Lanes start after the work already
+  // enqueued on the handle's stream.
+  const int nl = std::min<int>(batch, o.streams);
+  try {
+    while ((int)h->lanes.size() < nl) {
+      hipStream_t s = nullptr;
+      ck(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      mn_handle c = nullptr;
+      const int e = mn_create(&c, s);
+      if (e) {
+        (void)hipStreamDestroy(s);
+        return e;
+      }
+      c->owns_stream = true;
+      h->lanes.push_back(c);
+    }
+    ck(hipEventRecord(h->ev[6], h->stream));
+    for (int k = 0; k < nl; ++k) ck(hipStreamWaitEvent(h->lanes[k]->stream, h->ev[6], 0));
+  } catch (HipFail f) {
+    return fail_hip(f.e);
+  }
+  std::vector<int> order(batch);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return m[a] * n[a] > m[b] * n[b]; });
+  std::vector<int> st(batch, MN_OK);
+  std::atomic<int> next{0};
+  auto work = [&](int k) {
+    mn_handle c = h->lanes[k];
+    if (hipSetDevice(h->device) != hipSuccess) return;
+    while (true) {
+      const int j = next.fetch_add(1);
+      if (j >= batch) break;
+      const int i = order[j];
+      const void* alo = A_lo ? A_lo[i] : nullptr;
+      int s;
+      try {
+        s = solve_impl(c, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i], l[i], d[i],
+                       idx[i], o, x[i], n[i], info ? &info[i] : nullptr);
+      } catch (HipFail f) {
+        s = fail_hip(f.e);
+      }
+      if (info) info[i].status = s == -16 ? -14 : s;
+      st[i] = s;
+    }
+  };
+  std::vector<std::thread> th;
+  for (int k = 1; k < nl; ++k) th.emplace_back(work, k);
+  work(0);
+  for (auto& t : th) t.join();
   int worst = MN_OK;
   int argerr = 0;
   for (int32_t i = 0; i < batch; ++i) {
-    const void* alo = A_lo ? A_lo[i] : nullptr;
-    int s;
-    try {
-      s = solve_impl(h, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i], l[i], d[i],
-                     idx[i], o, x[i], n[i], info ? &info[i] : nullptr);
-    } catch (HipFail f) {
-      s = fail_hip(f.e);
-      if (info) info[i].status = s;
+    if (st[i] == -16) argerr = -14;  // idx of this system failed the device-side check
+    else if (st[i] > worst) worst = st[i];
+  }
+  try {
+    for (int k = 0; k < nl; ++k) {
+      ck(hipEventRecord(h->lanes[k]->ev[7], h->lanes[k]->stream));
+      ck(hipStreamWaitEvent(h->stream, h->lanes[k]->ev[7], 0));
     }
-    if (s == -16) {  // idx of this system failed the device-side check
-      argerr = -14;
-      if (info) info[i].status = -14;
-      continue;
-    }
-    if (s > worst) worst = s;
+  } catch (HipFail f) {
+    return fail_hip(f.e);
   }
   return argerr ? argerr : worst;
 }

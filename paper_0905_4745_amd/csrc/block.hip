@@ -787,12 +787,9 @@ hipError_t bf_go(const BfGemmArgs& a, int splits, hipStream_t st) {
   constexpr int NCOL = NT * 16;
   const size_t lds = (size_t)2 * 2 * NCOL * kBfStride * sizeof(uint16_t);
   auto kern = k_gemm_bf<CPLX, CONJ, NT, MODE>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static const hipError_t attr =
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
   const dim3 grid((unsigned)ceil_div(a.M, kBfRows), (unsigned)splits);
   hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a);
   return hipGetLastError();

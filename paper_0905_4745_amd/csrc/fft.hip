@@ -419,15 +419,14 @@ FftPlan make_plan(int L) {
 
 // Per-workgroup LDS limit of the current device (bytes).
 static int lds_limit() {
-  static int v = -1;
-  if (v < 0) {
+  // queried once (thread-safe static initialisation)
+  static const int v = [] {
     int dev = 0, x = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && x > 0)
-      v = x;
-    else
-      v = 65536;
-  }
+      return x;
+    return 65536;
+  }();
   return v;
 }
 

@@ -26,6 +26,8 @@ CASES = [
     (33, 4096, 4096, 132),
     (33, 5000, 8192, 132),
     (17, 65536, 65536, 68),
+    (3, 100000, 131072, 12),
+    (2, 262144, 262144, 8),
 ]
 
 

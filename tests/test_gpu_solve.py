@@ -237,3 +237,51 @@ def test_unfused_and_unaligned_paths(m, n, kind):
     say(f"  err {rel(x, p):.2e} iters {info['iters']}")
     assert info["status"] == 0
     assert rel(x, p) <= 1e-10
+
+
+@pytest.mark.parametrize("streams", [1, 8])
+def test_batched_concurrent_lanes(streams):
+    """24 uneven real systems (FP64 data + FP32 copies) on 1 and 8 concurrent lanes."""
+    import torch
+    from paper_0905_4745_amd import api
+    say(f"batched 24 systems on {streams} lanes")
+    shapes = synth.make_batch_shapes(24, seed=11, m_lo=8, m_hi=128, n_lo=300, n_hi=4000)
+    systems = synth.make_batch(shapes, seed=12, kappa=1e4)
+    As = [to_dev(A) for A, _ in systems]
+    A_los = [a.to(torch.float32) for a in As]
+    bs = [to_dev(b) for _, b in systems]
+    ds, idxs, Ns = [], [], []
+    for k, (m, n) in enumerate(shapes):
+        N = synth.next_pow2(n)
+        d, idx = synth.draw_srft(N, synth.sketch_width(m, N), seed=100 + k, real=True)
+        ds.append(d), idxs.append(idx), Ns.append(N)
+    xs, infos = api.minnorm_solve_batched(As, bs, 1e-10, ds, idxs, Ns, A_los=A_los,
+                                          opts=api.SolveOptions(streams=streams))
+    worst = 0.0
+    for (A, b), x, info in zip(systems, xs, infos):
+        assert info["status"] == 0
+        worst = max(worst, rel(to_np(x), oracle.refined_minnorm(A, b)))
+    say(f"  worst err {worst:.2e}")
+    assert worst <= 1e-10
+
+
+def test_batched_one_bad_idx_others_solved():
+    from paper_0905_4745_amd import api
+    sys_ = [synth.make_gaussian(m, n, seed=s) for s, (m, n) in enumerate([(20, 500), (33, 900), (12, 300)])]
+    As = [to_dev(A) for A, _ in sys_]
+    bs = [to_dev(b) for _, b in sys_]
+    ds, idxs, Ns = [], [], []
+    for k, (A, _) in enumerate(sys_):
+        m, n = A.shape
+        N = synth.next_pow2(n)
+        d, idx = synth.draw_srft(N, synth.sketch_width(m, N), seed=k)
+        if k == 1:
+            idx = np.sort(np.concatenate([idx[:-1], idx[:1]]))  # a repeated index
+        ds.append(d), idxs.append(idx), Ns.append(N)
+    xs, infos = api.minnorm_solve_batched(As, bs, 1e-12, ds, idxs, Ns, opts=api.SolveOptions(streams=3),
+                                          raise_on_status=False)
+    assert infos[1]["status"] == -14
+    for k in (0, 2):
+        assert infos[k]["status"] == 0
+        A, b = sys_[k]
+        assert rel(to_np(xs[k]), oracle.classical_minnorm(A, b)) <= 1e-12
