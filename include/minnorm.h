@@ -95,7 +95,15 @@ typedef struct {
                             column is certified by FP64 refinement         [0] */
   int32_t streams;       /* minnorm_solve_batched: systems solved concurrently,
                             each on its own stream and host thread          [8] */
-  int32_t reserved[1];
+  int32_t precond;       /* source of Step 2's triangular factor R for the
+                            solve: 0 = automatic: Cholesky of the FP64 Gram
+                            matrix S* S (R* R = S* S for every QR of S), kept
+                            when every pivot is positive and the diagonal of R
+                            spans at most 1e5 (then R* R = S* S + E with
+                            |E| <= c u64 |S|^2 leaves the preconditioned
+                            operator within about 1e-6 of the identity),
+                            otherwise the Householder factorisation;
+                            1 = Householder QR of S always                  [0] */
 } mn_opts;
 
 /* Per-solve report (host struct written by the library). */

@@ -14,7 +14,7 @@ MN_C128, MN_C64, MN_F64, MN_F32 = 0, 1, 2, 3
 class MnOpts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("stop_rule", C.c_int32), ("max_iter", C.c_int32),
                 ("max_refine", C.c_int32), ("check_every", C.c_int32), ("inner_digits", C.c_int32),
-                ("block", C.c_int32), ("streams", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("block", C.c_int32), ("streams", C.c_int32), ("precond", C.c_int32)]
 
 
 class MnInfo(C.Structure):

@@ -120,6 +120,7 @@ class SolveOptions:
     inner_digits: int = 4
     block: int = 0  # several RHS: 0 automatic, 1 one at a time, 2 block form
     streams: int = 8  # batched: systems solved concurrently
+    precond: int = 0  # 0: Cholesky of the FP64 Gram matrix when safe, else Householder; 1: Householder
 
     def to_c(self):
         o = L.MnOpts()
@@ -131,6 +132,7 @@ class SolveOptions:
         o.inner_digits = self.inner_digits
         o.block = self.block
         o.streams = self.streams
+        o.precond = self.precond
         return o
 
 

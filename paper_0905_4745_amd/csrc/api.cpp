@@ -215,6 +215,44 @@ int run_qr(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t 
 
 int64_t wide_size(int dtype) { return is_complex(dtype) ? 16 : 8; }
 
+int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+// Step 2's triangular factor through the Gram matrix: G = S* S in FP64 on
+// the matrix cores, R with R* R = G by blocked Cholesky (chol.hip).  Returns
+// true with R64 (FP64, m x m, ld m) when every pivot is positive and finite
+// and max|R_ii| / min|R_ii| <= 1e5; otherwise the caller uses the
+// Householder factorisation (which also classifies rank deficiency and
+// non-finite input).
+bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t lds, void* R64) {
+  hipStream_t st = h->stream;
+  const bool cplx = is_complex(dtype);
+  const int64_t W = cplx ? 16 : 8;
+  void* G = ws(h, "gram_G", (size_t)(m * m * W));
+  const int64_t nz = cdiv(m, gram_col_block(dtype));
+  const int64_t tiles = cdiv(m, 128);
+  const int64_t wgs = std::max<int64_t>(1, tiles * nz / 2 + 1);
+  int64_t splits = std::min<int64_t>(std::max<int64_t>(cdiv(512, wgs), 1), cdiv(l, 64));
+  const int64_t ks = rup(cdiv(l, splits), 16);
+  splits = cdiv(l, ks);
+  const int64_t ldc = rup(m, 4);
+  double* Cp = nullptr;
+  if (splits > 1) Cp = (double*)ws(h, "gram_part", (size_t)(nz * splits * 128 * ldc * 8));
+  ck(launch_gram_s(dtype, S, lds, l, m, G, m, Cp, ldc, (int)splits, ks, st));
+  if (splits > 1) ck(launch_gram_fold(cplx, Cp, (int)splits, ldc, m, G, m, st));
+  int32_t* bad = (int32_t*)ws(h, "chol_bad", 16);
+  ck(launch_fill0(bad, 16, st));
+  ck(launch_chol(cplx, G, m, m, R64, m, bad, st));
+  double* dr = (double*)ws(h, "qr_diag", 64);
+  ck(launch_rdiag_range(cplx ? MN_C128 : MN_F64, R64, m, m, dr, st));
+  ck(hipMemcpyAsync(h->host_diag, dr, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  ck(hipMemcpyAsync(h->host_flag, bad, 4, hipMemcpyDeviceToHost, st));
+  ck(hipStreamSynchronize(st));
+  const double mx = h->host_diag[0], mn_ = h->host_diag[1], nonfin = h->host_diag[2];
+  if (*h->host_flag != 0 || nonfin != 0.0 || !std::isfinite(mx) || !(mn_ > 0.0)) return false;
+  return mx <= 1e5 * mn_;
+}
+
+
 struct SolveCtx {
   mn_handle h;
   int dtype;      // problem dtype (A)
@@ -732,7 +770,7 @@ mn_opts resolve_opts(const mn_opts* o) {
 
 bool opts_valid(const mn_opts& o) {
   return o.alpha > 1.0 && (o.stop_rule == 0 || o.stop_rule == 1) && o.max_iter > 0 && o.max_refine > 0 &&
-         o.block >= 0 && o.block <= 2 && o.streams > 0 && o.streams <= 64 &&
+         o.block >= 0 && o.block <= 2 && o.streams > 0 && o.streams <= 64 && (o.precond == 0 || o.precond == 1) &&
          o.check_every > 0 && o.check_every <= 1024 && o.inner_digits > 0 && o.inner_digits <= 12;
 }
 
@@ -777,19 +815,32 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   void* S = ws(h, "S", (size_t)(l * m * bes));
   run_sketch(h, c.bulk, m, n, c.Ab, c.ldab, N, l, d, idx, inv, S, l);
   ev_record(h, 1);
-  c.R = ws(h, "R", (size_t)(m * m * bes));
-  int st = run_qr(h, c.bulk, l, m, S, l, c.R, m);
-  ev_record(h, 2);
-  if (st != MN_OK) {
-    if (info) info->status = st;
-    return st;
+  // Step 2's R: Cholesky of the FP64 Gram matrix when that is accurate,
+  // Householder QR of S otherwise
+  const int wdt = is_complex(dtype) ? MN_C128 : MN_F64;
+  int rdt = c.bulk;
+  bool gram = false;
+  if (o.precond == 0) {
+    c.R = ws(h, "R64", (size_t)(m * m * wide_size(dtype)));
+    gram = gram_factor(h, c.bulk, l, m, S, l, c.R);
+    if (gram) rdt = wdt;
   }
+  if (!gram) {
+    c.R = ws(h, "R", (size_t)(m * m * bes));
+    const int st = run_qr(h, c.bulk, l, m, S, l, c.R, m);
+    if (st != MN_OK) {
+      ev_record(h, 2);
+      if (info) info->status = st;
+      return st;
+    }
+  }
+  ev_record(h, 2);
   const int64_t ldxi = rinv_ld(m);
   c.X = ws(h, "Xinv", (size_t)(ldxi * ldxi * wide_size(dtype)));
   const bool block = o.block == 2 || (o.block == 0 && nrhs >= 2 && c.mixed);
   // the block products read whole tiles of X, so its strict lower part must be zero
   if (block) ck(launch_fill0(c.X, ldxi * ldxi * wide_size(dtype), h->stream));
-  ck(launch_rinv(c.bulk, c.R, m, m, c.X, h->stream));
+  ck(launch_rinv(rdt, c.R, m, m, c.X, h->stream));
   const int64_t W = wide_size(dtype);
   int worst = MN_OK;
   if (block) worst = solve_block(c, b, ldb, (int)nrhs, x, ldx, info);

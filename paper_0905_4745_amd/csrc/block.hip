@@ -364,17 +364,22 @@ __global__ void __launch_bounds__(256) k_gemm_bf(BfGemmArgs g) {
 constexpr int kDKc = 16;
 constexpr int kDRows = 128;
 
-template <typename T, bool TRANS, bool CONJ, int NT, int MODE>
+template <typename T, typename BS, bool TRANS, bool CONJ, int NT, int MODE>
 __global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
   constexpr bool CPLX = Elem<T>::cplx;
   using BT = typename std::conditional<CPLX, cd, double>::type;
   constexpr int NCOL = NT * 16;
   constexpr int KCOL = CPLX ? NCOL / 2 : NCOL;
   __shared__ BT Bs[2][KCOL][kDKc + 1];
+  // blockIdx.z: block of KCOL right-hand columns starting at c0
+  const int64_t c0 = (int64_t)blockIdx.z * KCOL;
+  const int kcz = g.kc - c0 < KCOL ? (int)(g.kc - c0) : KCOL;
+  const int64_t wg_row0 = (int64_t)blockIdx.x * kDRows;
+  // Hermitian product: only tiles that reach the upper triangle
+  if (g.herm && wg_row0 > c0 + KCOL - 1) return;
   if (g.flag && *g.flag) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int rl = lane & 15, grp = lane >> 4;
-  const int64_t wg_row0 = (int64_t)blockIdx.x * kDRows;
   const int64_t row0 = wg_row0 + wv * 32;
   int64_t k_begin = (int64_t)blockIdx.y * g.ks;
   int64_t k_end = k_begin + g.ks < g.K ? k_begin + g.ks : g.K;
@@ -387,7 +392,7 @@ __global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
   }
   const int nch = k_end > k_begin ? (int)((k_end - k_begin + kDKc - 1) / kDKc) : 0;
   const T* L = reinterpret_cast<const T*>(g.A);
-  const BT* B = reinterpret_cast<const BT*>(g.B);
+  const BS* B = reinterpret_cast<const BS*>(g.B) + c0 * g.ldb;
 
   int64_t rows[2];
 #pragma unroll
@@ -429,7 +434,10 @@ __global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
       BT v{};
       if (u < UNITS) {
         const int col = u / kDKc, q = u % kDKc;
-        if (col < g.kc && k + q < k_end) v = B[col * g.ldb + k + q];
+        if (col < kcz && k + q < k_end) {
+          const BS e = B[col * g.ldb + k + q];
+          v = vconv<BT>(e);
+        }
       }
       b_nxt[i] = v;
     }
@@ -501,7 +509,7 @@ __global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
       const int cp = 16 * t + rl;
       const f64x4 v = acc[mt][t];
       if constexpr (MODE == 0) {
-        double* dst = g.Cp + ((int64_t)blockIdx.y * NCOL + cp) * g.ldc + rb;
+        double* dst = g.Cp + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * NCOL + cp) * g.ldc + rb;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if (rb + 4 * q < g.M) dst[4 * q] = v[q];
@@ -511,8 +519,8 @@ __global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
         for (int q = 0; q < 4; ++q) other[q] = dpp<kDppXor1>(v[q]);
         const int col = cp >> 1;
         // even lane: rows rb, rb+4; odd lane: rows rb+8, rb+12
-        cd* dst = reinterpret_cast<cd*>(g.O) + col * g.ldo;
-        if (col < g.kc) {
+        cd* dst = reinterpret_cast<cd*>(g.O) + (c0 + col) * g.ldo;
+        if (col < kcz) {
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const int q = odd ? 2 + h : h;
@@ -523,8 +531,8 @@ __global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
         }
       } else {
         const int col = cp;
-        double* dst = reinterpret_cast<double*>(g.O) + col * g.ldo;
-        if (col < g.kc) {
+        double* dst = reinterpret_cast<double*>(g.O) + (c0 + col) * g.ldo;
+        if (col < kcz) {
 #pragma unroll
           for (int q = 0; q < 4; ++q)
             if (rb + 4 * q < g.M) dst[rb + 4 * q] = v[q];
@@ -823,12 +831,13 @@ hipError_t launch_gemm_bf(bool cplx, bool conj, int mode, const BfGemmArgs& a, i
 
 template <typename T, bool TRANS, bool CONJ, int MODE>
 hipError_t d_nt_go(const DGemmArgs& a, int nt, int splits, hipStream_t st) {
+  using W = typename std::conditional<Elem<T>::cplx, cd, double>::type;
   const dim3 grid((unsigned)ceil_div(a.M, kDRows), (unsigned)splits);
   switch (nt) {
-    case 1: hipLaunchKernelGGL((k_gemm_d<T, TRANS, CONJ, 1, MODE>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_gemm_d<T, TRANS, CONJ, 2, MODE>), grid, dim3(256), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_gemm_d<T, TRANS, CONJ, 4, MODE>), grid, dim3(256), 0, st, a); break;
-    case 8: hipLaunchKernelGGL((k_gemm_d<T, TRANS, CONJ, 8, MODE>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_gemm_d<T, W, TRANS, CONJ, 1, MODE>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_gemm_d<T, W, TRANS, CONJ, 2, MODE>), grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_gemm_d<T, W, TRANS, CONJ, 4, MODE>), grid, dim3(256), 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_gemm_d<T, W, TRANS, CONJ, 8, MODE>), grid, dim3(256), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -845,7 +854,8 @@ hipError_t d_go(bool trans, bool conj, int mode, const DGemmArgs& a, int nt, int
 }
 
 hipError_t launch_gemm_d(int dtype, bool trans, bool conj, int mode, const DGemmArgs& a, int splits, hipStream_t st) {
-  if (a.kc < 1 || a.kc > 64 || splits < 1 || (int64_t)splits * a.ks < a.K || a.ks % kDKc != 0) return hipErrorInvalidValue;
+  if (a.kc < 1 || a.kc > 64 || a.herm || splits < 1 || (int64_t)splits * a.ks < a.K || a.ks % kDKc != 0)
+    return hipErrorInvalidValue;
   if (mode == 1 && splits != 1) return hipErrorInvalidValue;
   const bool cplx = dtype == 0 || dtype == 1;
   const int nt = bf_nt(cplx, a.kc);
@@ -932,6 +942,85 @@ hipError_t launch_blk_refine(bool cplx, int kc, int64_t m, void* y_out, const vo
     hipLaunchKernelGGL(k_blk_refine<double>, grid, dim3(256), 0, st, m, (double*)y_out, (const double*)y, state);
   return hipGetLastError();
 }
+
+// Gram matrix G = S* S (m x m, FP64, upper triangle) of the column-major l x m
+// sketch S, on the FP64 matrix cores.  Column blocks of 64 (complex) or 128
+// (real) run along blockIdx.z; with several splits of the l rows the partials
+// Cp[((z * splits + split) * 128 + c') * ldc + row] are folded by
+// launch_gram_fold.
+template <typename T, int MODE>
+hipError_t gram_go(const DGemmArgs& a, int splits, hipStream_t st) {
+  constexpr bool C = Elem<T>::cplx;
+  const int kb = C ? 64 : 128;
+  const dim3 grid((unsigned)ceil_div(a.M, kDRows), (unsigned)splits, (unsigned)ceil_div(a.kc, kb));
+  hipLaunchKernelGGL((k_gemm_d<T, T, false, C, 8, MODE>), grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+int gram_col_block(int dtype) { return (dtype == 0 || dtype == 1) ? 64 : 128; }
+
+hipError_t launch_gram_s(int dtype, const void* S, int64_t lds, int64_t l, int64_t m, void* G, int64_t ldg,
+                         double* Cp, int64_t ldc, int splits, int64_t ks, hipStream_t st) {
+  DGemmArgs a{};
+  a.A = S;
+  a.lda = lds;
+  a.M = m;
+  a.K = l;
+  a.B = S;
+  a.ldb = lds;
+  a.kc = (int)m;
+  a.ks = ks;
+  a.herm = 1;
+  a.Cp = Cp;
+  a.ldc = ldc;
+  a.O = G;
+  a.ldo = ldg;
+  if (splits < 1 || (int64_t)splits * ks < l || ks % kDKc != 0) return hipErrorInvalidValue;
+  const int mode = splits > 1 ? 0 : 1;
+  switch (dtype) {
+    case 0: return mode ? gram_go<cd, 1>(a, 1, st) : gram_go<cd, 0>(a, splits, st);
+    case 1: return mode ? gram_go<cf, 1>(a, 1, st) : gram_go<cf, 0>(a, splits, st);
+    case 2: return mode ? gram_go<double, 1>(a, 1, st) : gram_go<double, 0>(a, splits, st);
+    case 3: return mode ? gram_go<float, 1>(a, 1, st) : gram_go<float, 0>(a, splits, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// G[r][c] = sum over splits (upper triangle r <= c only).  grid (ceil(m/256), m).
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_gram_fold(const double* __restrict__ Cp, int splits, int64_t ldc,
+                                                   int64_t m, double* __restrict__ G, int64_t ldg) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (r >= m || r > c) return;
+  constexpr int KB = CPLX ? 64 : 128;
+  const int64_t z = c / KB, cc = c % KB;
+  if (CPLX) {
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < splits; ++s) {
+      const double* base = Cp + ((z * splits + s) * 128) * ldc;
+      re += base[(2 * cc) * ldc + r];
+      im += base[(2 * cc + 1) * ldc + r];
+    }
+    G[2 * (c * ldg + r)] = re;
+    G[2 * (c * ldg + r) + 1] = im;
+  } else {
+    double v = 0.0;
+    for (int s = 0; s < splits; ++s) v += Cp[((z * splits + s) * 128 + cc) * ldc + r];
+    G[c * ldg + r] = v;
+  }
+}
+
+hipError_t launch_gram_fold(bool cplx, const double* Cp, int splits, int64_t ldc, int64_t m, void* G, int64_t ldg,
+                            hipStream_t st) {
+  const dim3 grid((unsigned)ceil_div(m, 256), (unsigned)m);
+  if (cplx)
+    hipLaunchKernelGGL(k_gram_fold<true>, grid, dim3(256), 0, st, Cp, splits, ldc, m, (double*)G, ldg);
+  else
+    hipLaunchKernelGGL(k_gram_fold<false>, grid, dim3(256), 0, st, Cp, splits, ldc, m, (double*)G, ldg);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_fill0(void* p, int64_t bytes, hipStream_t st) {
   if (bytes % 16 != 0 || ((uintptr_t)p & 15) != 0) return hipErrorInvalidValue;

@@ -55,6 +55,8 @@ struct QrArgs {
 };
 int64_t qr_work_bytes(int dtype, int64_t l, int64_t m);
 hipError_t launch_qr(int dtype, const QrArgs& a, hipStream_t st);
+// out = [max |R_ii|, min |R_ii|, 1 if a diagonal entry is not finite]
+hipError_t launch_rdiag_range(int dtype, const void* R, int64_t ldr, int64_t m, double* out, hipStream_t st);
 
 struct AdjArgs {
   const void* A;
@@ -159,6 +161,7 @@ struct DGemmArgs {
   int kc;
   int64_t ks;
   int tri;
+  int herm;  // Gram product: skip tiles below the diagonal
   double* Cp;
   int64_t ldc;
   void* O;
@@ -194,5 +197,16 @@ hipError_t launch_blk_flag(BlkState* state, hipStream_t st);
 hipError_t launch_blk_refine(bool cplx, int kc, int64_t m, void* y_out, const void* y, BlkState* state,
                              hipStream_t st);
 hipError_t launch_fill0(void* p, int64_t bytes, hipStream_t st);
+
+// Preconditioner from the Gram matrix (chol.hip, block.hip): G = S* S in
+// FP64, then R with R* R = G by blocked Cholesky (tiles of 32).
+int gram_col_block(int dtype);
+hipError_t launch_gram_s(int dtype, const void* S, int64_t lds, int64_t l, int64_t m, void* G, int64_t ldg,
+                         double* Cp, int64_t ldc, int splits, int64_t ks, hipStream_t st);
+hipError_t launch_gram_fold(bool cplx, const double* Cp, int splits, int64_t ldc, int64_t m, void* G, int64_t ldg,
+                            hipStream_t st);
+// R (FP64, upper, ld ldr) from G (upper part, overwritten by Schur
+// complements); bad[0] = 1 if a pivot is not positive and finite.
+hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, int32_t* bad, hipStream_t st);
 
 }  // namespace mn

@@ -421,6 +421,17 @@ int64_t qr_work_bytes(int dtype, int64_t l, int64_t m) {
   return elems * dtype_size(dtype);
 }
 
+hipError_t launch_rdiag_range(int dtype, const void* R, int64_t ldr, int64_t m, double* out, hipStream_t st) {
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL((k_rdiag_range<cd>), dim3(1), dim3(1024), 0, st, (const cd*)R, ldr, m, out); break;
+    case 1: hipLaunchKernelGGL((k_rdiag_range<cf>), dim3(1), dim3(1024), 0, st, (const cf*)R, ldr, m, out); break;
+    case 2: hipLaunchKernelGGL((k_rdiag_range<double>), dim3(1), dim3(1024), 0, st, (const double*)R, ldr, m, out); break;
+    case 3: hipLaunchKernelGGL((k_rdiag_range<float>), dim3(1), dim3(1024), 0, st, (const float*)R, ldr, m, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_qr(int dtype, const QrArgs& a, hipStream_t st) {
   switch (dtype) {
     case 0: return qr_impl<cd>(a, st);

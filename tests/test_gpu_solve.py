@@ -285,3 +285,35 @@ def test_batched_one_bad_idx_others_solved():
         assert infos[k]["status"] == 0
         A, b = sys_[k]
         assert rel(to_np(xs[k]), oracle.classical_minnorm(A, b)) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["c128", "f64", "c64"])
+def test_gram_and_householder_factors_agree(kind):
+    """Step 2's R from the Cholesky of the FP64 Gram matrix (default) and from
+    Householder QR of S give the same preconditioner: both solves meet eps
+    and take the same number of iterations up to one."""
+    from paper_0905_4745_amd import api
+    real = kind == "f64"
+    A, b, _ = synth.make_svd(150, 4000, 1e3, seed=21, complex_=not real)
+    if kind == "c64":
+        A = A.astype(np.complex64)
+    N = synth.next_pow2(4000)
+    d, idx = synth.draw_srft(N, 600, seed=21, real=real)
+    xg, ig = _solve(A, b, 1e-10, d, idx, N, opts=api.SolveOptions(precond=0))
+    xh, ih = _solve(A, b, 1e-10, d, idx, N, opts=api.SolveOptions(precond=1))
+    p = oracle.refined_minnorm(A.astype(np.complex128) if kind == "c64" else A, b)
+    say(f"  {kind}: gram iters {ig['iters']} err {rel(xg, p):.2e}; householder iters {ih['iters']} err {rel(xh, p):.2e}")
+    assert ig["status"] == 0 and ih["status"] == 0
+    assert rel(xg, p) <= 1e-10 and rel(xh, p) <= 1e-10
+    assert abs(ig["iters"] - ih["iters"]) <= max(1, ih["iters"] // 10)
+
+
+def test_ill_conditioned_falls_back_and_meets_eps():
+    """cond 1e7: the Gram route declines (diagonal spread beyond 1e5) and the
+    Householder factor is used; the FP64 result still meets eps."""
+    A, b, _ = synth.make_svd(40, 1500, 1e7, seed=22)
+    N = 2048
+    d, idx = synth.draw_srft(N, 160, seed=22)
+    x, info = _solve(A, b, 1e-8, d, idx, N)
+    assert info["status"] == 0
+    assert rel(x, oracle.refined_minnorm(A, b)) <= 1e-8
