@@ -64,7 +64,18 @@ def parse():
                          "10^U(-2,2), 64 RHS through the block path; batched: 256 uneven real "
                          "systems (FP64 data + FP32 copies) in one batched call")
     ap.add_argument("--streams", type=int, default=8, help="batched: concurrent lanes")
+    ap.add_argument("--no-tune", action="store_true", help="built-in launch plans instead of tuned ones")
+    ap.add_argument("--plans-out", default=None, help="write the tuned launch plans (JSON) here")
     return ap.parse_args()
+
+
+def plans_dump(api, args):
+    """The handle's launch plans (as saved to JSON), optionally kept on disk."""
+    import tempfile
+    path = args.plans_out or os.path.join(tempfile.mkdtemp(), "plans.json")
+    api.plans_save(path)
+    with open(path) as f:
+        return json.load(f)["plans"]
 
 
 def log(msg):
@@ -105,10 +116,13 @@ def main():
     x = torch.empty((1, n), dtype=torch.complex128, device=dev)
     torch.cuda.synchronize()
 
+    # launch plans are tuned on the first warm-up solve (timed candidates on
+    # the live operands, outside the timed region) and reused afterwards
+    opts = api.SolveOptions(tune=0 if args.no_tune else 1)
     log(f"[bench] warmup {args.warmup}")
     for s in range(args.warmup):
         d, idx = draws[s]
-        api.minnorm_solve(At, bt, eps, d, idx, N, x=x)
+        api.minnorm_solve(At, bt, eps, d, idx, N, x=x, opts=opts)
     torch.cuda.synchronize()
 
     log(f"[bench] timed {args.steps} solves")
@@ -117,7 +131,7 @@ def main():
     t0 = time.perf_counter()
     for s in range(args.steps):
         d, idx = draws[args.warmup + s]
-        _, info = api.minnorm_solve(At, bt, eps, d, idx, N, x=x)
+        _, info = api.minnorm_solve(At, bt, eps, d, idx, N, x=x, opts=opts)
         iters.append(info["iters"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -194,6 +208,7 @@ def main():
         "cg_iters": iters,
         "rel_err": rel_err,
         "cpu_baseline": cpu,
+        "plans": plans_dump(api, args),
     }
     print(json.dumps(out), flush=True)
 
@@ -228,9 +243,10 @@ def main_multirhs(args):
         draws.append((torch.from_numpy(d).to(dev), torch.from_numpy(idx).to(dev)))
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup}")
+    opts = api.SolveOptions(tune=0 if args.no_tune else 1)
     for s_ in range(args.warmup):
         d, idx = draws[s_]
-        _, info = api.minnorm_solve(At, Bt, eps, d, idx, N, x=X)
+        _, info = api.minnorm_solve(At, Bt, eps, d, idx, N, x=X, opts=opts)
         log(f"[bench]   info {info}")
     torch.cuda.synchronize()
     log(f"[bench] timed {args.steps} solves of {k} RHS")
@@ -239,7 +255,7 @@ def main_multirhs(args):
     t0 = time.perf_counter()
     for s_ in range(args.steps):
         d, idx = draws[args.warmup + s_]
-        _, info = api.minnorm_solve(At, Bt, eps, d, idx, N, x=X)
+        _, info = api.minnorm_solve(At, Bt, eps, d, idx, N, x=X, opts=opts)
         infos.append(info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -285,6 +301,7 @@ def main_multirhs(args):
         "stage_ms": infos[-1]["stage_ms"],
         "cert_rel_max": max(i["cert_rel"] for i in infos),
         "cpu_baseline": None,
+        "plans": plans_dump(api, args),
     }
     print(json.dumps(out), flush=True)
 

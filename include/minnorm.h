@@ -104,6 +104,11 @@ typedef struct {
                             operator within about 1e-6 of the identity),
                             otherwise the Householder factorisation;
                             1 = Householder QR of S always                  [0] */
+  int32_t tune;          /* 1: a launch shape without a plan is timed over its
+                            candidates on the live operands before use and the
+                            fastest is kept in the handle's plan table (see
+                            mn_plans_save); 0: plans already in the table, else
+                            the built-in choices                            [0] */
 } mn_opts;
 
 /* Per-solve report (host struct written by the library). */
@@ -131,14 +136,35 @@ int64_t mn_workspace_bytes(mn_handle h);
  * enable != 0, every later launch of the passes over A is bracketed by a
  * pair of HIP events on the handle's stream; mn_profile_read synchronises the
  * stream and returns how many launches of `kernel` ("gemv_adj": w = A* u,
- * "gemv_fwd": q = A w, "gram": the fused q = A (A* p) used when m <= 512)
- * were recorded since the last mn_profile call and their
+ * "gemv_fwd": q = A w, "gram": the fused q = A (A* p) used when m <= 512,
+ * "block_adj" / "block_fwd": the split-BF16 products W = A* P and Q = A W of
+ * the multi-right-hand-side form, "block_residual": its FP64 products
+ * U = A* Y and A U) were recorded since the last mn_profile call and their
  * summed duration in milliseconds.  Launches enqueued after the iteration
  * had already stopped (they return at once) are not counted.  mn_profile
  * clears the records.
  * Errors: -1 NULL handle; -2 unknown kernel name; -3/-4 NULL output. */
 int mn_profile(mn_handle h, int enable);
 int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* total_ms);
+
+/* Launch plans (autotuning).  A plan is one integer per kernel and shape:
+ * "gram/<dtype>/<m>/<n>/0"   fused pass: workgroup count (low 16 bits; 256,
+ *                            512 or 1024) and strip width (bit 16 set: 16
+ *                            bytes of a row per thread instead of 32);
+ * "sketch_chunk_mb/<dtype>/<m>/<N>/0"  four-step FFT: MB of the intermediate
+ *                            per chunk of rows (16, 32, 64 or 128);
+ * "block_fwd_wg/<dtype>/<m>/<n>/<k>"   block product A W: workgroups aimed
+ *                            for when splitting its n columns (512..2048).
+ * Plans are chosen by timing when mn_opts.tune = 1 (see there).
+ * mn_plans_save writes the handle's table as JSON {"format":
+ * "minnorm-plans-1", "plans": {key: value}, "best_ms": {key: ms}};
+ * mn_plans_load merges such a file into the table (existing keys are
+ * replaced).  mn_plans_count returns the number of plans held.
+ * Errors: -1 NULL handle; -2 NULL path, unreadable/unwritable file or a file
+ * without a "plans" object of "key": integer pairs. */
+int mn_plans_save(mn_handle h, const char* path);
+int mn_plans_load(mn_handle h, const char* path);
+int mn_plans_count(mn_handle h);
 
 /* Step 1, eq. (randmat): S = T A*, T = S F D of size l x N (eqs. SRFT,
  * SRFT2, with H = I), applied to every row of A:

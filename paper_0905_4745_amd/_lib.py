@@ -14,7 +14,8 @@ MN_C128, MN_C64, MN_F64, MN_F32 = 0, 1, 2, 3
 class MnOpts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("stop_rule", C.c_int32), ("max_iter", C.c_int32),
                 ("max_refine", C.c_int32), ("check_every", C.c_int32), ("inner_digits", C.c_int32),
-                ("block", C.c_int32), ("streams", C.c_int32), ("precond", C.c_int32)]
+                ("block", C.c_int32), ("streams", C.c_int32), ("precond", C.c_int32),
+                ("tune", C.c_int32)]
 
 
 class MnInfo(C.Structure):
@@ -31,8 +32,8 @@ class MnInfo(C.Structure):
 
 
 EXPORTS = ["mn_create", "mn_destroy", "mn_set_stream", "mn_status_string", "mn_last_hip_error",
-           "mn_workspace_bytes", "mn_profile", "mn_profile_read", "srft_sketch", "build_preconditioner", "minnorm_solve",
-           "minnorm_solve_batched"]
+           "mn_workspace_bytes", "mn_profile", "mn_profile_read", "mn_plans_save", "mn_plans_load",
+           "mn_plans_count", "srft_sketch", "build_preconditioner", "minnorm_solve", "minnorm_solve_batched"]
 
 _lib = None
 
@@ -64,6 +65,12 @@ def load():
     lib.mn_profile.restype = I32
     lib.mn_profile_read.argtypes = [P, C.c_char_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     lib.mn_profile_read.restype = I32
+    lib.mn_plans_save.argtypes = [P, C.c_char_p]
+    lib.mn_plans_save.restype = I32
+    lib.mn_plans_load.argtypes = [P, C.c_char_p]
+    lib.mn_plans_load.restype = I32
+    lib.mn_plans_count.argtypes = [P]
+    lib.mn_plans_count.restype = I32
     lib.srft_sketch.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, P, I64]
     lib.srft_sketch.restype = I32
     lib.build_preconditioner.argtypes = [P, I32, I64, I64, P, I64, P, I64]

@@ -9,6 +9,7 @@ buffers, i.e. column-major l x m and m x m arrays.
 from __future__ import annotations
 
 import ctypes as C
+import os
 from dataclasses import dataclass
 
 import torch
@@ -121,6 +122,7 @@ class SolveOptions:
     block: int = 0  # several RHS: 0 automatic, 1 one at a time, 2 block form
     streams: int = 8  # batched: systems solved concurrently
     precond: int = 0  # 0: Cholesky of the FP64 Gram matrix when safe, else Householder; 1: Householder
+    tune: int = 0  # 1: time the launch candidates of new shapes and keep the fastest plan
 
     def to_c(self):
         o = L.MnOpts()
@@ -133,6 +135,7 @@ class SolveOptions:
         o.block = self.block
         o.streams = self.streams
         o.precond = self.precond
+        o.tune = self.tune
         return o
 
 
@@ -211,6 +214,27 @@ def minnorm_solve_batched(As, bs, eps, ds, idxs, Ns, A_los=None, opts: SolveOpti
 def workspace_bytes(device=None) -> int:
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     return int(L.load().mn_workspace_bytes(_handle(dev)))
+
+
+def plans_save(path: str, device=None) -> None:
+    """Write the handle's launch plans (autotuned choices) as JSON."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    st = L.load().mn_plans_save(_handle(dev), os.fsencode(path))
+    if st != 0:
+        raise MinnormError("mn_plans_save", st)
+
+
+def plans_load(path: str, device=None) -> None:
+    """Merge launch plans from a JSON file written by plans_save."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    st = L.load().mn_plans_load(_handle(dev), os.fsencode(path))
+    if st != 0:
+        raise MinnormError("mn_plans_load", st)
+
+
+def plans_count(device=None) -> int:
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    return int(L.load().mn_plans_count(_handle(dev)))
 
 
 def profile(enable: bool, device=None) -> None:

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <atomic>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <tuple>
@@ -55,6 +56,11 @@ struct mn_handle_s {
   // concurrent lanes of minnorm_solve_batched: child handles on their own streams
   bool owns_stream = false;
   std::vector<mn_handle> lanes;
+  // launch plans chosen by timing (mn_opts.tune), keyed by kernel and shape
+  std::map<std::string, int> plans;
+  std::map<std::string, float> plan_ms;
+  hipEvent_t tev[2] = {};
+  mn_handle parent = nullptr;  // lanes read and add plans through their parent
 };
 
 namespace {
@@ -145,11 +151,68 @@ void ev_record(mn_handle h, int i) {
   if (h->events) (void)hipEventRecord(h->ev[i], h->stream);
 }
 
+// ---- launch plans -------------------------------------------------------------
+// A plan is one integer per (kernel, dtype, shape) key.  With mn_opts.tune set,
+// a key without a plan is decided by timing every candidate on the live
+// operands (one warm-up launch, then the best of three, HIP events on the
+// handle's stream); mn_plans_save / mn_plans_load keep the table as JSON.
+// Lanes of the batched call share their parent's table.
+std::mutex g_plan_mu;
+
+mn_handle plan_owner(mn_handle h) { return h->parent ? h->parent : h; }
+
+bool plan_find(mn_handle h, const std::string& key, int* v) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  mn_handle o = plan_owner(h);
+  auto it = o->plans.find(key);
+  if (it == o->plans.end()) return false;
+  *v = it->second;
+  return true;
+}
+
+template <typename F>
+int plan_get(mn_handle h, const mn_opts& o, const std::string& key, const std::vector<int>& cands, F run) {
+  int v = 0;
+  if (plan_find(h, key, &v)) return v;
+  if (!o.tune) return cands[0];
+  float best = 1e30f;
+  int pick = cands[0];
+  for (int c : cands) {
+    run(c);
+    float tmin = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+      ck(hipEventRecord(h->tev[0], h->stream));
+      run(c);
+      ck(hipEventRecord(h->tev[1], h->stream));
+      ck(hipEventSynchronize(h->tev[1]));
+      float t = 0.f;
+      ck(hipEventElapsedTime(&t, h->tev[0], h->tev[1]));
+      tmin = std::min(tmin, t);
+    }
+    if (tmin < best) {
+      best = tmin;
+      pick = c;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  mn_handle ow = plan_owner(h);
+  ow->plans[key] = pick;
+  ow->plan_ms[key] = best;
+  return pick;
+}
+
+std::string plan_key(const char* kind, int64_t a, int64_t b, int64_t c, int64_t d) {
+  char buf[128];
+  snprintf(buf, sizeof buf, "%s/%lld/%lld/%lld/%lld", kind, (long long)a, (long long)b, (long long)c, (long long)d);
+  return buf;
+}
+
 // ----------------------------------------------------------------------------
 // Step 1: sketch of the rows of A (dtype) into S (l x m, lds).  idx must
 // already be validated into the inverse map `inv`.
 void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, int64_t N, int64_t l,
-                const void* d, const int32_t* idx, const int32_t* inv, void* S, int64_t lds) {
+                const void* d, const int32_t* idx, const int32_t* inv, void* S, int64_t lds,
+                const mn_opts* o = nullptr) {
   const bool single = is_single(dtype);
   const int64_t ces = single ? 8 : 16;
   SketchArgs a{};
@@ -165,16 +228,26 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   a.S = S;
   a.lds = lds;
   a.twiddle = twiddles(h, N, single);
-  if (N > kFftMaxLds) {
-    // rows per four-step chunk: intermediate of about 64 MB, so it can stay
-    // in the 256 MB last-level cache between the two passes
-    int64_t chunk = (int64_t)(64ll << 20) / (N * ces);
+  if (N <= kFftMaxLds) {
+    ck(launch_sketch(dtype, a, h->stream));
+    return;
+  }
+  // rows per four-step chunk: an intermediate of 64 MB by default (it can
+  // stay in the 256 MB last-level cache between the two passes); the plan
+  // picks 16 .. 128 MB
+  auto run = [&](int mb) {
+    int64_t chunk = ((int64_t)mb << 20) / (N * ces);
     if (chunk < 1) chunk = 1;
     if (chunk > m) chunk = m;
     a.chunk_rows = chunk;
     a.work = ws(h, "fft_y", (size_t)(chunk * N * ces));
-  }
-  ck(launch_sketch(dtype, a, h->stream));
+    ck(launch_sketch(dtype, a, h->stream));
+  };
+  int mb = 64;
+  const std::string key = plan_key("sketch_chunk_mb", dtype, m, N, 0);
+  if (o) mb = plan_get(h, *o, key, {64, 16, 32, 128}, run);
+  else plan_find(h, key, &mb);
+  run(mb);
 }
 
 // Validate idx on the device and build the inverse subsample map.
@@ -334,6 +407,25 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
   const size_t rec_begin = h->recs.size();
   const int32_t* flag = &v.st->done;
   const bool fused = gram_supported(c.bulk, c.m, c.Ab, c.ldab);
+  int gram_plan = 512;
+  if (fused) {
+    // plan: workgroup count (low 16 bits) and strip width (bit 16: narrow)
+    auto run = [&](int pl) {
+      GramArgs ga{};
+      ga.A = c.Ab;
+      ga.lda = c.ldab;
+      ga.m = c.m;
+      ga.n = c.n;
+      ga.p = v.p;
+      ga.qpart = v.qpart;
+      ga.q = v.q;
+      ga.max_wg = pl & 0xFFFF;
+      ga.narrow = pl >> 16;
+      ck(launch_gram(c.bulk, ga, h->stream));
+    };
+    gram_plan = plan_get(h, c.o, plan_key("gram", c.bulk, c.m, c.n, 0),
+                         {512, 256, 1024, 512 | 0x10000, 256 | 0x10000, 1024 | 0x10000}, run);
+  }
   int enqueued = 0;
   while (true) {
     for (int k = 0; k < c.o.check_every; ++k) {
@@ -347,6 +439,8 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
         ga.qpart = v.qpart;
         ga.q = v.q;
         ga.flag = flag;
+        ga.max_wg = gram_plan & 0xFFFF;
+        ga.narrow = gram_plan >> 16;
         std::tie(ga.ev_begin, ga.ev_end) = prof_pair(h, K_GRAM);
         ck(launch_gram(c.bulk, ga, h->stream));
         CgStep a{};
@@ -528,7 +622,7 @@ struct BlockPlan {
   int ncol;                  // real output columns
 };
 
-BlockPlan plan_block(bool cplx, int64_t m, int64_t n, int kc) {
+BlockPlan plan_block(bool cplx, int64_t m, int64_t n, int kc, int target_wg = 1024) {
   BlockPlan p{};
   const int64_t E = cplx ? 2 : 1;
   const int64_t kt = bf_ktile();
@@ -537,8 +631,8 @@ BlockPlan plan_block(bool cplx, int64_t m, int64_t n, int kc) {
   p.ldc = round_up(m, 4);
   p.ncol = gemm_ncol(cplx, kc);
   const int64_t tiles = cdiv(m, 128);
-  // about 1024 workgroups for the bulk product, 512 for the FP64 ones
-  int64_t s = cdiv(1024, tiles);
+  // about target_wg workgroups for the bulk product A W, 512 for the FP64 ones
+  int64_t s = cdiv(target_wg, tiles);
   s = std::min<int64_t>(std::max<int64_t>(s, 1), p.Kp2 / kt);
   p.ks_fwd = round_up(cdiv(p.Kp2, s), kt);
   p.s_fwd = (int)cdiv(p.Kp2, p.ks_fwd);
@@ -562,7 +656,7 @@ int solve_block(const SolveCtx& c, const void* b, int64_t ldb, int kc, void* x, 
   const bool cplx = is_complex(c.dtype);
   const int64_t W = wide_size(c.dtype);
   const int64_t m = c.m, n = c.n;
-  const BlockPlan pl = plan_block(cplx, m, n, kc);
+  BlockPlan pl = plan_block(cplx, m, n, kc);
   const int64_t ldx_pre = rinv_ld(m);
   // bulk planes: A (m x Kp2) and its transpose (n x Kp1)
   uint16_t* a_hi = (uint16_t*)ws(h, "blk_a_hi", (size_t)(m * pl.Kp2 * 2));
@@ -591,6 +685,29 @@ int solve_block(const SolveCtx& c, const void* b, int64_t ldb, int kc, void* x, 
   void* q = ws(h, "blk_q", vb);
   void* s = ws(h, "blk_s", vb);
   void* z = ws(h, "blk_z", vb);
+  // plan: workgroups of the A W product (split count over its n columns)
+  {
+    auto run = [&](int target) {
+      const BlockPlan pp = plan_block(cplx, m, n, kc, target);
+      float* qpt = (float*)ws(h, "blk_qp", (size_t)pp.s_fwd * pp.ncol * pp.ldc * 4);
+      BfGemmArgs g2{};
+      g2.Ahi = a_hi;
+      g2.Alo = a_lo;
+      g2.lda = pp.Kp2;
+      g2.M = m;
+      g2.Bhi = w_hi;
+      g2.Blo = w_lo;
+      g2.ldb = pp.Kp2;
+      g2.kc = kc;
+      g2.Kp = pp.Kp2;
+      g2.ks = pp.ks_fwd;
+      g2.Cp = qpt;
+      g2.ldc = pp.ldc;
+      ck(launch_gemm_bf(cplx, false, 0, g2, pp.s_fwd, st));
+    };
+    const int target = plan_get(h, c.o, plan_key("block_fwd_wg", c.bulk, m, n, kc), {1024, 512, 2048}, run);
+    pl = plan_block(cplx, m, n, kc, target);
+  }
   float* qp = (float*)ws(h, "blk_qp", (size_t)pl.s_fwd * pl.ncol * pl.ldc * 4);
   const int sd_max = std::max(pl.s_d, pl.s_res);
   double* dp = (double*)ws(h, "blk_dp", (size_t)sd_max * pl.ncol * pl.ldc * 8);
@@ -771,6 +888,7 @@ mn_opts resolve_opts(const mn_opts* o) {
 bool opts_valid(const mn_opts& o) {
   return o.alpha > 1.0 && (o.stop_rule == 0 || o.stop_rule == 1) && o.max_iter > 0 && o.max_refine > 0 &&
          o.block >= 0 && o.block <= 2 && o.streams > 0 && o.streams <= 64 && (o.precond == 0 || o.precond == 1) &&
+         (o.tune == 0 || o.tune == 1) &&
          o.check_every > 0 && o.check_every <= 1024 && o.inner_digits > 0 && o.inner_digits <= 12;
 }
 
@@ -813,7 +931,7 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   if (!prepare_idx(h, idx, l, N, &inv)) return -16;
   const int64_t bes = dtype_size(c.bulk);
   void* S = ws(h, "S", (size_t)(l * m * bes));
-  run_sketch(h, c.bulk, m, n, c.Ab, c.ldab, N, l, d, idx, inv, S, l);
+  run_sketch(h, c.bulk, m, n, c.Ab, c.ldab, N, l, d, idx, inv, S, l, &o);
   ev_record(h, 1);
   // Step 2's R: Cholesky of the FP64 Gram matrix when that is accurate,
   // Householder QR of S otherwise
@@ -913,6 +1031,7 @@ int mn_create(mn_handle* hp, void* stream) {
     ck(hipHostMalloc((void**)&h->host_flag, 64, hipHostMallocDefault));
     ck(hipHostMalloc((void**)&h->host_diag, 64, hipHostMallocDefault));
     for (auto& e : h->ev) ck(hipEventCreate(&e));
+    for (auto& e : h->tev) ck(hipEventCreate(&e));
   } catch (HipFail f) {
     mn_destroy(h);
     return fail_hip(f.e);
@@ -935,6 +1054,8 @@ int mn_destroy(mn_handle h) {
   if (h->host_flag) (void)hipHostFree(h->host_flag);
   if (h->host_diag) (void)hipHostFree(h->host_diag);
   for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : h->tev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : h->pool) (void)hipEventDestroy(e);
   if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -999,6 +1120,70 @@ int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* tot
     return fail_hip(f.e);
   }
   return 0;
+}
+
+int mn_plans_save(mn_handle h, const char* path) {
+  if (!h) return -1;
+  if (!path) return -2;
+  FILE* f = fopen(path, "w");
+  if (!f) return -2;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  fprintf(f, "{\n  \"format\": \"minnorm-plans-1\",\n  \"plans\": {");
+  bool first = true;
+  for (auto& kv : h->plans) {
+    fprintf(f, "%s\n    \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+    first = false;
+  }
+  fprintf(f, "\n  },\n  \"best_ms\": {");
+  first = true;
+  for (auto& kv : h->plan_ms) {
+    fprintf(f, "%s\n    \"%s\": %.6g", first ? "" : ",", kv.first.c_str(), (double)kv.second);
+    first = false;
+  }
+  fprintf(f, "\n  }\n}\n");
+  const bool ok = fclose(f) == 0;
+  return ok ? 0 : -2;
+}
+
+int mn_plans_load(mn_handle h, const char* path) {
+  if (!h) return -1;
+  if (!path) return -2;
+  FILE* f = fopen(path, "r");
+  if (!f) return -2;
+  std::string txt;
+  char buf[4096];
+  size_t k;
+  while ((k = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, k);
+  fclose(f);
+  // the "plans" object: "key": integer pairs
+  const size_t at = txt.find("\"plans\"");
+  if (at == std::string::npos) return -2;
+  size_t i = txt.find('{', at);
+  const size_t end = i == std::string::npos ? std::string::npos : txt.find('}', i);
+  if (end == std::string::npos) return -2;
+  std::map<std::string, int> got;
+  while (true) {
+    const size_t q0 = txt.find('"', i);
+    if (q0 == std::string::npos || q0 > end) break;
+    const size_t q1 = txt.find('"', q0 + 1);
+    if (q1 == std::string::npos || q1 > end) return -2;
+    const size_t colon = txt.find(':', q1);
+    if (colon == std::string::npos || colon > end) return -2;
+    char* stop = nullptr;
+    const long v = strtol(txt.c_str() + colon + 1, &stop, 10);
+    if (stop == txt.c_str() + colon + 1) return -2;
+    got[txt.substr(q0 + 1, q1 - q0 - 1)] = (int)v;
+    i = (size_t)(stop - txt.c_str());
+  }
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  for (auto& kv : got) h->plans[kv.first] = kv.second;
+  return (int)got.size() >= 0 ? 0 : -2;
+}
+
+int mn_plans_count(mn_handle h) {
+  if (!h) return -1;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  return (int)h->plans.size();
 }
 
 int64_t mn_workspace_bytes(mn_handle h) {
@@ -1110,6 +1295,7 @@ int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* 
         return e;
       }
       c->owns_stream = true;
+      c->parent = h;
       h->lanes.push_back(c);
     }
     ck(hipEventRecord(h->ev[6], h->stream));

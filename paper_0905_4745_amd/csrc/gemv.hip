@@ -388,12 +388,12 @@ static hipError_t fwd_impl(const FwdArgs& a, hipStream_t st) {
 
 // the widest vector (4 elements) gives the fewest column blocks and hence
 // the most slabs: size the partial buffer for that case
-template <typename V, typename C, typename U>
-static hipError_t gram_impl(const GramArgs& a, hipStream_t st) {
-  constexpr int CPT = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;  // 32 bytes of a row per thread
+template <typename V, typename C, typename U, int CPT>
+static hipError_t gram_go(const GramArgs& a, hipStream_t st) {
   constexpr int WD = 8 * CPT;
   const int64_t nstrips = ceil_div(a.n, WD);
-  int64_t G = nstrips < kGramMaxWg ? nstrips : kGramMaxWg;
+  const int64_t maxwg = a.max_wg > 0 && a.max_wg <= kGramMaxWg ? a.max_wg : 512;
+  int64_t G = nstrips < maxwg ? nstrips : maxwg;
   const int64_t spw = ceil_div(nstrips, G);
   G = ceil_div(nstrips, spw);
   const V* A = reinterpret_cast<const V*>(a.A);
@@ -417,6 +417,14 @@ static hipError_t gram_impl(const GramArgs& a, hipStream_t st) {
   hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64), 8), dim3(256), 0, st, qpart, (int)G,
                      a.m, reinterpret_cast<U*>(a.q), a.flag);
   return hipGetLastError();
+}
+
+// Strip width: 32 bytes of a row per thread (CPT0), or half of that.
+template <typename V, typename C, typename U>
+static hipError_t gram_impl(const GramArgs& a, hipStream_t st) {
+  constexpr int CPT0 = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;
+  constexpr int CPT1 = CPT0 / 2 > 0 ? CPT0 / 2 : 1;
+  return a.narrow ? gram_go<V, C, U, CPT1>(a, st) : gram_go<V, C, U, CPT0>(a, st);
 }
 
 bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda) {

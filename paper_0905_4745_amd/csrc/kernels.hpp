@@ -84,7 +84,7 @@ hipError_t launch_gemv_fwd(int dtype, bool wide, const FwdArgs& a, hipStream_t s
 
 // Fused q = A (A* p) in one read of A (m <= kGramMaxRows, 16-byte aligned rows).
 constexpr int kGramMaxRows = 512;
-constexpr int kGramMaxWg = 512;  // partial sums per row
+constexpr int kGramMaxWg = 1024;  // partial sums per row (largest workgroup count)
 constexpr int kGramParts = 8;    // slices of q left for the CG kernel to add
 struct GramArgs {
   const void* A;
@@ -94,6 +94,8 @@ struct GramArgs {
   void* q;         // FP64, kGramParts * m: q = sum of the kGramParts slices
   const int32_t* flag;
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+  int max_wg = 512;  // plan: workgroups (each streams a contiguous run of strips)
+  int narrow = 0;    // plan: strips of 16 bytes per thread and row instead of 32
 };
 bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda);
 hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st);
