@@ -109,6 +109,11 @@ typedef struct {
                             fastest is kept in the handle's plan table (see
                             mn_plans_save); 0: plans already in the table, else
                             the built-in choices                            [0] */
+  int32_t batch_form;    /* minnorm_solve_batched: 0 = fused when every system
+                            has m <= 512 and precond = 0 (each stage of all
+                            systems is one launch; the systems iterate in
+                            lockstep, each with its own stopping test), else
+                            concurrent lanes; 1 = concurrent lanes           [0] */
 } mn_opts;
 
 /* Per-solve report (host struct written by the library). */
@@ -149,8 +154,12 @@ int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* tot
 
 /* Launch plans (autotuning).  A plan is one integer per kernel and shape:
  * "gram/<dtype>/<m>/<n>/0"   fused pass: workgroup count (low 16 bits; 256,
- *                            512 or 1024) and strip width (bit 16 set: 16
- *                            bytes of a row per thread instead of 32);
+ *                            512 or 1024), strip width (bit 16 set: 16
+ *                            bytes of a row per thread instead of 32) and
+ *                            strip order (bit 17 set: workgroup g takes strips
+ *                            g, g + G, ... instead of a contiguous run) and
+ *                            workgroup size (bit 18 set: 1024 threads, half
+ *                            the rows per thread; 512 otherwise);
  * "sketch_chunk_mb/<dtype>/<m>/<N>/0"  four-step FFT: MB of the intermediate
  *                            per chunk of rows (16, 32, 64 or 128);
  * "block_fwd_wg/<dtype>/<m>/<n>/<k>"   block product A W: workgroups aimed

@@ -15,7 +15,7 @@ class MnOpts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("stop_rule", C.c_int32), ("max_iter", C.c_int32),
                 ("max_refine", C.c_int32), ("check_every", C.c_int32), ("inner_digits", C.c_int32),
                 ("block", C.c_int32), ("streams", C.c_int32), ("precond", C.c_int32),
-                ("tune", C.c_int32)]
+                ("tune", C.c_int32), ("batch_form", C.c_int32)]
 
 
 class MnInfo(C.Structure):

@@ -123,6 +123,7 @@ class SolveOptions:
     streams: int = 8  # batched: systems solved concurrently
     precond: int = 0  # 0: Cholesky of the FP64 Gram matrix when safe, else Householder; 1: Householder
     tune: int = 0  # 1: time the launch candidates of new shapes and keep the fastest plan
+    batch_form: int = 0  # batched: 0 fused when possible, 1 concurrent lanes
 
     def to_c(self):
         o = L.MnOpts()
@@ -136,6 +137,7 @@ class SolveOptions:
         o.streams = self.streams
         o.precond = self.precond
         o.tune = self.tune
+        o.batch_form = self.batch_form
         return o
 
 

@@ -41,7 +41,7 @@ struct mn_handle_s {
   hipStream_t stream = nullptr;
   int device = 0;
   std::map<std::string, Buf> bufs;
-  Twiddle tw[2];  // [0] complex double, [1] complex float
+  std::map<std::pair<int64_t, int>, Twiddle> tw;  // W_N^k tables by (N, single precision)
   PcgState* host_state = nullptr;  // pinned
   BlkState* host_blk = nullptr;    // pinned
   int32_t* host_flag = nullptr;    // pinned
@@ -61,6 +61,8 @@ struct mn_handle_s {
   std::map<std::string, float> plan_ms;
   hipEvent_t tev[2] = {};
   mn_handle parent = nullptr;  // lanes read and add plans through their parent
+  void* host_stage = nullptr;  // pinned staging of the fused batched form
+  size_t host_stage_bytes = 0;
 };
 
 namespace {
@@ -96,14 +98,8 @@ int compute_cplx_dtype(int dtype) { return is_single(dtype) ? 1 : 0; }  // twidd
 
 // W_N^k = exp(-2 pi i k / N), k < N, computed in long double and rounded.
 const void* twiddles(mn_handle h, int64_t N, bool single) {
-  Twiddle& t = h->tw[single ? 1 : 0];
+  Twiddle& t = h->tw[{N, single ? 1 : 0}];
   if (t.N == N && t.p) return t.p;
-  if (t.p) {
-    ck(hipStreamSynchronize(h->stream));
-    ck(hipFree(t.p));
-    t.p = nullptr;
-    t.N = 0;
-  }
   const size_t es = single ? 8 : 16;
   std::vector<unsigned char> host((size_t)N * es);
   const long double two_pi = 6.283185307179586476925286766559005768L;
@@ -420,11 +416,17 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
       ga.qpart = v.qpart;
       ga.q = v.q;
       ga.max_wg = pl & 0xFFFF;
-      ga.narrow = pl >> 16;
+      ga.narrow = (pl >> 16) & 1;
+      ga.interleave = (pl >> 17) & 1;
+      ga.wide_wg = (pl >> 18) & 1;
       ck(launch_gram(c.bulk, ga, h->stream));
     };
-    gram_plan = plan_get(h, c.o, plan_key("gram", c.bulk, c.m, c.n, 0),
-                         {512, 256, 1024, 512 | 0x10000, 256 | 0x10000, 1024 | 0x10000}, run);
+    std::vector<int> cands;
+    for (int ww : {0, 0x40000})
+      for (int il : {0, 0x20000})
+        for (int nw : {0, 0x10000})
+          for (int wg : {512, 256, 1024}) cands.push_back(wg | nw | il | ww);
+    gram_plan = plan_get(h, c.o, plan_key("gram", c.bulk, c.m, c.n, 0), cands, run);
   }
   int enqueued = 0;
   while (true) {
@@ -440,7 +442,9 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
         ga.q = v.q;
         ga.flag = flag;
         ga.max_wg = gram_plan & 0xFFFF;
-        ga.narrow = gram_plan >> 16;
+        ga.narrow = (gram_plan >> 16) & 1;
+        ga.interleave = (gram_plan >> 17) & 1;
+        ga.wide_wg = (gram_plan >> 18) & 1;
         std::tie(ga.ev_begin, ga.ev_end) = prof_pair(h, K_GRAM);
         ck(launch_gram(c.bulk, ga, h->stream));
         CgStep a{};
@@ -888,7 +892,7 @@ mn_opts resolve_opts(const mn_opts* o) {
 bool opts_valid(const mn_opts& o) {
   return o.alpha > 1.0 && (o.stop_rule == 0 || o.stop_rule == 1) && o.max_iter > 0 && o.max_refine > 0 &&
          o.block >= 0 && o.block <= 2 && o.streams > 0 && o.streams <= 64 && (o.precond == 0 || o.precond == 1) &&
-         (o.tune == 0 || o.tune == 1) &&
+         (o.tune == 0 || o.tune == 1) && (o.batch_form == 0 || o.batch_form == 1) &&
          o.check_every > 0 && o.check_every <= 1024 && o.inner_digits > 0 && o.inner_digits <= 12;
 }
 
@@ -989,6 +993,360 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   return worst;
 }
 
+// ----------------------------------------------------------------------------
+// Batched systems, fused form: every stage of every system is one launch
+// whose workgroups find their system through a prefix table (BGrid), and the
+// systems iterate in lockstep with their own stop flags, so the host waits a
+// few times per batch instead of several times per system.  Requires m <= 512
+// for every system (fused A-pass) and the Gram route for R; systems whose idx
+// is invalid or whose Gram factor is declined are solved afterwards one by one.
+struct GridTable {
+  std::vector<BGrid> g;
+  int total = 0;
+  size_t off = 0;  // offset (entries) in the uploaded table buffer
+  void init(int n) { g.assign((size_t)n + 1, BGrid{0, 0, 1, 1}); }
+  void finish() {
+    int acc = 0;
+    for (size_t i = 0; i + 1 < g.size(); ++i) {
+      const int cnt = g[i].gx * g[i].gy * g[i].gz;
+      g[i].start = acc;
+      acc += cnt;
+    }
+    g.back() = BGrid{acc, 1, 1, 1};
+    total = acc;
+  }
+};
+
+int64_t a256(int64_t v) { return (v + 255) / 256 * 256; }
+
+bool fused_batch_ok(int batch, const int64_t* m, const mn_opts& o) {
+  if (o.precond != 0 || o.batch_form == 1 || batch < 2) return false;
+  for (int i = 0; i < batch; ++i)
+    if (m[i] > kGramMaxRows) return false;
+  return true;
+}
+
+void fill_info_from_state(const PcgState& s, bool mixed, mn_info* info) {
+  info->status = s.status;
+  info->iters = s.iter_total;
+  info->refine_steps = s.refine_steps;
+  info->nrhs_done = s.status == MN_OK ? 1 : 0;
+  const double rho = mixed ? s.outer_rho : s.rho;
+  const double xi = mixed ? s.outer_xi : s.xi;
+  info->cert_rel = xi > 0 ? std::sqrt(rho / xi) : 0.0;
+  info->rho0 = s.rho0;
+  info->rho = rho;
+  info->xi = xi;
+}
+
+// Returns the per-system statuses in st_out; systems listed in redo still
+// need a one-system solve.
+void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, const int64_t* n, const void* const* A,
+                         const int64_t* lda, const void* const* A_lo, const void* const* b, const double* eps,
+                         const int64_t* N, const int64_t* l, const void* const* d, const int32_t* const* idx,
+                         const mn_opts& o, void* const* x, mn_info* info, std::vector<int>& st_out,
+                         std::vector<int>& redo) {
+  hipStream_t st = h->stream;
+  const bool cplx = is_complex(dtype);
+  const bool mixed = A_lo != nullptr || is_single(dtype);
+  const int bulk = A_lo ? dtype + 1 : dtype;
+  const int64_t W = wide_size(dtype);
+  const int64_t be = dtype_size(bulk);
+  const int64_t ces = is_single(bulk) ? 8 : 16;
+  std::vector<BSys> hs((size_t)batch);
+  // grids
+  GridTable fill, map, sk_small, sk_cols, sk_rows, gram_s, rdiag, invd, gramA, gramU, gred, adjA, adjU, sum, fwdA,
+      fwdU, cgs, cgp, vec;
+  for (GridTable* t : {&fill, &map, &sk_small, &sk_cols, &sk_rows, &gram_s, &rdiag, &invd, &gramA, &gramU, &gred, &adjA,
+                       &adjU, &sum, &fwdA, &fwdU, &cgs, &cgp, &vec})
+    t->init(batch);
+  int maxnbk = 0;
+  size_t lds_small = 0, lds_cols = 0, lds_rows = 0;
+  int64_t maxm = 0;
+  std::vector<int64_t> wbytes((size_t)batch);
+  for (int i = 0; i < batch; ++i) {
+    BSys& q = hs[i];
+    memset(&q, 0, sizeof(q));
+    q.A = A[i];
+    q.lda = lda[i];
+    q.Ab = A_lo ? A_lo[i] : A[i];
+    q.ldab = lda[i];
+    q.m = m[i];
+    q.n = n[i];
+    q.N = N[i];
+    q.l = l[i];
+    q.b = b[i];
+    q.x = x[i];
+    q.d = d[i];
+    q.idx = idx[i];
+    q.ldx = rinv_ld(m[i]);
+    maxm = std::max(maxm, m[i]);
+    BGrid g0, g1, g2;
+    size_t a0, a1, a2;
+    b_plan_sketch(bulk, q, g0, g1, g2, a0, a1, a2);
+    sk_small.g[i] = g0;
+    sk_cols.g[i] = g1;
+    sk_rows.g[i] = g2;
+    lds_small = std::max(lds_small, a0);
+    lds_cols = std::max(lds_cols, a1);
+    lds_rows = std::max(lds_rows, a2);
+    q.tw = twiddles(h, N[i], is_single(bulk));
+    fill.g[i] = BGrid{0, (int)cdiv(N[i], 256), 1, 1};
+    map.g[i] = BGrid{0, (int)cdiv(l[i], 256), 1, 1};
+    gram_s.g[i] = BGrid{0, (int)cdiv(m[i], 128), 1, (int)cdiv(m[i], gram_col_block(bulk))};
+    rdiag.g[i] = BGrid{0, 1, 1, 1};
+    invd.g[i] = BGrid{0, (int)cdiv(m[i], 32), 1, 1};
+    maxnbk = std::max(maxnbk, (int)cdiv(m[i], 32));
+    BGrid gg, gr;
+    b_plan_gram(bulk, q, gg, gr);
+    const bool al_b = b_aligned16(q.Ab, q.ldab, bulk);
+    (al_b ? gramA : gramU).g[i] = gg;
+    gred.g[i] = gr;
+    BGrid ga, gs, gf;
+    const bool al = b_aligned16(q.A, q.lda, dtype);
+    b_plan_wide(dtype, al, q, ga, gs, gf);
+    (al ? adjA : adjU).g[i] = ga;
+    sum.g[i] = gs;
+    (al ? fwdA : fwdU).g[i] = gf;
+    cgs.g[i] = BGrid{0, (int)cdiv(m[i], 8), 1, 1};
+    cgp.g[i] = BGrid{0, (int)cdiv(m[i], 16), 1, 1};
+    vec.g[i] = BGrid{0, (int)cdiv(m[i], 256), 1, 1};
+    const int64_t mm = m[i];
+    wbytes[i] = a256(N[i] * 4) + a256(l[i] * mm * be) + a256(b_sketch_work_elems(bulk, mm, N[i]) * ces) +
+                2 * a256(mm * mm * W) + a256(q.ldx * q.ldx * W) + 6 * a256(mm * W) + a256(kGramParts * mm * W) +
+                a256((int64_t)q.gram_G * mm * W) + a256(n[i] * W) + a256((int64_t)q.adj_slabs * n[i] * W) +
+                a256((int64_t)q.fwd_chunks * mm * W);
+  }
+  std::vector<GridTable> chol((size_t)maxnbk), trtri((size_t)maxnbk);
+  for (int k = 0; k < maxnbk; ++k) {
+    chol[k].init(batch);
+    trtri[k].init(batch);
+    for (int i = 0; i < batch; ++i) {
+      const int nb = (int)cdiv(m[i], 32);
+      if (k < nb) chol[k].g[i] = BGrid{0, (nb - k) + (nb - k - 1) * (nb - k) / 2, 1, 1};
+      else chol[k].g[i] = BGrid{0, 0, 1, 1};
+      if (k >= 1 && k < nb) trtri[k].g[i] = BGrid{0, nb - k, 1, 1};
+      else trtri[k].g[i] = BGrid{0, 0, 1, 1};
+    }
+  }
+  // mark the grids of systems outside a launch
+  for (int i = 0; i < batch; ++i) {
+    if (!b_aligned16(hs[i].Ab, hs[i].ldab, bulk)) gramA.g[i].gx = 0;
+    else gramU.g[i].gx = 0;
+    const bool al = b_aligned16(hs[i].A, hs[i].lda, dtype);
+    if (al) {
+      adjU.g[i].gx = 0;
+      fwdU.g[i].gx = 0;
+    } else {
+      adjA.g[i].gx = 0;
+      fwdA.g[i].gx = 0;
+    }
+  }
+  std::vector<GridTable*> all = {&fill, &map,  &sk_small, &sk_cols, &sk_rows, &gram_s, &rdiag, &invd, &gramA, &gramU,
+                                 &gred, &adjA, &adjU,     &sum,     &fwdA,    &fwdU,   &cgs,   &cgp,  &vec};
+  for (auto& t : chol) all.push_back(&t);
+  for (auto& t : trtri) all.push_back(&t);
+  size_t nent = 0;
+  for (GridTable* t : all) {
+    t->finish();
+    t->off = nent;
+    nent += t->g.size();
+  }
+  // workspace: per-system slices, plus contiguous flags/diag/state arrays
+  int64_t total = 0;
+  std::vector<int64_t> base((size_t)batch);
+  for (int i = 0; i < batch; ++i) {
+    base[i] = total;
+    total += wbytes[i];
+  }
+  char* wsb = (char*)ws(h, "batch_ws", (size_t)total);
+  int32_t* flags = (int32_t*)ws(h, "batch_flags", (size_t)batch * 16);
+  double* diag = (double*)ws(h, "batch_diag", (size_t)batch * 32);
+  PcgState* states = (PcgState*)ws(h, "batch_states", (size_t)batch * sizeof(PcgState));
+  for (int i = 0; i < batch; ++i) {
+    BSys& q = hs[i];
+    char* p = wsb + base[i];
+    auto take = [&](int64_t bytes) {
+      char* r = p;
+      p += a256(bytes);
+      return (void*)r;
+    };
+    const int64_t mm = m[i];
+    q.inv = (int32_t*)take(N[i] * 4);
+    q.S = take(l[i] * mm * be);
+    q.Y = take(b_sketch_work_elems(bulk, mm, N[i]) * ces);
+    q.G = take(mm * mm * W);
+    q.R = take(mm * mm * W);
+    q.X = take(q.ldx * q.ldx * W);
+    q.y = take(mm * W);
+    q.r0 = take(mm * W);
+    q.r1 = take(mm * W);
+    q.p = take(mm * W);
+    q.s = take(mm * W);
+    q.y_outer = take(mm * W);
+    q.q = take(kGramParts * mm * W);
+    q.qpart = take((int64_t)q.gram_G * mm * W);
+    q.w64 = take(n[i] * W);
+    q.apart = take((int64_t)q.adj_slabs * n[i] * W);
+    q.fpart = take((int64_t)q.fwd_chunks * mm * W);
+    q.flags = flags + 4 * i;
+    q.diag = diag + 4 * i;
+    q.st = states + i;
+  }
+  // upload descriptors and tables through pinned staging
+  const size_t sys_bytes = sizeof(BSys) * (size_t)batch, tab_bytes = sizeof(BGrid) * nent;
+  BSys* dsys = (BSys*)ws(h, "batch_sys", sys_bytes);
+  BGrid* dtab = (BGrid*)ws(h, "batch_tab", tab_bytes);
+  if (h->host_stage_bytes < sys_bytes + tab_bytes + (size_t)batch * sizeof(PcgState)) {
+    ck(hipStreamSynchronize(st));
+    if (h->host_stage) ck(hipHostFree(h->host_stage));
+    h->host_stage = nullptr;
+    h->host_stage_bytes = sys_bytes + tab_bytes + (size_t)batch * sizeof(PcgState) + 4096;
+    ck(hipHostMalloc((void**)&h->host_stage, h->host_stage_bytes, hipHostMallocDefault));
+  }
+  char* hst = (char*)h->host_stage;
+  memcpy(hst, hs.data(), sys_bytes);
+  for (GridTable* t : all) memcpy(hst + sys_bytes + t->off * sizeof(BGrid), t->g.data(), t->g.size() * sizeof(BGrid));
+  ck(hipMemcpyAsync(dsys, hst, sys_bytes, hipMemcpyHostToDevice, st));
+  ck(hipMemcpyAsync(dtab, hst + sys_bytes, tab_bytes, hipMemcpyHostToDevice, st));
+  ck(launch_fill0(flags, (int64_t)batch * 16, st));
+  ck(hipStreamSynchronize(st));
+  auto L = [&](GridTable& t) { return BLaunch{dsys, dtab + t.off, batch, t.total}; };
+  const BLaunch none{dsys, dtab + fill.off, batch, 0};
+
+  // idx check first: a system with an invalid idx takes no part in any later
+  // launch (the sketch gathers through idx)
+  ck(launch_b_prep(L(fill), L(map), st));
+  ck(hipMemcpyAsync(hst, flags, (size_t)batch * 16, hipMemcpyDeviceToHost, st));
+  ck(hipStreamSynchronize(st));
+  std::vector<char> idx_bad((size_t)batch, 0);
+  bool any_bad = false;
+  for (int i = 0; i < batch; ++i) {
+    idx_bad[i] = reinterpret_cast<const int32_t*>(hst)[4 * i] != 0;
+    any_bad = any_bad || idx_bad[i];
+  }
+  if (any_bad) {
+    for (GridTable* t : all) {
+      if (t == &fill || t == &map) continue;
+      for (int i = 0; i < batch; ++i)
+        if (idx_bad[i]) t->g[i].gx = 0;
+      t->finish();
+      memcpy(hst + sys_bytes + t->off * sizeof(BGrid), t->g.data(), t->g.size() * sizeof(BGrid));
+    }
+    memcpy(hst, hs.data(), sys_bytes);
+    ck(hipMemcpyAsync(dtab, hst + sys_bytes, tab_bytes, hipMemcpyHostToDevice, st));
+    ck(hipStreamSynchronize(st));
+  }
+  // Steps 1-2: sketch, Gram matrix, Cholesky, diagonal range
+  ck(launch_b_sketch(bulk, L(sk_small), L(sk_cols), L(sk_rows), lds_small, lds_cols, lds_rows, st));
+  ck(launch_b_gram_s(bulk, L(gram_s), st));
+  for (int k = 0; k < maxnbk; ++k) ck(launch_b_chol_step(cplx, L(chol[k]), k, st));
+  ck(launch_b_rdiag(cplx, L(rdiag), st));
+  std::vector<int32_t> hflags((size_t)batch * 4);
+  std::vector<double> hdiag((size_t)batch * 4);
+  ck(hipMemcpyAsync(hst, flags, (size_t)batch * 16, hipMemcpyDeviceToHost, st));
+  ck(hipMemcpyAsync(hst + (size_t)batch * 16, diag, (size_t)batch * 32, hipMemcpyDeviceToHost, st));
+  ck(hipStreamSynchronize(st));
+  memcpy(hflags.data(), hst, (size_t)batch * 16);
+  memcpy(hdiag.data(), hst + (size_t)batch * 16, (size_t)batch * 32);
+  std::vector<char> skip((size_t)batch, 0);
+  st_out.assign((size_t)batch, MN_OK);
+  for (int i = 0; i < batch; ++i) {
+    const double mx = hdiag[4 * i], mn_ = hdiag[4 * i + 1], nf = hdiag[4 * i + 2];
+    const bool bad_idx = idx_bad[i] != 0;
+    const bool gram_ok = hflags[4 * i + 1] == 0 && nf == 0.0 && std::isfinite(mx) && mn_ > 0.0 && mx <= 1e5 * mn_;
+    if (bad_idx) {
+      st_out[i] = -16;
+      skip[i] = 1;
+    } else if (!gram_ok) {
+      redo.push_back(i);
+      skip[i] = 1;
+    }
+  }
+  // X = R^{-1}
+  ck(launch_b_inv_diag(cplx, L(invd), st));
+  for (int k = 1; k < maxnbk; ++k) ck(launch_b_trtri_step(cplx, L(trtri[k]), k, st));
+  // CG states (skipped systems start finished)
+  std::vector<PcgState> hst_state((size_t)batch);
+  for (int i = 0; i < batch; ++i) {
+    PcgState& s0 = hst_state[i];
+    memset(&s0, 0, sizeof(s0));
+    s0.eps = mixed ? std::pow(10.0, -(double)o.inner_digits) : eps[i];
+    s0.alpha = o.alpha;
+    s0.l = (double)l[i];
+    s0.N = (double)N[i];
+    s0.eps_outer = eps[i];
+    s0.rule = mixed ? 2 : o.stop_rule;
+    s0.max_iter = o.max_iter;
+    s0.max_refine = o.max_refine;
+    if (skip[i]) {
+      s0.done = 1;
+      s0.outer_done = 1;
+    }
+  }
+  auto read_states = [&]() {
+    ck(hipMemcpyAsync(hst, states, (size_t)batch * sizeof(PcgState), hipMemcpyDeviceToHost, st));
+    ck(hipStreamSynchronize(st));
+    memcpy(hst_state.data(), hst, (size_t)batch * sizeof(PcgState));
+  };
+  memcpy(hst, hst_state.data(), (size_t)batch * sizeof(PcgState));
+  ck(hipMemcpyAsync(states, hst, (size_t)batch * sizeof(PcgState), hipMemcpyHostToDevice, st));
+  ck(hipStreamSynchronize(st));
+  const size_t cg_lds = (size_t)maxm * W;
+  int par = 0;
+  auto all_done = [&](bool outer) {
+    for (int i = 0; i < batch; ++i)
+      if (!(outer ? hst_state[i].outer_done : hst_state[i].done)) return false;
+    return true;
+  };
+  auto inner_loop = [&]() {
+    int guard = 0;
+    while (true) {
+      for (int it = 0; it < o.check_every; ++it) {
+        ck(launch_b_gram(bulk, true, L(gramA), none, st));
+        ck(launch_b_gram(bulk, false, L(gramU), L(gred), st));
+        ck(launch_b_cg(cplx, L(cgs), L(cgp), 0, 2, 0, par, cg_lds, st));
+        par ^= 1;
+      }
+      read_states();
+      if (all_done(false)) break;
+      if ((guard += o.check_every) > o.max_iter + 2 * o.check_every) break;  // the kernels cap iterations
+    }
+  };
+  if (mixed) {
+    ck(launch_b_zero_outer(cplx, L(vec), st));
+    for (int outer = 0; outer <= o.max_refine + 1; ++outer) {
+      ck(launch_b_adj_wide(dtype, true, L(adjA), none, 0, 0, st));
+      ck(launch_b_adj_wide(dtype, false, L(adjU), L(sum), 0, 0, st));
+      ck(launch_b_fwd_wide(dtype, true, L(fwdA), st));
+      ck(launch_b_fwd_wide(dtype, false, L(fwdU), st));
+      ck(launch_b_cg(cplx, L(cgs), L(cgp), 1, 1, 1, par, cg_lds, st));
+      read_states();
+      if (all_done(true)) break;
+      inner_loop();
+      ck(launch_b_refine(cplx, L(vec), st));
+    }
+    // x = A* y_outer
+    ck(launch_b_adj_wide(dtype, true, L(adjA), none, 0, 1, st));
+    ck(launch_b_adj_wide(dtype, false, L(adjU), L(sum), 0, 1, st));
+  } else {
+    ck(launch_b_cg(cplx, L(cgs), L(cgp), 1, 0, 0, par, cg_lds, st));
+    inner_loop();
+    ck(launch_b_adj_wide(dtype, true, L(adjA), none, 1, 1, st));
+    ck(launch_b_adj_wide(dtype, false, L(adjU), L(sum), 1, 1, st));
+  }
+  read_states();
+  for (int i = 0; i < batch; ++i) {
+    if (skip[i]) continue;
+    st_out[i] = hst_state[i].status;
+    if (info) {
+      memset(&info[i], 0, sizeof(mn_info));
+      fill_info_from_state(hst_state[i], mixed, &info[i]);
+    }
+  }
+}
+
+
 int check_solve_args(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const void* A_lo,
                      int64_t lda_lo, const void* b, int64_t ldb, int64_t nrhs, double eps, int64_t N, int64_t l,
                      const void* d, const int32_t* idx, const mn_opts& o, void* x, int64_t ldx) {
@@ -1047,10 +1405,11 @@ int mn_destroy(mn_handle h) {
   (void)hipStreamSynchronize(h->stream);
   for (auto& kv : h->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
-  for (auto& t : h->tw)
-    if (t.p) (void)hipFree(t.p);
+  for (auto& kv : h->tw)
+    if (kv.second.p) (void)hipFree(kv.second.p);
   if (h->host_state) (void)hipHostFree(h->host_state);
   if (h->host_blk) (void)hipHostFree(h->host_blk);
+  if (h->host_stage) (void)hipHostFree(h->host_stage);
   if (h->host_flag) (void)hipHostFree(h->host_flag);
   if (h->host_diag) (void)hipHostFree(h->host_diag);
   for (auto& e : h->ev)
@@ -1190,7 +1549,7 @@ int64_t mn_workspace_bytes(mn_handle h) {
   if (!h) return -1;
   int64_t t = 0;
   for (auto& kv : h->bufs) t += (int64_t)kv.second.bytes;
-  for (auto& tw : h->tw) t += tw.N * 16;
+  for (auto& kv : h->tw) t += kv.second.N * (kv.first.second ? 8 : 16);
   return t;
 }
 
@@ -1278,6 +1637,32 @@ int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* 
     const int e = check_solve_args(h, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i],
                                    l[i], d[i], idx[i], o, x[i], n[i]);
     if (e) return remap[-e];
+  }
+  if (fused_batch_ok(batch, m, o)) {
+    std::vector<int> stv, redo;
+    try {
+      solve_batched_fused(h, dtype, batch, m, n, A, lda, A_lo, b, eps, N, l, d, idx, o, x, info, stv, redo);
+      for (int i : redo) {
+        const void* alo = A_lo ? A_lo[i] : nullptr;
+        stv[i] = solve_impl(h, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i], l[i], d[i],
+                            idx[i], o, x[i], n[i], info ? &info[i] : nullptr);
+      }
+    } catch (HipFail f) {
+      return fail_hip(f.e);
+    }
+    int worst = MN_OK, argerr = 0;
+    for (int32_t i = 0; i < batch; ++i) {
+      if (stv[i] == -16) {
+        argerr = -14;
+        if (info) {
+          memset(&info[i], 0, sizeof(mn_info));
+          info[i].status = -14;
+        }
+      } else if (stv[i] > worst) {
+        worst = stv[i];
+      }
+    }
+    return argerr ? argerr : worst;
   }
   // Systems run concurrently on `streams` lanes (child handles, each with its
   // own stream, workspace and host thread), longest first; each lane solves

@@ -31,6 +31,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "batch_dev.hpp"
 
 namespace mn {
 
@@ -155,7 +156,7 @@ constexpr int kBfRows = 128;
 constexpr int kBfStride = 72;  // bf16 per staged column: 64 + 8 (bank spread)
 
 template <bool CPLX, bool CONJ, int NT, int MODE>
-__global__ void __launch_bounds__(256) k_gemm_bf(BfGemmArgs g) {
+__global__ void __launch_bounds__(256, 2) k_gemm_bf(BfGemmArgs g) {
   constexpr int NCOL = NT * 16;             // real (expanded) columns
   constexpr int KCOL = CPLX ? NCOL / 2 : NCOL;  // compact columns
   extern __shared__ unsigned char smem_raw[];
@@ -251,20 +252,31 @@ __global__ void __launch_bounds__(256) k_gemm_bf(BfGemmArgs g) {
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const uint16_t* bb = Bs + (ch & 1) * BUF;
+    // issue order: for a group of up to 2 column tiles, the hi*hi products of
+    // all (row tile, column tile) pairs, then hi*lo, then lo*hi, so that
+    // consecutive matrix-core instructions accumulate into different tiles
+    constexpr int TG = NT < 2 ? NT : 2;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int c = 16 * t + rl;
-        const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(bb + c * kBfStride + 16 * grp + 8 * s));
-        const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(bb + (NCOL + c) * kBfStride + 16 * grp + 8 * s));
+      for (int t0 = 0; t0 < NT; t0 += TG) {
+        bf16x8 bh[TG], bl[TG];
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-          const bf16x8 ah = __builtin_bit_cast(bf16x8, a_cur[mt][0][s]);
-          const bf16x8 al = __builtin_bit_cast(bf16x8, a_cur[mt][1][s]);
-          acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[mt][t], 0, 0, 0);
-          acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[mt][t], 0, 0, 0);
-          acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[mt][t], 0, 0, 0);
+        for (int tt = 0; tt < TG; ++tt) {
+          const int c = 16 * (t0 + tt) + rl;
+          bh[tt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(bb + c * kBfStride + 16 * grp + 8 * s));
+          bl[tt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(bb + (NCOL + c) * kBfStride + 16 * grp + 8 * s));
+        }
+#pragma unroll
+        for (int pass = 0; pass < 3; ++pass) {
+#pragma unroll
+          for (int tt = 0; tt < TG; ++tt)
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+              const bf16x8 a = __builtin_bit_cast(bf16x8, a_cur[mt][pass == 2 ? 1 : 0][s]);
+              const bf16x8 b = pass == 1 ? bl[tt] : bh[tt];
+              acc[mt][t0 + tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[mt][t0 + tt], 0, 0, 0);
+            }
         }
       }
     }
@@ -365,23 +377,23 @@ constexpr int kDKc = 16;
 constexpr int kDRows = 128;
 
 template <typename T, typename BS, bool TRANS, bool CONJ, int NT, int MODE>
-__global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
+__device__ __forceinline__ void k_gemm_d_body(const Bk bk, DGemmArgs g) {
   constexpr bool CPLX = Elem<T>::cplx;
   using BT = typename std::conditional<CPLX, cd, double>::type;
   constexpr int NCOL = NT * 16;
   constexpr int KCOL = CPLX ? NCOL / 2 : NCOL;
   __shared__ BT Bs[2][KCOL][kDKc + 1];
-  // blockIdx.z: block of KCOL right-hand columns starting at c0
-  const int64_t c0 = (int64_t)blockIdx.z * KCOL;
+  // bk.z: block of KCOL right-hand columns starting at c0
+  const int64_t c0 = (int64_t)bk.z * KCOL;
   const int kcz = g.kc - c0 < KCOL ? (int)(g.kc - c0) : KCOL;
-  const int64_t wg_row0 = (int64_t)blockIdx.x * kDRows;
+  const int64_t wg_row0 = (int64_t)bk.x * kDRows;
   // Hermitian product: only tiles that reach the upper triangle
   if (g.herm && wg_row0 > c0 + KCOL - 1) return;
   if (g.flag && *g.flag) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int rl = lane & 15, grp = lane >> 4;
   const int64_t row0 = wg_row0 + wv * 32;
-  int64_t k_begin = (int64_t)blockIdx.y * g.ks;
+  int64_t k_begin = (int64_t)bk.y * g.ks;
   int64_t k_end = k_begin + g.ks < g.K ? k_begin + g.ks : g.K;
   if (g.tri == 1) {
     const int64_t lo = (wg_row0 / kDKc) * kDKc;
@@ -466,19 +478,30 @@ __global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int kl = kidx(u);
+      if constexpr (CPLX) {
+        // expanded column: even (br, -bi) / conj (br, bi); odd (bi, br) / conj (bi, -br).
+        // All real parts first, then all imaginary parts: consecutive
+        // instructions accumulate into different tiles.
+        double b_re[NT], b_im[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        if constexpr (CPLX) {
+        for (int t = 0; t < NT; ++t) {
           const cd b = Bs[buf][8 * t + (rl >> 1)][kl];
-          // expanded column: even (br, -bi) / conj (br, bi); odd (bi, br) / conj (bi, -br)
-          const double b_re = odd ? b.im : b.re;
-          const double b_im = CONJ ? (odd ? -b.re : b.im) : (odd ? b.re : -b.im);
+          b_re[t] = odd ? b.im : b.re;
+          b_im[t] = CONJ ? (odd ? -b.re : b.im) : (odd ? b.re : -b.im);
+        }
 #pragma unroll
-          for (int mt = 0; mt < 2; ++mt) {
-            acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)vre(a_cur[mt][u]), b_re, acc[mt][t], 0, 0, 0);
-            acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)vim(a_cur[mt][u]), b_im, acc[mt][t], 0, 0, 0);
-          }
-        } else {
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt)
+            acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)vre(a_cur[mt][u]), b_re[t], acc[mt][t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt)
+            acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)vim(a_cur[mt][u]), b_im[t], acc[mt][t], 0, 0, 0);
+      } else {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
           const double b = Bs[buf][16 * t + rl][kl];
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt)
@@ -509,7 +532,7 @@ __global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
       const int cp = 16 * t + rl;
       const f64x4 v = acc[mt][t];
       if constexpr (MODE == 0) {
-        double* dst = g.Cp + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * NCOL + cp) * g.ldc + rb;
+        double* dst = g.Cp + (((int64_t)bk.z * bk.gy + bk.y) * NCOL + cp) * g.ldc + rb;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if (rb + 4 * q < g.M) dst[4 * q] = v[q];
@@ -540,6 +563,10 @@ __global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
       }
     }
   }
+}
+template <typename T, typename BS, bool TRANS, bool CONJ, int NT, int MODE>
+__global__ void __launch_bounds__(256) k_gemm_d(DGemmArgs g) {
+  k_gemm_d_body<T, BS, TRANS, CONJ, NT, MODE>(bk_hw(), g);
 }
 
 // ---------------------------------------------------------------------------
@@ -1027,6 +1054,47 @@ hipError_t launch_fill0(void* p, int64_t bytes, hipStream_t st) {
   const int64_t n16 = bytes / 16;
   if (n16 == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill16, dim3((unsigned)ceil_div(n16, 256)), dim3(256), 0, st, (u32x4*)p, n16);
+  return hipGetLastError();
+}
+
+// ------------------------------ batched systems -------------------------------
+namespace {
+// G = S* S of each system (one split, upper tiles only)
+template <typename T>
+__global__ void __launch_bounds__(256) kb_gram_s(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                 int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  DGemmArgs a{};
+  a.A = s.S;
+  a.lda = s.l;
+  a.M = s.m;
+  a.K = s.l;
+  a.B = s.S;
+  a.ldb = s.l;
+  a.kc = (int)s.m;
+  a.ks = ceil_div(s.l, kDKc) * kDKc;
+  a.herm = 1;
+  a.O = s.G;
+  a.ldo = s.m;
+  const Bk bk = bgrid_local(grid[i], (int)blockIdx.x - grid[i].start);
+  if (bk.x * kDRows > bk.z * (Elem<T>::cplx ? 64 : 128) + (Elem<T>::cplx ? 63 : 127)) return;
+  k_gemm_d_body<T, T, false, Elem<T>::cplx, 8, 1>(bk, a);
+}
+}  // namespace
+
+hipError_t launch_b_gram_s(int dtype, const BLaunch& L, hipStream_t st) {
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL(kb_gram_s<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys); break;
+    case 1: hipLaunchKernelGGL(kb_gram_s<cf>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys); break;
+    case 2:
+      hipLaunchKernelGGL(kb_gram_s<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
+      break;
+    case 3:
+      hipLaunchKernelGGL(kb_gram_s<float>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 // itself.  FP64 throughout.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "batch_dev.hpp"
 
 namespace mn {
 
@@ -89,7 +90,7 @@ __device__ void solve_tile(const V* R, V* B) {
 }
 
 template <typename V>
-__global__ void __launch_bounds__(256) k_chol_step(V* __restrict__ G, int64_t ldg, int64_t m, int k, int nbk,
+__device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G, int64_t ldg, int64_t m, int k, int nbk,
                                                    V* __restrict__ R, int64_t ldr, int32_t* __restrict__ bad) {
   __shared__ V Rkk[CB * LDC];
   __shared__ V T1[CB * LDC];
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(256) k_chol_step(V* __restrict__ G, int64_t ld
   // trailing upper tiles (i, j), k < i <= j, row by row
   const int nrow = nbk - k;
   int bi, bj;
-  int w = blockIdx.x;
+  int w = bk.x;
   if (w < nrow) {
     bi = k;
     bj = k + w;
@@ -166,6 +167,11 @@ __global__ void __launch_bounds__(256) k_chol_step(V* __restrict__ G, int64_t ld
     G[gr + gc * ldg] = vsub(G[gr + gc * ldg], acc);
   }
 }
+template <typename V>
+__global__ void __launch_bounds__(256) k_chol_step(V* __restrict__ G, int64_t ldg, int64_t m, int k, int nbk,
+                                                   V* __restrict__ R, int64_t ldr, int32_t* __restrict__ bad) {
+  k_chol_step_body<V>(bk_hw(), G, ldg, m, k, nbk, R, ldr, bad);
+}
 
 template <typename V>
 hipError_t chol_impl(void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, int32_t* bad, hipStream_t st) {
@@ -185,6 +191,25 @@ hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int6
                        hipStream_t st) {
   if (m < 1 || ldg < m || ldr < m) return hipErrorInvalidValue;
   return cplx ? chol_impl<cd>(G, ldg, m, R, ldr, bad, st) : chol_impl<double>(G, ldg, m, R, ldr, bad, st);
+}
+
+namespace {
+template <typename V>
+__global__ void __launch_bounds__(256) kb_chol_step(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                    int nsys, int k) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_chol_step_body<V>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<V*>(s.G), s.m, s.m, k,
+                      (int)ceil_div(s.m, CB), reinterpret_cast<V*>(s.R), s.m, s.flags + 1);
+}
+}  // namespace
+
+// one block step of every system that has block column k (grid: as launch_chol's step k)
+hipError_t launch_b_chol_step(bool cplx, const BLaunch& L, int k, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  if (cplx) hipLaunchKernelGGL(kb_chol_step<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, k);
+  else hipLaunchKernelGGL(kb_chol_step<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, k);
+  return hipGetLastError();
 }
 
 }  // namespace mn

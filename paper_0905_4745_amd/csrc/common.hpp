@@ -199,4 +199,15 @@ __device__ inline double block_max(double v, double* red) {
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Block coordinates of a kernel body: the hardware ones for a plain launch,
+// or a system's own grid inside a batched launch (kernels.hpp, BGrid).
+struct Bk {
+  int x, y, z;
+  int gx, gy, gz;
+};
+__device__ inline Bk bk_hw() {
+  return Bk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.x, (int)gridDim.y, (int)gridDim.z};
+}
+
+
 }  // namespace mn

@@ -19,6 +19,7 @@
 // thread, radix-16/8/4/2 butterflies in registers, LDS between stages.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "batch_dev.hpp"
 
 namespace mn {
 
@@ -193,7 +194,7 @@ __device__ inline V out_value(C x, typename VT<C>::real scale) {
 // --------------------------- whole rows in LDS ------------------------------
 // grid.x = ceil(m / B); B rows per workgroup, 256 threads.
 template <typename V, typename C>
-__global__ void __launch_bounds__(256) k_sketch_small(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+__device__ __forceinline__ void k_sketch_small_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                       FftPlan pl, int B, const void* __restrict__ d,
                                                       const int32_t* __restrict__ idx, int64_t l,
                                                       V* __restrict__ S, int64_t lds, const C* __restrict__ tw,
@@ -204,7 +205,7 @@ __global__ void __launch_bounds__(256) k_sketch_small(const V* __restrict__ A, i
   const int Lp = lds_stride(L);
   const int E = L < 16 ? L : 16;
   const int tpf = L / E;
-  const int64_t row0 = (int64_t)blockIdx.x * B;
+  const int64_t row0 = (int64_t)bk.x * B;
   // load: consecutive threads read consecutive entries of one row; all of a
   // thread's loads are issued before any is used
   {
@@ -250,12 +251,20 @@ __global__ void __launch_bounds__(256) k_sketch_small(const V* __restrict__ A, i
     }
   }
 }
+template <typename V, typename C>
+__global__ void __launch_bounds__(256) k_sketch_small(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                      FftPlan pl, int B, const void* __restrict__ d,
+                                                      const int32_t* __restrict__ idx, int64_t l,
+                                                      V* __restrict__ S, int64_t lds, const C* __restrict__ tw,
+                                                      typename VT<C>::real scale) {
+  k_sketch_small_body<V, C>(bk_hw(), A, lda, m, n, pl, B, d, idx, l, S, lds, tw, scale);
+}
 
 // ----------------------- four-step, pass 1: columns -------------------------
 // Row i viewed as N2 x N1 (x[n1 + N1 n2]); FFT over n2 for B consecutive n1,
 // times W_N^{n1 k2}; writes Y[i][k2][n1].  grid = (N1 / B, rows in chunk).
 template <typename V, typename C>
-__global__ void __launch_bounds__(256) k_sketch_cols(const V* __restrict__ A, int64_t lda, int64_t row0, int64_t m,
+__device__ __forceinline__ void k_sketch_cols_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t row0, int64_t m,
                                                      int64_t n, int N1, FftPlan pl2, int B,
                                                      const void* __restrict__ d, C* __restrict__ Y,
                                                      const C* __restrict__ tw) {
@@ -263,8 +272,8 @@ __global__ void __launch_bounds__(256) k_sketch_cols(const V* __restrict__ A, in
   C* sm = reinterpret_cast<C*>(smem_raw);
   const int N2 = pl2.L;
   const int Lp = lds_stride(N2);
-  const int64_t i = row0 + blockIdx.y;
-  const int c0 = blockIdx.x * B;
+  const int64_t i = row0 + bk.y;
+  const int c0 = bk.x * B;
   const int64_t N = (int64_t)N1 * N2;
   const V* row = A + i * lda;
   // load: consecutive threads take consecutive n1 (contiguous in memory);
@@ -305,7 +314,7 @@ __global__ void __launch_bounds__(256) k_sketch_cols(const V* __restrict__ A, in
   }
   if (i >= m) return;
   // twiddle W_N^{n1 k2} and store Y[i][k2][n1]: consecutive threads, consecutive n1
-  C* Yi = Y + (int64_t)blockIdx.y * N;
+  C* Yi = Y + (int64_t)bk.y * N;
   C wv[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
@@ -322,12 +331,19 @@ __global__ void __launch_bounds__(256) k_sketch_cols(const V* __restrict__ A, in
     }
   }
 }
+template <typename V, typename C>
+__global__ void __launch_bounds__(256) k_sketch_cols(const V* __restrict__ A, int64_t lda, int64_t row0, int64_t m,
+                                                     int64_t n, int N1, FftPlan pl2, int B,
+                                                     const void* __restrict__ d, C* __restrict__ Y,
+                                                     const C* __restrict__ tw) {
+  k_sketch_cols_body<V, C>(bk_hw(), A, lda, row0, m, n, N1, pl2, B, d, Y, tw);
+}
 
 // ---------------------- four-step, pass 2: rows + gather ---------------------
 // FFT over n1 of Y[i][k2][:] for B consecutive k2; output index k = k2 + N2 k1
 // is kept when inv[k] >= 0, written to S(inv[k], i).  grid = (N2 / B, rows).
 template <typename V, typename C>
-__global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, int64_t row0, int64_t m, int N2,
+__device__ __forceinline__ void k_sketch_rows_body(const Bk bk, const C* __restrict__ Y, int64_t row0, int64_t m, int N2,
                                                      FftPlan pl1, int B, const int32_t* __restrict__ inv,
                                                      V* __restrict__ S, int64_t lds, const C* __restrict__ tw,
                                                      typename VT<C>::real scale) {
@@ -336,9 +352,9 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, in
   const int N1 = pl1.L;
   const int Lp = lds_stride(N1);
   const int64_t N = (int64_t)N1 * N2;
-  const int64_t i = row0 + blockIdx.y;
-  const int c0 = blockIdx.x * B;
-  const C* Yi = Y + (int64_t)blockIdx.y * N;
+  const int64_t i = row0 + bk.y;
+  const int c0 = bk.x * B;
+  const C* Yi = Y + (int64_t)bk.y * N;
   {
     C v[16];
 #pragma unroll
@@ -384,24 +400,38 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, in
     if (pos[u] >= 0) S[pos[u] + i * lds] = out_value<V, C>(sm[(t / N1) * Lp + lpad(t % N1)], scale);
   }
 }
+template <typename V, typename C>
+__global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, int64_t row0, int64_t m, int N2,
+                                                     FftPlan pl1, int B, const int32_t* __restrict__ inv,
+                                                     V* __restrict__ S, int64_t lds, const C* __restrict__ tw,
+                                                     typename VT<C>::real scale) {
+  k_sketch_rows_body<V, C>(bk_hw(), Y, row0, m, N2, pl1, B, inv, S, lds, tw, scale);
+}
 
 // ------------------------------ helpers -------------------------------------
 // inv[k] = position of k in idx, or -1; also flags invalid idx (out of range
 // or not strictly increasing) in *bad.  Writes stay inside inv[0, N).
-__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_fill_i32_body(const Bk bk, int32_t* p, int64_t count, int32_t v) {
+  const int64_t t = (int64_t)bk.x * blockDim.x + threadIdx.x;
   if (t < count) p[t] = v;
 }
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
+  k_fill_i32_body(bk_hw(), p, count, v);
+}
 
-__global__ void k_inverse_map(const int32_t* __restrict__ idx, int64_t l, int64_t N, int32_t* __restrict__ inv,
+__device__ __forceinline__ void k_inverse_map_body(const Bk bk, const int32_t* __restrict__ idx, int64_t l, int64_t N, int32_t* __restrict__ inv,
                               int32_t* __restrict__ bad) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = (int64_t)bk.x * blockDim.x + threadIdx.x;
   if (k >= l) return;
   const int32_t v = idx[k];
   bool ok = v >= 0 && (int64_t)v < N;
   if (k + 1 < l && !(idx[k + 1] > v)) ok = false;
   if (ok) inv[v] = (int32_t)k;
   else atomicOr(bad, 1);
+}
+__global__ void k_inverse_map(const int32_t* __restrict__ idx, int64_t l, int64_t N, int32_t* __restrict__ inv,
+                              int32_t* __restrict__ bad) {
+  k_inverse_map_body(bk_hw(), idx, l, N, inv, bad);
 }
 
 // ------------------------------ launchers -----------------------------------
@@ -519,6 +549,133 @@ hipError_t launch_sketch(int dtype, const SketchArgs& a, hipStream_t st) {
     case 1: return sketch_impl<cf, cf>(a, st);
     case 2: return sketch_impl<double, cd>(a, st);
     case 3: return sketch_impl<float, cf>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------ batched systems -------------------------------
+namespace {
+
+template <typename V, typename C>
+__global__ void __launch_bounds__(256) kb_sketch_small(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                       int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  using R = typename VT<C>::real;
+  k_sketch_small_body<V, C>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const V*>(s.Ab),
+                            s.ldab, s.m, s.n, s.pl_a, s.fft_ba, s.d, s.idx, s.l, reinterpret_cast<V*>(s.S), s.l,
+                            reinterpret_cast<const C*>(s.tw), (R)(1.0 / sqrt((double)s.N)));
+}
+
+template <typename V, typename C>
+__global__ void __launch_bounds__(256) kb_sketch_cols(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                      int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_sketch_cols_body<V, C>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const V*>(s.Ab),
+                           s.ldab, 0, s.m, s.n, s.N1, s.pl_b, s.fft_bb, s.d, reinterpret_cast<C*>(s.Y),
+                           reinterpret_cast<const C*>(s.tw));
+}
+
+template <typename V, typename C>
+__global__ void __launch_bounds__(256) kb_sketch_rows(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                      int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  using R = typename VT<C>::real;
+  k_sketch_rows_body<V, C>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const C*>(s.Y), 0,
+                           s.m, s.N2, s.pl_a, s.fft_ba, s.inv, reinterpret_cast<V*>(s.S), s.l,
+                           reinterpret_cast<const C*>(s.tw), (R)(1.0 / sqrt((double)s.N)));
+}
+
+__global__ void kb_fill_inv(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_fill_i32_body(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), s.inv, s.N, -1);
+}
+
+__global__ void kb_inverse_map(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_inverse_map_body(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), s.idx, s.l, s.N, s.inv, s.flags);
+}
+
+template <typename C> void plan_sketch_t(BSys& s, BGrid& small, BGrid& cols, BGrid& rows, size_t& ls, size_t& lc,
+                                         size_t& lr) {
+  const int N = (int)s.N;
+  small = BGrid{0, 0, 1, 1};
+  cols = BGrid{0, 0, 1, 1};
+  rows = BGrid{0, 0, 1, 1};
+  ls = lc = lr = 0;
+  if (N <= max_lds_fft_len<C>()) {
+    s.pl_a = make_plan(N);
+    s.fft_ba = fft_batch<C>(N);
+    s.N1 = N;
+    s.N2 = 1;
+    small.gx = (int)ceil_div(s.m, s.fft_ba);
+    ls = (size_t)s.fft_ba * lds_stride(N) * sizeof(C);
+    return;
+  }
+  int k = 0;
+  while ((1 << k) < N) ++k;
+  s.N2 = 1 << (k / 2);
+  s.N1 = N >> (k / 2);
+  s.pl_a = make_plan(s.N1);
+  s.pl_b = make_plan(s.N2);
+  s.fft_bb = fft_batch<C>(s.N2);
+  s.fft_ba = fft_batch<C>(s.N1);
+  cols.gx = s.N1 / s.fft_bb;
+  cols.gy = (int)s.m;
+  rows.gx = s.N2 / s.fft_ba;
+  rows.gy = (int)s.m;
+  lc = (size_t)s.fft_bb * lds_stride(s.N2) * sizeof(C);
+  lr = (size_t)s.fft_ba * lds_stride(s.N1) * sizeof(C);
+}
+
+template <typename V, typename C>
+hipError_t b_sketch_t(const BLaunch& sm, const BLaunch& co, const BLaunch& ro, size_t ls, size_t lc, size_t lr,
+                      hipStream_t st) {
+  if (sm.total > 0) {
+    allow_lds(kb_sketch_small<V, C>, ls);
+    hipLaunchKernelGGL((kb_sketch_small<V, C>), dim3((unsigned)sm.total), dim3(256), ls, st, sm.sys, sm.grid,
+                       sm.nsys);
+  }
+  if (co.total > 0) {
+    allow_lds(kb_sketch_cols<V, C>, lc);
+    allow_lds(kb_sketch_rows<V, C>, lr);
+    hipLaunchKernelGGL((kb_sketch_cols<V, C>), dim3((unsigned)co.total), dim3(256), lc, st, co.sys, co.grid,
+                       co.nsys);
+    hipLaunchKernelGGL((kb_sketch_rows<V, C>), dim3((unsigned)ro.total), dim3(256), lr, st, ro.sys, ro.grid,
+                       ro.nsys);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+void b_plan_sketch(int dtype, BSys& s, BGrid& small, BGrid& cols, BGrid& rows, size_t& ls, size_t& lc, size_t& lr) {
+  if (dtype == 1 || dtype == 3) plan_sketch_t<cf>(s, small, cols, rows, ls, lc, lr);
+  else plan_sketch_t<cd>(s, small, cols, rows, ls, lc, lr);
+}
+
+int64_t b_sketch_work_elems(int dtype, int64_t m, int64_t N) {
+  const int L = (dtype == 1 || dtype == 3) ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>();
+  return N <= L ? 0 : m * N;
+}
+
+hipError_t launch_b_prep(const BLaunch& fill, const BLaunch& map, hipStream_t st) {
+  hipLaunchKernelGGL(kb_fill_inv, dim3((unsigned)fill.total), dim3(256), 0, st, fill.sys, fill.grid, fill.nsys);
+  hipLaunchKernelGGL(kb_inverse_map, dim3((unsigned)map.total), dim3(256), 0, st, map.sys, map.grid, map.nsys);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_sketch(int dtype, const BLaunch& small, const BLaunch& cols, const BLaunch& rows, size_t ls,
+                           size_t lc, size_t lr, hipStream_t st) {
+  switch (dtype) {
+    case 0: return b_sketch_t<cd, cd>(small, cols, rows, ls, lc, lr, st);
+    case 1: return b_sketch_t<cf, cf>(small, cols, rows, ls, lc, lr, st);
+    case 2: return b_sketch_t<double, cd>(small, cols, rows, ls, lc, lr, st);
+    case 3: return b_sketch_t<float, cf>(small, cols, rows, ls, lc, lr, st);
   }
   return hipErrorInvalidValue;
 }

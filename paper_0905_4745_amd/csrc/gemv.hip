@@ -12,6 +12,7 @@
 // FP64.  All kernels return at once when the iteration's stop flag is set.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "batch_dev.hpp"
 
 namespace mn {
 
@@ -34,13 +35,13 @@ __device__ inline bool stopped(const int32_t* flag) { return flag != nullptr && 
 // w (or its RS partial slabs) = A* u.  grid (ceil(n / (256*VEC)), RS), 256 thr.
 // If RS == 1 the result goes straight to w, else to part[rs * n + j].
 template <typename V, typename C, typename U, int VEC>
-__global__ void __launch_bounds__(256) k_gemv_adj(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+__device__ __forceinline__ void k_gemv_adj_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                   const U* __restrict__ u, int64_t rows_per_slab,
                                                   C* __restrict__ out, const int32_t* __restrict__ flag) {
   if (stopped(flag)) return;
   __shared__ C su[1024];
-  const int64_t j0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * VEC;
-  const int64_t r0 = (int64_t)blockIdx.y * rows_per_slab;
+  const int64_t j0 = ((int64_t)bk.x * 256 + threadIdx.x) * VEC;
+  const int64_t r0 = (int64_t)bk.y * rows_per_slab;
   const int64_t r1 = (r0 + rows_per_slab) < m ? (r0 + rows_per_slab) : m;
   C acc[VEC];
 #pragma unroll
@@ -82,7 +83,7 @@ __global__ void __launch_bounds__(256) k_gemv_adj(const V* __restrict__ A, int64
     }
   }
   if (j0 >= n) return;
-  C* o = out + (int64_t)blockIdx.y * n + j0;
+  C* o = out + (int64_t)bk.y * n + j0;
   if (full && ((uintptr_t)o % 16 == 0)) {
     Pack<C, VEC> pk;
 #pragma unroll
@@ -93,30 +94,41 @@ __global__ void __launch_bounds__(256) k_gemv_adj(const V* __restrict__ A, int64
       if (j0 + v < n) o[v] = acc[v];
   }
 }
+template <typename V, typename C, typename U, int VEC>
+__global__ void __launch_bounds__(256) k_gemv_adj(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                  const U* __restrict__ u, int64_t rows_per_slab,
+                                                  C* __restrict__ out, const int32_t* __restrict__ flag) {
+  k_gemv_adj_body<V, C, U, VEC>(bk_hw(), A, lda, m, n, u, rows_per_slab, out, flag);
+}
 
 // w[j] = sum_s part[s * n + j] in slab order; optionally also a wide copy.
 template <typename V, typename W>
-__global__ void k_sum_slabs(const V* __restrict__ part, int rs, int64_t n, V* __restrict__ w, W* __restrict__ wide,
+__device__ __forceinline__ void k_sum_slabs_body(const Bk bk, const V* __restrict__ part, int rs, int64_t n, V* __restrict__ w, W* __restrict__ wide,
                             const int32_t* __restrict__ flag) {
   if (stopped(flag)) return;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = (int64_t)bk.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   V s = part[j];
   for (int k = 1; k < rs; ++k) s = vadd(s, part[(int64_t)k * n + j]);
   if (w) w[j] = s;
   if (wide) wide[j] = vconv<W>(s);
 }
+template <typename V, typename W>
+__global__ void k_sum_slabs(const V* __restrict__ part, int rs, int64_t n, V* __restrict__ w, W* __restrict__ wide,
+                            const int32_t* __restrict__ flag) {
+  k_sum_slabs_body<V, W>(bk_hw(), part, rs, n, w, wide, flag);
+}
 
 // ---------------------------------------------------------------------------
 // qpart[cs * m + i] = sum_{j in chunk cs} A_ij w_j.  grid (CS, ceil(m / RB)).
 template <typename V, typename C, typename W, int RB, int VEC>
-__global__ void __launch_bounds__(256) k_gemv_fwd(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+__device__ __forceinline__ void k_gemv_fwd_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                   const C* __restrict__ w, int64_t chunk,
                                                   W* __restrict__ qpart, const int32_t* __restrict__ flag) {
   if (stopped(flag)) return;
   __shared__ W red[RB][4];
-  const int64_t i0 = (int64_t)blockIdx.y * RB;
-  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i0 = (int64_t)bk.y * RB;
+  const int64_t c0 = (int64_t)bk.x * chunk;
   const int64_t c1 = (c0 + chunk) < n ? (c0 + chunk) : n;
   C acc[RB];
 #pragma unroll
@@ -158,8 +170,14 @@ __global__ void __launch_bounds__(256) k_gemv_fwd(const V* __restrict__ A, int64
   if (threadIdx.x < RB && threadIdx.x < rows) {
     const int r = threadIdx.x;
     W s = vadd(vadd(red[r][0], red[r][1]), vadd(red[r][2], red[r][3]));
-    qpart[(int64_t)blockIdx.x * m + i0 + r] = s;
+    qpart[(int64_t)bk.x * m + i0 + r] = s;
   }
+}
+template <typename V, typename C, typename W, int RB, int VEC>
+__global__ void __launch_bounds__(256) k_gemv_fwd(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                  const C* __restrict__ w, int64_t chunk,
+                                                  W* __restrict__ qpart, const int32_t* __restrict__ flag) {
+  k_gemv_fwd_body<V, C, W, RB, VEC>(bk_hw(), A, lda, m, n, w, chunk, qpart, flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -173,14 +191,15 @@ __global__ void __launch_bounds__(256) k_gemv_fwd(const V* __restrict__ A, int64
 //   qacc_r += sum_c A_rc t_c     (registers, reduced over column groups once
 //                                 per workgroup at the end)
 // Output: qpart[g * m + i], FP64; the strips of a workgroup are contiguous.
-template <typename V, typename C, typename U, int CPT, int RPT, int TPB>
-__global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+template <typename V, typename C, typename U, int CPT, int RPT, int TPB, int VEC>
+__device__ __forceinline__ void k_gram_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                               const U* __restrict__ p, int64_t strips_per_wg, int64_t nstrips,
-                                              U* __restrict__ qpart, const int32_t* __restrict__ flag) {
+                                              U* __restrict__ qpart, const int32_t* __restrict__ flag,
+                                              int interleave) {
   if (stopped(flag)) return;
   constexpr int WD = 8 * CPT;
-  constexpr int VEC = Vec16<V>::n;  // elements per 16-byte load
-  constexpr int LPR = CPT / VEC;    // 16-byte loads per row segment
+  // VEC: elements per load (16 bytes when rows are 16-byte aligned, else 1)
+  constexpr int LPR = CPT / VEC;    // loads per row segment
   constexpr int RG = TPB / 8;       // row groups
   constexpr int NW = TPB / 64;      // waves
   __shared__ C sp[RG * RPT];
@@ -191,9 +210,20 @@ __global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t l
   C qacc[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) qacc[k] = vzero<C>();
-  const int64_t s0 = (int64_t)blockIdx.x * strips_per_wg;
-  int64_t s1 = s0 + strips_per_wg;
-  if (s1 > nstrips) s1 = nstrips;
+  // this workgroup's strips: a contiguous run, or (interleave) every
+  // bk.gx-th strip, so that the workgroups in flight read neighbouring
+  // columns rather than addresses one run apart
+  int64_t s0, s1, sstep;
+  if (interleave) {
+    s0 = bk.x;
+    s1 = nstrips;
+    sstep = bk.gx;
+  } else {
+    s0 = (int64_t)bk.x * strips_per_wg;
+    s1 = s0 + strips_per_wg;
+    if (s1 > nstrips) s1 = nstrips;
+    sstep = 1;
+  }
   __syncthreads();
   // strip loads into registers; two register sets so that the next strip's
   // loads are in flight while the current one is reduced
@@ -264,11 +294,11 @@ __global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t l
   };
   V xa[RPT][CPT], xb[RPT][CPT];
   if (s0 < s1) load_strip(xa, s0);
-  for (int64_t sidx = s0; sidx < s1; sidx += 2) {
-    if (sidx + 1 < s1) load_strip(xb, sidx + 1);
+  for (int64_t sidx = s0; sidx < s1; sidx += 2 * sstep) {
+    if (sidx + sstep < s1) load_strip(xb, sidx + sstep);
     process(xa);
-    if (sidx + 1 < s1) {
-      if (sidx + 2 < s1) load_strip(xa, sidx + 2);
+    if (sidx + sstep < s1) {
+      if (sidx + 2 * sstep < s1) load_strip(xa, sidx + 2 * sstep);
       process(xb);
     }
   }
@@ -287,29 +317,41 @@ __global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t l
       }
     }
     const int64_t r = rg + RG * k;
-    if (cg == 0 && r < m) qpart[(int64_t)blockIdx.x * m + r] = v;
+    if (cg == 0 && r < m) qpart[(int64_t)bk.x * m + r] = v;
   }
+}
+template <typename V, typename C, typename U, int CPT, int RPT, int TPB, int VEC>
+__global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                              const U* __restrict__ p, int64_t strips_per_wg, int64_t nstrips,
+                                              U* __restrict__ qpart, const int32_t* __restrict__ flag,
+                                              int interleave) {
+  k_gram_body<V, C, U, CPT, RPT, TPB, VEC>(bk_hw(), A, lda, m, n, p, strips_per_wg, nstrips, qpart, flag, interleave);
 }
 
 // First level of the sum over workgroup partials: q8[gr * m + i] = sum of
 // qpart[g * m + i] over the gr-th eighth of g, in a fixed order.
 // grid = (ceil(m/64), 8), 256 threads (64 rows x 4 interleaved quarters).
 template <typename U>
-__global__ void __launch_bounds__(256) k_gram_reduce(const U* __restrict__ qpart, int G, int64_t m,
+__device__ __forceinline__ void k_gram_reduce_body(const Bk bk, const U* __restrict__ qpart, int G, int64_t m,
                                                      U* __restrict__ q8, const int32_t* __restrict__ flag) {
   if (stopped(flag)) return;
   __shared__ U red[4][64];
   const int rr = threadIdx.x & 63, quarter = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 64 + rr;
+  const int64_t i = (int64_t)bk.x * 64 + rr;
   const int per = (G + 7) / 8;
-  const int g0 = blockIdx.y * per, g1 = (g0 + per) < G ? (g0 + per) : G;
+  const int g0 = bk.y * per, g1 = (g0 + per) < G ? (g0 + per) : G;
   U acc = vzero<U>();
   if (i < m)
     for (int g = g0 + quarter; g < g1; g += 4) acc = vadd(acc, qpart[(int64_t)g * m + i]);
   red[quarter][rr] = acc;
   __syncthreads();
   if (quarter == 0 && i < m)
-    q8[(int64_t)blockIdx.y * m + i] = vadd(vadd(red[0][rr], red[1][rr]), vadd(red[2][rr], red[3][rr]));
+    q8[(int64_t)bk.y * m + i] = vadd(vadd(red[0][rr], red[1][rr]), vadd(red[2][rr], red[3][rr]));
+}
+template <typename U>
+__global__ void __launch_bounds__(256) k_gram_reduce(const U* __restrict__ qpart, int G, int64_t m,
+                                                     U* __restrict__ q8, const int32_t* __restrict__ flag) {
+  k_gram_reduce_body<U>(bk_hw(), qpart, G, m, q8, flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,7 +430,7 @@ static hipError_t fwd_impl(const FwdArgs& a, hipStream_t st) {
 
 // the widest vector (4 elements) gives the fewest column blocks and hence
 // the most slabs: size the partial buffer for that case
-template <typename V, typename C, typename U, int CPT>
+template <typename V, typename C, typename U, int CPT, int VEC>
 static hipError_t gram_go(const GramArgs& a, hipStream_t st) {
   constexpr int WD = 8 * CPT;
   const int64_t nstrips = ceil_div(a.n, WD);
@@ -400,19 +442,31 @@ static hipError_t gram_go(const GramArgs& a, hipStream_t st) {
   const U* p = reinterpret_cast<const U*>(a.p);
   U* qpart = reinterpret_cast<U*>(a.qpart);
   if (a.ev_begin) (void)hipEventRecord(a.ev_begin, st);
-  // 512 threads: 64 row groups, RPT rows each
-  if (a.m <= 64)
-    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 1, 512>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
-                       spw, nstrips, qpart, a.flag);
-  else if (a.m <= 128)
-    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 2, 512>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
-                       spw, nstrips, qpart, a.flag);
-  else if (a.m <= 256)
-    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 4, 512>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
-                       spw, nstrips, qpart, a.flag);
-  else
-    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 8, 512>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
-                       spw, nstrips, qpart, a.flag);
+  if (a.wide_wg) {
+    // 1024 threads: 128 row groups, RPT rows each
+    if (a.m <= 128)
+      hipLaunchKernelGGL((k_gram<V, C, U, CPT, 1, 1024, VEC>), dim3((unsigned)G), dim3(1024), 0, st, A, a.lda, a.m, a.n,
+                         p, spw, nstrips, qpart, a.flag, a.interleave);
+    else if (a.m <= 256)
+      hipLaunchKernelGGL((k_gram<V, C, U, CPT, 2, 1024, VEC>), dim3((unsigned)G), dim3(1024), 0, st, A, a.lda, a.m, a.n,
+                         p, spw, nstrips, qpart, a.flag, a.interleave);
+    else
+      hipLaunchKernelGGL((k_gram<V, C, U, CPT, 4, 1024, VEC>), dim3((unsigned)G), dim3(1024), 0, st, A, a.lda, a.m, a.n,
+                         p, spw, nstrips, qpart, a.flag, a.interleave);
+  } else if (a.m <= 64) {
+    // 512 threads: 64 row groups, RPT rows each
+    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 1, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
+                       spw, nstrips, qpart, a.flag, a.interleave);
+  } else if (a.m <= 128) {
+    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 2, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
+                       spw, nstrips, qpart, a.flag, a.interleave);
+  } else if (a.m <= 256) {
+    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 4, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
+                       spw, nstrips, qpart, a.flag, a.interleave);
+  } else {
+    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 8, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
+                       spw, nstrips, qpart, a.flag, a.interleave);
+  }
   if (a.ev_end) (void)hipEventRecord(a.ev_end, st);
   hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64), 8), dim3(256), 0, st, qpart, (int)G,
                      a.m, reinterpret_cast<U*>(a.q), a.flag);
@@ -424,11 +478,17 @@ template <typename V, typename C, typename U>
 static hipError_t gram_impl(const GramArgs& a, hipStream_t st) {
   constexpr int CPT0 = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;
   constexpr int CPT1 = CPT0 / 2 > 0 ? CPT0 / 2 : 1;
-  return a.narrow ? gram_go<V, C, U, CPT1>(a, st) : gram_go<V, C, U, CPT0>(a, st);
+  constexpr int VA = Vec16<V>::n;
+  if (aligned16(a.A, a.lda, sizeof(V)))
+    return a.narrow ? gram_go<V, C, U, CPT1, (CPT1 < VA ? CPT1 : VA)>(a, st) : gram_go<V, C, U, CPT0, VA>(a, st);
+  return a.narrow ? gram_go<V, C, U, CPT1, 1>(a, st) : gram_go<V, C, U, CPT0, 1>(a, st);
 }
 
 bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda) {
-  return m <= kGramMaxRows && aligned16(A, lda, dtype_size(dtype));
+  (void)dtype;
+  (void)A;
+  (void)lda;
+  return m <= kGramMaxRows;
 }
 
 hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st) {
@@ -461,6 +521,191 @@ hipError_t launch_gemv_fwd(int dtype, bool wide, const FwdArgs& a, hipStream_t s
     case 1: return wide ? fwd_impl<cf, cd, cd>(a, st) : fwd_impl<cf, cf, cd>(a, st);
     case 2: return fwd_impl<double, double, double>(a, st);
     case 3: return wide ? fwd_impl<float, double, double>(a, st) : fwd_impl<float, float, double>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------ batched systems -------------------------------
+namespace {
+
+template <typename V, typename C, typename U, int CPT, int VEC>
+__global__ void __launch_bounds__(512) kb_gram(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_gram_body<V, C, U, CPT, 8, 512, VEC>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start),
+                                         reinterpret_cast<const V*>(s.Ab), s.ldab, s.m, s.n,
+                                         reinterpret_cast<const U*>(s.p), s.gram_spw, s.gram_nstrips,
+                                         reinterpret_cast<U*>(s.qpart), &s.st->done, 0);
+}
+
+template <typename U>
+__global__ void __launch_bounds__(256) kb_gram_reduce(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                      int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_gram_reduce_body<U>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const U*>(s.qpart),
+                        s.gram_G, s.m, reinterpret_cast<U*>(s.q), &s.st->done);
+}
+
+// A* u in FP64 into slab partials; u = y (use_y) or y_outer
+template <typename V, typename W, int VEC>
+__global__ void __launch_bounds__(256) kb_adj(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys,
+                                              int use_y) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_gemv_adj_body<V, W, W, VEC>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start),
+                                reinterpret_cast<const V*>(s.A), s.lda, s.m, s.n,
+                                reinterpret_cast<const W*>(use_y ? s.y : s.y_outer), s.adj_rps,
+                                reinterpret_cast<W*>(s.apart), nullptr);
+}
+
+template <typename W>
+__global__ void __launch_bounds__(256) kb_sum_slabs(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                    int nsys, int to_x) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_sum_slabs_body<W, W>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const W*>(s.apart),
+                         s.adj_slabs, s.n, reinterpret_cast<W*>(to_x ? s.x : s.w64), nullptr, nullptr);
+}
+
+template <typename V, typename W, int VEC>
+__global__ void __launch_bounds__(256) kb_fwd(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_gemv_fwd_body<V, W, W, 8, VEC>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start),
+                                   reinterpret_cast<const V*>(s.A), s.lda, s.m, s.n,
+                                   reinterpret_cast<const W*>(s.w64), s.fwd_chunk, reinterpret_cast<W*>(s.fpart),
+                                   nullptr);
+}
+
+template <typename V> void plan_gram_t(BSys& s, BGrid& gram, BGrid& red) {
+  constexpr int CPT = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;
+  const int64_t nstrips = ceil_div(s.n, 8 * CPT);
+  int64_t G = nstrips < 512 ? nstrips : 512;
+  const int64_t spw = ceil_div(nstrips, G);
+  G = ceil_div(nstrips, spw);
+  s.gram_spw = spw;
+  s.gram_nstrips = nstrips;
+  s.gram_G = (int)G;
+  gram = BGrid{0, (int)G, 1, 1};
+  red = BGrid{0, (int)ceil_div(s.m, 64), 8, 1};
+}
+
+template <typename V> void plan_wide_t(bool aligned, BSys& s, BGrid& adj, BGrid& sum, BGrid& fwd) {
+  const int VEC = aligned ? Vec16<V>::n : 1;
+  const int64_t nb = ceil_div(s.n, (int64_t)256 * VEC);
+  const int64_t rs = slabs_for(s.m, s.n, VEC);
+  s.adj_slabs = (int)rs;
+  s.adj_rps = ceil_div(s.m, rs);
+  adj = BGrid{0, (int)nb, (int)rs, 1};
+  sum = BGrid{0, (int)ceil_div(s.n, 256), 1, 1};
+  const int64_t rb = ceil_div(s.m, 8);
+  int64_t cs = ceil_div(2048, rb);
+  const int64_t min_chunk = 256 * VEC * 2;
+  if (cs > ceil_div(s.n, min_chunk)) cs = ceil_div(s.n, min_chunk);
+  if (cs < 1) cs = 1;
+  if (cs > kMaxChunks) cs = kMaxChunks;
+  int64_t chunk = ceil_div(s.n, cs);
+  chunk = ceil_div(chunk, 256 * VEC) * (256 * VEC);
+  cs = ceil_div(s.n, chunk);
+  s.fwd_chunk = chunk;
+  s.fwd_chunks = (int)cs;
+  fwd = BGrid{0, (int)cs, (int)rb, 1};
+}
+
+}  // namespace
+
+bool b_aligned16(const void* p, int64_t ld, int dtype) { return aligned16(p, ld, dtype_size(dtype)); }
+
+void b_plan_gram(int bulk_dtype, BSys& s, BGrid& gram, BGrid& red) {
+  switch (bulk_dtype) {
+    case 0: plan_gram_t<cd>(s, gram, red); break;
+    case 1: plan_gram_t<cf>(s, gram, red); break;
+    case 2: plan_gram_t<double>(s, gram, red); break;
+    default: plan_gram_t<float>(s, gram, red); break;
+  }
+}
+
+void b_plan_wide(int dtype, bool aligned, BSys& s, BGrid& adj, BGrid& sum, BGrid& fwd) {
+  switch (dtype) {
+    case 0: plan_wide_t<cd>(aligned, s, adj, sum, fwd); break;
+    case 1: plan_wide_t<cf>(aligned, s, adj, sum, fwd); break;
+    case 2: plan_wide_t<double>(aligned, s, adj, sum, fwd); break;
+    default: plan_wide_t<float>(aligned, s, adj, sum, fwd); break;
+  }
+}
+
+template <typename V, typename C, typename U>
+static hipError_t b_gram_go(bool aligned, const BLaunch& L, const BLaunch& red, hipStream_t st) {
+  constexpr int CPT = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;
+  if (L.total > 0) {
+    if (aligned)
+      hipLaunchKernelGGL((kb_gram<V, C, U, CPT, Vec16<V>::n>), dim3((unsigned)L.total), dim3(512), 0, st, L.sys,
+                         L.grid, L.nsys);
+    else
+      hipLaunchKernelGGL((kb_gram<V, C, U, CPT, 1>), dim3((unsigned)L.total), dim3(512), 0, st, L.sys, L.grid,
+                         L.nsys);
+  }
+  if (red.total > 0)
+    hipLaunchKernelGGL((kb_gram_reduce<U>), dim3((unsigned)red.total), dim3(256), 0, st, red.sys, red.grid,
+                       red.nsys);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_gram(int dtype, bool aligned, const BLaunch& L, const BLaunch& red, hipStream_t st) {
+  switch (dtype) {
+    case 0: return b_gram_go<cd, cd, cd>(aligned, L, red, st);
+    case 1: return b_gram_go<cf, cf, cd>(aligned, L, red, st);
+    case 2: return b_gram_go<double, double, double>(aligned, L, red, st);
+    case 3: return b_gram_go<float, float, double>(aligned, L, red, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename V, typename W>
+static hipError_t b_adj_go(bool aligned, const BLaunch& L, const BLaunch& sum, int use_y, int to_x, hipStream_t st) {
+  if (L.total > 0) {
+    if (aligned)
+      hipLaunchKernelGGL((kb_adj<V, W, Vec16<V>::n>), dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid,
+                         L.nsys, use_y);
+    else
+      hipLaunchKernelGGL((kb_adj<V, W, 1>), dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, use_y);
+  }
+  if (sum.total > 0)
+    hipLaunchKernelGGL((kb_sum_slabs<W>), dim3((unsigned)sum.total), dim3(256), 0, st, sum.sys, sum.grid, sum.nsys,
+                       to_x);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_adj_wide(int dtype, bool aligned, const BLaunch& L, const BLaunch& sum, int use_y, int to_x,
+                             hipStream_t st) {
+  switch (dtype) {
+    case 0: return b_adj_go<cd, cd>(aligned, L, sum, use_y, to_x, st);
+    case 1: return b_adj_go<cf, cd>(aligned, L, sum, use_y, to_x, st);
+    case 2: return b_adj_go<double, double>(aligned, L, sum, use_y, to_x, st);
+    case 3: return b_adj_go<float, double>(aligned, L, sum, use_y, to_x, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename V, typename W>
+static hipError_t b_fwd_go(bool aligned, const BLaunch& L, hipStream_t st) {
+  if (L.total > 0) {
+    if (aligned)
+      hipLaunchKernelGGL((kb_fwd<V, W, Vec16<V>::n>), dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid,
+                         L.nsys);
+    else
+      hipLaunchKernelGGL((kb_fwd<V, W, 1>), dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_b_fwd_wide(int dtype, bool aligned, const BLaunch& L, hipStream_t st) {
+  switch (dtype) {
+    case 0: return b_fwd_go<cd, cd>(aligned, L, st);
+    case 1: return b_fwd_go<cf, cd>(aligned, L, st);
+    case 2: return b_fwd_go<double, double>(aligned, L, st);
+    case 3: return b_fwd_go<float, double>(aligned, L, st);
   }
   return hipErrorInvalidValue;
 }

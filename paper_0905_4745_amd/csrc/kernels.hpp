@@ -96,6 +96,8 @@ struct GramArgs {
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
   int max_wg = 512;  // plan: workgroups (each streams a contiguous run of strips)
   int narrow = 0;    // plan: strips of 16 bytes per thread and row instead of 32
+  int interleave = 0;  // plan: workgroup g takes strips g, g + G, ... instead of a run
+  int wide_wg = 0;     // plan: 1024 threads per workgroup (half the rows per thread)
 };
 bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda);
 hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st);
@@ -210,5 +212,86 @@ hipError_t launch_gram_fold(bool cplx, const double* Cp, int splits, int64_t ldc
 // R (FP64, upper, ld ldr) from G (upper part, overwritten by Schur
 // complements); bad[0] = 1 if a pivot is not positive and finite.
 hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, int32_t* bad, hipStream_t st);
+
+// ---- batched systems -----------------------------------------------------------
+// Batched launch over several systems: entry i holds system i's first
+// workgroup (a prefix sum) and its own grid; entry nsys holds the total.  A
+// system with no work in a launch has start[i] == start[i + 1].
+struct BGrid {
+  int32_t start, gx, gy, gz;
+};
+
+// One descriptor per system of minnorm_solve_batched's fused form: the
+// caller's buffers, the system's launch parameters and its slice of the
+// batch workspace.  Every batched kernel finds its system through a BGrid
+// table (common.hpp) and runs the plain kernel's body on it.
+struct BSys {
+  const void* A;   // problem data (FP64 residuals, x = A* y)
+  int64_t lda;
+  const void* Ab;  // bulk copy (the sketch and the inner iterations)
+  int64_t ldab;
+  int64_t m, n, N, l;
+  const void* b;   // FP64 right-hand side (wide type)
+  void* x;         // FP64 solution (wide type)
+  const void* d;
+  const int32_t* idx;
+  // sketch plan: small FFT (N in LDS): pl_a = plan(N), fft_ba transforms per
+  // workgroup; four-step: pl_a = plan(N1) with fft_ba (rows pass), pl_b =
+  // plan(N2) with fft_bb (columns pass)
+  FftPlan pl_a, pl_b;
+  int fft_ba, fft_bb, N1, N2;
+  const void* tw;  // W_N^k, k < N, compute precision
+  // workspace
+  int32_t* inv;    // N
+  int32_t* flags;  // [0] idx invalid, [1] Cholesky pivot not positive
+  void* S;         // l x m, bulk dtype, column-major
+  void* Y;         // four-step intermediate, m x N (compute precision, complex)
+  void* G;         // m x m, wide
+  void* R;         // m x m, wide
+  void* X;         // ldx x ldx, wide
+  int64_t ldx;
+  double* diag;    // [max |R_ii|, min |R_ii|, nonfinite]
+  void *y, *r0, *r1, *p, *s, *q, *qpart, *w64, *apart, *fpart, *y_outer;
+  PcgState* st;
+  int64_t gram_spw, gram_nstrips;
+  int gram_G;
+  int adj_slabs;
+  int64_t adj_rps;
+  int fwd_chunks;
+  int64_t fwd_chunk;
+};
+struct BLaunch {
+  const BSys* sys;   // device array
+  const BGrid* grid; // device array of nsys + 1
+  int nsys;
+  int total;         // workgroups (grid[nsys].start)
+};
+// per-system grids (host) for the passes whose shapes depend on the data
+void b_plan_sketch(int dtype, BSys& s, BGrid& small, BGrid& cols, BGrid& rows, size_t& lds_small, size_t& lds_cols,
+                   size_t& lds_rows);
+int64_t b_sketch_work_elems(int dtype, int64_t m, int64_t N);  // Y entries (0 for the small FFT)
+void b_plan_gram(int bulk_dtype, BSys& s, BGrid& gram, BGrid& gram_red);
+void b_plan_wide(int dtype, bool aligned, BSys& s, BGrid& adj, BGrid& sum, BGrid& fwd);
+bool b_aligned16(const void* p, int64_t ld, int dtype);
+hipError_t launch_b_prep(const BLaunch& fill, const BLaunch& map, hipStream_t st);
+hipError_t launch_b_sketch(int dtype, const BLaunch& small, const BLaunch& cols, const BLaunch& rows,
+                           size_t lds_small, size_t lds_cols, size_t lds_rows, hipStream_t st);
+hipError_t launch_b_gram_s(int dtype, const BLaunch& L, hipStream_t st);
+hipError_t launch_b_chol_step(bool cplx, const BLaunch& L, int k, hipStream_t st);
+hipError_t launch_b_rdiag(bool cplx, const BLaunch& L, hipStream_t st);
+hipError_t launch_b_inv_diag(bool cplx, const BLaunch& L, hipStream_t st);
+hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int d, hipStream_t st);
+// the fused pass q = A (A* p) on the bulk copy (aligned: 16-byte rows)
+hipError_t launch_b_gram(int dtype, bool aligned, const BLaunch& L, const BLaunch& red, hipStream_t st);
+// FP64 passes on the problem data: w64 (or x) = A* u, u = y_outer (outer) or y;
+// fpart = A w64 in column chunks
+hipError_t launch_b_adj_wide(int dtype, bool aligned, const BLaunch& L, const BLaunch& sum, int use_y, int to_x,
+                             hipStream_t st);
+hipError_t launch_b_fwd_wide(int dtype, bool aligned, const BLaunch& L, hipStream_t st);
+// CG step: parts 0 none (start from r = b), 1 the FP64 chunks fpart, 2 the q slices
+hipError_t launch_b_cg(bool cplx, const BLaunch& Ls, const BLaunch& Lp, int start, int parts, int outer, int par,
+                       size_t lds, hipStream_t st);
+hipError_t launch_b_refine(bool cplx, const BLaunch& L, hipStream_t st);
+hipError_t launch_b_zero_outer(bool cplx, const BLaunch& L, hipStream_t st);
 
 }  // namespace mn

@@ -32,6 +32,7 @@
 //   rule 2 -- relative reduction of an inner solve: rho <= eps^2 rho0.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "batch_dev.hpp"
 
 namespace mn {
 
@@ -47,11 +48,11 @@ __device__ inline W r_at(const RV* R, int64_t ldr, int64_t m, int64_t gi, int64_
 // Diagonal blocks X_ii = R_ii^{-1} (back substitution, one thread per
 // column of the block).  grid = K blocks, 256 threads.
 template <typename RV, typename W>
-__global__ void __launch_bounds__(256) k_inv_diag(const RV* __restrict__ R, int64_t ldr, int64_t m,
+__device__ __forceinline__ void k_inv_diag_body(const Bk bk, const RV* __restrict__ R, int64_t ldr, int64_t m,
                                                   W* __restrict__ X, int64_t ldx) {
   __shared__ W T[TB * TB];
   __shared__ W Xs[TB * TB];
-  const int64_t c0 = (int64_t)blockIdx.x * TB;
+  const int64_t c0 = (int64_t)bk.x * TB;
   for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
     const int r = e % TB, c = e / TB;
     T[e] = r_at<RV, W>(R, ldr, m, c0 + r, c0 + c);
@@ -73,15 +74,20 @@ __global__ void __launch_bounds__(256) k_inv_diag(const RV* __restrict__ R, int6
     X[(c0 + r) + (c0 + c) * ldx] = Xs[e];
   }
 }
+template <typename RV, typename W>
+__global__ void __launch_bounds__(256) k_inv_diag(const RV* __restrict__ R, int64_t ldr, int64_t m,
+                                                  W* __restrict__ X, int64_t ldx) {
+  k_inv_diag_body<RV, W>(bk_hw(), R, ldr, m, X, ldx);
+}
 
 // Off-diagonal blocks at distance d: X_{i,i+d} = -X_ii sum_{k=i+1}^{i+d} R_ik X_{k,i+d}.
 // grid = K - d blocks, 256 threads; thread t owns row t%32, columns 4*(t/32)..+3.
 template <typename RV, typename W>
-__global__ void __launch_bounds__(256) k_trtri_step(const RV* __restrict__ R, int64_t ldr, int64_t m,
+__device__ __forceinline__ void k_trtri_step_body(const Bk bk, const RV* __restrict__ R, int64_t ldr, int64_t m,
                                                     W* __restrict__ X, int64_t ldx, int d) {
   __shared__ W Rs[TB * TB];
   __shared__ W Xs[TB * TB];
-  const int i = blockIdx.x, j = i + d;
+  const int i = bk.x, j = i + d;
   const int64_t i0 = (int64_t)i * TB, j0 = (int64_t)j * TB;
   const int r = threadIdx.x % TB, cg = (threadIdx.x / TB) * 4;
   W acc[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
@@ -117,6 +123,11 @@ __global__ void __launch_bounds__(256) k_trtri_step(const RV* __restrict__ R, in
 #pragma unroll
   for (int u = 0; u < 4; ++u) X[(i0 + r) + (j0 + cg + u) * ldx] = vsub(vzero<W>(), o[u]);
 }
+template <typename RV, typename W>
+__global__ void __launch_bounds__(256) k_trtri_step(const RV* __restrict__ R, int64_t ldr, int64_t m,
+                                                    W* __restrict__ X, int64_t ldx, int d) {
+  k_trtri_step_body<RV, W>(bk_hw(), R, ldr, m, X, ldx, d);
+}
 
 __device__ inline bool stop_test(const PcgState& st, double rho, double xi) {
   if (st.rule == 2) return rho <= st.eps * st.eps * st.rho0;
@@ -134,7 +145,7 @@ __device__ inline bool stop_test(const PcgState& st, double rho, double xi) {
 // Then s_j = sum_{i<=j} conj(X_ij) r'_i for this workgroup's 8 columns.
 // grid = ceil(m / 8), 256 threads, dynamic LDS = m FP64 entries (r').
 template <typename W>
-__global__ void __launch_bounds__(256) k_cg_s(const W* __restrict__ X, int64_t ldx, int64_t m, int start,
+__device__ __forceinline__ void k_cg_s_body(const Bk bk, const W* __restrict__ X, int64_t ldx, int64_t m, int start,
                                               const W* __restrict__ b, const W* __restrict__ parts, int nparts,
                                               W* __restrict__ p, W* __restrict__ y, const W* __restrict__ r_in,
                                               W* __restrict__ r_out, W* __restrict__ s, PcgState* __restrict__ stp) {
@@ -142,7 +153,7 @@ __global__ void __launch_bounds__(256) k_cg_s(const W* __restrict__ X, int64_t l
   W* rs = reinterpret_cast<W*>(smem_raw);
   __shared__ double red[4];
   PcgState& st = *stp;
-  const bool lead = blockIdx.x == 0;
+  const bool lead = bk.x == 0;
   if (start) {
     if (st.outer_done) return;
     for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
@@ -194,7 +205,7 @@ __global__ void __launch_bounds__(256) k_cg_s(const W* __restrict__ X, int64_t l
   __syncthreads();
   // s for columns c0 .. c0+7: wave w takes 2 columns, lanes run down each
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t c0 = (int64_t)blockIdx.x * 8 + 2 * wv;
+  const int64_t c0 = (int64_t)bk.x * 8 + 2 * wv;
   W acc0 = vzero<W>(), acc1 = vzero<W>();
   const int64_t j0 = c0, j1 = c0 + 1;
   if (j0 < m) {
@@ -212,6 +223,13 @@ __global__ void __launch_bounds__(256) k_cg_s(const W* __restrict__ X, int64_t l
     if (j1 < m) s[j1] = acc1;
   }
 }
+template <typename W>
+__global__ void __launch_bounds__(256) k_cg_s(const W* __restrict__ X, int64_t ldx, int64_t m, int start,
+                                              const W* __restrict__ b, const W* __restrict__ parts, int nparts,
+                                              W* __restrict__ p, W* __restrict__ y, const W* __restrict__ r_in,
+                                              W* __restrict__ r_out, W* __restrict__ s, PcgState* __restrict__ stp) {
+  k_cg_s_body<W>(bk_hw(), X, ldx, m, start, b, parts, nparts, p, y, r_in, r_out, s, stp);
+}
 
 // ---------------------------------------------------------------------------
 // k_cg_p.  rho' = ||s||^2 (and xi, the stopping test); z = X s on this
@@ -219,7 +237,7 @@ __global__ void __launch_bounds__(256) k_cg_s(const W* __restrict__ X, int64_t l
 // With y_outer (start of an FP64 refinement step) the outer certificate is
 // tested first.  grid = ceil(m / 16), 256 threads.
 template <typename W>
-__global__ void __launch_bounds__(256) k_cg_p(const W* __restrict__ X, int64_t ldx, int64_t m, int start,
+__device__ __forceinline__ void k_cg_p_body(const Bk bk, const W* __restrict__ X, int64_t ldx, int64_t m, int start,
                                               const W* __restrict__ b, const W* __restrict__ y,
                                               const W* __restrict__ y_outer, const W* __restrict__ r,
                                               const W* __restrict__ s, W* __restrict__ p,
@@ -230,7 +248,7 @@ __global__ void __launch_bounds__(256) k_cg_p(const W* __restrict__ X, int64_t l
   __shared__ double red[4];
   __shared__ W part[16][RB];
   PcgState& st = *stp;
-  const bool lead = blockIdx.x == 0;
+  const bool lead = bk.x == 0;
   if (start ? (st.outer_done != 0) : (st.done != 0)) return;
   double rho = 0.0;
   for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
@@ -312,7 +330,7 @@ __global__ void __launch_bounds__(256) k_cg_p(const W* __restrict__ X, int64_t l
     beta = rho / st.rho_prev;
   }
   // z = X s on rows i0 .. i0+15: thread t takes row t%16 and every 16th column
-  const int64_t i0 = (int64_t)blockIdx.x * RB;
+  const int64_t i0 = (int64_t)bk.x * RB;
   const int rr = threadIdx.x % RB, cgrp = threadIdx.x / RB;  // 16 column groups
   const int64_t i = i0 + rr;
   // X is zero below the diagonal inside the diagonal block, so the band can
@@ -337,18 +355,33 @@ __global__ void __launch_bounds__(256) k_cg_p(const W* __restrict__ X, int64_t l
     p[ii] = start ? z : vadd(z, vscale(p[ii], beta));
   }
 }
+template <typename W>
+__global__ void __launch_bounds__(256) k_cg_p(const W* __restrict__ X, int64_t ldx, int64_t m, int start,
+                                              const W* __restrict__ b, const W* __restrict__ y,
+                                              const W* __restrict__ y_outer, const W* __restrict__ r,
+                                              const W* __restrict__ s, W* __restrict__ p,
+                                              PcgState* __restrict__ stp) {
+  k_cg_p_body<W>(bk_hw(), X, ldx, m, start, b, y, y_outer, r, s, p, stp);
+}
 
 // y_outer += y (after an inner solve).
 template <typename W>
-__global__ void k_refine_update(W* __restrict__ y_outer, const W* __restrict__ y, int64_t m, const PcgState* st) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void k_refine_update_body(const Bk bk, W* __restrict__ y_outer, const W* __restrict__ y, int64_t m, const PcgState* st) {
+  const int64_t i = (int64_t)bk.x * blockDim.x + threadIdx.x;
   if (st->outer_done) return;
   if (i < m) y_outer[i] = vadd(y_outer[i], y[i]);
 }
+template <typename W>
+__global__ void k_refine_update(W* __restrict__ y_outer, const W* __restrict__ y, int64_t m, const PcgState* st) {
+  k_refine_update_body<W>(bk_hw(), y_outer, y, m, st);
+}
 
-template <typename W> __global__ void k_zero_vec(W* __restrict__ v, int64_t m) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <typename W> __device__ __forceinline__ void k_zero_vec_body(const Bk bk, W* __restrict__ v, int64_t m) {
+  const int64_t i = (int64_t)bk.x * blockDim.x + threadIdx.x;
   if (i < m) v[i] = vzero<W>();
+}
+template <typename W> __global__ void k_zero_vec(W* __restrict__ v, int64_t m) {
+  k_zero_vec_body<W>(bk_hw(), v, m);
 }
 
 // ------------------------------ launchers -----------------------------------
@@ -420,6 +453,128 @@ hipError_t launch_zero(bool cplx, void* v, int64_t m, hipStream_t st) {
   else
     hipLaunchKernelGGL(k_zero_vec<double>, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st,
                        reinterpret_cast<double*>(v), m);
+  return hipGetLastError();
+}
+
+// ------------------------------ batched systems -------------------------------
+namespace {
+
+template <typename W>
+__global__ void __launch_bounds__(256) kb_inv_diag(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                   int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_inv_diag_body<W, W>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const W*>(s.R), s.m,
+                        s.m, reinterpret_cast<W*>(s.X), s.ldx);
+}
+
+template <typename W>
+__global__ void __launch_bounds__(256) kb_trtri_step(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                     int nsys, int d) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_trtri_step_body<W, W>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const W*>(s.R),
+                          s.m, s.m, reinterpret_cast<W*>(s.X), s.ldx, d);
+}
+
+// r ping-pong: at iteration parity par, r_in = r[par] and r_out = r[par ^ 1];
+// a start writes r[par]
+template <typename W>
+__device__ inline W* r_buf(const BSys& s, int which) {
+  return reinterpret_cast<W*>(which ? s.r1 : s.r0);
+}
+
+template <typename W>
+__global__ void __launch_bounds__(256) kb_cg_s(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys,
+                                               int start, int parts, int par) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  const W* pp = parts == 1 ? reinterpret_cast<const W*>(s.fpart) : parts == 2 ? reinterpret_cast<const W*>(s.q) : nullptr;
+  const int np = parts == 1 ? s.fwd_chunks : parts == 2 ? kGramParts : 0;
+  k_cg_s_body<W>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const W*>(s.X), s.ldx, s.m,
+                 start, reinterpret_cast<const W*>(s.b), pp, np, reinterpret_cast<W*>(s.p), reinterpret_cast<W*>(s.y),
+                 start ? nullptr : r_buf<W>(s, par), start ? r_buf<W>(s, par) : r_buf<W>(s, par ^ 1),
+                 reinterpret_cast<W*>(s.s), s.st);
+}
+
+template <typename W>
+__global__ void __launch_bounds__(256) kb_cg_p(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys,
+                                               int start, int outer, int par) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_cg_p_body<W>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const W*>(s.X), s.ldx, s.m,
+                 start, reinterpret_cast<const W*>(s.b), reinterpret_cast<const W*>(s.y),
+                 outer ? reinterpret_cast<const W*>(s.y_outer) : nullptr,
+                 start ? r_buf<W>(s, par) : r_buf<W>(s, par ^ 1), reinterpret_cast<const W*>(s.s),
+                 reinterpret_cast<W*>(s.p), s.st);
+}
+
+template <typename W>
+__global__ void __launch_bounds__(256) kb_refine(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                 int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_refine_update_body<W>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<W*>(s.y_outer),
+                          reinterpret_cast<const W*>(s.y), s.m, s.st);
+}
+
+template <typename W>
+__global__ void __launch_bounds__(256) kb_zero_outer(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                     int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_zero_vec_body<W>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<W*>(s.y_outer), s.m);
+}
+
+template <typename W>
+hipError_t b_cg_t(const BLaunch& Ls, const BLaunch& Lp, int start, int parts, int outer, int par, size_t lds,
+                  hipStream_t st) {
+  if (lds > 48 * 1024) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kb_cg_s<W>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kb_cg_p<W>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  }
+  hipLaunchKernelGGL(kb_cg_s<W>, dim3((unsigned)Ls.total), dim3(256), lds, st, Ls.sys, Ls.grid, Ls.nsys, start, parts,
+                     par);
+  hipLaunchKernelGGL(kb_cg_p<W>, dim3((unsigned)Lp.total), dim3(256), lds, st, Lp.sys, Lp.grid, Lp.nsys, start, outer,
+                     par);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_b_inv_diag(bool cplx, const BLaunch& L, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  if (cplx) hipLaunchKernelGGL(kb_inv_diag<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
+  else hipLaunchKernelGGL(kb_inv_diag<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int d, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  if (cplx)
+    hipLaunchKernelGGL(kb_trtri_step<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, d);
+  else
+    hipLaunchKernelGGL(kb_trtri_step<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_cg(bool cplx, const BLaunch& Ls, const BLaunch& Lp, int start, int parts, int outer, int par,
+                       size_t lds, hipStream_t st) {
+  return cplx ? b_cg_t<cd>(Ls, Lp, start, parts, outer, par, lds, st)
+              : b_cg_t<double>(Ls, Lp, start, parts, outer, par, lds, st);
+}
+
+hipError_t launch_b_refine(bool cplx, const BLaunch& L, hipStream_t st) {
+  if (cplx) hipLaunchKernelGGL(kb_refine<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
+  else hipLaunchKernelGGL(kb_refine<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_zero_outer(bool cplx, const BLaunch& L, hipStream_t st) {
+  if (cplx) hipLaunchKernelGGL(kb_zero_outer<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
+  else hipLaunchKernelGGL(kb_zero_outer<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
   return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@
 // block is exactly R_S.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "batch_dev.hpp"
 
 namespace mn {
 
@@ -357,7 +358,7 @@ __global__ void k_qr_extract(const V* __restrict__ Sp, int64_t lp, const V* __re
 }
 
 template <typename V>
-__global__ void k_rdiag_range(const V* __restrict__ R, int64_t ldr, int64_t m, double* __restrict__ out) {
+__device__ __forceinline__ void k_rdiag_range_body(const Bk bk, const V* __restrict__ R, int64_t ldr, int64_t m, double* __restrict__ out) {
   __shared__ double red[16];
   double mx = 0.0, mn = 1.0e308;
   bool fin = true;
@@ -377,6 +378,10 @@ __global__ void k_rdiag_range(const V* __restrict__ R, int64_t ldr, int64_t m, d
     out[1] = mn;
     out[2] = f;
   }
+}
+template <typename V>
+__global__ void k_rdiag_range(const V* __restrict__ R, int64_t ldr, int64_t m, double* __restrict__ out) {
+  k_rdiag_range_body<V>(bk_hw(), R, ldr, m, out);
 }
 
 template <typename V>
@@ -440,6 +445,22 @@ hipError_t launch_qr(int dtype, const QrArgs& a, hipStream_t st) {
     case 3: return qr_impl<float>(a, st);
   }
   return hipErrorInvalidValue;
+}
+
+namespace {
+template <typename V>
+__global__ void kb_rdiag(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_rdiag_range_body<V>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const V*>(s.R), s.m,
+                        s.m, s.diag);
+}
+}  // namespace
+
+hipError_t launch_b_rdiag(bool cplx, const BLaunch& L, hipStream_t st) {
+  if (cplx) hipLaunchKernelGGL(kb_rdiag<cd>, dim3((unsigned)L.total), dim3(1024), 0, st, L.sys, L.grid, L.nsys);
+  else hipLaunchKernelGGL(kb_rdiag<double>, dim3((unsigned)L.total), dim3(1024), 0, st, L.sys, L.grid, L.nsys);
+  return hipGetLastError();
 }
 
 }  // namespace mn

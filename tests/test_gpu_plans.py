@@ -32,7 +32,7 @@ def test_tuned_plans_roundtrip(tmp_path):
     key = "gram/0/200/12000/0"
     assert key in doc["plans"] and key in doc["best_ms"]
     plan = doc["plans"][key]
-    assert (plan & 0xFFFF) in (256, 512, 1024) and (plan >> 16) in (0, 1)
+    assert (plan & 0xFFFF) in (256, 512, 1024) and (plan >> 16) in range(8)
     # a hand-written plan file is merged and used
     doc["plans"][key] = 256 | 0x10000
     path.write_text(json.dumps(doc))
@@ -54,7 +54,7 @@ def test_plan_file_errors(tmp_path):
 
 
 def test_every_fused_plan_meets_eps(tmp_path):
-    """All six fused-pass plans (3 workgroup counts x 2 strip widths) give
+    """Fused-pass plans (workgroup counts, strip widths, strip orders) give
     parity with the oracle on a ragged shape (n not a multiple of a strip)."""
     from paper_0905_4745_amd import api
     A, b, _ = synth.make_svd(96, 5001, 1e3, seed=32)
@@ -62,7 +62,8 @@ def test_every_fused_plan_meets_eps(tmp_path):
     d, idx = synth.draw_srft(N, 384, seed=32)
     p = oracle.classical_minnorm(A, b)
     path = tmp_path / "p.json"
-    for plan in (256, 512, 1024, 256 | 0x10000, 512 | 0x10000, 1024 | 0x10000):
+    for plan in (256, 512, 1024, 256 | 0x10000, 1024 | 0x10000, 512 | 0x20000, 1024 | 0x30000, 512 | 0x40000,
+                 256 | 0x70000):
         path.write_text(json.dumps({"plans": {"gram/0/96/5001/0": plan}}))
         api.plans_load(str(path))
         x, info = api.minnorm_solve(to_dev(A), to_dev(b), 1e-10, d, idx, N)

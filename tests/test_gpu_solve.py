@@ -239,12 +239,13 @@ def test_unfused_and_unaligned_paths(m, n, kind):
     assert rel(x, p) <= 1e-10
 
 
-@pytest.mark.parametrize("streams", [1, 8])
-def test_batched_concurrent_lanes(streams):
-    """24 uneven real systems (FP64 data + FP32 copies) on 1 and 8 concurrent lanes."""
+@pytest.mark.parametrize("form,streams", [(1, 1), (1, 8), (0, 8)])
+def test_batched_concurrent_lanes(form, streams):
+    """24 uneven real systems (FP64 data + FP32 copies): concurrent lanes (1 and
+    8) and the fused form (every stage of all systems in one launch)."""
     import torch
     from paper_0905_4745_amd import api
-    say(f"batched 24 systems on {streams} lanes")
+    say(f"batched 24 systems, form {form}, {streams} lanes")
     shapes = synth.make_batch_shapes(24, seed=11, m_lo=8, m_hi=128, n_lo=300, n_hi=4000)
     systems = synth.make_batch(shapes, seed=12, kappa=1e4)
     As = [to_dev(A) for A, _ in systems]
@@ -256,7 +257,7 @@ def test_batched_concurrent_lanes(streams):
         d, idx = synth.draw_srft(N, synth.sketch_width(m, N), seed=100 + k, real=True)
         ds.append(d), idxs.append(idx), Ns.append(N)
     xs, infos = api.minnorm_solve_batched(As, bs, 1e-10, ds, idxs, Ns, A_los=A_los,
-                                          opts=api.SolveOptions(streams=streams))
+                                          opts=api.SolveOptions(streams=streams, batch_form=form))
     worst = 0.0
     for (A, b), x, info in zip(systems, xs, infos):
         assert info["status"] == 0
@@ -317,3 +318,49 @@ def test_ill_conditioned_falls_back_and_meets_eps():
     x, info = _solve(A, b, 1e-8, d, idx, N)
     assert info["status"] == 0
     assert rel(x, oracle.refined_minnorm(A, b)) <= 1e-8
+
+
+def _batch_inputs(shapes, seed, complex_, kappa, real_signs):
+    ds, idxs, Ns = [], [], []
+    for k, (m, n) in enumerate(shapes):
+        N = synth.next_pow2(n)
+        d, idx = synth.draw_srft(N, synth.sketch_width(m, N), seed=seed + k, real=real_signs)
+        ds.append(d), idxs.append(idx), Ns.append(N)
+    return ds, idxs, Ns
+
+
+def test_batched_fused_plain_c128_matches_lanes():
+    """Plain complex128 systems (one with N <= 4096, others four-step; ragged m):
+    fused and lane forms both meet eps against the classical oracle, with the
+    same iteration counts up to one."""
+    from paper_0905_4745_amd import api
+    shapes = [(20, 600), (64, 5000), (37, 9000), (130, 4100), (7, 33)]
+    systems = [synth.make_svd(m, n, 1e3, seed=40 + k)[:2] for k, (m, n) in enumerate(shapes)]
+    As = [to_dev(A) for A, _ in systems]
+    bs = [to_dev(b) for _, b in systems]
+    ds, idxs, Ns = _batch_inputs(shapes, 50, True, 1e3, False)
+    xf, inf_f = api.minnorm_solve_batched(As, bs, 1e-10, ds, idxs, Ns, opts=api.SolveOptions(batch_form=0))
+    xl, inf_l = api.minnorm_solve_batched(As, bs, 1e-10, ds, idxs, Ns, opts=api.SolveOptions(batch_form=1))
+    for (A, b), a, c, ia, ic in zip(systems, xf, xl, inf_f, inf_l):
+        p = oracle.classical_minnorm(A, b)
+        assert ia["status"] == 0 and ic["status"] == 0
+        assert rel(to_np(a), p) <= 1e-10 and rel(to_np(c), p) <= 1e-10
+        assert abs(ia["iters"] - ic["iters"]) <= 1
+
+
+def test_batched_fused_mixed_c128_and_fallback():
+    """complex128 data with complex64 copies; one system at cond 1e6 makes the
+    Gram route decline and is finished by the Householder route."""
+    import torch
+    from paper_0905_4745_amd import api
+    shapes = [(48, 2000), (100, 6000), (32, 1500)]
+    kappas = [1e3, 1e4, 1e6]
+    systems = [synth.make_svd(m, n, kp, seed=60 + k)[:2] for k, ((m, n), kp) in enumerate(zip(shapes, kappas))]
+    As = [to_dev(A) for A, _ in systems]
+    A_los = [a.to(torch.complex64) for a in As]
+    bs = [to_dev(b) for _, b in systems]
+    ds, idxs, Ns = _batch_inputs(shapes, 70, True, 1e3, False)
+    xs, infos = api.minnorm_solve_batched(As, bs, 1e-9, ds, idxs, Ns, A_los=A_los)
+    for (A, b), x, info in zip(systems, xs, infos):
+        assert info["status"] == 0
+        assert rel(to_np(x), oracle.refined_minnorm(A, b)) <= 1e-9
