@@ -931,6 +931,17 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   }
   h->events = info != nullptr;
   ev_record(h, 0);
+  // the fused pass reads 16-byte vectors: an unaligned bulk row start is
+  // re-laid once with a padded leading dimension (one pass over the bulk copy)
+  if (m <= kGramMaxRows && !b_aligned16(c.Ab, c.ldab, c.bulk)) {
+    const int64_t be = dtype_size(c.bulk);
+    const int64_t pld = rup(n, std::max<int64_t>(16 / be, 1));
+    void* pad = ws(h, "bulk_padded", (size_t)(pld * m * be));
+    ck(hipMemcpy2DAsync(pad, (size_t)(pld * be), c.Ab, (size_t)(c.ldab * be), (size_t)(n * be), (size_t)m,
+                        hipMemcpyDeviceToDevice, h->stream));
+    c.Ab = pad;
+    c.ldab = pld;
+  }
   int32_t* inv = nullptr;
   if (!prepare_idx(h, idx, l, N, &inv)) return -16;
   const int64_t bes = dtype_size(c.bulk);
@@ -1055,10 +1066,10 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   const int64_t ces = is_single(bulk) ? 8 : 16;
   std::vector<BSys> hs((size_t)batch);
   // grids
-  GridTable fill, map, sk_small, sk_cols, sk_rows, gram_s, rdiag, invd, gramA, gramU, gred, adjA, adjU, sum, fwdA,
-      fwdU, cgs, cgp, vec;
-  for (GridTable* t : {&fill, &map, &sk_small, &sk_cols, &sk_rows, &gram_s, &rdiag, &invd, &gramA, &gramU, &gred, &adjA,
-                       &adjU, &sum, &fwdA, &fwdU, &cgs, &cgp, &vec})
+  GridTable fill, map, sk_small, sk_cols, sk_rows, gram_s, rdiag, invd, gramR[4], gred, adjA, adjU, sum, fwdA, fwdU,
+      cgs, cgp, vec;
+  for (GridTable* t : {&fill, &map, &sk_small, &sk_cols, &sk_rows, &gram_s, &rdiag, &invd, &gramR[0], &gramR[1],
+                       &gramR[2], &gramR[3], &gred, &adjA, &adjU, &sum, &fwdA, &fwdU, &cgs, &cgp, &vec})
     t->init(batch);
   int maxnbk = 0;
   size_t lds_small = 0, lds_cols = 0, lds_rows = 0;
@@ -1098,9 +1109,9 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     invd.g[i] = BGrid{0, (int)cdiv(m[i], 32), 1, 1};
     maxnbk = std::max(maxnbk, (int)cdiv(m[i], 32));
     BGrid gg, gr;
-    b_plan_gram(bulk, q, gg, gr);
-    const bool al_b = b_aligned16(q.Ab, q.ldab, bulk);
-    (al_b ? gramA : gramU).g[i] = gg;
+    // every bulk row start is 16-byte aligned (padded below if not)
+    const int cls = b_plan_gram(bulk, q, gg, gr);
+    for (int c = 0; c < 4; ++c) gramR[c].g[i] = c == cls ? gg : BGrid{0, 0, 1, 1};
     gred.g[i] = gr;
     BGrid ga, gs, gf;
     const bool al = b_aligned16(q.A, q.lda, dtype);
@@ -1112,7 +1123,11 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     cgp.g[i] = BGrid{0, (int)cdiv(m[i], 16), 1, 1};
     vec.g[i] = BGrid{0, (int)cdiv(m[i], 256), 1, 1};
     const int64_t mm = m[i];
-    wbytes[i] = a256(N[i] * 4) + a256(l[i] * mm * be) + a256(b_sketch_work_elems(bulk, mm, N[i]) * ces) +
+    // an unaligned bulk row start is re-laid with a padded leading dimension
+    // (one extra pass over the bulk copy) so that the fused pass reads
+    // 16-byte vectors
+    const int64_t pad_ld = b_aligned16(q.Ab, q.ldab, bulk) ? 0 : rup(n[i], std::max<int64_t>(16 / be, 1));
+    wbytes[i] = a256(pad_ld * mm * be) + a256(N[i] * 4) + a256(l[i] * mm * be) + a256(b_sketch_work_elems(bulk, mm, N[i]) * ces) +
                 2 * a256(mm * mm * W) + a256(q.ldx * q.ldx * W) + 6 * a256(mm * W) + a256(kGramParts * mm * W) +
                 a256((int64_t)q.gram_G * mm * W) + a256(n[i] * W) + a256((int64_t)q.adj_slabs * n[i] * W) +
                 a256((int64_t)q.fwd_chunks * mm * W);
@@ -1131,8 +1146,6 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   }
   // mark the grids of systems outside a launch
   for (int i = 0; i < batch; ++i) {
-    if (!b_aligned16(hs[i].Ab, hs[i].ldab, bulk)) gramA.g[i].gx = 0;
-    else gramU.g[i].gx = 0;
     const bool al = b_aligned16(hs[i].A, hs[i].lda, dtype);
     if (al) {
       adjU.g[i].gx = 0;
@@ -1142,8 +1155,9 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       fwdA.g[i].gx = 0;
     }
   }
-  std::vector<GridTable*> all = {&fill, &map,  &sk_small, &sk_cols, &sk_rows, &gram_s, &rdiag, &invd, &gramA, &gramU,
-                                 &gred, &adjA, &adjU,     &sum,     &fwdA,    &fwdU,   &cgs,   &cgp,  &vec};
+  std::vector<GridTable*> all = {&fill,     &map,      &sk_small, &sk_cols, &sk_rows, &gram_s, &rdiag,
+                                 &invd,     &gramR[0], &gramR[1], &gramR[2], &gramR[3], &gred,  &adjA,
+                                 &adjU,     &sum,      &fwdA,     &fwdU,    &cgs,     &cgp,    &vec};
   for (auto& t : chol) all.push_back(&t);
   for (auto& t : trtri) all.push_back(&t);
   size_t nent = 0;
@@ -1172,6 +1186,14 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       return (void*)r;
     };
     const int64_t mm = m[i];
+    if (!b_aligned16(q.Ab, q.ldab, bulk)) {
+      const int64_t pld = rup(n[i], std::max<int64_t>(16 / be, 1));
+      void* pad = take(pld * mm * be);
+      ck(hipMemcpy2DAsync(pad, (size_t)(pld * be), q.Ab, (size_t)(q.ldab * be), (size_t)(n[i] * be), (size_t)mm,
+                          hipMemcpyDeviceToDevice, st));
+      q.Ab = pad;
+      q.ldab = pld;
+    }
     q.inv = (int32_t*)take(N[i] * 4);
     q.S = take(l[i] * mm * be);
     q.Y = take(b_sketch_work_elems(bulk, mm, N[i]) * ces);
@@ -1303,8 +1325,8 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     int guard = 0;
     while (true) {
       for (int it = 0; it < o.check_every; ++it) {
-        ck(launch_b_gram(bulk, true, L(gramA), none, st));
-        ck(launch_b_gram(bulk, false, L(gramU), L(gred), st));
+        const BLaunch gl[4] = {L(gramR[0]), L(gramR[1]), L(gramR[2]), L(gramR[3])};
+        ck(launch_b_gram(bulk, gl, L(gred), st));
         ck(launch_b_cg(cplx, L(cgs), L(cgp), 0, 2, 0, par, cg_lds, st));
         par ^= 1;
       }

@@ -528,11 +528,11 @@ hipError_t launch_gemv_fwd(int dtype, bool wide, const FwdArgs& a, hipStream_t s
 // ------------------------------ batched systems -------------------------------
 namespace {
 
-template <typename V, typename C, typename U, int CPT, int VEC>
+template <typename V, typename C, typename U, int CPT, int RPT, int VEC>
 __global__ void __launch_bounds__(512) kb_gram(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys) {
   const int i = bgrid_find(grid, nsys, blockIdx.x);
   const BSys& s = sys[i];
-  k_gram_body<V, C, U, CPT, 8, 512, VEC>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start),
+  k_gram_body<V, C, U, CPT, RPT, 512, VEC>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start),
                                          reinterpret_cast<const V*>(s.Ab), s.ldab, s.m, s.n,
                                          reinterpret_cast<const U*>(s.p), s.gram_spw, s.gram_nstrips,
                                          reinterpret_cast<U*>(s.qpart), &s.st->done, 0);
@@ -578,10 +578,14 @@ __global__ void __launch_bounds__(256) kb_fwd(const BSys* __restrict__ sys, cons
                                    nullptr);
 }
 
-template <typename V> void plan_gram_t(BSys& s, BGrid& gram, BGrid& red) {
+template <typename V> int plan_gram_t(BSys& s, BGrid& gram, BGrid& red) {
   constexpr int CPT = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;
   const int64_t nstrips = ceil_div(s.n, 8 * CPT);
-  int64_t G = nstrips < 512 ? nstrips : 512;
+  // about 256 KB of A per workgroup (small systems take few workgroups)
+  int64_t G = ceil_div(s.m * s.n * (int64_t)sizeof(V), 256 << 10);
+  if (G > 512) G = 512;
+  if (G > nstrips) G = nstrips;
+  if (G < 1) G = 1;
   const int64_t spw = ceil_div(nstrips, G);
   G = ceil_div(nstrips, spw);
   s.gram_spw = spw;
@@ -589,6 +593,8 @@ template <typename V> void plan_gram_t(BSys& s, BGrid& gram, BGrid& red) {
   s.gram_G = (int)G;
   gram = BGrid{0, (int)G, 1, 1};
   red = BGrid{0, (int)ceil_div(s.m, 64), 8, 1};
+  // rows per thread class: 512 threads hold 64 RPT rows
+  return s.m <= 64 ? 0 : s.m <= 128 ? 1 : s.m <= 256 ? 2 : 3;
 }
 
 template <typename V> void plan_wide_t(bool aligned, BSys& s, BGrid& adj, BGrid& sum, BGrid& fwd) {
@@ -617,12 +623,12 @@ template <typename V> void plan_wide_t(bool aligned, BSys& s, BGrid& adj, BGrid&
 
 bool b_aligned16(const void* p, int64_t ld, int dtype) { return aligned16(p, ld, dtype_size(dtype)); }
 
-void b_plan_gram(int bulk_dtype, BSys& s, BGrid& gram, BGrid& red) {
+int b_plan_gram(int bulk_dtype, BSys& s, BGrid& gram, BGrid& red) {
   switch (bulk_dtype) {
-    case 0: plan_gram_t<cd>(s, gram, red); break;
-    case 1: plan_gram_t<cf>(s, gram, red); break;
-    case 2: plan_gram_t<double>(s, gram, red); break;
-    default: plan_gram_t<float>(s, gram, red); break;
+    case 0: return plan_gram_t<cd>(s, gram, red);
+    case 1: return plan_gram_t<cf>(s, gram, red);
+    case 2: return plan_gram_t<double>(s, gram, red);
+    default: return plan_gram_t<float>(s, gram, red);
   }
 }
 
@@ -635,29 +641,32 @@ void b_plan_wide(int dtype, bool aligned, BSys& s, BGrid& adj, BGrid& sum, BGrid
   }
 }
 
-template <typename V, typename C, typename U>
-static hipError_t b_gram_go(bool aligned, const BLaunch& L, const BLaunch& red, hipStream_t st) {
+template <typename V, typename C, typename U, int RPT>
+static void b_gram_one(const BLaunch& L, hipStream_t st) {
   constexpr int CPT = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;
-  if (L.total > 0) {
-    if (aligned)
-      hipLaunchKernelGGL((kb_gram<V, C, U, CPT, Vec16<V>::n>), dim3((unsigned)L.total), dim3(512), 0, st, L.sys,
-                         L.grid, L.nsys);
-    else
-      hipLaunchKernelGGL((kb_gram<V, C, U, CPT, 1>), dim3((unsigned)L.total), dim3(512), 0, st, L.sys, L.grid,
-                         L.nsys);
-  }
+  if (L.total > 0)
+    hipLaunchKernelGGL((kb_gram<V, C, U, CPT, RPT, Vec16<V>::n>), dim3((unsigned)L.total), dim3(512), 0, st, L.sys,
+                       L.grid, L.nsys);
+}
+
+template <typename V, typename C, typename U>
+static hipError_t b_gram_go(const BLaunch* L, const BLaunch& red, hipStream_t st) {
+  b_gram_one<V, C, U, 1>(L[0], st);
+  b_gram_one<V, C, U, 2>(L[1], st);
+  b_gram_one<V, C, U, 4>(L[2], st);
+  b_gram_one<V, C, U, 8>(L[3], st);
   if (red.total > 0)
     hipLaunchKernelGGL((kb_gram_reduce<U>), dim3((unsigned)red.total), dim3(256), 0, st, red.sys, red.grid,
                        red.nsys);
   return hipGetLastError();
 }
 
-hipError_t launch_b_gram(int dtype, bool aligned, const BLaunch& L, const BLaunch& red, hipStream_t st) {
+hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st) {
   switch (dtype) {
-    case 0: return b_gram_go<cd, cd, cd>(aligned, L, red, st);
-    case 1: return b_gram_go<cf, cf, cd>(aligned, L, red, st);
-    case 2: return b_gram_go<double, double, double>(aligned, L, red, st);
-    case 3: return b_gram_go<float, float, double>(aligned, L, red, st);
+    case 0: return b_gram_go<cd, cd, cd>(L, red, st);
+    case 1: return b_gram_go<cf, cf, cd>(L, red, st);
+    case 2: return b_gram_go<double, double, double>(L, red, st);
+    case 3: return b_gram_go<float, float, double>(L, red, st);
   }
   return hipErrorInvalidValue;
 }

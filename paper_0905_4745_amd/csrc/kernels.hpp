@@ -270,7 +270,8 @@ struct BLaunch {
 void b_plan_sketch(int dtype, BSys& s, BGrid& small, BGrid& cols, BGrid& rows, size_t& lds_small, size_t& lds_cols,
                    size_t& lds_rows);
 int64_t b_sketch_work_elems(int dtype, int64_t m, int64_t N);  // Y entries (0 for the small FFT)
-void b_plan_gram(int bulk_dtype, BSys& s, BGrid& gram, BGrid& gram_red);
+// returns the rows-per-thread class (0..3: m <= 64, 128, 256, 512)
+int b_plan_gram(int bulk_dtype, BSys& s, BGrid& gram, BGrid& gram_red);
 void b_plan_wide(int dtype, bool aligned, BSys& s, BGrid& adj, BGrid& sum, BGrid& fwd);
 bool b_aligned16(const void* p, int64_t ld, int dtype);
 hipError_t launch_b_prep(const BLaunch& fill, const BLaunch& map, hipStream_t st);
@@ -281,8 +282,9 @@ hipError_t launch_b_chol_step(bool cplx, const BLaunch& L, int k, hipStream_t st
 hipError_t launch_b_rdiag(bool cplx, const BLaunch& L, hipStream_t st);
 hipError_t launch_b_inv_diag(bool cplx, const BLaunch& L, hipStream_t st);
 hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int d, hipStream_t st);
-// the fused pass q = A (A* p) on the bulk copy (aligned: 16-byte rows)
-hipError_t launch_b_gram(int dtype, bool aligned, const BLaunch& L, const BLaunch& red, hipStream_t st);
+// the fused pass q = A (A* p) on the bulk copy (16-byte aligned rows), one
+// launch per rows-per-thread class L[0..3], then the partial sums
+hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st);
 // FP64 passes on the problem data: w64 (or x) = A* u, u = y_outer (outer) or y;
 // fpart = A w64 in column chunks
 hipError_t launch_b_adj_wide(int dtype, bool aligned, const BLaunch& L, const BLaunch& sum, int use_y, int to_x,
