@@ -67,24 +67,29 @@ __device__ bool chol_tile(V* T, int valid, double* piv) {
   return ok;
 }
 
-// In place: B <- R^{-*} B (forward substitution on R* X = B, R upper).
+// In place: B1 <- R^{-*} B1 and (if B2) B2 <- R^{-*} B2 (forward substitution
+// on R* X = B, R upper).  One wave; lane j takes column j of B1 (lanes 0-31)
+// or of B2 (lanes 32-63) in registers, so the 32 dependent row steps need no
+// barrier: every lane reads the same entries of R (LDS broadcast).
 template <typename V>
-__device__ void solve_tile(const V* R, V* B) {
-  for (int q = 0; q < CB; ++q) {
-    const double inv = 1.0 / vre(R[q + q * LDC]);
-    // row q is final after dividing by r_qq; rows below subtract its multiple
-    for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-      const int r = e % CB, j = e / CB;
-      if (r > q) {
-        const V xq = vscale(B[q + j * LDC], inv);
-        B[r + j * LDC] = vsub(B[r + j * LDC], vcmul(R[q + r * LDC], xq));
+__device__ void solve_tiles(const V* R, V* B1, V* B2) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    V* B = lane < CB ? B1 : B2;
+    const int j = lane & (CB - 1);
+    if (B) {
+      V x[CB];
+#pragma unroll
+      for (int r = 0; r < CB; ++r) x[r] = B[r + j * LDC];
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        x[q] = vscale(x[q], 1.0 / vre(R[q + q * LDC]));
+#pragma unroll
+        for (int r = q + 1; r < CB; ++r) x[r] = vsub(x[r], vcmul(R[q + r * LDC], x[q]));
       }
+#pragma unroll
+      for (int r = 0; r < CB; ++r) B[r + j * LDC] = x[r];
     }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e % CB, j = e / CB;
-    B[r + j * LDC] = vscale(B[r + j * LDC], 1.0 / vre(R[r + r * LDC]));
   }
   __syncthreads();
 }
@@ -137,7 +142,7 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
     }
     tile_in(T1, G, ldg, m, k, bj);
     __syncthreads();
-    solve_tile(Rkk, T1);
+    solve_tiles(Rkk, T1, (V*)nullptr);
     for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
       const int r = e % CB, c = e / CB;
       const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)bj * CB + c;
@@ -155,8 +160,7 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
   tile_in(T1, G, ldg, m, k, bi);
   if (bj != bi) tile_in(T2, G, ldg, m, k, bj);
   __syncthreads();
-  solve_tile(Rkk, T1);
-  if (bj != bi) solve_tile(Rkk, T2);
+  solve_tiles(Rkk, T1, bj != bi ? T2 : (V*)nullptr);
   const V* Rj = bj != bi ? T2 : T1;
   for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
     const int r = e % CB, c = e / CB;
