@@ -153,7 +153,8 @@ int mn_profile(mn_handle h, int enable);
 int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* total_ms);
 
 /* Launch plans (autotuning).  A plan is one integer per kernel and shape:
- * "gram/<dtype>/<m>/<n>/0"   fused pass: workgroup count (low 16 bits; 256,
+ * "gram/<dtype>/<m>/<n>/<a>" fused pass (a = 1: single-precision data
+ *                            accumulated in FP64): workgroup count (low 16 bits; 256,
  *                            512 or 1024), strip width (bit 16 set: 16
  *                            bytes of a row per thread instead of 32) and
  *                            strip order (bit 17 set: workgroup g takes strips

@@ -61,6 +61,7 @@ struct mn_handle_s {
   std::map<std::string, float> plan_ms;
   hipEvent_t tev[2] = {};
   mn_handle parent = nullptr;  // lanes read and add plans through their parent
+  double kappa_hat = 1.0;      // max|R_ii| / min|R_ii| of the last factorisation
   void* host_stage = nullptr;  // pinned staging of the fused batched form
   size_t host_stage_bytes = 0;
 };
@@ -272,6 +273,7 @@ int run_qr(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t 
   ck(hipMemcpyAsync(h->host_diag, a.diag_out, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   ck(hipStreamSynchronize(h->stream));
   const double mx = h->host_diag[0], mn_ = h->host_diag[1], nonfin = h->host_diag[2];
+  h->kappa_hat = mn_ > 0.0 ? mx / mn_ : 1e300;
   if (nonfin != 0.0 || !std::isfinite(mx)) return MN_NONFINITE;
   // numerical rank test on the pivots: min |R_ii| >= sigma_min(R) and
   // max |R_ii| <= sigma_max(R), so a tiny ratio means a (nearly) singular
@@ -317,6 +319,7 @@ bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, in
   ck(hipMemcpyAsync(h->host_flag, bad, 4, hipMemcpyDeviceToHost, st));
   ck(hipStreamSynchronize(st));
   const double mx = h->host_diag[0], mn_ = h->host_diag[1], nonfin = h->host_diag[2];
+  h->kappa_hat = mn_ > 0.0 ? mx / mn_ : 1e300;
   if (*h->host_flag != 0 || nonfin != 0.0 || !std::isfinite(mx) || !(mn_ > 0.0)) return false;
   return mx <= 1e5 * mn_;
 }
@@ -336,6 +339,8 @@ struct SolveCtx {
   mn_opts o;
   void* R;  // m x m, bulk dtype
   void* X;  // inverted diagonal blocks, FP64
+  bool comp = false;  // compensated FP64 refinement passes (cond(A) u64 near eps)
+  bool wide_acc = false;  // single-precision bulk accumulated in FP64 (large cond(A))
 };
 
 void init_state(mn_handle h, PcgState* dst, const SolveCtx& c, int rule, double eps, int max_iter) {
@@ -419,6 +424,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
       ga.narrow = (pl >> 16) & 1;
       ga.interleave = (pl >> 17) & 1;
       ga.wide_wg = (pl >> 18) & 1;
+      ga.wide_acc = c.wide_acc;
       ck(launch_gram(c.bulk, ga, h->stream));
     };
     std::vector<int> cands;
@@ -426,7 +432,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
       for (int il : {0, 0x20000})
         for (int nw : {0, 0x10000})
           for (int wg : {512, 256, 1024}) cands.push_back(wg | nw | il | ww);
-    gram_plan = plan_get(h, c.o, plan_key("gram", c.bulk, c.m, c.n, 0), cands, run);
+    gram_plan = plan_get(h, c.o, plan_key("gram", c.bulk, c.m, c.n, c.wide_acc ? 1 : 0), cands, run);
   }
   int enqueued = 0;
   while (true) {
@@ -445,6 +451,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
         ga.narrow = (gram_plan >> 16) & 1;
         ga.interleave = (gram_plan >> 17) & 1;
         ga.wide_wg = (gram_plan >> 18) & 1;
+        ga.wide_acc = c.wide_acc;
         std::tie(ga.ev_begin, ga.ev_end) = prof_pair(h, K_GRAM);
         ck(launch_gram(c.bulk, ga, h->stream));
         CgStep a{};
@@ -474,7 +481,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
       aa.part = v.part;
       aa.flag = flag;
       std::tie(aa.ev_begin, aa.ev_end) = prof_pair(h, K_ADJ);
-      ck(launch_gemv_adj(c.bulk, false, aa, h->stream));
+      ck(launch_gemv_adj(c.bulk, c.wide_acc || !is_single(c.bulk), aa, h->stream));
       FwdArgs fa{};
       fa.A = c.Ab;
       fa.lda = c.ldab;
@@ -486,7 +493,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
       int chunks = 1;
       fa.chunks_out = &chunks;
       std::tie(fa.ev_begin, fa.ev_end) = prof_pair(h, K_FWD);
-      ck(launch_gemv_fwd(c.bulk, false, fa, h->stream));
+      ck(launch_gemv_fwd(c.bulk, c.wide_acc || !is_single(c.bulk), fa, h->stream));
       CgStep a{};
       a.X = c.X;
       a.m = c.m;
@@ -523,9 +530,8 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
   v.r[1] = ws(h, "r1", m * W);
   v.p = ws(h, "p", m * W);
   v.s = ws(h, "s", m * W);
-  const int64_t bes = is_single(c.bulk) ? W / 2 : W;  // bulk compute element size
-  v.w = ws(h, "w", (size_t)(n * bes + 64));
-  v.part = ws(h, "adj_part", (size_t)(adj_part_elems(m, n) * W + 64));
+  v.w = ws(h, "w", (size_t)(n * W + 64));  // A* p in FP64
+  v.part = ws(h, "adj_part", (size_t)(std::max(adj_part_elems(m, n), adj_dd_part_elems(m, n)) * W + 64));
   v.qpart = ws(h, "qpart", (size_t)((kMaxChunks > kGramMaxWg ? kMaxChunks : kGramMaxWg) * m * W));
   v.q = ws(h, "q", kGramParts * m * W);
   ev_record(h, 3);
@@ -551,6 +557,7 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
     // precision on the bulk copy, y_outer += dy, until the FP64 certificate
     // meets eps.
     void* y_outer = ws(h, "y_outer", m * W);
+    void* qdd = ws(h, "q_dd", m * W);
     void* w64 = ws(h, "w64", (size_t)(n * W + 64));
     ck(launch_zero(is_complex(c.dtype), y_outer, m, h->stream));
     const double inner_eps = std::pow(10.0, -(double)c.o.inner_digits);
@@ -564,7 +571,6 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
       aa.u = y_outer;
       aa.w = w64;
       aa.part = v.part;
-      ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
       FwdArgs fa{};
       fa.A = c.A;
       fa.lda = c.lda;
@@ -574,8 +580,17 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
       fa.qpart = v.qpart;
       int chunks = 1;
       fa.chunks_out = &chunks;
-      ck(launch_gemv_fwd(c.dtype, true, fa, h->stream));
-      cg_start(c, v, b, v.qpart, chunks, y_outer);
+      if (c.comp) {
+        // b - A (A* y_outer) with double-double accumulation: the sums cancel
+        // to about cond(A) times below their terms
+        ck(launch_gemv_adj_dd(c.dtype, aa, h->stream));
+        ck(launch_gemv_fwd_dd(c.dtype, fa, qdd, h->stream));
+        cg_start(c, v, b, qdd, 1, y_outer);
+      } else {
+        ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
+        ck(launch_gemv_fwd(c.dtype, true, fa, h->stream));
+        cg_start(c, v, b, v.qpart, chunks, y_outer);
+      }
       read_state(h, v.st);
       if (h->host_state->outer_done) break;
       cg_loop(c, v, b, c.o.max_iter);
@@ -590,7 +605,8 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
     aa.u = y_outer;
     aa.w = x;
     aa.part = v.part;
-    ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
+    if (c.comp) ck(launch_gemv_adj_dd(c.dtype, aa, h->stream));
+    else ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
     ev_record(h, 5);
     read_state(h, v.st);
   }
@@ -968,6 +984,13 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     }
   }
   ev_record(h, 2);
+  // compensated refinement passes when the rounding of plain FP64 sums,
+  // about cond(A) u64 relative, is within a hundredth of eps
+  c.comp = c.mixed && h->kappa_hat * 1.11e-16 > eps / 100.0;
+  // single-precision sums over n terms carry about 1e-6 relative error; with
+  // cond(A) above 3e4 the inner solves would stop contracting, so the bulk
+  // passes then accumulate in FP64 (same bytes read)
+  c.wide_acc = is_single(c.bulk) && h->kappa_hat > 3e4;
   const int64_t ldxi = rinv_ld(m);
   c.X = ws(h, "Xinv", (size_t)(ldxi * ldxi * wide_size(dtype)));
   const bool block = o.block == 2 || (o.block == 0 && nrhs >= 2 && c.mixed);

@@ -494,9 +494,9 @@ bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda) {
 hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st) {
   switch (dtype) {
     case 0: return gram_impl<cd, cd, cd>(a, st);
-    case 1: return gram_impl<cf, cf, cd>(a, st);
+    case 1: return a.wide_acc ? gram_impl<cf, cd, cd>(a, st) : gram_impl<cf, cf, cd>(a, st);
     case 2: return gram_impl<double, double, double>(a, st);
-    case 3: return gram_impl<float, float, double>(a, st);
+    case 3: return a.wide_acc ? gram_impl<float, double, double>(a, st) : gram_impl<float, float, double>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -715,6 +715,248 @@ hipError_t launch_b_fwd_wide(int dtype, bool aligned, const BLaunch& L, hipStrea
     case 1: return b_fwd_go<cf, cd>(aligned, L, st);
     case 2: return b_fwd_go<double, double>(aligned, L, st);
     case 3: return b_fwd_go<float, double>(aligned, L, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------- compensated FP64 passes ----------------------------
+// For the refinement residual b - A (A* y) and x = A* y when cond(A) u64
+// approaches eps (cancellation in the sums is then of order cond(A)): every
+// dot product is accumulated in double-double (Ogita, Rump and Oishi 2005:
+// TwoProd by FMA, TwoSum by Knuth's six additions), partial sums are kept as
+// (hi, lo) pairs and folded with TwoSum, and each result is rounded once.
+// Floating-point contraction is off inside these helpers: the error-free
+// transformations need the products and sums exactly as written.
+namespace {
+
+struct ddv {
+  double hi, lo;
+};
+
+__device__ inline void dd_add(ddv& a, double x) {
+#pragma clang fp contract(off)
+  const double s = a.hi + x;
+  const double z = s - a.hi;
+  const double e = (a.hi - (s - z)) + (x - z);
+  a.hi = s;
+  a.lo += e;
+}
+__device__ inline void dd_fma(ddv& a, double x, double y) {
+#pragma clang fp contract(off)
+  const double p = x * y;
+  const double ep = fma(x, y, -p);
+  dd_add(a, p);
+  a.lo += ep;
+}
+__device__ inline void dd_merge(ddv& a, const ddv& b) {
+#pragma clang fp contract(off)
+  dd_add(a, b.hi);
+  a.lo += b.lo;
+}
+__device__ inline double dd_round(const ddv& a) {
+#pragma clang fp contract(off)
+  return a.hi + a.lo;
+}
+__device__ inline ddv dd_shfl_xor(const ddv& a, int off) {
+  return ddv{__shfl_xor(a.hi, off, 64), __shfl_xor(a.lo, off, 64)};
+}
+
+// complex or real accumulator: 2 (re, im) or 1 double-double
+template <bool CPLX> struct Acc2 {
+  ddv c[CPLX ? 2 : 1];
+};
+
+// acc += conj(a) u (adjoint) or a w (forward), a promoted to FP64
+template <bool CONJ, typename V, typename W>
+__device__ inline void acc_mac(Acc2<VT<W>::cplx>& acc, const V& a, const W& u) {
+  if constexpr (VT<W>::cplx) {
+    const double ar = (double)vre(a), ai = (double)vim(a), ur = vre(u), ui = vim(u);
+    dd_fma(acc.c[0], ar, ur);
+    dd_fma(acc.c[0], CONJ ? ai : -ai, ui);
+    dd_fma(acc.c[1], ar, ui);
+    dd_fma(acc.c[1], CONJ ? -ai : ai, ur);
+  } else {
+    dd_fma(acc.c[0], (double)vre(a), (double)vre(u));
+  }
+}
+
+// w (hi/lo slab partials) = A* u.  grid (ceil(n / 256), RS), 256 threads.
+template <typename V, typename W>
+__global__ void __launch_bounds__(256) k_adj_dd(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                const W* __restrict__ u, int64_t rows_per_slab, W* __restrict__ ph,
+                                                W* __restrict__ pl) {
+  constexpr bool C = VT<W>::cplx;
+  __shared__ W su[1024];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_slab;
+  const int64_t r1 = (r0 + rows_per_slab) < m ? (r0 + rows_per_slab) : m;
+  Acc2<C> acc{};
+  for (int64_t rb = r0; rb < r1; rb += 1024) {
+    const int64_t rn = (r1 - rb) < 1024 ? (r1 - rb) : 1024;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < rn; t += 256) su[t] = u[rb + t];
+    __syncthreads();
+    if (j < n) {
+      const V* a = A + rb * lda + j;
+      int64_t i = 0;
+      for (; i + 4 <= rn; i += 4) {
+        V x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = a[(i + k) * lda];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc_mac<true>(acc, x[k], su[i + k]);
+      }
+      for (; i < rn; ++i) acc_mac<true>(acc, a[i * lda], su[i]);
+    }
+  }
+  if (j >= n) return;
+  const int64_t o = (int64_t)blockIdx.y * n + j;
+  if constexpr (C) {
+    ph[o] = W{acc.c[0].hi, acc.c[1].hi};
+    pl[o] = W{acc.c[0].lo, acc.c[1].lo};
+  } else {
+    ph[o] = acc.c[0].hi;
+    pl[o] = acc.c[0].lo;
+  }
+}
+
+// w[j] = sum over slabs of (hi + lo), compensated, rounded once.
+template <typename W>
+__global__ void __launch_bounds__(256) k_sum_dd(const W* __restrict__ ph, const W* __restrict__ pl, int rs, int64_t n,
+                                                W* __restrict__ w) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  ddv re{0.0, 0.0}, im{0.0, 0.0};
+  for (int k = 0; k < rs; ++k) {
+    const W h = ph[(int64_t)k * n + j], l = pl[(int64_t)k * n + j];
+    dd_merge(re, ddv{vre(h), vre(l)});
+    if constexpr (VT<W>::cplx) dd_merge(im, ddv{vim(h), vim(l)});
+  }
+  w[j] = vmake<W>(dd_round(re), dd_round(im));
+}
+
+// (hi, lo) chunk partials of q = A w.  grid (CS, ceil(m / RB)), 256 threads.
+template <typename V, typename W, int RB>
+__global__ void __launch_bounds__(256) k_fwd_dd(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                const W* __restrict__ w, int64_t chunk, W* __restrict__ qh,
+                                                W* __restrict__ ql) {
+  constexpr bool C = VT<W>::cplx;
+  constexpr int NC = C ? 2 : 1;
+  __shared__ ddv red[RB][NC][4];
+  const int64_t i0 = (int64_t)blockIdx.y * RB;
+  const int64_t c0 = (int64_t)blockIdx.x * chunk;
+  const int64_t c1 = (c0 + chunk) < n ? (c0 + chunk) : n;
+  int64_t rows = m - i0;
+  if (rows > RB) rows = RB;
+  Acc2<C> acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = Acc2<C>{};
+  for (int64_t j = c0 + threadIdx.x; j < c1; j += 256) {
+    const W wj = w[j];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (r < rows) acc_mac<false>(acc[r], A[(i0 + r) * lda + j], wj);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      ddv v = acc[r].c[c];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) dd_merge(v, dd_shfl_xor(v, off));
+      if (lane == 0) red[r][c][wv] = v;
+    }
+  __syncthreads();
+  if (threadIdx.x < RB && threadIdx.x < rows) {
+    const int r = threadIdx.x;
+    ddv v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      v[c] = red[r][c][0];
+      for (int k = 1; k < 4; ++k) dd_merge(v[c], red[r][c][k]);
+    }
+    const int64_t o = (int64_t)blockIdx.x * m + i0 + r;
+    if constexpr (C) {
+      qh[o] = W{v[0].hi, v[1].hi};
+      ql[o] = W{v[0].lo, v[1].lo};
+    } else {
+      qh[o] = v[0].hi;
+      ql[o] = v[0].lo;
+    }
+  }
+}
+
+template <typename W>
+__global__ void __launch_bounds__(256) k_fold_dd(const W* __restrict__ qh, const W* __restrict__ ql, int cs, int64_t m,
+                                                 W* __restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  ddv re{0.0, 0.0}, im{0.0, 0.0};
+  for (int k = 0; k < cs; ++k) {
+    const W h = qh[(int64_t)k * m + i], l = ql[(int64_t)k * m + i];
+    dd_merge(re, ddv{vre(h), vre(l)});
+    if constexpr (VT<W>::cplx) dd_merge(im, ddv{vim(h), vim(l)});
+  }
+  q[i] = vmake<W>(dd_round(re), dd_round(im));
+}
+
+template <typename V, typename W>
+hipError_t adj_dd_impl(const AdjArgs& a, hipStream_t st) {
+  const int64_t nb = ceil_div(a.n, (int64_t)256);
+  const int64_t rs = slabs_for(a.m, a.n, 1);
+  const int64_t rps = ceil_div(a.m, rs);
+  W* ph = reinterpret_cast<W*>(a.part);
+  W* pl = ph + rs * a.n;
+  hipLaunchKernelGGL((k_adj_dd<V, W>), dim3((unsigned)nb, (unsigned)rs), dim3(256), 0, st,
+                     reinterpret_cast<const V*>(a.A), a.lda, a.m, a.n, reinterpret_cast<const W*>(a.u), rps, ph, pl);
+  hipLaunchKernelGGL((k_sum_dd<W>), dim3((unsigned)ceil_div(a.n, 256)), dim3(256), 0, st, ph, pl, (int)rs, a.n,
+                     reinterpret_cast<W*>(a.w));
+  return hipGetLastError();
+}
+
+template <typename V, typename W>
+hipError_t fwd_dd_impl(const FwdArgs& a, void* q, hipStream_t st) {
+  constexpr int RB = 8;
+  const int64_t rb = ceil_div(a.m, RB);
+  int64_t cs = ceil_div(2048, rb);
+  if (cs > ceil_div(a.n, 512)) cs = ceil_div(a.n, 512);
+  if (cs < 1) cs = 1;
+  if (cs > kMaxChunks / 2) cs = kMaxChunks / 2;
+  int64_t chunk = ceil_div(a.n, cs);
+  chunk = ceil_div(chunk, 256) * 256;
+  cs = ceil_div(a.n, chunk);
+  W* qh = reinterpret_cast<W*>(a.qpart);
+  W* ql = qh + cs * a.m;
+  hipLaunchKernelGGL((k_fwd_dd<V, W, RB>), dim3((unsigned)cs, (unsigned)rb), dim3(256), 0, st,
+                     reinterpret_cast<const V*>(a.A), a.lda, a.m, a.n, reinterpret_cast<const W*>(a.w), chunk, qh,
+                     ql);
+  hipLaunchKernelGGL((k_fold_dd<W>), dim3((unsigned)ceil_div(a.m, 256)), dim3(256), 0, st, qh, ql, (int)cs, a.m,
+                     reinterpret_cast<W*>(q));
+  if (a.chunks_out) *a.chunks_out = 1;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t adj_dd_part_elems(int64_t m, int64_t n) { return 2 * slabs_for(m, n, 1) * n; }
+
+hipError_t launch_gemv_adj_dd(int dtype, const AdjArgs& a, hipStream_t st) {
+  switch (dtype) {
+    case 0: return adj_dd_impl<cd, cd>(a, st);
+    case 1: return adj_dd_impl<cf, cd>(a, st);
+    case 2: return adj_dd_impl<double, double>(a, st);
+    case 3: return adj_dd_impl<float, double>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemv_fwd_dd(int dtype, const FwdArgs& a, void* q, hipStream_t st) {
+  switch (dtype) {
+    case 0: return fwd_dd_impl<cd, cd>(a, q, st);
+    case 1: return fwd_dd_impl<cf, cd>(a, q, st);
+    case 2: return fwd_dd_impl<double, double>(a, q, st);
+    case 3: return fwd_dd_impl<float, double>(a, q, st);
   }
   return hipErrorInvalidValue;
 }

@@ -81,6 +81,13 @@ struct FwdArgs {
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
 };
 hipError_t launch_gemv_fwd(int dtype, bool wide, const FwdArgs& a, hipStream_t st);
+// Compensated (double-double accumulated) FP64 passes for the refinement:
+// w = A* u (a.part holds adj_dd_part_elems(m, n) FP64 entries) and
+// q = A w (a.qpart holds kMaxChunks * m entries; q receives the m sums and
+// *a.chunks_out is set to 1).
+int64_t adj_dd_part_elems(int64_t m, int64_t n);
+hipError_t launch_gemv_adj_dd(int dtype, const AdjArgs& a, hipStream_t st);
+hipError_t launch_gemv_fwd_dd(int dtype, const FwdArgs& a, void* q, hipStream_t st);
 
 // Fused q = A (A* p) in one read of A (m <= kGramMaxRows, 16-byte aligned rows).
 constexpr int kGramMaxRows = 512;
@@ -98,6 +105,7 @@ struct GramArgs {
   int narrow = 0;    // plan: strips of 16 bytes per thread and row instead of 32
   int interleave = 0;  // plan: workgroup g takes strips g, g + G, ... instead of a run
   int wide_wg = 0;     // plan: 1024 threads per workgroup (half the rows per thread)
+  int wide_acc = 0;    // single-precision data: accumulate in FP64
 };
 bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda);
 hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st);

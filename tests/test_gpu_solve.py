@@ -364,3 +364,23 @@ def test_batched_fused_mixed_c128_and_fallback():
     for (A, b), x, info in zip(systems, xs, infos):
         assert info["status"] == 0
         assert rel(to_np(x), oracle.refined_minnorm(A, b)) <= 1e-9
+
+
+@pytest.mark.slow
+def test_mixed_kappa_1e6_512x65536():
+    """complex128 data, complex64 bulk, cond 1e6 at 512 x 65536: the FP64
+    refinement still certifies eps = 1e-10 against the longdouble-refined
+    oracle (the rounding of the FP64 residual grows with m and n)."""
+    import torch
+    from paper_0905_4745_amd import api
+    say("mixed c128/c64 kappa 1e6 512x65536")
+    A, b, _ = synth.make_svd(512, 65536, 1e6, seed=77)
+    N = 65536
+    d, idx = synth.draw_srft(N, 2048, seed=77)
+    At = to_dev(A)
+    x, info = api.minnorm_solve(At, to_dev(b), 1e-10, d, idx, N, A_lo=At.to(torch.complex64), raise_on_status=False)
+    p = oracle.refined_minnorm(A, b)
+    say(f"  status {info['status']} err {rel(to_np(x), p):.2e} iters {info['iters']} refine {info['refine_steps']} "
+        f"cert {info['cert_rel']:.2e} rho0 {info['rho0']:.2e} rho {info['rho']:.2e} xi {info['xi']:.2e}")
+    assert info["status"] == 0
+    assert rel(to_np(x), p) <= 1e-10
