@@ -163,11 +163,15 @@ def minnorm_solve(A, b, eps: float, d, idx, N: int, A_lo=None, opts: SolveOption
     l = it.numel()
     if x is None:
         x = torch.empty((nrhs, n), dtype=wide, device=A.device)
+    x2 = x.reshape(1, -1) if x.dim() == 1 else x
+    if (x2.dtype != wide or not x2.is_cuda or x2.shape != (nrhs, n)
+            or (x2.stride(1) != 1 and n > 1)):
+        raise ValueError(f"x must be a device {wide} tensor of shape ({nrhs}, {n}) with unit column stride")
     info = L.MnInfo()
     o = (opts or SolveOptions()).to_c()
     st = L.load().minnorm_solve(_handle(A.device), code, m, n, _ptr(A), _ld(A, 0, n), _ptr(A_lo),
                                 _ld(A_lo, 0, n) if A_lo is not None else 0, _ptr(b2), _ld(b2, 0, m), nrhs,
-                                float(eps), int(N), l, _ptr(dt), _ptr(it), C.byref(o), _ptr(x), x.stride(0),
+                                float(eps), int(N), l, _ptr(dt), _ptr(it), C.byref(o), _ptr(x2), _ld(x2, 0, n),
                                 C.byref(info))
     if st != 0 and raise_on_status:
         raise MinnormError("minnorm_solve", st)

@@ -20,3 +20,4 @@ from .gen import (  # noqa: F401
     make_batch,
     CONFIGS,
 )
+from .device import make_svd_device  # noqa: F401
