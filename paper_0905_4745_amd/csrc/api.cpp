@@ -312,7 +312,8 @@ bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, in
   if (splits > 1) ck(launch_gram_fold(cplx, Cp, (int)splits, ldc, m, G, m, st));
   int32_t* bad = (int32_t*)ws(h, "chol_bad", 16);
   ck(launch_fill0(bad, 16, st));
-  ck(launch_chol(cplx, G, m, m, R64, m, bad, st));
+  void* Yd = ws(h, "chol_yd", (size_t)(chol_scratch_elems(m) * W));
+  ck(launch_chol(cplx, G, m, m, R64, m, Yd, bad, st));
   double* dr = (double*)ws(h, "qr_diag", 64);
   ck(launch_rdiag_range(cplx ? MN_C128 : MN_F64, R64, m, m, dr, st));
   ck(hipMemcpyAsync(h->host_diag, dr, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1151,17 +1152,21 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     // 16-byte vectors
     const int64_t pad_ld = b_aligned16(q.Ab, q.ldab, bulk) ? 0 : rup(n[i], std::max<int64_t>(16 / be, 1));
     wbytes[i] = a256(pad_ld * mm * be) + a256(N[i] * 4) + a256(l[i] * mm * be) + a256(b_sketch_work_elems(bulk, mm, N[i]) * ces) +
-                2 * a256(mm * mm * W) + a256(q.ldx * q.ldx * W) + 6 * a256(mm * W) + a256(kGramParts * mm * W) +
+                2 * a256(mm * mm * W) + a256(q.ldx * q.ldx * W) + a256(chol_scratch_elems(mm) * W) +
+                6 * a256(mm * W) + a256(kGramParts * mm * W) +
                 a256((int64_t)q.gram_G * mm * W) + a256(n[i] * W) + a256((int64_t)q.adj_slabs * n[i] * W) +
                 a256((int64_t)q.fwd_chunks * mm * W);
   }
+  // chol[0]: the first diagonal tiles; chol[k + 1]: block step k
   std::vector<GridTable> chol((size_t)maxnbk), trtri((size_t)maxnbk);
   for (int k = 0; k < maxnbk; ++k) {
     chol[k].init(batch);
     trtri[k].init(batch);
     for (int i = 0; i < batch; ++i) {
       const int nb = (int)cdiv(m[i], 32);
-      if (k < nb) chol[k].g[i] = BGrid{0, (nb - k) + (nb - k - 1) * (nb - k) / 2, 1, 1};
+      const int ks = k - 1;
+      if (k == 0) chol[k].g[i] = BGrid{0, 1, 1, 1};
+      else if (ks + 1 < nb) chol[k].g[i] = BGrid{0, (nb - ks - 1) + (nb - ks - 1) * (nb - ks) / 2, 1, 1};
       else chol[k].g[i] = BGrid{0, 0, 1, 1};
       if (k >= 1 && k < nb) trtri[k].g[i] = BGrid{0, nb - k, 1, 1};
       else trtri[k].g[i] = BGrid{0, 0, 1, 1};
@@ -1223,6 +1228,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     q.G = take(mm * mm * W);
     q.R = take(mm * mm * W);
     q.X = take(q.ldx * q.ldx * W);
+    q.Yd = take(chol_scratch_elems(mm) * W);
     q.y = take(mm * W);
     q.r0 = take(mm * W);
     q.r1 = take(mm * W);
@@ -1285,7 +1291,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   // Steps 1-2: sketch, Gram matrix, Cholesky, diagonal range
   ck(launch_b_sketch(bulk, L(sk_small), L(sk_cols), L(sk_rows), lds_small, lds_cols, lds_rows, st));
   ck(launch_b_gram_s(bulk, L(gram_s), st));
-  for (int k = 0; k < maxnbk; ++k) ck(launch_b_chol_step(cplx, L(chol[k]), k, st));
+  for (int k = 0; k < maxnbk; ++k) ck(launch_b_chol_step(cplx, L(chol[k]), k - 1, st));
   ck(launch_b_rdiag(cplx, L(rdiag), st));
   std::vector<int32_t> hflags((size_t)batch * 4);
   std::vector<double> hdiag((size_t)batch * 4);

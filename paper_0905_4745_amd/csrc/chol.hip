@@ -94,21 +94,96 @@ __device__ void solve_tiles(const V* R, V* B1, V* B2) {
   __syncthreads();
 }
 
+// T <- A^* B for 32 x 32 tiles in LDS (C may alias neither)
+template <typename V>
+__device__ void tile_ahb(const V* A, const V* B, V* C) {
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    const int r = e % CB, c = e / CB;
+    V acc = vzero<V>();
+#pragma unroll 8
+    for (int q = 0; q < CB; ++q) acc = vcfma(A[q + r * LDC], B[q + c * LDC], acc);
+    C[r + c * LDC] = acc;
+  }
+}
+// T <- Y B for tiles in LDS (Y = R_kk^{-*}, lower triangular)
+template <typename V>
+__device__ void tile_ab_lower(const V* Y, const V* B, V* C) {
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    const int r = e % CB, c = e / CB;
+    V acc = vzero<V>();
+    for (int q = 0; q <= r; ++q) acc = vfma(Y[r + q * LDC], B[q + c * LDC], acc);
+    C[r + c * LDC] = acc;
+  }
+}
+
+// Factor the (updated) diagonal tile held in T for block k: R_kk -> R,
+// Y_kk = R_kk^{-*} -> Yd[k] (32 x 32, column-major, ld 32).
+template <typename V>
+__device__ void finish_diag(V* T, V* Y, double* piv, int k, int64_t m, V* R, int64_t ldr, V* Yd, int32_t* bad) {
+  const int valid = (int)((m - (int64_t)k * CB) < CB ? (m - (int64_t)k * CB) : CB);
+  const bool ok = chol_tile(T, valid, piv);
+  if (!ok && threadIdx.x == 0) bad[0] = 1;
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    const int r = e % CB, c = e / CB;
+    Y[r + c * LDC] = (r == c) ? vmake<V>(1.0, 0.0) : vzero<V>();
+  }
+  __syncthreads();
+  solve_tiles(T, Y, (V*)nullptr);  // Y = R_kk^{-*}
+  V* yd = Yd + (int64_t)k * CB * CB;
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    const int r = e % CB, c = e / CB;
+    const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)k * CB + c;
+    if (gr < m && gc < m) R[gr + gc * ldr] = T[r + c * LDC];
+    yd[e] = Y[r + c * LDC];
+  }
+  // the strictly lower part of R's block column k
+  const int64_t below = m - (int64_t)(k + 1) * CB;
+  for (int64_t e = threadIdx.x; e < below * CB; e += blockDim.x) {
+    const int64_t r = (int64_t)(k + 1) * CB + e % below;
+    const int64_t c = (int64_t)k * CB + e / below;
+    if (c < m) R[r + c * ldr] = vzero<V>();
+  }
+}
+
+// Block step 0's diagonal tile (one workgroup).
+template <typename V>
+__device__ __forceinline__ void k_chol_diag0_body(const Bk bk, V* __restrict__ G, int64_t ldg, int64_t m,
+                                                   V* __restrict__ R, int64_t ldr, V* __restrict__ Yd,
+                                                   int32_t* __restrict__ bad) {
+  (void)bk;
+  __shared__ V T[CB * LDC];
+  __shared__ V Y[CB * LDC];
+  __shared__ double piv[CB];
+  tile_in(T, G, ldg, m, 0, 0);
+  __syncthreads();
+  finish_diag(T, Y, piv, 0, m, R, ldr, Yd, bad);
+}
+template <typename V>
+__global__ void __launch_bounds__(256) k_chol_diag0(V* __restrict__ G, int64_t ldg, int64_t m, V* __restrict__ R,
+                                                    int64_t ldr, V* __restrict__ Yd, int32_t* __restrict__ bad) {
+  k_chol_diag0_body<V>(bk_hw(), G, ldg, m, R, ldr, Yd, bad);
+}
+
+// Block step k (R_kk and Y_kk = R_kk^{-*} known):
+//   tile (k, j), j > k:      R_kj = Y_kk G_kj                     -> R
+//   tile (i, j), k < i <= j: G_ij -= (Y_kk G_ki)^* (Y_kk G_kj); the workgroup
+//                            of (k+1, k+1) then factors it (R, Y of block k+1).
+// grid = (nbk - k - 1) + (nbk - k - 1)(nbk - k)/2 workgroups.
 template <typename V>
 __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G, int64_t ldg, int64_t m, int k, int nbk,
-                                                   V* __restrict__ R, int64_t ldr, int32_t* __restrict__ bad) {
-  __shared__ V Rkk[CB * LDC];
+                                                   V* __restrict__ R, int64_t ldr, V* __restrict__ Yd,
+                                                   int32_t* __restrict__ bad) {
+  __shared__ V Y[CB * LDC];
   __shared__ V T1[CB * LDC];
   __shared__ V T2[CB * LDC];
+  __shared__ V T3[CB * LDC];
   __shared__ double piv[CB];
-  // workgroup -> tile: first the nbk - k tiles of block row k, then the
-  // trailing upper tiles (i, j), k < i <= j, row by row
-  const int nrow = nbk - k;
+  const int nrow = nbk - k - 1;
   int bi, bj;
   int w = bk.x;
   if (w < nrow) {
     bi = k;
-    bj = k + w;
+    bj = k + 1 + w;
   } else {
     w -= nrow;
     bi = k + 1;
@@ -120,99 +195,117 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
     }
     bj = bi + w;
   }
-  const int valid = (int)((m - (int64_t)k * CB) < CB ? (m - (int64_t)k * CB) : CB);
-  tile_in(Rkk, G, ldg, m, k, k);
-  __syncthreads();
-  const bool ok = chol_tile(Rkk, valid, piv);
+  const V* yd = Yd + (int64_t)k * CB * CB;
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) Y[(e % CB) + (e / CB) * LDC] = yd[e];
   if (bi == k) {
-    if (bj == k) {
-      if (!ok && threadIdx.x == 0) bad[0] = 1;
-      for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-        const int r = e % CB, c = e / CB;
-        const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)k * CB + c;
-        if (gr < m && gc < m) R[gr + gc * ldr] = Rkk[r + c * LDC];
-      }
-      // zero the strictly lower part of R's block column k below the diagonal tile
-      for (int64_t e = threadIdx.x; e < (m - (int64_t)(k + 1) * CB) * CB; e += blockDim.x) {
-        const int64_t r = (int64_t)(k + 1) * CB + e % (m - (int64_t)(k + 1) * CB);
-        const int64_t c = (int64_t)k * CB + e / (m - (int64_t)(k + 1) * CB);
-        if (r < m && c < m) R[r + c * ldr] = vzero<V>();
-      }
-      return;
-    }
     tile_in(T1, G, ldg, m, k, bj);
     __syncthreads();
-    solve_tiles(Rkk, T1, (V*)nullptr);
+    tile_ab_lower(Y, T1, T2);  // R_kj
+    __syncthreads();
     for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
       const int r = e % CB, c = e / CB;
       const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)bj * CB + c;
-      if (gr < m && gc < m) R[gr + gc * ldr] = T1[r + c * LDC];
-    }
-    // R's strictly lower tile (bj, k) is zero
-    for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-      const int r = e % CB, c = e / CB;
-      const int64_t gr = (int64_t)bj * CB + r, gc = (int64_t)k * CB + c;
-      if (gr < m && gc < m) R[gr + gc * ldr] = vzero<V>();
+      if (gr < m && gc < m) R[gr + gc * ldr] = T2[r + c * LDC];
     }
     return;
   }
-  // trailing tile: R_ki and R_kj, then G_ij -= R_ki^* R_kj
+  // trailing tile: R_ki (T2), R_kj (T3), then G_ij -= R_ki^* R_kj
   tile_in(T1, G, ldg, m, k, bi);
-  if (bj != bi) tile_in(T2, G, ldg, m, k, bj);
   __syncthreads();
-  solve_tiles(Rkk, T1, bj != bi ? T2 : (V*)nullptr);
-  const V* Rj = bj != bi ? T2 : T1;
+  tile_ab_lower(Y, T1, T2);
+  __syncthreads();
+  if (bj != bi) {
+    tile_in(T1, G, ldg, m, k, bj);
+    __syncthreads();
+    tile_ab_lower(Y, T1, T3);
+    __syncthreads();
+  }
+  const V* Rj = bj != bi ? T3 : T2;
+  tile_in(T1, G, ldg, m, bi, bj);
+  __syncthreads();
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    const int r = e % CB, c = e / CB;
+    V acc = vzero<V>();
+#pragma unroll 8
+    for (int q = 0; q < CB; ++q) acc = vcfma(T2[q + r * LDC], Rj[q + c * LDC], acc);
+    T1[r + c * LDC] = vsub(T1[r + c * LDC], acc);
+  }
+  __syncthreads();
+  if (bi == k + 1 && bj == k + 1) {
+    // the next diagonal tile is final: factor it for block step k + 1
+    finish_diag(T1, T3, piv, k + 1, m, R, ldr, Yd, bad);
+    return;
+  }
   for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
     const int r = e % CB, c = e / CB;
     const int64_t gr = (int64_t)bi * CB + r, gc = (int64_t)bj * CB + c;
-    if (gr >= m || gc >= m || gr > gc) continue;
-    V acc = vzero<V>();
-    for (int q = 0; q < CB; ++q) acc = vcfma(T1[q + r * LDC], Rj[q + c * LDC], acc);
-    G[gr + gc * ldg] = vsub(G[gr + gc * ldg], acc);
+    if (gr < m && gc < m && gr <= gc) G[gr + gc * ldg] = T1[r + c * LDC];
   }
 }
 template <typename V>
 __global__ void __launch_bounds__(256) k_chol_step(V* __restrict__ G, int64_t ldg, int64_t m, int k, int nbk,
-                                                   V* __restrict__ R, int64_t ldr, int32_t* __restrict__ bad) {
-  k_chol_step_body<V>(bk_hw(), G, ldg, m, k, nbk, R, ldr, bad);
+                                                   V* __restrict__ R, int64_t ldr, V* __restrict__ Yd,
+                                                   int32_t* __restrict__ bad) {
+  k_chol_step_body<V>(bk_hw(), G, ldg, m, k, nbk, R, ldr, Yd, bad);
 }
 
 template <typename V>
-hipError_t chol_impl(void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, int32_t* bad, hipStream_t st) {
+hipError_t chol_impl(void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, int32_t* bad, hipStream_t st) {
   const int nbk = (int)ceil_div(m, CB);
-  for (int k = 0; k < nbk; ++k) {
-    const int nrow = nbk - k;
+  hipLaunchKernelGGL((k_chol_diag0<V>), dim3(1), dim3(256), 0, st, reinterpret_cast<V*>(G), ldg, m,
+                     reinterpret_cast<V*>(R), ldr, reinterpret_cast<V*>(Yd), bad);
+  for (int k = 0; k + 1 < nbk; ++k) {
+    const int nrow = nbk - k - 1;
     const int ntrail = (nbk - k - 1) * (nbk - k) / 2;
     hipLaunchKernelGGL((k_chol_step<V>), dim3((unsigned)(nrow + ntrail)), dim3(256), 0, st, reinterpret_cast<V*>(G),
-                       ldg, m, k, nbk, reinterpret_cast<V*>(R), ldr, bad);
+                       ldg, m, k, nbk, reinterpret_cast<V*>(R), ldr, reinterpret_cast<V*>(Yd), bad);
   }
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, int32_t* bad,
+int64_t chol_scratch_elems(int64_t m) { return ceil_div(m, CB) * CB * CB; }
+
+hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, int32_t* bad,
                        hipStream_t st) {
   if (m < 1 || ldg < m || ldr < m) return hipErrorInvalidValue;
-  return cplx ? chol_impl<cd>(G, ldg, m, R, ldr, bad, st) : chol_impl<double>(G, ldg, m, R, ldr, bad, st);
+  return cplx ? chol_impl<cd>(G, ldg, m, R, ldr, Yd, bad, st) : chol_impl<double>(G, ldg, m, R, ldr, Yd, bad, st);
 }
 
 namespace {
+template <typename V>
+__global__ void __launch_bounds__(256) kb_chol_diag0(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                     int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_chol_diag0_body<V>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<V*>(s.G), s.m, s.m,
+                       reinterpret_cast<V*>(s.R), s.m, reinterpret_cast<V*>(s.Yd), s.flags + 1);
+}
 template <typename V>
 __global__ void __launch_bounds__(256) kb_chol_step(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
                                                     int nsys, int k) {
   const int i = bgrid_find(grid, nsys, blockIdx.x);
   const BSys& s = sys[i];
   k_chol_step_body<V>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<V*>(s.G), s.m, s.m, k,
-                      (int)ceil_div(s.m, CB), reinterpret_cast<V*>(s.R), s.m, s.flags + 1);
+                      (int)ceil_div(s.m, CB), reinterpret_cast<V*>(s.R), s.m, reinterpret_cast<V*>(s.Yd),
+                      s.flags + 1);
 }
 }  // namespace
 
-// one block step of every system that has block column k (grid: as launch_chol's step k)
+// k < 0: every system's first diagonal tile (one workgroup each); k >= 0: block
+// step k of every system with more than k + 1 block columns
 hipError_t launch_b_chol_step(bool cplx, const BLaunch& L, int k, hipStream_t st) {
   if (L.total == 0) return hipSuccess;
-  if (cplx) hipLaunchKernelGGL(kb_chol_step<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, k);
-  else hipLaunchKernelGGL(kb_chol_step<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, k);
+  if (k < 0) {
+    if (cplx) hipLaunchKernelGGL(kb_chol_diag0<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
+    else hipLaunchKernelGGL(kb_chol_diag0<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys);
+  } else {
+    if (cplx)
+      hipLaunchKernelGGL(kb_chol_step<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, k);
+    else
+      hipLaunchKernelGGL(kb_chol_step<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, k);
+  }
   return hipGetLastError();
 }
 

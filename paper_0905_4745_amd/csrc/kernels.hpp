@@ -218,8 +218,11 @@ hipError_t launch_gram_s(int dtype, const void* S, int64_t lds, int64_t l, int64
 hipError_t launch_gram_fold(bool cplx, const double* Cp, int splits, int64_t ldc, int64_t m, void* G, int64_t ldg,
                             hipStream_t st);
 // R (FP64, upper, ld ldr) from G (upper part, overwritten by Schur
-// complements); bad[0] = 1 if a pivot is not positive and finite.
-hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, int32_t* bad, hipStream_t st);
+// complements); Yd: chol_scratch_elems(m) FP64 entries (the inverses of the
+// diagonal tiles); bad[0] = 1 if a pivot is not positive and finite.
+int64_t chol_scratch_elems(int64_t m);
+hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, int32_t* bad,
+                       hipStream_t st);
 
 // ---- batched systems -----------------------------------------------------------
 // Batched launch over several systems: entry i holds system i's first
@@ -258,6 +261,7 @@ struct BSys {
   void* R;         // m x m, wide
   void* X;         // ldx x ldx, wide
   int64_t ldx;
+  void* Yd;        // chol_scratch_elems(m), wide (inverses of R's diagonal tiles)
   double* diag;    // [max |R_ii|, min |R_ii|, nonfinite]
   void *y, *r0, *r1, *p, *s, *q, *qpart, *w64, *apart, *fpart, *y_outer;
   PcgState* st;
