@@ -97,12 +97,17 @@ bool is_complex(int dtype) { return dtype == MN_C128 || dtype == MN_C64; }
 bool is_single(int dtype) { return dtype == MN_C64 || dtype == MN_F32; }
 int compute_cplx_dtype(int dtype) { return is_single(dtype) ? 1 : 0; }  // twiddle table slot
 
-// W_N^k = exp(-2 pi i k / N), k < N, computed in long double and rounded.
+// W_N^k = exp(-2 pi i k / N), k < N, computed in long double and rounded,
+// followed by the compact table W_{N1}^k = W_N^{k N2}, k < N1, of the
+// four-step split N = N1 N2 (N2 = 2^floor(log2(N) / 2)).
 const void* twiddles(mn_handle h, int64_t N, bool single) {
   Twiddle& t = h->tw[{N, single ? 1 : 0}];
   if (t.N == N && t.p) return t.p;
   const size_t es = single ? 8 : 16;
-  std::vector<unsigned char> host((size_t)N * es);
+  int lg = 0;
+  while (((int64_t)1 << lg) < N) ++lg;
+  const int64_t N2 = (int64_t)1 << (lg / 2), N1 = N >> (lg / 2);
+  std::vector<unsigned char> host((size_t)(N + N1) * es);
   const long double two_pi = 6.283185307179586476925286766559005768L;
   for (int64_t k = 0; k < N; ++k) {
     const long double a = two_pi * (long double)k / (long double)N;
@@ -115,6 +120,7 @@ const void* twiddles(mn_handle h, int64_t N, bool single) {
       memcpy(&host[(size_t)k * es], v, es);
     }
   }
+  for (int64_t k = 0; k < N1; ++k) memcpy(&host[(size_t)(N + k) * es], &host[(size_t)(k * N2) * es], es);
   ck(hipMalloc(&t.p, host.size()));
   ck(hipMemcpy(t.p, host.data(), host.size(), hipMemcpyHostToDevice));
   t.N = N;
@@ -231,7 +237,8 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   }
   // rows per four-step chunk: an intermediate of 64 MB by default (it can
   // stay in the 256 MB last-level cache between the two passes); the plan
-  // picks 16 .. 128 MB
+  // picks 16 .. 512 MB (larger chunks give each launch more workgroups to
+  // overlap loads with transforms)
   auto run = [&](int mb) {
     int64_t chunk = ((int64_t)mb << 20) / (N * ces);
     if (chunk < 1) chunk = 1;
@@ -242,7 +249,7 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   };
   int mb = 64;
   const std::string key = plan_key("sketch_chunk_mb", dtype, m, N, 0);
-  if (o) mb = plan_get(h, *o, key, {64, 16, 32, 128}, run);
+  if (o) mb = plan_get(h, *o, key, {64, 16, 32, 128, 256, 512}, run);
   else plan_find(h, key, &mb);
   run(mb);
 }

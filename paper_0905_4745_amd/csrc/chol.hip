@@ -3,13 +3,13 @@
 // S* S holds for the R of any QR decomposition S = Q R).
 //
 // Right-looking blocked Cholesky on 32 x 32 tiles, one launch per block step
-// k: every workgroup factors the diagonal tile G_kk itself (32 steps in LDS),
-// then
-//   tile (k, j), j >= k:        R_kj = R_kk^{-*} G_kj      (written to R)
+// k.  The diagonal tile is factored once, by the workgroup that applies its
+// last update in step k - 1, which also stores R_kk^{-*}; step k then forms
+//   tile (k, j), j > k:         R_kj = R_kk^{-*} G_kj      (written to R)
 //   tile (i, j), k < i <= j:    G_ij -= R_ki^* R_kj        (Schur complement)
-// recomputing the R_k* tiles it needs.  G tiles of block row k are only read
-// during step k, so R goes to a separate buffer and no step races with
-// itself.  FP64 throughout.
+// as plain 32 x 32 products, recomputing the R_k* tiles it needs.  G tiles of
+// block row k are only read during step k, so R goes to a separate buffer and
+// no step races with itself.  FP64 throughout.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "batch_dev.hpp"
@@ -36,113 +36,125 @@ __device__ void tile_in(V* T, const V* G, int64_t ld, int64_t m, int bi, int bj)
 // T = R* R.  Padding rows/columns beyond `valid` are set to the identity so
 // the factor stays invertible.  One barrier per column: the trailing update
 // uses the unscaled row c divided by the pivot, rows are scaled at the end.
-// Returns false if a pivot is not positive and finite.
+// Every thread issues all LDS reads of a step before its arithmetic (the
+// chain of 32 steps is latency-bound).  rinv[i] = 1 / R_ii.  Returns false if
+// a pivot is not positive and finite.
 template <typename V>
-__device__ bool chol_tile(V* T, int valid, double* piv) {
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e % CB, c = e / CB;
-    if (r >= valid || c >= valid) T[r + c * LDC] = (r == c) ? vmake<V>(1.0, 0.0) : vzero<V>();
+__device__ __forceinline__ bool chol_tile(V* T, int valid, double* piv, double* rinv) {
+  const int i = threadIdx.x % CB, jb = threadIdx.x / CB;  // rows i, columns jb + 8u
+  for (int u = 0; u < 4; ++u) {
+    const int j = jb + 8 * u;
+    if (i >= valid || j >= valid) T[i + j * LDC] = (i == j) ? vmake<V>(1.0, 0.0) : vzero<V>();
   }
   __syncthreads();
   for (int c = 0; c < CB; ++c) {
     const double d = vre(T[c + c * LDC]);
+    const V tci = T[c + i * LDC];
+    V tcj[4], tij[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = jb + 8 * u;
+      tcj[u] = T[c + j * LDC];
+      tij[u] = T[i + j * LDC];
+    }
     if (threadIdx.x == 0) piv[c] = d;
     const double inv = 1.0 / d;
-    for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-      const int i = e % CB, j = e / CB;
-      if (i > c && i <= j) T[i + j * LDC] = vsub(T[i + j * LDC], vscale(vcmul(T[c + i * LDC], T[c + j * LDC]), inv));
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = jb + 8 * u;
+      if (i > c && i <= j) T[i + j * LDC] = vsub(tij[u], vscale(vcmul(tci, tcj[u]), inv));
     }
     __syncthreads();
   }
   bool ok = true;
   for (int c = 0; c < CB; ++c) ok = ok && (piv[c] > 0.0) && isfinite(piv[c]);
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int i = e % CB, j = e / CB;
-    const double s = piv[i] > 0.0 ? 1.0 / sqrt(piv[i]) : 0.0;
+  const double pi = piv[i];
+  const double s = pi > 0.0 ? 1.0 / sqrt(pi) : 0.0;
+  if (jb == 0) rinv[i] = s;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = jb + 8 * u;
     if (i < j) T[i + j * LDC] = vscale(T[i + j * LDC], s);
-    else if (i == j) T[i + j * LDC] = vmake<V>(piv[i] > 0.0 ? sqrt(piv[i]) : 0.0, 0.0);
+    else if (i == j) T[i + j * LDC] = vmake<V>(pi > 0.0 ? sqrt(pi) : 0.0, 0.0);
     else T[i + j * LDC] = vzero<V>();
   }
   __syncthreads();
   return ok;
 }
 
-// In place: B1 <- R^{-*} B1 and (if B2) B2 <- R^{-*} B2 (forward substitution
-// on R* X = B, R upper).  One wave; lane j takes column j of B1 (lanes 0-31)
-// or of B2 (lanes 32-63) in registers, so the 32 dependent row steps need no
-// barrier: every lane reads the same entries of R (LDS broadcast).
+// Y <- R^{-*} (forward substitution on R* Y = I, R upper with 1 / R_qq in
+// rinv).  One wave; lane j < 32 keeps column j of Y in registers, every lane
+// reads the same entries of R (LDS broadcast), row q of R is read in one
+// batch before its updates.  Y's strictly upper part comes out exactly zero.
 template <typename V>
-__device__ void solve_tiles(const V* R, V* B1, V* B2) {
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    V* B = lane < CB ? B1 : B2;
-    const int j = lane & (CB - 1);
-    if (B) {
-      V x[CB];
+__device__ __forceinline__ void inv_tile(const V* R, const double* rinv, V* Y) {
+  if (threadIdx.x < CB) {
+    const int j = threadIdx.x;
+    V x[CB];
 #pragma unroll
-      for (int r = 0; r < CB; ++r) x[r] = B[r + j * LDC];
+    for (int r = 0; r < CB; ++r) x[r] = (r == j) ? vmake<V>(1.0, 0.0) : vzero<V>();
+    // fixed trip counts throughout, so that every loop unrolls fully and x
+    // stays in registers
 #pragma unroll
-      for (int q = 0; q < CB; ++q) {
-        x[q] = vscale(x[q], 1.0 / vre(R[q + q * LDC]));
+    for (int q = 0; q < CB; ++q) {
+      x[q] = vscale(x[q], rinv[q]);
 #pragma unroll
-        for (int r = q + 1; r < CB; ++r) x[r] = vsub(x[r], vcmul(R[q + r * LDC], x[q]));
+      for (int c8 = 0; c8 < CB / 8; ++c8) {
+        if (c8 * 8 + 7 > q) {
+          V rq[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) rq[u] = R[q + (c8 * 8 + u) * LDC];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (c8 * 8 + u > q) x[c8 * 8 + u] = vsub(x[c8 * 8 + u], vcmul(rq[u], x[q]));
+        }
       }
-#pragma unroll
-      for (int r = 0; r < CB; ++r) B[r + j * LDC] = x[r];
     }
+#pragma unroll
+    for (int r = 0; r < CB; ++r) Y[r + j * LDC] = x[r];
   }
   __syncthreads();
 }
 
-// T <- A^* B for 32 x 32 tiles in LDS (C may alias neither)
+// acc[u] = sum_q A(r, q) B(q, cg + 8u) for tiles in LDS; thread t takes row
+// r = t % 32 and columns cg + 8u, cg = t / 32.
 template <typename V>
-__device__ void tile_ahb(const V* A, const V* B, V* C) {
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e % CB, c = e / CB;
-    V acc = vzero<V>();
+__device__ __forceinline__ void tile_mm(const V* A, const V* B, V acc[4]) {
+  const int r = threadIdx.x % CB, cg = threadIdx.x / CB;
 #pragma unroll 8
-    for (int q = 0; q < CB; ++q) acc = vcfma(A[q + r * LDC], B[q + c * LDC], acc);
-    C[r + c * LDC] = acc;
-  }
-}
-// T <- Y B for tiles in LDS (Y = R_kk^{-*}, lower triangular)
-template <typename V>
-__device__ void tile_ab_lower(const V* Y, const V* B, V* C) {
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e % CB, c = e / CB;
-    V acc = vzero<V>();
-    for (int q = 0; q <= r; ++q) acc = vfma(Y[r + q * LDC], B[q + c * LDC], acc);
-    C[r + c * LDC] = acc;
+  for (int q = 0; q < CB; ++q) {
+    const V a = A[r + q * LDC];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = vfma(a, B[q + (cg + 8 * u) * LDC], acc[u]);
   }
 }
 
 // Factor the (updated) diagonal tile held in T for block k: R_kk -> R,
-// Y_kk = R_kk^{-*} -> Yd[k] (32 x 32, column-major, ld 32).
+// Y_kk = R_kk^{-*} -> Yd[k] (32 x 32, column-major, ld 32); Y is LDS scratch.
 template <typename V>
-__device__ void finish_diag(V* T, V* Y, double* piv, int k, int64_t m, V* R, int64_t ldr, V* Yd, int32_t* bad) {
+__device__ __forceinline__ void finish_diag(V* T, V* Y, double* piv, double* rinv, int k, int64_t m, V* R, int64_t ldr, V* Yd,
+                            int32_t* bad) {
   const int valid = (int)((m - (int64_t)k * CB) < CB ? (m - (int64_t)k * CB) : CB);
-  const bool ok = chol_tile(T, valid, piv);
+  const bool ok = chol_tile(T, valid, piv, rinv);
   if (!ok && threadIdx.x == 0) bad[0] = 1;
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e % CB, c = e / CB;
-    Y[r + c * LDC] = (r == c) ? vmake<V>(1.0, 0.0) : vzero<V>();
+  {
+    const int r = threadIdx.x % CB, cg = threadIdx.x / CB;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = cg + 8 * u;
+      const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)k * CB + c;
+      if (gr < m && gc < m) R[gr + gc * ldr] = T[r + c * LDC];
+    }
   }
-  __syncthreads();
-  solve_tiles(T, Y, (V*)nullptr);  // Y = R_kk^{-*}
+  inv_tile(T, rinv, Y);
   V* yd = Yd + (int64_t)k * CB * CB;
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e % CB, c = e / CB;
-    const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)k * CB + c;
-    if (gr < m && gc < m) R[gr + gc * ldr] = T[r + c * LDC];
-    yd[e] = Y[r + c * LDC];
-  }
-  // the strictly lower part of R's block column k
-  const int64_t below = m - (int64_t)(k + 1) * CB;
-  for (int64_t e = threadIdx.x; e < below * CB; e += blockDim.x) {
-    const int64_t r = (int64_t)(k + 1) * CB + e % below;
-    const int64_t c = (int64_t)k * CB + e / below;
-    if (c < m) R[r + c * ldr] = vzero<V>();
-  }
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) yd[e] = Y[(e % CB) + (e / CB) * LDC];
+  // the strictly lower part of R's block column k (32-bit loop indices: a
+  // 64-bit divide per element would dominate the step)
+  const int r0 = (k + 1) * CB;
+  const int cend = (int)(m < (int64_t)r0 ? m : (int64_t)r0);
+  for (int c = k * CB; c < cend; ++c)
+    for (int r = r0 + (int)threadIdx.x; r < (int)m; r += blockDim.x) R[r + (int64_t)c * ldr] = vzero<V>();
 }
 
 // Block step 0's diagonal tile (one workgroup).
@@ -154,9 +166,10 @@ __device__ __forceinline__ void k_chol_diag0_body(const Bk bk, V* __restrict__ G
   __shared__ V T[CB * LDC];
   __shared__ V Y[CB * LDC];
   __shared__ double piv[CB];
+  __shared__ double rinv[CB];
   tile_in(T, G, ldg, m, 0, 0);
   __syncthreads();
-  finish_diag(T, Y, piv, 0, m, R, ldr, Yd, bad);
+  finish_diag(T, Y, piv, rinv, 0, m, R, ldr, Yd, bad);
 }
 template <typename V>
 __global__ void __launch_bounds__(256) k_chol_diag0(V* __restrict__ G, int64_t ldg, int64_t m, V* __restrict__ R,
@@ -174,10 +187,10 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
                                                    V* __restrict__ R, int64_t ldr, V* __restrict__ Yd,
                                                    int32_t* __restrict__ bad) {
   __shared__ V Y[CB * LDC];
-  __shared__ V T1[CB * LDC];
-  __shared__ V T2[CB * LDC];
-  __shared__ V T3[CB * LDC];
+  __shared__ V TA[CB * LDC];
+  __shared__ V TB[CB * LDC];
   __shared__ double piv[CB];
+  __shared__ double rinv[CB];
   const int nrow = nbk - k - 1;
   int bi, bj;
   int w = bk.x;
@@ -195,51 +208,65 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
     }
     bj = bi + w;
   }
+  const int r = threadIdx.x % CB, cg = threadIdx.x / CB;
   const V* yd = Yd + (int64_t)k * CB * CB;
   for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) Y[(e % CB) + (e / CB) * LDC] = yd[e];
   if (bi == k) {
-    tile_in(T1, G, ldg, m, k, bj);
+    tile_in(TA, G, ldg, m, k, bj);
     __syncthreads();
-    tile_ab_lower(Y, T1, T2);  // R_kj
-    __syncthreads();
-    for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-      const int r = e % CB, c = e / CB;
-      const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)bj * CB + c;
-      if (gr < m && gc < m) R[gr + gc * ldr] = T2[r + c * LDC];
+    V acc[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
+    tile_mm(Y, TA, acc);  // R_kj
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)bj * CB + cg + 8 * u;
+      if (gr < m && gc < m) R[gr + gc * ldr] = acc[u];
     }
     return;
   }
-  // trailing tile: R_ki (T2), R_kj (T3), then G_ij -= R_ki^* R_kj
-  tile_in(T1, G, ldg, m, k, bi);
+  // trailing tile: P = R_ki = Y G_ki, Q = R_kj = Y G_kj; G_ij -= P^* Q
+  tile_in(TA, G, ldg, m, k, bi);
+  if (bj != bi) tile_in(TB, G, ldg, m, k, bj);
   __syncthreads();
-  tile_ab_lower(Y, T1, T2);
-  __syncthreads();
-  if (bj != bi) {
-    tile_in(T1, G, ldg, m, k, bj);
-    __syncthreads();
-    tile_ab_lower(Y, T1, T3);
-    __syncthreads();
+  // TA <- P^* (so the product reads rows of P^* contiguously), TB <- Q
+  {
+    V p[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
+    tile_mm(Y, TA, p);
+    if (bj != bi) {
+      V q[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
+      tile_mm(Y, TB, q);
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) TB[r + (cg + 8 * u) * LDC] = q[u];
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) TB[r + (cg + 8 * u) * LDC] = p[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) TA[(cg + 8 * u) + r * LDC] = vconj(p[u]);
   }
-  const V* Rj = bj != bi ? T3 : T2;
-  tile_in(T1, G, ldg, m, bi, bj);
   __syncthreads();
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e % CB, c = e / CB;
-    V acc = vzero<V>();
-#pragma unroll 8
-    for (int q = 0; q < CB; ++q) acc = vcfma(T2[q + r * LDC], Rj[q + c * LDC], acc);
-    T1[r + c * LDC] = vsub(T1[r + c * LDC], acc);
-  }
-  __syncthreads();
+  V acc[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
+  tile_mm(TA, TB, acc);
   if (bi == k + 1 && bj == k + 1) {
     // the next diagonal tile is final: factor it for block step k + 1
-    finish_diag(T1, T3, piv, k + 1, m, R, ldr, Yd, bad);
+    __syncthreads();  // TB's reads are done before it is overwritten
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = cg + 8 * u;
+      const int64_t gr = (int64_t)bi * CB + r, gc = (int64_t)bj * CB + c;
+      const V g = (gr < m && gc < m) ? G[gr + gc * ldg] : vzero<V>();
+      TB[r + c * LDC] = vsub(g, acc[u]);
+    }
+    __syncthreads();
+    finish_diag(TB, TA, piv, rinv, k + 1, m, R, ldr, Yd, bad);
     return;
   }
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e % CB, c = e / CB;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = cg + 8 * u;
     const int64_t gr = (int64_t)bi * CB + r, gc = (int64_t)bj * CB + c;
-    if (gr < m && gc < m && gr <= gc) G[gr + gc * ldg] = T1[r + c * LDC];
+    if (gr < m && gc < m && gr <= gc) G[gr + gc * ldg] = vsub(G[gr + gc * ldg], acc[u]);
   }
 }
 template <typename V>

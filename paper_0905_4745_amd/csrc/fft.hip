@@ -15,6 +15,10 @@
 //     twiddles W_N^{n1 k2}; pass 2 does the N1-point FFTs along the rows of
 //     the intermediate and scatters the kept outputs into S through the
 //     inverse subsample map.
+// The twiddle table holds W_N^k (k < N) followed by W_{N1}^k (k < N1): the
+// four-step stages and the W_N^{n1 k2} = W_N^{rem} W_{N2}^{q} factors
+// (n1 k2 = q N1 + rem) read only the first N1 entries and that compact
+// part, both small enough to stay in the vector L1 cache.
 // Both use the same batched Stockham FFT: 256 threads, 16 elements per
 // thread, radix-16/8/4/2 butterflies in registers, LDS between stages.
 #include "common.hpp"
@@ -299,28 +303,32 @@ __device__ __forceinline__ void k_sketch_cols_body(const Bk bk, const V* __restr
   const int b = threadIdx.x / tpf, tl = threadIdx.x % tpf;
   const bool active = b < B;
   C* buf = sm + (active ? b : 0) * Lp;
+  const C* twc = tw + N;  // W_{N1}^k, k < N1
   {
     int Ns = 1;
-    const int twm = N1;  // table of size N: W_N2^k = W_N^{k N1}
+    const int twm = N1 / N2;  // W_N2^k = W_N1^{k N1 / N2}
     for (int s = 0; s < pl2.nst; ++s) {
       const int R = pl2.radix[s];
       const int tl_eff = active ? tl : tpf;
-      if (R == 16) fft_stage<16>(buf, N2, Ns, tpf, tl_eff, tw, twm);
-      else if (R == 8) fft_stage<8>(buf, N2, Ns, tpf, tl_eff, tw, twm);
-      else if (R == 4) fft_stage<4>(buf, N2, Ns, tpf, tl_eff, tw, twm);
-      else fft_stage<2>(buf, N2, Ns, tpf, tl_eff, tw, twm);
+      if (R == 16) fft_stage<16>(buf, N2, Ns, tpf, tl_eff, twc, twm);
+      else if (R == 8) fft_stage<8>(buf, N2, Ns, tpf, tl_eff, twc, twm);
+      else if (R == 4) fft_stage<4>(buf, N2, Ns, tpf, tl_eff, twc, twm);
+      else fft_stage<2>(buf, N2, Ns, tpf, tl_eff, twc, twm);
       Ns *= R;
     }
   }
   if (i >= m) return;
   // twiddle W_N^{n1 k2} and store Y[i][k2][n1]: consecutive threads, consecutive n1
   C* Yi = Y + (int64_t)bk.y * N;
+  const int lg1 = __builtin_ctz((unsigned)N1);
+  const unsigned r12 = (unsigned)(N1 / N2);
   C wv[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int t = threadIdx.x + u * 256;
-    const int64_t e = (int64_t)(c0 + t % B) * (t / B);  // n1 k2 < N
-    wv[u] = (t < B * N2) ? tw[e] : vzero<C>();
+    const unsigned e = (unsigned)(c0 + t % B) * (unsigned)(t / B);  // n1 k2 < N
+    // W_N^e = W_N^{e mod N1} W_N2^{floor(e / N1)}
+    wv[u] = (t < B * N2) ? vmul(tw[e & (unsigned)(N1 - 1)], twc[(e >> lg1) * r12]) : vzero<C>();
   }
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
@@ -376,14 +384,14 @@ __device__ __forceinline__ void k_sketch_rows_body(const Bk bk, const C* __restr
   C* buf = sm + (active ? b : 0) * Lp;
   {
     int Ns = 1;
-    const int twm = N2;
+    const C* twc = tw + N;  // W_{N1}^k, k < N1
     for (int s = 0; s < pl1.nst; ++s) {
       const int R = pl1.radix[s];
       const int tl_eff = active ? tl : tpf;
-      if (R == 16) fft_stage<16>(buf, N1, Ns, tpf, tl_eff, tw, twm);
-      else if (R == 8) fft_stage<8>(buf, N1, Ns, tpf, tl_eff, tw, twm);
-      else if (R == 4) fft_stage<4>(buf, N1, Ns, tpf, tl_eff, tw, twm);
-      else fft_stage<2>(buf, N1, Ns, tpf, tl_eff, tw, twm);
+      if (R == 16) fft_stage<16>(buf, N1, Ns, tpf, tl_eff, twc, 1);
+      else if (R == 8) fft_stage<8>(buf, N1, Ns, tpf, tl_eff, twc, 1);
+      else if (R == 4) fft_stage<4>(buf, N1, Ns, tpf, tl_eff, twc, 1);
+      else fft_stage<2>(buf, N1, Ns, tpf, tl_eff, twc, 1);
       Ns *= R;
     }
   }
