@@ -26,6 +26,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# the timed region brackets every PROFILE_EVERY-th launch of each pass over A
+# with HIP events (the sampled launches give the kernel's average duration)
+PROFILE_EVERY = 4
 
 # HBM bytes per live launch of the fused pass, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE on this workload, each scaled by what the same counter reads for a
@@ -129,7 +132,9 @@ def main():
     torch.cuda.synchronize()
 
     log(f"[bench] timed {args.steps} solves")
-    api.profile(True)
+    # every PROFILE_EVERY-th pass over A is bracketed by HIP events (each
+    # event pair costs a few microseconds of stream time)
+    api.profile(PROFILE_EVERY)
     iters = []
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -253,7 +258,7 @@ def main_multirhs(args):
         log(f"[bench]   info {info}")
     torch.cuda.synchronize()
     log(f"[bench] timed {args.steps} solves of {k} RHS")
-    api.profile(True)
+    api.profile(PROFILE_EVERY)
     infos = []
     t0 = time.perf_counter()
     for s_ in range(args.steps):

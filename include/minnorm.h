@@ -138,8 +138,10 @@ const char* mn_last_hip_error(void);
 int64_t mn_workspace_bytes(mn_handle h);
 
 /* Per-kernel timing for measurement (not part of the method).  With
- * enable != 0, every later launch of the passes over A is bracketed by a
- * pair of HIP events on the handle's stream; mn_profile_read synchronises the
+ * enable = k > 0, every k-th later launch of each pass over A (k = 1: every
+ * launch) is bracketed by a pair of HIP events on the handle's stream (each
+ * pair adds a few microseconds between launches, hence the sampling);
+ * enable <= 0 turns timing off.  mn_profile_read synchronises the
  * stream and returns how many launches of `kernel` ("gemv_adj": w = A* u,
  * "gemv_fwd": q = A w, "gram": the fused q = A (A* p) used when m <= 512,
  * "block_adj" / "block_fwd": the split-BF16 products W = A* P and Q = A W of

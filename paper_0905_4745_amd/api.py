@@ -243,10 +243,17 @@ def plans_count(device=None) -> int:
     return int(L.load().mn_plans_count(_handle(dev)))
 
 
-def profile(enable: bool, device=None) -> None:
-    """Turn per-launch event timing of the passes over A on or off (clears records)."""
+def profile(enable, device=None) -> None:
+    """Turn per-launch event timing of the passes over A on or off (clears records).
+
+    `enable` False/0 turns it off; True/1 brackets every launch; an integer
+    k > 1 brackets every k-th launch of each kernel (fewer event records on
+    the stream while still timing launches from the whole run)."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-    st = L.load().mn_profile(_handle(dev), 1 if enable else 0)
+    every = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+    if every < 0:
+        raise ValueError("profile: enable must be >= 0")
+    st = L.load().mn_profile(_handle(dev), every)
     if st != 0:
         raise MinnormError("mn_profile", st)
 

@@ -52,7 +52,14 @@ struct mn_handle_s {
   bool prof = false;
   std::vector<hipEvent_t> pool;
   size_t pool_used = 0;
-  std::vector<std::pair<int, size_t>> recs;  // (kernel id, index of begin event)
+  int prof_every = 1;                       // bracket every prof_every-th launch
+  int64_t prof_seen[8] = {};                // launches seen per kernel id
+  struct ProfRec {
+    int kid;      // kernel id
+    size_t ev;    // index of the begin event in pool
+    int64_t ord;  // launch ordinal of that kernel id
+  };
+  std::vector<ProfRec> recs;
   // concurrent lanes of minnorm_solve_batched: child handles on their own streams
   bool owns_stream = false;
   std::vector<mn_handle> lanes;
@@ -137,8 +144,11 @@ enum { K_ADJ = 0, K_FWD = 1, K_GRAM = 2, K_BADJ = 3, K_BFWD = 4, K_DRES = 5 };
 const char* kKernelNames[] = {"gemv_adj", "gemv_fwd", "gram", "block_adj", "block_fwd", "block_residual"};
 
 // a begin/end event pair for one timed launch, or nulls when not profiling
+// (or when this launch is not one of the sampled ones)
 std::pair<hipEvent_t, hipEvent_t> prof_pair(mn_handle h, int kid) {
   if (!h->prof) return {nullptr, nullptr};
+  const int64_t ord = h->prof_seen[kid]++;
+  if (ord % h->prof_every != 0) return {nullptr, nullptr};
   while (h->pool.size() < h->pool_used + 2) {
     hipEvent_t e;
     ck(hipEventCreate(&e));
@@ -146,7 +156,7 @@ std::pair<hipEvent_t, hipEvent_t> prof_pair(mn_handle h, int kid) {
   }
   const size_t i = h->pool_used;
   h->pool_used += 2;
-  h->recs.push_back({kid, i});
+  h->recs.push_back({kid, i, ord});
   return {h->pool[i], h->pool[i + 1]};
 }
 
@@ -398,15 +408,14 @@ void cg_start(const SolveCtx& c, CgBufs& v, const void* b, const void* parts, in
 
 // CG iterations until the device flag is set (checked every check_every).
 // Drop timing records of launches that found the stop flag set and returned
-// at once: only the first `iters` launches of each kernel since `begin` did
-// an iteration's work.
-void prune_records(mn_handle h, size_t begin, int iters) {
+// at once: only the first `iters` launches of each kernel since the loop
+// began (launch ordinals base[kid] on) did an iteration's work.
+void prune_records(mn_handle h, size_t begin, const int64_t* base, int iters) {
   if (!h->prof) return;
-  std::vector<std::pair<int, size_t>> kept(h->recs.begin(), h->recs.begin() + begin);
-  int seen[8] = {0};
+  std::vector<mn_handle_s::ProfRec> kept(h->recs.begin(), h->recs.begin() + begin);
   for (size_t r = begin; r < h->recs.size(); ++r) {
-    const int kid = h->recs[r].first;
-    if (seen[kid]++ < iters) kept.push_back(h->recs[r]);
+    const auto& rec = h->recs[r];
+    if (rec.ord - base[rec.kid] < iters) kept.push_back(rec);
   }
   h->recs.swap(kept);
 }
@@ -414,6 +423,8 @@ void prune_records(mn_handle h, size_t begin, int iters) {
 void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
   mn_handle h = c.h;
   const size_t rec_begin = h->recs.size();
+  int64_t rec_base[8];
+  std::copy(h->prof_seen, h->prof_seen + 8, rec_base);
   const int32_t* flag = &v.st->done;
   const bool fused = gram_supported(c.bulk, c.m, c.Ab, c.ldab);
   int gram_plan = 512;
@@ -523,7 +534,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
     if (h->host_state->done) break;
     if (enqueued > max_iter + 2 * c.o.check_every) break;  // cannot happen: the kernels cap iterations
   }
-  prune_records(h, rec_begin, h->host_state->iter_local);
+  prune_records(h, rec_begin, rec_base, h->host_state->iter_local);
 }
 
 // One right-hand side; b and x FP64 device vectors.  Returns a status.
@@ -822,6 +833,8 @@ int solve_block(const SolveCtx& c, const void* b, int64_t ldb, int kc, void* x, 
     x_product(false, s, z, nullptr);
     ck(launch_blk_beta(cplx, kc, m, 1, s, z, p, p_hi, p_lo, pl.Kp1, bst, st));
     const size_t rec_begin = h->recs.size();
+    int64_t rec_base[8];
+    std::copy(h->prof_seen, h->prof_seen + 8, rec_base);
     while (true) {
       for (int it = 0; it < c.o.check_every; ++it) {
         BfGemmArgs g1{};  // W = A* P (transposed planes, conjugated)
@@ -872,7 +885,7 @@ int solve_block(const SolveCtx& c, const void* b, int64_t ldb, int kc, void* x, 
     }
     int live = 0;
     for (int j = 0; j < kc; ++j) live = std::max(live, h->host_blk->col[j].inner_it);
-    prune_records(h, rec_begin, live);
+    prune_records(h, rec_begin, rec_base, live);
     ck(launch_blk_refine(cplx, kc, m, yo, y, bst, st));
   }
   ev_record(h, 4);
@@ -1175,7 +1188,8 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       if (k == 0) chol[k].g[i] = BGrid{0, 1, 1, 1};
       else if (ks + 1 < nb) chol[k].g[i] = BGrid{0, (nb - ks - 1) + (nb - ks - 1) * (nb - ks) / 2, 1, 1};
       else chol[k].g[i] = BGrid{0, 0, 1, 1};
-      if (k >= 1 && k < nb) trtri[k].g[i] = BGrid{0, nb - k, 1, 1};
+      // trtri[k]: block step k of the right-looking inverse
+      if (k + 1 < nb) trtri[k].g[i] = BGrid{0, (k + 1) * (nb - k - 1), 1, 1};
       else trtri[k].g[i] = BGrid{0, 0, 1, 1};
     }
   }
@@ -1323,7 +1337,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   }
   // X = R^{-1}
   ck(launch_b_inv_diag(cplx, L(invd), st));
-  for (int k = 1; k < maxnbk; ++k) ck(launch_b_trtri_step(cplx, L(trtri[k]), k, st));
+  for (int k = 0; k + 1 < maxnbk; ++k) ck(launch_b_trtri_step(cplx, L(trtri[k]), k, st));
   // CG states (skipped systems start finished)
   std::vector<PcgState> hst_state((size_t)batch);
   for (int i = 0; i < batch; ++i) {
@@ -1507,9 +1521,11 @@ int mn_profile(mn_handle h, int enable) {
   } catch (HipFail f) {
     return fail_hip(f.e);
   }
-  h->prof = enable != 0;
+  h->prof = enable > 0;
+  h->prof_every = enable > 0 ? enable : 1;
   h->pool_used = 0;
   h->recs.clear();
+  std::fill(h->prof_seen, h->prof_seen + 8, 0);
   return 0;
 }
 
@@ -1527,9 +1543,9 @@ int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* tot
   try {
     ck(hipStreamSynchronize(h->stream));
     for (auto& r : h->recs) {
-      if (r.first != kid) continue;
+      if (r.kid != kid) continue;
       float t = 0.f;
-      ck(hipEventElapsedTime(&t, h->pool[r.second], h->pool[r.second + 1]));
+      ck(hipEventElapsedTime(&t, h->pool[r.ev], h->pool[r.ev + 1]));
       *count += 1;
       *total_ms += t;
     }

@@ -293,7 +293,7 @@ hipError_t launch_b_gram_s(int dtype, const BLaunch& L, hipStream_t st);
 hipError_t launch_b_chol_step(bool cplx, const BLaunch& L, int k, hipStream_t st);
 hipError_t launch_b_rdiag(bool cplx, const BLaunch& L, hipStream_t st);
 hipError_t launch_b_inv_diag(bool cplx, const BLaunch& L, hipStream_t st);
-hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int d, hipStream_t st);
+hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int k, hipStream_t st);
 // the fused pass q = A (A* p) on the bulk copy (16-byte aligned rows), one
 // launch per rows-per-thread class L[0..3], then the partial sums
 hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st);

@@ -80,53 +80,67 @@ __global__ void __launch_bounds__(256) k_inv_diag(const RV* __restrict__ R, int6
   k_inv_diag_body<RV, W>(bk_hw(), R, ldr, m, X, ldx);
 }
 
-// Off-diagonal blocks at distance d: X_{i,i+d} = -X_ii sum_{k=i+1}^{i+d} R_ik X_{k,i+d}.
-// grid = K - d blocks, 256 threads; thread t owns row t%32, columns 4*(t/32)..+3.
+// Off-diagonal blocks, right-looking: in block step k (block column k of X
+// final: X_ik for i <= k) every tile (i, j), i <= k < j, adds X_ik R_kj to the
+// running sum held in X_ij (stored, not added, for its first term k = i); the
+// tiles of column j = k + 1 then hold the whole sum S and are finished as
+// X_{i,k+1} = -S X_{k+1,k+1}.  Each workgroup does one or two 32 x 32
+// products, so the chain is K - 1 short launches.  grid = (k + 1)(K - k - 1).
+constexpr int LDT = TB + 1;  // LDS column stride
+
+// acc[u] += A(r, q) B(q, cg + 8u); thread t: row r = t % 32, columns cg + 8u
+template <typename W>
+__device__ __forceinline__ void tile_mm32(const W* A, const W* B, W acc[4]) {
+  const int r = threadIdx.x % TB, cg = threadIdx.x / TB;
+#pragma unroll 8
+  for (int q = 0; q < TB; ++q) {
+    const W a = A[r + q * LDT];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = vfma(a, B[q + (cg + 8 * u) * LDT], acc[u]);
+  }
+}
+
 template <typename RV, typename W>
 __device__ __forceinline__ void k_trtri_step_body(const Bk bk, const RV* __restrict__ R, int64_t ldr, int64_t m,
-                                                    W* __restrict__ X, int64_t ldx, int d) {
-  __shared__ W Rs[TB * TB];
-  __shared__ W Xs[TB * TB];
-  const int i = bk.x, j = i + d;
-  const int64_t i0 = (int64_t)i * TB, j0 = (int64_t)j * TB;
-  const int r = threadIdx.x % TB, cg = (threadIdx.x / TB) * 4;
-  W acc[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
-  for (int k = i + 1; k <= j; ++k) {
-    const int64_t k0 = (int64_t)k * TB;
-    __syncthreads();
-    for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
-      const int rr = e % TB, cc = e / TB;
-      Rs[e] = r_at<RV, W>(R, ldr, m, i0 + rr, k0 + cc);
-      Xs[e] = X[(k0 + rr) + (j0 + cc) * ldx];
-    }
-    __syncthreads();
-    for (int q = 0; q < TB; ++q) {
-      const W a = Rs[r + q * TB];
+                                                    W* __restrict__ X, int64_t ldx, int k, int K) {
+  __shared__ W As[TB * LDT];
+  __shared__ W Bs[TB * LDT];
+  const int ncol = K - k - 1;
+  const int i = bk.x / ncol, j = k + 1 + bk.x % ncol;
+  const int64_t i0 = (int64_t)i * TB, j0 = (int64_t)j * TB, k0 = (int64_t)k * TB;
+  const int r = threadIdx.x % TB, cg = threadIdx.x / TB;
+  W acc[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = vfma(a, Xs[q + (cg + u) * TB], acc[u]);
-    }
+  for (int u = 0; u < 4; ++u) {
+    const int c = cg + 8 * u;
+    As[r + c * LDT] = X[(i0 + r) + (k0 + c) * ldx];         // X_ik
+    Bs[r + c * LDT] = r_at<RV, W>(R, ldr, m, k0 + r, j0 + c);  // R_kj
+    acc[u] = (k == i) ? vzero<W>() : X[(i0 + r) + (j0 + c) * ldx];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
-    const int rr = e % TB, cc = e / TB;
-    Rs[e] = X[(i0 + rr) + (i0 + cc) * ldx];  // X_ii
+  tile_mm32(As, Bs, acc);
+  if (j == k + 1) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = cg + 8 * u;
+      As[r + c * LDT] = acc[u];                             // S
+      Bs[r + c * LDT] = X[(j0 + r) + (j0 + c) * ldx];       // X_jj
+    }
+    __syncthreads();
+    W o[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
+    tile_mm32(As, Bs, o);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) X[(i0 + r) + (j0 + cg + 8 * u) * ldx] = vsub(vzero<W>(), o[u]);
+    return;
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) Xs[r + (cg + u) * TB] = acc[u];
-  __syncthreads();
-  W o[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
-  for (int q = 0; q < TB; ++q) {
-    const W a = Rs[r + q * TB];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) o[u] = vfma(a, Xs[q + (cg + u) * TB], o[u]);
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) X[(i0 + r) + (j0 + cg + u) * ldx] = vsub(vzero<W>(), o[u]);
+  for (int u = 0; u < 4; ++u) X[(i0 + r) + (j0 + cg + 8 * u) * ldx] = acc[u];
 }
 template <typename RV, typename W>
 __global__ void __launch_bounds__(256) k_trtri_step(const RV* __restrict__ R, int64_t ldr, int64_t m,
-                                                    W* __restrict__ X, int64_t ldx, int d) {
-  k_trtri_step_body<RV, W>(bk_hw(), R, ldr, m, X, ldx, d);
+                                                    W* __restrict__ X, int64_t ldx, int k, int K) {
+  k_trtri_step_body<RV, W>(bk_hw(), R, ldr, m, X, ldx, k, K);
 }
 
 __device__ inline bool stop_test(const PcgState& st, double rho, double xi) {
@@ -206,18 +220,25 @@ __device__ __forceinline__ void k_cg_s_body(const Bk bk, const W* __restrict__ X
   // s for columns c0 .. c0+7: wave w takes 2 columns, lanes run down each
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t c0 = (int64_t)bk.x * 8 + 2 * wv;
-  W acc0 = vzero<W>(), acc1 = vzero<W>();
   const int64_t j0 = c0, j1 = c0 + 1;
-  if (j0 < m) {
-    const W* col = X + j0 * ldx;
-    for (int64_t i = lane; i <= j0; i += 64) acc0 = vcfma(col[i], rs[i], acc0);
+  // column j of X has entries 0 .. j; both columns are walked together with
+  // four accumulators each, so all of a lane's loads are in flight at once
+  const int64_t e0 = j0 < m ? j0 + 1 : 0, e1 = j1 < m ? j1 + 1 : 0;
+  const W* col0 = X + j0 * ldx;
+  const W* col1 = X + j1 * ldx;
+  W a0[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
+  W a1[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
+  const int64_t emax = e0 > e1 ? e0 : e1;
+  for (int64_t i = lane; i < emax; i += 256) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t ii = i + 64 * u;
+      if (ii < e0) a0[u] = vcfma(col0[ii], rs[ii], a0[u]);
+      if (ii < e1) a1[u] = vcfma(col1[ii], rs[ii], a1[u]);
+    }
   }
-  if (j1 < m) {
-    const W* col = X + j1 * ldx;
-    for (int64_t i = lane; i <= j1; i += 64) acc1 = vcfma(col[i], rs[i], acc1);
-  }
-  acc0 = wave_sum(acc0);
-  acc1 = wave_sum(acc1);
+  W acc0 = wave_sum(vadd(vadd(a0[0], a0[1]), vadd(a0[2], a0[3])));
+  W acc1 = wave_sum(vadd(vadd(a1[0], a1[1]), vadd(a1[2], a1[3])));
   if (lane == 0) {
     if (j0 < m) s[j0] = acc0;
     if (j1 < m) s[j1] = acc1;
@@ -390,9 +411,9 @@ static hipError_t inverse_impl(const void* R, int64_t ldr, int64_t m, void* X, i
   const int K = (int)ceil_div(m, TB);
   hipLaunchKernelGGL((k_inv_diag<RV, W>), dim3(K), dim3(256), 0, st, reinterpret_cast<const RV*>(R), ldr, m,
                      reinterpret_cast<W*>(X), ldx);
-  for (int d = 1; d < K; ++d)
-    hipLaunchKernelGGL((k_trtri_step<RV, W>), dim3(K - d), dim3(256), 0, st, reinterpret_cast<const RV*>(R), ldr,
-                       m, reinterpret_cast<W*>(X), ldx, d);
+  for (int k = 0; k + 1 < K; ++k)
+    hipLaunchKernelGGL((k_trtri_step<RV, W>), dim3((k + 1) * (K - k - 1)), dim3(256), 0, st,
+                       reinterpret_cast<const RV*>(R), ldr, m, reinterpret_cast<W*>(X), ldx, k, K);
   return hipGetLastError();
 }
 
@@ -470,11 +491,11 @@ __global__ void __launch_bounds__(256) kb_inv_diag(const BSys* __restrict__ sys,
 
 template <typename W>
 __global__ void __launch_bounds__(256) kb_trtri_step(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
-                                                     int nsys, int d) {
+                                                     int nsys, int k) {
   const int i = bgrid_find(grid, nsys, blockIdx.x);
   const BSys& s = sys[i];
   k_trtri_step_body<W, W>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const W*>(s.R),
-                          s.m, s.m, reinterpret_cast<W*>(s.X), s.ldx, d);
+                          s.m, s.m, reinterpret_cast<W*>(s.X), s.ldx, k, (int)ceil_div(s.m, TB));
 }
 
 // r ping-pong: at iteration parity par, r_in = r[par] and r_out = r[par ^ 1];
@@ -551,12 +572,13 @@ hipError_t launch_b_inv_diag(bool cplx, const BLaunch& L, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int d, hipStream_t st) {
+// block step k of every system with more than k + 1 block columns
+hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int k, hipStream_t st) {
   if (L.total == 0) return hipSuccess;
   if (cplx)
-    hipLaunchKernelGGL(kb_trtri_step<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, d);
+    hipLaunchKernelGGL(kb_trtri_step<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, k);
   else
-    hipLaunchKernelGGL(kb_trtri_step<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, d);
+    hipLaunchKernelGGL(kb_trtri_step<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, k);
   return hipGetLastError();
 }
 

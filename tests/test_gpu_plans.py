@@ -69,3 +69,29 @@ def test_every_fused_plan_meets_eps(tmp_path):
         x, info = api.minnorm_solve(to_dev(A), to_dev(b), 1e-10, d, idx, N)
         assert info["status"] == 0
         assert rel(to_np(x), p) <= 1e-10, plan
+
+
+def test_profile_sampling_counts_live_launches():
+    """mn_profile(k): every k-th launch of the fused pass is timed, and only
+    launches that ran an iteration are counted."""
+    from paper_0905_4745_amd import api
+    A, b, _ = synth.make_svd(96, 6000, 1e3, seed=33)
+    N = synth.next_pow2(6000)
+    d, idx = synth.draw_srft(N, 384, seed=33)
+    At, bt = to_dev(A), to_dev(b)
+    counts = {}
+    for every in (1, 4):
+        api.profile(every)
+        x, info = api.minnorm_solve(At, bt, 1e-10, d, idx, N)
+        cnt, ms = api.profile_read("gram")
+        api.profile(False)
+        assert info["status"] == 0
+        assert rel(to_np(x), oracle.classical_minnorm(A, b)) <= 1e-10
+        say(f"  every {every}: iters {info['iters']} timed launches {cnt} ({ms:.3f} ms)")
+        counts[every] = (info["iters"], cnt, ms)
+    it1, c1, ms1 = counts[1]
+    it4, c4, ms4 = counts[4]
+    assert c1 == it1 and ms1 > 0
+    assert c4 == (it4 + 3) // 4 and ms4 > 0
+    with pytest.raises(ValueError):
+        api.profile(-1)
