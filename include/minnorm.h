@@ -164,7 +164,9 @@ int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* tot
  *                            workgroup size (bit 18 set: 1024 threads, half
  *                            the rows per thread; 512 otherwise);
  * "sketch_chunk_mb/<dtype>/<m>/<N>/0"  four-step FFT: MB of the intermediate
- *                            per chunk of rows (16, 32, 64 or 128);
+ *                            per chunk of rows (low 16 bits: 16 .. 512) and
+ *                            workgroup size in elements (bit 16 set: 2048,
+ *                            else 4096);
  * "block_fwd_wg/<dtype>/<m>/<n>/<k>"   block product A W: workgroups aimed
  *                            for when splitting its n columns (512..2048).
  * Plans are chosen by timing when mn_opts.tune = 1 (see there).

@@ -43,6 +43,8 @@ struct mn_handle_s {
   std::map<std::string, Buf> bufs;
   std::map<std::pair<int64_t, int>, Twiddle> tw;  // W_N^k tables by (N, single precision)
   PcgState* host_state = nullptr;  // pinned
+  PcgState* host_snap = nullptr;   // pinned, 2 slots: state snapshots read back one batch late
+  hipEvent_t snap_ev[2] = {};
   BlkState* host_blk = nullptr;    // pinned
   int32_t* host_flag = nullptr;    // pinned
   double* host_diag = nullptr;     // pinned, 4 doubles
@@ -249,7 +251,11 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   // stay in the 256 MB last-level cache between the two passes); the plan
   // picks 16 .. 512 MB (larger chunks give each launch more workgroups to
   // overlap loads with transforms)
-  auto run = [&](int mb) {
+  // plan: MB of intermediate per chunk (low 16 bits), bit 16 set: 2048
+  // elements per workgroup instead of 4096
+  auto run = [&](int pl) {
+    const int mb = pl & 0xFFFF;
+    a.wg_elems = (pl >> 16) & 1 ? 2048 : 4096;
     int64_t chunk = ((int64_t)mb << 20) / (N * ces);
     if (chunk < 1) chunk = 1;
     if (chunk > m) chunk = m;
@@ -259,7 +265,9 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   };
   int mb = 64;
   const std::string key = plan_key("sketch_chunk_mb", dtype, m, N, 0);
-  if (o) mb = plan_get(h, *o, key, {64, 16, 32, 128, 256, 512}, run);
+  if (o)
+    mb = plan_get(h, *o, key, {64, 16, 32, 128, 256, 512, 0x10000 | 64, 0x10000 | 128, 0x10000 | 256, 0x10000 | 512},
+                  run);
   else plan_find(h, key, &mb);
   run(mb);
 }
@@ -453,7 +461,8 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
           for (int wg : {512, 256, 1024}) cands.push_back(wg | nw | il | ww);
     gram_plan = plan_get(h, c.o, plan_key("gram", c.bulk, c.m, c.n, c.wide_acc ? 1 : 0), cands, run);
   }
-  int enqueued = 0;
+  int enqueued = 0, snap = 0;
+  bool pending = false;
   while (true) {
     for (int k = 0; k < c.o.check_every; ++k) {
       if (fused) {
@@ -530,9 +539,25 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
       v.par ^= 1;
     }
     enqueued += c.o.check_every;
-    read_state(h, v.st);
-    if (h->host_state->done) break;
-    if (enqueued > max_iter + 2 * c.o.check_every) break;  // cannot happen: the kernels cap iterations
+    // the state after this batch is copied back asynchronously and read one
+    // batch later, so the host never leaves the stream idle while it checks
+    // the stop flag; after the stop, the kernels of the batch still in
+    // flight return at once and leave the state unchanged
+    ck(hipMemcpyAsync(&h->host_snap[snap], v.st, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
+    ck(hipEventRecord(h->snap_ev[snap], h->stream));
+    if (pending) {
+      ck(hipEventSynchronize(h->snap_ev[snap ^ 1]));
+      if (h->host_snap[snap ^ 1].done) {
+        *h->host_state = h->host_snap[snap ^ 1];
+        break;
+      }
+    }
+    pending = true;
+    snap ^= 1;
+    if (enqueued > max_iter + 3 * c.o.check_every) {  // cannot happen: the kernels cap iterations
+      read_state(h, v.st);
+      break;
+    }
   }
   prune_records(h, rec_begin, rec_base, h->host_state->iter_local);
 }
@@ -1457,6 +1482,8 @@ int mn_create(mn_handle* hp, void* stream) {
     h->stream = (hipStream_t)stream;
     ck(hipGetDevice(&h->device));
     ck(hipHostMalloc((void**)&h->host_state, sizeof(PcgState), hipHostMallocDefault));
+    ck(hipHostMalloc((void**)&h->host_snap, 2 * sizeof(PcgState), hipHostMallocDefault));
+    for (auto& e : h->snap_ev) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     ck(hipHostMalloc((void**)&h->host_blk, sizeof(BlkState), hipHostMallocDefault));
     ck(hipHostMalloc((void**)&h->host_flag, 64, hipHostMallocDefault));
     ck(hipHostMalloc((void**)&h->host_diag, 64, hipHostMallocDefault));
@@ -1480,6 +1507,9 @@ int mn_destroy(mn_handle h) {
   for (auto& kv : h->tw)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (h->host_state) (void)hipHostFree(h->host_state);
+  if (h->host_snap) (void)hipHostFree(h->host_snap);
+  for (auto& e : h->snap_ev)
+    if (e) (void)hipEventDestroy(e);
   if (h->host_blk) (void)hipHostFree(h->host_blk);
   if (h->host_stage) (void)hipHostFree(h->host_stage);
   if (h->host_flag) (void)hipHostFree(h->host_flag);

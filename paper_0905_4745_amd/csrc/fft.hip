@@ -481,8 +481,8 @@ template <typename K> static void allow_lds(K* kern, size_t bytes) {
 }
 
 // transforms per workgroup: up to 4096 elements (256 threads x 16) within LDS
-template <typename C> static int fft_batch(int L) {
-  int B = 4096 / L;
+template <typename C> static int fft_batch(int L, int elems = 4096) {
+  int B = elems / L;
   if (B > 256) B = 256;  // L < 16: one thread per transform
   if (B < 1) B = 1;
   while (B > 1 && (int64_t)B * lds_stride(L) * (int64_t)sizeof(C) > lds_limit()) B >>= 1;
@@ -514,8 +514,12 @@ static hipError_t sketch_impl(const SketchArgs& a, hipStream_t st) {
   const int N2 = 1 << (k / 2), N1 = N >> (k / 2);
   if (N1 > Lmax) return hipErrorInvalidValue;
   FftPlan pl1 = make_plan(N1), pl2 = make_plan(N2);
-  const int Bc = fft_batch<C>(N2);  // columns per workgroup, pass 1
-  const int Br = fft_batch<C>(N1);  // rows of the intermediate per workgroup, pass 2
+  // fewer elements per workgroup (half the threads idle in the transform,
+  // all of them load) halve the LDS footprint and double the workgroups
+  // resident per CU
+  const int elems = a.wg_elems == 2048 ? 2048 : 4096;
+  const int Bc = fft_batch<C>(N2, elems);  // columns per workgroup, pass 1
+  const int Br = fft_batch<C>(N1, elems);  // rows of the intermediate per workgroup, pass 2
   const size_t smc = (size_t)Bc * lds_stride(N2) * sizeof(C);
   const size_t smr = (size_t)Br * lds_stride(N1) * sizeof(C);
   allow_lds(k_sketch_cols<V, C>, smc);

@@ -40,6 +40,7 @@ struct SketchArgs {
   const void* twiddle;  // W_N^k, k < N, in the compute precision
   void* work;           // four-step intermediate, chunk_rows * N complex
   int64_t chunk_rows;
+  int wg_elems;         // four-step: elements per workgroup (4096 or 2048; 0 = 4096)
 };
 hipError_t launch_sketch(int dtype, const SketchArgs& a, hipStream_t st);
 int sketch_max_log2n(int dtype);  // largest log2(N) the four-step supports

@@ -168,6 +168,21 @@ __device__ __forceinline__ void k_cg_s_body(const Bk bk, const W* __restrict__ X
   __shared__ double red[4];
   PcgState& st = *stp;
   const bool lead = bk.x == 0;
+  // s for columns c0 .. c0+7: wave w takes 2 columns, lanes run down each.
+  // Column j of X has entries 0 .. j; its first 256 entries do not depend on
+  // the iteration, so their loads are issued before anything else.
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t j0 = (int64_t)bk.x * 8 + 2 * wv, j1 = j0 + 1;
+  const int64_t e0 = j0 < m ? j0 + 1 : 0, e1 = j1 < m ? j1 + 1 : 0;
+  const W* col0 = X + j0 * ldx;
+  const W* col1 = X + j1 * ldx;
+  W x0[4], x1[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t ii = lane + 64 * u;
+    x0[u] = ii < e0 ? col0[ii] : vzero<W>();
+    x1[u] = ii < e1 ? col1[ii] : vzero<W>();
+  }
   if (start) {
     if (st.outer_done) return;
     for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
@@ -217,19 +232,18 @@ __device__ __forceinline__ void k_cg_s_body(const Bk bk, const W* __restrict__ X
     }
   }
   __syncthreads();
-  // s for columns c0 .. c0+7: wave w takes 2 columns, lanes run down each
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t c0 = (int64_t)bk.x * 8 + 2 * wv;
-  const int64_t j0 = c0, j1 = c0 + 1;
-  // column j of X has entries 0 .. j; both columns are walked together with
-  // four accumulators each, so all of a lane's loads are in flight at once
-  const int64_t e0 = j0 < m ? j0 + 1 : 0, e1 = j1 < m ? j1 + 1 : 0;
-  const W* col0 = X + j0 * ldx;
-  const W* col1 = X + j1 * ldx;
+  // both columns are walked together with four accumulators each, so all of
+  // a lane's loads are in flight at once
   W a0[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
   W a1[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t ii = lane + 64 * u;
+    if (ii < e0) a0[u] = vcfma(x0[u], rs[ii], a0[u]);
+    if (ii < e1) a1[u] = vcfma(x1[u], rs[ii], a1[u]);
+  }
   const int64_t emax = e0 > e1 ? e0 : e1;
-  for (int64_t i = lane; i < emax; i += 256) {
+  for (int64_t i = lane + 256; i < emax; i += 256) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t ii = i + 64 * u;
@@ -270,6 +284,17 @@ __device__ __forceinline__ void k_cg_p_body(const Bk bk, const W* __restrict__ X
   __shared__ W part[16][RB];
   PcgState& st = *stp;
   const bool lead = bk.x == 0;
+  // z = X s on rows i0 .. i0+15: thread t takes row t%16 and every 16th
+  // column.  X is zero below the diagonal inside the diagonal block, so the
+  // band can be read from column i0 on; the first group of four columns per
+  // thread does not depend on the iteration and is loaded first.
+  const int64_t i0 = (int64_t)bk.x * RB;
+  const int rr = threadIdx.x % RB, cgrp = threadIdx.x / RB;  // 16 column groups
+  const int64_t i = i0 + rr;
+  const bool first = i < m && i0 + cgrp + 48 < m;
+  W xf[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) xf[u] = first ? X[i + (i0 + cgrp + 16 * u) * ldx] : vzero<W>();
   if (start ? (st.outer_done != 0) : (st.done != 0)) return;
   double rho = 0.0;
   for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
@@ -350,16 +375,16 @@ __device__ __forceinline__ void k_cg_p_body(const Bk bk, const W* __restrict__ X
     if (stop) return;
     beta = rho / st.rho_prev;
   }
-  // z = X s on rows i0 .. i0+15: thread t takes row t%16 and every 16th column
-  const int64_t i0 = (int64_t)bk.x * RB;
-  const int rr = threadIdx.x % RB, cgrp = threadIdx.x / RB;  // 16 column groups
-  const int64_t i = i0 + rr;
-  // X is zero below the diagonal inside the diagonal block, so the band can
-  // be read from column i0 on; four independent accumulators keep the loads
-  // of a thread in flight together
+  // four independent accumulators keep the loads of a thread in flight
+  // together
   W a4[4] = {vzero<W>(), vzero<W>(), vzero<W>(), vzero<W>()};
   if (i < m) {
     int64_t j = i0 + cgrp;
+    if (first) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] = vfma(xf[u], ss[j + 16 * u], a4[u]);
+      j += 64;
+    }
     for (; j + 48 < m; j += 64) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) a4[u] = vfma(X[i + (j + 16 * u) * ldx], ss[j + 16 * u], a4[u]);
