@@ -29,18 +29,24 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # the timed region brackets every PROFILE_EVERY-th launch of each pass over A
 # with HIP events (the sampled launches give the kernel's average duration)
 PROFILE_EVERY = 4
+# launch plans tuned on an MI355X for the default workload (written by
+# `bench.py --plans-out`), so that every run times the same kernel variants
+DEFAULT_PLANS = os.path.join(ROOT, "paper_0905_4745_amd", "plans", "mi355x.json")
 
 # HBM bytes per live launch of the fused pass, from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE on this workload, each scaled by what the same counter reads for a
 # plain 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the
 # kernel source it was measured on: a changed source reports null.
 MEASURED_TRAFFIC = {
-    "k_gram": {"bytes": 541.48e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-               "sha256": "ee16c9fce7e93793dead1a5d876914c1ee0e41d1589e29af07dbce91ca23c8d3"},
+    "k_gram": {"bytes": 539.24e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
+               "sha256": "e44c3a67bab6b307ca94d9cb6dc4cea233fd50149de4cf8c8b99da64f999017b",
+               "plan_key": "gram/0/512/65536/0", "plan": 131328},
 }
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, plans):
+    """Counter-measured HBM bytes per launch, while the kernel source and the
+    launch plan this run chose are the ones the counters were taken with."""
     import hashlib
     rec = MEASURED_TRAFFIC.get(kernel)
     if rec is None:
@@ -48,6 +54,8 @@ def measured_traffic(kernel):
     with open(os.path.join(ROOT, rec["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
             return None
+    if plans.get(rec["plan_key"]) != rec["plan"]:
+        return None
     return rec["bytes"]
 
 
@@ -70,6 +78,11 @@ def parse():
     ap.add_argument("--streams", type=int, default=8, help="batched: concurrent lanes")
     ap.add_argument("--no-tune", action="store_true", help="built-in launch plans instead of tuned ones")
     ap.add_argument("--plans-out", default=None, help="write the tuned launch plans (JSON) here")
+    ap.add_argument("--plans-in", default=DEFAULT_PLANS if os.path.exists(DEFAULT_PLANS) else None,
+                    help="load launch plans (JSON, as written by --plans-out) before the warm-up; "
+                         "shapes found there are not tuned again (default: the MI355X table "
+                         "shipped with the package, when present)")
+    ap.add_argument("--no-plans-in", action="store_true", help="tune every shape on the live operands")
     return ap.parse_args()
 
 
@@ -124,6 +137,9 @@ def main():
 
     # launch plans are tuned on the first warm-up solve (timed candidates on
     # the live operands, outside the timed region) and reused afterwards
+    if args.plans_in and not args.no_plans_in:
+        log(f"[bench] launch plans from {args.plans_in}")
+        api.plans_load(args.plans_in)
     opts = api.SolveOptions(tune=0 if args.no_tune else 1)
     log(f"[bench] warmup {args.warmup}")
     for s in range(args.warmup):
@@ -190,6 +206,7 @@ def main():
                          f"each, took {c1 - c0:.2f} s"}
         log(f"[bench] CPU oracle {done} solves in {c1 - c0:.2f} s on {threads} threads")
 
+    plans = plans_dump(api, args)
     out = {
         "metric": "solves/s at rel-err <= 1e-10 (with HBM GB/s per A-pass)",
         "value": solves_per_s,
@@ -208,7 +225,7 @@ def main():
                    "m": m, "n": n, "l": l, "N": N, "eps": eps, "kappa": args.kappa},
         "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, plans),
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_us": avg_s * 1e6},
         "kernels": kernel_table,
@@ -216,7 +233,7 @@ def main():
         "cg_iters": iters,
         "rel_err": rel_err,
         "cpu_baseline": cpu,
-        "plans": plans_dump(api, args),
+        "plans": plans,
     }
     print(json.dumps(out), flush=True)
 
@@ -419,6 +436,9 @@ def main_mixed(args):
         d, idx = synth.draw_srft(N, l, seed=3000 + s_)
         draws.append((torch.from_numpy(d).to(dev), torch.from_numpy(idx).to(dev)))
     torch.cuda.synchronize()
+    if args.plans_in and not args.no_plans_in:
+        log(f"[bench] launch plans from {args.plans_in}")
+        api.plans_load(args.plans_in)
     opts = api.SolveOptions(tune=0 if args.no_tune else 1)
     log(f"[bench] warmup {args.warmup}")
     for s_ in range(args.warmup):

@@ -82,7 +82,9 @@ typedef struct {
   int32_t max_iter;      /* cap on CG iterations (per refinement step)      [1000] */
   int32_t max_refine;    /* mixed precision: cap on FP64 refinement steps     [40] */
   int32_t check_every;   /* iterations enqueued between host reads of the
-                            device stop flag                                  [8] */
+                            device stop flag; 0 = 2 for one right-hand side
+                            (each read overlaps the next batch), 8 for the
+                            block and batched forms                          [0] */
   int32_t inner_digits;  /* mixed precision: decimal digits each low-precision
                             inner solve gains                                 [4] */
   int32_t block;         /* several right-hand sides: 0 = automatic (block form

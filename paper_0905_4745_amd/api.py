@@ -117,7 +117,7 @@ class SolveOptions:
     stop_rule: int = 0
     max_iter: int = 1000
     max_refine: int = 40
-    check_every: int = 8
+    check_every: int = 0  # 0: library default (2 for one RHS, 8 for block/batched)
     inner_digits: int = 4
     block: int = 0  # several RHS: 0 automatic, 1 one at a time, 2 block form
     streams: int = 8  # batched: systems solved concurrently

@@ -107,16 +107,20 @@ bool is_single(int dtype) { return dtype == MN_C64 || dtype == MN_F32; }
 int compute_cplx_dtype(int dtype) { return is_single(dtype) ? 1 : 0; }  // twiddle table slot
 
 // W_N^k = exp(-2 pi i k / N), k < N, computed in long double and rounded,
-// followed by the compact table W_{N1}^k = W_N^{k N2}, k < N1, of the
-// four-step split N = N1 N2 (N2 = 2^floor(log2(N) / 2)).
+// followed by the compact tables W_{N1'}^k = W_N^{k N / N1'}, k < N1', for
+// the four-step splits N1' = N1, 2 N1, 4 N1 (N1 = N / 2^floor(log2(N) / 2)).
 const void* twiddles(mn_handle h, int64_t N, bool single) {
   Twiddle& t = h->tw[{N, single ? 1 : 0}];
   if (t.N == N && t.p) return t.p;
   const size_t es = single ? 8 : 16;
   int lg = 0;
   while (((int64_t)1 << lg) < N) ++lg;
-  const int64_t N2 = (int64_t)1 << (lg / 2), N1 = N >> (lg / 2);
-  std::vector<unsigned char> host((size_t)(N + N1) * es);
+  const int64_t N1 = N >> (lg / 2);
+  // compact tables W_{N1'}^k for N1' = N1, 2 N1, 4 N1 (where N1' <= N)
+  int64_t extra = 0;
+  for (int s = 0; s < 3; ++s)
+    if ((N1 << s) <= N) extra += N1 << s;
+  std::vector<unsigned char> host((size_t)(N + extra) * es);
   const long double two_pi = 6.283185307179586476925286766559005768L;
   for (int64_t k = 0; k < N; ++k) {
     const long double a = two_pi * (long double)k / (long double)N;
@@ -129,7 +133,13 @@ const void* twiddles(mn_handle h, int64_t N, bool single) {
       memcpy(&host[(size_t)k * es], v, es);
     }
   }
-  for (int64_t k = 0; k < N1; ++k) memcpy(&host[(size_t)(N + k) * es], &host[(size_t)(k * N2) * es], es);
+  int64_t off = N;
+  for (int s = 0; s < 3; ++s) {
+    const int64_t L = N1 << s;
+    if (L > N) break;
+    for (int64_t k = 0; k < L; ++k) memcpy(&host[(size_t)(off + k) * es], &host[(size_t)(k * (N / L)) * es], es);
+    off += L;
+  }
   ck(hipMalloc(&t.p, host.size()));
   ck(hipMemcpy(t.p, host.data(), host.size(), hipMemcpyHostToDevice));
   t.N = N;
@@ -252,10 +262,11 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   // picks 16 .. 512 MB (larger chunks give each launch more workgroups to
   // overlap loads with transforms)
   // plan: MB of intermediate per chunk (low 16 bits), bit 16 set: 2048
-  // elements per workgroup instead of 4096
+  // elements per workgroup instead of 4096, bits 17-18: four-step split
   auto run = [&](int pl) {
     const int mb = pl & 0xFFFF;
     a.wg_elems = (pl >> 16) & 1 ? 2048 : 4096;
+    a.split = (pl >> 17) & 3;
     int64_t chunk = ((int64_t)mb << 20) / (N * ces);
     if (chunk < 1) chunk = 1;
     if (chunk > m) chunk = m;
@@ -265,9 +276,14 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   };
   int mb = 64;
   const std::string key = plan_key("sketch_chunk_mb", dtype, m, N, 0);
-  if (o)
-    mb = plan_get(h, *o, key, {64, 16, 32, 128, 256, 512, 0x10000 | 64, 0x10000 | 128, 0x10000 | 256, 0x10000 | 512},
-                  run);
+  if (o) {
+    std::vector<int> cands{64, 16, 32};
+    for (int sp : {0, 1, 2})
+      for (int c : {64, 128, 256, 512})
+        if (sp || c != 64) cands.push_back((sp << 17) | c);
+    cands.push_back(0x10000 | 512);
+    mb = plan_get(h, *o, key, cands, run);
+  }
   else plan_find(h, key, &mb);
   run(mb);
 }
@@ -461,10 +477,13 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
           for (int wg : {512, 256, 1024}) cands.push_back(wg | nw | il | ww);
     gram_plan = plan_get(h, c.o, plan_key("gram", c.bulk, c.m, c.n, c.wide_acc ? 1 : 0), cands, run);
   }
+  // the state is read one batch late (below), so short batches cost no idle
+  // time and bound the launches enqueued after the stop
+  const int ce = c.o.check_every > 0 ? c.o.check_every : 2;
   int enqueued = 0, snap = 0;
   bool pending = false;
   while (true) {
-    for (int k = 0; k < c.o.check_every; ++k) {
+    for (int k = 0; k < ce; ++k) {
       if (fused) {
         GramArgs ga{};
         ga.A = c.Ab;
@@ -538,7 +557,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
       ck(launch_cg_step(is_complex(c.dtype), a, h->stream));
       v.par ^= 1;
     }
-    enqueued += c.o.check_every;
+    enqueued += ce;
     // the state after this batch is copied back asynchronously and read one
     // batch later, so the host never leaves the stream idle while it checks
     // the stop flag; after the stop, the kernels of the batch still in
@@ -554,7 +573,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
     }
     pending = true;
     snap ^= 1;
-    if (enqueued > max_iter + 3 * c.o.check_every) {  // cannot happen: the kernels cap iterations
+    if (enqueued > max_iter + 3 * ce) {  // cannot happen: the kernels cap iterations
       read_state(h, v.st);
       break;
     }
@@ -861,7 +880,7 @@ int solve_block(const SolveCtx& c, const void* b, int64_t ldb, int kc, void* x, 
     int64_t rec_base[8];
     std::copy(h->prof_seen, h->prof_seen + 8, rec_base);
     while (true) {
-      for (int it = 0; it < c.o.check_every; ++it) {
+      for (int it = 0; it < (c.o.check_every > 0 ? c.o.check_every : 8); ++it) {
         BfGemmArgs g1{};  // W = A* P (transposed planes, conjugated)
         g1.Ahi = t_hi;
         g1.Alo = t_lo;
@@ -945,7 +964,6 @@ mn_opts resolve_opts(const mn_opts* o) {
   if (r.alpha == 0.0) r.alpha = 4.0;
   if (r.max_iter == 0) r.max_iter = 1000;
   if (r.max_refine == 0) r.max_refine = 40;
-  if (r.check_every == 0) r.check_every = 8;
   if (r.inner_digits == 0) r.inner_digits = 4;
   if (r.streams == 0) r.streams = 8;
   return r;
@@ -955,7 +973,7 @@ bool opts_valid(const mn_opts& o) {
   return o.alpha > 1.0 && (o.stop_rule == 0 || o.stop_rule == 1) && o.max_iter > 0 && o.max_refine > 0 &&
          o.block >= 0 && o.block <= 2 && o.streams > 0 && o.streams <= 64 && (o.precond == 0 || o.precond == 1) &&
          (o.tune == 0 || o.tune == 1) && (o.batch_form == 0 || o.batch_form == 1) &&
-         o.check_every > 0 && o.check_every <= 1024 && o.inner_digits > 0 && o.inner_digits <= 12;
+         o.check_every >= 0 && o.check_every <= 1024 && o.inner_digits > 0 && o.inner_digits <= 12;
 }
 
 int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const void* A_lo,
@@ -1398,8 +1416,9 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   };
   auto inner_loop = [&]() {
     int guard = 0;
+    const int ce = o.check_every > 0 ? o.check_every : 8;
     while (true) {
-      for (int it = 0; it < o.check_every; ++it) {
+      for (int it = 0; it < ce; ++it) {
         const BLaunch gl[4] = {L(gramR[0]), L(gramR[1]), L(gramR[2]), L(gramR[3])};
         ck(launch_b_gram(bulk, gl, L(gred), st));
         ck(launch_b_cg(cplx, L(cgs), L(cgp), 0, 2, 0, par, cg_lds, st));
@@ -1407,7 +1426,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       }
       read_states();
       if (all_done(false)) break;
-      if ((guard += o.check_every) > o.max_iter + 2 * o.check_every) break;  // the kernels cap iterations
+      if ((guard += ce) > o.max_iter + 2 * ce) break;  // the kernels cap iterations
     }
   };
   if (mixed) {

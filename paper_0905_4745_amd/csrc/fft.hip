@@ -15,10 +15,12 @@
 //     twiddles W_N^{n1 k2}; pass 2 does the N1-point FFTs along the rows of
 //     the intermediate and scatters the kept outputs into S through the
 //     inverse subsample map.
-// The twiddle table holds W_N^k (k < N) followed by W_{N1}^k (k < N1): the
-// four-step stages and the W_N^{n1 k2} = W_N^{rem} W_{N2}^{q} factors
-// (n1 k2 = q N1 + rem) read only the first N1 entries and that compact
-// part, both small enough to stay in the vector L1 cache.
+// The twiddle table holds W_N^k (k < N) followed by compact tables W_{N1}^k
+// (k < N1) for the splits N1 = N1_0, 2 N1_0, 4 N1_0 (N1_0 = N / 2^floor(log2(N)/2)):
+// the four-step stages and the W_N^{n1 k2} = W_N^{rem} W_{N2}^{q} factors
+// (n1 k2 = q N1 + rem) read only the first N1 entries and one compact
+// table, small enough to stay in cache.  A split with a shorter N2 gives
+// pass 1 longer contiguous row segments (4096 / N2 elements).
 // Both use the same batched Stockham FFT: 256 threads, 16 elements per
 // thread, radix-16/8/4/2 butterflies in registers, LDS between stages.
 #include "common.hpp"
@@ -271,7 +273,7 @@ template <typename V, typename C>
 __device__ __forceinline__ void k_sketch_cols_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t row0, int64_t m,
                                                      int64_t n, int N1, FftPlan pl2, int B,
                                                      const void* __restrict__ d, C* __restrict__ Y,
-                                                     const C* __restrict__ tw) {
+                                                     const C* __restrict__ tw, const C* __restrict__ twc) {
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
   const int N2 = pl2.L;
@@ -303,7 +305,6 @@ __device__ __forceinline__ void k_sketch_cols_body(const Bk bk, const V* __restr
   const int b = threadIdx.x / tpf, tl = threadIdx.x % tpf;
   const bool active = b < B;
   C* buf = sm + (active ? b : 0) * Lp;
-  const C* twc = tw + N;  // W_{N1}^k, k < N1
   {
     int Ns = 1;
     const int twm = N1 / N2;  // W_N2^k = W_N1^{k N1 / N2}
@@ -343,8 +344,8 @@ template <typename V, typename C>
 __global__ void __launch_bounds__(256) k_sketch_cols(const V* __restrict__ A, int64_t lda, int64_t row0, int64_t m,
                                                      int64_t n, int N1, FftPlan pl2, int B,
                                                      const void* __restrict__ d, C* __restrict__ Y,
-                                                     const C* __restrict__ tw) {
-  k_sketch_cols_body<V, C>(bk_hw(), A, lda, row0, m, n, N1, pl2, B, d, Y, tw);
+                                                     const C* __restrict__ tw, const C* __restrict__ twc) {
+  k_sketch_cols_body<V, C>(bk_hw(), A, lda, row0, m, n, N1, pl2, B, d, Y, tw, twc);
 }
 
 // ---------------------- four-step, pass 2: rows + gather ---------------------
@@ -384,7 +385,7 @@ __device__ __forceinline__ void k_sketch_rows_body(const Bk bk, const C* __restr
   C* buf = sm + (active ? b : 0) * Lp;
   {
     int Ns = 1;
-    const C* twc = tw + N;  // W_{N1}^k, k < N1
+    const C* twc = tw;  // W_{N1}^k, k < N1
     for (int s = 0; s < pl1.nst; ++s) {
       const int R = pl1.radix[s];
       const int tl_eff = active ? tl : tpf;
@@ -508,11 +509,16 @@ static hipError_t sketch_impl(const SketchArgs& a, hipStream_t st) {
                        a.l, S, a.lds, tw, scale);
     return hipGetLastError();
   }
-  // four-step: N = N1 * N2, N1 >= N2, both transformed whole in LDS
+  // four-step: N = N1 * N2, N1 >= N2, both transformed whole in LDS; split
+  // s halves N2 s times (fewer for shapes where N1 would outgrow LDS)
   int k = 0;
   while ((1 << k) < N) ++k;
-  const int N2 = 1 << (k / 2), N1 = N >> (k / 2);
+  const int N2_0 = 1 << (k / 2), N1_0 = N >> (k / 2);
+  int split = a.split < 0 ? 0 : (a.split > 2 ? 2 : a.split);
+  while (split > 0 && ((N1_0 << split) > Lmax || (N2_0 >> split) < 16)) --split;
+  const int N2 = N2_0 >> split, N1 = N1_0 << split;
   if (N1 > Lmax) return hipErrorInvalidValue;
+  const C* twc = tw + N + (split == 0 ? 0 : split == 1 ? N1_0 : 3 * N1_0);
   FftPlan pl1 = make_plan(N1), pl2 = make_plan(N2);
   // fewer elements per workgroup (half the threads idle in the transform,
   // all of them load) halve the LDS footprint and double the workgroups
@@ -529,9 +535,9 @@ static hipError_t sketch_impl(const SketchArgs& a, hipStream_t st) {
     const int64_t rows = (a.m - r0) < a.chunk_rows ? (a.m - r0) : a.chunk_rows;
     dim3 g1((unsigned)(N1 / Bc), (unsigned)rows);
     hipLaunchKernelGGL((k_sketch_cols<V, C>), g1, dim3(256), smc, st, A, a.lda, r0, a.m, a.n, N1, pl2, Bc, a.d, Y,
-                       tw);
+                       tw, twc);
     dim3 g2((unsigned)(N2 / Br), (unsigned)rows);
-    hipLaunchKernelGGL((k_sketch_rows<V, C>), g2, dim3(256), smr, st, Y, r0, a.m, N2, pl1, Br, a.inv, S, a.lds, tw,
+    hipLaunchKernelGGL((k_sketch_rows<V, C>), g2, dim3(256), smr, st, Y, r0, a.m, N2, pl1, Br, a.inv, S, a.lds, twc,
                        scale);
   }
   return hipGetLastError();
@@ -586,7 +592,7 @@ __global__ void __launch_bounds__(256) kb_sketch_cols(const BSys* __restrict__ s
   const BSys& s = sys[i];
   k_sketch_cols_body<V, C>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const V*>(s.Ab),
                            s.ldab, 0, s.m, s.n, s.N1, s.pl_b, s.fft_bb, s.d, reinterpret_cast<C*>(s.Y),
-                           reinterpret_cast<const C*>(s.tw));
+                           reinterpret_cast<const C*>(s.tw), reinterpret_cast<const C*>(s.tw) + s.N);
 }
 
 template <typename V, typename C>
@@ -597,7 +603,7 @@ __global__ void __launch_bounds__(256) kb_sketch_rows(const BSys* __restrict__ s
   using R = typename VT<C>::real;
   k_sketch_rows_body<V, C>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const C*>(s.Y), 0,
                            s.m, s.N2, s.pl_a, s.fft_ba, s.inv, reinterpret_cast<V*>(s.S), s.l,
-                           reinterpret_cast<const C*>(s.tw), (R)(1.0 / sqrt((double)s.N)));
+                           reinterpret_cast<const C*>(s.tw) + s.N, (R)(1.0 / sqrt((double)s.N)));
 }
 
 __global__ void kb_fill_inv(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys) {

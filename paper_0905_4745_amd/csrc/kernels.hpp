@@ -41,6 +41,7 @@ struct SketchArgs {
   void* work;           // four-step intermediate, chunk_rows * N complex
   int64_t chunk_rows;
   int wg_elems;         // four-step: elements per workgroup (4096 or 2048; 0 = 4096)
+  int split;            // four-step: N2 = 2^(floor(log2 N / 2) - split), split 0..2
 };
 hipError_t launch_sketch(int dtype, const SketchArgs& a, hipStream_t st);
 int sketch_max_log2n(int dtype);  // largest log2(N) the four-step supports

@@ -82,3 +82,34 @@ def test_sketch_invalid_idx_rejected():
     with pytest.raises(api.MinnormError) as e:
         api.srft_sketch(A, d, np.array([0, 3, 5, 8], dtype=np.int32), 8)
     assert e.value.status == -10
+
+
+@pytest.mark.parametrize("m,n,N,l", [(17, 65536, 65536, 68), (3, 100000, 131072, 12), (5, 8192, 8192, 20)])
+@pytest.mark.parametrize("kind", ["c128", "f32"])
+@pytest.mark.parametrize("split", [1, 2])
+def test_sketch_four_step_splits(m, n, N, l, kind, split, tmp_path):
+    """Each four-step split (N2 halved `split` times) forced through a loaded
+    plan gives the same sketch, to the same bar."""
+    import json
+    import torch
+    from paper_0905_4745_amd import api
+    say(f"sketch split {split} {kind} m={m} n={n} N={N}")
+    real = kind.startswith("f")
+    g = np.random.default_rng(m * 11 + n)
+    A = g.standard_normal((m, n)) if real else synth.complex_gaussian(g, (m, n))
+    d, idx = synth.draw_srft(N, l, seed=N + 3 * l, real=real)
+    tdt = {"c128": torch.complex128, "f32": torch.float32}[kind]
+    dcode = {"c128": 0, "f32": 3}[kind]
+    plan = (split << 17) | 64
+    path = tmp_path / "plans.json"
+    path.write_text(json.dumps({"format": "minnorm-plans-1",
+                                "plans": {f"sketch_chunk_mb/{dcode}/{m}/{N}/0": plan}, "best_ms": {}}))
+    api.plans_load(str(path))
+    At = to_dev(A, tdt)
+    A_used = to_np(At).astype(np.float64 if real else np.complex128)
+    S = to_np(api.srft_sketch(At, d, idx, N))
+    ref = oracle.sketch_real(A_used, d, idx, N) if real else oracle.sketch(A_used, d, idx, N)
+    u = U32 if kind == "f32" else U64
+    err = _colerr(S.astype(ref.dtype), ref)
+    say(f"  col rel err {err:.2e}")
+    assert err <= 20 * u * max(np.log2(N), 1)
