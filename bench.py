@@ -39,7 +39,7 @@ DEFAULT_PLANS = os.path.join(ROOT, "paper_0905_4745_amd", "plans", "mi355x.json"
 # kernel source it was measured on: a changed source reports null.
 MEASURED_TRAFFIC = {
     "k_gram": {"bytes": 539.24e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-               "sha256": "e44c3a67bab6b307ca94d9cb6dc4cea233fd50149de4cf8c8b99da64f999017b",
+               "sha256": "b1b260aecc8ddbcc2091c23776b441da951a79723a361c112ce9d90714a96e35",
                "plan_key": "gram/0/512/65536/0", "plan": 131328},
 }
 

@@ -10,6 +10,8 @@
 // are bitwise reproducible.  u comes in FP64 (the iteration's vectors are kept
 // in FP64); A and w are in A's precision; partial sums of q are written in
 // FP64.  All kernels return at once when the iteration's stop flag is set.
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "batch_dev.hpp"
@@ -379,17 +381,15 @@ static hipError_t adj_run(const AdjArgs& a, hipStream_t st) {
   const W* u = reinterpret_cast<const W*>(a.u);
   C* w = reinterpret_cast<C*>(a.w);
   W* wide = reinterpret_cast<W*>(a.w_wide);
-  if (a.ev_begin) (void)hipEventRecord(a.ev_begin, st);
+  // the timing events (if any) belong to the dispatch itself
   if (rs == 1 && wide == nullptr) {
-    hipLaunchKernelGGL((k_gemv_adj<V, C, W, VEC>), dim3((unsigned)nb, 1), dim3(256), 0, st, A, a.lda, a.m, a.n, u,
-                       rps, w, a.flag);
-    if (a.ev_end) (void)hipEventRecord(a.ev_end, st);
+    hipExtLaunchKernelGGL((k_gemv_adj<V, C, W, VEC>), dim3((unsigned)nb, 1), dim3(256), 0, st, a.ev_begin, a.ev_end,
+                          0, A, a.lda, a.m, a.n, u, rps, w, a.flag);
     return hipGetLastError();
   }
   C* part = reinterpret_cast<C*>(a.part);
-  hipLaunchKernelGGL((k_gemv_adj<V, C, W, VEC>), dim3((unsigned)nb, (unsigned)rs), dim3(256), 0, st, A, a.lda, a.m,
-                     a.n, u, rps, part, a.flag);
-  if (a.ev_end) (void)hipEventRecord(a.ev_end, st);
+  hipExtLaunchKernelGGL((k_gemv_adj<V, C, W, VEC>), dim3((unsigned)nb, (unsigned)rs), dim3(256), 0, st, a.ev_begin,
+                        a.ev_end, 0, A, a.lda, a.m, a.n, u, rps, part, a.flag);
   hipLaunchKernelGGL((k_sum_slabs<C, W>), dim3((unsigned)ceil_div(a.n, 256)), dim3(256), 0, st, part, (int)rs, a.n,
                      w, wide, a.flag);
   return hipGetLastError();
@@ -413,11 +413,9 @@ static hipError_t fwd_run(const FwdArgs& a, hipStream_t st) {
   int64_t chunk = ceil_div(a.n, cs);
   chunk = ceil_div(chunk, 256 * VEC) * (256 * VEC);
   cs = ceil_div(a.n, chunk);
-  if (a.ev_begin) (void)hipEventRecord(a.ev_begin, st);
-  hipLaunchKernelGGL((k_gemv_fwd<V, C, W, RB, VEC>), dim3((unsigned)cs, (unsigned)rb), dim3(256), 0, st,
-                     reinterpret_cast<const V*>(a.A), a.lda, a.m, a.n, reinterpret_cast<const C*>(a.w), chunk,
-                     reinterpret_cast<W*>(a.qpart), a.flag);
-  if (a.ev_end) (void)hipEventRecord(a.ev_end, st);
+  hipExtLaunchKernelGGL((k_gemv_fwd<V, C, W, RB, VEC>), dim3((unsigned)cs, (unsigned)rb), dim3(256), 0, st,
+                        a.ev_begin, a.ev_end, 0, reinterpret_cast<const V*>(a.A), a.lda, a.m, a.n,
+                        reinterpret_cast<const C*>(a.w), chunk, reinterpret_cast<W*>(a.qpart), a.flag);
   if (a.chunks_out) *a.chunks_out = (int)cs;
   return hipGetLastError();
 }
@@ -441,33 +439,31 @@ static hipError_t gram_go(const GramArgs& a, hipStream_t st) {
   const V* A = reinterpret_cast<const V*>(a.A);
   const U* p = reinterpret_cast<const U*>(a.p);
   U* qpart = reinterpret_cast<U*>(a.qpart);
-  if (a.ev_begin) (void)hipEventRecord(a.ev_begin, st);
   if (a.wide_wg) {
     // 1024 threads: 128 row groups, RPT rows each
     if (a.m <= 128)
-      hipLaunchKernelGGL((k_gram<V, C, U, CPT, 1, 1024, VEC>), dim3((unsigned)G), dim3(1024), 0, st, A, a.lda, a.m, a.n,
-                         p, spw, nstrips, qpart, a.flag, a.interleave);
+      hipExtLaunchKernelGGL((k_gram<V, C, U, CPT, 1, 1024, VEC>), dim3((unsigned)G), dim3(1024), 0, st, a.ev_begin,
+                            a.ev_end, 0, A, a.lda, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
     else if (a.m <= 256)
-      hipLaunchKernelGGL((k_gram<V, C, U, CPT, 2, 1024, VEC>), dim3((unsigned)G), dim3(1024), 0, st, A, a.lda, a.m, a.n,
-                         p, spw, nstrips, qpart, a.flag, a.interleave);
+      hipExtLaunchKernelGGL((k_gram<V, C, U, CPT, 2, 1024, VEC>), dim3((unsigned)G), dim3(1024), 0, st, a.ev_begin,
+                            a.ev_end, 0, A, a.lda, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
     else
-      hipLaunchKernelGGL((k_gram<V, C, U, CPT, 4, 1024, VEC>), dim3((unsigned)G), dim3(1024), 0, st, A, a.lda, a.m, a.n,
-                         p, spw, nstrips, qpart, a.flag, a.interleave);
+      hipExtLaunchKernelGGL((k_gram<V, C, U, CPT, 4, 1024, VEC>), dim3((unsigned)G), dim3(1024), 0, st, a.ev_begin,
+                            a.ev_end, 0, A, a.lda, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
   } else if (a.m <= 64) {
     // 512 threads: 64 row groups, RPT rows each
-    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 1, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
-                       spw, nstrips, qpart, a.flag, a.interleave);
+    hipExtLaunchKernelGGL((k_gram<V, C, U, CPT, 1, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, a.ev_begin,
+                          a.ev_end, 0, A, a.lda, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
   } else if (a.m <= 128) {
-    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 2, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
-                       spw, nstrips, qpart, a.flag, a.interleave);
+    hipExtLaunchKernelGGL((k_gram<V, C, U, CPT, 2, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, a.ev_begin,
+                          a.ev_end, 0, A, a.lda, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
   } else if (a.m <= 256) {
-    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 4, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
-                       spw, nstrips, qpart, a.flag, a.interleave);
+    hipExtLaunchKernelGGL((k_gram<V, C, U, CPT, 4, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, a.ev_begin,
+                          a.ev_end, 0, A, a.lda, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
   } else {
-    hipLaunchKernelGGL((k_gram<V, C, U, CPT, 8, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m, a.n, p,
-                       spw, nstrips, qpart, a.flag, a.interleave);
+    hipExtLaunchKernelGGL((k_gram<V, C, U, CPT, 8, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, a.ev_begin,
+                          a.ev_end, 0, A, a.lda, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
   }
-  if (a.ev_end) (void)hipEventRecord(a.ev_end, st);
   hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64), 8), dim3(256), 0, st, qpart, (int)G,
                      a.m, reinterpret_cast<U*>(a.q), a.flag);
   return hipGetLastError();
