@@ -122,25 +122,28 @@ __host__ __device__ inline int lds_stride(int L) { return L + (L >> 4) + 1; }
 //   L   transform length, Ns product of the radices already applied,
 //   tpf threads per FFT, tl this thread's index within its FFT,
 //   tw  table of W_Nt^k, k < Nt, twm = Nt / L.
+// All sizes are powers of two: index arithmetic uses shifts and masks of the
+// (wave-uniform) base-2 logarithms rather than integer division.
 template <int R, typename C>
 __device__ inline void fft_stage(C* buf, int L, int Ns, int tpf, int tl, const C* __restrict__ tw, int twm) {
   constexpr int SMAX = 16 / R;
-  const int slots = (L / R) / tpf;  // 16 / R when E = 16
+  constexpr int LGR = R == 16 ? 4 : (R == 8 ? 3 : (R == 4 ? 2 : 1));
+  const int lgL = __builtin_ctz((unsigned)L), lgNs = __builtin_ctz((unsigned)Ns);
+  const int lgtpf = __builtin_ctz((unsigned)tpf), lgtwm = __builtin_ctz((unsigned)twm);
+  const int slots = L >> (LGR + lgtpf);  // 16 / R when E = 16
+  const int LR = L >> LGR;
+  // W_{Ns R}^{r jm} = W_Nt^{r jm Nt/(Ns R)}, Nt / (Ns R) = (L / (Ns R)) twm
+  const int lge = lgL - lgNs - LGR + lgtwm;
   C v[16];
-  const int LR = L / R;
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) {
     if (s < slots && tl < tpf) {
-      const int j = tl + s * tpf;
-      const int jm = j % Ns;
+      const int j = tl + (s << lgtpf);
+      const int jm = j & (Ns - 1);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         C x = buf[lpad(j + r * LR)];
-        if (r > 0 && jm > 0) {
-          // W_{Ns R}^{r jm} = W_Nt^{r jm Nt/(Ns R)}
-          const int e = r * jm * (L / (Ns * R)) * twm;
-          x = vmul(x, tw[e]);
-        }
+        if (r > 0 && jm > 0) x = vmul(x, tw[(r * jm) << lge]);
         v[s * R + r] = x;
       }
       dftR<R>(v + s * R);
@@ -150,11 +153,11 @@ __device__ inline void fft_stage(C* buf, int L, int Ns, int tpf, int tl, const C
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) {
     if (s < slots && tl < tpf) {
-      const int j = tl + s * tpf;
-      const int jm = j % Ns;
-      const int d0 = (j / Ns) * Ns * R + jm;
+      const int j = tl + (s << lgtpf);
+      const int jm = j & (Ns - 1);
+      const int d0 = ((j >> lgNs) << (lgNs + LGR)) + jm;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lpad(d0 + r * Ns)] = v[s * R + out_slot<R>(r)];
+      for (int r = 0; r < R; ++r) buf[lpad(d0 + (r << lgNs))] = v[s * R + out_slot<R>(r)];
     }
   }
   __syncthreads();
@@ -208,9 +211,11 @@ __device__ __forceinline__ void k_sketch_small_body(const Bk bk, const V* __rest
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
   const int L = pl.L;
+  const int lgL = __builtin_ctz((unsigned)L);
   const int Lp = lds_stride(L);
   const int E = L < 16 ? L : 16;
   const int tpf = L / E;
+  const int lgtpf = __builtin_ctz((unsigned)tpf);
   const int64_t row0 = (int64_t)bk.x * B;
   // load: consecutive threads read consecutive entries of one row; all of a
   // thread's loads are issued before any is used
@@ -219,18 +224,18 @@ __device__ __forceinline__ void k_sketch_small_body(const Bk bk, const V* __rest
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int t = threadIdx.x + u * 256;
-      const int b = t / L, pos = t % L;
+      const int b = t >> lgL, pos = t & (L - 1);
       const int64_t i = row0 + b;
       v[u] = (t < B * L && i < m) ? load_row_entry<V, C>(A + i * lda, pos, n, d) : vzero<C>();
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int t = threadIdx.x + u * 256;
-      if (t < B * L) sm[(t / L) * Lp + lpad(t % L)] = v[u];
+      if (t < B * L) sm[(t >> lgL) * Lp + lpad(t & (L - 1))] = v[u];
     }
   }
   __syncthreads();
-  const int b = threadIdx.x / tpf, tl = threadIdx.x % tpf;
+  const int b = threadIdx.x >> lgtpf, tl = threadIdx.x & (tpf - 1);
   const bool active = b < B;
   {
     // every thread must reach the stage barriers: inactive threads work on a
@@ -281,6 +286,7 @@ __device__ __forceinline__ void k_sketch_cols_body(const Bk bk, const V* __restr
   const int64_t i = row0 + bk.y;
   const int c0 = bk.x * B;
   const int64_t N = (int64_t)N1 * N2;
+  const int lgB = __builtin_ctz((unsigned)B);
   const V* row = A + i * lda;
   // load: consecutive threads take consecutive n1 (contiguous in memory);
   // B * N2 <= 4096 = 16 per thread, all issued before use
@@ -289,20 +295,21 @@ __device__ __forceinline__ void k_sketch_cols_body(const Bk bk, const V* __restr
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int t = threadIdx.x + u * 256;
-      const int bb = t % B, n2 = t / B;
-      const int64_t j = (int64_t)c0 + bb + (int64_t)N1 * n2;
+      const int bb = t & (B - 1), n2 = t >> lgB;
+      const int64_t j = (int64_t)(c0 + bb) + (int64_t)N1 * n2;
       v[u] = (t < B * N2 && i < m) ? load_row_entry<V, C>(row, j, n, d) : vzero<C>();
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int t = threadIdx.x + u * 256;
-      if (t < B * N2) sm[(t % B) * Lp + lpad(t / B)] = v[u];
+      if (t < B * N2) sm[(t & (B - 1)) * Lp + lpad(t >> lgB)] = v[u];
     }
   }
   __syncthreads();
   const int E = N2 < 16 ? N2 : 16;
   const int tpf = N2 / E;
-  const int b = threadIdx.x / tpf, tl = threadIdx.x % tpf;
+  const int lgtpf = __builtin_ctz((unsigned)tpf);
+  const int b = threadIdx.x >> lgtpf, tl = threadIdx.x & (tpf - 1);
   const bool active = b < B;
   C* buf = sm + (active ? b : 0) * Lp;
   {
@@ -327,7 +334,7 @@ __device__ __forceinline__ void k_sketch_cols_body(const Bk bk, const V* __restr
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int t = threadIdx.x + u * 256;
-    const unsigned e = (unsigned)(c0 + t % B) * (unsigned)(t / B);  // n1 k2 < N
+    const unsigned e = (unsigned)(c0 + (t & (B - 1))) * (unsigned)(t >> lgB);  // n1 k2 < N
     // W_N^e = W_N^{e mod N1} W_N2^{floor(e / N1)}
     wv[u] = (t < B * N2) ? vmul(tw[e & (unsigned)(N1 - 1)], twc[(e >> lg1) * r12]) : vzero<C>();
   }
@@ -335,7 +342,7 @@ __device__ __forceinline__ void k_sketch_cols_body(const Bk bk, const V* __restr
   for (int u = 0; u < 16; ++u) {
     const int t = threadIdx.x + u * 256;
     if (t < B * N2) {
-      const int bb = t % B, k2 = t / B;
+      const int bb = t & (B - 1), k2 = t >> lgB;
       Yi[(int64_t)k2 * N1 + c0 + bb] = vmul(sm[bb * Lp + lpad(k2)], wv[u]);
     }
   }
@@ -363,24 +370,28 @@ __device__ __forceinline__ void k_sketch_rows_body(const Bk bk, const C* __restr
   const int64_t N = (int64_t)N1 * N2;
   const int64_t i = row0 + bk.y;
   const int c0 = bk.x * B;
+  const int lgN1 = __builtin_ctz((unsigned)N1);
   const C* Yi = Y + (int64_t)bk.y * N;
   {
+    // rows c0 .. c0 + B - 1 of the N2 x N1 intermediate are contiguous
+    const C* blk = Yi + (int64_t)c0 * N1;
     C v[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int t = threadIdx.x + u * 256;
-      v[u] = (t < B * N1 && i < m) ? Yi[(int64_t)(c0 + t / N1) * N1 + t % N1] : vzero<C>();
+      v[u] = (t < B * N1 && i < m) ? blk[t] : vzero<C>();
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int t = threadIdx.x + u * 256;
-      if (t < B * N1) sm[(t / N1) * Lp + lpad(t % N1)] = v[u];
+      if (t < B * N1) sm[(t >> lgN1) * Lp + lpad(t & (N1 - 1))] = v[u];
     }
   }
   __syncthreads();
   const int E = N1 < 16 ? N1 : 16;
   const int tpf = N1 / E;
-  const int b = threadIdx.x / tpf, tl = threadIdx.x % tpf;
+  const int lgtpf = __builtin_ctz((unsigned)tpf);
+  const int b = threadIdx.x >> lgtpf, tl = threadIdx.x & (tpf - 1);
   const bool active = b < B;
   C* buf = sm + (active ? b : 0) * Lp;
   {
@@ -401,12 +412,12 @@ __device__ __forceinline__ void k_sketch_rows_body(const Bk bk, const C* __restr
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int t = threadIdx.x + u * 256;
-    pos[u] = (t < B * N1) ? inv[(int64_t)(c0 + t / N1) + (int64_t)N2 * (t % N1)] : -1;
+    pos[u] = (t < B * N1) ? inv[(int64_t)(c0 + (t >> lgN1)) + (int64_t)N2 * (t & (N1 - 1))] : -1;
   }
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int t = threadIdx.x + u * 256;
-    if (pos[u] >= 0) S[pos[u] + i * lds] = out_value<V, C>(sm[(t / N1) * Lp + lpad(t % N1)], scale);
+    if (pos[u] >= 0) S[pos[u] + i * lds] = out_value<V, C>(sm[(t >> lgN1) * Lp + lpad(t & (N1 - 1))], scale);
   }
 }
 template <typename V, typename C>
