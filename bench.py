@@ -268,6 +268,9 @@ def main_multirhs(args):
         draws.append((torch.from_numpy(d).to(dev), torch.from_numpy(idx).to(dev)))
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup}")
+    if args.plans_in and not args.no_plans_in:
+        log(f"[bench] launch plans from {args.plans_in}")
+        api.plans_load(args.plans_in)
     opts = api.SolveOptions(tune=0 if args.no_tune else 1)
     for s_ in range(args.warmup):
         d, idx = draws[s_]

@@ -169,6 +169,9 @@ int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* tot
  *                            per chunk of rows (low 16 bits: 16 .. 512) and
  *                            workgroup size in elements (bit 16 set: 2048,
  *                            else 4096);
+ * "gram_s/<dtype>/<m>/<l>/0"  Step 2's Gram matrix S* S: 0 on the FP64
+ *                            matrix cores, 1 register-tiled on the vector
+ *                            units (default 1 for m > 1024);
  * "block_fwd_wg/<dtype>/<m>/<n>/<k>"   block product A W: workgroups aimed
  *                            for when splitting its n columns (512..2048).
  * Plans are chosen by timing when mn_opts.tune = 1 (see there).

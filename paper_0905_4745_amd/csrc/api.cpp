@@ -335,22 +335,41 @@ int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 // and max|R_ii| / min|R_ii| <= 1e5; otherwise the caller uses the
 // Householder factorisation (which also classifies rank deficiency and
 // non-finite input).
-bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t lds, void* R64) {
+bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t lds, void* R64,
+                 const mn_opts* o) {
   hipStream_t st = h->stream;
   const bool cplx = is_complex(dtype);
   const int64_t W = cplx ? 16 : 8;
   void* G = ws(h, "gram_G", (size_t)(m * m * W));
-  const int64_t nz = cdiv(m, gram_col_block(dtype));
-  const int64_t tiles = cdiv(m, 128);
-  const int64_t wgs = std::max<int64_t>(1, tiles * nz / 2 + 1);
-  int64_t splits = std::min<int64_t>(std::max<int64_t>(cdiv(512, wgs), 1), cdiv(l, 64));
-  const int64_t ks = rup(cdiv(l, splits), 16);
-  splits = cdiv(l, ks);
-  const int64_t ldc = rup(m, 4);
-  double* Cp = nullptr;
-  if (splits > 1) Cp = (double*)ws(h, "gram_part", (size_t)(nz * splits * 128 * ldc * 8));
-  ck(launch_gram_s(dtype, S, lds, l, m, G, m, Cp, ldc, (int)splits, ks, st));
-  if (splits > 1) ck(launch_gram_fold(cplx, Cp, (int)splits, ldc, m, G, m, st));
+  // G = S* S: FP64 matrix-core product (plan 0) or register-tiled FP64
+  // product on the vector units (plan 1)
+  auto run = [&](int pl) {
+    if (pl == 1) {
+      const int64_t tiles = std::max<int64_t>(1, cdiv(m, 128) * cdiv(m, 64) / 2);
+      int64_t splits = std::min<int64_t>(std::min<int64_t>(std::max<int64_t>(cdiv(512, tiles), 1), 8), cdiv(l, 64));
+      const int64_t ks = rup(cdiv(l, splits), 8);
+      splits = cdiv(l, ks);
+      void* Cp = splits > 1 ? ws(h, "herk_part", (size_t)(herk_part_elems(m, (int)splits) * W)) : nullptr;
+      ck(launch_herk(dtype, S, lds, l, m, G, m, Cp, (int)splits, ks, st));
+      return;
+    }
+    const int64_t nz = cdiv(m, gram_col_block(dtype));
+    const int64_t tiles = cdiv(m, 128);
+    const int64_t wgs = std::max<int64_t>(1, tiles * nz / 2 + 1);
+    int64_t splits = std::min<int64_t>(std::max<int64_t>(cdiv(512, wgs), 1), cdiv(l, 64));
+    const int64_t ks = rup(cdiv(l, splits), 16);
+    splits = cdiv(l, ks);
+    const int64_t ldc = rup(m, 4);
+    double* Cp = nullptr;
+    if (splits > 1) Cp = (double*)ws(h, "gram_part", (size_t)(nz * splits * 128 * ldc * 8));
+    ck(launch_gram_s(dtype, S, lds, l, m, G, m, Cp, ldc, (int)splits, ks, st));
+    if (splits > 1) ck(launch_gram_fold(cplx, Cp, (int)splits, ldc, m, G, m, st));
+  };
+  int pl = m > 1024 ? 1 : 0;
+  const std::string key = plan_key("gram_s", dtype, m, l, 0);
+  if (o) pl = plan_get(h, *o, key, {pl, 1 - pl}, run);
+  else plan_find(h, key, &pl);
+  run(pl);
   int32_t* bad = (int32_t*)ws(h, "chol_bad", 16);
   ck(launch_fill0(bad, 16, st));
   void* Yd = ws(h, "chol_yd", (size_t)(chol_scratch_elems(m) * W));
@@ -1035,7 +1054,7 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   bool gram = false;
   if (o.precond == 0) {
     c.R = ws(h, "R64", (size_t)(m * m * wide_size(dtype)));
-    gram = gram_factor(h, c.bulk, l, m, S, l, c.R);
+    gram = gram_factor(h, c.bulk, l, m, S, l, c.R, &o);
     if (gram) rdt = wdt;
   }
   if (!gram) {

@@ -215,6 +215,12 @@ hipError_t launch_fill0(void* p, int64_t bytes, hipStream_t st);
 // Preconditioner from the Gram matrix (chol.hip, block.hip): G = S* S in
 // FP64, then R with R* R = G by blocked Cholesky (tiles of 32).
 int gram_col_block(int dtype);
+// G (FP64, upper triangle, ld ldg) = S* S on the vector units; with splits >
+// 1 the K range is split in pieces of ks and Cp holds herk_part_elems(m,
+// splits) FP64 (complex for complex data) partial entries.
+int64_t herk_part_elems(int64_t m, int splits);
+hipError_t launch_herk(int dtype, const void* S, int64_t lds, int64_t l, int64_t m, void* G, int64_t ldg, void* Cp,
+                       int splits, int64_t ks, hipStream_t st);
 hipError_t launch_gram_s(int dtype, const void* S, int64_t lds, int64_t l, int64_t m, void* G, int64_t ldg,
                          double* Cp, int64_t ldc, int splits, int64_t ks, hipStream_t st);
 hipError_t launch_gram_fold(bool cplx, const double* Cp, int splits, int64_t ldc, int64_t m, void* G, int64_t ldg,

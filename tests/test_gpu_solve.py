@@ -309,6 +309,38 @@ def test_gram_and_householder_factors_agree(kind):
     assert abs(ig["iters"] - ih["iters"]) <= max(1, ih["iters"] // 10)
 
 
+@pytest.mark.parametrize("kind,m,n", [("c128", 200, 8000), ("f64", 130, 5000), ("c64", 1100, 8800)])
+def test_gram_product_routes_agree(kind, m, n, tmp_path):
+    """Step 2's Gram matrix S* S on the FP64 matrix cores (plan 0) and on the
+    vector units (plan 1, with split-K partials for these shapes) gives the
+    same factor: both solves meet eps in the same number of iterations up to
+    one.  Ragged m (not a multiple of the 128 x 64 tile)."""
+    import json
+    from paper_0905_4745_amd import api
+    real = kind == "f64"
+    A, b, _ = synth.make_svd(m, n, 1e3, seed=23, complex_=not real)
+    if kind == "c64":
+        A = A.astype(np.complex64)
+    N = synth.next_pow2(n)
+    l = synth.sketch_width(m, N)
+    d, idx = synth.draw_srft(N, l, seed=23, real=real)
+    dcode = {"c128": 0, "c64": 1, "f64": 2}[kind]
+    key = f"gram_s/{dcode}/{m}/{l}/0"
+    res = {}
+    for plan in (0, 1):
+        path = tmp_path / f"plans{plan}.json"
+        path.write_text(json.dumps({"format": "minnorm-plans-1", "plans": {key: plan}, "best_ms": {}}))
+        api.plans_load(str(path))
+        res[plan] = _solve(A, b, 1e-10, d, idx, N)
+    p = oracle.refined_minnorm(A.astype(np.complex128) if kind == "c64" else A, b)
+    (x0, i0), (x1, i1) = res[0], res[1]
+    say(f"  {kind} m={m}: matrix-core iters {i0['iters']} err {rel(x0, p):.2e}; "
+        f"vector iters {i1['iters']} err {rel(x1, p):.2e}")
+    assert i0["status"] == 0 and i1["status"] == 0
+    assert rel(x0, p) <= 1e-10 and rel(x1, p) <= 1e-10
+    assert abs(i0["iters"] - i1["iters"]) <= 1
+
+
 def test_ill_conditioned_falls_back_and_meets_eps():
     """cond 1e7: the Gram route declines (diagonal spread beyond 1e5) and the
     Householder factor is used; the FP64 result still meets eps."""
