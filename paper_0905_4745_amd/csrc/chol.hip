@@ -33,39 +33,58 @@ __device__ void tile_in(V* T, const V* G, int64_t ld, int64_t m, int bi, int bj)
 }
 
 // In place: T (upper part of a Hermitian tile) -> its Cholesky factor R (upper),
-// T = R* R.  Padding rows/columns beyond `valid` are set to the identity so
-// the factor stays invertible.  One barrier per column: the trailing update
-// uses the unscaled row c divided by the pivot, rows are scaled at the end.
-// Every thread issues all LDS reads of a step before its arithmetic (the
-// chain of 32 steps is latency-bound).  rinv[i] = 1 / R_ii.  Returns false if
-// a pivot is not positive and finite.
+// T = R* R, and Z (LDS, 32 x 32) -> R^{-*}.  Padding rows/columns beyond
+// `valid` are set to the identity so the factor stays invertible.  Step c
+// subtracts conj(T_ci)/T_cc times row c from every row i > c (right-looking
+// elimination T = L D L*, upper part only), and the same row operations turn
+// Z = I into L^{-1}; at the end the rows of T are scaled to R = D^{1/2} L*
+// and those of Z to R^{-*} = D^{-1/2} L^{-1}.  (Column q of L^{-1} receives
+// exactly the operations of a forward substitution L z = e_q.)
+// Thread t keeps its elements (i, j) = (t % 32, t / 32 + 8u) of T and Z in
+// registers; at step c the threads of row c publish that row to a small
+// double-buffered LDS row (one barrier per step), which every thread reads.
+// rinv[i] = 1 / R_ii.  Returns false if a pivot is not positive and finite.
 template <typename V>
-__device__ __forceinline__ bool chol_tile(V* T, int valid, double* piv, double* rinv) {
+__device__ __forceinline__ bool chol_tile(V* T, V* Z, int valid, double* piv, double* rinv) {
+  __shared__ V rowT[2][CB];
+  __shared__ V rowZ[2][CB];
   const int i = threadIdx.x % CB, jb = threadIdx.x / CB;  // rows i, columns jb + 8u
+  V t[4], z[4];
+#pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int j = jb + 8 * u;
-    if (i >= valid || j >= valid) T[i + j * LDC] = (i == j) ? vmake<V>(1.0, 0.0) : vzero<V>();
+    t[u] = (i >= valid || j >= valid) ? ((i == j) ? vmake<V>(1.0, 0.0) : vzero<V>()) : T[i + j * LDC];
+    z[u] = (i == j) ? vmake<V>(1.0, 0.0) : vzero<V>();
   }
-  __syncthreads();
   for (int c = 0; c < CB; ++c) {
-    const double d = vre(T[c + c * LDC]);
-    const V tci = T[c + i * LDC];
-    V tcj[4], tij[4];
+    const int buf = c & 1;
+    if (i == c) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        rowT[buf][jb + 8 * u] = t[u];
+        rowZ[buf][jb + 8 * u] = z[u];
+      }
+    }
+    __syncthreads();
+    const double d = vre(rowT[buf][c]);
+    const V tci = rowT[buf][i];
+    V tcj[4], zcq[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int j = jb + 8 * u;
-      tcj[u] = T[c + j * LDC];
-      tij[u] = T[i + j * LDC];
+      tcj[u] = rowT[buf][jb + 8 * u];
+      zcq[u] = rowZ[buf][jb + 8 * u];
     }
     if (threadIdx.x == 0) piv[c] = d;
     const double inv = 1.0 / d;
+    const V f = vscale(vconj(tci), inv);  // multiplier of row c for row i
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = jb + 8 * u;
-      if (i > c && i <= j) T[i + j * LDC] = vsub(tij[u], vscale(vcmul(tci, tcj[u]), inv));
+      if (i > c && i <= j) t[u] = vsub(t[u], vmul(f, tcj[u]));
+      if (i > c && j <= c) z[u] = vsub(z[u], vmul(f, zcq[u]));
     }
-    __syncthreads();
   }
+  __syncthreads();
   bool ok = true;
   for (int c = 0; c < CB; ++c) ok = ok && (piv[c] > 0.0) && isfinite(piv[c]);
   const double pi = piv[i];
@@ -74,46 +93,13 @@ __device__ __forceinline__ bool chol_tile(V* T, int valid, double* piv, double* 
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int j = jb + 8 * u;
-    if (i < j) T[i + j * LDC] = vscale(T[i + j * LDC], s);
+    if (i < j) T[i + j * LDC] = vscale(t[u], s);
     else if (i == j) T[i + j * LDC] = vmake<V>(pi > 0.0 ? sqrt(pi) : 0.0, 0.0);
     else T[i + j * LDC] = vzero<V>();
+    Z[i + j * LDC] = vscale(z[u], s);
   }
   __syncthreads();
   return ok;
-}
-
-// Y <- R^{-*} (forward substitution on R* Y = I, R upper with 1 / R_qq in
-// rinv).  One wave; lane j < 32 keeps column j of Y in registers, every lane
-// reads the same entries of R (LDS broadcast), row q of R is read in one
-// batch before its updates.  Y's strictly upper part comes out exactly zero.
-template <typename V>
-__device__ __forceinline__ void inv_tile(const V* R, const double* rinv, V* Y) {
-  if (threadIdx.x < CB) {
-    const int j = threadIdx.x;
-    V x[CB];
-#pragma unroll
-    for (int r = 0; r < CB; ++r) x[r] = (r == j) ? vmake<V>(1.0, 0.0) : vzero<V>();
-    // fixed trip counts throughout, so that every loop unrolls fully and x
-    // stays in registers
-#pragma unroll
-    for (int q = 0; q < CB; ++q) {
-      x[q] = vscale(x[q], rinv[q]);
-#pragma unroll
-      for (int c8 = 0; c8 < CB / 8; ++c8) {
-        if (c8 * 8 + 7 > q) {
-          V rq[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) rq[u] = R[q + (c8 * 8 + u) * LDC];
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (c8 * 8 + u > q) x[c8 * 8 + u] = vsub(x[c8 * 8 + u], vcmul(rq[u], x[q]));
-        }
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < CB; ++r) Y[r + j * LDC] = x[r];
-  }
-  __syncthreads();
 }
 
 // acc[u] = sum_q A(r, q) B(q, cg + 8u) for tiles in LDS; thread t takes row
@@ -131,30 +117,22 @@ __device__ __forceinline__ void tile_mm(const V* A, const V* B, V acc[4]) {
 
 // Factor the (updated) diagonal tile held in T for block k: R_kk -> R,
 // Y_kk = R_kk^{-*} -> Yd[k] (32 x 32, column-major, ld 32); Y is LDS scratch.
+// The strictly lower blocks of R are zeroed by the panel workgroups.
 template <typename V>
-__device__ __forceinline__ void finish_diag(V* T, V* Y, double* piv, double* rinv, int k, int64_t m, V* R, int64_t ldr, V* Yd,
-                            int32_t* bad) {
+__device__ __forceinline__ void finish_diag(V* T, V* Y, double* piv, double* rinv, int k, int64_t m, V* R,
+                                            int64_t ldr, V* Yd, int32_t* bad) {
   const int valid = (int)((m - (int64_t)k * CB) < CB ? (m - (int64_t)k * CB) : CB);
-  const bool ok = chol_tile(T, valid, piv, rinv);
+  const bool ok = chol_tile(T, Y, valid, piv, rinv);
   if (!ok && threadIdx.x == 0) bad[0] = 1;
-  {
-    const int r = threadIdx.x % CB, cg = threadIdx.x / CB;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = cg + 8 * u;
-      const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)k * CB + c;
-      if (gr < m && gc < m) R[gr + gc * ldr] = T[r + c * LDC];
-    }
-  }
-  inv_tile(T, rinv, Y);
+  const int r = threadIdx.x % CB, cg = threadIdx.x / CB;
   V* yd = Yd + (int64_t)k * CB * CB;
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) yd[e] = Y[(e % CB) + (e / CB) * LDC];
-  // the strictly lower part of R's block column k (32-bit loop indices: a
-  // 64-bit divide per element would dominate the step)
-  const int r0 = (k + 1) * CB;
-  const int cend = (int)(m < (int64_t)r0 ? m : (int64_t)r0);
-  for (int c = k * CB; c < cend; ++c)
-    for (int r = r0 + (int)threadIdx.x; r < (int)m; r += blockDim.x) R[r + (int64_t)c * ldr] = vzero<V>();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = cg + 8 * u;
+    const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)k * CB + c;
+    if (gr < m && gc < m) R[gr + gc * ldr] = T[r + c * LDC];
+    yd[r + c * CB] = Y[r + c * LDC];
+  }
 }
 
 // Block step 0's diagonal tile (one workgroup).
@@ -220,10 +198,21 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
     for (int u = 0; u < 4; ++u) {
       const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)bj * CB + cg + 8 * u;
       if (gr < m && gc < m) R[gr + gc * ldr] = acc[u];
+      // the mirrored tile (bj, k) of R's strictly lower part
+      const int64_t lr = (int64_t)bj * CB + r, lc = (int64_t)k * CB + cg + 8 * u;
+      if (lr < m && lc < m) R[lr + lc * ldr] = vzero<V>();
     }
     return;
   }
-  // trailing tile: P = R_ki = Y G_ki, Q = R_kj = Y G_kj; G_ij -= P^* Q
+  // trailing tile: P = R_ki = Y G_ki, Q = R_kj = Y G_kj; G_ij -= P^* Q.
+  // This workgroup's own G_ij is loaded first (no other workgroup writes it
+  // in this step).
+  V gij[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t gr = (int64_t)bi * CB + r, gc = (int64_t)bj * CB + cg + 8 * u;
+    gij[u] = (gr < m && gc < m) ? G[gr + gc * ldg] : vzero<V>();
+  }
   tile_in(TA, G, ldg, m, k, bi);
   if (bj != bi) tile_in(TB, G, ldg, m, k, bj);
   __syncthreads();
@@ -252,12 +241,7 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
     // the next diagonal tile is final: factor it for block step k + 1
     __syncthreads();  // TB's reads are done before it is overwritten
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = cg + 8 * u;
-      const int64_t gr = (int64_t)bi * CB + r, gc = (int64_t)bj * CB + c;
-      const V g = (gr < m && gc < m) ? G[gr + gc * ldg] : vzero<V>();
-      TB[r + c * LDC] = vsub(g, acc[u]);
-    }
+    for (int u = 0; u < 4; ++u) TB[r + (cg + 8 * u) * LDC] = vsub(gij[u], acc[u]);
     __syncthreads();
     finish_diag(TB, TA, piv, rinv, k + 1, m, R, ldr, Yd, bad);
     return;
@@ -266,7 +250,7 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
   for (int u = 0; u < 4; ++u) {
     const int c = cg + 8 * u;
     const int64_t gr = (int64_t)bi * CB + r, gc = (int64_t)bj * CB + c;
-    if (gr < m && gc < m && gr <= gc) G[gr + gc * ldg] = vsub(G[gr + gc * ldg], acc[u]);
+    if (gr < m && gc < m && gr <= gc) G[gr + gc * ldg] = vsub(gij[u], acc[u]);
   }
 }
 template <typename V>
