@@ -336,7 +336,7 @@ int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 // Householder factorisation (which also classifies rank deficiency and
 // non-finite input).
 bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t lds, void* R64,
-                 const mn_opts* o) {
+                 const mn_opts* o, void* X = nullptr, int64_t ldx = 0) {
   hipStream_t st = h->stream;
   const bool cplx = is_complex(dtype);
   const int64_t W = cplx ? 16 : 8;
@@ -373,7 +373,7 @@ bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, in
   int32_t* bad = (int32_t*)ws(h, "chol_bad", 16);
   ck(launch_fill0(bad, 16, st));
   void* Yd = ws(h, "chol_yd", (size_t)(chol_scratch_elems(m) * W));
-  ck(launch_chol(cplx, G, m, m, R64, m, Yd, bad, st));
+  ck(launch_chol(cplx, G, m, m, R64, m, Yd, X, ldx, bad, st));
   double* dr = (double*)ws(h, "qr_diag", 64);
   ck(launch_rdiag_range(cplx ? MN_C128 : MN_F64, R64, m, m, dr, st));
   ck(hipMemcpyAsync(h->host_diag, dr, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1052,9 +1052,16 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   const int wdt = is_complex(dtype) ? MN_C128 : MN_F64;
   int rdt = c.bulk;
   bool gram = false;
+  // X = R^{-1}: built by the Cholesky launches on the Gram route, by its own
+  // launches after the Householder factorisation otherwise
+  const int64_t ldxi = rinv_ld(m);
+  c.X = ws(h, "Xinv", (size_t)(ldxi * ldxi * wide_size(dtype)));
+  const bool block = o.block == 2 || (o.block == 0 && nrhs >= 2 && c.mixed);
+  // the block products read whole tiles of X, so its strict lower part must be zero
+  if (block) ck(launch_fill0(c.X, ldxi * ldxi * wide_size(dtype), h->stream));
   if (o.precond == 0) {
     c.R = ws(h, "R64", (size_t)(m * m * wide_size(dtype)));
-    gram = gram_factor(h, c.bulk, l, m, S, l, c.R, &o);
+    gram = gram_factor(h, c.bulk, l, m, S, l, c.R, &o, c.X, ldxi);
     if (gram) rdt = wdt;
   }
   if (!gram) {
@@ -1074,12 +1081,7 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   // cond(A) above 3e4 the inner solves would stop contracting, so the bulk
   // passes then accumulate in FP64 (same bytes read)
   c.wide_acc = is_single(c.bulk) && h->kappa_hat > 3e4;
-  const int64_t ldxi = rinv_ld(m);
-  c.X = ws(h, "Xinv", (size_t)(ldxi * ldxi * wide_size(dtype)));
-  const bool block = o.block == 2 || (o.block == 0 && nrhs >= 2 && c.mixed);
-  // the block products read whole tiles of X, so its strict lower part must be zero
-  if (block) ck(launch_fill0(c.X, ldxi * ldxi * wide_size(dtype), h->stream));
-  ck(launch_rinv(rdt, c.R, m, m, c.X, h->stream));
+  if (!gram) ck(launch_rinv(rdt, c.R, m, m, c.X, h->stream));
   const int64_t W = wide_size(dtype);
   int worst = MN_OK;
   if (block) worst = solve_block(c, b, ldb, (int)nrhs, x, ldx, info);

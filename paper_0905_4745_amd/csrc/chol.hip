@@ -118,9 +118,11 @@ __device__ __forceinline__ void tile_mm(const V* A, const V* B, V acc[4]) {
 // Factor the (updated) diagonal tile held in T for block k: R_kk -> R,
 // Y_kk = R_kk^{-*} -> Yd[k] (32 x 32, column-major, ld 32); Y is LDS scratch.
 // The strictly lower blocks of R are zeroed by the panel workgroups.
+// With X, also X_kk = R_kk^{-1} = Y_kk^* (the whole 32 x 32 block, identity
+// beyond m, so X is padded to whole blocks).
 template <typename V>
 __device__ __forceinline__ void finish_diag(V* T, V* Y, double* piv, double* rinv, int k, int64_t m, V* R,
-                                            int64_t ldr, V* Yd, int32_t* bad) {
+                                            int64_t ldr, V* Yd, V* X, int64_t ldx, int32_t* bad) {
   const int valid = (int)((m - (int64_t)k * CB) < CB ? (m - (int64_t)k * CB) : CB);
   const bool ok = chol_tile(T, Y, valid, piv, rinv);
   if (!ok && threadIdx.x == 0) bad[0] = 1;
@@ -132,14 +134,49 @@ __device__ __forceinline__ void finish_diag(V* T, V* Y, double* piv, double* rin
     const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)k * CB + c;
     if (gr < m && gc < m) R[gr + gc * ldr] = T[r + c * LDC];
     yd[r + c * CB] = Y[r + c * LDC];
+    if (X) X[gr + gc * ldx] = vconj(Y[c + r * LDC]);
   }
+}
+
+// Block step s of X = R^{-1}, right-looking (block column s of X final: X_is
+// for i <= s): tile (i, j), i <= s < j, adds X_is R_sj to the running sum
+// held in X_ij (stored, not added, for its first term s = i); the tiles of
+// column j = s + 1 then hold the whole sum S and become X_ij = -S X_jj.
+template <typename V>
+__device__ __forceinline__ void trtri_tile(int w, int s, int nbk, int64_t m, const V* __restrict__ R, int64_t ldr,
+                                           V* __restrict__ X, int64_t ldx, V* As, V* Bs) {
+  const int ncol = nbk - s - 1;
+  const int i = w / ncol, j = s + 1 + w % ncol;
+  const int r = threadIdx.x % CB, cg = threadIdx.x / CB;
+  const int64_t mx = (int64_t)nbk * CB;  // X is stored on whole blocks
+  V acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    acc[u] = (s == i) ? vzero<V>() : X[((int64_t)i * CB + r) + ((int64_t)j * CB + cg + 8 * u) * ldx];
+  tile_in(As, X, ldx, mx, i, s);  // X_is
+  tile_in(Bs, R, ldr, m, s, j);   // R_sj (off the diagonal: zero beyond m)
+  __syncthreads();
+  tile_mm(As, Bs, acc);
+  if (j == s + 1) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) As[r + (cg + 8 * u) * LDC] = acc[u];
+    tile_in(Bs, X, ldx, mx, j, j);  // X_jj
+    __syncthreads();
+    V o[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
+    tile_mm(As, Bs, o);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = vsub(vzero<V>(), o[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) X[((int64_t)i * CB + r) + ((int64_t)j * CB + cg + 8 * u) * ldx] = acc[u];
 }
 
 // Block step 0's diagonal tile (one workgroup).
 template <typename V>
 __device__ __forceinline__ void k_chol_diag0_body(const Bk bk, V* __restrict__ G, int64_t ldg, int64_t m,
-                                                   V* __restrict__ R, int64_t ldr, V* __restrict__ Yd,
-                                                   int32_t* __restrict__ bad) {
+                                                   V* __restrict__ R, int64_t ldr, V* __restrict__ Yd, V* X,
+                                                   int64_t ldx, int32_t* __restrict__ bad) {
   (void)bk;
   __shared__ V T[CB * LDC];
   __shared__ V Y[CB * LDC];
@@ -147,29 +184,38 @@ __device__ __forceinline__ void k_chol_diag0_body(const Bk bk, V* __restrict__ G
   __shared__ double rinv[CB];
   tile_in(T, G, ldg, m, 0, 0);
   __syncthreads();
-  finish_diag(T, Y, piv, rinv, 0, m, R, ldr, Yd, bad);
+  finish_diag(T, Y, piv, rinv, 0, m, R, ldr, Yd, X, ldx, bad);
 }
 template <typename V>
 __global__ void __launch_bounds__(256) k_chol_diag0(V* __restrict__ G, int64_t ldg, int64_t m, V* __restrict__ R,
-                                                    int64_t ldr, V* __restrict__ Yd, int32_t* __restrict__ bad) {
-  k_chol_diag0_body<V>(bk_hw(), G, ldg, m, R, ldr, Yd, bad);
+                                                    int64_t ldr, V* __restrict__ Yd, V* X, int64_t ldx,
+                                                    int32_t* __restrict__ bad) {
+  k_chol_diag0_body<V>(bk_hw(), G, ldg, m, R, ldr, Yd, X, ldx, bad);
 }
 
 // Block step k (R_kk and Y_kk = R_kk^{-*} known):
 //   tile (k, j), j > k:      R_kj = Y_kk G_kj                     -> R
 //   tile (i, j), k < i <= j: G_ij -= (Y_kk G_ki)^* (Y_kk G_kj); the workgroup
 //                            of (k+1, k+1) then factors it (R, Y of block k+1).
-// grid = (nbk - k - 1) + (nbk - k - 1)(nbk - k)/2 workgroups.
+// grid = (nbk - k - 1) + (nbk - k - 1)(nbk - k)/2 workgroups, plus, with X,
+// k (nbk - k) workgroups for block step k - 1 of X = R^{-1} (its inputs, R's
+// block row k - 1 and X_kk, come from the previous launch; k = nbk - 1 runs
+// only those).
 template <typename V>
 __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G, int64_t ldg, int64_t m, int k, int nbk,
-                                                   V* __restrict__ R, int64_t ldr, V* __restrict__ Yd,
-                                                   int32_t* __restrict__ bad) {
+                                                   V* __restrict__ R, int64_t ldr, V* __restrict__ Yd, V* X,
+                                                   int64_t ldx, int32_t* __restrict__ bad) {
   __shared__ V Y[CB * LDC];
   __shared__ V TA[CB * LDC];
   __shared__ V TB[CB * LDC];
   __shared__ double piv[CB];
   __shared__ double rinv[CB];
   const int nrow = nbk - k - 1;
+  const int nchol = nrow + nrow * (nrow + 1) / 2;
+  if (bk.x >= nchol) {
+    trtri_tile(bk.x - nchol, k - 1, nbk, m, R, ldr, X, ldx, TA, TB);
+    return;
+  }
   int bi, bj;
   int w = bk.x;
   if (w < nrow) {
@@ -243,7 +289,7 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
 #pragma unroll
     for (int u = 0; u < 4; ++u) TB[r + (cg + 8 * u) * LDC] = vsub(gij[u], acc[u]);
     __syncthreads();
-    finish_diag(TB, TA, piv, rinv, k + 1, m, R, ldr, Yd, bad);
+    finish_diag(TB, TA, piv, rinv, k + 1, m, R, ldr, Yd, X, ldx, bad);
     return;
   }
 #pragma unroll
@@ -255,21 +301,26 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
 }
 template <typename V>
 __global__ void __launch_bounds__(256) k_chol_step(V* __restrict__ G, int64_t ldg, int64_t m, int k, int nbk,
-                                                   V* __restrict__ R, int64_t ldr, V* __restrict__ Yd,
-                                                   int32_t* __restrict__ bad) {
-  k_chol_step_body<V>(bk_hw(), G, ldg, m, k, nbk, R, ldr, Yd, bad);
+                                                   V* __restrict__ R, int64_t ldr, V* __restrict__ Yd, V* X,
+                                                   int64_t ldx, int32_t* __restrict__ bad) {
+  k_chol_step_body<V>(bk_hw(), G, ldg, m, k, nbk, R, ldr, Yd, X, ldx, bad);
 }
 
 template <typename V>
-hipError_t chol_impl(void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, int32_t* bad, hipStream_t st) {
+hipError_t chol_impl(void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, void* X, int64_t ldx,
+                     int32_t* bad, hipStream_t st) {
   const int nbk = (int)ceil_div(m, CB);
+  V* Xv = reinterpret_cast<V*>(X);
   hipLaunchKernelGGL((k_chol_diag0<V>), dim3(1), dim3(256), 0, st, reinterpret_cast<V*>(G), ldg, m,
-                     reinterpret_cast<V*>(R), ldr, reinterpret_cast<V*>(Yd), bad);
-  for (int k = 0; k + 1 < nbk; ++k) {
+                     reinterpret_cast<V*>(R), ldr, reinterpret_cast<V*>(Yd), Xv, ldx, bad);
+  for (int k = 0; k < nbk; ++k) {
     const int nrow = nbk - k - 1;
     const int ntrail = (nbk - k - 1) * (nbk - k) / 2;
-    hipLaunchKernelGGL((k_chol_step<V>), dim3((unsigned)(nrow + ntrail)), dim3(256), 0, st, reinterpret_cast<V*>(G),
-                       ldg, m, k, nbk, reinterpret_cast<V*>(R), ldr, reinterpret_cast<V*>(Yd), bad);
+    const int ntri = (X && k >= 1) ? k * (nbk - k) : 0;
+    if (nrow + ntrail + ntri == 0) continue;
+    hipLaunchKernelGGL((k_chol_step<V>), dim3((unsigned)(nrow + ntrail + ntri)), dim3(256), 0, st,
+                       reinterpret_cast<V*>(G), ldg, m, k, nbk, reinterpret_cast<V*>(R), ldr,
+                       reinterpret_cast<V*>(Yd), Xv, ldx, bad);
   }
   return hipGetLastError();
 }
@@ -278,10 +329,12 @@ hipError_t chol_impl(void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void
 
 int64_t chol_scratch_elems(int64_t m) { return ceil_div(m, CB) * CB * CB; }
 
-hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, int32_t* bad,
-                       hipStream_t st) {
+hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, void* X,
+                       int64_t ldx, int32_t* bad, hipStream_t st) {
   if (m < 1 || ldg < m || ldr < m) return hipErrorInvalidValue;
-  return cplx ? chol_impl<cd>(G, ldg, m, R, ldr, Yd, bad, st) : chol_impl<double>(G, ldg, m, R, ldr, Yd, bad, st);
+  if (X && ldx < ceil_div(m, CB) * CB) return hipErrorInvalidValue;
+  return cplx ? chol_impl<cd>(G, ldg, m, R, ldr, Yd, X, ldx, bad, st)
+              : chol_impl<double>(G, ldg, m, R, ldr, Yd, X, ldx, bad, st);
 }
 
 namespace {
@@ -291,7 +344,7 @@ __global__ void __launch_bounds__(256) kb_chol_diag0(const BSys* __restrict__ sy
   const int i = bgrid_find(grid, nsys, blockIdx.x);
   const BSys& s = sys[i];
   k_chol_diag0_body<V>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<V*>(s.G), s.m, s.m,
-                       reinterpret_cast<V*>(s.R), s.m, reinterpret_cast<V*>(s.Yd), s.flags + 1);
+                       reinterpret_cast<V*>(s.R), s.m, reinterpret_cast<V*>(s.Yd), (V*)nullptr, 0, s.flags + 1);
 }
 template <typename V>
 __global__ void __launch_bounds__(256) kb_chol_step(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
@@ -300,7 +353,7 @@ __global__ void __launch_bounds__(256) kb_chol_step(const BSys* __restrict__ sys
   const BSys& s = sys[i];
   k_chol_step_body<V>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<V*>(s.G), s.m, s.m, k,
                       (int)ceil_div(s.m, CB), reinterpret_cast<V*>(s.R), s.m, reinterpret_cast<V*>(s.Yd),
-                      s.flags + 1);
+                      (V*)nullptr, 0, s.flags + 1);
 }
 }  // namespace
 

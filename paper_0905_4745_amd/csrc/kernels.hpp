@@ -227,10 +227,12 @@ hipError_t launch_gram_fold(bool cplx, const double* Cp, int splits, int64_t ldc
                             hipStream_t st);
 // R (FP64, upper, ld ldr) from G (upper part, overwritten by Schur
 // complements); Yd: chol_scratch_elems(m) FP64 entries (the inverses of the
-// diagonal tiles); bad[0] = 1 if a pivot is not positive and finite.
+// diagonal tiles); bad[0] = 1 if a pivot is not positive and finite.  With X
+// (FP64, ld ldx >= rinv_ld(m)), X = R^{-1} on whole 32 x 32 blocks of the
+// upper block triangle as well (lower blocks untouched).
 int64_t chol_scratch_elems(int64_t m);
-hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, int32_t* bad,
-                       hipStream_t st);
+hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, void* X,
+                       int64_t ldx, int32_t* bad, hipStream_t st);
 
 // ---- batched systems -----------------------------------------------------------
 // Batched launch over several systems: entry i holds system i's first
