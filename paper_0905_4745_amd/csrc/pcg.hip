@@ -201,9 +201,27 @@ __device__ __forceinline__ void k_cg_s_body(const Bk bk, const W* __restrict__ X
     if (lead && threadIdx.x == 0) st.refine_snap = st.refine_steps + (parts ? 1 : 0);
   } else {
     if (st.done) return;
-    // q = sum of the partial products (kept in p-order), alpha = rho / p^* q
+    // q = sum of the partial products (kept in p-order), alpha = rho / p^* q.
+    // For the first 1024 entries the iteration's other vectors (r, and p, y
+    // in the lead workgroup) are loaded together with q's slices.
+    constexpr int PF = 4;
     double pq = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+    W rv[PF], pv[PF], yv[PF];
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int64_t i = threadIdx.x + 256 * t;
+      rv[t] = pv[t] = yv[t] = vzero<W>();
+      if (i < m) {
+        W q = parts[i];
+        for (int c = 1; c < nparts; ++c) q = vadd(q, parts[(int64_t)c * m + i]);
+        pv[t] = p[i];
+        rv[t] = r_in[i];
+        if (lead) yv[t] = y[i];
+        rs[i] = q;
+        pq += vre(vcmul(pv[t], q));
+      }
+    }
+    for (int64_t i = threadIdx.x + 256 * PF; i < m; i += blockDim.x) {
       W q = parts[i];
       for (int c = 1; c < nparts; ++c) q = vadd(q, parts[(int64_t)c * m + i]);
       rs[i] = q;
@@ -218,7 +236,19 @@ __device__ __forceinline__ void k_cg_s_body(const Bk bk, const W* __restrict__ X
       }
       return;
     }
-    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int64_t i = threadIdx.x + 256 * t;
+      if (i < m) {
+        const W v = vsub(rv[t], vscale(rs[i], alpha));
+        rs[i] = v;
+        if (lead) {
+          r_out[i] = v;
+          y[i] = vadd(yv[t], vscale(pv[t], alpha));
+        }
+      }
+    }
+    for (int64_t i = threadIdx.x + 256 * PF; i < m; i += blockDim.x) {
       const W v = vsub(r_in[i], vscale(rs[i], alpha));
       rs[i] = v;
       if (lead) {
@@ -280,7 +310,6 @@ __device__ __forceinline__ void k_cg_p_body(const Bk bk, const W* __restrict__ X
   constexpr int RB = 16;
   extern __shared__ unsigned char smem_raw[];
   W* ss = reinterpret_cast<W*>(smem_raw);  // s, m entries
-  __shared__ double red[4];
   __shared__ W part[16][RB];
   PcgState& st = *stp;
   const bool lead = bk.x == 0;
@@ -295,22 +324,29 @@ __device__ __forceinline__ void k_cg_p_body(const Bk bk, const W* __restrict__ X
   W xf[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) xf[u] = first ? X[i + (i0 + cgrp + 16 * u) * ldx] : vzero<W>();
+  const int64_t ip = i0 + threadIdx.x;  // this workgroup's entries of p (threads < 16)
+  const W p_old = (!start && threadIdx.x < RB && ip < m) ? p[ip] : vzero<W>();
   if (start ? (st.outer_done != 0) : (st.done != 0)) return;
-  double rho = 0.0;
+  // rho = ||s||^2 and, where the stopping test needs it, xi = Re(y* (b - r))
+  // (y_outer at the start of a refinement step): one pass, one reduction
+  const W* yx = start ? y_outer : y;
+  const bool want_xi = start ? (y_outer != nullptr) : (st.rule != 2);
+  cd rx = cd{0.0, 0.0};
   for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
     const W v = s[i];
     ss[i] = v;
-    rho += vabs2(v);
+    rx.re += vabs2(v);
+    if (want_xi) rx.im += vre(vcmul(yx[i], vsub(b[i], r[i])));
   }
-  rho = block_sum(rho, red);
+  __shared__ cd redc[4];
+  rx = block_sum(rx, redc);
+  const double rho = rx.re;
   double beta = 0.0;
   if (start) {
     if (y_outer) {
       // FP64 certificate of the current outer iterate: ||x - p|| <= sqrt(rho)/sigma
       // with sigma >= ~0.9 for an R from single-precision data: test eps/2
-      double xi = 0.0;
-      for (int64_t i = threadIdx.x; i < m; i += blockDim.x) xi += vre(vcmul(y_outer[i], vsub(b[i], r[i])));
-      xi = block_sum(xi, red);
+      const double xi = rx.im;
       const double e = 0.5 * st.eps_outer;
       const double tol = e / (1.0 + e);
       int od = 0, status = st.status;
@@ -348,11 +384,7 @@ __device__ __forceinline__ void k_cg_p_body(const Bk bk, const W* __restrict__ X
     }
     if (rho == 0.0 || !isfinite(rho)) return;
   } else {
-    double xi = 0.0;
-    if (st.rule != 2) {
-      for (int64_t i = threadIdx.x; i < m; i += blockDim.x) xi += vre(vcmul(y[i], vsub(b[i], r[i])));
-      xi = block_sum(xi, red);
-    }
+    const double xi = want_xi ? rx.im : 0.0;
     const int it = st.iter_snap + 1;
     int stop = 0, status = st.status;
     if (!isfinite(rho)) {
@@ -398,7 +430,7 @@ __device__ __forceinline__ void k_cg_p_body(const Bk bk, const W* __restrict__ X
     W z = part[0][threadIdx.x];
     for (int c = 1; c < 16; ++c) z = vadd(z, part[c][threadIdx.x]);
     const int64_t ii = i0 + threadIdx.x;
-    p[ii] = start ? z : vadd(z, vscale(p[ii], beta));
+    p[ii] = start ? z : vadd(z, vscale(p_old, beta));
   }
 }
 template <typename W>
