@@ -166,9 +166,15 @@ int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* tot
  *                            workgroup size (bit 18 set: 1024 threads, half
  *                            the rows per thread; 512 otherwise);
  * "sketch_chunk_mb/<dtype>/<m>/<N>/0"  four-step FFT: MB of the intermediate
- *                            per chunk of rows (low 16 bits: 16 .. 512) and
+ *                            per chunk of rows (low 16 bits: 16 .. 512),
  *                            workgroup size in elements (bit 16 set: 2048,
- *                            else 4096);
+ *                            else 4096), split (bits 17-18: N2 halved 0 .. 2
+ *                            times), kept-outputs-only form (bits 19-20: 0
+ *                            off, 1 / 2 / 3 for B = 16 / 8 / 4 columns per
+ *                            block; applies for l <= 2048, else the full
+ *                            four-step runs) with 2^(bits 21-24) column
+ *                            groups per row.  Default: that form with B = 16
+ *                            and groups enough for 512 workgroups;
  * "gram_s/<dtype>/<m>/<l>/0"  Step 2's Gram matrix S* S: 0 on the FP64
  *                            matrix cores, 1 register-tiled on the vector
  *                            units (default 1 for m > 1024);

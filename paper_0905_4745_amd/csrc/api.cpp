@@ -262,26 +262,54 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   // picks 16 .. 512 MB (larger chunks give each launch more workgroups to
   // overlap loads with transforms)
   // plan: MB of intermediate per chunk (low 16 bits), bit 16 set: 2048
-  // elements per workgroup instead of 4096, bits 17-18: four-step split
+  // elements per workgroup instead of 4096, bits 17-18: four-step split,
+  // bits 19-20: kept outputs only (pruned) with B = 16, 8, 4 columns per
+  // block (codes 1, 2, 3; 0 = full four-step), bits 21-24: log2 of the
+  // pruned form's column groups per row
+  static const int pruned_b[4] = {0, 16, 8, 4};
   auto run = [&](int pl) {
     const int mb = pl & 0xFFFF;
     a.wg_elems = (pl >> 16) & 1 ? 2048 : 4096;
     a.split = (pl >> 17) & 3;
-    int64_t chunk = ((int64_t)mb << 20) / (N * ces);
+    a.pruned_b = pruned_b[(pl >> 19) & 3];
+    a.pruned_ng = 1 << ((pl >> 21) & 15);
+    int64_t per_row = N;  // intermediate elements per row
+    if (a.pruned_b) {
+      const int ng = sketch_pruned_groups(dtype, N, l, a.pruned_b, a.pruned_ng);
+      if (ng < 1) a.pruned_b = 0;  // not applicable to this shape: full four-step
+      else per_row = ng > 1 ? (int64_t)ng * l : 0;
+    }
+    int64_t chunk = per_row > 0 ? ((int64_t)mb << 20) / (per_row * ces) : m;
     if (chunk < 1) chunk = 1;
     if (chunk > m) chunk = m;
     a.chunk_rows = chunk;
-    a.work = ws(h, "fft_y", (size_t)(chunk * N * ces));
+    a.work = per_row > 0 ? ws(h, "fft_y", (size_t)(chunk * per_row * ces)) : nullptr;
+    a.order = a.pruned_b ? (int32_t*)ws(h, "sk_order", (size_t)l * 4) : nullptr;
     ck(launch_sketch(dtype, a, h->stream));
   };
+  // default: the pruned form with B = 16 where it applies, with enough
+  // column groups per row for 512 workgroups (two per CU)
   int mb = 64;
+  if (sketch_pruned_groups(dtype, N, l, 16, 1) > 0) {
+    int lg = 0;
+    while ((m << lg) < 512 && lg < 10) ++lg;
+    mb = 64 | (1 << 19) | (lg << 21);
+  }
   const std::string key = plan_key("sketch_chunk_mb", dtype, m, N, 0);
   if (o) {
-    std::vector<int> cands{64, 16, 32};
+    std::vector<int> cands{mb};
+    for (int c : {64, 16, 32})
+      if (c != mb) cands.push_back(c);
     for (int sp : {0, 1, 2})
       for (int c : {64, 128, 256, 512})
         if (sp || c != 64) cands.push_back((sp << 17) | c);
     cands.push_back(0x10000 | 512);
+    for (int bc : {1, 2, 3})
+      for (int lg : {0, 1, 2, 3, 4})
+        if (sketch_pruned_groups(dtype, N, l, pruned_b[bc], 1 << lg) == (1 << lg)) {
+          const int c = 64 | (bc << 19) | (lg << 21);
+          if (c != cands[0]) cands.push_back(c);
+        }
     mb = plan_get(h, *o, key, cands, run);
   }
   else plan_find(h, key, &mb);

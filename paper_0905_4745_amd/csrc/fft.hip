@@ -428,6 +428,212 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, in
   k_sketch_rows_body<V, C>(bk_hw(), Y, row0, m, N2, pl1, B, inv, S, lds, tw, scale);
 }
 
+// ------------------ four-step, kept outputs only (pruned) ---------------------
+// Only l of the N outputs of each row's transform are kept.  With the input
+// index n = n1 + N1 n2 (n1 < N1, n2 < N2) and an output k,
+//   V[k] = sum_{n1} W_N^{n1 k} Z_{n1}[k mod N2],
+//   Z_{n1}[k2] = sum_{n2} v[n1 + N1 n2] W_{N2}^{n2 k2}
+// since W_N^{N1 n2 k} = W_{N2}^{n2 k}.  A workgroup takes one row and G
+// blocks of B consecutive n1: it transforms the block's B columns in LDS
+// (N2 = 4096 / B points each; the first radix-16 stage runs on the loaded
+// registers) and adds the block's share of the outer sum to one register
+// accumulator per kept output.  Neither the N2 x N1 intermediate nor the
+// discarded outputs reach memory; the outer sum costs l N1 multiply-adds per
+// row, so this form pays while l / N2 is small.  The factors W_N^{n1 k} of
+// one block come from one table entry and a recurrence in n1.  Thread slot
+// q = tid + 256 u takes kept output order[q]: the order groups outputs of
+// equal k mod N2 (k_sketch_order), so the lanes of a wave read a few LDS
+// addresses (broadcast) rather than 64 scattered ones.  With one column
+// group per row (grid.x = 1) the workgroup writes S; otherwise the group's
+// sums go to P[g][row][s] and k_sketch_fold adds them.
+// one-touch load of a streamed operand
+template <typename V> __device__ __forceinline__ V ld_stream(const V* p) {
+  if constexpr (VT<V>::cplx) {
+    using Rl = typename VT<V>::real;
+    const Rl* q = reinterpret_cast<const Rl*>(p);
+    return V{__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1)};
+  } else {
+    return __builtin_nontemporal_load(p);
+  }
+}
+
+template <typename V> struct PhaseOf { using type = typename std::conditional<VT<V>::cplx, cd, double>::type; };
+
+template <int X> __host__ __device__ constexpr int ilog2c() { return X <= 1 ? 0 : 1 + ilog2c<X / 2>(); }
+
+template <typename V, typename C, int B, int KPT>
+__global__ void __launch_bounds__(256, 2) k_sketch_pruned(const V* __restrict__ A, int64_t lda, int64_t row0, int64_t rows,
+                                                       int64_t n, int N1, int G, FftPlan pl2,
+                                                       const void* __restrict__ dv, const int32_t* __restrict__ idx,
+                                                       const int32_t* __restrict__ order, int64_t l,
+                                                       const C* __restrict__ tw, V* __restrict__ S, int64_t lds,
+                                                       C* __restrict__ P, typename VT<C>::real scale) {
+  constexpr int N2 = 4096 / B;
+  constexpr int LR = N2 / 16;  // = 256 / B: butterflies per column in a radix-16 stage
+  constexpr int lgB = ilog2c<B>(), lgLR = ilog2c<LR>();
+  constexpr int Lp = N2 + N2 / 16 + 1;
+  using D = typename PhaseOf<V>::type;
+  using R = typename VT<C>::real;
+  // the stage twiddles W_{N2}^k (k < N2) sit in LDS after the B columns,
+  // where they fit two workgroups to a CU (B = 16, 8); B = 4 reads W_N
+  constexpr bool TW_LDS = B >= 8;
+  extern __shared__ unsigned char smem_raw[];
+  C* sm = reinterpret_cast<C*>(smem_raw);
+  const unsigned Nm = (unsigned)N1 * (unsigned)N2 - 1u;
+  const int64_t i = row0 + blockIdx.y;
+  const V* row = A + i * lda;
+  C* tws = sm + B * Lp;
+  if constexpr (TW_LDS) {
+    for (int k = threadIdx.x; k < N2; k += 256) tws[k] = tw[(unsigned)k * (unsigned)N1];
+  }
+  const C* twst = TW_LDS ? tws : tw;
+  const int twm = TW_LDS ? 1 : N1;
+  const D* dp = reinterpret_cast<const D*>(dv);
+  const int tid = threadIdx.x;
+  // first stage and loads: column bb of the block, butterfly jj (inputs jj + r LR)
+  const int bb = tid & (B - 1), jj = tid >> lgB;
+  // later stages: column fb, thread tl of its LR
+  const int fb = tid >> lgLR, tl = tid & (LR - 1);
+
+  C acc[KPT];
+#pragma unroll
+  for (int u = 0; u < KPT; ++u) acc[u] = vzero<C>();
+  // kept output of slot u; slots past l compute on k = 0 and store nothing
+  // (no branch in the sum)
+  unsigned kq[KPT];
+#pragma unroll
+  for (int u = 0; u < KPT; ++u) {
+    const int q = tid + 256 * u;
+    kq[u] = q < l ? (unsigned)idx[order[q]] & Nm : 0u;
+  }
+  // the empty asm makes k opaque inside the block loop, so the table reads
+  // that depend on it stay there (hoisted, they would hold 4 KPT registers
+  // through the whole loop)
+  auto kept = [&](int u) -> unsigned {
+    unsigned k = kq[u];
+    asm volatile("" : "+v"(k));
+    return k;
+  };
+
+  // the next block's entries of A are loaded into registers before the
+  // outer sum and used after it; A is read once, as a stream (non-temporal:
+  // it does not push the phase and twiddle tables, which every row reads,
+  // out of the cache).  The phases are read when the block is formed.
+  V pa[16];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t j = (int64_t)(c0 + bb) + (int64_t)N1 * (jj + r * LR);
+      pa[r] = j < n ? ld_stream(row + j) : V{};
+    }
+  };
+  const int cbeg = (int)blockIdx.x * G * B;
+  load(cbeg);
+  for (int g = 0; g < G; ++g) {
+    const int c0 = cbeg + g * B;
+    {
+      C v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t j = (int64_t)(c0 + bb) + (int64_t)N1 * (jj + r * LR);
+        const D dd = j < n ? dp[j] : D{};
+        if constexpr (VT<V>::cplx) v[r] = vcmul(vconv<C>(pa[r]), vmake<C>(dd.re, dd.im));  // conj(a) d
+        else v[r] = C{(R)pa[r] * (R)dd, (R)0};
+      }
+      dft16(v);
+      C* buf = sm + bb * Lp;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) buf[lpad(jj * 16 + r)] = v[out_slot<16>(r)];
+    }
+    __syncthreads();
+    {
+      C* buf = sm + fb * Lp;
+      int Ns = 16;
+      for (int s = 1; s < pl2.nst; ++s) {
+        const int Rd = pl2.radix[s];
+        if (Rd == 16) fft_stage<16>(buf, N2, Ns, LR, tl, twst, twm);
+        else if (Rd == 8) fft_stage<8>(buf, N2, Ns, LR, tl, twst, twm);
+        else if (Rd == 4) fft_stage<4>(buf, N2, Ns, LR, tl, twst, twm);
+        else fft_stage<2>(buf, N2, Ns, LR, tl, twst, twm);
+        Ns *= Rd;
+      }
+    }
+    // Z of the block is in LDS (the last stage ends with a barrier); the
+    // next block's loads fly during the outer sum
+    if (g + 1 < G) load(c0 + B);
+    // two kept outputs at a time (two independent recurrences interleave;
+    // the scheduling barrier keeps the next pair's LDS reads from being
+    // hoisted into this one's registers)
+#pragma unroll
+    for (int u = 0; u < KPT; u += 2) {
+      const unsigned k0 = kept(u), k1 = kept(u + 1);
+      C w0 = tw[((unsigned)c0 * k0) & Nm], w1 = tw[((unsigned)c0 * k1) & Nm];  // W_N^{c0 k}
+      const C st0 = tw[k0], st1 = tw[k1];                                       // W_N^k
+      const C* zp0 = sm + lpad((int)(k0 & (unsigned)(N2 - 1)));
+      const C* zp1 = sm + lpad((int)(k1 & (unsigned)(N2 - 1)));
+      C a0 = acc[u], a1 = acc[u + 1];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        a0 = vfma(w0, zp0[b * Lp], a0);
+        a1 = vfma(w1, zp1[b * Lp], a1);
+        w0 = vmul(w0, st0);
+        w1 = vmul(w1, st1);
+      }
+      acc[u] = a0;
+      acc[u + 1] = a1;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < KPT; ++u) {
+    const int q = tid + 256 * u;
+    if (q < l) {
+      const int64_t s = order[q];
+      if (gridDim.x == 1) S[s + i * lds] = out_value<V, C>(acc[u], scale);
+      else P[((int64_t)blockIdx.x * rows + blockIdx.y) * l + s] = acc[u];
+    }
+  }
+}
+
+// order[0 .. l) = a permutation of 0 .. l that groups the kept outputs by
+// idx[s] mod N2 (counting sort on the residue; the order inside a group is
+// whatever the LDS atomics give, which changes no result).  One workgroup of
+// 1024 threads; N2 <= 1024.
+__global__ void __launch_bounds__(1024) k_sketch_order(const int32_t* __restrict__ idx, int64_t l, int N2,
+                                                       int32_t* __restrict__ order) {
+  __shared__ int cnt[1024];
+  const int tid = threadIdx.x;
+  cnt[tid] = 0;
+  __syncthreads();
+  for (int64_t s = tid; s < l; s += 1024) atomicAdd(&cnt[idx[s] & (N2 - 1)], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int r = 0; r < N2; ++r) {
+      const int c = cnt[r];
+      cnt[r] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int64_t s = tid; s < l; s += 1024) order[atomicAdd(&cnt[idx[s] & (N2 - 1)], 1)] = (int32_t)s;
+}
+
+// S[s + i lds] = scale * sum over the ng column groups of P[g][i - row0][s]
+// grid (ceil(l / 256), rows)
+template <typename V, typename C>
+__global__ void __launch_bounds__(256) k_sketch_fold(const C* __restrict__ P, int ng, int64_t rows, int64_t l,
+                                                     int64_t row0, V* __restrict__ S, int64_t lds,
+                                                     typename VT<C>::real scale) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (s >= l) return;
+  C a = P[r * l + s];
+  for (int g = 1; g < ng; ++g) a = vadd(a, P[((int64_t)g * rows + r) * l + s]);
+  S[s + (row0 + r) * lds] = out_value<V, C>(a, scale);
+}
+
 // ------------------------------ helpers -------------------------------------
 // inv[k] = position of k in idx, or -1; also flags invalid idx (out of range
 // or not strictly increasing) in *bad.  Writes stay inside inv[0, N).
@@ -501,6 +707,82 @@ template <typename C> static int fft_batch(int L, int elems = 4096) {
   return B;
 }
 
+// Column groups per row of the pruned four-step for B columns per block and
+// ng groups asked for (clamped to 1 .. N1 / B), or 0 where it does not apply:
+// l above 2048 kept outputs (eight accumulators per thread), N not a multiple
+// of N2 = 4096 / B, or a block larger than the LDS limit.
+template <typename C> static int pruned_groups(int64_t N, int64_t l, int B, int ng) {
+  if (!(B == 16 || B == 8 || B == 4) || l < 1 || l > 2048) return 0;
+  const int64_t N2 = 4096 / B;
+  if (N <= N2 || N % N2) return 0;
+  if (((int64_t)B * lds_stride((int)N2) + (B >= 8 ? N2 : 0)) * (int64_t)sizeof(C) > lds_limit()) return 0;
+  const int64_t nb = N / N2 / B;  // blocks per row
+  if (nb < 1) return 0;
+  int g = ng < 1 ? 1 : ng;
+  while (g > 1 && (nb % g || g > nb)) g >>= 1;
+  return g;
+}
+
+template <typename V, typename C, int B>
+static void pruned_launch(int kpt, dim3 grid, size_t smb, hipStream_t st, const V* A, int64_t lda, int64_t row0,
+                          int64_t rows, int64_t n, int N1, int G, FftPlan pl2, const void* d, const int32_t* idx,
+                          const int32_t* order, int64_t l, const C* tw, V* S, int64_t lds, C* P,
+                          typename VT<C>::real scale) {
+  if (kpt == 2) {
+    allow_lds(k_sketch_pruned<V, C, B, 2>, smb);
+    hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 2>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2, d,
+                       idx, order, l, tw, S, lds, P, scale);
+  } else if (kpt == 4) {
+    allow_lds(k_sketch_pruned<V, C, B, 4>, smb);
+    hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 4>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2, d,
+                       idx, order, l, tw, S, lds, P, scale);
+  } else {
+    allow_lds(k_sketch_pruned<V, C, B, 8>, smb);
+    hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 8>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2, d,
+                       idx, order, l, tw, S, lds, P, scale);
+  }
+}
+
+template <typename V, typename C>
+static hipError_t sketch_pruned_impl(const SketchArgs& a, hipStream_t st) {
+  const int N = (int)a.N;
+  const int B = a.pruned_b;
+  const int ng = pruned_groups<C>(a.N, a.l, B, a.pruned_ng);
+  if (ng < 1) return hipErrorInvalidValue;
+  const int N2 = 4096 / B, N1 = N / N2;
+  const int G = N1 / (B * ng);
+  const int kpt = a.l <= 512 ? 2 : (a.l <= 1024 ? 4 : 8);
+  const FftPlan pl2 = make_plan(N2);
+  using R = typename VT<C>::real;
+  const R scale = (R)(1.0 / sqrt((double)N));
+  const C* tw = reinterpret_cast<const C*>(a.twiddle);
+  const V* A = reinterpret_cast<const V*>(a.A);
+  V* S = reinterpret_cast<V*>(a.S);
+  C* P = reinterpret_cast<C*>(a.work);
+  const size_t smb = ((size_t)B * lds_stride(N2) + (B >= 8 ? (size_t)N2 : 0)) * sizeof(C);
+  // one group per row: no partial sums, every row in one launch
+  const int64_t per = ng == 1 ? a.m : a.chunk_rows;
+  if (per < 1 || (ng > 1 && P == nullptr) || a.order == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sketch_order, dim3(1), dim3(1024), 0, st, a.idx, a.l, N2, a.order);
+  for (int64_t r0 = 0; r0 < a.m; r0 += per) {
+    const int64_t rows = (a.m - r0) < per ? (a.m - r0) : per;
+    const dim3 grid((unsigned)ng, (unsigned)rows);
+    if (B == 16)
+      pruned_launch<V, C, 16>(kpt, grid, smb, st, A, a.lda, r0, rows, a.n, N1, G, pl2, a.d, a.idx, a.order, a.l, tw, S, a.lds,
+                              P, scale);
+    else if (B == 8)
+      pruned_launch<V, C, 8>(kpt, grid, smb, st, A, a.lda, r0, rows, a.n, N1, G, pl2, a.d, a.idx, a.order, a.l, tw, S, a.lds,
+                             P, scale);
+    else
+      pruned_launch<V, C, 4>(kpt, grid, smb, st, A, a.lda, r0, rows, a.n, N1, G, pl2, a.d, a.idx, a.order, a.l, tw, S, a.lds,
+                             P, scale);
+    if (ng > 1)
+      hipLaunchKernelGGL((k_sketch_fold<V, C>), dim3((unsigned)ceil_div(a.l, 256), (unsigned)rows), dim3(256), 0, st,
+                         P, ng, rows, a.l, r0, S, a.lds, scale);
+  }
+  return hipGetLastError();
+}
+
 template <typename V, typename C>
 static hipError_t sketch_impl(const SketchArgs& a, hipStream_t st) {
   const int N = (int)a.N;
@@ -520,6 +802,7 @@ static hipError_t sketch_impl(const SketchArgs& a, hipStream_t st) {
                        a.l, S, a.lds, tw, scale);
     return hipGetLastError();
   }
+  if (a.pruned_b > 0) return sketch_pruned_impl<V, C>(a, st);
   // four-step: N = N1 * N2, N1 >= N2, both transformed whole in LDS; split
   // s halves N2 s times (fewer for shapes where N1 would outgrow LDS)
   int k = 0;
@@ -552,6 +835,12 @@ static hipError_t sketch_impl(const SketchArgs& a, hipStream_t st) {
                        scale);
   }
   return hipGetLastError();
+}
+
+int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng) {
+  const bool sp = dtype == 1 || dtype == 3;
+  if (N <= (sp ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>())) return 0;  // one-workgroup transform
+  return sp ? pruned_groups<cf>(N, l, B, ng) : pruned_groups<cd>(N, l, B, ng);
 }
 
 int sketch_max_log2n(int dtype) {

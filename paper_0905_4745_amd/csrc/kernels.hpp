@@ -42,7 +42,14 @@ struct SketchArgs {
   int64_t chunk_rows;
   int wg_elems;         // four-step: elements per workgroup (4096 or 2048; 0 = 4096)
   int split;            // four-step: N2 = 2^(floor(log2 N / 2) - split), split 0..2
+  int pruned_b;         // > 0: kept outputs only, B = 16, 8 or 4 columns per block (N2 = 4096 / B)
+  int pruned_ng;        // pruned: column groups per row (partial sums in work when > 1)
+  int32_t* order;       // pruned: l entries of scratch (kept outputs grouped by k mod N2)
 };
+// column groups per row the pruned four-step uses for (B, ng), 0 if it does
+// not apply to this (dtype, N, l); work then holds ng * chunk_rows * l
+// elements of the compute type
+int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng);
 hipError_t launch_sketch(int dtype, const SketchArgs& a, hipStream_t st);
 int sketch_max_log2n(int dtype);  // largest log2(N) the four-step supports
 hipError_t launch_inverse_map(const int32_t* idx, int64_t l, int64_t N, int32_t* inv, int32_t* bad, hipStream_t st);

@@ -113,3 +113,37 @@ def test_sketch_four_step_splits(m, n, N, l, kind, split, tmp_path):
     err = _colerr(S.astype(ref.dtype), ref)
     say(f"  col rel err {err:.2e}")
     assert err <= 20 * u * max(np.log2(N), 1)
+
+
+@pytest.mark.parametrize("m,n,N,l", [(17, 65536, 65536, 68), (5, 8192, 8192, 2048), (3, 100000, 131072, 700),
+                                     (9, 40000, 65536, 1100)])
+@pytest.mark.parametrize("kind", ["c128", "c64", "f64", "f32"])
+@pytest.mark.parametrize("bcode,lgng", [(1, 0), (1, 2), (2, 1), (3, 0), (3, 3)])
+def test_sketch_pruned_variants(m, n, N, l, kind, bcode, lgng, tmp_path):
+    """The kept-outputs-only four-step (B = 16, 8, 4 columns per block; 1 to
+    8 column groups per row, partial sums folded) forced through a loaded
+    plan gives the oracle's sketch to the same bar, including ragged n and
+    l = 2048 (eight kept outputs per thread)."""
+    import json
+    import torch
+    from paper_0905_4745_amd import api
+    say(f"sketch pruned b{bcode} ng{1 << lgng} {kind} m={m} n={n} N={N} l={l}")
+    real = kind.startswith("f")
+    g = np.random.default_rng(m * 13 + n + l)
+    A = g.standard_normal((m, n)) if real else synth.complex_gaussian(g, (m, n))
+    d, idx = synth.draw_srft(N, l, seed=N + 5 * l, real=real)
+    tdt = {"c128": torch.complex128, "c64": torch.complex64, "f64": torch.float64, "f32": torch.float32}[kind]
+    dcode = {"c128": 0, "c64": 1, "f64": 2, "f32": 3}[kind]
+    plan = 64 | (bcode << 19) | (lgng << 21)
+    path = tmp_path / "plans.json"
+    path.write_text(json.dumps({"format": "minnorm-plans-1",
+                                "plans": {f"sketch_chunk_mb/{dcode}/{m}/{N}/0": plan}, "best_ms": {}}))
+    api.plans_load(str(path))
+    At = to_dev(A, tdt)
+    A_used = to_np(At).astype(np.float64 if real else np.complex128)
+    S = to_np(api.srft_sketch(At, d, idx, N))
+    ref = oracle.sketch_real(A_used, d, idx, N) if real else oracle.sketch(A_used, d, idx, N)
+    u = U32 if kind in ("c64", "f32") else U64
+    err = _colerr(S.astype(ref.dtype), ref)
+    say(f"  col rel err {err:.2e}")
+    assert err <= 20 * u * max(np.log2(N), 1)
