@@ -1202,13 +1202,14 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   const int64_t ces = is_single(bulk) ? 8 : 16;
   std::vector<BSys> hs((size_t)batch);
   // grids
-  GridTable fill, map, sk_small, sk_cols, sk_rows, gram_s, rdiag, invd, gramR[4], gred, adjA, adjU, sum, fwdA, fwdU,
-      cgs, cgp, vec;
-  for (GridTable* t : {&fill, &map, &sk_small, &sk_cols, &sk_rows, &gram_s, &rdiag, &invd, &gramR[0], &gramR[1],
-                       &gramR[2], &gramR[3], &gred, &adjA, &adjU, &sum, &fwdA, &fwdU, &cgs, &cgp, &vec})
+  GridTable fill, map, sk_small, sk_cols, sk_rows, sk_ord, sk_pr[3], gram_s, rdiag, invd, gramR[4], gred, adjA, adjU,
+      sum, fwdA, fwdU, cgs, cgp, vec;
+  for (GridTable* t : {&fill, &map, &sk_small, &sk_cols, &sk_rows, &sk_ord, &sk_pr[0], &sk_pr[1], &sk_pr[2], &gram_s,
+                       &rdiag, &invd, &gramR[0], &gramR[1], &gramR[2], &gramR[3], &gred, &adjA, &adjU, &sum, &fwdA,
+                       &fwdU, &cgs, &cgp, &vec})
     t->init(batch);
   int maxnbk = 0;
-  size_t lds_small = 0, lds_cols = 0, lds_rows = 0;
+  size_t lds_small = 0, lds_cols = 0, lds_rows = 0, lds_pr = 0;
   int64_t maxm = 0;
   std::vector<int64_t> wbytes((size_t)batch);
   for (int i = 0; i < batch; ++i) {
@@ -1228,15 +1229,19 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     q.idx = idx[i];
     q.ldx = rinv_ld(m[i]);
     maxm = std::max(maxm, m[i]);
-    BGrid g0, g1, g2;
-    size_t a0, a1, a2;
-    b_plan_sketch(bulk, q, g0, g1, g2, a0, a1, a2);
+    BGrid g0, g1, g2, g3;
+    size_t a0, a1, a2, a3;
+    b_plan_sketch(bulk, q, g0, g1, g2, g3, a0, a1, a2, a3);
     sk_small.g[i] = g0;
     sk_cols.g[i] = g1;
     sk_rows.g[i] = g2;
+    const int kc = q.sk_kpt == 2 ? 0 : (q.sk_kpt == 4 ? 1 : (q.sk_kpt == 8 ? 2 : -1));
+    for (int c = 0; c < 3; ++c) sk_pr[c].g[i] = c == kc ? g3 : BGrid{0, 0, 1, 1};
+    sk_ord.g[i] = kc >= 0 ? BGrid{0, 1, 1, 1} : BGrid{0, 0, 1, 1};
     lds_small = std::max(lds_small, a0);
     lds_cols = std::max(lds_cols, a1);
     lds_rows = std::max(lds_rows, a2);
+    lds_pr = std::max(lds_pr, a3);
     q.tw = twiddles(h, N[i], is_single(bulk));
     fill.g[i] = BGrid{0, (int)cdiv(N[i], 256), 1, 1};
     map.g[i] = BGrid{0, (int)cdiv(l[i], 256), 1, 1};
@@ -1263,7 +1268,8 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     // (one extra pass over the bulk copy) so that the fused pass reads
     // 16-byte vectors
     const int64_t pad_ld = b_aligned16(q.Ab, q.ldab, bulk) ? 0 : rup(n[i], std::max<int64_t>(16 / be, 1));
-    wbytes[i] = a256(pad_ld * mm * be) + a256(N[i] * 4) + a256(l[i] * mm * be) + a256(b_sketch_work_elems(bulk, mm, N[i]) * ces) +
+    wbytes[i] = a256(pad_ld * mm * be) + a256(N[i] * 4) + a256(l[i] * 4) + a256(l[i] * mm * be) +
+                a256(b_sketch_work_elems(bulk, mm, N[i], l[i]) * ces) +
                 2 * a256(mm * mm * W) + a256(q.ldx * q.ldx * W) + a256(chol_scratch_elems(mm) * W) +
                 6 * a256(mm * W) + a256(kGramParts * mm * W) +
                 a256((int64_t)q.gram_G * mm * W) + a256(n[i] * W) + a256((int64_t)q.adj_slabs * n[i] * W) +
@@ -1296,9 +1302,10 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       fwdA.g[i].gx = 0;
     }
   }
-  std::vector<GridTable*> all = {&fill,     &map,      &sk_small, &sk_cols, &sk_rows, &gram_s, &rdiag,
-                                 &invd,     &gramR[0], &gramR[1], &gramR[2], &gramR[3], &gred,  &adjA,
-                                 &adjU,     &sum,      &fwdA,     &fwdU,    &cgs,     &cgp,    &vec};
+  std::vector<GridTable*> all = {&fill,     &map,      &sk_small, &sk_cols,  &sk_rows,  &sk_ord, &sk_pr[0],
+                                 &sk_pr[1], &sk_pr[2], &gram_s,   &rdiag,    &invd,     &gramR[0], &gramR[1],
+                                 &gramR[2], &gramR[3], &gred,     &adjA,     &adjU,     &sum,    &fwdA,
+                                 &fwdU,     &cgs,      &cgp,      &vec};
   for (auto& t : chol) all.push_back(&t);
   for (auto& t : trtri) all.push_back(&t);
   size_t nent = 0;
@@ -1336,8 +1343,9 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       q.ldab = pld;
     }
     q.inv = (int32_t*)take(N[i] * 4);
+    q.order = (int32_t*)take(l[i] * 4);
     q.S = take(l[i] * mm * be);
-    q.Y = take(b_sketch_work_elems(bulk, mm, N[i]) * ces);
+    q.Y = take(b_sketch_work_elems(bulk, mm, N[i], l[i]) * ces);
     q.G = take(mm * mm * W);
     q.R = take(mm * mm * W);
     q.X = take(q.ldx * q.ldx * W);
@@ -1402,7 +1410,9 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     ck(hipStreamSynchronize(st));
   }
   // Steps 1-2: sketch, Gram matrix, Cholesky, diagonal range
-  ck(launch_b_sketch(bulk, L(sk_small), L(sk_cols), L(sk_rows), lds_small, lds_cols, lds_rows, st));
+  const BLaunch prl[3] = {L(sk_pr[0]), L(sk_pr[1]), L(sk_pr[2])};
+  ck(launch_b_sketch(bulk, L(sk_small), L(sk_cols), L(sk_rows), L(sk_ord), prl, lds_small, lds_cols, lds_rows, lds_pr,
+                     st));
   ck(launch_b_gram_s(bulk, L(gram_s), st));
   for (int k = 0; k < maxnbk; ++k) ck(launch_b_chol_step(cplx, L(chol[k]), k - 1, st));
   ck(launch_b_rdiag(cplx, L(rdiag), st));

@@ -461,9 +461,10 @@ template <typename V> struct PhaseOf { using type = typename std::conditional<VT
 
 template <int X> __host__ __device__ constexpr int ilog2c() { return X <= 1 ? 0 : 1 + ilog2c<X / 2>(); }
 
+// bk.x = column group, bk.y = row within the launch, bk.gx = groups per row
 template <typename V, typename C, int B, int KPT>
-__global__ void __launch_bounds__(256, 2) k_sketch_pruned(const V* __restrict__ A, int64_t lda, int64_t row0, int64_t rows,
-                                                       int64_t n, int N1, int G, FftPlan pl2,
+__device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t row0,
+                                                       int64_t rows, int64_t n, int N1, int G, FftPlan pl2,
                                                        const void* __restrict__ dv, const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ order, int64_t l,
                                                        const C* __restrict__ tw, V* __restrict__ S, int64_t lds,
@@ -480,7 +481,7 @@ __global__ void __launch_bounds__(256, 2) k_sketch_pruned(const V* __restrict__ 
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
   const unsigned Nm = (unsigned)N1 * (unsigned)N2 - 1u;
-  const int64_t i = row0 + blockIdx.y;
+  const int64_t i = row0 + bk.y;
   const V* row = A + i * lda;
   C* tws = sm + B * Lp;
   if constexpr (TW_LDS) {
@@ -527,7 +528,7 @@ __global__ void __launch_bounds__(256, 2) k_sketch_pruned(const V* __restrict__ 
       pa[r] = j < n ? ld_stream(row + j) : V{};
     }
   };
-  const int cbeg = (int)blockIdx.x * G * B;
+  const int cbeg = bk.x * G * B;
   load(cbeg);
   for (int g = 0; g < G; ++g) {
     const int c0 = cbeg + g * B;
@@ -590,18 +591,28 @@ __global__ void __launch_bounds__(256, 2) k_sketch_pruned(const V* __restrict__ 
     const int q = tid + 256 * u;
     if (q < l) {
       const int64_t s = order[q];
-      if (gridDim.x == 1) S[s + i * lds] = out_value<V, C>(acc[u], scale);
-      else P[((int64_t)blockIdx.x * rows + blockIdx.y) * l + s] = acc[u];
+      if (bk.gx == 1) S[s + i * lds] = out_value<V, C>(acc[u], scale);
+      else P[((int64_t)bk.x * rows + bk.y) * l + s] = acc[u];
     }
   }
+}
+template <typename V, typename C, int B, int KPT>
+__global__ void __launch_bounds__(256, 2) k_sketch_pruned(const V* __restrict__ A, int64_t lda, int64_t row0, int64_t rows,
+                                                       int64_t n, int N1, int G, FftPlan pl2,
+                                                       const void* __restrict__ dv, const int32_t* __restrict__ idx,
+                                                       const int32_t* __restrict__ order, int64_t l,
+                                                       const C* __restrict__ tw, V* __restrict__ S, int64_t lds,
+                                                       C* __restrict__ P, typename VT<C>::real scale) {
+  k_sketch_pruned_body<V, C, B, KPT>(bk_hw(), A, lda, row0, rows, n, N1, G, pl2, dv, idx, order, l, tw, S, lds, P,
+                                     scale);
 }
 
 // order[0 .. l) = a permutation of 0 .. l that groups the kept outputs by
 // idx[s] mod N2 (counting sort on the residue; the order inside a group is
 // whatever the LDS atomics give, which changes no result).  One workgroup of
 // 1024 threads; N2 <= 1024.
-__global__ void __launch_bounds__(1024) k_sketch_order(const int32_t* __restrict__ idx, int64_t l, int N2,
-                                                       int32_t* __restrict__ order) {
+__device__ __forceinline__ void k_sketch_order_body(const int32_t* __restrict__ idx, int64_t l, int N2,
+                                                    int32_t* __restrict__ order) {
   __shared__ int cnt[1024];
   const int tid = threadIdx.x;
   cnt[tid] = 0;
@@ -618,6 +629,10 @@ __global__ void __launch_bounds__(1024) k_sketch_order(const int32_t* __restrict
   }
   __syncthreads();
   for (int64_t s = tid; s < l; s += 1024) order[atomicAdd(&cnt[idx[s] & (N2 - 1)], 1)] = (int32_t)s;
+}
+__global__ void __launch_bounds__(1024) k_sketch_order(const int32_t* __restrict__ idx, int64_t l, int N2,
+                                                       int32_t* __restrict__ order) {
+  k_sketch_order_body(idx, l, N2, order);
 }
 
 // S[s + i lds] = scale * sum over the ng column groups of P[g][i - row0][s]
@@ -906,6 +921,27 @@ __global__ void __launch_bounds__(256) kb_sketch_rows(const BSys* __restrict__ s
                            reinterpret_cast<const C*>(s.tw) + s.N, (R)(1.0 / sqrt((double)s.N)));
 }
 
+// kept-outputs-only four-step (B = 16, one column group per row): one
+// workgroup per row of a system; KPT = the system's accumulator class
+template <typename V, typename C, int KPT>
+__global__ void __launch_bounds__(256, 2) kb_sketch_pruned(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                           int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  using R = typename VT<C>::real;
+  k_sketch_pruned_body<V, C, 16, KPT>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start),
+                                      reinterpret_cast<const V*>(s.Ab), s.ldab, 0, s.m, s.n, s.N1, s.N1 / 16, s.pl_b,
+                                      s.d, s.idx, s.order, s.l, reinterpret_cast<const C*>(s.tw),
+                                      reinterpret_cast<V*>(s.S), s.l, nullptr, (R)(1.0 / sqrt((double)s.N)));
+}
+
+__global__ void __launch_bounds__(1024) kb_sketch_order(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                        int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_sketch_order_body(s.idx, s.l, s.N2, s.order);
+}
+
 __global__ void kb_fill_inv(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys) {
   const int i = bgrid_find(grid, nsys, blockIdx.x);
   const BSys& s = sys[i];
@@ -918,13 +954,15 @@ __global__ void kb_inverse_map(const BSys* __restrict__ sys, const BGrid* __rest
   k_inverse_map_body(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), s.idx, s.l, s.N, s.inv, s.flags);
 }
 
-template <typename C> void plan_sketch_t(BSys& s, BGrid& small, BGrid& cols, BGrid& rows, size_t& ls, size_t& lc,
-                                         size_t& lr) {
+template <typename C> void plan_sketch_t(BSys& s, BGrid& small, BGrid& cols, BGrid& rows, BGrid& pruned, size_t& ls,
+                                         size_t& lc, size_t& lr, size_t& lp) {
   const int N = (int)s.N;
   small = BGrid{0, 0, 1, 1};
   cols = BGrid{0, 0, 1, 1};
   rows = BGrid{0, 0, 1, 1};
-  ls = lc = lr = 0;
+  pruned = BGrid{0, 0, 1, 1};
+  ls = lc = lr = lp = 0;
+  s.sk_kpt = 0;
   if (N <= max_lds_fft_len<C>()) {
     s.pl_a = make_plan(N);
     s.fft_ba = fft_batch<C>(N);
@@ -932,6 +970,16 @@ template <typename C> void plan_sketch_t(BSys& s, BGrid& small, BGrid& cols, BGr
     s.N2 = 1;
     small.gx = (int)ceil_div(s.m, s.fft_ba);
     ls = (size_t)s.fft_ba * lds_stride(N) * sizeof(C);
+    return;
+  }
+  if (pruned_groups<C>(N, s.l, 16, 1) > 0) {
+    // kept outputs only: N2 = 256, one workgroup per row
+    s.N2 = 256;
+    s.N1 = N / 256;
+    s.pl_b = make_plan(256);
+    s.sk_kpt = s.l <= 512 ? 2 : (s.l <= 1024 ? 4 : 8);
+    pruned = BGrid{0, 1, (int)s.m, 1};
+    lp = ((size_t)16 * lds_stride(256) + 256) * sizeof(C);
     return;
   }
   int k = 0;
@@ -951,8 +999,26 @@ template <typename C> void plan_sketch_t(BSys& s, BGrid& small, BGrid& cols, BGr
 }
 
 template <typename V, typename C>
-hipError_t b_sketch_t(const BLaunch& sm, const BLaunch& co, const BLaunch& ro, size_t ls, size_t lc, size_t lr,
-                      hipStream_t st) {
+hipError_t b_sketch_t(const BLaunch& sm, const BLaunch& co, const BLaunch& ro, const BLaunch& ord, const BLaunch* pr,
+                      size_t ls, size_t lc, size_t lr, size_t lp, hipStream_t st) {
+  if (ord.total > 0) {
+    hipLaunchKernelGGL(kb_sketch_order, dim3((unsigned)ord.total), dim3(1024), 0, st, ord.sys, ord.grid, ord.nsys);
+    if (pr[0].total > 0) {
+      allow_lds(kb_sketch_pruned<V, C, 2>, lp);
+      hipLaunchKernelGGL((kb_sketch_pruned<V, C, 2>), dim3((unsigned)pr[0].total), dim3(256), lp, st, pr[0].sys,
+                         pr[0].grid, pr[0].nsys);
+    }
+    if (pr[1].total > 0) {
+      allow_lds(kb_sketch_pruned<V, C, 4>, lp);
+      hipLaunchKernelGGL((kb_sketch_pruned<V, C, 4>), dim3((unsigned)pr[1].total), dim3(256), lp, st, pr[1].sys,
+                         pr[1].grid, pr[1].nsys);
+    }
+    if (pr[2].total > 0) {
+      allow_lds(kb_sketch_pruned<V, C, 8>, lp);
+      hipLaunchKernelGGL((kb_sketch_pruned<V, C, 8>), dim3((unsigned)pr[2].total), dim3(256), lp, st, pr[2].sys,
+                         pr[2].grid, pr[2].nsys);
+    }
+  }
   if (sm.total > 0) {
     allow_lds(kb_sketch_small<V, C>, ls);
     hipLaunchKernelGGL((kb_sketch_small<V, C>), dim3((unsigned)sm.total), dim3(256), ls, st, sm.sys, sm.grid,
@@ -971,14 +1037,16 @@ hipError_t b_sketch_t(const BLaunch& sm, const BLaunch& co, const BLaunch& ro, s
 
 }  // namespace
 
-void b_plan_sketch(int dtype, BSys& s, BGrid& small, BGrid& cols, BGrid& rows, size_t& ls, size_t& lc, size_t& lr) {
-  if (dtype == 1 || dtype == 3) plan_sketch_t<cf>(s, small, cols, rows, ls, lc, lr);
-  else plan_sketch_t<cd>(s, small, cols, rows, ls, lc, lr);
+void b_plan_sketch(int dtype, BSys& s, BGrid& small, BGrid& cols, BGrid& rows, BGrid& pruned, size_t& ls, size_t& lc,
+                   size_t& lr, size_t& lp) {
+  if (dtype == 1 || dtype == 3) plan_sketch_t<cf>(s, small, cols, rows, pruned, ls, lc, lr, lp);
+  else plan_sketch_t<cd>(s, small, cols, rows, pruned, ls, lc, lr, lp);
 }
 
-int64_t b_sketch_work_elems(int dtype, int64_t m, int64_t N) {
+int64_t b_sketch_work_elems(int dtype, int64_t m, int64_t N, int64_t l) {
   const int L = (dtype == 1 || dtype == 3) ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>();
-  return N <= L ? 0 : m * N;
+  if (N <= L || sketch_pruned_groups(dtype, N, l, 16, 1) > 0) return 0;
+  return m * N;
 }
 
 hipError_t launch_b_prep(const BLaunch& fill, const BLaunch& map, hipStream_t st) {
@@ -987,13 +1055,14 @@ hipError_t launch_b_prep(const BLaunch& fill, const BLaunch& map, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_b_sketch(int dtype, const BLaunch& small, const BLaunch& cols, const BLaunch& rows, size_t ls,
-                           size_t lc, size_t lr, hipStream_t st) {
+hipError_t launch_b_sketch(int dtype, const BLaunch& small, const BLaunch& cols, const BLaunch& rows,
+                           const BLaunch& order, const BLaunch* pruned, size_t ls, size_t lc, size_t lr, size_t lp,
+                           hipStream_t st) {
   switch (dtype) {
-    case 0: return b_sketch_t<cd, cd>(small, cols, rows, ls, lc, lr, st);
-    case 1: return b_sketch_t<cf, cf>(small, cols, rows, ls, lc, lr, st);
-    case 2: return b_sketch_t<double, cd>(small, cols, rows, ls, lc, lr, st);
-    case 3: return b_sketch_t<float, cf>(small, cols, rows, ls, lc, lr, st);
+    case 0: return b_sketch_t<cd, cd>(small, cols, rows, order, pruned, ls, lc, lr, lp, st);
+    case 1: return b_sketch_t<cf, cf>(small, cols, rows, order, pruned, ls, lc, lr, lp, st);
+    case 2: return b_sketch_t<double, cd>(small, cols, rows, order, pruned, ls, lc, lr, lp, st);
+    case 3: return b_sketch_t<float, cf>(small, cols, rows, order, pruned, ls, lc, lr, lp, st);
   }
   return hipErrorInvalidValue;
 }

@@ -268,6 +268,8 @@ struct BSys {
   // plan(N2) with fft_bb (columns pass)
   FftPlan pl_a, pl_b;
   int fft_ba, fft_bb, N1, N2;
+  int sk_kpt;      // kept-outputs-only four-step: accumulators per thread (2, 4, 8), or 0
+  int32_t* order;  // l entries: kept outputs grouped by k mod N2 (kept-outputs-only form)
   const void* tw;  // W_N^k, k < N, compute precision
   // workspace
   int32_t* inv;    // N
@@ -296,16 +298,22 @@ struct BLaunch {
   int total;         // workgroups (grid[nsys].start)
 };
 // per-system grids (host) for the passes whose shapes depend on the data
-void b_plan_sketch(int dtype, BSys& s, BGrid& small, BGrid& cols, BGrid& rows, size_t& lds_small, size_t& lds_cols,
-                   size_t& lds_rows);
-int64_t b_sketch_work_elems(int dtype, int64_t m, int64_t N);  // Y entries (0 for the small FFT)
+// (pruned: the kept-outputs-only four-step, one workgroup per row; s.sk_kpt
+// is then its accumulator class 2, 4 or 8, else 0)
+void b_plan_sketch(int dtype, BSys& s, BGrid& small, BGrid& cols, BGrid& rows, BGrid& pruned, size_t& lds_small,
+                   size_t& lds_cols, size_t& lds_rows, size_t& lds_pruned);
+// Y entries (0 for the small FFT and the kept-outputs-only form)
+int64_t b_sketch_work_elems(int dtype, int64_t m, int64_t N, int64_t l);
 // returns the rows-per-thread class (0..3: m <= 64, 128, 256, 512)
 int b_plan_gram(int bulk_dtype, BSys& s, BGrid& gram, BGrid& gram_red);
 void b_plan_wide(int dtype, bool aligned, BSys& s, BGrid& adj, BGrid& sum, BGrid& fwd);
 bool b_aligned16(const void* p, int64_t ld, int dtype);
 hipError_t launch_b_prep(const BLaunch& fill, const BLaunch& map, hipStream_t st);
+// pruned[c]: the kept-outputs-only launches of accumulator class c (2, 4, 8
+// kept outputs per thread); order: one 1024-thread workgroup per system
 hipError_t launch_b_sketch(int dtype, const BLaunch& small, const BLaunch& cols, const BLaunch& rows,
-                           size_t lds_small, size_t lds_cols, size_t lds_rows, hipStream_t st);
+                           const BLaunch& order, const BLaunch* pruned, size_t lds_small, size_t lds_cols,
+                           size_t lds_rows, size_t lds_pruned, hipStream_t st);
 hipError_t launch_b_gram_s(int dtype, const BLaunch& L, hipStream_t st);
 hipError_t launch_b_chol_step(bool cplx, const BLaunch& L, int k, hipStream_t st);
 hipError_t launch_b_rdiag(bool cplx, const BLaunch& L, hipStream_t st);
