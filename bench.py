@@ -167,11 +167,16 @@ def main():
 
     # dominant kernel: the pass over A with the larger total time
     name = max(kstats, key=lambda k: kstats[k][1])
-    kname = {"gemv_adj": "k_gemv_adj", "gemv_fwd": "k_gemv_fwd", "gram": "k_gram"}[name]
+    plans = plans_dump(api, args)
+    # the fused pass reads the column-major copy of A when its plan has bit 19
+    cm = (plans.get(f"gram/0/{m}/{n}/0", 0) >> 19) & 1
+    kname = {"gemv_adj": "k_gemv_adj", "gemv_fwd": "k_gemv_fwd", "gram": "k_gram_cm" if cm else "k_gram"}[name]
     cnt, tot_ms = kstats[name]
     avg_s = tot_ms / cnt / 1e3
     es = 16
-    alg_bytes = m * n * es + (m + n) * es  # A once, plus the input and output vectors
+    # A once, plus the vectors: p in and q out (m each) for the fused pass,
+    # the m- and n-vector for a single product
+    alg_bytes = m * n * es + (2 * m if name == "gram" else m + n) * es
     achieved = alg_bytes / avg_s / 1e9
     kernel_table = {k: {"launches": c, "avg_us": 1e3 * t / max(c, 1)} for k, (c, t) in kstats.items() if c}
     log(f"[bench] kernels {kernel_table}")
@@ -206,7 +211,6 @@ def main():
                          f"each, took {c1 - c0:.2f} s"}
         log(f"[bench] CPU oracle {done} solves in {c1 - c0:.2f} s on {threads} threads")
 
-    plans = plans_dump(api, args)
     out = {
         "metric": "solves/s at rel-err <= 1e-10 (with HBM GB/s per A-pass)",
         "value": solves_per_s,

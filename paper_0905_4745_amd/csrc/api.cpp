@@ -457,6 +457,10 @@ struct CgBufs {
   void *y, *r[2], *p, *s, *w, *part, *qpart, *q;
   PcgState* st;
   int par = 0;
+  // column-major copy of the bulk matrix for the fused pass (written by the
+  // first fused pass of the solve that uses it)
+  void* at = nullptr;
+  bool at_valid = false;
 };
 
 void cg_start(const SolveCtx& c, CgBufs& v, const void* b, const void* parts, int nparts, const void* y_outer) {
@@ -499,25 +503,61 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
   const int32_t* flag = &v.st->done;
   const bool fused = gram_supported(c.bulk, c.m, c.Ab, c.ldab);
   int gram_plan = 512;
+  // One fused pass q = A (A* p).  plan: workgroup count (low 16 bits), bit 16
+  // narrow strips, bit 17 interleaved strips, bit 18 1024 threads, bit 19:
+  // read a column-major copy of A (the solve's first fused pass writes it,
+  // with the row-major kernel and the other bits; it is never skipped by the
+  // stop flag, so the copy is whole before any pass reads it)
+  const int64_t ldt = rup(c.m, 64);
+  // the copy is taken only where it fits in half of the free device memory
+  bool cm_ok = v.at != nullptr;
+  if (fused && !cm_ok) {
+    size_t fr = 0, tot = 0;
+    cm_ok = hipMemGetInfo(&fr, &tot) == hipSuccess && (double)(ldt * c.n * dtype_size(c.bulk)) <= 0.5 * (double)fr;
+  }
+  auto gram = [&](int pl, const int32_t* flg, bool sampled) {
+    if (!cm_ok) pl &= ~0x80000;
+    GramArgs ga{};
+    ga.A = c.Ab;
+    ga.lda = c.ldab;
+    ga.m = c.m;
+    ga.n = c.n;
+    ga.p = v.p;
+    ga.qpart = v.qpart;
+    ga.q = v.q;
+    ga.flag = flg;
+    ga.max_wg = pl & 0xFFFF;
+    ga.narrow = (pl >> 16) & 1;
+    ga.interleave = (pl >> 17) & 1;
+    ga.wide_wg = (pl >> 18) & 1;
+    ga.wide_acc = c.wide_acc;
+    if ((pl >> 19) & 1) {
+      if (!v.at) v.at = ws(h, "gram_at", (size_t)(ldt * c.n * dtype_size(c.bulk)));
+      ga.At = v.at;
+      ga.ldt = ldt;
+      if (!v.at_valid) {
+        ga.at_mode = 1;
+        ga.flag = nullptr;
+        ck(launch_gram(c.bulk, ga, h->stream));
+        v.at_valid = true;
+        // not sampled (another kernel), but it takes its iteration's ordinal
+        // so that the launches after the stop are still recognised
+        if (sampled && h->prof) h->prof_seen[K_GRAM]++;
+        return;
+      }
+      ga.at_mode = 2;
+    }
+    if (sampled) std::tie(ga.ev_begin, ga.ev_end) = prof_pair(h, K_GRAM);
+    ck(launch_gram(c.bulk, ga, h->stream));
+  };
   if (fused) {
-    // plan: workgroup count (low 16 bits) and strip width (bit 16: narrow)
-    auto run = [&](int pl) {
-      GramArgs ga{};
-      ga.A = c.Ab;
-      ga.lda = c.ldab;
-      ga.m = c.m;
-      ga.n = c.n;
-      ga.p = v.p;
-      ga.qpart = v.qpart;
-      ga.q = v.q;
-      ga.max_wg = pl & 0xFFFF;
-      ga.narrow = (pl >> 16) & 1;
-      ga.interleave = (pl >> 17) & 1;
-      ga.wide_wg = (pl >> 18) & 1;
-      ga.wide_acc = c.wide_acc;
-      ck(launch_gram(c.bulk, ga, h->stream));
-    };
+    auto run = [&](int pl) { gram(pl, nullptr, false); };
+    // default (first candidate): the column-major pass, 256 interleaved
+    // workgroups, where the copy fits; else the row-major pass, 512
     std::vector<int> cands;
+    if (cm_ok)
+      for (int il : {0x20000, 0})
+        for (int wg : {256, 512, 1024}) cands.push_back(wg | il | 0x80000);
     for (int ww : {0, 0x40000})
       for (int il : {0, 0x20000})
         for (int nw : {0, 0x10000})
@@ -532,22 +572,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
   while (true) {
     for (int k = 0; k < ce; ++k) {
       if (fused) {
-        GramArgs ga{};
-        ga.A = c.Ab;
-        ga.lda = c.ldab;
-        ga.m = c.m;
-        ga.n = c.n;
-        ga.p = v.p;
-        ga.qpart = v.qpart;
-        ga.q = v.q;
-        ga.flag = flag;
-        ga.max_wg = gram_plan & 0xFFFF;
-        ga.narrow = (gram_plan >> 16) & 1;
-        ga.interleave = (gram_plan >> 17) & 1;
-        ga.wide_wg = (gram_plan >> 18) & 1;
-        ga.wide_acc = c.wide_acc;
-        std::tie(ga.ev_begin, ga.ev_end) = prof_pair(h, K_GRAM);
-        ck(launch_gram(c.bulk, ga, h->stream));
+        gram(gram_plan, flag, true);
         CgStep a{};
         a.X = c.X;
         a.m = c.m;

@@ -193,11 +193,14 @@ __global__ void __launch_bounds__(256) k_gemv_fwd(const V* __restrict__ A, int64
 //   qacc_r += sum_c A_rc t_c     (registers, reduced over column groups once
 //                                 per workgroup at the end)
 // Output: qpart[g * m + i], FP64; the strips of a workgroup are contiguous.
-template <typename V, typename C, typename U, int CPT, int RPT, int TPB, int VEC>
+// WT: also store every entry read into the column-major copy At (column c
+// at At + c ldt); for one register slot the lanes of a wave then write 8
+// columns x 8 consecutive rows, 128-byte runs.
+template <typename V, typename C, typename U, int CPT, int RPT, int TPB, int VEC, bool WT = false>
 __device__ __forceinline__ void k_gram_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                               const U* __restrict__ p, int64_t strips_per_wg, int64_t nstrips,
                                               U* __restrict__ qpart, const int32_t* __restrict__ flag,
-                                              int interleave) {
+                                              int interleave, V* __restrict__ At = nullptr, int64_t ldt = 0) {
   if (stopped(flag)) return;
   constexpr int WD = 8 * CPT;
   // VEC: elements per load (16 bytes when rows are 16-byte aligned, else 1)
@@ -245,6 +248,11 @@ __device__ __forceinline__ void k_gram_body(const Bk bk, const V* __restrict__ A
       } else {
 #pragma unroll
         for (int u = 0; u < CPT; ++u) x[k][u] = (r < m && cbase + u < n) ? A[r * lda + cbase + u] : vzero<V>();
+      }
+      if constexpr (WT) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u)
+          if (r < m && cbase + u < n) At[(cbase + u) * ldt + r] = x[k][u];
       }
     }
   };
@@ -328,6 +336,101 @@ __global__ void __launch_bounds__(TPB) k_gram(const V* __restrict__ A, int64_t l
                                               U* __restrict__ qpart, const int32_t* __restrict__ flag,
                                               int interleave) {
   k_gram_body<V, C, U, CPT, RPT, TPB, VEC>(bk_hw(), A, lda, m, n, p, strips_per_wg, nstrips, qpart, flag, interleave);
+}
+// the same pass, also writing the column-major copy At
+template <typename V, typename C, typename U, int CPT, int RPT, int TPB, int VEC>
+__global__ void __launch_bounds__(TPB) k_gram_wt(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                 const U* __restrict__ p, int64_t strips_per_wg, int64_t nstrips,
+                                                 U* __restrict__ qpart, const int32_t* __restrict__ flag,
+                                                 int interleave, V* __restrict__ At, int64_t ldt) {
+  k_gram_body<V, C, U, CPT, RPT, TPB, VEC, true>(bk_hw(), A, lda, m, n, p, strips_per_wg, nstrips, qpart, flag,
+                                                 interleave, At, ldt);
+}
+
+// ---------------------------------------------------------------------------
+// Fused pass q = A (A* p) from the column-major copy At (column c of A at
+// At + c ldt, its m rows contiguous), m <= 64 RPT.  512 threads; strips of
+// 8 CPT columns, wave w takes columns w CPT .. w CPT + CPT - 1 of each strip
+// and lane l rows l + 64 k (k < RPT) of them, so one load instruction of a
+// wave reads 64 consecutive entries of one column and a wave streams CPT
+// whole columns per strip.  The column sums t_c = sum_r conj(A_rc) p_r are a
+// single all-lane wave reduction -- no LDS and no barrier per strip, the
+// waves run decoupled -- and q_r += sum_c A_rc t_c stays in registers until
+// one reduction over the 8 waves at the end.  Output as k_gram.
+template <typename V, typename C, typename U, int CPT, int RPT>
+__global__ void __launch_bounds__(512) k_gram_cm(const V* __restrict__ At, int64_t ldt, int64_t m, int64_t n,
+                                                 const U* __restrict__ p, int64_t strips_per_wg, int64_t nstrips,
+                                                 U* __restrict__ qpart, const int32_t* __restrict__ flag,
+                                                 int interleave) {
+  if (stopped(flag)) return;
+  constexpr int WD = 8 * CPT;
+  __shared__ U red[8][64 * RPT];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int g = (int)blockIdx.x, G = (int)gridDim.x;
+  C pr[RPT], qacc[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int64_t r = lane + 64 * k;
+    pr[k] = r < m ? vconv<C>(p[r]) : vzero<C>();
+    qacc[k] = vzero<C>();
+  }
+  int64_t s0, s1, sstep;
+  if (interleave) {
+    s0 = g;
+    s1 = nstrips;
+    sstep = G;
+  } else {
+    s0 = (int64_t)g * strips_per_wg;
+    s1 = s0 + strips_per_wg;
+    if (s1 > nstrips) s1 = nstrips;
+    sstep = 1;
+  }
+  auto load_strip = [&](V (&x)[RPT][CPT], int64_t sidx) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int64_t c = sidx * WD + wv * CPT + u;
+      const V* col = At + c * ldt;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int64_t r = lane + 64 * k;
+        x[k][u] = (c < n && r < m) ? col[r] : vzero<V>();
+      }
+    }
+  };
+  auto process = [&](const V (&x)[RPT][CPT]) {
+    C tc[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      C a = vzero<C>();
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) a = vcfma(vconv<C>(x[k][u]), pr[k], a);
+      tc[u] = wave_sum(a);
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) qacc[k] = vfma(vconv<C>(x[k][u]), tc[u], qacc[k]);
+  };
+  V xa[RPT][CPT], xb[RPT][CPT];
+  if (s0 < s1) load_strip(xa, s0);
+  for (int64_t sidx = s0; sidx < s1; sidx += 2 * sstep) {
+    if (sidx + sstep < s1) load_strip(xb, sidx + sstep);
+    process(xa);
+    if (sidx + sstep < s1) {
+      if (sidx + 2 * sstep < s1) load_strip(xa, sidx + 2 * sstep);
+      process(xb);
+    }
+  }
+  // sum over the 8 waves (fixed order) and write this workgroup's partial
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) red[wv][lane + 64 * k] = vconv<U>(qacc[k]);
+  __syncthreads();
+  for (int r = t; r < 64 * RPT; r += 512) {
+    U v = red[0][r];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) v = vadd(v, red[w][r]);
+    if (r < m) qpart[(int64_t)g * m + r] = v;
+  }
 }
 
 // First level of the sum over workgroup partials: q8[gr * m + i] = sum of
@@ -439,7 +542,22 @@ static hipError_t gram_go(const GramArgs& a, hipStream_t st) {
   const V* A = reinterpret_cast<const V*>(a.A);
   const U* p = reinterpret_cast<const U*>(a.p);
   U* qpart = reinterpret_cast<U*>(a.qpart);
-  if (a.wide_wg) {
+  if (a.at_mode == 1) {
+    // the pass that also writes the column-major copy (512 threads)
+    V* At = reinterpret_cast<V*>(a.At);
+    if (a.m <= 64)
+      hipLaunchKernelGGL((k_gram_wt<V, C, U, CPT, 1, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m,
+                         a.n, p, spw, nstrips, qpart, a.flag, a.interleave, At, a.ldt);
+    else if (a.m <= 128)
+      hipLaunchKernelGGL((k_gram_wt<V, C, U, CPT, 2, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m,
+                         a.n, p, spw, nstrips, qpart, a.flag, a.interleave, At, a.ldt);
+    else if (a.m <= 256)
+      hipLaunchKernelGGL((k_gram_wt<V, C, U, CPT, 4, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m,
+                         a.n, p, spw, nstrips, qpart, a.flag, a.interleave, At, a.ldt);
+    else
+      hipLaunchKernelGGL((k_gram_wt<V, C, U, CPT, 8, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, A, a.lda, a.m,
+                         a.n, p, spw, nstrips, qpart, a.flag, a.interleave, At, a.ldt);
+  } else if (a.wide_wg) {
     // 1024 threads: 128 row groups, RPT rows each
     if (a.m <= 128)
       hipExtLaunchKernelGGL((k_gram<V, C, U, CPT, 1, 1024, VEC>), dim3((unsigned)G), dim3(1024), 0, st, a.ev_begin,
@@ -469,9 +587,42 @@ static hipError_t gram_go(const GramArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The pass over the column-major copy: RPT = ceil(m / 64) rows per lane
+// (1, 2, 4, 8) and CPT = 16 / RPT columns per wave and strip, at most 8
+// (16 entries per lane and register set, 8 for m <= 64).
+template <typename V, typename C, typename U>
+static hipError_t gram_cm_go(const GramArgs& a, hipStream_t st) {
+  const int rpt = a.m <= 64 ? 1 : (a.m <= 128 ? 2 : (a.m <= 256 ? 4 : 8));
+  const int64_t WD = 8 * (rpt == 1 ? 8 : 16 / rpt);
+  const int64_t nstrips = ceil_div(a.n, WD);
+  const int64_t maxwg = a.max_wg > 0 && a.max_wg <= kGramMaxWg ? a.max_wg : 512;
+  int64_t G = nstrips < maxwg ? nstrips : maxwg;
+  const int64_t spw = ceil_div(nstrips, G);
+  G = ceil_div(nstrips, spw);
+  const V* At = reinterpret_cast<const V*>(a.At);
+  const U* p = reinterpret_cast<const U*>(a.p);
+  U* qpart = reinterpret_cast<U*>(a.qpart);
+  if (rpt == 1)
+    hipExtLaunchKernelGGL((k_gram_cm<V, C, U, 8, 1>), dim3((unsigned)G), dim3(512), 0, st, a.ev_begin, a.ev_end, 0,
+                          At, a.ldt, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
+  else if (rpt == 2)
+    hipExtLaunchKernelGGL((k_gram_cm<V, C, U, 8, 2>), dim3((unsigned)G), dim3(512), 0, st, a.ev_begin, a.ev_end, 0,
+                          At, a.ldt, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
+  else if (rpt == 4)
+    hipExtLaunchKernelGGL((k_gram_cm<V, C, U, 4, 4>), dim3((unsigned)G), dim3(512), 0, st, a.ev_begin, a.ev_end, 0,
+                          At, a.ldt, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
+  else
+    hipExtLaunchKernelGGL((k_gram_cm<V, C, U, 2, 8>), dim3((unsigned)G), dim3(512), 0, st, a.ev_begin, a.ev_end, 0,
+                          At, a.ldt, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
+  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64), 8), dim3(256), 0, st, qpart, (int)G,
+                     a.m, reinterpret_cast<U*>(a.q), a.flag);
+  return hipGetLastError();
+}
+
 // Strip width: 32 bytes of a row per thread (CPT0), or half of that.
 template <typename V, typename C, typename U>
 static hipError_t gram_impl(const GramArgs& a, hipStream_t st) {
+  if (a.at_mode == 2) return gram_cm_go<V, C, U>(a, st);
   constexpr int CPT0 = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;
   constexpr int CPT1 = CPT0 / 2 > 0 ? CPT0 / 2 : 1;
   constexpr int VA = Vec16<V>::n;

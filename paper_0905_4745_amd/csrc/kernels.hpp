@@ -115,6 +115,12 @@ struct GramArgs {
   int interleave = 0;  // plan: workgroup g takes strips g, g + G, ... instead of a run
   int wide_wg = 0;     // plan: 1024 threads per workgroup (half the rows per thread)
   int wide_acc = 0;    // single-precision data: accumulate in FP64
+  // column-major copy of A (column c at At + c ldt, ldt >= m): at_mode 1 =
+  // the row-major pass that also writes it, 2 = the pass that reads it
+  // instead of A
+  void* At = nullptr;
+  int64_t ldt = 0;
+  int at_mode = 0;
 };
 bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda);
 hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st);
