@@ -38,9 +38,9 @@ DEFAULT_PLANS = os.path.join(ROOT, "paper_0905_4745_amd", "plans", "mi355x.json"
 # plain 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the
 # kernel source it was measured on: a changed source reports null.
 MEASURED_TRAFFIC = {
-    "k_gram": {"bytes": 539.24e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-               "sha256": "b1b260aecc8ddbcc2091c23776b441da951a79723a361c112ce9d90714a96e35",
-               "plan_key": "gram/0/512/65536/0", "plan": 131328},
+    "k_gram_cm": {"bytes": 539.15e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
+                  "sha256": "412fa7ba91c9bc184b05afb149bc2e2db6c82dc3f3aec740f023b7fd283c3922",
+                  "plan_key": "gram/0/512/65536/0", "plan": 655616},
 }
 
 
