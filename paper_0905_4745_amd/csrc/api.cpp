@@ -1235,6 +1235,16 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     t->init(batch);
   int maxnbk = 0;
   size_t lds_small = 0, lds_cols = 0, lds_rows = 0, lds_pr = 0;
+  // the fused passes read column-major copies of the bulk matrices (written
+  // by the first pass) where all of them fit in half the free memory; the
+  // copy also spares the padded re-layout of rows that are not 16-byte aligned
+  bool use_cm = false;
+  {
+    double need = 0.0;
+    for (int i = 0; i < batch; ++i) need += (double)(rup(m[i], 64) * n[i] * dtype_size(bulk));
+    size_t fr = 0, tot = 0;
+    use_cm = hipMemGetInfo(&fr, &tot) == hipSuccess && need <= 0.5 * (double)fr;
+  }
   int64_t maxm = 0;
   std::vector<int64_t> wbytes((size_t)batch);
   for (int i = 0; i < batch; ++i) {
@@ -1292,8 +1302,9 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     // an unaligned bulk row start is re-laid with a padded leading dimension
     // (one extra pass over the bulk copy) so that the fused pass reads
     // 16-byte vectors
-    const int64_t pad_ld = b_aligned16(q.Ab, q.ldab, bulk) ? 0 : rup(n[i], std::max<int64_t>(16 / be, 1));
-    wbytes[i] = a256(pad_ld * mm * be) + a256(N[i] * 4) + a256(l[i] * 4) + a256(l[i] * mm * be) +
+    const int64_t pad_ld = (use_cm || b_aligned16(q.Ab, q.ldab, bulk)) ? 0 : rup(n[i], std::max<int64_t>(16 / be, 1));
+    wbytes[i] = a256(pad_ld * mm * be) + (use_cm ? a256(rup(mm, 64) * n[i] * be) : 0) + a256(N[i] * 4) +
+                a256(l[i] * 4) + a256(l[i] * mm * be) +
                 a256(b_sketch_work_elems(bulk, mm, N[i], l[i]) * ces) +
                 2 * a256(mm * mm * W) + a256(q.ldx * q.ldx * W) + a256(chol_scratch_elems(mm) * W) +
                 6 * a256(mm * W) + a256(kGramParts * mm * W) +
@@ -1359,7 +1370,10 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       return (void*)r;
     };
     const int64_t mm = m[i];
-    if (!b_aligned16(q.Ab, q.ldab, bulk)) {
+    if (use_cm) {
+      q.ldt = rup(mm, 64);
+      q.At = take(q.ldt * n[i] * be);
+    } else if (!b_aligned16(q.Ab, q.ldab, bulk)) {
       const int64_t pld = rup(n[i], std::max<int64_t>(16 / be, 1));
       void* pad = take(pld * mm * be);
       ck(hipMemcpy2DAsync(pad, (size_t)(pld * be), q.Ab, (size_t)(q.ldab * be), (size_t)(n[i] * be), (size_t)mm,
@@ -1493,6 +1507,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   ck(hipStreamSynchronize(st));
   const size_t cg_lds = (size_t)maxm * W;
   int par = 0;
+  bool at_written = false;
   auto all_done = [&](bool outer) {
     for (int i = 0; i < batch; ++i)
       if (!(outer ? hst_state[i].outer_done : hst_state[i].done)) return false;
@@ -1504,7 +1519,8 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     while (true) {
       for (int it = 0; it < ce; ++it) {
         const BLaunch gl[4] = {L(gramR[0]), L(gramR[1]), L(gramR[2]), L(gramR[3])};
-        ck(launch_b_gram(bulk, gl, L(gred), st));
+        ck(launch_b_gram(bulk, gl, L(gred), use_cm ? (at_written ? 2 : 1) : 0, st));
+        at_written = true;
         ck(launch_b_cg(cplx, L(cgs), L(cgp), 0, 2, 0, par, cg_lds, st));
         par ^= 1;
       }

@@ -358,15 +358,15 @@ __global__ void __launch_bounds__(TPB) k_gram_wt(const V* __restrict__ A, int64_
 // waves run decoupled -- and q_r += sum_c A_rc t_c stays in registers until
 // one reduction over the 8 waves at the end.  Output as k_gram.
 template <typename V, typename C, typename U, int CPT, int RPT>
-__global__ void __launch_bounds__(512) k_gram_cm(const V* __restrict__ At, int64_t ldt, int64_t m, int64_t n,
-                                                 const U* __restrict__ p, int64_t strips_per_wg, int64_t nstrips,
-                                                 U* __restrict__ qpart, const int32_t* __restrict__ flag,
-                                                 int interleave) {
+__device__ __forceinline__ void k_gram_cm_body(const Bk bk, const V* __restrict__ At, int64_t ldt, int64_t m,
+                                                 int64_t n, const U* __restrict__ p, int64_t strips_per_wg,
+                                                 int64_t nstrips, U* __restrict__ qpart,
+                                                 const int32_t* __restrict__ flag, int interleave) {
   if (stopped(flag)) return;
   constexpr int WD = 8 * CPT;
   __shared__ U red[8][64 * RPT];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int g = (int)blockIdx.x, G = (int)gridDim.x;
+  const int g = bk.x, G = bk.gx;
   C pr[RPT], qacc[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
@@ -432,6 +432,13 @@ __global__ void __launch_bounds__(512) k_gram_cm(const V* __restrict__ At, int64
     if (r < m) qpart[(int64_t)g * m + r] = v;
   }
 }
+template <typename V, typename C, typename U, int CPT, int RPT>
+__global__ void __launch_bounds__(512) k_gram_cm(const V* __restrict__ At, int64_t ldt, int64_t m, int64_t n,
+                                                 const U* __restrict__ p, int64_t strips_per_wg, int64_t nstrips,
+                                                 U* __restrict__ qpart, const int32_t* __restrict__ flag,
+                                                 int interleave) {
+  k_gram_cm_body<V, C, U, CPT, RPT>(bk_hw(), At, ldt, m, n, p, strips_per_wg, nstrips, qpart, flag, interleave);
+}
 
 // First level of the sum over workgroup partials: q8[gr * m + i] = sum of
 // qpart[g * m + i] over the gr-th eighth of g, in a fixed order.
@@ -460,7 +467,7 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const U* __restrict__ qpart
 }
 
 // ---------------------------------------------------------------------------
-static bool aligned16(const void* p, int64_t ld, int64_t es) {
+__host__ __device__ static inline bool aligned16(const void* p, int64_t ld, int64_t es) {
   return ((uintptr_t)p % 16 == 0) && ((ld * es) % 16 == 0);
 }
 
@@ -685,6 +692,38 @@ __global__ void __launch_bounds__(512) kb_gram(const BSys* __restrict__ sys, con
                                          reinterpret_cast<U*>(s.qpart), &s.st->done, 0);
 }
 
+// the same pass, also writing each system's column-major copy At (16-byte
+// loads where the system's rows allow them); never skipped by the stop flag,
+// so every copy is whole before a pass reads it
+template <typename V, typename C, typename U, int CPT, int RPT, int VEC>
+__global__ void __launch_bounds__(512) kb_gram_wt(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                  int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  const Bk bk = bgrid_local(grid[i], (int)blockIdx.x - grid[i].start);
+  const V* A = reinterpret_cast<const V*>(s.Ab);
+  if (aligned16(A, s.ldab, sizeof(V)))
+    k_gram_body<V, C, U, CPT, RPT, 512, VEC, true>(bk, A, s.ldab, s.m, s.n, reinterpret_cast<const U*>(s.p),
+                                                   s.gram_spw, s.gram_nstrips, reinterpret_cast<U*>(s.qpart),
+                                                   nullptr, 0, reinterpret_cast<V*>(s.At), s.ldt);
+  else
+    k_gram_body<V, C, U, CPT, RPT, 512, 1, true>(bk, A, s.ldab, s.m, s.n, reinterpret_cast<const U*>(s.p),
+                                                 s.gram_spw, s.gram_nstrips, reinterpret_cast<U*>(s.qpart), nullptr,
+                                                 0, reinterpret_cast<V*>(s.At), s.ldt);
+}
+
+// the pass over each system's column-major copy
+template <typename V, typename C, typename U, int CPT, int RPT>
+__global__ void __launch_bounds__(512) kb_gram_cm(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                  int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  k_gram_cm_body<V, C, U, CPT, RPT>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start),
+                                    reinterpret_cast<const V*>(s.At), s.ldt, s.m, s.n,
+                                    reinterpret_cast<const U*>(s.p), s.cm_spw, s.cm_nstrips,
+                                    reinterpret_cast<U*>(s.qpart), &s.st->done, 0);
+}
+
 template <typename U>
 __global__ void __launch_bounds__(256) kb_gram_reduce(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
                                                       int nsys) {
@@ -738,6 +777,14 @@ template <typename V> int plan_gram_t(BSys& s, BGrid& gram, BGrid& red) {
   s.gram_spw = spw;
   s.gram_nstrips = nstrips;
   s.gram_G = (int)G;
+  // the pass over the column-major copy: the same G, its own strips (8 CPT'
+  // columns, CPT' = 16 / rows per lane, at most 8)
+  {
+    const int rpt = s.m <= 64 ? 1 : (s.m <= 128 ? 2 : (s.m <= 256 ? 4 : 8));
+    const int64_t wd = 8 * (rpt == 1 ? 8 : 16 / rpt);
+    s.cm_nstrips = ceil_div(s.n, wd);
+    s.cm_spw = ceil_div(s.cm_nstrips, G);
+  }
   gram = BGrid{0, (int)G, 1, 1};
   red = BGrid{0, (int)ceil_div(s.m, 64), 8, 1};
   // rows per thread class: 512 threads hold 64 RPT rows
@@ -789,31 +836,39 @@ void b_plan_wide(int dtype, bool aligned, BSys& s, BGrid& adj, BGrid& sum, BGrid
 }
 
 template <typename V, typename C, typename U, int RPT>
-static void b_gram_one(const BLaunch& L, hipStream_t st) {
+static void b_gram_one(const BLaunch& L, int mode, hipStream_t st) {
   constexpr int CPT = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;
-  if (L.total > 0)
+  constexpr int CPTC = RPT == 1 ? 8 : 16 / RPT;
+  if (L.total <= 0) return;
+  if (mode == 1)
+    hipLaunchKernelGGL((kb_gram_wt<V, C, U, CPT, RPT, Vec16<V>::n>), dim3((unsigned)L.total), dim3(512), 0, st, L.sys,
+                       L.grid, L.nsys);
+  else if (mode == 2)
+    hipLaunchKernelGGL((kb_gram_cm<V, C, U, CPTC, RPT>), dim3((unsigned)L.total), dim3(512), 0, st, L.sys, L.grid,
+                       L.nsys);
+  else
     hipLaunchKernelGGL((kb_gram<V, C, U, CPT, RPT, Vec16<V>::n>), dim3((unsigned)L.total), dim3(512), 0, st, L.sys,
                        L.grid, L.nsys);
 }
 
 template <typename V, typename C, typename U>
-static hipError_t b_gram_go(const BLaunch* L, const BLaunch& red, hipStream_t st) {
-  b_gram_one<V, C, U, 1>(L[0], st);
-  b_gram_one<V, C, U, 2>(L[1], st);
-  b_gram_one<V, C, U, 4>(L[2], st);
-  b_gram_one<V, C, U, 8>(L[3], st);
+static hipError_t b_gram_go(const BLaunch* L, const BLaunch& red, int mode, hipStream_t st) {
+  b_gram_one<V, C, U, 1>(L[0], mode, st);
+  b_gram_one<V, C, U, 2>(L[1], mode, st);
+  b_gram_one<V, C, U, 4>(L[2], mode, st);
+  b_gram_one<V, C, U, 8>(L[3], mode, st);
   if (red.total > 0)
     hipLaunchKernelGGL((kb_gram_reduce<U>), dim3((unsigned)red.total), dim3(256), 0, st, red.sys, red.grid,
                        red.nsys);
   return hipGetLastError();
 }
 
-hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st) {
+hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, int mode, hipStream_t st) {
   switch (dtype) {
-    case 0: return b_gram_go<cd, cd, cd>(L, red, st);
-    case 1: return b_gram_go<cf, cf, cd>(L, red, st);
-    case 2: return b_gram_go<double, double, double>(L, red, st);
-    case 3: return b_gram_go<float, float, double>(L, red, st);
+    case 0: return b_gram_go<cd, cd, cd>(L, red, mode, st);
+    case 1: return b_gram_go<cf, cf, cd>(L, red, mode, st);
+    case 2: return b_gram_go<double, double, double>(L, red, mode, st);
+    case 3: return b_gram_go<float, float, double>(L, red, mode, st);
   }
   return hipErrorInvalidValue;
 }

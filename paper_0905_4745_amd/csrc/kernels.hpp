@@ -292,6 +292,9 @@ struct BSys {
   PcgState* st;
   int64_t gram_spw, gram_nstrips;
   int gram_G;
+  void* At;        // column-major copy of Ab for the fused pass (ldt x n), or null
+  int64_t ldt;
+  int64_t cm_spw, cm_nstrips;  // strips of the pass over At
   int adj_slabs;
   int64_t adj_rps;
   int fwd_chunks;
@@ -327,7 +330,9 @@ hipError_t launch_b_inv_diag(bool cplx, const BLaunch& L, hipStream_t st);
 hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int k, hipStream_t st);
 // the fused pass q = A (A* p) on the bulk copy (16-byte aligned rows), one
 // launch per rows-per-thread class L[0..3], then the partial sums
-hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st);
+// mode 0: row-major pass over Ab; 1: the same, also writing each system's
+// column-major copy At (never skipped); 2: the pass over At
+hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, int mode, hipStream_t st);
 // FP64 passes on the problem data: w64 (or x) = A* u, u = y_outer (outer) or y;
 // fpart = A w64 in column chunks
 hipError_t launch_b_adj_wide(int dtype, bool aligned, const BLaunch& L, const BLaunch& sum, int use_y, int to_x,
