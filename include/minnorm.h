@@ -164,7 +164,13 @@ int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* tot
  *                            strip order (bit 17 set: workgroup g takes strips
  *                            g, g + G, ... instead of a contiguous run) and
  *                            workgroup size (bit 18 set: 1024 threads, half
- *                            the rows per thread; 512 otherwise);
+ *                            the rows per thread; 512 otherwise); bit 19 set:
+ *                            the passes read a column-major copy of the bulk
+ *                            matrix (m rounded up to 64, times n entries of
+ *                            device workspace, kept by the handle), written by
+ *                            the first pass of each solve with the other bits;
+ *                            the default where the copy fits in half the free
+ *                            device memory (else the row-major pass, 512);
  * "sketch_chunk_mb/<dtype>/<m>/<N>/0"  four-step FFT: MB of the intermediate
  *                            per chunk of rows (low 16 bits: 16 .. 512),
  *                            workgroup size in elements (bit 16 set: 2048,
