@@ -1287,6 +1287,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     BGrid gg, gr;
     // every bulk row start is 16-byte aligned (padded below if not)
     const int cls = b_plan_gram(bulk, q, gg, gr);
+    b_plan_gram_res(dtype, q);
     for (int c = 0; c < 4; ++c) gramR[c].g[i] = c == cls ? gg : BGrid{0, 0, 1, 1};
     gred.g[i] = gr;
     BGrid ga, gs, gf;
@@ -1532,11 +1533,20 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   if (mixed) {
     ck(launch_b_zero_outer(cplx, L(vec), st));
     for (int outer = 0; outer <= o.max_refine + 1; ++outer) {
-      ck(launch_b_adj_wide(dtype, true, L(adjA), none, 0, 0, st));
-      ck(launch_b_adj_wide(dtype, false, L(adjU), L(sum), 0, 0, st));
-      ck(launch_b_fwd_wide(dtype, true, L(fwdA), st));
-      ck(launch_b_fwd_wide(dtype, false, L(fwdU), st));
-      ck(launch_b_cg(cplx, L(cgs), L(cgp), 1, 1, 1, par, cg_lds, st));
+      // r = b - A (A* y_outer) in FP64: one fused pass over FP64 data (its
+      // instances for single-precision problem data with m > 256 would spill
+      // registers, so those keep the two passes A* then A)
+      if (!is_single(dtype)) {
+        const BLaunch gl[4] = {L(gramR[0]), L(gramR[1]), L(gramR[2]), L(gramR[3])};
+        ck(launch_b_gram_res(dtype, gl, L(gred), st));
+        ck(launch_b_cg(cplx, L(cgs), L(cgp), 1, 2, 1, par, cg_lds, st));
+      } else {
+        ck(launch_b_adj_wide(dtype, true, L(adjA), none, 0, 0, st));
+        ck(launch_b_adj_wide(dtype, false, L(adjU), L(sum), 0, 0, st));
+        ck(launch_b_fwd_wide(dtype, true, L(fwdA), st));
+        ck(launch_b_fwd_wide(dtype, false, L(fwdU), st));
+        ck(launch_b_cg(cplx, L(cgs), L(cgp), 1, 1, 1, par, cg_lds, st));
+      }
       read_states();
       if (all_done(true)) break;
       inner_loop();

@@ -726,11 +726,31 @@ __global__ void __launch_bounds__(512) kb_gram_cm(const BSys* __restrict__ sys, 
 
 template <typename U>
 __global__ void __launch_bounds__(256) kb_gram_reduce(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
-                                                      int nsys) {
+                                                      int nsys, int use_flag) {
   const int i = bgrid_find(grid, nsys, blockIdx.x);
   const BSys& s = sys[i];
   k_gram_reduce_body<U>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start), reinterpret_cast<const U*>(s.qpart),
-                        s.gram_G, s.m, reinterpret_cast<U*>(s.q), &s.st->done);
+                        s.gram_G, s.m, reinterpret_cast<U*>(s.q), use_flag ? &s.st->done : nullptr);
+}
+
+// FP64 residual product of the refinement, q = A (A* y_outer), as one fused
+// pass over each system's problem data A (16-byte loads where its rows
+// allow them); never skipped (the inner iteration's stop flag is set when a
+// residual is due)
+template <typename V, typename U, int CPT, int RPT>
+__global__ void __launch_bounds__(512) kb_gram_res(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                   int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  const Bk bk = bgrid_local(grid[i], (int)blockIdx.x - grid[i].start);
+  const V* A = reinterpret_cast<const V*>(s.A);
+  if (aligned16(A, s.lda, sizeof(V)))
+    k_gram_body<V, U, U, CPT, RPT, 512, Vec16<V>::n>(bk, A, s.lda, s.m, s.n, reinterpret_cast<const U*>(s.y_outer),
+                                                     s.res_spw, s.res_nstrips, reinterpret_cast<U*>(s.qpart),
+                                                     nullptr, 0);
+  else
+    k_gram_body<V, U, U, CPT, RPT, 512, 1>(bk, A, s.lda, s.m, s.n, reinterpret_cast<const U*>(s.y_outer), s.res_spw,
+                                           s.res_nstrips, reinterpret_cast<U*>(s.qpart), nullptr, 0);
 }
 
 // A* u in FP64 into slab partials; u = y (use_y) or y_outer
@@ -817,6 +837,13 @@ template <typename V> void plan_wide_t(bool aligned, BSys& s, BGrid& adj, BGrid&
 
 bool b_aligned16(const void* p, int64_t ld, int dtype) { return aligned16(p, ld, dtype_size(dtype)); }
 
+void b_plan_gram_res(int dtype, BSys& s) {
+  const int64_t es = dtype_size(dtype);
+  const int64_t cpt = 32 / es > 0 ? 32 / es : 1;
+  s.res_nstrips = ceil_div(s.n, 8 * cpt);
+  s.res_spw = ceil_div(s.res_nstrips, (int64_t)s.gram_G);
+}
+
 int b_plan_gram(int bulk_dtype, BSys& s, BGrid& gram, BGrid& red) {
   switch (bulk_dtype) {
     case 0: return plan_gram_t<cd>(s, gram, red);
@@ -859,8 +886,38 @@ static hipError_t b_gram_go(const BLaunch* L, const BLaunch& red, int mode, hipS
   b_gram_one<V, C, U, 8>(L[3], mode, st);
   if (red.total > 0)
     hipLaunchKernelGGL((kb_gram_reduce<U>), dim3((unsigned)red.total), dim3(256), 0, st, red.sys, red.grid,
-                       red.nsys);
+                       red.nsys, 1);
   return hipGetLastError();
+}
+
+template <typename V, typename U, int RPT>
+static void b_res_one(const BLaunch& L, hipStream_t st) {
+  constexpr int CPT = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;
+  if (L.total > 0)
+    hipLaunchKernelGGL((kb_gram_res<V, U, CPT, RPT>), dim3((unsigned)L.total), dim3(512), 0, st, L.sys, L.grid,
+                       L.nsys);
+}
+
+template <typename V, typename U>
+static hipError_t b_res_go(const BLaunch* L, const BLaunch& red, hipStream_t st) {
+  b_res_one<V, U, 1>(L[0], st);
+  b_res_one<V, U, 2>(L[1], st);
+  b_res_one<V, U, 4>(L[2], st);
+  b_res_one<V, U, 8>(L[3], st);
+  if (red.total > 0)
+    hipLaunchKernelGGL((kb_gram_reduce<U>), dim3((unsigned)red.total), dim3(256), 0, st, red.sys, red.grid,
+                       red.nsys, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_gram_res(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st) {
+  switch (dtype) {
+    case 0: return b_res_go<cd, cd>(L, red, st);
+    case 1: return b_res_go<cf, cd>(L, red, st);
+    case 2: return b_res_go<double, double>(L, red, st);
+    case 3: return b_res_go<float, double>(L, red, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, int mode, hipStream_t st) {

@@ -295,6 +295,7 @@ struct BSys {
   void* At;        // column-major copy of Ab for the fused pass (ldt x n), or null
   int64_t ldt;
   int64_t cm_spw, cm_nstrips;  // strips of the pass over At
+  int64_t res_spw, res_nstrips;  // strips of the FP64 residual pass over A
   int adj_slabs;
   int64_t adj_rps;
   int fwd_chunks;
@@ -333,6 +334,11 @@ hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int k, hipStream_t s
 // mode 0: row-major pass over Ab; 1: the same, also writing each system's
 // column-major copy At (never skipped); 2: the pass over At
 hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, int mode, hipStream_t st);
+// the refinement's FP64 residual product q = A (A* y_outer) as one fused pass
+// over each system's problem data A (dtype = the problem dtype); same grids
+// as launch_b_gram, strips from b_plan_gram_res (after b_plan_gram)
+hipError_t launch_b_gram_res(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st);
+void b_plan_gram_res(int dtype, BSys& s);
 // FP64 passes on the problem data: w64 (or x) = A* u, u = y_outer (outer) or y;
 // fpart = A w64 in column chunks
 hipError_t launch_b_adj_wide(int dtype, bool aligned, const BLaunch& L, const BLaunch& sum, int use_y, int to_x,

@@ -380,31 +380,37 @@ def test_batched_fused_plain_c128_matches_lanes():
         assert abs(ia["iters"] - ic["iters"]) <= 1
 
 
-def test_batched_fused_four_step_kept_output_classes():
+@pytest.mark.parametrize("bulk", ["f32", "f64"])
+def test_batched_fused_four_step_kept_output_classes(bulk):
     """Four-step systems in every kept-outputs-only accumulator class (l <= 512,
     <= 1024, <= 2048, up to l = 2048 at m = 512) in one fused batched call, real
-    data with an FP32 bulk: each meets eps against the oracle and takes the
-    iteration count of the same system solved alone (lanes form, whose sketch
-    is the single-system kernel), up to one."""
+    data: each meets eps against the oracle and takes about the iteration count
+    of the same system solved alone (lanes form, whose sketch is the
+    single-system kernel).  FP64 bulk (no refinement, the same passes on both
+    sides): equal up to one.  FP32 bulk with FP64 refinement: up to three, as
+    the fused form builds each FP64 residual A (A* y) in one pass and the lanes
+    in two, so the residuals (differences of nearly equal terms) round apart and
+    the inner solves they start can end an iteration or two apart."""
     import torch
     from paper_0905_4745_amd import api
     shapes = [(40, 6000), (200, 9000), (300, 20000), (512, 40000), (90, 33000)]
-    say(f"batched four-step classes {shapes}")
+    say(f"batched four-step classes {bulk} {shapes}")
     systems = synth.make_batch(shapes, seed=90, kappa=1e4)
     As = [to_dev(A) for A, _ in systems]
-    A_los = [a.to(torch.float32) for a in As]
+    A_los = [a.to(torch.float32) for a in As] if bulk == "f32" else None
     bs = [to_dev(b) for _, b in systems]
     ds, idxs, Ns = _batch_inputs(shapes, 91, False, 1e4, True)
     xf, inf_f = api.minnorm_solve_batched(As, bs, 1e-10, ds, idxs, Ns, A_los=A_los,
                                           opts=api.SolveOptions(batch_form=0))
     xl, inf_l = api.minnorm_solve_batched(As, bs, 1e-10, ds, idxs, Ns, A_los=A_los,
                                           opts=api.SolveOptions(batch_form=1))
+    tol = 3 if bulk == "f32" else 1
     for (A, b), a, c, ia, ic in zip(systems, xf, xl, inf_f, inf_l):
         p = oracle.refined_minnorm(A, b)
         say(f"  iters fused {ia['iters']} lanes {ic['iters']} err {rel(to_np(a), p):.2e}")
         assert ia["status"] == 0 and ic["status"] == 0
         assert rel(to_np(a), p) <= 1e-10 and rel(to_np(c), p) <= 1e-10
-        assert abs(ia["iters"] - ic["iters"]) <= 1
+        assert abs(ia["iters"] - ic["iters"]) <= tol
 
 
 def test_batched_fused_mixed_c128_and_fallback():
