@@ -38,8 +38,8 @@ DEFAULT_PLANS = os.path.join(ROOT, "paper_0905_4745_amd", "plans", "mi355x.json"
 # plain 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the
 # kernel source it was measured on: a changed source reports null.
 MEASURED_TRAFFIC = {
-    "k_gram_cm": {"bytes": 539.16e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-                  "sha256": "d42b88c7d79cbe44c159c63ada39c0cd5917d543d3af1df93e5b371ffb981bb2",
+    "k_gram_cm": {"bytes": 539.14e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
+                  "sha256": "0bf18377596683779af3c037152aa7128c3d7551ba1eef62cc2fe73e6ee972c3",
                   "plan_key": "gram/0/512/65536/0", "plan": 655616},
 }
 
