@@ -39,7 +39,7 @@ DEFAULT_PLANS = os.path.join(ROOT, "paper_0905_4745_amd", "plans", "mi355x.json"
 # kernel source it was measured on: a changed source reports null.
 MEASURED_TRAFFIC = {
     "k_gram_cm": {"bytes": 539.14e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-                  "sha256": "0bf18377596683779af3c037152aa7128c3d7551ba1eef62cc2fe73e6ee972c3",
+                  "sha256": "f81eccb1c146f39bbf7a8fa9f1f4c1e801624a1ed0217f0e1a7ec697096df590",
                   "plan_key": "gram/0/512/65536/0", "plan": 655616},
 }
 
