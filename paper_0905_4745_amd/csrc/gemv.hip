@@ -30,6 +30,27 @@ template <typename V, int K>
 __device__ inline Pack<V, K> loadk(const V* p) {
   return *reinterpret_cast<const Pack<V, K>*>(p);
 }
+// the same, non-temporal (an operand streamed once per pass)
+template <typename V, int K>
+__device__ inline Pack<V, K> loadk_once(const V* p) {
+  constexpr int B = (int)sizeof(Pack<V, K>);
+  Pack<V, K> out;
+  if constexpr (B == 16) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const u4 raw = __builtin_nontemporal_load(reinterpret_cast<const u4*>(p));
+    __builtin_memcpy(&out, &raw, 16);
+  } else if constexpr (B == 8) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 raw = __builtin_nontemporal_load(reinterpret_cast<const u2*>(p));
+    __builtin_memcpy(&out, &raw, 8);
+  } else if constexpr (B == 4) {
+    const unsigned int raw = __builtin_nontemporal_load(reinterpret_cast<const unsigned int*>(p));
+    __builtin_memcpy(&out, &raw, 4);
+  } else {
+    out = *reinterpret_cast<const Pack<V, K>*>(p);
+  }
+  return out;
+}
 
 __device__ inline bool stopped(const int32_t* flag) { return flag != nullptr && *(volatile const int32_t*)flag != 0; }
 
@@ -74,7 +95,7 @@ __device__ __forceinline__ void k_gemv_adj_body(const Bk bk, const V* __restrict
         for (; i + 8 <= rn; i += 8) {
           Pack<V, VEC> x[8];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) x[k] = loadk<V, VEC>(a + (i + k) * lda);
+          for (int k = 0; k < 8; ++k) x[k] = loadk_once<V, VEC>(a + (i + k) * lda);
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             const C ui = su[i + k];
@@ -83,7 +104,7 @@ __device__ __forceinline__ void k_gemv_adj_body(const Bk bk, const V* __restrict
           }
         }
         for (; i < rn; ++i) {
-          Pack<V, VEC> x = loadk<V, VEC>(a + i * lda);
+          Pack<V, VEC> x = loadk_once<V, VEC>(a + i * lda);
           const C ui = su[i];
 #pragma unroll
           for (int v = 0; v < VEC; ++v) acc[v] = vcfma(vconv<C>(x.v[v]), ui, acc[v]);
@@ -158,7 +179,7 @@ __device__ __forceinline__ void k_gemv_fwd_body(const Bk bk, const V* __restrict
       Pack<V, VEC> x[RB];
 #pragma unroll
       for (int r = 0; r < RB; ++r)
-        if (r < rows) x[r] = loadk<V, VEC>(A + (i0 + r) * lda + j);
+        if (r < rows) x[r] = loadk_once<V, VEC>(A + (i0 + r) * lda + j);
 #pragma unroll
       for (int r = 0; r < RB; ++r)
         if (r < rows)
