@@ -1095,11 +1095,11 @@ __global__ void __launch_bounds__(256) k_adj_dd(const V* __restrict__ A, int64_t
       for (; i + 4 <= rn; i += 4) {
         V x[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) x[k] = a[(i + k) * lda];
+        for (int k = 0; k < 4; ++k) x[k] = ld_once(a + (i + k) * lda);
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc_mac<true>(acc, x[k], su[i + k]);
       }
-      for (; i < rn; ++i) acc_mac<true>(acc, a[i * lda], su[i]);
+      for (; i < rn; ++i) acc_mac<true>(acc, ld_once(a + i * lda), su[i]);
     }
   }
   if (j >= n) return;
@@ -1148,7 +1148,7 @@ __global__ void __launch_bounds__(256) k_fwd_dd(const V* __restrict__ A, int64_t
     const W wj = w[j];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
-      if (r < rows) acc_mac<false>(acc[r], A[(i0 + r) * lda + j], wj);
+      if (r < rows) acc_mac<false>(acc[r], ld_once(A + (i0 + r) * lda + j), wj);
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
