@@ -39,7 +39,7 @@ DEFAULT_PLANS = os.path.join(ROOT, "paper_0905_4745_amd", "plans", "mi355x.json"
 # kernel source it was measured on: a changed source reports null.
 MEASURED_TRAFFIC = {
     "k_gram_cm": {"bytes": 539.14e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-                  "sha256": "333586c5a7dc18db190635e36ef2a87b7c107b229d783c4cd63a1b78c7e49fee",
+                  "sha256": "6aec2ea2bd8e3631a42988db9dc8f50d8bfe0db068036f981d8e53fb59ed64fa",
                   "plan_key": "gram/0/512/65536/0", "plan": 655616},
 }
 
