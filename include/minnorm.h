@@ -177,10 +177,11 @@ int mn_profile_read(mn_handle h, const char* kernel, int64_t* count, double* tot
  *                            else 4096), split (bits 17-18: N2 halved 0 .. 2
  *                            times), kept-outputs-only form (bits 19-20: 0
  *                            off, 1 / 2 / 3 for B = 16 / 8 / 4 columns per
- *                            block; applies for l <= 2048, else the full
- *                            four-step runs) with 2^(bits 21-24) column
- *                            groups per row.  Default: that form with B = 16
- *                            and groups enough for 512 workgroups;
+ *                            block; applies for l <= 2048, or l <= 8192 for
+ *                            single-precision data, else the full four-step
+ *                            runs) with 2^(bits 21-24) column groups per row.
+ *                            Default: that form with B = 16 and groups enough
+ *                            for 512 workgroups where l <= 2048;
  * "gram_s/<dtype>/<m>/<l>/0"  Step 2's Gram matrix S* S: 0 on the FP64
  *                            matrix cores, 1 register-tiled on the vector
  *                            units (default 1 for m > 1024);

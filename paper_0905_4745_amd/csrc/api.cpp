@@ -287,10 +287,12 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
     a.order = a.pruned_b ? (int32_t*)ws(h, "sk_order", (size_t)l * 4) : nullptr;
     ck(launch_sketch(dtype, a, h->stream));
   };
-  // default: the pruned form with B = 16 where it applies, with enough
-  // column groups per row for 512 workgroups (two per CU)
+  // default: the pruned form with B = 16 for l <= 2048, with enough column
+  // groups per row for 512 workgroups (two per CU).  For single-precision
+  // sketches with 2048 < l <= 8192 it is a tuning candidate only: at
+  // 2048 x 262144 (l = 8192) it measured no faster than the full four-step.
   int mb = 64;
-  if (sketch_pruned_groups(dtype, N, l, 16, 1) > 0) {
+  if (l <= 2048 && sketch_pruned_groups(dtype, N, l, 16, 1) > 0) {
     int lg = 0;
     while ((m << lg) < 512 && lg < 10) ++lg;
     mb = 64 | (1 << 19) | (lg << 21);

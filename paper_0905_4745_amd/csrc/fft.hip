@@ -724,10 +724,12 @@ template <typename C> static int fft_batch(int L, int elems = 4096) {
 
 // Column groups per row of the pruned four-step for B columns per block and
 // ng groups asked for (clamped to 1 .. N1 / B), or 0 where it does not apply:
-// l above 2048 kept outputs (eight accumulators per thread), N not a multiple
-// of N2 = 4096 / B, or a block larger than the LDS limit.
+// more kept outputs than accumulators fit (eight per thread in FP64, l <=
+// 2048; thirty-two in FP32, l <= 8192), N not a multiple of N2 = 4096 / B, or
+// a block larger than the LDS limit.
 template <typename C> static int pruned_groups(int64_t N, int64_t l, int B, int ng) {
-  if (!(B == 16 || B == 8 || B == 4) || l < 1 || l > 2048) return 0;
+  const int64_t lmax = std::is_same<C, cf>::value ? 8192 : 2048;
+  if (!(B == 16 || B == 8 || B == 4) || l < 1 || l > lmax) return 0;
   const int64_t N2 = 4096 / B;
   if (N <= N2 || N % N2) return 0;
   if (((int64_t)B * lds_stride((int)N2) + (B >= 8 ? N2 : 0)) * (int64_t)sizeof(C) > lds_limit()) return 0;
@@ -751,10 +753,21 @@ static void pruned_launch(int kpt, dim3 grid, size_t smb, hipStream_t st, const 
     allow_lds(k_sketch_pruned<V, C, B, 4>, smb);
     hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 4>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2, d,
                        idx, order, l, tw, S, lds, P, scale);
-  } else {
+  } else if (kpt == 8) {
     allow_lds(k_sketch_pruned<V, C, B, 8>, smb);
     hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 8>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2, d,
                        idx, order, l, tw, S, lds, P, scale);
+  } else if constexpr (std::is_same<C, cf>::value) {
+    // FP32 accumulators: up to 32 kept outputs per thread
+    if (kpt == 16) {
+      allow_lds(k_sketch_pruned<V, C, B, 16>, smb);
+      hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 16>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2,
+                         d, idx, order, l, tw, S, lds, P, scale);
+    } else {
+      allow_lds(k_sketch_pruned<V, C, B, 32>, smb);
+      hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 32>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2,
+                         d, idx, order, l, tw, S, lds, P, scale);
+    }
   }
 }
 
@@ -766,7 +779,7 @@ static hipError_t sketch_pruned_impl(const SketchArgs& a, hipStream_t st) {
   if (ng < 1) return hipErrorInvalidValue;
   const int N2 = 4096 / B, N1 = N / N2;
   const int G = N1 / (B * ng);
-  const int kpt = a.l <= 512 ? 2 : (a.l <= 1024 ? 4 : 8);
+  const int kpt = a.l <= 512 ? 2 : (a.l <= 1024 ? 4 : (a.l <= 2048 ? 8 : (a.l <= 4096 ? 16 : 32)));
   const FftPlan pl2 = make_plan(N2);
   using R = typename VT<C>::real;
   const R scale = (R)(1.0 / sqrt((double)N));
@@ -972,7 +985,7 @@ template <typename C> void plan_sketch_t(BSys& s, BGrid& small, BGrid& cols, BGr
     ls = (size_t)s.fft_ba * lds_stride(N) * sizeof(C);
     return;
   }
-  if (pruned_groups<C>(N, s.l, 16, 1) > 0) {
+  if (s.l <= 2048 && pruned_groups<C>(N, s.l, 16, 1) > 0) {
     // kept outputs only: N2 = 256, one workgroup per row
     s.N2 = 256;
     s.N1 = N / 256;
@@ -1045,7 +1058,7 @@ void b_plan_sketch(int dtype, BSys& s, BGrid& small, BGrid& cols, BGrid& rows, B
 
 int64_t b_sketch_work_elems(int dtype, int64_t m, int64_t N, int64_t l) {
   const int L = (dtype == 1 || dtype == 3) ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>();
-  if (N <= L || sketch_pruned_groups(dtype, N, l, 16, 1) > 0) return 0;
+  if (N <= L || (l <= 2048 && sketch_pruned_groups(dtype, N, l, 16, 1) > 0)) return 0;
   return m * N;
 }
 

@@ -116,14 +116,16 @@ def test_sketch_four_step_splits(m, n, N, l, kind, split, tmp_path):
 
 
 @pytest.mark.parametrize("m,n,N,l", [(17, 65536, 65536, 68), (5, 8192, 8192, 2048), (3, 100000, 131072, 700),
-                                     (9, 40000, 65536, 1100)])
+                                     (9, 40000, 65536, 1100), (3, 50000, 65536, 3000), (2, 100000, 131072, 8192)])
 @pytest.mark.parametrize("kind", ["c128", "c64", "f64", "f32"])
 @pytest.mark.parametrize("bcode,lgng", [(1, 0), (1, 2), (2, 1), (3, 0), (3, 3)])
 def test_sketch_pruned_variants(m, n, N, l, kind, bcode, lgng, tmp_path):
     """The kept-outputs-only four-step (B = 16, 8, 4 columns per block; 1 to
     8 column groups per row, partial sums folded) forced through a loaded
-    plan gives the oracle's sketch to the same bar, including ragged n and
-    l = 2048 (eight kept outputs per thread)."""
+    plan gives the oracle's sketch to the same bar, including ragged n,
+    l = 2048 (eight kept outputs per thread) and, in single precision,
+    l = 3000 and 8192 (16 and 32 per thread; FP64 takes the full four-step
+    there)."""
     import json
     import torch
     from paper_0905_4745_amd import api
