@@ -445,7 +445,9 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, in
 // equal k mod N2 (k_sketch_order), so the lanes of a wave read a few LDS
 // addresses (broadcast) rather than 64 scattered ones.  With one column
 // group per row (grid.x = 1) the workgroup writes S; otherwise the group's
-// sums go to P[g][row][s] and k_sketch_fold adds them.
+// sums go to P[g][row][s] and k_sketch_fold adds them.  KPT = kept outputs
+// per thread (2, 4, 8; with FP32 accumulators also 16 and 32).
+
 // one-touch load of a streamed operand
 template <typename V> __device__ __forceinline__ V ld_stream(const V* p) {
   if constexpr (VT<V>::cplx) {
