@@ -254,7 +254,10 @@ int minnorm_solve(mn_handle h, int dtype, int64_t m, int64_t n,
 /* Many independent systems of uneven sizes in one call.  Every array argument
  * below is a HOST array of `batch` entries; the pointers inside are device
  * pointers with the meaning of minnorm_solve (A_lo may be NULL, or hold NULL
- * entries).  b_i has m[i] entries, x_i has n[i] entries; lda[i] >= n[i].
+ * entries: those systems then run in plain FP64).  A_lo[i] is read with
+ * lda[i] as its leading dimension, the same as A[i].  b_i has m[i] entries,
+ * x_i has n[i] entries; lda[i] >= n[i].  When some but not all A_lo entries
+ * are NULL, every system runs on the concurrent lanes.
  * info, if not NULL, is a host array of `batch` reports.  Returns the largest
  * status over the systems (each system's own status is in info[i].status).
  * Errors: -3 batch < 1; -4..-16 the matching array is NULL or an entry of it

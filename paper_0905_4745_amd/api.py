@@ -186,11 +186,29 @@ def minnorm_solve_batched(As, bs, eps, ds, idxs, Ns, A_los=None, opts: SolveOpti
     code = _check_matrix(As[0])
     wide = _WIDE[code]
     dev = As[0].device
+    if len(bs) != batch or len(ds) != batch or len(idxs) != batch or len(Ns) != batch:
+        raise ValueError("As, bs, ds, idxs and Ns must have one entry per system")
+    if A_los is not None and len(A_los) != batch:
+        raise ValueError("A_los must have one entry per system (or be None)")
     xs, dts, its = [], [], []
-    for A in As:
+    for i, A in enumerate(As):
         if _check_matrix(A) != code:
             raise ValueError("all systems must share one dtype")
-        xs.append(torch.empty(A.shape[1], dtype=wide, device=dev))
+        if A.device != dev:
+            raise ValueError("all systems must live on one device")
+        m_i, n_i = A.shape
+        b = bs[i]
+        if (b.dtype != wide or not b.is_cuda or b.device != dev or b.dim() != 1 or b.numel() != m_i
+                or (b.stride(0) != 1 and m_i > 1)):
+            raise ValueError(f"b[{i}] must be a contiguous device {wide} vector of {m_i} entries")
+        if A_los is not None:
+            lo = A_los[i]
+            # the library reads A_lo[i] with A[i]'s leading dimension
+            if (lo.dtype != _SINGLE_OF.get(code) or lo.shape != A.shape or lo.device != dev
+                    or (lo.stride(1) != 1 and n_i > 1) or _ld(lo, 0, n_i) != _ld(A, 0, n_i)):
+                raise ValueError(f"A_los[{i}] must be the single-precision copy of As[{i}] "
+                                 "with the same leading dimension")
+        xs.append(torch.empty(n_i, dtype=wide, device=dev))
     for d, idx in zip(ds, idxs):
         dts.append(_d_tensor(d, code, dev))
         its.append(_idx_tensor(idx, dev))

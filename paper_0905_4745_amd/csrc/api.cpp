@@ -1193,10 +1193,15 @@ struct GridTable {
 
 int64_t a256(int64_t v) { return (v + 255) / 256 * 256; }
 
-bool fused_batch_ok(int batch, const int64_t* m, const mn_opts& o) {
+// The fused form takes one bulk type for all systems: either no system has a
+// single-precision copy or every system has one (a mix goes to the lanes).
+bool fused_batch_ok(int batch, const int64_t* m, const void* const* A_lo, const mn_opts& o) {
   if (o.precond != 0 || o.batch_form == 1 || batch < 2) return false;
   for (int i = 0; i < batch; ++i)
     if (m[i] > kGramMaxRows) return false;
+  if (A_lo)
+    for (int i = 0; i < batch; ++i)
+      if (!A_lo[i]) return false;
   return true;
 }
 
@@ -1873,7 +1878,7 @@ int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* 
                                    l[i], d[i], idx[i], o, x[i], n[i]);
     if (e) return remap[-e];
   }
-  if (fused_batch_ok(batch, m, o)) {
+  if (fused_batch_ok(batch, m, A_lo, o)) {
     std::vector<int> stv, redo;
     try {
       solve_batched_fused(h, dtype, batch, m, n, A, lda, A_lo, b, eps, N, l, d, idx, o, x, info, stv, redo);
