@@ -503,22 +503,28 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
   int64_t rec_base[8];
   std::copy(h->prof_seen, h->prof_seen + 8, rec_base);
   const int32_t* flag = &v.st->done;
-  const bool fused = gram_supported(c.bulk, c.m, c.Ab, c.ldab);
-  int gram_plan = 512;
   // One fused pass q = A (A* p).  plan: workgroup count (low 16 bits), bit 16
   // narrow strips, bit 17 interleaved strips, bit 18 1024 threads, bit 19:
   // read a column-major copy of A (the solve's first fused pass writes it,
   // with the row-major kernel and the other bits; it is never skipped by the
-  // stop flag, so the copy is whole before any pass reads it)
-  const int64_t ldt = rup(c.m, 64);
+  // stop flag, so the copy is whole before any pass reads it).  For m above
+  // kGramMaxRows (up to kGramTallMaxRows) only the pass over the copy exists
+  // (bits 20-21: its shape code); the first pass of a solve then writes the
+  // copy with a tiled transpose before reading it.
+  const bool fused_rm = gram_supported(c.bulk, c.m, c.Ab, c.ldab);
+  const bool tall = !fused_rm && c.m <= kGramTallMaxRows;
+  int gram_plan = 512;
+  const int64_t ldt = tall ? rup(c.m, gram_tall_ld_multiple()) : rup(c.m, 64);
   // the copy is taken only where it fits in half of the free device memory
   bool cm_ok = v.at != nullptr;
-  if (fused && !cm_ok) {
+  if ((fused_rm || tall) && !cm_ok) {
     size_t fr = 0, tot = 0;
     cm_ok = hipMemGetInfo(&fr, &tot) == hipSuccess && (double)(ldt * c.n * dtype_size(c.bulk)) <= 0.5 * (double)fr;
   }
+  const bool fused = fused_rm || (tall && cm_ok);
   auto gram = [&](int pl, const int32_t* flg, bool sampled) {
     if (!cm_ok) pl &= ~0x80000;
+    if (tall) pl |= 0x80000;
     GramArgs ga{};
     ga.A = c.Ab;
     ga.lda = c.ldab;
@@ -533,6 +539,7 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
     ga.interleave = (pl >> 17) & 1;
     ga.wide_wg = (pl >> 18) & 1;
     ga.wide_acc = c.wide_acc;
+    ga.tall = (pl >> 20) & 3;
     if ((pl >> 19) & 1) {
       if (!v.at) v.at = ws(h, "gram_at", (size_t)(ldt * c.n * dtype_size(c.bulk)));
       ga.At = v.at;
@@ -557,13 +564,19 @@ void cg_loop(const SolveCtx& c, CgBufs& v, const void* b, int max_iter) {
     // default (first candidate): the column-major pass, 256 interleaved
     // workgroups, where the copy fits; else the row-major pass, 512
     std::vector<int> cands;
-    if (cm_ok)
-      for (int il : {0x20000, 0})
-        for (int wg : {256, 512, 1024}) cands.push_back(wg | il | 0x80000);
-    for (int ww : {0, 0x40000})
-      for (int il : {0, 0x20000})
-        for (int nw : {0, 0x10000})
-          for (int wg : {512, 256, 1024}) cands.push_back(wg | nw | il | ww);
+    if (tall) {
+      // the pass over the copy: shape codes 0..3, 256 .. 1024 workgroups
+      for (int code : {0, 1, 2, 3})
+        for (int wg : {512, 256, 1024}) cands.push_back(wg | 0x80000 | (code << 20));
+    } else {
+      if (cm_ok)
+        for (int il : {0x20000, 0})
+          for (int wg : {256, 512, 1024}) cands.push_back(wg | il | 0x80000);
+      for (int ww : {0, 0x40000})
+        for (int il : {0, 0x20000})
+          for (int nw : {0, 0x10000})
+            for (int wg : {512, 256, 1024}) cands.push_back(wg | nw | il | ww);
+    }
     gram_plan = plan_get(h, c.o, plan_key("gram", c.bulk, c.m, c.n, c.wide_acc ? 1 : 0), cands, run);
   }
   // the state is read one batch late (below), so short batches cost no idle

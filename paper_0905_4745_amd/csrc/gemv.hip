@@ -474,6 +474,159 @@ __global__ void __launch_bounds__(512) k_gram_cm(const V* __restrict__ At, int64
   k_gram_cm_body<V, C, U, CPT, RPT>(bk_hw(), At, ldt, m, n, p, strips_per_wg, nstrips, qpart, flag, interleave);
 }
 
+// ---------------------------------------------------------------------------
+// The fused pass q = A (A* p) from the column-major copy for tall A (m up to
+// WPC * 64 * RPT, beyond the 512 rows one wave holds in k_gram_cm).  A column
+// group of WPC waves streams CPT whole columns per step: wave w of the group
+// holds rows w 64 RPT .. (w + 1) 64 RPT - 1 of them, VPL consecutive rows per
+// 16-byte load (lane l, load k: rows w 64 RPT + (64 k + l) VPL + v), so each
+// load instruction of a wave reads 1 KB of one column.  The column sums
+// t_c = sum_r conj(A_rc) p_r are a wave reduction per wave and, for WPC > 1,
+// a sum of the WPC wave results through LDS in wave order (one barrier per
+// step, two LDS slots so the next step's writes never meet this step's
+// reads); then q_r += A_rc t_c in registers.  The next step's columns load
+// into a second register set while the current one is reduced.  Column
+// group gc of workgroup g takes columns (s (G NG) + g NG + gc) CPT + u at
+// step s, so the grid's groups read neighbouring columns.  Rows m .. ldt - 1
+// of the copy are zero, and every group runs the same number of steps (a
+// column past n loads as zero), so the barriers are uniform.  At the end the
+// NG groups' q are added in group order through LDS and each workgroup
+// writes its partial as k_gram does.
+template <typename V, typename C, typename U, int RPT, int CPT, int WPC, int TPB>
+__device__ __forceinline__ void k_gram_tall_body(const Bk bk, const V* __restrict__ At, int64_t ldt, int64_t m,
+                                                   int64_t n, const U* __restrict__ p, U* __restrict__ qpart,
+                                                   const int32_t* __restrict__ flag) {
+  if (stopped(flag)) return;
+  constexpr int VPL = Vec16<V>::n;      // rows per 16-byte load
+  constexpr int KL = RPT / VPL;         // loads per column and lane
+  constexpr int NW = TPB / 64;          // waves
+  constexpr int NG = NW / WPC;          // column groups
+  constexpr int SLAB = 64 * RPT;        // rows per wave
+  static_assert(RPT % VPL == 0 && NW % WPC == 0, "tall pass shape");
+  __shared__ C red[2][NG][WPC][CPT];
+  __shared__ U qs[WPC * SLAB];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int gc = wv / WPC, w = wv % WPC;
+  const int64_t r0 = (int64_t)w * SLAB;
+  // loads of this wave that fall inside the copy's ldt rows (uniform)
+  int64_t kl = (ldt - r0) / (64 * VPL);
+  const int kmax = kl < 0 ? 0 : (kl > KL ? KL : (int)kl);
+  C pr[KL][VPL], qacc[KL][VPL];
+#pragma unroll
+  for (int k = 0; k < KL; ++k)
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+      const int64_t r = r0 + (64 * k + lane) * VPL + v;
+      pr[k][v] = r < m ? vconv<C>(p[r]) : vzero<C>();
+      qacc[k][v] = vzero<C>();
+    }
+  const int64_t groups = (int64_t)bk.gx * NG;
+  const int64_t gid = (int64_t)bk.x * NG + gc;
+  const int64_t steps = ceil_div(n, groups * CPT);
+  auto load = [&](Pack<V, VPL> (&x)[KL][CPT], int64_t s) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int64_t c = (s * groups + gid) * CPT + u;
+      const V* col = At + c * ldt + r0 + (int64_t)lane * VPL;
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        if (c < n && k < kmax) x[k][u] = loadk_once<V, VPL>(col + 64 * VPL * k);
+        else
+#pragma unroll
+          for (int v = 0; v < VPL; ++v) x[k][u].v[v] = vzero<V>();
+      }
+    }
+  };
+  int slot = 0;
+  auto process = [&](const Pack<V, VPL> (&x)[KL][CPT]) {
+    C tc[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      C a = vzero<C>();
+#pragma unroll
+      for (int k = 0; k < KL; ++k)
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) a = vcfma(vconv<C>(x[k][u].v[v]), pr[k][v], a);
+      tc[u] = wave_sum(a);
+    }
+    if constexpr (WPC > 1) {
+      if (lane == 0)
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) red[slot][gc][w][u] = tc[u];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        C s = red[slot][gc][0][u];
+#pragma unroll
+        for (int ww = 1; ww < WPC; ++ww) s = vadd(s, red[slot][gc][ww][u]);
+        tc[u] = s;
+      }
+      slot ^= 1;
+    }
+#pragma unroll
+    for (int k = 0; k < KL; ++k)
+#pragma unroll
+      for (int v = 0; v < VPL; ++v)
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) qacc[k][v] = vfma(vconv<C>(x[k][u].v[v]), tc[u], qacc[k][v]);
+  };
+  Pack<V, VPL> xa[KL][CPT], xb[KL][CPT];
+  if (steps > 0) load(xa, 0);
+  for (int64_t s = 0; s < steps; s += 2) {
+    if (s + 1 < steps) load(xb, s + 1);
+    process(xa);
+    if (s + 1 < steps) {
+      if (s + 2 < steps) load(xa, s + 2);
+      process(xb);
+    }
+  }
+  // the NG groups' q, added in group order, then this workgroup's partial
+  for (int g2 = 0; g2 < NG; ++g2) {
+    __syncthreads();
+    if (gc == g2)
+#pragma unroll
+      for (int k = 0; k < KL; ++k)
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+          const int i = w * SLAB + (64 * k + lane) * VPL + v;
+          const U val = vconv<U>(qacc[k][v]);
+          qs[i] = g2 == 0 ? val : vadd(qs[i], val);
+        }
+  }
+  __syncthreads();
+  for (int64_t r = t; r < m; r += TPB) qpart[(int64_t)bk.x * m + r] = qs[r];
+}
+template <typename V, typename C, typename U, int RPT, int CPT, int WPC, int TPB>
+__global__ void __launch_bounds__(TPB) k_gram_tall(const V* __restrict__ At, int64_t ldt, int64_t m, int64_t n,
+                                                   const U* __restrict__ p, U* __restrict__ qpart,
+                                                   const int32_t* __restrict__ flag) {
+  k_gram_tall_body<V, C, U, RPT, CPT, WPC, TPB>(bk_hw(), At, ldt, m, n, p, qpart, flag);
+}
+
+// Column-major copy of a row-major m x n matrix: At[c ldt + r] = A[r lda + c]
+// for r < m, zero for m <= r < ldt.  64 x 64 tiles through LDS (one padding
+// column against bank conflicts); rows are read and columns written as
+// contiguous runs by consecutive threads.  grid (ceil(n / 64), ldt / 64),
+// 256 threads.
+template <typename V>
+__global__ void __launch_bounds__(256) k_colmajor(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                  V* __restrict__ At, int64_t ldt) {
+  __shared__ V tile[64][65];
+  const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t r = r0 + rr, c = c0 + tx;
+    tile[rr][tx] = (r < m && c < n) ? ld_once(A + r * lda + c) : vzero<V>();
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int cc = ty; cc < 64; cc += 4) {
+    const int64_t c = c0 + cc, r = r0 + tx;
+    if (c < n) At[c * ldt + r] = tile[tx][cc];
+  }
+}
+
 // First level of the sum over workgroup partials: q8[gr * m + i] = sum of
 // qpart[g * m + i] over the gr-th eighth of g, in a fixed order.
 // grid = (ceil(m/64), 8), 256 threads (64 rows x 4 interleaved quarters).
@@ -660,9 +813,48 @@ static hipError_t gram_cm_go(const GramArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The tall pass (m > kGramMaxRows): shape code a.tall (RPT, CPT, WPC, TPB
+// below) for the row class m <= 1024 or m <= 2048; at_mode 1 first writes the
+// column-major copy (k_colmajor), then runs the pass over it.
+template <typename V, typename C, typename U, int RPT, int CPT, int WPC, int TPB>
+static void tall_launch(const GramArgs& a, int64_t G, hipStream_t st) {
+  hipExtLaunchKernelGGL((k_gram_tall<V, C, U, RPT, CPT, WPC, TPB>), dim3((unsigned)G), dim3(TPB), 0, st, a.ev_begin,
+                        a.ev_end, 0, reinterpret_cast<const V*>(a.At), a.ldt, a.m, a.n,
+                        reinterpret_cast<const U*>(a.p), reinterpret_cast<U*>(a.qpart), a.flag);
+}
+template <typename V, typename C, typename U>
+static hipError_t gram_tall_go(const GramArgs& a, hipStream_t st) {
+  if (a.m > kGramTallMaxRows || a.ldt < a.m || a.ldt % gram_tall_ld_multiple() != 0) return hipErrorInvalidValue;
+  if (a.at_mode == 1) {
+    hipLaunchKernelGGL((k_colmajor<V>), dim3((unsigned)ceil_div(a.n, 64), (unsigned)(a.ldt / 64)), dim3(256), 0, st,
+                       reinterpret_cast<const V*>(a.A), a.lda, a.m, a.n, reinterpret_cast<V*>(a.At), a.ldt);
+  }
+  const int64_t G = a.max_wg > 0 && a.max_wg <= kGramMaxWg ? a.max_wg : 512;
+  const int code = a.tall & 3;
+  if (a.m <= 1024) {
+    switch (code) {
+      case 0: tall_launch<V, C, U, 8, 2, 2, 256>(a, G, st); break;
+      case 1: tall_launch<V, C, U, 4, 4, 4, 256>(a, G, st); break;
+      case 2: tall_launch<V, C, U, 8, 1, 2, 256>(a, G, st); break;
+      default: tall_launch<V, C, U, 16, 1, 1, 256>(a, G, st); break;
+    }
+  } else {
+    switch (code) {
+      case 0: tall_launch<V, C, U, 8, 2, 4, 256>(a, G, st); break;
+      case 1: tall_launch<V, C, U, 4, 4, 8, 512>(a, G, st); break;
+      case 2: tall_launch<V, C, U, 8, 1, 4, 256>(a, G, st); break;
+      default: tall_launch<V, C, U, 16, 1, 2, 256>(a, G, st); break;
+    }
+  }
+  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64), 8), dim3(256), 0, st,
+                     reinterpret_cast<const U*>(a.qpart), (int)G, a.m, reinterpret_cast<U*>(a.q), a.flag);
+  return hipGetLastError();
+}
+
 // Strip width: 32 bytes of a row per thread (CPT0), or half of that.
 template <typename V, typename C, typename U>
 static hipError_t gram_impl(const GramArgs& a, hipStream_t st) {
+  if (a.m > kGramMaxRows) return gram_tall_go<V, C, U>(a, st);
   if (a.at_mode == 2) return gram_cm_go<V, C, U>(a, st);
   constexpr int CPT0 = 32 / (int)sizeof(V) > 0 ? 32 / (int)sizeof(V) : 1;
   constexpr int CPT1 = CPT0 / 2 > 0 ? CPT0 / 2 : 1;
@@ -678,6 +870,8 @@ bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda) {
   (void)lda;
   return m <= kGramMaxRows;
 }
+
+int64_t gram_tall_ld_multiple() { return 256; }
 
 hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st) {
   switch (dtype) {

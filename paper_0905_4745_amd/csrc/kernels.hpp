@@ -98,8 +98,10 @@ int64_t adj_dd_part_elems(int64_t m, int64_t n);
 hipError_t launch_gemv_adj_dd(int dtype, const AdjArgs& a, hipStream_t st);
 hipError_t launch_gemv_fwd_dd(int dtype, const FwdArgs& a, void* q, hipStream_t st);
 
-// Fused q = A (A* p) in one read of A (m <= kGramMaxRows, 16-byte aligned rows).
+// Fused q = A (A* p) in one read of A (m <= kGramMaxRows, 16-byte aligned rows;
+// up to kGramTallMaxRows from a column-major copy of A).
 constexpr int kGramMaxRows = 512;
+constexpr int kGramTallMaxRows = 2048;
 constexpr int kGramMaxWg = 1024;  // partial sums per row (largest workgroup count)
 constexpr int kGramParts = 8;    // slices of q left for the CG kernel to add
 struct GramArgs {
@@ -121,8 +123,14 @@ struct GramArgs {
   void* At = nullptr;
   int64_t ldt = 0;
   int at_mode = 0;
+  // m > kGramMaxRows: the pass over the column-major copy only (at_mode 1
+  // writes the copy first, from A); shape code 0..3 (plan bits 20-21)
+  int tall = 0;
 };
 bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda);
+// leading dimension of the column-major copy for m > kGramMaxRows: a
+// multiple of this (rows m .. ldt - 1 of the copy are zero)
+int64_t gram_tall_ld_multiple();
 hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st);
 
 // CG state in device memory, written by workgroup 0 of the CG kernels.
