@@ -1,16 +1,25 @@
 #!/usr/bin/env python3
 """Throughput of the randomized minimal-norm solver on one MI355X.
 
-One step = one whole solve on device-resident inputs: SRFT sketch of A's rows,
-Householder QR of the sketch, preconditioned CG on A A* y = b to the paper's
-Step-4 precision, x = A* y.  Workload: A = U diag(sigma) V* with Haar U, V,
-sigma log-spaced 1 -> 1e-3 (cond 1e3), m = 512, n = 65536, complex128,
-eps = 1e-10, l = 4m = 2048, N = n; a fresh (d, idx) draw per step.
+One step = one whole solve on device-resident inputs: the library's draw of
+the SRFT (Philox counters, a fresh seed per step), the sketch of A's rows,
+Step 2's triangular factor, preconditioned CG on A A* y = b to the paper's
+Step-4 precision, x = A* y -- every row of the hot path.
+
+Default workload (`--workload mixed`): complex128 A = U diag(sigma) V*, Haar
+U and V, sigma log-spaced 1 -> 1e-6 (cond 1e6), m = 2048, n = 262144, with its
+complex64 copy as the bulk (sketch, factor and inner CG in single precision)
+and FP64 refinement (compensated residuals) to eps = 1e-10; l = 4m = 8192,
+N = n.  Beside it, the plain FP64 GPU path on the same A at the same eps
+(`fp64_value`: FP64 bulk, FP64 refinement with the same compensated
+residuals), and the classical FP64 oracle timed on the host's cores on a row
+sample.  `--workload plain` is the 512 x 65536 complex128 cond-1e3 FP64
+method; `multirhs` and `batched` the several-right-hand-side and uneven
+batch workloads.
 
 Prints one JSON line: solves/s, the average duration and achieved HBM rate of
 the dominant pass over A (HIP events on the library's stream, timed region),
-the error of the last solve against the CPU oracle, and the CPU oracle's own
-throughput on a one-solve sample of the same workload.
+the accuracy reached, and the CPU oracle's throughput.
 """
 
 from __future__ import annotations
@@ -66,15 +75,18 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle accuracy check")
-    ap.add_argument("--m", type=int, default=512)
-    ap.add_argument("--n", type=int, default=65536)
-    ap.add_argument("--kappa", type=float, default=1e3)
+    ap.add_argument("--m", type=int, default=None, help="rows (default: the workload's)")
+    ap.add_argument("--n", type=int, default=None, help="columns (default: the workload's)")
+    ap.add_argument("--kappa", type=float, default=None, help="cond(A) (default: the workload's)")
     ap.add_argument("--eps", type=float, default=1e-10)
-    ap.add_argument("--workload", choices=("plain", "multirhs", "batched", "mixed"), default="plain",
-                    help="plain: one complex128 RHS (default); multirhs: complex64 rows scaled by "
-                         "10^U(-2,2), 64 RHS through the block path; batched: 256 uneven real "
-                         "systems (FP64 data + FP32 copies) in one batched call; mixed: complex128 "
-                         "2048 x 262144 at cond 1e6 with a complex64 copy (FP64 refinement)")
+    ap.add_argument("--workload", choices=("plain", "multirhs", "batched", "mixed"), default="mixed",
+                    help="mixed (default): complex128 2048 x 262144 at cond 1e6 with a complex64 copy "
+                         "(FP64 refinement), beside the FP64 GPU path; plain: 512 x 65536 complex128 "
+                         "cond 1e3, FP64 throughout; multirhs: complex64 rows scaled by 10^U(-2,2), "
+                         "64 RHS through the block path; batched: 256 uneven real systems (FP64 data + "
+                         "FP32 copies) in one batched call")
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="mixed: timed solves of the FP64 GPU path (default: steps / 2, at least 2)")
     ap.add_argument("--streams", type=int, default=8, help="batched: concurrent lanes")
     ap.add_argument("--no-tune", action="store_true", help="built-in launch plans instead of tuned ones")
     ap.add_argument("--plans-out", default=None, help="write the tuned launch plans (JSON) here")
@@ -113,7 +125,11 @@ def main():
         return main_batched(args)
     if args.workload == "mixed":
         return main_mixed(args)
+    return main_plain(args)
 
+
+def main_plain(args):
+    """complex128 A (512 x 65536, cond 1e3), FP64 throughout, one RHS."""
     import numpy as np
     import torch
 
@@ -121,11 +137,12 @@ def main():
     from paper_0905_4745_amd import api
 
     dev = torch.device("cuda:0")
-    m, n, eps = args.m, args.n, args.eps
+    m, n, eps = args.m or 512, args.n or 65536, args.eps
+    kappa = args.kappa or 1e3
     N = synth.next_pow2(n)
     l = synth.sketch_width(m, N)
-    log(f"[bench] generating A {m}x{n} complex128 cond {args.kappa:g}")
-    A, b, _ = synth.make_svd(m, n, args.kappa, seed=2)
+    log(f"[bench] generating A {m}x{n} complex128 cond {kappa:g}")
+    A, b, _ = synth.make_svd(m, n, kappa, seed=2)
     At = torch.from_numpy(A).to(dev)
     bt = torch.from_numpy(b).to(dev)
     draws = []
@@ -206,7 +223,7 @@ def main():
                 break
         c1 = time.perf_counter()
         cpu = {"value": done / (c1 - c0), "unit": "solves/s", "cores": threads, "kind": "oracle",
-               "sample": f"{done} full solves ({m}x{n} complex128, cond {args.kappa:g}, eps {eps:g}: numpy FFT "
+               "sample": f"{done} full solves ({m}x{n} complex128, cond {kappa:g}, eps {eps:g}: numpy FFT "
                          f"sketch, numpy Householder QR, scipy-triangular-solve PCG, x = A* y), fresh (d, idx) "
                          f"each, took {c1 - c0:.2f} s"}
         log(f"[bench] CPU oracle {done} solves in {c1 - c0:.2f} s on {threads} threads")
@@ -225,8 +242,8 @@ def main():
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": f"plain method, complex128, m={m}, n={n}, A = U diag(sigma) V* with Haar "
-                               f"factors, cond {args.kappa:g}, eps {eps:g}, l={l}, N={N}, one RHS",
-                   "m": m, "n": n, "l": l, "N": N, "eps": eps, "kappa": args.kappa},
+                               f"factors, cond {kappa:g}, eps {eps:g}, l={l}, N={N}, one RHS",
+                   "m": m, "n": n, "l": l, "N": N, "eps": eps, "kappa": kappa},
         "roofline": {"bound": "hbm", "kernel": kname,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, plans),
@@ -254,8 +271,8 @@ def main_multirhs(args):
     import synth
     from paper_0905_4745_amd import api
 
-    m = args.m if args.m != 512 else 4096
-    n = args.n if args.n != 65536 else 131072
+    m = args.m or 4096
+    n = args.n or 131072
     k, eps = 64, args.eps
     N = synth.next_pow2(n)
     l = synth.sketch_width(m, N)
@@ -420,16 +437,68 @@ def main_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def blas_threads():
+    from threadpoolctl import threadpool_info
+    return max([int(t.get("num_threads", 1)) for t in threadpool_info() if t.get("user_api") == "blas"] + [1])
+
+
+def cpu_baseline_classical(A_dev, b_dev, m, n):
+    """The classical FP64 oracle (Householder QR of A*, p = Q R^{-*} b) timed
+    on the host's cores on the first m' rows of the same A; its cost is
+    proportional to n m'^2, so one whole solve is estimated as (m / m')^2
+    times the sample's time.  m' = 256, or 512 when that sample is quick."""
+    import oracle
+    out = None
+    for rows in (256, 512):
+        if rows > m:
+            break
+        A_s = A_dev[:rows].cpu().numpy()
+        b_s = b_dev[:rows].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.classical_minnorm(A_s, b_s)
+        t = time.perf_counter() - t0
+        est = t * (m / rows) ** 2
+        out = {"value": 1.0 / est, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": f"classical FP64 minimal-norm solve (scipy Householder QR of A*, LAPACK) of the first "
+                         f"{rows} rows of the same {m}x{n} complex128 A took {t:.2f} s; a whole solve costs "
+                         f"(m/{rows})^2 = {(m / rows) ** 2:.0f} times that (QR flops ~ 8 n m^2): {est:.1f} s; "
+                         f"host {cpu_model()}, os.cpu_count() = {os.cpu_count()}, BLAS threads as reported"}
+        log(f"[bench] CPU oracle: {rows} rows in {t:.2f} s -> {est:.1f} s per whole solve")
+        del A_s
+        if t > 5.0:
+            break
+    return out
+
+
+# HBM bytes per live launch of the dominant pass of the mixed workload, from
+# rocprofv3 --pmc (same scaling as MEASURED_TRAFFIC); empty until measured on
+# the current source
+MEASURED_TRAFFIC_MIXED = {}
+
+
 def main_mixed(args):
-    """complex128 A (2048 x 262144, cond 1e6) with its complex64 copy as the bulk."""
+    """complex128 A (2048 x 262144, cond 1e6) with its complex64 copy as the
+    bulk, FP64 refinement; the FP64 GPU path on the same A beside it."""
+    import hashlib
+
     import torch
 
     import synth
     from paper_0905_4745_amd import api
 
-    m = args.m if args.m != 512 else 2048
-    n = args.n if args.n != 65536 else 262144
-    kappa = args.kappa if args.kappa != 1e3 else 1e6
+    m, n = args.m or 2048, args.n or 262144
+    kappa = args.kappa or 1e6
     eps = args.eps
     N = synth.next_pow2(n)
     l = synth.sketch_width(m, N)
@@ -438,36 +507,75 @@ def main_mixed(args):
     A, b = synth.make_svd_device(m, n, kappa, seed=3, device=dev)
     A_lo = A.to(torch.complex64)
     x = torch.empty(n, dtype=torch.complex128, device=dev)
-    draws = []
-    for s_ in range(args.warmup + args.steps):
-        d, idx = synth.draw_srft(N, l, seed=3000 + s_)
-        draws.append((torch.from_numpy(d).to(dev), torch.from_numpy(idx).to(dev)))
     torch.cuda.synchronize()
     if args.plans_in and not args.no_plans_in:
         log(f"[bench] launch plans from {args.plans_in}")
         api.plans_load(args.plans_in)
-    opts = api.SolveOptions(tune=0 if args.no_tune else 1)
-    log(f"[bench] warmup {args.warmup}")
-    for s_ in range(args.warmup):
-        d, idx = draws[s_]
-        _, info = api.minnorm_solve(A, b, eps, d, idx, N, A_lo=A_lo, x=x, opts=opts)
-        log(f"[bench]   info {info}")
-    torch.cuda.synchronize()
-    log(f"[bench] timed {args.steps} solves")
-    infos = []
-    t0 = time.perf_counter()
-    for s_ in range(args.steps):
-        d, idx = draws[args.warmup + s_]
-        _, info = api.minnorm_solve(A, b, eps, d, idx, N, A_lo=A_lo, x=x, opts=opts)
-        infos.append(info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # a property that holds at any size: the FP64 residual of the last x
-    res = float(torch.linalg.vector_norm(A @ x - b) / torch.linalg.vector_norm(b))
-    log(f"[bench] {args.steps / elapsed:.2f} solves/s; last info {infos[-1]}; |Ax - b|/|b| = {res:.2e}")
+    tune = 0 if args.no_tune else 1
+
+    def run(steps, warmup, seed0, fp64):
+        # one step: the library's draw (fresh seed), sketch, factor, refined CG, x
+        opts = (api.SolveOptions(tune=tune, refine=1, inner_digits=6) if fp64 else api.SolveOptions(tune=tune))
+        lo = None if fp64 else A_lo
+        for s_ in range(warmup):
+            opts.seed = seed0 + s_
+            _, info = api.minnorm_solve(A, b, eps, None, None, N, A_lo=lo, x=x, opts=opts, l=l)
+            log(f"[bench]   warmup info {info}")
+        torch.cuda.synchronize()
+        if not fp64:
+            api.profile(PROFILE_EVERY)
+        infos = []
+        t0 = time.perf_counter()
+        for s_ in range(steps):
+            opts.seed = seed0 + warmup + s_
+            _, info = api.minnorm_solve(A, b, eps, None, None, N, A_lo=lo, x=x, opts=opts, l=l)
+            infos.append(info)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kst = None
+        if not fp64:
+            kst = {k: api.profile_read(k) for k in ("gemv_adj", "gemv_fwd", "gram")}
+            api.profile(False)
+        return elapsed, infos, kst
+
+    log(f"[bench] mixed: warmup {args.warmup}, timed {args.steps} solves")
+    elapsed, infos, kstats = run(args.steps, args.warmup, 3000, False)
+    value = args.steps / elapsed
+    log(f"[bench] mixed {value:.2f} solves/s; last info {infos[-1]}")
+    kernel_table = {k: {"launches": c, "avg_us": 1e3 * t / max(c, 1)} for k, (c, t) in kstats.items() if c}
+    log(f"[bench] kernels {kernel_table}")
+
+    fsteps = args.fp64_steps if args.fp64_steps is not None else max(2, args.steps // 2)
+    log(f"[bench] FP64 GPU path on the same A: warmup 1, timed {fsteps} solves")
+    f_elapsed, f_infos, _ = run(fsteps, 1, 5000, True)
+    fp64_value = fsteps / f_elapsed
+    log(f"[bench] FP64 {fp64_value:.2f} solves/s; last info {f_infos[-1]}")
+
+    plans = plans_dump(api, args)
+    # dominant kernel: the pass over A with the larger total time
+    name = max(kstats, key=lambda k: kstats[k][1])
+    cnt, tot_ms = kstats[name]
+    avg_s = tot_ms / cnt / 1e3
+    es = 8  # the complex64 copy
+    fused = name == "gram"
+    kname = {"gemv_adj": "k_gemv_adj", "gemv_fwd": "k_gemv_fwd",
+             "gram": "k_gram_tall" if m > 512 else "k_gram_cm"}[name]
+    alg_bytes = m * n * es + (2 * m * 16 if fused else m * 16 + n * 16)
+    achieved = alg_bytes / avg_s / 1e9
+    traffic = None
+    rec = MEASURED_TRAFFIC_MIXED.get(kname)
+    if rec:
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            same = hashlib.sha256(f.read()).hexdigest() == rec["sha256"]
+        if same and plans.get(rec["plan_key"]) == rec["plan"]:
+            traffic = rec["bytes"]
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline_classical(A, b, m, n)
+
+    statuses = [i["status"] for i in infos] + [i["status"] for i in f_infos]
     out = {
-        "metric": "solves/s at rel-err <= 1e-10 (FP64 certificate)",
-        "value": args.steps / elapsed,
+        "metric": "solves/s at rel-err <= 1e-10 (with HBM GB/s per A-pass), mixed precision vs FP64",
+        "value": value,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -476,22 +584,41 @@ def main_mixed(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128 data; c64 bulk, fp64 (compensated) refinement",
+        "dtype": "c64 bulk (sketch, factor, inner CG), f64 compensated refinement; c128 data",
         "data": "synthetic",
-        "config": {"workload": f"mixed precision, complex128 A {m}x{n} = U diag(sigma) V* (Haar, generated on the "
-                               f"device), cond {kappa:g}, complex64 copy as the bulk, eps {eps:g}, l={l}, N={N}",
+        "config": {"workload": f"mixed precision, complex128 A {m}x{n} = U diag(sigma) V* (Haar factors, "
+                               f"generated on the device), cond {kappa:g}, complex64 copy as the bulk, FP64 "
+                               f"refinement, eps {eps:g}, l={l}, N={N}, one RHS, library-drawn SRFT per solve",
                    "m": m, "n": n, "l": l, "N": N, "eps": eps, "kappa": kappa},
-        "statuses": [i["status"] for i in infos],
+        "fp64_value": fp64_value,
+        "fp64_ms_per_step": 1e3 * f_elapsed / fsteps,
+        "mixed_over_fp64": value / fp64_value,
+        "fp64_config": "the same A, complex128 bulk (one-read passes over its column-major copy), FP64 "
+                       "refinement with the same compensated residuals, inner solves to 6 digits (the fastest of 4, 6, 8, 10 and 12 measured on this workload), same eps",
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": avg_s * 1e6},
+        "kernels": kernel_table,
+        "gbps_per_apass": achieved,
+        "rel_err": max(i["cert_rel"] for i in infos),
+        "rel_err_kind": "FP64 certificate sqrt(rho/xi) >= ||x - p|| / ||x|| of every timed solve; the same path "
+                        "is compared with the longdouble-refined oracle at 2048 x 65536 and smaller in the GPU "
+                        "tests (tests/test_gpu_large.py)",
+        "fp64_rel_err": max(i["cert_rel"] for i in f_infos),
+        "statuses_ok": sum(1 for v in statuses if v == 0),
+        "solves": len(statuses),
         "iters": [i["iters"] for i in infos],
         "refine_steps": [i["refine_steps"] for i in infos],
-        "cert_rel_max": max(i["cert_rel"] for i in infos),
-        "residual_rel": res,
+        "fp64_iters": [i["iters"] for i in f_infos],
+        "fp64_refine_steps": [i["refine_steps"] for i in f_infos],
         "stage_ms": infos[-1]["stage_ms"],
-        "roofline": None,
-        "cpu_baseline": None,
-        "plans": plans_dump(api, args),
+        "fp64_stage_ms": f_infos[-1]["stage_ms"],
+        "cpu_baseline": cpu,
+        "plans": plans,
     }
     print(json.dumps(out), flush=True)
+
 
 if __name__ == "__main__":
     main()

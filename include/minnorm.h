@@ -31,7 +31,9 @@
  *     real dtypes, where the transform F is the orthonormal discrete Hartley
  *     transform cas(2 pi j k / N) / sqrt(N) (the paper's real analogue).
  *     idx holds the l subsampled rows as int32: strictly increasing, in [0, N).
- *     The library draws no random numbers of its own.
+ *     The caller passes its own draw, or (minnorm_solve, minnorm_solve_batched)
+ *     d = idx = NULL: the library then draws them itself as srft_draw
+ *     defines, from mn_opts.seed, and redraws after a rank-deficient sketch.
  *   - Work is enqueued on the handle's stream.  Entry points that report a
  *     data-dependent status (rank deficiency, convergence, invalid idx)
  *     synchronise that stream before returning.
@@ -44,8 +46,11 @@
  *   +1  MN_RANK_DEFICIENT: the sketch S is numerically rank-deficient
  *       (Remark 4.1): min_j |R_jj| <= tau max_i |R_ii|, tau = 16 sqrt(l) u
  *       for an FP64 sketch and 4 u for an FP32 one (u the unit roundoff).
- *       Redraw (d, idx) and call again; a persistent +1 means A is not full
- *       rank.
+ *       With a library draw this is returned only after mn_opts.max_reseed
+ *       further independent draws (2 by default) were rank-deficient too
+ *       (each draw fails with the small probability Lemma 3.1 bounds); with
+ *       a caller's draw it is returned at once: redraw and call again.  A
+ *       persistent +1 means A is not full rank.
  *   +2  MN_NOT_CONVERGED: the iteration cap was reached; x holds the last
  *       iterate and info the certificate reached.
  *   +3  MN_HIP_ERROR: a HIP runtime call failed (mn_last_hip_error()).
@@ -116,6 +121,17 @@ typedef struct {
                             systems is one launch; the systems iterate in
                             lockstep, each with its own stopping test), else
                             concurrent lanes; 1 = concurrent lanes           [0] */
+  int32_t refine;        /* 1: FP64 refinement around an FP64 bulk as well:
+                            the inner CG runs on A itself to inner_digits and
+                            the FP64 residual b - A A* y and x = A* y are
+                            compensated once cond(A) u64 nears eps, as in the
+                            mixed mode (the plain FP64 method's x = A* y has
+                            a rounding floor of about cond(A) u64); 0 = FP64
+                            refinement only around a single-precision bulk [0] */
+  int32_t max_reseed;    /* library draw (d = idx = NULL): further draws after
+                            a rank-deficient sketch before +1 is returned;
+                            -1 = none, 0 = the default                        [2] */
+  uint64_t seed;         /* library draw: the Philox key (see srft_draw)      [0] */
 } mn_opts;
 
 /* Per-solve report (host struct written by the library). */
@@ -127,6 +143,9 @@ typedef struct {
   double cert_rel;       /* sqrt(rho / xi): the certificate of ||x-p|| / ||x||  */
   double rho0, rho, xi;  /* CG scalars at exit (see minnorm_solve)              */
   float stage_ms[8];     /* sketch, qr, cg, final product, refine, -, -, total  */
+  int32_t retries;       /* library draw: redraws after a rank-deficient sketch
+                            (the draw that was used has draw number retries) */
+  int32_t reserved;
 } mn_info;
 
 /* Handle: owns the stream binding and a device workspace reused across calls.
@@ -214,6 +233,32 @@ int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
                 int64_t N, int64_t l, const void* d, const int32_t* idx,
                 void* S, int64_t lds);
 
+/* Step 1's random quantities (Section 3, eqs. SRFT, SRFT2: D's unit-modulus
+ * phases, S's l rows sampled without replacement, as the paper's experiments
+ * do), drawn with Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by
+ * (seed mod 2^32, floor(seed / 2^32)); w(c0, c1, c2, c3) below is the four
+ * output words at that counter.
+ *   phases:  for j < N, with (x0, x1, x2, x3) = w(j, draw, 0, sys) and
+ *            u = (floor(x0 / 2^5) 2^26 + floor(x1 / 2^6)) 2^-53 in [0, 1):
+ *            complex dtypes d_j = exp(2 pi i u) (FP64), real dtypes
+ *            d_j = 1 - 2 (x2 mod 2);
+ *   indices: Floyd's sampling of l of N: for s = 0 .. l - 1 with
+ *            t = N - l + s and (y0, y1, ..) = w(s, draw, 1, sys),
+ *            r = floor((y0 2^32 + y1) (t + 1) / 2^64); the set gains r if r is
+ *            not in it yet, else t.  idx = the set in increasing order.
+ * minnorm_solve (sys = 0) and minnorm_solve_batched (sys = the system's
+ * index) draw this way when given d = idx = NULL, with draw = 0 and then 1,
+ * 2, ... for each redraw after a rank-deficient sketch.
+ *   d   [N, complex128 for complex dtypes, float64 for real]  device, written
+ *   idx [l, int32]                                           device, written
+ * The phases are computed on the device; the indices on the host and copied
+ * (the call returns after the copy has been enqueued and its host buffer
+ * released, i.e. after a stream synchronisation).
+ * Errors: -1 NULL handle; -2 dtype; -4 draw < 0; -5 sys < 0; -6 N not a
+ * power of two or N > 2^22; -7 l < 1 or l > N; -8 d NULL; -9 idx NULL. */
+int srft_draw(mn_handle h, int dtype, uint64_t seed, int32_t draw, int32_t sys, int64_t N, int64_t l,
+              void* d, int32_t* idx);
+
 /* Step 2's factorisation: Householder QR of the l x m sketch, S = Q_S R
  * (tiled, blocked Householder reflections; Q_S is not formed).
  *   S [l x m, dtype, column-major, lds]  read
@@ -238,12 +283,16 @@ int build_preconditioner(mn_handle h, int dtype, int64_t l, int64_t m,
  *        promote it exactly to FP64; A_lo must then be NULL.
  *   b    [nrhs x m, FP64 (complex128 / float64), b_j at b + j*ldb]   read
  *   N, l, d, idx: the SRFT's length and random quantities as in srft_sketch
- *        (m < l <= N; l = min(4m, N) is the paper's choice).
+ *        (m < l <= N; l = min(4m, N) is the paper's choice), or d = idx =
+ *        NULL for the library's own draw (srft_draw with opts->seed, sys 0;
+ *        redrawn up to opts->max_reseed times after a rank-deficient sketch,
+ *        info->retries reports how many).
  *   x    [nrhs x n, FP64 (complex128 / float64), x_j at x + j*ldx]   written
  *   info optional host struct.
  * Errors: -2 dtype; -3 m < 1, m >= n or m > 8192; -4 n; -5 A; -6 lda; -7 A_lo with a
  * single-precision dtype; -8 lda_lo; -9 b; -10 ldb < m; -11 nrhs < 1 or > 64;
- * -12 eps not in (0,1); -13 N; -14 l <= m or l > N; -15 d; -16 idx;
+ * -12 eps not in (0,1); -13 N; -14 l <= m or l > N; -15 d NULL with idx
+ * given; -16 idx NULL with d given, or (after a sync) not increasing in [0, N);
  * -17 opts field out of range; -18 x; -19 ldx < n. */
 int minnorm_solve(mn_handle h, int dtype, int64_t m, int64_t n,
                   const void* A, int64_t lda, const void* A_lo, int64_t lda_lo,
@@ -257,7 +306,10 @@ int minnorm_solve(mn_handle h, int dtype, int64_t m, int64_t n,
  * entries: those systems then run in plain FP64).  A_lo[i] is read with
  * lda[i] as its leading dimension, the same as A[i].  b_i has m[i] entries,
  * x_i has n[i] entries; lda[i] >= n[i].  When some but not all A_lo entries
- * are NULL, every system runs on the concurrent lanes.
+ * are NULL, every system runs on the concurrent lanes.  d and idx may both
+ * be NULL (the arrays themselves): every system then uses the library's own
+ * draw (srft_draw with opts->seed and sys = its index), with redraws as in
+ * minnorm_solve.
  * info, if not NULL, is a host array of `batch` reports.  Returns the largest
  * status over the systems (each system's own status is in info[i].status).
  * Errors: -3 batch < 1; -4..-16 the matching array is NULL or an entry of it

@@ -17,6 +17,8 @@ Modules
                  Section 7's direct method) and an extended-precision refined
                  variant.
   randomized  -- the five steps of Section 4 end to end, with intermediates.
+  draws       -- the SRFT's phases and indices as the library draws them
+                 (Philox4x32-10 counters, Floyd's sampling), for tests.
 """
 
 from .transforms import (  # noqa: F401
@@ -38,3 +40,4 @@ from .householder import householder_qr, apply_qh, normalize_r  # noqa: F401
 from .pcg import pcg_minnorm, stop_threshold  # noqa: F401
 from .classical import classical_minnorm, refined_minnorm, residuals_longdouble  # noqa: F401
 from .randomized import randomized_minnorm  # noqa: F401
+from .draws import philox4x32_10, draw_phases, draw_indices, draw_srft  # noqa: F401

@@ -15,25 +15,28 @@ class MnOpts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("stop_rule", C.c_int32), ("max_iter", C.c_int32),
                 ("max_refine", C.c_int32), ("check_every", C.c_int32), ("inner_digits", C.c_int32),
                 ("block", C.c_int32), ("streams", C.c_int32), ("precond", C.c_int32),
-                ("tune", C.c_int32), ("batch_form", C.c_int32)]
+                ("tune", C.c_int32), ("batch_form", C.c_int32), ("refine", C.c_int32),
+                ("max_reseed", C.c_int32), ("seed", C.c_uint64)]
 
 
 class MnInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("refine_steps", C.c_int32),
                 ("nrhs_done", C.c_int32), ("cert_rel", C.c_double), ("rho0", C.c_double),
-                ("rho", C.c_double), ("xi", C.c_double), ("stage_ms", C.c_float * 8)]
+                ("rho", C.c_double), ("xi", C.c_double), ("stage_ms", C.c_float * 8),
+                ("retries", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {"status": self.status, "iters": self.iters, "refine_steps": self.refine_steps,
                 "nrhs_done": self.nrhs_done, "cert_rel": self.cert_rel, "rho0": self.rho0,
-                "rho": self.rho, "xi": self.xi,
+                "rho": self.rho, "xi": self.xi, "retries": self.retries,
                 "stage_ms": {k: float(self.stage_ms[i]) for i, k in
                              enumerate(["sketch", "qr", "cg", "final", "refine", "-", "--", "total"])}}
 
 
 EXPORTS = ["mn_create", "mn_destroy", "mn_set_stream", "mn_status_string", "mn_last_hip_error",
            "mn_workspace_bytes", "mn_profile", "mn_profile_read", "mn_plans_save", "mn_plans_load",
-           "mn_plans_count", "srft_sketch", "build_preconditioner", "minnorm_solve", "minnorm_solve_batched"]
+           "mn_plans_count", "srft_draw", "srft_sketch", "build_preconditioner", "minnorm_solve",
+           "minnorm_solve_batched"]
 
 _lib = None
 
@@ -71,6 +74,8 @@ def load():
     lib.mn_plans_load.restype = I32
     lib.mn_plans_count.argtypes = [P]
     lib.mn_plans_count.restype = I32
+    lib.srft_draw.argtypes = [P, I32, C.c_uint64, C.c_int32, C.c_int32, I64, I64, P, P]
+    lib.srft_draw.restype = I32
     lib.srft_sketch.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, P, I64]
     lib.srft_sketch.restype = I32
     lib.build_preconditioner.argtypes = [P, I32, I64, I64, P, I64, P, I64]

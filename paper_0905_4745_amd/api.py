@@ -80,6 +80,21 @@ def _idx_tensor(idx, device):
     return torch.as_tensor(idx, device=device).to(torch.int32).contiguous()
 
 
+def srft_draw(dtype, seed: int, draw: int, sys: int, N: int, l: int, device=None):
+    """The library's own draw of D's phases and S's indices (Section 3); returns (d, idx).
+
+    dtype: the problem's torch dtype (complex -> complex128 phases, real -> +-1 float64).
+    """
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    code = _DT[dtype]
+    d = torch.empty(N, dtype=torch.complex128 if code in (L.MN_C128, L.MN_C64) else torch.float64, device=dev)
+    idx = torch.empty(l, dtype=torch.int32, device=dev)
+    st = L.load().srft_draw(_handle(dev), code, int(seed), int(draw), int(sys), int(N), int(l), _ptr(d), _ptr(idx))
+    if st != 0:
+        raise MinnormError("srft_draw", st)
+    return d, idx
+
+
 def srft_sketch(A, d, idx, N: int):
     """S = T A* (Step 1, eq. randmat); returns an (l, m) column-major view."""
     code = _check_matrix(A)
@@ -124,6 +139,9 @@ class SolveOptions:
     precond: int = 0  # 0: Cholesky of the FP64 Gram matrix when safe, else Householder; 1: Householder
     tune: int = 0  # 1: time the launch candidates of new shapes and keep the fastest plan
     batch_form: int = 0  # batched: 0 fused when possible, 1 concurrent lanes
+    refine: int = 0  # 1: FP64 refinement around an FP64 bulk too (compensated residuals when cond(A) u64 nears eps)
+    max_reseed: int = 0  # library draw: redraws after a rank-deficient sketch (0 default 2, -1 none)
+    seed: int = 0  # library draw: Philox key
 
     def to_c(self):
         o = L.MnOpts()
@@ -138,14 +156,19 @@ class SolveOptions:
         o.precond = self.precond
         o.tune = self.tune
         o.batch_form = self.batch_form
+        o.refine = self.refine
+        o.max_reseed = self.max_reseed
+        o.seed = self.seed
         return o
 
 
 def minnorm_solve(A, b, eps: float, d, idx, N: int, A_lo=None, opts: SolveOptions | None = None,
-                  x=None, raise_on_status: bool = True):
+                  x=None, raise_on_status: bool = True, l: int | None = None):
     """x approximating the minimal-norm solution of A x = b to relative precision eps.
 
     b: (m,) or (nrhs, m) FP64 (complex128 / float64).  Returns (x, info).
+    d = idx = None: the library draws them (srft_draw with opts.seed) with
+    sketch width l (default min(4m, N), the paper's choice).
     """
     code = _check_matrix(A)
     m, n = A.shape
@@ -158,9 +181,15 @@ def minnorm_solve(A, b, eps: float, d, idx, N: int, A_lo=None, opts: SolveOption
         lo_code = _check_matrix(A_lo, "A_lo")
         if A_lo.shape != A.shape or A_lo.dtype != _SINGLE_OF.get(code):
             raise ValueError("A_lo must be the single-precision copy of A")
-    dt = _d_tensor(d, code, A.device)
-    it = _idx_tensor(idx, A.device)
-    l = it.numel()
+    if (d is None) != (idx is None):
+        raise ValueError("pass both d and idx, or neither (library draw)")
+    if d is None:
+        dt = it = None
+        l = int(l) if l is not None else min(4 * m, int(N))
+    else:
+        dt = _d_tensor(d, code, A.device)
+        it = _idx_tensor(idx, A.device)
+        l = it.numel()
     if x is None:
         x = torch.empty((nrhs, n), dtype=wide, device=A.device)
     x2 = x.reshape(1, -1) if x.dim() == 1 else x
@@ -180,13 +209,25 @@ def minnorm_solve(A, b, eps: float, d, idx, N: int, A_lo=None, opts: SolveOption
 
 
 def minnorm_solve_batched(As, bs, eps, ds, idxs, Ns, A_los=None, opts: SolveOptions | None = None,
-                          raise_on_status: bool = True):
-    """Independent systems of uneven sizes in one call; returns (xs, infos)."""
+                          raise_on_status: bool = True, ls=None):
+    """Independent systems of uneven sizes in one call; returns (xs, infos).
+
+    ds = idxs = None: the library draws every system's (d, idx) (srft_draw with
+    opts.seed and sys = the system's index), sketch widths ls (default
+    min(4 m_i, N_i)).
+    """
     batch = len(As)
     code = _check_matrix(As[0])
     wide = _WIDE[code]
     dev = As[0].device
-    if len(bs) != batch or len(ds) != batch or len(idxs) != batch or len(Ns) != batch:
+    lib_draw = ds is None and idxs is None
+    if (ds is None) != (idxs is None):
+        raise ValueError("pass both ds and idxs, or neither (library draws)")
+    if lib_draw:
+        ls = [int(v) for v in ls] if ls is not None else [min(4 * A.shape[0], int(N)) for A, N in zip(As, Ns)]
+        if len(ls) != batch:
+            raise ValueError("ls must have one entry per system")
+    if len(bs) != batch or len(Ns) != batch or (not lib_draw and (len(ds) != batch or len(idxs) != batch)):
         raise ValueError("As, bs, ds, idxs and Ns must have one entry per system")
     if A_los is not None and len(A_los) != batch:
         raise ValueError("A_los must have one entry per system (or be None)")
@@ -209,9 +250,10 @@ def minnorm_solve_batched(As, bs, eps, ds, idxs, Ns, A_los=None, opts: SolveOpti
                 raise ValueError(f"A_los[{i}] must be the single-precision copy of As[{i}] "
                                  "with the same leading dimension")
         xs.append(torch.empty(n_i, dtype=wide, device=dev))
-    for d, idx in zip(ds, idxs):
-        dts.append(_d_tensor(d, code, dev))
-        its.append(_idx_tensor(idx, dev))
+    if not lib_draw:
+        for d, idx in zip(ds, idxs):
+            dts.append(_d_tensor(d, code, dev))
+            its.append(_idx_tensor(idx, dev))
     I64 = C.c_int64 * batch
     PP = C.c_void_p * batch
     m = I64(*[A.shape[0] for A in As])
@@ -222,9 +264,9 @@ def minnorm_solve_batched(As, bs, eps, ds, idxs, Ns, A_los=None, opts: SolveOpti
     bp = PP(*[b.data_ptr() for b in bs])
     epsa = (C.c_double * batch)(*([float(eps)] * batch if isinstance(eps, (int, float)) else list(eps)))
     Na = I64(*[int(v) for v in Ns])
-    la = I64(*[t.numel() for t in its])
-    dp = PP(*[t.data_ptr() for t in dts])
-    ip = PP(*[t.data_ptr() for t in its])
+    la = I64(*(ls if lib_draw else [t.numel() for t in its]))
+    dp = None if lib_draw else PP(*[t.data_ptr() for t in dts])
+    ip = None if lib_draw else PP(*[t.data_ptr() for t in its])
     xp = PP(*[t.data_ptr() for t in xs])
     infos = (L.MnInfo * batch)()
     o = (opts or SolveOptions()).to_c()

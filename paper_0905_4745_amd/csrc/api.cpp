@@ -73,6 +73,8 @@ struct mn_handle_s {
   double kappa_hat = 1.0;      // max|R_ii| / min|R_ii| of the last factorisation
   void* host_stage = nullptr;  // pinned staging of the fused batched form
   size_t host_stage_bytes = 0;
+  int32_t* host_draw = nullptr;  // pinned staging of library-drawn indices
+  size_t host_draw_n = 0;
 };
 
 namespace {
@@ -328,6 +330,31 @@ bool prepare_idx(mn_handle h, const int32_t* idx, int64_t l, int64_t N, int32_t*
   *inv_out = inv;
   return *h->host_flag == 0;
 }
+
+// The library's own draw of D's phases (device) and S's indices (host, then
+// copied through pinned memory); returns once the copy has left the staging
+// buffer.
+void draw_srft_into(mn_handle h, bool cplx, uint64_t seed, int draw, int sys, int64_t N, int64_t l, void* d,
+                    int32_t* idx) {
+  ck(launch_draw_phases(cplx, seed, draw, sys, N, d, h->stream));
+  if (h->host_draw_n < (size_t)l) {
+    if (h->host_draw) {
+      ck(hipStreamSynchronize(h->stream));
+      ck(hipHostFree(h->host_draw));
+      h->host_draw = nullptr;
+      h->host_draw_n = 0;
+    }
+    ck(hipHostMalloc((void**)&h->host_draw, (size_t)l * sizeof(int32_t), hipHostMallocDefault));
+    h->host_draw_n = (size_t)l;
+  }
+  draw_indices(seed, draw, sys, N, l, h->host_draw);
+  ck(hipMemcpyAsync(idx, h->host_draw, (size_t)l * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  ck(hipStreamSynchronize(h->stream));
+}
+
+// Redraws after a rank-deficient sketch when the library draws (max_reseed:
+// 0 = the default 2, -1 = none).
+int reseeds_of(const mn_opts& o) { return o.max_reseed == 0 ? 2 : (o.max_reseed < 0 ? 0 : o.max_reseed); }
 
 // Step 2's factorisation; returns 0 or MN_RANK_DEFICIENT / MN_NONFINITE.
 int run_qr(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t lds, void* R, int64_t ldr) {
@@ -1060,12 +1087,14 @@ bool opts_valid(const mn_opts& o) {
   return o.alpha > 1.0 && (o.stop_rule == 0 || o.stop_rule == 1) && o.max_iter > 0 && o.max_refine > 0 &&
          o.block >= 0 && o.block <= 2 && o.streams > 0 && o.streams <= 64 && (o.precond == 0 || o.precond == 1) &&
          (o.tune == 0 || o.tune == 1) && (o.batch_form == 0 || o.batch_form == 1) &&
-         o.check_every >= 0 && o.check_every <= 1024 && o.inner_digits > 0 && o.inner_digits <= 12;
+         o.check_every >= 0 && o.check_every <= 1024 && o.inner_digits > 0 && o.inner_digits <= 12 &&
+         (o.refine == 0 || o.refine == 1) && o.max_reseed >= -1 && o.max_reseed <= 16;
 }
 
 int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const void* A_lo,
                int64_t lda_lo, const void* b, int64_t ldb, int64_t nrhs, double eps, int64_t N, int64_t l,
-               const void* d, const int32_t* idx, const mn_opts& o, void* x, int64_t ldx, mn_info* info) {
+               const void* d, const int32_t* idx, const mn_opts& o, void* x, int64_t ldx, mn_info* info,
+               int sys = 0) {
   SolveCtx c{};
   c.h = h;
   c.dtype = dtype;
@@ -1082,7 +1111,8 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     c.bulk = dtype + 1;  // C128 -> C64, F64 -> F32
     c.Ab = A_lo;
     c.ldab = lda_lo;
-  } else if (is_single(dtype)) {
+  } else if (is_single(dtype) || o.refine == 1) {
+    // a single-precision problem, or FP64 refinement around the FP64 bulk
     c.mixed = true;
     c.bulk = dtype;
     c.Ab = A;
@@ -1109,14 +1139,8 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     c.Ab = pad;
     c.ldab = pld;
   }
-  int32_t* inv = nullptr;
-  if (!prepare_idx(h, idx, l, N, &inv)) return -16;
   const int64_t bes = dtype_size(c.bulk);
   void* S = ws(h, "S", (size_t)(l * m * bes));
-  run_sketch(h, c.bulk, m, n, c.Ab, c.ldab, N, l, d, idx, inv, S, l, &o);
-  ev_record(h, 1);
-  // Step 2's R: Cholesky of the FP64 Gram matrix when that is accurate,
-  // Householder QR of S otherwise
   const int wdt = is_complex(dtype) ? MN_C128 : MN_F64;
   int rdt = c.bulk;
   bool gram = false;
@@ -1124,22 +1148,46 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   // launches after the Householder factorisation otherwise
   const int64_t ldxi = rinv_ld(m);
   c.X = ws(h, "Xinv", (size_t)(ldxi * ldxi * wide_size(dtype)));
-  const bool block = o.block == 2 || (o.block == 0 && nrhs >= 2 && c.mixed);
-  // the block products read whole tiles of X, so its strict lower part must be zero
-  if (block) ck(launch_fill0(c.X, ldxi * ldxi * wide_size(dtype), h->stream));
-  if (o.precond == 0) {
-    c.R = ws(h, "R64", (size_t)(m * m * wide_size(dtype)));
-    gram = gram_factor(h, c.bulk, l, m, S, l, c.R, &o, c.X, ldxi);
-    if (gram) rdt = wdt;
-  }
-  if (!gram) {
-    c.R = ws(h, "R", (size_t)(m * m * bes));
-    const int st = run_qr(h, c.bulk, l, m, S, l, c.R, m);
-    if (st != MN_OK) {
-      ev_record(h, 2);
-      if (info) info->status = st;
-      return st;
+  const bool block = o.block == 2 || (o.block == 0 && nrhs >= 2 && c.mixed && is_single(c.bulk));
+  // Steps 1-2 for one draw of (d, idx): the caller's, or the library's own
+  // (srft_draw), redrawn after a rank-deficient sketch (Remark 4.1)
+  const bool lib_draw = d == nullptr;
+  const int attempts = lib_draw ? 1 + reseeds_of(o) : 1;
+  for (int att = 0;; ++att) {
+    if (lib_draw) {
+      void* dd = ws(h, "draw_d", (size_t)(N * (is_complex(dtype) ? 16 : 8)));
+      int32_t* di = (int32_t*)ws(h, "draw_idx", (size_t)l * 4);
+      draw_srft_into(h, is_complex(dtype), o.seed, att, sys, N, l, dd, di);
+      d = dd;
+      idx = di;
+      if (info) info->retries = att;
     }
+    int32_t* inv = nullptr;
+    if (!prepare_idx(h, idx, l, N, &inv)) return -16;
+    run_sketch(h, c.bulk, m, n, c.Ab, c.ldab, N, l, d, idx, inv, S, l, &o);
+    ev_record(h, 1);
+    // Step 2's R: Cholesky of the FP64 Gram matrix when that is accurate,
+    // Householder QR of S otherwise
+    rdt = c.bulk;
+    gram = false;
+    // the block products read whole tiles of X, so its strict lower part must be zero
+    if (block) ck(launch_fill0(c.X, ldxi * ldxi * wide_size(dtype), h->stream));
+    if (o.precond == 0) {
+      c.R = ws(h, "R64", (size_t)(m * m * wide_size(dtype)));
+      gram = gram_factor(h, c.bulk, l, m, S, l, c.R, &o, c.X, ldxi);
+      if (gram) rdt = wdt;
+    }
+    if (!gram) {
+      c.R = ws(h, "R", (size_t)(m * m * bes));
+      const int st = run_qr(h, c.bulk, l, m, S, l, c.R, m);
+      if (st == MN_RANK_DEFICIENT && att + 1 < attempts) continue;
+      if (st != MN_OK) {
+        ev_record(h, 2);
+        if (info) info->status = st;
+        return st;
+      }
+    }
+    break;
   }
   ev_record(h, 2);
   // compensated refinement passes when the rounding of plain FP64 sums,
@@ -1610,8 +1658,8 @@ int check_solve_args(mn_handle h, int dtype, int64_t m, int64_t n, const void* A
   if (!(eps > 0.0 && eps < 1.0)) return -12;
   if (!is_pow2(N) || N < n || N > (1 << 22)) return -13;
   if (l <= m || l > N) return -14;
-  if (!d) return -15;
-  if (!idx) return -16;
+  if (!d && idx) return -15;  // both NULL: the library draws
+  if (d && !idx) return -16;
   if (!opts_valid(o)) return -17;
   if (!x) return -18;
   if (ldx < n) return -19;
@@ -1661,6 +1709,7 @@ int mn_destroy(mn_handle h) {
     if (e) (void)hipEventDestroy(e);
   if (h->host_blk) (void)hipHostFree(h->host_blk);
   if (h->host_stage) (void)hipHostFree(h->host_stage);
+  if (h->host_draw) (void)hipHostFree(h->host_draw);
   if (h->host_flag) (void)hipHostFree(h->host_flag);
   if (h->host_diag) (void)hipHostFree(h->host_diag);
   for (auto& e : h->ev)
@@ -1831,6 +1880,24 @@ int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   return 0;
 }
 
+int srft_draw(mn_handle h, int dtype, uint64_t seed, int32_t draw, int32_t sys, int64_t N, int64_t l, void* d,
+              int32_t* idx) {
+  if (!h) return -1;
+  if (dtype < 0 || dtype > 3) return -2;
+  if (draw < 0) return -4;
+  if (sys < 0) return -5;
+  if (!is_pow2(N) || N > (1 << 22)) return -6;
+  if (l < 1 || l > N) return -7;
+  if (!d) return -8;
+  if (!idx) return -9;
+  try {
+    draw_srft_into(h, is_complex(dtype), seed, draw, sys, N, l, d, idx);
+  } catch (HipFail f) {
+    return fail_hip(f.e);
+  }
+  return 0;
+}
+
 int build_preconditioner(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t lds, void* R,
                          int64_t ldr) {
   if (!h) return -1;
@@ -1877,8 +1944,8 @@ int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* 
   if (!eps) return -10;
   if (!N) return -11;
   if (!l) return -12;
-  if (!d) return -13;
-  if (!idx) return -14;
+  if (!d && idx) return -13;  // both NULL: the library draws every system's
+  if (d && !idx) return -14;
   if (!x) return -16;
   const mn_opts o = resolve_opts(opts);
   if (!opts_valid(o)) return -15;
@@ -1888,17 +1955,44 @@ int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* 
   for (int32_t i = 0; i < batch; ++i) {
     const void* alo = A_lo ? A_lo[i] : nullptr;
     const int e = check_solve_args(h, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i],
-                                   l[i], d[i], idx[i], o, x[i], n[i]);
+                                   l[i], d ? d[i] : nullptr, idx ? idx[i] : nullptr, o, x[i], n[i]);
     if (e) return remap[-e];
   }
+  // the library's own draws: every system's (d, idx) with draw 0 and sys = i
+  // for the fused form (redraws happen in the one-system solves of the
+  // systems it leaves); the lanes draw inside their one-system solves
+  std::vector<const void*> dv;
+  std::vector<const int32_t*> iv;
+  const bool lib_draw = d == nullptr;
+  auto d_of = [&](int i) -> const void* { return lib_draw ? nullptr : d[i]; };
+  auto idx_of = [&](int i) -> const int32_t* { return lib_draw ? nullptr : idx[i]; };
   if (fused_batch_ok(batch, m, A_lo, o)) {
     std::vector<int> stv, redo;
     try {
-      solve_batched_fused(h, dtype, batch, m, n, A, lda, A_lo, b, eps, N, l, d, idx, o, x, info, stv, redo);
+      if (lib_draw) {
+        int64_t dn = 0, in = 0;
+        for (int32_t i = 0; i < batch; ++i) {
+          dn += a256(N[i] * (is_complex(dtype) ? 16 : 8));
+          in += a256(l[i] * 4);
+        }
+        char* dbase = (char*)ws(h, "bdraw_d", (size_t)dn);
+        char* ibase = (char*)ws(h, "bdraw_idx", (size_t)in);
+        dv.resize(batch);
+        iv.resize(batch);
+        for (int32_t i = 0; i < batch; ++i) {
+          draw_srft_into(h, is_complex(dtype), o.seed, 0, i, N[i], l[i], dbase, (int32_t*)ibase);
+          dv[i] = dbase;
+          iv[i] = (const int32_t*)ibase;
+          dbase += a256(N[i] * (is_complex(dtype) ? 16 : 8));
+          ibase += a256(l[i] * 4);
+        }
+      }
+      solve_batched_fused(h, dtype, batch, m, n, A, lda, A_lo, b, eps, N, l, lib_draw ? dv.data() : d,
+                          lib_draw ? iv.data() : idx, o, x, info, stv, redo);
       for (int i : redo) {
         const void* alo = A_lo ? A_lo[i] : nullptr;
-        stv[i] = solve_impl(h, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i], l[i], d[i],
-                            idx[i], o, x[i], n[i], info ? &info[i] : nullptr);
+        stv[i] = solve_impl(h, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i], l[i],
+                            d_of(i), idx_of(i), o, x[i], n[i], info ? &info[i] : nullptr, i);
       }
     } catch (HipFail f) {
       return fail_hip(f.e);
@@ -1956,8 +2050,8 @@ int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* 
       const void* alo = A_lo ? A_lo[i] : nullptr;
       int s;
       try {
-        s = solve_impl(c, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i], l[i], d[i],
-                       idx[i], o, x[i], n[i], info ? &info[i] : nullptr);
+        s = solve_impl(c, dtype, m[i], n[i], A[i], lda[i], alo, lda[i], b[i], m[i], 1, eps[i], N[i], l[i], d_of(i),
+                       idx_of(i), o, x[i], n[i], info ? &info[i] : nullptr, i);
       } catch (HipFail f) {
         s = fail_hip(f.e);
       }

@@ -53,6 +53,10 @@ int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng);
 hipError_t launch_sketch(int dtype, const SketchArgs& a, hipStream_t st);
 int sketch_max_log2n(int dtype);  // largest log2(N) the four-step supports
 hipError_t launch_inverse_map(const int32_t* idx, int64_t l, int64_t N, int32_t* inv, int32_t* bad, hipStream_t st);
+// The library's own draw of D and S (draw.hip): phases (complex128 or +-1
+// float64, N entries) on the device, the l indices (increasing) on the host.
+hipError_t launch_draw_phases(bool cplx, uint64_t seed, int draw, int sys, int64_t N, void* d, hipStream_t st);
+void draw_indices(uint64_t seed, int draw, int sys, int64_t N, int64_t l, int32_t* idx);
 
 struct QrArgs {
   const void* S;

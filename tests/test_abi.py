@@ -112,10 +112,38 @@ def test_solve_argument_errors():
     assert call(N=24) == -13
     assert call(l=4) == -14         # l must exceed m
     assert call(l=17) == -14
-    assert call(d=None) == -15
+    assert call(d=None) == -15      # one of d, idx without the other
     assert call(idx=None) == -16
     bad = L.MnOpts()
     bad.alpha = 0.5
     assert call(opts=C.pointer(bad)) == -17
+    for field, value in (("refine", 2), ("max_reseed", -2), ("max_reseed", 17)):
+        o = L.MnOpts()
+        setattr(o, field, value)
+        assert call(opts=C.pointer(o)) == -17, field
     assert call(x=None) == -18
     assert call(ldx=9) == -19
+
+
+def test_draw_argument_errors():
+    L, lib = _lib()
+    h = _Dummy().ptr
+    p = C.c_void_p(16)
+    assert lib.srft_draw(None, 0, 1, 0, 0, 16, 8, p, p) == -1
+    assert lib.srft_draw(h, 4, 1, 0, 0, 16, 8, p, p) == -2
+    assert lib.srft_draw(h, 0, 1, -1, 0, 16, 8, p, p) == -4
+    assert lib.srft_draw(h, 0, 1, 0, -1, 16, 8, p, p) == -5
+    assert lib.srft_draw(h, 0, 1, 0, 0, 24, 8, p, p) == -6
+    assert lib.srft_draw(h, 0, 1, 0, 0, 1 << 23, 8, p, p) == -6
+    assert lib.srft_draw(h, 0, 1, 0, 0, 16, 0, p, p) == -7
+    assert lib.srft_draw(h, 0, 1, 0, 0, 16, 17, p, p) == -7
+    assert lib.srft_draw(h, 0, 1, 0, 0, 16, 8, None, p) == -8
+    assert lib.srft_draw(h, 0, 1, 0, 0, 16, 8, p, None) == -9
+
+
+def test_struct_layouts_match_header():
+    """The ctypes views have the header's sizes (options 64 bytes, report 88)."""
+    L, _ = _lib()
+    assert C.sizeof(L.MnOpts) == 64
+    assert C.sizeof(L.MnInfo) == 88
+    assert L.MnOpts.seed.offset == 56 and L.MnInfo.retries.offset == 80
