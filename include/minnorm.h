@@ -233,6 +233,21 @@ int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
                 int64_t N, int64_t l, const void* d, const int32_t* idx,
                 void* S, int64_t lds);
 
+/* srft_sketch without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, result and errors as srft_sketch, for
+ * N <= 65536 (-7 beyond).  Its scratch (the twiddle table, the inverse
+ * subsample map, the kept-output order and the four-step work area) lives in
+ * a static device array of 32 MiB that the library holds on every GPU it
+ * runs on until the process ends; the array's device address is looked up
+ * once per device by mn_create.  Calls that overlap on one GPU (different
+ * streams or handles) share that array and race; calls on one stream are
+ * ordered.  The twiddle table is rebuilt when N or the precision changes.
+ * Like srft_sketch, the call synchronises the stream once (idx's check). */
+int srft_sketch_noalloc(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                        int64_t N, int64_t l, const void* d, const int32_t* idx,
+                        void* S, int64_t lds);
+
 /* Step 1's random quantities (Section 3, eqs. SRFT, SRFT2: D's unit-modulus
  * phases, S's l rows sampled without replacement, as the paper's experiments
  * do), drawn with Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by

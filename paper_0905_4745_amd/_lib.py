@@ -35,8 +35,8 @@ class MnInfo(C.Structure):
 
 EXPORTS = ["mn_create", "mn_destroy", "mn_set_stream", "mn_status_string", "mn_last_hip_error",
            "mn_workspace_bytes", "mn_profile", "mn_profile_read", "mn_plans_save", "mn_plans_load",
-           "mn_plans_count", "srft_draw", "srft_sketch", "build_preconditioner", "minnorm_solve",
-           "minnorm_solve_batched"]
+           "mn_plans_count", "srft_draw", "srft_sketch", "srft_sketch_noalloc", "build_preconditioner",
+           "minnorm_solve", "minnorm_solve_batched"]
 
 _lib = None
 
@@ -78,6 +78,8 @@ def load():
     lib.srft_draw.restype = I32
     lib.srft_sketch.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, P, I64]
     lib.srft_sketch.restype = I32
+    lib.srft_sketch_noalloc.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, P, I64]
+    lib.srft_sketch_noalloc.restype = I32
     lib.build_preconditioner.argtypes = [P, I32, I64, I64, P, I64, P, I64]
     lib.build_preconditioner.restype = I32
     lib.minnorm_solve.argtypes = [P, I32, I64, I64, P, I64, P, I64, P, I64, I64, D, I64, I64, P, P,

@@ -110,6 +110,27 @@ def srft_sketch(A, d, idx, N: int):
     return St.t()
 
 
+def srft_sketch_noalloc(A, d, idx, N: int, S=None):
+    """srft_sketch without device allocation inside the library (N <= 65536).
+
+    S: optional (m, l) row-major output buffer (its transpose is the column-
+    major l x m sketch); returns the (l, m) column-major view.
+    """
+    code = _check_matrix(A)
+    m, n = A.shape
+    dt = _d_tensor(d, code, A.device)
+    it = _idx_tensor(idx, A.device)
+    l = it.numel()
+    St = S if S is not None else torch.empty((m, l), dtype=A.dtype, device=A.device)
+    if St.shape != (m, l) or St.dtype != A.dtype or not St.is_contiguous():
+        raise ValueError(f"S must be a contiguous ({m}, {l}) {A.dtype} tensor")
+    st = L.load().srft_sketch_noalloc(_handle(A.device), code, m, n, _ptr(A), _ld(A, 0, n), int(N), l,
+                                      _ptr(dt), _ptr(it), _ptr(St), l)
+    if st != 0:
+        raise MinnormError("srft_sketch_noalloc", st)
+    return St.t()
+
+
 def build_preconditioner(S, allow_rank_deficient: bool = False):
     """R of the Householder QR of the (l, m) sketch; returns an (m, m) column-major view.
 

@@ -108,42 +108,13 @@ bool is_complex(int dtype) { return dtype == MN_C128 || dtype == MN_C64; }
 bool is_single(int dtype) { return dtype == MN_C64 || dtype == MN_F32; }
 int compute_cplx_dtype(int dtype) { return is_single(dtype) ? 1 : 0; }  // twiddle table slot
 
-// W_N^k = exp(-2 pi i k / N), k < N, computed in long double and rounded,
-// followed by the compact tables W_{N1'}^k = W_N^{k N / N1'}, k < N1', for
-// the four-step splits N1' = N1, 2 N1, 4 N1 (N1 = N / 2^floor(log2(N) / 2)).
+// The sketch's twiddle table for (N, precision), built once per handle on the
+// device (launch_twiddles) and kept.
 const void* twiddles(mn_handle h, int64_t N, bool single) {
   Twiddle& t = h->tw[{N, single ? 1 : 0}];
   if (t.N == N && t.p) return t.p;
-  const size_t es = single ? 8 : 16;
-  int lg = 0;
-  while (((int64_t)1 << lg) < N) ++lg;
-  const int64_t N1 = N >> (lg / 2);
-  // compact tables W_{N1'}^k for N1' = N1, 2 N1, 4 N1 (where N1' <= N)
-  int64_t extra = 0;
-  for (int s = 0; s < 3; ++s)
-    if ((N1 << s) <= N) extra += N1 << s;
-  std::vector<unsigned char> host((size_t)(N + extra) * es);
-  const long double two_pi = 6.283185307179586476925286766559005768L;
-  for (int64_t k = 0; k < N; ++k) {
-    const long double a = two_pi * (long double)k / (long double)N;
-    const long double c = cosl(a), s = -sinl(a);
-    if (single) {
-      float v[2] = {(float)c, (float)s};
-      memcpy(&host[(size_t)k * es], v, es);
-    } else {
-      double v[2] = {(double)c, (double)s};
-      memcpy(&host[(size_t)k * es], v, es);
-    }
-  }
-  int64_t off = N;
-  for (int s = 0; s < 3; ++s) {
-    const int64_t L = N1 << s;
-    if (L > N) break;
-    for (int64_t k = 0; k < L; ++k) memcpy(&host[(size_t)(off + k) * es], &host[(size_t)(k * (N / L)) * es], es);
-    off += L;
-  }
-  ck(hipMalloc(&t.p, host.size()));
-  ck(hipMemcpy(t.p, host.data(), host.size(), hipMemcpyHostToDevice));
+  ck(hipMalloc(&t.p, (size_t)(twiddle_entries(N) * (single ? 8 : 16))));
+  ck(launch_twiddles(single, N, t.p, h->stream));
   t.N = N;
   return t.p;
 }
@@ -237,9 +208,19 @@ std::string plan_key(const char* kind, int64_t a, int64_t b, int64_t c, int64_t 
 // ----------------------------------------------------------------------------
 // Step 1: sketch of the rows of A (dtype) into S (l x m, lds).  idx must
 // already be validated into the inverse map `inv`.
+// Caller-provided device memory for the sketch's scratch (the allocation-free
+// entry point): the twiddle table, the kept-output order, and `work_bytes`
+// bytes for the four-step intermediate or partial sums.
+struct SketchArena {
+  const void* twiddle;
+  int32_t* order;
+  void* work;
+  int64_t work_bytes;
+};
+
 void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, int64_t N, int64_t l,
                 const void* d, const int32_t* idx, const int32_t* inv, void* S, int64_t lds,
-                const mn_opts* o = nullptr) {
+                const mn_opts* o = nullptr, const SketchArena* ar = nullptr) {
   const bool single = is_single(dtype);
   const int64_t ces = single ? 8 : 16;
   SketchArgs a{};
@@ -254,7 +235,7 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   a.inv = inv;
   a.S = S;
   a.lds = lds;
-  a.twiddle = twiddles(h, N, single);
+  a.twiddle = ar ? ar->twiddle : twiddles(h, N, single);
   if (N <= kFftMaxLds) {
     ck(launch_sketch(dtype, a, h->stream));
     return;
@@ -282,11 +263,18 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
       else per_row = ng > 1 ? (int64_t)ng * l : 0;
     }
     int64_t chunk = per_row > 0 ? ((int64_t)mb << 20) / (per_row * ces) : m;
+    // the arena's work area bounds the chunk (one row always fits there)
+    if (ar && per_row > 0) chunk = std::min<int64_t>(chunk, ar->work_bytes / (per_row * ces));
     if (chunk < 1) chunk = 1;
     if (chunk > m) chunk = m;
     a.chunk_rows = chunk;
-    a.work = per_row > 0 ? ws(h, "fft_y", (size_t)(chunk * per_row * ces)) : nullptr;
-    a.order = a.pruned_b ? (int32_t*)ws(h, "sk_order", (size_t)l * 4) : nullptr;
+    if (ar) {
+      a.work = per_row > 0 ? ar->work : nullptr;
+      a.order = a.pruned_b ? ar->order : nullptr;
+    } else {
+      a.work = per_row > 0 ? ws(h, "fft_y", (size_t)(chunk * per_row * ces)) : nullptr;
+      a.order = a.pruned_b ? (int32_t*)ws(h, "sk_order", (size_t)l * 4) : nullptr;
+    }
     ck(launch_sketch(dtype, a, h->stream));
   };
   // default: the pruned form with B = 16 for l <= 2048, with enough column
@@ -320,10 +308,12 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   run(mb);
 }
 
-// Validate idx on the device and build the inverse subsample map.
-bool prepare_idx(mn_handle h, const int32_t* idx, int64_t l, int64_t N, int32_t** inv_out) {
-  int32_t* inv = (int32_t*)ws(h, "inv", (size_t)N * 4);
-  int32_t* bad = (int32_t*)ws(h, "bad", 16);
+// Validate idx on the device and build the inverse subsample map (in the
+// handle's workspace, or in inv_buf / bad_buf when given).
+bool prepare_idx(mn_handle h, const int32_t* idx, int64_t l, int64_t N, int32_t** inv_out,
+                 int32_t* inv_buf = nullptr, int32_t* bad_buf = nullptr) {
+  int32_t* inv = inv_buf ? inv_buf : (int32_t*)ws(h, "inv", (size_t)N * 4);
+  int32_t* bad = bad_buf ? bad_buf : (int32_t*)ws(h, "bad", 16);
   ck(launch_inverse_map(idx, l, N, inv, bad, h->stream));
   ck(hipMemcpyAsync(h->host_flag, bad, 4, hipMemcpyDeviceToHost, h->stream));
   ck(hipStreamSynchronize(h->stream));
@@ -1678,6 +1668,9 @@ int mn_create(mn_handle* hp, void* stream) {
   try {
     h->stream = (hipStream_t)stream;
     ck(hipGetDevice(&h->device));
+    // the allocation-free entry point's static array: its address on this
+    // device, looked up once while the device is current
+    ck(noalloc_init(h->device));
     ck(hipHostMalloc((void**)&h->host_state, sizeof(PcgState), hipHostMallocDefault));
     ck(hipHostMalloc((void**)&h->host_snap, 2 * sizeof(PcgState), hipHostMallocDefault));
     for (auto& e : h->snap_ev) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1873,6 +1866,53 @@ int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
     int32_t* inv = nullptr;
     if (!prepare_idx(h, idx, l, N, &inv)) return -10;
     run_sketch(h, dtype, m, n, A, lda, N, l, d, idx, inv, S, lds);
+    ck(hipGetLastError());
+  } catch (HipFail f) {
+    return fail_hip(f.e);
+  }
+  return 0;
+}
+
+int srft_sketch_noalloc(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, int64_t N,
+                        int64_t l, const void* d, const int32_t* idx, void* S, int64_t lds) {
+  if (!h) return -1;
+  if (dtype < 0 || dtype > 3) return -2;
+  if (m < 1) return -3;
+  if (n < 1) return -4;
+  if (!A) return -5;
+  if (lda < n) return -6;
+  if (!is_pow2(N) || N < n || N > kNoAllocMaxN) return -7;
+  if (l < 1 || l > N) return -8;
+  if (!d) return -9;
+  if (!idx) return -10;
+  if (!S) return -11;
+  if (lds < l) return -12;
+  unsigned char* base = (unsigned char*)noalloc_ptr(h->device);
+  if (!base) {
+    g_last_hip_error = "the allocation-free workspace was not set up on this device";
+    return MN_HIP_ERROR;
+  }
+  const bool single = is_single(dtype);
+  // layout of the static array: twiddles | inverse map | flag | order | work
+  unsigned char* tw = base;
+  int32_t* inv = (int32_t*)(base + kNoAllocTwBytes);
+  int32_t* bad = (int32_t*)(base + kNoAllocTwBytes + kNoAllocIdxBytes);
+  int32_t* order = (int32_t*)(base + kNoAllocTwBytes + kNoAllocIdxBytes + 256);
+  unsigned char* work = base + kNoAllocTwBytes + 2 * kNoAllocIdxBytes + 256;
+  const int64_t work_bytes = kNoAllocBytes - (kNoAllocTwBytes + 2 * kNoAllocIdxBytes + 256);
+  if (twiddle_entries(N) * (single ? 8 : 16) > kNoAllocTwBytes) return -7;
+  try {
+    if (noalloc_twiddle_swap(h->device, (N << 1) | (single ? 1 : 0))) {
+      const hipError_t e = launch_twiddles(single, N, tw, h->stream);
+      if (e != hipSuccess) {
+        noalloc_twiddle_swap(h->device, -1);
+        throw HipFail{e};
+      }
+    }
+    int32_t* inv_out = nullptr;
+    if (!prepare_idx(h, idx, l, N, &inv_out, inv, bad)) return -10;
+    const SketchArena ar{tw, order, work, work_bytes};
+    run_sketch(h, dtype, m, n, A, lda, N, l, d, idx, inv_out, S, lds, nullptr, &ar);
     ck(hipGetLastError());
   } catch (HipFail f) {
     return fail_hip(f.e);

@@ -880,6 +880,56 @@ int sketch_max_log2n(int dtype) {
   return 2 * k;
 }
 
+// Twiddle table: W_N^k = exp(-2 pi i k / N) for k < N, then the compact
+// tables W_L^k (k < L) for L = N1, 2 N1, 4 N1 where L <= N, N1 = N / 2^floor(
+// log2(N) / 2) (the four-step splits).  cos and sin of pi (-2k / L), an exact
+// argument, in FP64, rounded once to the table's precision.
+template <typename C>
+__global__ void __launch_bounds__(256) k_twiddles(int64_t N, int64_t N1, int64_t total, C* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= total) return;
+  int64_t k = t, L = N;
+  if (t >= N) {
+    int64_t off = N;
+    for (int s = 0; s < 3; ++s) {
+      const int64_t Ls = N1 << s;
+      if (t < off + Ls) {
+        k = t - off;
+        L = Ls;
+        break;
+      }
+      off += Ls;
+    }
+  }
+  double sn, cs;
+  sincospi(-2.0 * (double)k / (double)L, &sn, &cs);
+  out[t] = vmake<C>(cs, sn);
+}
+
+static int64_t twiddle_n1(int64_t N) {
+  int lg = 0;
+  while (((int64_t)1 << lg) < N) ++lg;
+  return N >> (lg / 2);
+}
+
+int64_t twiddle_entries(int64_t N) {
+  const int64_t N1 = twiddle_n1(N);
+  int64_t total = N;
+  for (int s = 0; s < 3; ++s)
+    if ((N1 << s) <= N) total += N1 << s;
+  return total;
+}
+
+hipError_t launch_twiddles(bool single, int64_t N, void* out, hipStream_t st) {
+  const int64_t total = twiddle_entries(N);
+  const dim3 grid((unsigned)ceil_div(total, 256));
+  if (single)
+    hipLaunchKernelGGL((k_twiddles<cf>), grid, dim3(256), 0, st, N, twiddle_n1(N), total, reinterpret_cast<cf*>(out));
+  else
+    hipLaunchKernelGGL((k_twiddles<cd>), grid, dim3(256), 0, st, N, twiddle_n1(N), total, reinterpret_cast<cd*>(out));
+  return hipGetLastError();
+}
+
 hipError_t launch_inverse_map(const int32_t* idx, int64_t l, int64_t N, int32_t* inv, int32_t* bad, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(N, 256)), dim3(256), 0, st, inv, N, -1);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, bad, 1, 0);

@@ -53,6 +53,25 @@ int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng);
 hipError_t launch_sketch(int dtype, const SketchArgs& a, hipStream_t st);
 int sketch_max_log2n(int dtype);  // largest log2(N) the four-step supports
 hipError_t launch_inverse_map(const int32_t* idx, int64_t l, int64_t N, int32_t* inv, int32_t* bad, hipStream_t st);
+// Twiddle table of the sketch (W_N^k, k < N, then the four-step splits'
+// compact tables): twiddle_entries(N) complex entries of the compute precision.
+int64_t twiddle_entries(int64_t N);
+hipError_t launch_twiddles(bool single, int64_t N, void* out, hipStream_t st);
+// Allocation-free sketch (noalloc.hip): a static device array of
+// kNoAllocBytes per GPU, laid out as the twiddle table (kNoAllocTwBytes,
+// enough for N <= kNoAllocMaxN), the inverse subsample map and the flag of
+// idx's check, the kept-output order, then the four-step work area.
+constexpr int64_t kNoAllocBytes = (int64_t)32 << 20;
+constexpr int64_t kNoAllocMaxN = 65536;
+constexpr int64_t kNoAllocTwBytes = (int64_t)1152 << 10;   // >= twiddle_entries(65536) x 16 bytes
+constexpr int64_t kNoAllocIdxBytes = kNoAllocMaxN * 4;      // inverse map, then the order
+// device address of this device's array (set up by noalloc_init, which runs
+// with the device current); null before
+hipError_t noalloc_init(int device);
+void* noalloc_ptr(int device);
+// records that the twiddle region of `device` now holds table `tag`; true
+// when it held another one (the caller then rebuilds it)
+bool noalloc_twiddle_swap(int device, int64_t tag);
 // The library's own draw of D and S (draw.hip): phases (complex128 or +-1
 // float64, N entries) on the device, the l indices (increasing) on the host.
 hipError_t launch_draw_phases(bool cplx, uint64_t seed, int draw, int sys, int64_t N, void* d, hipStream_t st);
