@@ -86,7 +86,17 @@ def parse():
                          "64 RHS through the block path; batched: 256 uneven real systems (FP64 data + "
                          "FP32 copies) in one batched call")
     ap.add_argument("--fp64-steps", type=int, default=None,
-                    help="mixed: timed solves of the FP64 GPU path (default: steps / 2, at least 2)")
+                    help="mixed: timed solves of the FP64 GPU path (default: steps / 2, at least 2; 0 skips it)")
+    ap.add_argument("--inner-digits", type=int, default=None,
+                    help="mixed: digits each single-precision inner solve gains (default: the library's)")
+    ap.add_argument("--save-a", default=None,
+                    help="mixed: generate A and b, save them to this file (torch.save) and exit")
+    ap.add_argument("--load-a", default=None,
+                    help="mixed: load A and b saved by --save-a instead of generating them (for profiler runs "
+                         "that cannot host the generator's QR)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run one plain 1 GiB device-to-device copy (the reference kernel for scaling "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE readings) and exit")
     ap.add_argument("--streams", type=int, default=8, help="batched: concurrent lanes")
     ap.add_argument("--no-tune", action="store_true", help="built-in launch plans instead of tuned ones")
     ap.add_argument("--plans-out", default=None, help="write the tuned launch plans (JSON) here")
@@ -119,6 +129,15 @@ def main():
                           "its CG recurrences stay on a single device; use --gpus 1"}), flush=True)
         sys.exit(2)
 
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8}), flush=True)
+        return
     if args.workload == "multirhs":
         return main_multirhs(args)
     if args.workload == "batched":
@@ -482,9 +501,14 @@ def cpu_baseline_classical(A_dev, b_dev, m, n):
 
 
 # HBM bytes per live launch of the dominant pass of the mixed workload, from
-# rocprofv3 --pmc (same scaling as MEASURED_TRAFFIC); empty until measured on
-# the current source
-MEASURED_TRAFFIC_MIXED = {}
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (same copy scaling as
+# MEASURED_TRAFFIC: the A copy once, plus the workgroups' q partials written);
+# valid while the source and the plan are the measured ones
+MEASURED_TRAFFIC_MIXED = {
+    "k_gram_tall": {"bytes": 4312112000.0, "source": "paper_0905_4745_amd/csrc/gemv.hip",
+                    "sha256": "7db483bead65faa2d15612b37276c5d2dd7c7b56fc14f4a84d2b354c217bf28b",
+                    "plan_key": "gram/1/2048/262144/1", "plan": 524800},
+}
 
 
 def main_mixed(args):
@@ -503,8 +527,20 @@ def main_mixed(args):
     N = synth.next_pow2(n)
     l = synth.sketch_width(m, N)
     dev = torch.device("cuda:0")
-    log(f"[bench] generating A {m}x{n} complex128 cond {kappa:g} on the device")
-    A, b = synth.make_svd_device(m, n, kappa, seed=3, device=dev)
+    if args.load_a:
+        log(f"[bench] loading A, b from {args.load_a}")
+        A, b = torch.load(args.load_a, map_location="cpu", weights_only=True)
+        A, b = A.to(dev), b.to(dev)
+        m, n = A.shape
+        N = synth.next_pow2(n)
+        l = synth.sketch_width(m, N)
+    else:
+        log(f"[bench] generating A {m}x{n} complex128 cond {kappa:g} on the device")
+        A, b = synth.make_svd_device(m, n, kappa, seed=3, device=dev)
+    if args.save_a:
+        torch.save((A.cpu(), b.cpu()), args.save_a)
+        log(f"[bench] saved A, b to {args.save_a}")
+        return
     A_lo = A.to(torch.complex64)
     x = torch.empty(n, dtype=torch.complex128, device=dev)
     torch.cuda.synchronize()
@@ -515,7 +551,8 @@ def main_mixed(args):
 
     def run(steps, warmup, seed0, fp64):
         # one step: the library's draw (fresh seed), sketch, factor, refined CG, x
-        opts = (api.SolveOptions(tune=tune, refine=1, inner_digits=6) if fp64 else api.SolveOptions(tune=tune))
+        opts = (api.SolveOptions(tune=tune, refine=1, inner_digits=6) if fp64 else
+                api.SolveOptions(tune=tune, inner_digits=args.inner_digits or 0))
         lo = None if fp64 else A_lo
         for s_ in range(warmup):
             opts.seed = seed0 + s_
@@ -546,10 +583,12 @@ def main_mixed(args):
     log(f"[bench] kernels {kernel_table}")
 
     fsteps = args.fp64_steps if args.fp64_steps is not None else max(2, args.steps // 2)
-    log(f"[bench] FP64 GPU path on the same A: warmup 1, timed {fsteps} solves")
-    f_elapsed, f_infos, _ = run(fsteps, 1, 5000, True)
-    fp64_value = fsteps / f_elapsed
-    log(f"[bench] FP64 {fp64_value:.2f} solves/s; last info {f_infos[-1]}")
+    f_elapsed, f_infos, fp64_value = 0.0, [], None
+    if fsteps > 0:
+        log(f"[bench] FP64 GPU path on the same A: warmup 1, timed {fsteps} solves")
+        f_elapsed, f_infos, _ = run(fsteps, 1, 5000, True)
+        fp64_value = fsteps / f_elapsed
+        log(f"[bench] FP64 {fp64_value:.2f} solves/s; last info {f_infos[-1]}")
 
     plans = plans_dump(api, args)
     # dominant kernel: the pass over A with the larger total time
@@ -591,8 +630,8 @@ def main_mixed(args):
                                f"refinement, eps {eps:g}, l={l}, N={N}, one RHS, library-drawn SRFT per solve",
                    "m": m, "n": n, "l": l, "N": N, "eps": eps, "kappa": kappa},
         "fp64_value": fp64_value,
-        "fp64_ms_per_step": 1e3 * f_elapsed / fsteps,
-        "mixed_over_fp64": value / fp64_value,
+        "fp64_ms_per_step": 1e3 * f_elapsed / fsteps if fsteps else None,
+        "mixed_over_fp64": value / fp64_value if fp64_value else None,
         "fp64_config": "the same A, complex128 bulk (one-read passes over its column-major copy), FP64 "
                        "refinement with the same compensated residuals, inner solves to 6 digits (the fastest of 4, 6, 8, 10 and 12 measured on this workload), same eps",
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -605,7 +644,7 @@ def main_mixed(args):
         "rel_err_kind": "FP64 certificate sqrt(rho/xi) >= ||x - p|| / ||x|| of every timed solve; the same path "
                         "is compared with the longdouble-refined oracle at 2048 x 65536 and smaller in the GPU "
                         "tests (tests/test_gpu_large.py)",
-        "fp64_rel_err": max(i["cert_rel"] for i in f_infos),
+        "fp64_rel_err": max(i["cert_rel"] for i in f_infos) if f_infos else None,
         "statuses_ok": sum(1 for v in statuses if v == 0),
         "solves": len(statuses),
         "iters": [i["iters"] for i in infos],
@@ -613,7 +652,7 @@ def main_mixed(args):
         "fp64_iters": [i["iters"] for i in f_infos],
         "fp64_refine_steps": [i["refine_steps"] for i in f_infos],
         "stage_ms": infos[-1]["stage_ms"],
-        "fp64_stage_ms": f_infos[-1]["stage_ms"],
+        "fp64_stage_ms": f_infos[-1]["stage_ms"] if f_infos else None,
         "cpu_baseline": cpu,
         "plans": plans,
     }

@@ -91,7 +91,11 @@ typedef struct {
                             (each read overlaps the next batch), 8 for the
                             block and batched forms                          [0] */
   int32_t inner_digits;  /* mixed precision: decimal digits each low-precision
-                            inner solve gains                                 [4] */
+                            inner solve gains; 0 = automatic: 3 where the
+                            single-precision bulk accumulates in FP64 (the
+                            factor's diagonal spans more than 3e4; a
+                            refinement step then gains about two digits), else
+                            4                                                [0] */
   int32_t block;         /* several right-hand sides: 0 = automatic (block form
                             when nrhs >= 2 and the bulk runs in single
                             precision), 1 = one right-hand side at a time,

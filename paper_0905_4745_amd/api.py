@@ -154,7 +154,7 @@ class SolveOptions:
     max_iter: int = 1000
     max_refine: int = 40
     check_every: int = 0  # 0: library default (2 for one RHS, 8 for block/batched)
-    inner_digits: int = 4
+    inner_digits: int = 0  # 0: automatic (3 for an ill-conditioned single-precision bulk, else 4)
     block: int = 0  # several RHS: 0 automatic, 1 one at a time, 2 block form
     streams: int = 8  # batched: systems solved concurrently
     precond: int = 0  # 0: Cholesky of the FP64 Gram matrix when safe, else Householder; 1: Householder
