@@ -136,6 +136,11 @@ typedef struct {
                             a rank-deficient sketch before +1 is returned;
                             -1 = none, 0 = the default                        [2] */
   uint64_t seed;         /* library draw: the Philox key (see srft_draw)      [0] */
+  int32_t graph;         /* minnorm_solve_batched's fused form: 0 or 1 = each
+                            block of check_every lockstep iterations is
+                            captured once as a HIP graph and replayed; -1 =
+                            every kernel launched one by one                [0] */
+  int32_t reserved;
 } mn_opts;
 
 /* Per-solve report (host struct written by the library). */

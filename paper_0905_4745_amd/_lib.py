@@ -16,7 +16,7 @@ class MnOpts(C.Structure):
                 ("max_refine", C.c_int32), ("check_every", C.c_int32), ("inner_digits", C.c_int32),
                 ("block", C.c_int32), ("streams", C.c_int32), ("precond", C.c_int32),
                 ("tune", C.c_int32), ("batch_form", C.c_int32), ("refine", C.c_int32),
-                ("max_reseed", C.c_int32), ("seed", C.c_uint64)]
+                ("max_reseed", C.c_int32), ("seed", C.c_uint64), ("graph", C.c_int32), ("reserved", C.c_int32)]
 
 
 class MnInfo(C.Structure):

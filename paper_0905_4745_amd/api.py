@@ -163,6 +163,7 @@ class SolveOptions:
     refine: int = 0  # 1: FP64 refinement around an FP64 bulk too (compensated residuals when cond(A) u64 nears eps)
     max_reseed: int = 0  # library draw: redraws after a rank-deficient sketch (0 default 2, -1 none)
     seed: int = 0  # library draw: Philox key
+    graph: int = 0  # batched fused form: 0/1 replay captured iteration blocks, -1 launch every kernel
 
     def to_c(self):
         o = L.MnOpts()
@@ -180,6 +181,7 @@ class SolveOptions:
         o.refine = self.refine
         o.max_reseed = self.max_reseed
         o.seed = self.seed
+        o.graph = self.graph
         return o
 
 

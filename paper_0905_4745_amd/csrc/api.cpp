@@ -75,6 +75,7 @@ struct mn_handle_s {
   size_t host_stage_bytes = 0;
   int32_t* host_draw = nullptr;  // pinned staging of library-drawn indices
   size_t host_draw_n = 0;
+  hipStream_t cap_stream = nullptr;  // records HIP graphs of the batched iteration blocks
 };
 
 namespace {
@@ -1078,7 +1079,8 @@ bool opts_valid(const mn_opts& o) {
          o.block >= 0 && o.block <= 2 && o.streams > 0 && o.streams <= 64 && (o.precond == 0 || o.precond == 1) &&
          (o.tune == 0 || o.tune == 1) && (o.batch_form == 0 || o.batch_form == 1) &&
          o.check_every >= 0 && o.check_every <= 1024 && o.inner_digits >= 0 && o.inner_digits <= 12 &&
-         (o.refine == 0 || o.refine == 1) && o.max_reseed >= -1 && o.max_reseed <= 16;
+         (o.refine == 0 || o.refine == 1) && o.max_reseed >= -1 && o.max_reseed <= 16 && o.graph >= -1 &&
+         o.graph <= 1;
 }
 
 int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const void* A_lo,
@@ -1579,17 +1581,66 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       if (!(outer ? hst_state[i].outer_done : hst_state[i].done)) return false;
     return true;
   };
+  // One block of check_every lockstep iterations: per iteration the fused
+  // pass of every system and its CG step.  Once the column-major copies are
+  // written the block's launches are the same every time (the kernels read
+  // each system's stop flag), so the block is captured once as a HIP graph
+  // per parity of the r ping-pong and replayed (no memset or host transfer
+  // inside the captured region); opts.graph = -1 launches every kernel.
+  const int ce = o.check_every > 0 ? o.check_every : 8;
+  auto enqueue_block = [&](hipStream_t s) {
+    for (int it = 0; it < ce; ++it) {
+      const BLaunch gl[4] = {L(gramR[0]), L(gramR[1]), L(gramR[2]), L(gramR[3])};
+      // timing (mn_profile, launched blocks only): the fused passes of all
+      // systems with their partial-sum reduction, as one interval
+      const auto ev = s == st ? prof_pair(h, K_GRAM) : std::pair<hipEvent_t, hipEvent_t>{nullptr, nullptr};
+      if (ev.first) ck(hipEventRecord(ev.first, s));
+      ck(launch_b_gram(bulk, gl, L(gred), use_cm ? (at_written ? 2 : 1) : 0, s));
+      if (ev.second) ck(hipEventRecord(ev.second, s));
+      at_written = true;
+      ck(launch_b_cg(cplx, L(cgs), L(cgp), 0, 2, 0, par, cg_lds, s));
+      par ^= 1;
+    }
+  };
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  struct GraphsOut {
+    hipGraphExec_t* g;
+    ~GraphsOut() {
+      for (int k = 0; k < 2; ++k)
+        if (g[k]) (void)hipGraphExecDestroy(g[k]);
+    }
+  } graphs_out{gexec};
+  const bool use_graph = o.graph >= 0;
+  auto replay_block = [&]() {
+    const int p0 = par;
+    if (!gexec[p0]) {
+      // recorded on the handle's capture stream (the handle's own stream may
+      // be the null stream, which cannot be captured); nothing runs there
+      if (!h->cap_stream) ck(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+      hipStream_t cs = h->cap_stream;
+      hipGraph_t g = nullptr;
+      ck(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue_block(cs);
+      } catch (HipFail) {
+        (void)hipStreamEndCapture(cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      ck(hipStreamEndCapture(cs, &g));
+      const hipError_t e = hipGraphInstantiate(&gexec[p0], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      ck(e);
+      par = p0;  // the capture only recorded the block
+    }
+    ck(hipGraphLaunch(gexec[p0], st));
+    par = p0 ^ (ce & 1);
+  };
   auto inner_loop = [&]() {
     int guard = 0;
-    const int ce = o.check_every > 0 ? o.check_every : 8;
     while (true) {
-      for (int it = 0; it < ce; ++it) {
-        const BLaunch gl[4] = {L(gramR[0]), L(gramR[1]), L(gramR[2]), L(gramR[3])};
-        ck(launch_b_gram(bulk, gl, L(gred), use_cm ? (at_written ? 2 : 1) : 0, st));
-        at_written = true;
-        ck(launch_b_cg(cplx, L(cgs), L(cgp), 0, 2, 0, par, cg_lds, st));
-        par ^= 1;
-      }
+      if (use_graph && (!use_cm || at_written)) replay_block();
+      else enqueue_block(st);
       read_states();
       if (all_done(false)) break;
       if ((guard += ce) > o.max_iter + 2 * ce) break;  // the kernels cap iterations
@@ -1718,6 +1769,7 @@ int mn_destroy(mn_handle h) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : h->pool) (void)hipEventDestroy(e);
   if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
   return 0;
 }

@@ -117,7 +117,7 @@ def test_solve_argument_errors():
     bad = L.MnOpts()
     bad.alpha = 0.5
     assert call(opts=C.pointer(bad)) == -17
-    for field, value in (("refine", 2), ("max_reseed", -2), ("max_reseed", 17)):
+    for field, value in (("refine", 2), ("max_reseed", -2), ("max_reseed", 17), ("graph", 2), ("graph", -2)):
         o = L.MnOpts()
         setattr(o, field, value)
         assert call(opts=C.pointer(o)) == -17, field
@@ -142,8 +142,8 @@ def test_draw_argument_errors():
 
 
 def test_struct_layouts_match_header():
-    """The ctypes views have the header's sizes (options 64 bytes, report 88)."""
+    """The ctypes views have the header's sizes (options 72 bytes, report 88)."""
     L, _ = _lib()
-    assert C.sizeof(L.MnOpts) == 64
+    assert C.sizeof(L.MnOpts) == 72
     assert C.sizeof(L.MnInfo) == 88
     assert L.MnOpts.seed.offset == 56 and L.MnInfo.retries.offset == 80
