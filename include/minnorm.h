@@ -76,6 +76,21 @@ enum mn_dtype { MN_C128 = 0, MN_C64 = 1, MN_F64 = 2, MN_F32 = 3 };
 
 typedef struct mn_handle_s* mn_handle;
 
+/* The optional factor H = Theta Pi Z Theta~ Pi~ Z~ of the SRFT (Section 3,
+ * eqs. Rokhlin_trans and big_def), T = S F D H: device arrays of the caller.
+ * Theta = R_1 R_2 ... R_{N-1}, R_k rotating coordinates (k-1, k) (zero-based)
+ * by the block [[cos t_k, sin t_k], [-sin t_k, cos t_k]]; (Pi w)[j] =
+ * w[perm[j]]; Z = diag(zeta). */
+typedef struct {
+  const double* theta;    /* [N-1] t_1 .. t_{N-1} of Theta (radians)            */
+  const int32_t* perm;    /* [N] a permutation of 0 .. N-1                      */
+  const void* zeta;       /* [N] unit-modulus complex128 (complex dtypes) or
+                             +-1 float64 (real dtypes)                          */
+  const double* theta_t;  /* the same for Theta~, Pi~, Z~                       */
+  const int32_t* perm_t;
+  const void* zeta_t;
+} mn_hfactor;
+
 /* Options of minnorm_solve / minnorm_solve_batched.  A NULL pointer or a zero
  * field selects the default given in brackets. */
 typedef struct {
@@ -141,6 +156,10 @@ typedef struct {
                             captured once as a HIP graph and replayed; -1 =
                             every kernel launched one by one                [0] */
   int32_t reserved;
+  const mn_hfactor* hfactor;  /* host pointer: the SRFT's factor H (the sketch
+                            is then S F D H applied to the rows); NULL = H = I,
+                            the transform T = S F D.  Batched systems with H
+                            run on the concurrent lanes                  [NULL] */
 } mn_opts;
 
 /* Per-solve report (host struct written by the library). */
@@ -241,6 +260,18 @@ int mn_plans_count(mn_handle h);
 int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
                 int64_t N, int64_t l, const void* d, const int32_t* idx,
                 void* S, int64_t lds);
+
+/* Step 1 with the paper's full transform T = S F D H (eq. SRFT with H of
+ * eq. Rokhlin_trans): S(k, i) = (F (d o H conj(a_i)))[idx[k]] (real dtypes:
+ * Hartley transform of d o H a_i).  H is applied to each row as two stages
+ * (gather through the permutation times the phases, then the rotation chain
+ * as a scan of affine maps) before the transform.  Arguments as srft_sketch,
+ * with H (host struct of device arrays) at position 11.
+ * Errors as srft_sketch (S, lds are -12, -13), and -11 for H NULL, an array
+ * of it NULL, or (after a sync) a perm entry outside [0, N). */
+int srft_sketch_h(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                  int64_t N, int64_t l, const void* d, const int32_t* idx, const mn_hfactor* H,
+                  void* S, int64_t lds);
 
 /* srft_sketch without any device allocation, for callers that cannot
  * allocate: code under HIP graph capture, tight serving loops, harnesses that

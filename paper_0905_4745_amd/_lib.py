@@ -11,12 +11,18 @@ LIB_PATH = os.path.join(HERE, "libminnorm.so")
 MN_C128, MN_C64, MN_F64, MN_F32 = 0, 1, 2, 3
 
 
+class MnHFactor(C.Structure):
+    _fields_ = [("theta", C.c_void_p), ("perm", C.c_void_p), ("zeta", C.c_void_p),
+                ("theta_t", C.c_void_p), ("perm_t", C.c_void_p), ("zeta_t", C.c_void_p)]
+
+
 class MnOpts(C.Structure):
     _fields_ = [("alpha", C.c_double), ("stop_rule", C.c_int32), ("max_iter", C.c_int32),
                 ("max_refine", C.c_int32), ("check_every", C.c_int32), ("inner_digits", C.c_int32),
                 ("block", C.c_int32), ("streams", C.c_int32), ("precond", C.c_int32),
                 ("tune", C.c_int32), ("batch_form", C.c_int32), ("refine", C.c_int32),
-                ("max_reseed", C.c_int32), ("seed", C.c_uint64), ("graph", C.c_int32), ("reserved", C.c_int32)]
+                ("max_reseed", C.c_int32), ("seed", C.c_uint64), ("graph", C.c_int32), ("reserved", C.c_int32),
+                ("hfactor", C.POINTER(MnHFactor))]
 
 
 class MnInfo(C.Structure):
@@ -35,7 +41,7 @@ class MnInfo(C.Structure):
 
 EXPORTS = ["mn_create", "mn_destroy", "mn_set_stream", "mn_status_string", "mn_last_hip_error",
            "mn_workspace_bytes", "mn_profile", "mn_profile_read", "mn_plans_save", "mn_plans_load",
-           "mn_plans_count", "srft_draw", "srft_sketch", "srft_sketch_noalloc", "build_preconditioner",
+           "mn_plans_count", "srft_draw", "srft_sketch", "srft_sketch_h", "srft_sketch_noalloc", "build_preconditioner",
            "minnorm_solve", "minnorm_solve_batched"]
 
 _lib = None
@@ -78,6 +84,8 @@ def load():
     lib.srft_draw.restype = I32
     lib.srft_sketch.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, P, I64]
     lib.srft_sketch.restype = I32
+    lib.srft_sketch_h.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, C.POINTER(MnHFactor), P, I64]
+    lib.srft_sketch_h.restype = I32
     lib.srft_sketch_noalloc.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, P, I64]
     lib.srft_sketch_noalloc.restype = I32
     lib.build_preconditioner.argtypes = [P, I32, I64, I64, P, I64, P, I64]

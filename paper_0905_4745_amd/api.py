@@ -110,6 +110,40 @@ def srft_sketch(A, d, idx, N: int):
     return St.t()
 
 
+class HFactor:
+    """The SRFT's factor H = Theta Pi Z Theta~ Pi~ Z~ (device copies of its six arrays).
+
+    theta, theta_t: N-1 angles; perm, perm_t: permutations of range(N);
+    zeta, zeta_t: N unit-modulus complex phases (complex problems) or +-1 (real).
+    """
+
+    def __init__(self, theta, perm, zeta, theta_t, perm_t, zeta_t, complex_: bool = True, device=None):
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        zt = torch.complex128 if complex_ else torch.float64
+        self.t = [torch.as_tensor(theta, device=dev).to(torch.float64).contiguous(),
+                  torch.as_tensor(perm, device=dev).to(torch.int32).contiguous(),
+                  torch.as_tensor(zeta, device=dev).to(zt).contiguous(),
+                  torch.as_tensor(theta_t, device=dev).to(torch.float64).contiguous(),
+                  torch.as_tensor(perm_t, device=dev).to(torch.int32).contiguous(),
+                  torch.as_tensor(zeta_t, device=dev).to(zt).contiguous()]
+        self.c = L.MnHFactor(*[C.c_void_p(x.data_ptr()) for x in self.t])
+
+
+def srft_sketch_h(A, d, idx, N: int, H: HFactor):
+    """S = S F D H A* (Step 1 with the paper's full transform); (l, m) column-major view."""
+    code = _check_matrix(A)
+    m, n = A.shape
+    dt = _d_tensor(d, code, A.device)
+    it = _idx_tensor(idx, A.device)
+    l = it.numel()
+    St = torch.empty((m, l), dtype=A.dtype, device=A.device)
+    st = L.load().srft_sketch_h(_handle(A.device), code, m, n, _ptr(A), _ld(A, 0, n), int(N), l,
+                                _ptr(dt), _ptr(it), C.byref(H.c), _ptr(St), l)
+    if st != 0:
+        raise MinnormError("srft_sketch_h", st)
+    return St.t()
+
+
 def srft_sketch_noalloc(A, d, idx, N: int, S=None):
     """srft_sketch without device allocation inside the library (N <= 65536).
 
@@ -164,6 +198,7 @@ class SolveOptions:
     max_reseed: int = 0  # library draw: redraws after a rank-deficient sketch (0 default 2, -1 none)
     seed: int = 0  # library draw: Philox key
     graph: int = 0  # batched fused form: 0/1 replay captured iteration blocks, -1 launch every kernel
+    hfactor: "HFactor | None" = None  # the SRFT's factor H (None: H = I)
 
     def to_c(self):
         o = L.MnOpts()
@@ -182,6 +217,8 @@ class SolveOptions:
         o.max_reseed = self.max_reseed
         o.seed = self.seed
         o.graph = self.graph
+        if self.hfactor is not None:
+            o.hfactor = C.pointer(self.hfactor.c)
         return o
 
 

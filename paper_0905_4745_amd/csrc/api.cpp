@@ -221,7 +221,51 @@ struct SketchArena {
 
 void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, int64_t N, int64_t l,
                 const void* d, const int32_t* idx, const int32_t* inv, void* S, int64_t lds,
-                const mn_opts* o = nullptr, const SketchArena* ar = nullptr) {
+                const mn_opts* o = nullptr, const SketchArena* ar = nullptr, const mn_hfactor* H = nullptr);
+
+// Checks H's arrays (non-null, permutations in range; one stream sync).
+bool hfactor_valid(mn_handle h, const mn_hfactor* H, int64_t N) {
+  if (!H || !H->theta || !H->perm || !H->zeta || !H->theta_t || !H->perm_t || !H->zeta_t) return false;
+  int32_t* bad = (int32_t*)ws(h, "h_bad", 16);
+  ck(launch_fill0(bad, 16, h->stream));
+  ck(launch_h_check_perm(H->perm, N, bad, h->stream));
+  ck(launch_h_check_perm(H->perm_t, N, bad, h->stream));
+  ck(hipMemcpyAsync(h->host_flag, bad, 4, hipMemcpyDeviceToHost, h->stream));
+  ck(hipStreamSynchronize(h->stream));
+  return *h->host_flag == 0;
+}
+
+// Step 1 with T = S F D H: H applied to chunks of rows (two stages into two
+// N-wide row buffers), then the sketch of the transformed rows.
+void run_sketch_h(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, int64_t N, int64_t l,
+                  const void* d, const int32_t* idx, const int32_t* inv, void* S, int64_t lds, const mn_opts* o,
+                  const mn_hfactor* H) {
+  const int64_t es = dtype_size(dtype);
+  double* cs = (double*)ws(h, "h_cs", (size_t)(N * 16));
+  double* cs_t = (double*)ws(h, "h_cs_t", (size_t)(N * 16));
+  ck(launch_h_rotations(H->theta, N, cs, h->stream));
+  ck(launch_h_rotations(H->theta_t, N, cs_t, h->stream));
+  // rows per chunk: 128 MB per buffer
+  int64_t chunk = std::max<int64_t>(1, ((int64_t)128 << 20) / (N * es));
+  chunk = std::min(chunk, m);
+  void* T1 = ws(h, "h_rows1", (size_t)(chunk * N * es));
+  void* T2 = ws(h, "h_rows2", (size_t)(chunk * N * es));
+  for (int64_t r0 = 0; r0 < m; r0 += chunk) {
+    const int64_t rows = std::min(chunk, m - r0);
+    const void* Ar = (const char*)A + r0 * lda * es;
+    ck(launch_h_rows(dtype, true, Ar, lda, n, T1, N, rows, N, H->perm_t, H->zeta_t, cs_t, h->stream));
+    ck(launch_h_rows(dtype, false, T1, N, N, T2, N, rows, N, H->perm, H->zeta, cs, h->stream));
+    run_sketch(h, dtype, rows, N, T2, N, N, l, d, idx, inv, (char*)S + r0 * lds * es, lds, o);
+  }
+}
+
+void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, int64_t N, int64_t l,
+                const void* d, const int32_t* idx, const int32_t* inv, void* S, int64_t lds,
+                const mn_opts* o, const SketchArena* ar, const mn_hfactor* H) {
+  if (H) {
+    run_sketch_h(h, dtype, m, n, A, lda, N, l, d, idx, inv, S, lds, o, H);
+    return;
+  }
   const bool single = is_single(dtype);
   const int64_t ces = single ? 8 : 16;
   SketchArgs a{};
@@ -1119,6 +1163,7 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     memset(info, 0, sizeof(*info));
   }
   h->events = info != nullptr;
+  if (o.hfactor && !hfactor_valid(h, o.hfactor, N)) return -17;
   ev_record(h, 0);
   // the fused pass reads 16-byte vectors: an unaligned bulk row start is
   // re-laid once with a padded leading dimension (one pass over the bulk copy)
@@ -1156,7 +1201,7 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     }
     int32_t* inv = nullptr;
     if (!prepare_idx(h, idx, l, N, &inv)) return -16;
-    run_sketch(h, c.bulk, m, n, c.Ab, c.ldab, N, l, d, idx, inv, S, l, &o);
+    run_sketch(h, c.bulk, m, n, c.Ab, c.ldab, N, l, d, idx, inv, S, l, &o, nullptr, o.hfactor);
     ev_record(h, 1);
     // Step 2's R: Cholesky of the FP64 Gram matrix when that is accurate,
     // Householder QR of S otherwise
@@ -1256,7 +1301,7 @@ int64_t a256(int64_t v) { return (v + 255) / 256 * 256; }
 // The fused form takes one bulk type for all systems: either no system has a
 // single-precision copy or every system has one (a mix goes to the lanes).
 bool fused_batch_ok(int batch, const int64_t* m, const void* const* A_lo, const mn_opts& o) {
-  if (o.precond != 0 || o.batch_form == 1 || batch < 2) return false;
+  if (o.precond != 0 || o.batch_form == 1 || batch < 2 || o.hfactor) return false;
   for (int i = 0; i < batch; ++i)
     if (m[i] > kGramMaxRows) return false;
   if (A_lo)
@@ -1925,6 +1970,33 @@ int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
     int32_t* inv = nullptr;
     if (!prepare_idx(h, idx, l, N, &inv)) return -10;
     run_sketch(h, dtype, m, n, A, lda, N, l, d, idx, inv, S, lds);
+    ck(hipGetLastError());
+  } catch (HipFail f) {
+    return fail_hip(f.e);
+  }
+  return 0;
+}
+
+int srft_sketch_h(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, int64_t N, int64_t l,
+                  const void* d, const int32_t* idx, const mn_hfactor* H, void* S, int64_t lds) {
+  if (!h) return -1;
+  if (dtype < 0 || dtype > 3) return -2;
+  if (m < 1) return -3;
+  if (n < 1) return -4;
+  if (!A) return -5;
+  if (lda < n) return -6;
+  if (!is_pow2(N) || N < n || N > (1 << 22)) return -7;
+  if (l < 1 || l > N) return -8;
+  if (!d) return -9;
+  if (!idx) return -10;
+  if (!H || !H->theta || !H->perm || !H->zeta || !H->theta_t || !H->perm_t || !H->zeta_t) return -11;
+  if (!S) return -12;
+  if (lds < l) return -13;
+  try {
+    if (!hfactor_valid(h, H, N)) return -11;
+    int32_t* inv = nullptr;
+    if (!prepare_idx(h, idx, l, N, &inv)) return -10;
+    run_sketch(h, dtype, m, n, A, lda, N, l, d, idx, inv, S, lds, nullptr, nullptr, H);
     ck(hipGetLastError());
   } catch (HipFail f) {
     return fail_hip(f.e);

@@ -53,6 +53,16 @@ int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng);
 hipError_t launch_sketch(int dtype, const SketchArgs& a, hipStream_t st);
 int sketch_max_log2n(int dtype);  // largest log2(N) the four-step supports
 hipError_t launch_inverse_map(const int32_t* idx, int64_t l, int64_t N, int32_t* inv, int32_t* bad, hipStream_t st);
+// The SRFT factor H = Theta Pi Z Theta~ Pi~ Z~ (hfactor.hip): rotation
+// table cs (N pairs (cos, sin) of theta_k at index k), perm range check, and
+// one stage "Theta Pi Z" on rows (first: the source is A, conjugated for
+// complex data; else an earlier stage's rows, the result stored conjugated
+// for complex data, ready for the sketch kernels).
+hipError_t launch_h_rotations(const double* theta, int64_t N, double* cs, hipStream_t st);
+hipError_t launch_h_check_perm(const int32_t* perm, int64_t N, int32_t* bad, hipStream_t st);
+hipError_t launch_h_rows(int dtype, bool first, const void* src, int64_t ld_src, int64_t n_src, void* dst,
+                         int64_t ld_dst, int64_t rows, int64_t N, const int32_t* perm, const void* zeta,
+                         const double* cs, hipStream_t st);
 // Twiddle table of the sketch (W_N^k, k < N, then the four-step splits'
 // compact tables): twiddle_entries(N) complex entries of the compute precision.
 int64_t twiddle_entries(int64_t N);

@@ -12,6 +12,7 @@ from .gen import (  # noqa: F401
     next_pow2,
     sketch_width,
     draw_srft,
+    draw_hfactor,
     make_gaussian,
     make_svd,
     make_row_scaled,

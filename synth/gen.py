@@ -84,6 +84,24 @@ def draw_srft(N: int, l: int, seed: int, real: bool = False):
     return d, idx
 
 
+def draw_hfactor(N: int, seed: int, real: bool = False):
+    """Random quantities of the SRFT's factor H = Theta Pi Z Theta~ Pi~ Z~ (Section 3).
+
+    Returns (theta, perm, zeta, theta_t, perm_t, zeta_t): angles of the two
+    rotation chains (N - 1 each, uniform on [0, 2 pi)), two uniformly random
+    permutations of range(N) (int32), and two diagonals uniform on the unit
+    circle (complex128), or random signs +-1 (float64) when real is True.
+    """
+    g = rng_for(seed)
+    out = []
+    for _ in range(2):
+        theta = 2.0 * np.pi * g.random(N - 1)
+        perm = g.permutation(N).astype(np.int32)
+        zeta = np.where(g.random(N) < 0.5, -1.0, 1.0) if real else np.exp(2j * np.pi * g.random(N))
+        out.append((theta, perm, zeta))
+    return out[0] + out[1]
+
+
 def make_gaussian(m: int, n: int, seed: int, nrhs: int = 1, complex_: bool = True):
     """A and b with i.i.d. standard Gaussian entries (complex: N(0,1/2) parts)."""
     g = rng_for(seed)

@@ -142,8 +142,30 @@ def test_draw_argument_errors():
 
 
 def test_struct_layouts_match_header():
-    """The ctypes views have the header's sizes (options 72 bytes, report 88)."""
+    """The ctypes views have the header's sizes (options 80 bytes, report 88, H 48)."""
     L, _ = _lib()
-    assert C.sizeof(L.MnOpts) == 72
+    assert C.sizeof(L.MnOpts) == 80 and C.sizeof(L.MnHFactor) == 48 and L.MnOpts.hfactor.offset == 72
     assert C.sizeof(L.MnInfo) == 88
     assert L.MnOpts.seed.offset == 56 and L.MnInfo.retries.offset == 80
+
+
+def test_sketch_h_argument_errors():
+    L, lib = _lib()
+    h = _Dummy().ptr
+    p = C.c_void_p(16)
+    H = L.MnHFactor(p, p, p, p, p, p)
+    ok = dict(dtype=0, m=4, n=10, A=p, lda=10, N=16, l=8, d=p, idx=p, H=C.pointer(H), S=p, lds=8)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.srft_sketch_h(h, a["dtype"], a["m"], a["n"], a["A"], a["lda"], a["N"], a["l"], a["d"],
+                                 a["idx"], a["H"], a["S"], a["lds"])
+
+    assert lib.srft_sketch_h(None, 0, 4, 10, p, 10, 16, 8, p, p, C.pointer(H), p, 8) == -1
+    assert call(dtype=5) == -2
+    assert call(N=12) == -7
+    assert call(H=None) == -11
+    Hbad = L.MnHFactor(p, None, p, p, p, p)
+    assert call(H=C.pointer(Hbad)) == -11
+    assert call(S=None) == -12
+    assert call(lds=7) == -13
