@@ -261,6 +261,26 @@ int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
                 int64_t N, int64_t l, const void* d, const int32_t* idx,
                 void* S, int64_t lds);
 
+/* Steps 2-3 made explicit (Section 4, eqs. lineq and nonminnorm), a check
+ * and export path beside minnorm_solve, which folds them into Step 4: with
+ * S = T A* and its triangular factor R as the solve computes them,
+ *   z = S R^{-1} R^{-*} b   the minimal-norm solution of S* z = b (eq. lineq)
+ *   c = T* z                (eq. nonminnorm; c has N entries, the rows of A
+ *                            being zero-padded to N)
+ * By Lemma 5.1, A c = b (c's first n entries) and ||c|| = ||z||.
+ *   A [m x n, dtype, row-major, lda]; b [m, FP64 wide type]; N, l, d, idx as
+ *   in srft_sketch (m < l <= N)
+ *   z [l, FP64 wide type (complex128 / float64)]  device, written
+ *   c [N, FP64 wide type]                          device, written
+ *   checks [3] optional host output: ||A c - b|| / ||b|| with A c summed in
+ *   FP64 on the device, ||z||, ||c||.
+ * Returns 0, +1 (rank-deficient sketch), +3, +4, or -k: -3 m < 1, m >= n or
+ * m > 8192; -4 n; -5 A; -6 lda; -7 b; -8 N; -9 l <= m or l > N; -10 d;
+ * -11 idx (also after a sync: not increasing in [0, N)); -12 z; -13 c. */
+int minnorm_steps23(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
+                    const void* b, int64_t N, int64_t l, const void* d, const int32_t* idx,
+                    void* z, void* c, double* checks);
+
 /* Step 1 with the paper's full transform T = S F D H (eq. SRFT with H of
  * eq. Rokhlin_trans): S(k, i) = (F (d o H conj(a_i)))[idx[k]] (real dtypes:
  * Hartley transform of d o H a_i).  H is applied to each row as two stages

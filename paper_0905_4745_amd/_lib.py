@@ -42,7 +42,7 @@ class MnInfo(C.Structure):
 EXPORTS = ["mn_create", "mn_destroy", "mn_set_stream", "mn_status_string", "mn_last_hip_error",
            "mn_workspace_bytes", "mn_profile", "mn_profile_read", "mn_plans_save", "mn_plans_load",
            "mn_plans_count", "srft_draw", "srft_sketch", "srft_sketch_h", "srft_sketch_noalloc", "build_preconditioner",
-           "minnorm_solve", "minnorm_solve_batched"]
+           "minnorm_solve", "minnorm_solve_batched", "minnorm_steps23"]
 
 _lib = None
 
@@ -84,6 +84,8 @@ def load():
     lib.srft_draw.restype = I32
     lib.srft_sketch.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, P, I64]
     lib.srft_sketch.restype = I32
+    lib.minnorm_steps23.argtypes = [P, I32, I64, I64, P, I64, P, I64, I64, P, P, P, P, C.POINTER(C.c_double)]
+    lib.minnorm_steps23.restype = I32
     lib.srft_sketch_h.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, C.POINTER(MnHFactor), P, I64]
     lib.srft_sketch_h.restype = I32
     lib.srft_sketch_noalloc.argtypes = [P, I32, I64, I64, P, I64, I64, I64, P, P, P, I64]

@@ -110,6 +110,28 @@ def srft_sketch(A, d, idx, N: int):
     return St.t()
 
 
+def minnorm_steps23(A, b, d, idx, N: int):
+    """Steps 2-3 made explicit: (z, c, checks) with z the minimal-norm solution of
+    S* z = b, c = T* z (N entries; A c = b by Lemma 5.1), and checks =
+    (||A c - b|| / ||b||, ||z||, ||c||) computed on the device."""
+    code = _check_matrix(A)
+    m, n = A.shape
+    wide = _WIDE[code]
+    if b.dtype != wide or not b.is_cuda or b.dim() != 1 or b.numel() != m or (b.stride(0) != 1 and m > 1):
+        raise ValueError(f"b must be a contiguous device {wide} vector of {m} entries")
+    dt = _d_tensor(d, code, A.device)
+    it = _idx_tensor(idx, A.device)
+    l = it.numel()
+    z = torch.empty(l, dtype=wide, device=A.device)
+    c = torch.empty(int(N), dtype=wide, device=A.device)
+    chk = (C.c_double * 3)()
+    st = L.load().minnorm_steps23(_handle(A.device), code, m, n, _ptr(A), _ld(A, 0, n), _ptr(b), int(N), l,
+                                  _ptr(dt), _ptr(it), _ptr(z), _ptr(c), chk)
+    if st != 0:
+        raise MinnormError("minnorm_steps23", st)
+    return z, c, {"resid_rel": chk[0], "z_norm": chk[1], "c_norm": chk[2]}
+
+
 class HFactor:
     """The SRFT's factor H = Theta Pi Z Theta~ Pi~ Z~ (device copies of its six arrays).
 

@@ -1977,6 +1977,87 @@ int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   return 0;
 }
 
+int minnorm_steps23(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, const void* b,
+                    int64_t N, int64_t l, const void* d, const int32_t* idx, void* z, void* c, double* checks) {
+  if (!h) return -1;
+  if (dtype < 0 || dtype > 3) return -2;
+  if (m < 1 || m >= n || m > kMaxRows) return -3;
+  if (n < 2) return -4;
+  if (!A) return -5;
+  if (lda < n) return -6;
+  if (!b) return -7;
+  if (!is_pow2(N) || N < n || N > (1 << 22)) return -8;
+  if (l <= m || l > N) return -9;
+  if (!d) return -10;
+  if (!idx) return -11;
+  if (!z) return -12;
+  if (!c) return -13;
+  hipStream_t st = h->stream;
+  const bool cplx = is_complex(dtype);
+  const int wdt = cplx ? MN_C128 : MN_F64;
+  const int64_t W = wide_size(dtype);
+  try {
+    // Steps 1-2 as the solve takes them: sketch, then R (Gram route when
+    // accepted, else Householder) and X = R^{-1} in FP64
+    int32_t* inv = nullptr;
+    if (!prepare_idx(h, idx, l, N, &inv)) return -11;
+    void* S = ws(h, "S", (size_t)(l * m * dtype_size(dtype)));
+    run_sketch(h, dtype, m, n, A, lda, N, l, d, idx, inv, S, l);
+    const int64_t ldxi = rinv_ld(m);
+    void* X = ws(h, "Xinv", (size_t)(ldxi * ldxi * W));
+    void* R64 = ws(h, "R64", (size_t)(m * m * W));
+    if (!gram_factor(h, dtype, l, m, S, l, R64, nullptr, X, ldxi)) {
+      void* R = ws(h, "R", (size_t)(m * m * dtype_size(dtype)));
+      const int rs = run_qr(h, dtype, l, m, S, l, R, m);
+      if (rs != MN_OK) return rs;
+      ck(launch_rinv(dtype, R, m, m, X, st));
+    }
+    // Step 2: z = S X X* b;  Step 3: c = T* z
+    void* g = ws(h, "st_g", (size_t)(m * W));
+    void* u = ws(h, "st_u", (size_t)(m * W));
+    ck(launch_st_solve(cplx, X, ldxi, m, b, g, u, st));
+    void* y = ws(h, "st_y", (size_t)(N * W));
+    ck(launch_fill0(y, N * W, st));
+    ck(launch_st_z(dtype, S, l, l, m, u, idx, z, y, st));
+    void* ones = ws(h, "st_ones", (size_t)(N * W));
+    int32_t* iota = (int32_t*)ws(h, "st_iota", (size_t)(N * 4));
+    ck(launch_st_ones_iota(cplx, N, ones, iota, st));
+    int32_t* inv_all = nullptr;
+    if (!prepare_idx(h, iota, N, N, &inv_all)) return MN_HIP_ERROR;
+    void* t = ws(h, "st_t", (size_t)(N * W));
+    run_sketch(h, wdt, 1, N, y, N, N, N, ones, iota, inv_all, t, N);
+    ck(launch_st_c(cplx, t, d, N, c, st));
+    if (checks) {
+      // ||A c - b|| / ||b|| (FP64 products of A's stored values), ||z||, ||c||
+      FwdArgs fa{};
+      fa.A = A;
+      fa.lda = lda;
+      fa.m = m;
+      fa.n = n;
+      fa.w = c;
+      fa.qpart = ws(h, "qpart", (size_t)((kMaxChunks > kGramMaxWg ? kMaxChunks : kGramMaxWg) * m * W));
+      int chunks = 1;
+      fa.chunks_out = &chunks;
+      ck(launch_gemv_fwd(dtype, true, fa, st));
+      double* out = (double*)ws(h, "st_out", 64);
+      ck(launch_st_resid(cplx, fa.qpart, chunks, m, b, out, st));
+      double* nz = out + 2;
+      ck(launch_st_resid(cplx, nullptr, 0, l, z, nz, st));   // ||z||^2 (as ||z - 0||^2)
+      ck(launch_st_resid(cplx, nullptr, 0, N, c, nz + 2, st));
+      ck(hipMemcpyAsync(h->host_diag, out, 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+      ck(hipStreamSynchronize(st));
+      checks[0] = h->host_diag[1] > 0 ? std::sqrt(h->host_diag[0] / h->host_diag[1]) : std::sqrt(h->host_diag[0]);
+      checks[1] = std::sqrt(h->host_diag[3]);
+      checks[2] = std::sqrt(h->host_diag[5]);
+    } else {
+      ck(hipStreamSynchronize(st));
+    }
+  } catch (HipFail f) {
+    return fail_hip(f.e);
+  }
+  return 0;
+}
+
 int srft_sketch_h(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda, int64_t N, int64_t l,
                   const void* d, const int32_t* idx, const mn_hfactor* H, void* S, int64_t lds) {
   if (!h) return -1;

@@ -63,6 +63,18 @@ hipError_t launch_h_check_perm(const int32_t* perm, int64_t N, int32_t* bad, hip
 hipError_t launch_h_rows(int dtype, bool first, const void* src, int64_t ld_src, int64_t n_src, void* dst,
                          int64_t ld_dst, int64_t rows, int64_t N, const int32_t* perm, const void* zeta,
                          const double* cs, hipStream_t st);
+// Steps 2-3 made explicit (steps23.hip): g = X* b and u = X g (X = R^{-1},
+// FP64); z = S u with z scattered to y (N entries, zeroed before) at idx;
+// d' = 1 and idx' = 0 .. N-1; c from the one-row transform t of y; the
+// FP64 residual norms ||b - A c||^2, ||b||^2 from gemv_fwd chunk partials.
+hipError_t launch_st_solve(bool cplx, const void* X, int64_t ldx, int64_t m, const void* b, void* g, void* u,
+                           hipStream_t st);
+hipError_t launch_st_z(int dtype, const void* S, int64_t lds, int64_t l, int64_t m, const void* u, const int32_t* idx,
+                       void* z, void* y, hipStream_t st);
+hipError_t launch_st_ones_iota(bool cplx, int64_t N, void* ones, int32_t* iota, hipStream_t st);
+hipError_t launch_st_c(bool cplx, const void* t, const void* d, int64_t N, void* c, hipStream_t st);
+hipError_t launch_st_resid(bool cplx, const void* qpart, int chunks, int64_t m, const void* b, double* out,
+                           hipStream_t st);
 // Twiddle table of the sketch (W_N^k, k < N, then the four-step splits'
 // compact tables): twiddle_entries(N) complex entries of the compute precision.
 int64_t twiddle_entries(int64_t N);

@@ -169,3 +169,28 @@ def test_sketch_h_argument_errors():
     assert call(H=C.pointer(Hbad)) == -11
     assert call(S=None) == -12
     assert call(lds=7) == -13
+
+
+def test_steps23_argument_errors():
+    L, lib = _lib()
+    h = _Dummy().ptr
+    p = C.c_void_p(16)
+    ok = dict(dtype=0, m=4, n=10, A=p, lda=10, b=p, N=16, l=8, d=p, idx=p, z=p, c=p)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.minnorm_steps23(h, a["dtype"], a["m"], a["n"], a["A"], a["lda"], a["b"], a["N"], a["l"], a["d"],
+                                   a["idx"], a["z"], a["c"], None)
+
+    assert lib.minnorm_steps23(None, 0, 4, 10, p, 10, p, 16, 8, p, p, p, p, None) == -1
+    assert call(dtype=4) == -2
+    assert call(m=10) == -3
+    assert call(A=None) == -5
+    assert call(lda=9) == -6
+    assert call(b=None) == -7
+    assert call(N=24) == -8
+    assert call(l=4) == -9
+    assert call(d=None) == -10
+    assert call(idx=None) == -11
+    assert call(z=None) == -12
+    assert call(c=None) == -13
