@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libminnorm.so")
-SOURCES = ["api.cpp", "fft.hip", "qr.hip", "gemv.hip", "pcg.hip", "block.hip", "chol.hip", "herk.hip", "draw.hip", "noalloc.hip", "hfactor.hip", "steps23.hip"]
+SOURCES = ["api.cpp", "fft.hip", "qr.hip", "gemv.hip", "pcg.hip", "block.hip", "chol.hip", "herk.hip", "draw.hip", "noalloc.hip", "hfactor.hip", "steps23.hip", "resid.hip"]
 ARCH = os.environ.get("MN_OFFLOAD_ARCH", "gfx950")
 
 

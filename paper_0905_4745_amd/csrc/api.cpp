@@ -293,17 +293,20 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   // elements per workgroup instead of 4096, bits 17-18: four-step split,
   // bits 19-20: kept outputs only (pruned) with B = 16, 8, 4 columns per
   // block (codes 1, 2, 3; 0 = full four-step), bits 21-24: log2 of the
-  // pruned form's column groups per row
+  // pruned form's column groups per row, bit 25: the pruned form's wide
+  // workgroup (one per CU, N2 = 16 x its threads / B)
   static const int pruned_b[4] = {0, 16, 8, 4};
+  const int wide_tpb = sketch_pruned_wide_tpb(dtype);
   auto run = [&](int pl) {
     const int mb = pl & 0xFFFF;
     a.wg_elems = (pl >> 16) & 1 ? 2048 : 4096;
     a.split = (pl >> 17) & 3;
     a.pruned_b = pruned_b[(pl >> 19) & 3];
     a.pruned_ng = 1 << ((pl >> 21) & 15);
+    a.pruned_tpb = (pl >> 25) & 1 ? wide_tpb : 256;
     int64_t per_row = N;  // intermediate elements per row
     if (a.pruned_b) {
-      const int ng = sketch_pruned_groups(dtype, N, l, a.pruned_b, a.pruned_ng);
+      const int ng = sketch_pruned_groups(dtype, N, l, a.pruned_b, a.pruned_ng, a.pruned_tpb);
       if (ng < 1) a.pruned_b = 0;  // not applicable to this shape: full four-step
       else per_row = ng > 1 ? (int64_t)ng * l : 0;
     }
@@ -326,11 +329,22 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   // groups per row for 512 workgroups (two per CU).  For single-precision
   // sketches with 2048 < l <= 8192 it is a tuning candidate only: at
   // 2048 x 262144 (l = 8192) it measured no faster than the full four-step.
+  // For larger l the wide form with B = 16 (N2 = 512), groups enough for
+  // 256 workgroups: at 2048 x 262144 complex64, l = 8192, it measured 6.68
+  // ms against 9.35 ms for the full four-step (B = 8: 7.17, B = 4: 8.41; the
+  // strided column loads, 16 B-wide runs at B = 4, not the outer sum, set
+  // the pace); at 4096 x 131072, l = 16384, B = 8 measured best (8.87 ms
+  // against 9.32), a tuning candidate.
   int mb = 64;
   if (l <= 2048 && sketch_pruned_groups(dtype, N, l, 16, 1) > 0) {
     int lg = 0;
     while ((m << lg) < 512 && lg < 10) ++lg;
     mb = 64 | (1 << 19) | (lg << 21);
+  } else if (sketch_pruned_groups(dtype, N, l, 16, 1, wide_tpb) > 0) {
+    int lg = 0;
+    while ((m << lg) < 256 && lg < 10 && sketch_pruned_groups(dtype, N, l, 16, 1 << (lg + 1), wide_tpb) == (1 << (lg + 1)))
+      ++lg;
+    mb = 64 | (1 << 19) | (lg << 21) | (1 << 25);
   }
   const std::string key = plan_key("sketch_chunk_mb", dtype, m, N, 0);
   if (o) {
@@ -341,12 +355,13 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
       for (int c : {64, 128, 256, 512})
         if (sp || c != 64) cands.push_back((sp << 17) | c);
     cands.push_back(0x10000 | 512);
-    for (int bc : {1, 2, 3})
-      for (int lg : {0, 1, 2, 3, 4})
-        if (sketch_pruned_groups(dtype, N, l, pruned_b[bc], 1 << lg) == (1 << lg)) {
-          const int c = 64 | (bc << 19) | (lg << 21);
-          if (c != cands[0]) cands.push_back(c);
-        }
+    for (int wide : {0, 1})
+      for (int bc : {1, 2, 3})
+        for (int lg : {0, 1, 2, 3, 4})
+          if (sketch_pruned_groups(dtype, N, l, pruned_b[bc], 1 << lg, wide ? wide_tpb : 256) == (1 << lg)) {
+            const int c = 64 | (bc << 19) | (lg << 21) | (wide << 25);
+            if (c != cands[0]) cands.push_back(c);
+          }
     mb = plan_get(h, *o, key, cands, run);
   }
   else plan_find(h, key, &mb);
@@ -774,6 +789,28 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
     ck(launch_zero(is_complex(c.dtype), y_outer, m, h->stream));
     const double inner_eps = std::pow(10.0, -(double)c.o.inner_digits);
     init_state(h, v.st, c, 2, inner_eps, c.o.max_iter);
+    // compensated residuals for m <= kGramTallMaxRows: one pass over a
+    // column-major copy of the problem matrix (written once per solve, where
+    // it fits in half the free memory) instead of an adjoint and a forward
+    // pass; its column sums are x = A* y of the residual's y, kept for Step 5
+    const int64_t rldt = rup(m, gram_tall_ld_multiple());
+    bool fused_res = false;
+    if (c.comp && m <= kGramTallMaxRows) {
+      size_t fr = 0, tot = 0;
+      fused_res = hipMemGetInfo(&fr, &tot) == hipSuccess &&
+                  (double)(rldt * n * dtype_size(c.dtype)) <= 0.5 * (double)fr;
+    }
+    constexpr int kResG = 512;
+    void* res_at = nullptr;
+    void* res_x = nullptr;
+    void* res_part = nullptr;
+    if (fused_res) {
+      res_at = ws(h, "res_at", (size_t)(rldt * n * dtype_size(c.dtype)));
+      res_x = ws(h, "res_x", (size_t)(n * W + 64));
+      res_part = ws(h, "res_part", (size_t)(resid_part_elems(m, kResG) * W));
+      ck(launch_colmajor(c.dtype, c.A, c.lda, m, n, res_at, rldt, h->stream));
+    }
+    bool x_current = false;  // res_x holds A* y_outer of the current y_outer
     for (int outer = 0; outer <= c.o.max_refine + 1; ++outer) {
       AdjArgs aa{};
       aa.A = c.A;
@@ -792,7 +829,11 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
       fa.qpart = v.qpart;
       int chunks = 1;
       fa.chunks_out = &chunks;
-      if (c.comp) {
+      if (fused_res) {
+        ck(launch_resid_tall(c.dtype, res_at, rldt, m, n, y_outer, res_x, res_part, kResG, qdd, h->stream));
+        x_current = true;
+        cg_start(c, v, b, qdd, 1, y_outer);
+      } else if (c.comp) {
         // b - A (A* y_outer) with double-double accumulation: the sums cancel
         // to about cond(A) times below their terms
         ck(launch_gemv_adj_dd(c.dtype, aa, h->stream));
@@ -807,6 +848,7 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
       if (h->host_state->outer_done) break;
       cg_loop(c, v, b, c.o.max_iter);
       ck(launch_refine_update(is_complex(c.dtype), y_outer, v.y, m, v.st, h->stream));
+      x_current = false;
     }
     ev_record(h, 4);
     AdjArgs aa{};
@@ -817,7 +859,8 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
     aa.u = y_outer;
     aa.w = x;
     aa.part = v.part;
-    if (c.comp) ck(launch_gemv_adj_dd(c.dtype, aa, h->stream));
+    if (x_current) ck(hipMemcpyAsync(x, res_x, (size_t)(n * W), hipMemcpyDeviceToDevice, h->stream));
+    else if (c.comp) ck(launch_gemv_adj_dd(c.dtype, aa, h->stream));
     else ck(launch_gemv_adj(c.dtype, true, aa, h->stream));
     ev_record(h, 5);
     read_state(h, v.st);

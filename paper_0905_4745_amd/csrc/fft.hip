@@ -435,13 +435,16 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, in
 //   Z_{n1}[k2] = sum_{n2} v[n1 + N1 n2] W_{N2}^{n2 k2}
 // since W_N^{N1 n2 k} = W_{N2}^{n2 k}.  A workgroup takes one row and G
 // blocks of B consecutive n1: it transforms the block's B columns in LDS
-// (N2 = 4096 / B points each; the first radix-16 stage runs on the loaded
-// registers) and adds the block's share of the outer sum to one register
-// accumulator per kept output.  Neither the N2 x N1 intermediate nor the
-// discarded outputs reach memory; the outer sum costs l N1 multiply-adds per
-// row, so this form pays while l / N2 is small.  The factors W_N^{n1 k} of
+// (N2 = 16 TPB / B points each: 4096 / B with 256 threads, 8192 / B with
+// the wide 512-thread form, 2048 at B = 4; the first radix-16 stage
+// runs on the loaded registers) and adds the block's share of the outer sum
+// to one register accumulator per kept output.  Neither the N2 x N1
+// intermediate nor the discarded outputs reach memory; the outer sum costs
+// l N1 = l N / N2 multiply-adds per row, so with N2 near l (the wide form)
+// the row costs O(N log N2) for the column transforms plus about 8 N flops
+// for the outer sum: O(N log l).  The factors W_N^{n1 k} of
 // one block come from one table entry and a recurrence in n1.  Thread slot
-// q = tid + 256 u takes kept output order[q]: the order groups outputs of
+// q = tid + TPB u takes kept output order[q]: the order groups outputs of
 // equal k mod N2 (k_sketch_order), so the lanes of a wave read a few LDS
 // addresses (broadcast) rather than 64 scattered ones.  With one column
 // group per row (grid.x = 1) the workgroup writes S; otherwise the group's
@@ -463,23 +466,36 @@ template <typename V> struct PhaseOf { using type = typename std::conditional<VT
 
 template <int X> __host__ __device__ constexpr int ilog2c() { return X <= 1 ? 0 : 1 + ilog2c<X / 2>(); }
 
-// bk.x = column group, bk.y = row within the launch, bk.gx = groups per row
-template <typename V, typename C, int B, int KPT>
+// Whether the kept-outputs-only form keeps its stage twiddles W_{N2}^k in LDS
+// after the B columns: with 256 threads where two workgroups still fit a CU
+// (B = 16, 8); with wider workgroups (one per CU) where the 160 KB hold both.
+template <typename C, int B, int TPB> __host__ __device__ constexpr bool pruned_tw_lds() {
+  constexpr int N2 = TPB * 16 / B;
+  constexpr int64_t cols = (int64_t)B * (N2 + N2 / 16 + 1) * (int64_t)sizeof(C);
+  constexpr int64_t with_tw = cols + (int64_t)N2 * (int64_t)sizeof(C);
+  // wide form: where the table still leaves two workgroups to a CU, or where
+  // the columns alone already take one CU
+  return TPB == 256 ? B >= 8 : (with_tw <= 80 * 1024 || (cols > 80 * 1024 && with_tw <= 160 * 1024));
+}
+
+// bk.x = column group, bk.y = row within the launch, bk.gx = groups per row.
+// TPB threads hold 16 elements each: N2 = 16 TPB / B points per column.
+template <typename V, typename C, int B, int KPT, int TPB = 256>
 __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t row0,
                                                        int64_t rows, int64_t n, int N1, int G, FftPlan pl2,
                                                        const void* __restrict__ dv, const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ order, int64_t l,
                                                        const C* __restrict__ tw, V* __restrict__ S, int64_t lds,
                                                        C* __restrict__ P, typename VT<C>::real scale) {
-  constexpr int N2 = 4096 / B;
-  constexpr int LR = N2 / 16;  // = 256 / B: butterflies per column in a radix-16 stage
+  constexpr int N2 = TPB * 16 / B;
+  constexpr int LR = N2 / 16;  // = TPB / B: butterflies per column in a radix-16 stage
   constexpr int lgB = ilog2c<B>(), lgLR = ilog2c<LR>();
   constexpr int Lp = N2 + N2 / 16 + 1;
   using D = typename PhaseOf<V>::type;
   using R = typename VT<C>::real;
-  // the stage twiddles W_{N2}^k (k < N2) sit in LDS after the B columns,
-  // where they fit two workgroups to a CU (B = 16, 8); B = 4 reads W_N
-  constexpr bool TW_LDS = B >= 8;
+  // the stage twiddles W_{N2}^k (k < N2) sit in LDS after the B columns
+  // where they fit (pruned_tw_lds); otherwise the stages read W_N
+  constexpr bool TW_LDS = pruned_tw_lds<C, B, TPB>();
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
   const unsigned Nm = (unsigned)N1 * (unsigned)N2 - 1u;
@@ -487,7 +503,7 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
   const V* row = A + i * lda;
   C* tws = sm + B * Lp;
   if constexpr (TW_LDS) {
-    for (int k = threadIdx.x; k < N2; k += 256) tws[k] = tw[(unsigned)k * (unsigned)N1];
+    for (int k = threadIdx.x; k < N2; k += TPB) tws[k] = tw[(unsigned)k * (unsigned)N1];
   }
   const C* twst = TW_LDS ? tws : tw;
   const int twm = TW_LDS ? 1 : N1;
@@ -506,7 +522,7 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
   unsigned kq[KPT];
 #pragma unroll
   for (int u = 0; u < KPT; ++u) {
-    const int q = tid + 256 * u;
+    const int q = tid + TPB * u;
     kq[u] = q < l ? (unsigned)idx[order[q]] & Nm : 0u;
   }
   // the empty asm makes k opaque inside the block loop, so the table reads
@@ -590,7 +606,7 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
   }
 #pragma unroll
   for (int u = 0; u < KPT; ++u) {
-    const int q = tid + 256 * u;
+    const int q = tid + TPB * u;
     if (q < l) {
       const int64_t s = order[q];
       if (bk.gx == 1) S[s + i * lds] = out_value<V, C>(acc[u], scale);
@@ -598,36 +614,47 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
     }
   }
 }
-template <typename V, typename C, int B, int KPT>
-__global__ void __launch_bounds__(256, 2) k_sketch_pruned(const V* __restrict__ A, int64_t lda, int64_t row0, int64_t rows,
-                                                       int64_t n, int N1, int G, FftPlan pl2,
-                                                       const void* __restrict__ dv, const int32_t* __restrict__ idx,
-                                                       const int32_t* __restrict__ order, int64_t l,
-                                                       const C* __restrict__ tw, V* __restrict__ S, int64_t lds,
-                                                       C* __restrict__ P, typename VT<C>::real scale) {
-  k_sketch_pruned_body<V, C, B, KPT>(bk_hw(), A, lda, row0, rows, n, N1, G, pl2, dv, idx, order, l, tw, S, lds, P,
-                                     scale);
+template <typename V, typename C, int B, int KPT, int TPB = 256>
+__global__ void __launch_bounds__(TPB, TPB == 256 ? 2 : 1) k_sketch_pruned(
+    const V* __restrict__ A, int64_t lda, int64_t row0, int64_t rows, int64_t n, int N1, int G, FftPlan pl2,
+    const void* __restrict__ dv, const int32_t* __restrict__ idx, const int32_t* __restrict__ order, int64_t l,
+    const C* __restrict__ tw, V* __restrict__ S, int64_t lds, C* __restrict__ P, typename VT<C>::real scale) {
+  k_sketch_pruned_body<V, C, B, KPT, TPB>(bk_hw(), A, lda, row0, rows, n, N1, G, pl2, dv, idx, order, l, tw, S, lds,
+                                          P, scale);
 }
 
 // order[0 .. l) = a permutation of 0 .. l that groups the kept outputs by
 // idx[s] mod N2 (counting sort on the residue; the order inside a group is
 // whatever the LDS atomics give, which changes no result).  One workgroup of
-// 1024 threads; N2 <= 1024.
+// 1024 threads; N2 <= kOrderMaxN2 (the counts live in LDS; their exclusive
+// prefix sum runs in parallel: each thread sums a run of N2 / 1024 counts,
+// the run totals are scanned across the workgroup, then each run is filled).
+constexpr int kOrderMaxN2 = 16384;
 __device__ __forceinline__ void k_sketch_order_body(const int32_t* __restrict__ idx, int64_t l, int N2,
                                                     int32_t* __restrict__ order) {
-  __shared__ int cnt[1024];
+  __shared__ int cnt[kOrderMaxN2];
+  __shared__ int tot[1024];
   const int tid = threadIdx.x;
-  cnt[tid] = 0;
+  for (int r = tid; r < N2; r += 1024) cnt[r] = 0;
   __syncthreads();
   for (int64_t s = tid; s < l; s += 1024) atomicAdd(&cnt[idx[s] & (N2 - 1)], 1);
   __syncthreads();
-  if (tid == 0) {
-    int run = 0;
-    for (int r = 0; r < N2; ++r) {
-      const int c = cnt[r];
-      cnt[r] = run;
-      run += c;
-    }
+  const int per = (N2 + 1023) / 1024, r0 = tid * per;
+  int run = 0;
+  for (int r = r0; r < r0 + per && r < N2; ++r) run += cnt[r];
+  tot[tid] = run;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan of the run totals
+    const int v = tid >= d ? tot[tid - d] : 0;
+    __syncthreads();
+    tot[tid] += v;
+    __syncthreads();
+  }
+  int base = tot[tid] - run;  // exclusive
+  for (int r = r0; r < r0 + per && r < N2; ++r) {
+    const int c = cnt[r];
+    cnt[r] = base;
+    base += c;
   }
   __syncthreads();
   for (int64_t s = tid; s < l; s += 1024) order[atomicAdd(&cnt[idx[s] & (N2 - 1)], 1)] = (int32_t)s;
@@ -726,15 +753,32 @@ template <typename C> static int fft_batch(int L, int elems = 4096) {
 
 // Column groups per row of the pruned four-step for B columns per block and
 // ng groups asked for (clamped to 1 .. N1 / B), or 0 where it does not apply:
-// more kept outputs than accumulators fit (eight per thread in FP64, l <=
-// 2048; thirty-two in FP32, l <= 8192), N not a multiple of N2 = 4096 / B, or
-// a block larger than the LDS limit.
-template <typename C> static int pruned_groups(int64_t N, int64_t l, int B, int ng) {
-  const int64_t lmax = std::is_same<C, cf>::value ? 8192 : 2048;
-  if (!(B == 16 || B == 8 || B == 4) || l < 1 || l > lmax) return 0;
-  const int64_t N2 = 4096 / B;
-  if (N <= N2 || N % N2) return 0;
-  if (((int64_t)B * lds_stride((int)N2) + (B >= 8 ? N2 : 0)) * (int64_t)sizeof(C) > lds_limit()) return 0;
+// more kept outputs than accumulators fit (eight per thread in FP64,
+// thirty-two in FP32, times the workgroup's threads), N not a multiple of
+// N2 = 16 tpb / B, or a block larger than the LDS limit.
+// workgroup widths of the kept-outputs-only form: 256 threads, and a wide
+// form of 512 threads (8192 elements, so that N2 reaches 2048 at B = 4; two
+// workgroups to a CU in single precision, one in double).  1024 threads
+// would cap a thread at 128 registers and spill.
+template <typename C> static constexpr int pruned_wide_tpb() { return 512; }
+
+template <typename C> static size_t pruned_smem(int B, int tpb) {
+  const int N2 = tpb * 16 / B;
+  const int64_t cols = (int64_t)B * lds_stride(N2) * (int64_t)sizeof(C);
+  const int64_t with_tw = cols + (int64_t)N2 * (int64_t)sizeof(C);
+  bool twl;
+  if (tpb == 256) twl = B >= 8;
+  else twl = with_tw <= 80 * 1024 || (cols > 80 * 1024 && with_tw <= 160 * 1024);
+  return (size_t)(twl ? with_tw : cols);
+}
+
+template <typename C> static int pruned_groups(int64_t N, int64_t l, int B, int ng, int tpb = 256) {
+  if (tpb != 256 && tpb != pruned_wide_tpb<C>()) return 0;
+  const int64_t kmax = std::is_same<C, cf>::value ? 32 : 8;  // accumulators per thread
+  if (!(B == 16 || B == 8 || B == 4) || l < 1 || l > kmax * tpb) return 0;
+  const int64_t N2 = (int64_t)tpb * 16 / B;
+  if (N2 > kOrderMaxN2 || N <= N2 || N % N2) return 0;
+  if ((int64_t)pruned_smem<C>(B, tpb) > lds_limit()) return 0;
   const int64_t nb = N / N2 / B;  // blocks per row
   if (nb < 1) return 0;
   int g = ng < 1 ? 1 : ng;
@@ -742,46 +786,61 @@ template <typename C> static int pruned_groups(int64_t N, int64_t l, int B, int 
   return g;
 }
 
-template <typename V, typename C, int B>
+template <typename V, typename C, int B, int KPT, int TPB>
+static void pruned_go(dim3 grid, size_t smb, hipStream_t st, const V* A, int64_t lda, int64_t row0, int64_t rows,
+                      int64_t n, int N1, int G, FftPlan pl2, const void* d, const int32_t* idx, const int32_t* order,
+                      int64_t l, const C* tw, V* S, int64_t lds, C* P, typename VT<C>::real scale) {
+  allow_lds(k_sketch_pruned<V, C, B, KPT, TPB>, smb);
+  hipLaunchKernelGGL((k_sketch_pruned<V, C, B, KPT, TPB>), grid, dim3(TPB), smb, st, A, lda, row0, rows, n, N1, G, pl2,
+                     d, idx, order, l, tw, S, lds, P, scale);
+}
+
+template <typename V, typename C, int B, int TPB>
 static void pruned_launch(int kpt, dim3 grid, size_t smb, hipStream_t st, const V* A, int64_t lda, int64_t row0,
                           int64_t rows, int64_t n, int N1, int G, FftPlan pl2, const void* d, const int32_t* idx,
                           const int32_t* order, int64_t l, const C* tw, V* S, int64_t lds, C* P,
                           typename VT<C>::real scale) {
-  if (kpt == 2) {
-    allow_lds(k_sketch_pruned<V, C, B, 2>, smb);
-    hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 2>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2, d,
-                       idx, order, l, tw, S, lds, P, scale);
-  } else if (kpt == 4) {
-    allow_lds(k_sketch_pruned<V, C, B, 4>, smb);
-    hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 4>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2, d,
-                       idx, order, l, tw, S, lds, P, scale);
-  } else if (kpt == 8) {
-    allow_lds(k_sketch_pruned<V, C, B, 8>, smb);
-    hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 8>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2, d,
-                       idx, order, l, tw, S, lds, P, scale);
-  } else if constexpr (std::is_same<C, cf>::value) {
+  if (kpt == 2)
+    pruned_go<V, C, B, 2, TPB>(grid, smb, st, A, lda, row0, rows, n, N1, G, pl2, d, idx, order, l, tw, S, lds, P, scale);
+  else if (kpt == 4)
+    pruned_go<V, C, B, 4, TPB>(grid, smb, st, A, lda, row0, rows, n, N1, G, pl2, d, idx, order, l, tw, S, lds, P, scale);
+  else if (kpt == 8)
+    pruned_go<V, C, B, 8, TPB>(grid, smb, st, A, lda, row0, rows, n, N1, G, pl2, d, idx, order, l, tw, S, lds, P, scale);
+  else if constexpr (std::is_same<C, cf>::value) {
     // FP32 accumulators: up to 32 kept outputs per thread
-    if (kpt == 16) {
-      allow_lds(k_sketch_pruned<V, C, B, 16>, smb);
-      hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 16>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2,
-                         d, idx, order, l, tw, S, lds, P, scale);
-    } else {
-      allow_lds(k_sketch_pruned<V, C, B, 32>, smb);
-      hipLaunchKernelGGL((k_sketch_pruned<V, C, B, 32>), grid, dim3(256), smb, st, A, lda, row0, rows, n, N1, G, pl2,
-                         d, idx, order, l, tw, S, lds, P, scale);
-    }
+    if (kpt == 16)
+      pruned_go<V, C, B, 16, TPB>(grid, smb, st, A, lda, row0, rows, n, N1, G, pl2, d, idx, order, l, tw, S, lds, P,
+                                  scale);
+    else
+      pruned_go<V, C, B, 32, TPB>(grid, smb, st, A, lda, row0, rows, n, N1, G, pl2, d, idx, order, l, tw, S, lds, P,
+                                  scale);
   }
+}
+
+template <typename V, typename C, int B>
+static void pruned_launch_tpb(int tpb, int kpt, dim3 grid, size_t smb, hipStream_t st, const V* A, int64_t lda,
+                              int64_t row0, int64_t rows, int64_t n, int N1, int G, FftPlan pl2, const void* d,
+                              const int32_t* idx, const int32_t* order, int64_t l, const C* tw, V* S, int64_t lds,
+                              C* P, typename VT<C>::real scale) {
+  if (tpb == 256)
+    pruned_launch<V, C, B, 256>(kpt, grid, smb, st, A, lda, row0, rows, n, N1, G, pl2, d, idx, order, l, tw, S, lds, P,
+                                scale);
+  else
+    pruned_launch<V, C, B, pruned_wide_tpb<C>()>(kpt, grid, smb, st, A, lda, row0, rows, n, N1, G, pl2, d, idx, order,
+                                                 l, tw, S, lds, P, scale);
 }
 
 template <typename V, typename C>
 static hipError_t sketch_pruned_impl(const SketchArgs& a, hipStream_t st) {
   const int N = (int)a.N;
   const int B = a.pruned_b;
-  const int ng = pruned_groups<C>(a.N, a.l, B, a.pruned_ng);
+  const int tpb = a.pruned_tpb > 0 ? a.pruned_tpb : 256;
+  const int ng = pruned_groups<C>(a.N, a.l, B, a.pruned_ng, tpb);
   if (ng < 1) return hipErrorInvalidValue;
-  const int N2 = 4096 / B, N1 = N / N2;
+  const int N2 = tpb * 16 / B, N1 = N / N2;
   const int G = N1 / (B * ng);
-  const int kpt = a.l <= 512 ? 2 : (a.l <= 1024 ? 4 : (a.l <= 2048 ? 8 : (a.l <= 4096 ? 16 : 32)));
+  const int64_t per_thread = ceil_div(a.l, tpb);
+  const int kpt = per_thread <= 2 ? 2 : (per_thread <= 4 ? 4 : (per_thread <= 8 ? 8 : (per_thread <= 16 ? 16 : 32)));
   const FftPlan pl2 = make_plan(N2);
   using R = typename VT<C>::real;
   const R scale = (R)(1.0 / sqrt((double)N));
@@ -789,7 +848,7 @@ static hipError_t sketch_pruned_impl(const SketchArgs& a, hipStream_t st) {
   const V* A = reinterpret_cast<const V*>(a.A);
   V* S = reinterpret_cast<V*>(a.S);
   C* P = reinterpret_cast<C*>(a.work);
-  const size_t smb = ((size_t)B * lds_stride(N2) + (B >= 8 ? (size_t)N2 : 0)) * sizeof(C);
+  const size_t smb = pruned_smem<C>(B, tpb);
   // one group per row: no partial sums, every row in one launch
   const int64_t per = ng == 1 ? a.m : a.chunk_rows;
   if (per < 1 || (ng > 1 && P == nullptr) || a.order == nullptr) return hipErrorInvalidValue;
@@ -798,13 +857,13 @@ static hipError_t sketch_pruned_impl(const SketchArgs& a, hipStream_t st) {
     const int64_t rows = (a.m - r0) < per ? (a.m - r0) : per;
     const dim3 grid((unsigned)ng, (unsigned)rows);
     if (B == 16)
-      pruned_launch<V, C, 16>(kpt, grid, smb, st, A, a.lda, r0, rows, a.n, N1, G, pl2, a.d, a.idx, a.order, a.l, tw, S, a.lds,
+      pruned_launch_tpb<V, C, 16>(tpb, kpt, grid, smb, st, A, a.lda, r0, rows, a.n, N1, G, pl2, a.d, a.idx, a.order, a.l, tw, S, a.lds,
                               P, scale);
     else if (B == 8)
-      pruned_launch<V, C, 8>(kpt, grid, smb, st, A, a.lda, r0, rows, a.n, N1, G, pl2, a.d, a.idx, a.order, a.l, tw, S, a.lds,
+      pruned_launch_tpb<V, C, 8>(tpb, kpt, grid, smb, st, A, a.lda, r0, rows, a.n, N1, G, pl2, a.d, a.idx, a.order, a.l, tw, S, a.lds,
                              P, scale);
     else
-      pruned_launch<V, C, 4>(kpt, grid, smb, st, A, a.lda, r0, rows, a.n, N1, G, pl2, a.d, a.idx, a.order, a.l, tw, S, a.lds,
+      pruned_launch_tpb<V, C, 4>(tpb, kpt, grid, smb, st, A, a.lda, r0, rows, a.n, N1, G, pl2, a.d, a.idx, a.order, a.l, tw, S, a.lds,
                              P, scale);
     if (ng > 1)
       hipLaunchKernelGGL((k_sketch_fold<V, C>), dim3((unsigned)ceil_div(a.l, 256), (unsigned)rows), dim3(256), 0, st,
@@ -867,11 +926,13 @@ static hipError_t sketch_impl(const SketchArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng) {
+int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng, int tpb) {
   const bool sp = dtype == 1 || dtype == 3;
   if (N <= (sp ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>())) return 0;  // one-workgroup transform
-  return sp ? pruned_groups<cf>(N, l, B, ng) : pruned_groups<cd>(N, l, B, ng);
+  return sp ? pruned_groups<cf>(N, l, B, ng, tpb) : pruned_groups<cd>(N, l, B, ng, tpb);
 }
+
+int sketch_pruned_wide_tpb(int dtype) { return (dtype == 1 || dtype == 3) ? pruned_wide_tpb<cf>() : pruned_wide_tpb<cd>(); }
 
 int sketch_max_log2n(int dtype) {
   const int L = (dtype == 1 || dtype == 3) ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>();

@@ -873,6 +873,22 @@ bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda) {
 
 int64_t gram_tall_ld_multiple() { return 256; }
 
+hipError_t launch_colmajor(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, void* At, int64_t ldt,
+                           hipStream_t st) {
+  if (ldt < m || ldt % 64 != 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)ceil_div(n, 64), (unsigned)(ldt / 64));
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL((k_colmajor<cd>), grid, dim3(256), 0, st, (const cd*)A, lda, m, n, (cd*)At, ldt); break;
+    case 1: hipLaunchKernelGGL((k_colmajor<cf>), grid, dim3(256), 0, st, (const cf*)A, lda, m, n, (cf*)At, ldt); break;
+    case 2: hipLaunchKernelGGL((k_colmajor<double>), grid, dim3(256), 0, st, (const double*)A, lda, m, n, (double*)At,
+                               ldt); break;
+    case 3: hipLaunchKernelGGL((k_colmajor<float>), grid, dim3(256), 0, st, (const float*)A, lda, m, n, (float*)At,
+                               ldt); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st) {
   switch (dtype) {
     case 0: return gram_impl<cd, cd, cd>(a, st);

@@ -42,14 +42,17 @@ struct SketchArgs {
   int64_t chunk_rows;
   int wg_elems;         // four-step: elements per workgroup (4096 or 2048; 0 = 4096)
   int split;            // four-step: N2 = 2^(floor(log2 N / 2) - split), split 0..2
-  int pruned_b;         // > 0: kept outputs only, B = 16, 8 or 4 columns per block (N2 = 4096 / B)
+  int pruned_b;         // > 0: kept outputs only, B = 16, 8 or 4 columns per block (N2 = 16 pruned_tpb / B)
   int pruned_ng;        // pruned: column groups per row (partial sums in work when > 1)
+  int pruned_tpb;       // pruned: threads per workgroup (256, or sketch_pruned_wide_tpb: N2 = 16 tpb / B)
   int32_t* order;       // pruned: l entries of scratch (kept outputs grouped by k mod N2)
 };
 // column groups per row the pruned four-step uses for (B, ng), 0 if it does
 // not apply to this (dtype, N, l); work then holds ng * chunk_rows * l
 // elements of the compute type
-int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng);
+int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng, int tpb = 256);
+// the wide workgroup of the kept-outputs-only form (512 threads)
+int sketch_pruned_wide_tpb(int dtype);
 hipError_t launch_sketch(int dtype, const SketchArgs& a, hipStream_t st);
 int sketch_max_log2n(int dtype);  // largest log2(N) the four-step supports
 hipError_t launch_inverse_map(const int32_t* idx, int64_t l, int64_t N, int32_t* inv, int32_t* bad, hipStream_t st);
@@ -177,6 +180,17 @@ bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda);
 // multiple of this (rows m .. ldt - 1 of the copy are zero)
 int64_t gram_tall_ld_multiple();
 hipError_t launch_gram(int dtype, const GramArgs& a, hipStream_t st);
+// Column-major copy At (ldt x n, ldt a multiple of 64 >= m, rows m .. ldt - 1
+// zero) of a row-major m x n matrix of type dtype.
+hipError_t launch_colmajor(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, void* At, int64_t ldt,
+                           hipStream_t st);
+// The refinement residual's product q = A (A* y) in one compensated pass over
+// the column-major copy At of the problem matrix (resid.hip), m <=
+// kGramTallMaxRows; x_out (n, optional) receives A* y; part holds
+// resid_part_elems(m, G) entries of the wide type.
+int64_t resid_part_elems(int64_t m, int G);
+hipError_t launch_resid_tall(int dtype, const void* At, int64_t ldt, int64_t m, int64_t n, const void* y, void* x_out,
+                             void* part, int G, void* q, hipStream_t st);
 
 // CG state in device memory, written by workgroup 0 of the CG kernels.
 struct PcgState {

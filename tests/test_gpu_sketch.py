@@ -149,3 +149,39 @@ def test_sketch_pruned_variants(m, n, N, l, kind, bcode, lgng, tmp_path):
     err = _colerr(S.astype(ref.dtype), ref)
     say(f"  col rel err {err:.2e}")
     assert err <= 20 * u * max(np.log2(N), 1)
+
+
+@pytest.mark.parametrize("m,n,N,l", [(3, 50000, 65536, 3000), (2, 100000, 131072, 8192), (4, 262144, 262144, 8192),
+                                     (2, 131072, 131072, 16384), (5, 30000, 32768, 600), (3, 70000, 131072, 4096)])
+@pytest.mark.parametrize("kind", ["c128", "c64", "f64", "f32"])
+@pytest.mark.parametrize("bcode,lgng", [(1, 0), (2, 1), (3, 0), (3, 2)])
+def test_sketch_pruned_wide_variants(m, n, N, l, kind, bcode, lgng, tmp_path):
+    """The kept-outputs-only form with the wide 512-thread workgroup (N2 =
+    8192 / B points per column: N2 = 2048 at B = 4, so that the outer sum
+    costs about 8 N flops per row at l = 8192) forced through a loaded plan:
+    the oracle's sketch to the same bar, for every B, with and without
+    partial sums, up to l = 16384 in single precision (32 kept outputs per
+    thread) and l = 4096 in double (FP64 takes the full four-step beyond)."""
+    import json
+    import torch
+    from paper_0905_4745_amd import api
+    say(f"sketch pruned wide b{bcode} ng{1 << lgng} {kind} m={m} n={n} N={N} l={l}")
+    real = kind.startswith("f")
+    g = np.random.default_rng(m * 17 + n + l)
+    A = g.standard_normal((m, n)) if real else synth.complex_gaussian(g, (m, n))
+    d, idx = synth.draw_srft(N, l, seed=N + 7 * l, real=real)
+    tdt = {"c128": torch.complex128, "c64": torch.complex64, "f64": torch.float64, "f32": torch.float32}[kind]
+    dcode = {"c128": 0, "c64": 1, "f64": 2, "f32": 3}[kind]
+    plan = 64 | (bcode << 19) | (lgng << 21) | (1 << 25)
+    path = tmp_path / "plans.json"
+    path.write_text(json.dumps({"format": "minnorm-plans-1",
+                                "plans": {f"sketch_chunk_mb/{dcode}/{m}/{N}/0": plan}, "best_ms": {}}))
+    api.plans_load(str(path))
+    At = to_dev(A, tdt)
+    A_used = to_np(At).astype(np.float64 if real else np.complex128)
+    S = to_np(api.srft_sketch(At, d, idx, N))
+    ref = oracle.sketch_real(A_used, d, idx, N) if real else oracle.sketch(A_used, d, idx, N)
+    u = U32 if kind in ("c64", "f32") else U64
+    err = _colerr(S.astype(ref.dtype), ref)
+    say(f"  col rel err {err:.2e}")
+    assert err <= 20 * u * max(np.log2(N), 1)
