@@ -576,7 +576,7 @@ def cpu_baseline_classical(A_dev, b_dev, m, n):
 # valid while the source and the plan are the measured ones
 MEASURED_TRAFFIC_MIXED = {
     "k_gram_tall": {"bytes": 4312112000.0, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-                    "sha256": "7db483bead65faa2d15612b37276c5d2dd7c7b56fc14f4a84d2b354c217bf28b",
+                    "sha256": "13676a381cfa603c9c3c450ceddc9673be69505945e570e0c54adec64b79551d",
                     "plan_key": "gram/1/2048/262144/1", "plan": 524800},
 }
 

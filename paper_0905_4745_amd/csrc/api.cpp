@@ -809,6 +809,12 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
       res_x = ws(h, "res_x", (size_t)(n * W + 64));
       res_part = ws(h, "res_part", (size_t)(resid_part_elems(m, kResG) * W));
       ck(launch_colmajor(c.dtype, c.A, c.lda, m, n, res_at, rldt, h->stream));
+      // FP64 refinement around the FP64 matrix itself: the inner passes read
+      // the same column-major copy (same leading dimension, zero padding)
+      if (c.Ab == c.A && c.bulk == c.dtype && m > kGramMaxRows && rldt == rup(m, gram_tall_ld_multiple())) {
+        v.at = res_at;
+        v.at_valid = true;
+      }
     }
     bool x_current = false;  // res_x holds A* y_outer of the current y_outer
     for (int outer = 0; outer <= c.o.max_refine + 1; ++outer) {

@@ -604,27 +604,47 @@ __global__ void __launch_bounds__(TPB) k_gram_tall(const V* __restrict__ At, int
 }
 
 // Column-major copy of a row-major m x n matrix: At[c ldt + r] = A[r lda + c]
-// for r < m, zero for m <= r < ldt.  64 x 64 tiles through LDS (one padding
+// for r < m, zero for m <= r < ldt.  Tiles of 64 rows x TW columns (1 KB of a
+// row: TW = 64 complex128 or 128 complex64 entries) through LDS (one padding
 // column against bank conflicts); rows are read and columns written as
-// contiguous runs by consecutive threads.  grid (ceil(n / 64), ldt / 64),
-// 256 threads.
+// contiguous 1 KB and 512-1024 B runs by consecutive threads, and each thread
+// issues all its loads of a tile before storing any.  grid (ceil(n / TW),
+// ldt / 64), 256 threads.
 template <typename V>
 __global__ void __launch_bounds__(256) k_colmajor(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
                                                   V* __restrict__ At, int64_t ldt) {
-  __shared__ V tile[64][65];
-  const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-#pragma unroll 4
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int64_t r = r0 + rr, c = c0 + tx;
-    tile[rr][tx] = (r < m && c < n) ? ld_once(A + r * lda + c) : vzero<V>();
+  constexpr int TW = 1024 / (int)sizeof(V) < 64 ? 1024 / (int)sizeof(V) : (1024 / (int)sizeof(V) > 128 ? 128 : 1024 / (int)sizeof(V));
+  constexpr int PER = 64 * TW / 256;  // entries per thread
+  __shared__ V tile[64][TW + 1];
+  const int64_t c0 = (int64_t)blockIdx.x * TW, r0 = (int64_t)blockIdx.y * 64;
+  const int tid = threadIdx.x;
+  V v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u, rr = e / TW, cc = e % TW;
+    const int64_t r = r0 + rr, c = c0 + cc;
+    v[u] = (r < m && c < n) ? ld_once(A + r * lda + c) : vzero<V>();
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u;
+    tile[e / TW][e % TW] = v[u];
   }
   __syncthreads();
-#pragma unroll 4
-  for (int cc = ty; cc < 64; cc += 4) {
-    const int64_t c = c0 + cc, r = r0 + tx;
-    if (c < n) At[c * ldt + r] = tile[tx][cc];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u, cc = e / 64, rr = e % 64;
+    v[u] = tile[rr][cc];
   }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = tid + 256 * u, cc = e / 64, rr = e % 64;
+    const int64_t c = c0 + cc;
+    if (c < n) At[c * ldt + r0 + rr] = v[u];
+  }
+}
+template <typename V> constexpr int colmajor_tw() {
+  return 1024 / (int)sizeof(V) < 64 ? 1024 / (int)sizeof(V) : (1024 / (int)sizeof(V) > 128 ? 128 : 1024 / (int)sizeof(V));
 }
 
 // First level of the sum over workgroup partials: q8[gr * m + i] = sum of
@@ -826,8 +846,9 @@ template <typename V, typename C, typename U>
 static hipError_t gram_tall_go(const GramArgs& a, hipStream_t st) {
   if (a.m > kGramTallMaxRows || a.ldt < a.m || a.ldt % gram_tall_ld_multiple() != 0) return hipErrorInvalidValue;
   if (a.at_mode == 1) {
-    hipLaunchKernelGGL((k_colmajor<V>), dim3((unsigned)ceil_div(a.n, 64), (unsigned)(a.ldt / 64)), dim3(256), 0, st,
-                       reinterpret_cast<const V*>(a.A), a.lda, a.m, a.n, reinterpret_cast<V*>(a.At), a.ldt);
+    hipLaunchKernelGGL((k_colmajor<V>), dim3((unsigned)ceil_div(a.n, colmajor_tw<V>()), (unsigned)(a.ldt / 64)),
+                       dim3(256), 0, st, reinterpret_cast<const V*>(a.A), a.lda, a.m, a.n, reinterpret_cast<V*>(a.At),
+                       a.ldt);
   }
   const int64_t G = a.max_wg > 0 && a.max_wg <= kGramMaxWg ? a.max_wg : 512;
   const int code = a.tall & 3;
@@ -876,14 +897,16 @@ int64_t gram_tall_ld_multiple() { return 256; }
 hipError_t launch_colmajor(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, void* At, int64_t ldt,
                            hipStream_t st) {
   if (ldt < m || ldt % 64 != 0) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)ceil_div(n, 64), (unsigned)(ldt / 64));
+  const unsigned gy = (unsigned)(ldt / 64);
   switch (dtype) {
-    case 0: hipLaunchKernelGGL((k_colmajor<cd>), grid, dim3(256), 0, st, (const cd*)A, lda, m, n, (cd*)At, ldt); break;
-    case 1: hipLaunchKernelGGL((k_colmajor<cf>), grid, dim3(256), 0, st, (const cf*)A, lda, m, n, (cf*)At, ldt); break;
-    case 2: hipLaunchKernelGGL((k_colmajor<double>), grid, dim3(256), 0, st, (const double*)A, lda, m, n, (double*)At,
-                               ldt); break;
-    case 3: hipLaunchKernelGGL((k_colmajor<float>), grid, dim3(256), 0, st, (const float*)A, lda, m, n, (float*)At,
-                               ldt); break;
+    case 0: hipLaunchKernelGGL((k_colmajor<cd>), dim3((unsigned)ceil_div(n, colmajor_tw<cd>()), gy), dim3(256), 0, st,
+                               (const cd*)A, lda, m, n, (cd*)At, ldt); break;
+    case 1: hipLaunchKernelGGL((k_colmajor<cf>), dim3((unsigned)ceil_div(n, colmajor_tw<cf>()), gy), dim3(256), 0, st,
+                               (const cf*)A, lda, m, n, (cf*)At, ldt); break;
+    case 2: hipLaunchKernelGGL((k_colmajor<double>), dim3((unsigned)ceil_div(n, colmajor_tw<double>()), gy), dim3(256),
+                               0, st, (const double*)A, lda, m, n, (double*)At, ldt); break;
+    case 3: hipLaunchKernelGGL((k_colmajor<float>), dim3((unsigned)ceil_div(n, colmajor_tw<float>()), gy), dim3(256),
+                               0, st, (const float*)A, lda, m, n, (float*)At, ldt); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
