@@ -173,7 +173,18 @@ typedef struct {
   float stage_ms[8];     /* sketch, qr, cg, final product, refine, -, -, total  */
   int32_t retries;       /* library draw: redraws after a rank-deficient sketch
                             (the draw that was used has draw number retries) */
-  int32_t reserved;
+  int32_t factor;        /* Step 2's R: 1 = Cholesky of the FP64 Gram matrix
+                            S* S, 2 = Householder QR of S                     */
+  double kappa_hat;      /* lower estimate of cond(R) = cond(S): the larger of
+                            max|R_ii| / min|R_ii| and, where the Gram route's
+                            Cholesky ran through, the power-step estimate
+                            sqrt(||R R*|| ||R^{-1} R^{-*}||) from 4 steps each;
+                            it selects the Gram route (delta = sqrt(l) u64
+                            kappa_hat^2 <= 0.1, or <= u32 kappa_hat for a
+                            single-precision sketch; the plain solve's stopping
+                            test then runs at eps sqrt(1 - delta)),
+                            compensated residuals and FP64 accumulation of a
+                            single-precision bulk                            */
 } mn_info;
 
 /* Handle: owns the stream binding and a device workspace reused across calls.

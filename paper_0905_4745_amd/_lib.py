@@ -29,12 +29,13 @@ class MnInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("refine_steps", C.c_int32),
                 ("nrhs_done", C.c_int32), ("cert_rel", C.c_double), ("rho0", C.c_double),
                 ("rho", C.c_double), ("xi", C.c_double), ("stage_ms", C.c_float * 8),
-                ("retries", C.c_int32), ("reserved", C.c_int32)]
+                ("retries", C.c_int32), ("factor", C.c_int32), ("kappa_hat", C.c_double)]
 
     def as_dict(self):
         return {"status": self.status, "iters": self.iters, "refine_steps": self.refine_steps,
                 "nrhs_done": self.nrhs_done, "cert_rel": self.cert_rel, "rho0": self.rho0,
                 "rho": self.rho, "xi": self.xi, "retries": self.retries,
+                "factor": {1: "gram", 2: "householder"}.get(self.factor, None), "kappa_hat": self.kappa_hat,
                 "stage_ms": {k: float(self.stage_ms[i]) for i, k in
                              enumerate(["sketch", "qr", "cg", "final", "refine", "-", "--", "total"])}}
 

@@ -47,7 +47,7 @@ struct mn_handle_s {
   hipEvent_t snap_ev[2] = {};
   BlkState* host_blk = nullptr;    // pinned
   int32_t* host_flag = nullptr;    // pinned
-  double* host_diag = nullptr;     // pinned, 4 doubles
+  double* host_diag = nullptr;     // pinned, 32 doubles
   hipEvent_t ev[9] = {};
   bool events = false;
   // per-kernel timing (mn_profile): event pairs recorded around launches
@@ -436,14 +436,34 @@ int64_t wide_size(int dtype) { return is_complex(dtype) ? 16 : 8; }
 
 int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 
-// Step 2's triangular factor through the Gram matrix: G = S* S in FP64 on
-// the matrix cores, R with R* R = G by blocked Cholesky (chol.hip).  Returns
-// true with R64 (FP64, m x m, ld m) when every pivot is positive and finite
-// and max|R_ii| / min|R_ii| <= 1e5; otherwise the caller uses the
-// Householder factorisation (which also classifies rank deficiency and
-// non-finite input).
+// Step 2's triangular factor through the Gram matrix: G = S* S in FP64, R
+// with R* R = G by blocked Cholesky (chol.hip).  Returns true with R64 (FP64,
+// m x m, ld m) when every pivot is positive and finite and the factor is
+// accurate enough; otherwise the caller uses the Householder factorisation
+// (which also classifies rank deficiency and non-finite input).
+//
+// Accuracy: the computed R satisfies R* R = S* S + E with ||E|| about
+// sqrt(l) u64 ||S||^2, so R^{-*} S* S R^{-1} is within delta = sqrt(l) u64
+// cond(S)^2 of the identity, and sigma_min(A* R^{-1}) >= sqrt(1 - delta)
+// (Step 4's bound sigma_min >= 1 for an exact R).  cond(S) = cond(R) is
+// estimated from below by power steps on R R* and X X* (X = R^{-1}, both on
+// the device) and by the diagonal spread; the larger of the two is
+// kappa_hat.  The factor is kept when delta(kappa_hat) <= 0.1, or, for a
+// single-precision sketch, when delta is no more than u32 kappa_hat: S's own
+// rounding perturbs the preconditioned operator by that much whichever
+// factorisation runs.  The plain solve's stopping test then runs at eps
+// sqrt(1 - delta) (sigma_floor), which keeps its guarantee.
+// the acceptance rule above, for a cond(S) estimate kap
+double gram_delta(int64_t l, double kap) { return std::sqrt((double)l) * 1.11e-16 * kap * kap; }
+bool gram_accurate(int64_t l, bool single_sketch, double kap) {
+  const double tol = single_sketch ? std::max(0.1, 5.96e-8 * kap) : 0.1;
+  return gram_delta(l, kap) <= tol;
+}
+// lower bound of sigma_min(A* R^{-1}) for a Gram-route R
+double sigma_floor(int64_t l, double kap) { return std::sqrt(std::max(0.0, 1.0 - gram_delta(l, kap))); }
+
 bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, int64_t lds, void* R64,
-                 const mn_opts* o, void* X = nullptr, int64_t ldx = 0) {
+                 const mn_opts* o, void* X = nullptr, int64_t ldx = 0, double* kap_out = nullptr) {
   hipStream_t st = h->stream;
   const bool cplx = is_complex(dtype);
   const int64_t W = cplx ? 16 : 8;
@@ -481,15 +501,26 @@ bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, in
   ck(launch_fill0(bad, 16, st));
   void* Yd = ws(h, "chol_yd", (size_t)(chol_scratch_elems(m) * W));
   ck(launch_chol(cplx, G, m, m, R64, m, Yd, X, ldx, bad, st));
-  double* dr = (double*)ws(h, "qr_diag", 64);
+  // dr[0..2]: the diagonal's range and non-finite count; dr[4..]: power
+  // step records for R, then for X
+  constexpr int kPow = 4;
+  double* dr = (double*)ws(h, "qr_diag", (size_t)(4 + 2 * kPow) * 8);
   ck(launch_rdiag_range(cplx ? MN_C128 : MN_F64, R64, m, m, dr, st));
-  ck(hipMemcpyAsync(h->host_diag, dr, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  ck(launch_fill0(dr + 4, 2 * kPow * 8, st));
+  if (X != nullptr) ck(launch_power_sq(cplx, R64, m, X, ldx, m, ws(h, "cond_pw", (size_t)(6 * m * W)), dr + 4, kPow, st));
+  ck(hipMemcpyAsync(h->host_diag, dr, (size_t)(4 + 2 * kPow) * 8, hipMemcpyDeviceToHost, st));
   ck(hipMemcpyAsync(h->host_flag, bad, 4, hipMemcpyDeviceToHost, st));
   ck(hipStreamSynchronize(st));
   const double mx = h->host_diag[0], mn_ = h->host_diag[1], nonfin = h->host_diag[2];
-  h->kappa_hat = mn_ > 0.0 ? mx / mn_ : 1e300;
+  const double pr = h->host_diag[4 + kPow - 1], px = h->host_diag[4 + 2 * kPow - 1];
+  double kap = mn_ > 0.0 ? mx / mn_ : 1e300;
+  if (std::isfinite(pr) && std::isfinite(px) && pr > 0.0 && px > 0.0) kap = std::max(kap, std::sqrt(pr * px));
+  else if (X != nullptr) kap = 1e300;
+  h->kappa_hat = kap;
+  if (kap_out) *kap_out = 0.0;
   if (*h->host_flag != 0 || nonfin != 0.0 || !std::isfinite(mx) || !(mn_ > 0.0)) return false;
-  return mx <= 1e5 * mn_;
+  if (kap_out) *kap_out = kap;
+  return gram_accurate(l, is_single(dtype), kap);
 }
 
 
@@ -507,6 +538,7 @@ struct SolveCtx {
   mn_opts o;
   void* R;  // m x m, bulk dtype
   void* X;  // inverted diagonal blocks, FP64
+  double sigma_lo = 1.0;  // lower bound of sigma_min(A* R^{-1}) (below 1 for a Gram-route R)
   bool comp = false;  // compensated FP64 refinement passes (cond(A) u64 near eps)
   bool wide_acc = false;  // single-precision bulk accumulated in FP64 (large cond(A))
 };
@@ -514,7 +546,8 @@ struct SolveCtx {
 void init_state(mn_handle h, PcgState* dst, const SolveCtx& c, int rule, double eps, int max_iter) {
   PcgState& s = *h->host_state;
   memset(&s, 0, sizeof(s));
-  s.eps = eps;
+  // rules 0 and 1 bound ||x - p|| by sqrt(rho) / sigma_min(A* R^{-1})
+  s.eps = rule == 2 ? eps : eps * c.sigma_lo;
   s.alpha = c.o.alpha;
   s.l = (double)c.l;
   s.N = (double)c.N;
@@ -1258,14 +1291,18 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     gram = false;
     // the block products read whole tiles of X, so its strict lower part must be zero
     if (block) ck(launch_fill0(c.X, ldxi * ldxi * wide_size(dtype), h->stream));
+    double kap_gram = 0.0;
     if (o.precond == 0) {
       c.R = ws(h, "R64", (size_t)(m * m * wide_size(dtype)));
-      gram = gram_factor(h, c.bulk, l, m, S, l, c.R, &o, c.X, ldxi);
+      gram = gram_factor(h, c.bulk, l, m, S, l, c.R, &o, c.X, ldxi, &kap_gram);
       if (gram) rdt = wdt;
     }
     if (!gram) {
       c.R = ws(h, "R", (size_t)(m * m * bes));
       const int st = run_qr(h, c.bulk, l, m, S, l, c.R, m);
+      // the Gram route's estimate (when its Cholesky ran through) stays a
+      // lower bound of cond(S)
+      h->kappa_hat = std::max(h->kappa_hat, kap_gram);
       if (st == MN_RANK_DEFICIENT && att + 1 < attempts) continue;
       if (st != MN_OK) {
         ev_record(h, 2);
@@ -1276,6 +1313,11 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     break;
   }
   ev_record(h, 2);
+  if (info) {
+    info->factor = gram ? 1 : 2;
+    info->kappa_hat = h->kappa_hat;
+  }
+  if (gram) c.sigma_lo = sigma_floor(l, h->kappa_hat);
   // compensated refinement passes when the rounding of plain FP64 sums,
   // about cond(A) u64 relative, is within a hundredth of eps
   c.comp = c.mixed && h->kappa_hat * 1.11e-16 > eps / 100.0;
@@ -1469,7 +1511,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
                 a256(l[i] * 4) + a256(l[i] * mm * be) +
                 a256(b_sketch_work_elems(bulk, mm, N[i], l[i]) * ces) +
                 2 * a256(mm * mm * W) + a256(q.ldx * q.ldx * W) + a256(chol_scratch_elems(mm) * W) +
-                6 * a256(mm * W) + a256(kGramParts * mm * W) +
+                6 * a256(mm * W) + a256(kGramParts * mm * W) + a256(3 * mm * W) +
                 a256((int64_t)q.gram_G * mm * W) + a256(n[i] * W) + a256((int64_t)q.adj_slabs * n[i] * W) +
                 a256((int64_t)q.fwd_chunks * mm * W);
   }
@@ -1562,6 +1604,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     q.w64 = take(n[i] * W);
     q.apart = take((int64_t)q.adj_slabs * n[i] * W);
     q.fpart = take((int64_t)q.fwd_chunks * mm * W);
+    q.pw = take(3 * mm * W);
     q.flags = flags + 4 * i;
     q.diag = diag + 4 * i;
     q.st = states + i;
@@ -1617,6 +1660,10 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   ck(launch_b_gram_s(bulk, L(gram_s), st));
   for (int k = 0; k < maxnbk; ++k) ck(launch_b_chol_step(cplx, L(chol[k]), k - 1, st));
   ck(launch_b_rdiag(cplx, L(rdiag), st));
+  // X = R^{-1}, then the condition estimate (gram_factor's rule)
+  ck(launch_b_inv_diag(cplx, L(invd), st));
+  for (int k = 0; k + 1 < maxnbk; ++k) ck(launch_b_trtri_step(cplx, L(trtri[k]), k, st));
+  ck(launch_b_power(cplx, L(rdiag), 4, st));
   std::vector<int32_t> hflags((size_t)batch * 4);
   std::vector<double> hdiag((size_t)batch * 4);
   ck(hipMemcpyAsync(hst, flags, (size_t)batch * 16, hipMemcpyDeviceToHost, st));
@@ -1625,11 +1672,17 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   memcpy(hflags.data(), hst, (size_t)batch * 16);
   memcpy(hdiag.data(), hst + (size_t)batch * 16, (size_t)batch * 32);
   std::vector<char> skip((size_t)batch, 0);
+  std::vector<double> kap_of((size_t)batch, 0.0);
   st_out.assign((size_t)batch, MN_OK);
   for (int i = 0; i < batch; ++i) {
     const double mx = hdiag[4 * i], mn_ = hdiag[4 * i + 1], nf = hdiag[4 * i + 2];
     const bool bad_idx = idx_bad[i] != 0;
-    const bool gram_ok = hflags[4 * i + 1] == 0 && nf == 0.0 && std::isfinite(mx) && mn_ > 0.0 && mx <= 1e5 * mn_;
+    const double pk = hdiag[4 * i + 3];
+    double kap = mn_ > 0.0 ? mx / mn_ : 1e300;
+    kap = (std::isfinite(pk) && pk > 0.0) ? std::max(kap, std::sqrt(pk)) : 1e300;
+    const bool gram_ok = hflags[4 * i + 1] == 0 && nf == 0.0 && std::isfinite(mx) && mn_ > 0.0 &&
+                         gram_accurate(l[i], is_single(bulk), kap);
+    kap_of[i] = kap;
     if (bad_idx) {
       st_out[i] = -16;
       skip[i] = 1;
@@ -1638,15 +1691,13 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       skip[i] = 1;
     }
   }
-  // X = R^{-1}
-  ck(launch_b_inv_diag(cplx, L(invd), st));
-  for (int k = 0; k + 1 < maxnbk; ++k) ck(launch_b_trtri_step(cplx, L(trtri[k]), k, st));
   // CG states (skipped systems start finished)
   std::vector<PcgState> hst_state((size_t)batch);
   for (int i = 0; i < batch; ++i) {
     PcgState& s0 = hst_state[i];
     memset(&s0, 0, sizeof(s0));
-    s0.eps = mixed ? std::pow(10.0, -(double)(o.inner_digits ? o.inner_digits : 4)) : eps[i];
+    s0.eps = mixed ? std::pow(10.0, -(double)(o.inner_digits ? o.inner_digits : 4))
+                   : eps[i] * (skip[i] ? 1.0 : sigma_floor(l[i], kap_of[i]));
     s0.alpha = o.alpha;
     s0.l = (double)l[i];
     s0.N = (double)N[i];
@@ -1778,6 +1829,8 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     if (info) {
       memset(&info[i], 0, sizeof(mn_info));
       fill_info_from_state(hst_state[i], mixed, &info[i]);
+      info[i].factor = 1;
+      info[i].kappa_hat = kap_of[i];
     }
   }
 }
@@ -1828,7 +1881,7 @@ int mn_create(mn_handle* hp, void* stream) {
     for (auto& e : h->snap_ev) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     ck(hipHostMalloc((void**)&h->host_blk, sizeof(BlkState), hipHostMallocDefault));
     ck(hipHostMalloc((void**)&h->host_flag, 64, hipHostMallocDefault));
-    ck(hipHostMalloc((void**)&h->host_diag, 64, hipHostMallocDefault));
+    ck(hipHostMalloc((void**)&h->host_diag, 256, hipHostMallocDefault));
     for (auto& e : h->ev) ck(hipEventCreate(&e));
     for (auto& e : h->tev) ck(hipEventCreate(&e));
   } catch (HipFail f) {

@@ -373,4 +373,203 @@ hipError_t launch_b_chol_step(bool cplx, const BLaunch& L, int k, hipStream_t st
   return hipGetLastError();
 }
 
+// ---- condition estimate of a triangular factor -----------------------------
+// sigma_max(T)^2 for an upper triangular FP64 T by power steps on T T*: from a
+// fixed unit start vector v, each step forms u = T (T* v) and records
+// ||u||, then v = u / ||u||.  The recorded norms increase towards
+// sigma_max(T)^2 from below (every record is a lower bound), so
+// sqrt(record_X * record_R) for X = R^{-1} bounds cond(R) from below.
+namespace {
+template <typename W> __device__ inline W pw_start(int64_t i) {
+  // a Weyl sequence: no fixed relation to any matrix's singular vectors
+  const uint64_t a = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+  const uint64_t b = (uint64_t)(i + 1) * 0xD1B54A32D192ED03ull;
+  return vmake<W>((double)(a >> 11) * 0x1.0p-53 - 0.5, (double)(b >> 11) * 0x1.0p-53 - 0.5);
+}
+
+// Two matrices (T0, T1) advance together: blockIdx.y (or the workgroup
+// index for the norm) selects the matrix; vectors of matrix t sit at v + t m.
+struct PwPair {
+  const void* T[2];
+  int64_t ld[2];
+};
+
+template <typename W>
+__global__ void __launch_bounds__(256) k_pw_init(int64_t m, W* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < m) v[i] = v[m + i] = pw_start<W>(i);
+}
+
+// g_j = sum_{i <= j} conj(T_ij) v_i: a wave per column, four columns per
+// workgroup.  grid (ceil(m / 4), 2), 256 threads.
+template <typename W>
+__global__ void __launch_bounds__(256) k_pw_adj(PwPair P, int64_t m, const W* __restrict__ v, W* __restrict__ g) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= m) return;
+  const W* col = reinterpret_cast<const W*>(P.T[t]) + j * P.ld[t];
+  const W* vt = v + t * m;
+  W a0 = vzero<W>(), a1 = vzero<W>();
+  int64_t i = lane;
+  for (; i + 64 <= j; i += 128) {
+    a0 = vcfma(col[i], vt[i], a0);
+    a1 = vcfma(col[i + 64], vt[i + 64], a1);
+  }
+  if (i <= j) a0 = vcfma(col[i], vt[i], a0);
+  const W a = wave_sum(vadd(a0, a1));
+  if (lane == 0) g[t * m + j] = a;
+}
+
+// u_i = sum_{j >= i} T_ij g_j for one 64-row block per workgroup: lane = row,
+// the eight waves take every eighth column (each load a contiguous 64-entry
+// piece of a column), then the waves' sums are added in wave order.
+// grid (ceil(m / 64), 2), 512 threads.
+template <typename W>
+__global__ void __launch_bounds__(512) k_pw_fwd(PwPair P, int64_t m, const W* __restrict__ g, W* __restrict__ u) {
+  __shared__ W part[8][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = blockIdx.y;
+  const W* T = reinterpret_cast<const W*>(P.T[t]);
+  const int64_t ldt = P.ld[t];
+  const W* gt = g + t * m;
+  const int64_t r0 = (int64_t)blockIdx.x * 64, r = r0 + lane;
+  W a0 = vzero<W>(), a1 = vzero<W>();
+  int64_t j = r0 + wv;
+  for (; j + 8 < m; j += 16) {
+    if (r <= j) a0 = vfma(T[r + j * ldt], gt[j], a0);
+    if (r <= j + 8) a1 = vfma(T[r + (j + 8) * ldt], gt[j + 8], a1);
+  }
+  if (j < m && r <= j) a0 = vfma(T[r + j * ldt], gt[j], a0);
+  part[wv][lane] = vadd(a0, a1);
+  __syncthreads();
+  if (wv == 0 && r < m) {
+    W a = part[0][lane];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) a = vadd(a, part[w][lane]);
+    u[t * m + r] = a;
+  }
+}
+
+// workgroup t: out[t * stride + slot] = ||u_t|| (slot >= 0), v_t = u_t /
+// ||u_t|| when the norm is positive and finite (else v_t keeps its entries).
+// grid 2, 1024 threads.
+template <typename W>
+__global__ void __launch_bounds__(1024) k_pw_norm(const W* __restrict__ u, int64_t m, W* __restrict__ v,
+                                                  double* __restrict__ out, int stride, int slot) {
+  __shared__ double red[16];
+  const int t = blockIdx.x;
+  const W* ut = u + t * m;
+  W* vt = v + t * m;
+  double s2 = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += 1024) s2 += vabs2(ut[i]);
+  const double s = sqrt(block_sum(s2, red));
+  if (threadIdx.x == 0 && slot >= 0) out[t * stride + slot] = s;
+  if (!(s > 0.0) || !isfinite(s)) return;
+  const double r = 1.0 / s;
+  for (int64_t i = threadIdx.x; i < m; i += 1024) vt[i] = vscale(ut[i], r);
+}
+
+template <typename W>
+hipError_t power_t(const PwPair& P, int64_t m, void* work, double* out, int steps, hipStream_t st) {
+  W* v = reinterpret_cast<W*>(work);
+  W* g = v + 2 * m;
+  W* u = v + 4 * m;
+  hipLaunchKernelGGL((k_pw_init<W>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, m, v);
+  hipLaunchKernelGGL((k_pw_norm<W>), dim3(2), dim3(1024), 0, st, v, m, v, out, steps, -1);
+  for (int k = 0; k < steps; ++k) {
+    hipLaunchKernelGGL((k_pw_adj<W>), dim3((unsigned)ceil_div(m, 4), 2), dim3(256), 0, st, P, m, v, g);
+    hipLaunchKernelGGL((k_pw_fwd<W>), dim3((unsigned)ceil_div(m, 64), 2), dim3(512), 0, st, P, m, g, u);
+    hipLaunchKernelGGL((k_pw_norm<W>), dim3(2), dim3(1024), 0, st, u, m, v, out, steps, k);
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_power_sq(bool cplx, const void* T0, int64_t ld0, const void* T1, int64_t ld1, int64_t m, void* work,
+                           double* out, int steps, hipStream_t st) {
+  if (m < 1 || ld0 < m || ld1 < m || steps < 1) return hipErrorInvalidValue;
+  PwPair P;
+  P.T[0] = T0;
+  P.T[1] = T1;
+  P.ld[0] = ld0;
+  P.ld[1] = ld1;
+  return cplx ? power_t<cd>(P, m, work, out, steps, st) : power_t<double>(P, m, work, out, steps, st);
+}
+
+namespace {
+// sigma_max(T)^2 record after `steps` power steps on T T* (T upper, FP64,
+// ld ldt), the same steps as launch_power_sq, inside one workgroup of 256
+// threads: g = T* v a wave per column, u = T g a 64-row block at a time
+// (lane = row, the waves taking every fourth column).
+template <typename W>
+__device__ double b_power_one(const W* __restrict__ T, int64_t ldt, int64_t m, W* v, W* g, W* u, int steps,
+                              double* red, W (*part)[64]) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int64_t i = t; i < m; i += 256) v[i] = pw_start<W>(i);
+  __syncthreads();
+  double s2 = 0.0;
+  for (int64_t i = t; i < m; i += 256) s2 += vabs2(v[i]);
+  const double nrm = sqrt(block_sum(s2, red));
+  for (int64_t i = t; i < m; i += 256) v[i] = vscale(v[i], 1.0 / nrm);
+  double rec = 0.0;
+  for (int k = 0; k < steps; ++k) {
+    __syncthreads();
+    for (int64_t j = wv; j < m; j += 4) {
+      W a = vzero<W>();
+      for (int64_t i = lane; i <= j; i += 64) a = vcfma(T[i + j * ldt], v[i], a);
+      a = wave_sum(a);
+      if (lane == 0) g[j] = a;
+    }
+    __syncthreads();
+    s2 = 0.0;
+    for (int64_t r0 = 0; r0 < m; r0 += 64) {
+      const int64_t r = r0 + lane;
+      W a0 = vzero<W>(), a1 = vzero<W>();
+      int64_t j = r0 + wv;
+      for (; j + 4 < m; j += 8) {
+        if (r <= j) a0 = vfma(T[r + j * ldt], g[j], a0);
+        if (r <= j + 4) a1 = vfma(T[r + (j + 4) * ldt], g[j + 4], a1);
+      }
+      if (j < m && r <= j) a0 = vfma(T[r + j * ldt], g[j], a0);
+      part[wv][lane] = vadd(a0, a1);
+      __syncthreads();
+      if (wv == 0 && r < m) {
+        const W a = vadd(vadd(part[0][lane], part[1][lane]), vadd(part[2][lane], part[3][lane]));
+        u[r] = a;
+        s2 += vabs2(a);
+      }
+      __syncthreads();
+    }
+    rec = sqrt(block_sum(s2, red));
+    if (!(rec > 0.0) || !isfinite(rec)) return rec;
+    for (int64_t i = t; i < m; i += 256) v[i] = vscale(u[i], 1.0 / rec);
+  }
+  return rec;
+}
+
+template <typename W>
+__global__ void __launch_bounds__(256) kb_power(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                int nsys, int steps) {
+  __shared__ double red[4];
+  __shared__ W part[4][64];
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  const int64_t m = s.m;
+  W* v = reinterpret_cast<W*>(s.pw);
+  const double pr = b_power_one<W>(reinterpret_cast<const W*>(s.R), m, m, v, v + m, v + 2 * m, steps, red, part);
+  __syncthreads();
+  const double px =
+      b_power_one<W>(reinterpret_cast<const W*>(s.X), s.ldx, m, v, v + m, v + 2 * m, steps, red, part);
+  if (threadIdx.x == 0) s.diag[3] = pr * px;
+}
+}  // namespace
+
+hipError_t launch_b_power(bool cplx, const BLaunch& L, int steps, hipStream_t st) {
+  if (L.total == 0) return hipSuccess;
+  if (cplx) hipLaunchKernelGGL(kb_power<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, steps);
+  else hipLaunchKernelGGL(kb_power<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, steps);
+  return hipGetLastError();
+}
+
 }  // namespace mn

@@ -313,6 +313,12 @@ hipError_t launch_gram_fold(bool cplx, const double* Cp, int splits, int64_t ldc
 int64_t chol_scratch_elems(int64_t m);
 hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, void* X,
                        int64_t ldx, int32_t* bad, hipStream_t st);
+// Power steps on T T* for two upper triangular FP64 matrices T0, T1 (ld0,
+// ld1) at once: out[t * steps + k] (k < steps) = ||T_t T_t* v_k|| with v_0 a
+// fixed unit vector and v_{k+1} the normalised product; each is a lower
+// bound of sigma_max(T_t)^2.  work: 6 m entries (wide).
+hipError_t launch_power_sq(bool cplx, const void* T0, int64_t ld0, const void* T1, int64_t ld1, int64_t m, void* work,
+                           double* out, int steps, hipStream_t st);
 
 // ---- batched systems -----------------------------------------------------------
 // Batched launch over several systems: entry i holds system i's first
@@ -354,7 +360,8 @@ struct BSys {
   void* X;         // ldx x ldx, wide
   int64_t ldx;
   void* Yd;        // chol_scratch_elems(m), wide (inverses of R's diagonal tiles)
-  double* diag;    // [max |R_ii|, min |R_ii|, nonfinite]
+  double* diag;    // [max |R_ii|, min |R_ii|, nonfinite, power records of R R* times X X*]
+  void* pw;        // 3 m, wide (power-step vectors)
   void *y, *r0, *r1, *p, *s, *q, *qpart, *w64, *apart, *fpart, *y_outer;
   PcgState* st;
   int64_t gram_spw, gram_nstrips;
@@ -393,6 +400,10 @@ hipError_t launch_b_sketch(int dtype, const BLaunch& small, const BLaunch& cols,
                            size_t lds_rows, size_t lds_pruned, hipStream_t st);
 hipError_t launch_b_gram_s(int dtype, const BLaunch& L, hipStream_t st);
 hipError_t launch_b_chol_step(bool cplx, const BLaunch& L, int k, hipStream_t st);
+// diag[3] = (power record of R R*) x (power record of X X*), steps power
+// steps each (launch_power_sq's records), one workgroup per system; reads R
+// and X = R^{-1}, uses pw
+hipError_t launch_b_power(bool cplx, const BLaunch& L, int steps, hipStream_t st);
 hipError_t launch_b_rdiag(bool cplx, const BLaunch& L, hipStream_t st);
 hipError_t launch_b_inv_diag(bool cplx, const BLaunch& L, hipStream_t st);
 hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int k, hipStream_t st);

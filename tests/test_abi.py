@@ -142,10 +142,11 @@ def test_draw_argument_errors():
 
 
 def test_struct_layouts_match_header():
-    """The ctypes views have the header's sizes (options 80 bytes, report 88, H 48)."""
+    """The ctypes views have the header's sizes (options 80 bytes, report 96, H 48)."""
     L, _ = _lib()
     assert C.sizeof(L.MnOpts) == 80 and C.sizeof(L.MnHFactor) == 48 and L.MnOpts.hfactor.offset == 72
-    assert C.sizeof(L.MnInfo) == 88
+    assert C.sizeof(L.MnInfo) == 96
+    assert L.MnInfo.factor.offset == 84 and L.MnInfo.kappa_hat.offset == 88
     assert L.MnOpts.seed.offset == 56 and L.MnInfo.retries.offset == 80
 
 
