@@ -23,8 +23,16 @@
  *     are stored interleaved (re, im), as in C99 / C++ / numpy / torch.
  *   - A is row-major: entry (i, j) at A[i*lda + j], lda >= n.  Vectors are
  *     contiguous.  S and R are column-major: S(k, i) at S[k + i*lds].
- *   - N is the transform length: a power of two with n <= N <= 2^22.  Rows of
- *     A are zero-padded from n to N; this does not change the minimal-norm
+ *   - N is the transform length, n <= N <= 2^22: a power of two, or N = N1 2^k
+ *     with 2^k >= 256 and any N1 >= 2 (so any multiple of 256 from 512 up),
+ *     since eq. (DFT) is defined for every length.  Such N keep the padding
+ *     below 256 entries; their sketch runs only in the kept-outputs-only
+ *     form (the l kept outputs of each row from N1 transforms of length 2^k),
+ *     which holds l <= 2048 complex128 / float64 outputs per row at 256
+ *     threads, 4096 at 512, and up to 8192 / 16384 for single precision; a
+ *     larger l with such N is refused as an invalid N.  minnorm_steps23 and
+ *     srft_sketch_noalloc take powers of two only.  Rows of A are
+ *     zero-padded from n to N; this does not change the minimal-norm
  *     solution (its last N - n entries are zero).
  *   - d holds the N diagonal entries of D in FP64 whatever dtype is: complex
  *     unit-modulus phases (complex128) for complex dtypes, +-1 (float64) for
@@ -265,8 +273,9 @@ int mn_plans_count(mn_handle h);
  *   d  [N, complex128 or float64]          read
  *   idx[l, int32]                          read
  *   S  [l x m, dtype, column-major, lds]   written
- * Errors: -3/-4 m, n < 1; -6 lda < n; -7 N not a power of two, N < n or
- * N > 2^22; -8 l < 1 or l > N; -12 lds < l; -5/-9/-10/-11 NULL pointer;
+ * Errors: -3/-4 m, n < 1; -6 lda < n; -7 N not a transform length (see the
+ * top of this file; also for (N, l) the kept-outputs-only form cannot hold),
+ * N < n or N > 2^22; -8 l < 1 or l > N; -12 lds < l; -5/-9/-10/-11 NULL pointer;
  * -10 (after a sync) idx not strictly increasing or out of [0, N). */
 int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int64_t lda,
                 int64_t N, int64_t l, const void* d, const int32_t* idx,
@@ -340,8 +349,8 @@ int srft_sketch_noalloc(mn_handle h, int dtype, int64_t m, int64_t n, const void
  * The phases are computed on the device; the indices on the host and copied
  * (the call returns after the copy has been enqueued and its host buffer
  * released, i.e. after a stream synchronisation).
- * Errors: -1 NULL handle; -2 dtype; -4 draw < 0; -5 sys < 0; -6 N not a
- * power of two or N > 2^22; -7 l < 1 or l > N; -8 d NULL; -9 idx NULL. */
+ * Errors: -1 NULL handle; -2 dtype; -4 draw < 0; -5 sys < 0; -6 N < 1 or
+ * N > 2^22; -7 l < 1 or l > N; -8 d NULL; -9 idx NULL. */
 int srft_draw(mn_handle h, int dtype, uint64_t seed, int32_t draw, int32_t sys, int64_t N, int64_t l,
               void* d, int32_t* idx);
 

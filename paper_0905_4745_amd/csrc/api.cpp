@@ -104,6 +104,9 @@ void* ws(mn_handle h, const char* name, size_t bytes) {
 }
 
 bool is_pow2(int64_t N) { return N > 0 && (N & (N - 1)) == 0; }
+// Transform lengths the sketch takes: powers of two, and N = N1 2^k (any N1
+// >= 2, 2^k >= 256) through the kept-outputs-only form
+bool is_fft_len(int64_t N) { return is_pow2(N) || (N >= 512 && N % 256 == 0); }
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 bool is_complex(int dtype) { return dtype == MN_C128 || dtype == MN_C64; }
 bool is_single(int dtype) { return dtype == MN_C64 || dtype == MN_F32; }
@@ -223,6 +226,17 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
                 const void* d, const int32_t* idx, const int32_t* inv, void* S, int64_t lds,
                 const mn_opts* o = nullptr, const SketchArena* ar = nullptr, const mn_hfactor* H = nullptr);
 
+// A length N that is not a power of two runs only in the kept-outputs-only
+// form: some (B, workgroup) must apply to (N, l)
+bool sketch_ok(int dtype, int64_t N, int64_t l) {
+  if (is_pow2(N)) return true;
+  if (!is_fft_len(N)) return false;
+  for (int tpb : {256, sketch_pruned_wide_tpb(dtype)})
+    for (int B : {16, 8, 4})
+      if (sketch_pruned_groups(dtype, N, l, B, 1, tpb) > 0) return true;
+  return false;
+}
+
 // Checks H's arrays (non-null, permutations in range; one stream sync).
 bool hfactor_valid(mn_handle h, const mn_hfactor* H, int64_t N) {
   if (!H || !H->theta || !H->perm || !H->zeta || !H->theta_t || !H->perm_t || !H->zeta_t) return false;
@@ -281,7 +295,8 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   a.S = S;
   a.lds = lds;
   a.twiddle = ar ? ar->twiddle : twiddles(h, N, single);
-  if (N <= kFftMaxLds) {
+  const bool p2 = is_pow2(N);
+  if (p2 && N <= kFftMaxLds) {
     ck(launch_sketch(dtype, a, h->stream));
     return;
   }
@@ -336,7 +351,22 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   // the pace); at 4096 x 131072, l = 16384, B = 8 measured best (8.87 ms
   // against 9.32), a tuning candidate.
   int mb = 64;
-  if (l <= 2048 && sketch_pruned_groups(dtype, N, l, 16, 1) > 0) {
+  if (!p2) {
+    // N = N1 2^k: the first kept-outputs-only shape that applies, with
+    // column groups enough for 256 workgroups
+    mb = -1;
+    for (int wide : {0, 1})
+      for (int bc : {1, 2, 3}) {
+        const int tpb = wide ? wide_tpb : 256;
+        if (mb >= 0 || sketch_pruned_groups(dtype, N, l, pruned_b[bc], 1, tpb) < 1) continue;
+        int lg = 0;
+        while ((m << lg) < 256 && lg < 10 &&
+               sketch_pruned_groups(dtype, N, l, pruned_b[bc], 1 << (lg + 1), tpb) == (1 << (lg + 1)))
+          ++lg;
+        mb = 64 | (bc << 19) | (lg << 21) | (wide << 25);
+      }
+    if (mb < 0) throw HipFail{hipErrorInvalidValue};
+  } else if (l <= 2048 && sketch_pruned_groups(dtype, N, l, 16, 1) > 0) {
     int lg = 0;
     while ((m << lg) < 512 && lg < 10) ++lg;
     mb = 64 | (1 << 19) | (lg << 21);
@@ -349,12 +379,14 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   const std::string key = plan_key("sketch_chunk_mb", dtype, m, N, 0);
   if (o) {
     std::vector<int> cands{mb};
-    for (int c : {64, 16, 32})
-      if (c != mb) cands.push_back(c);
-    for (int sp : {0, 1, 2})
-      for (int c : {64, 128, 256, 512})
-        if (sp || c != 64) cands.push_back((sp << 17) | c);
-    cands.push_back(0x10000 | 512);
+    if (p2) {
+      for (int c : {64, 16, 32})
+        if (c != mb) cands.push_back(c);
+      for (int sp : {0, 1, 2})
+        for (int c : {64, 128, 256, 512})
+          if (sp || c != 64) cands.push_back((sp << 17) | c);
+      cands.push_back(0x10000 | 512);
+    }
     for (int wide : {0, 1})
       for (int bc : {1, 2, 3})
         for (int lg : {0, 1, 2, 3, 4})
@@ -1391,10 +1423,16 @@ int64_t a256(int64_t v) { return (v + 255) / 256 * 256; }
 
 // The fused form takes one bulk type for all systems: either no system has a
 // single-precision copy or every system has one (a mix goes to the lanes).
-bool fused_batch_ok(int batch, const int64_t* m, const void* const* A_lo, const mn_opts& o) {
+bool fused_batch_ok(int dtype, int batch, const int64_t* m, const int64_t* N, const int64_t* l,
+                    const void* const* A_lo, const mn_opts& o) {
   if (o.precond != 0 || o.batch_form == 1 || batch < 2 || o.hfactor) return false;
   for (int i = 0; i < batch; ++i)
     if (m[i] > kGramMaxRows) return false;
+  // a length N = N1 2^k needs the fused form's kept-outputs-only sketch
+  // (B = 16, 256 threads, l <= 2048)
+  const int bulk = A_lo ? dtype + 1 : dtype;
+  for (int i = 0; i < batch; ++i)
+    if (!is_pow2(N[i]) && !(l[i] <= 2048 && sketch_pruned_groups(bulk, N[i], l[i], 16, 1) > 0)) return false;
   if (A_lo)
     for (int i = 0; i < batch; ++i)
       if (!A_lo[i]) return false;
@@ -1851,8 +1889,10 @@ int check_solve_args(mn_handle h, int dtype, int64_t m, int64_t n, const void* A
   if (ldb < m) return -10;
   if (nrhs < 1 || nrhs > 64) return -11;
   if (!(eps > 0.0 && eps < 1.0)) return -12;
-  if (!is_pow2(N) || N < n || N > (1 << 22)) return -13;
+  if (!is_fft_len(N) || N < n || N > (1 << 22)) return -13;
   if (l <= m || l > N) return -14;
+  // the sketch runs in the bulk precision (single with A_lo)
+  if (!sketch_ok(A_lo ? dtype + 1 : dtype, N, l)) return -13;
   if (!d && idx) return -15;  // both NULL: the library draws
   if (d && !idx) return -16;
   if (!opts_valid(o)) return -17;
@@ -2062,8 +2102,9 @@ int srft_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   if (n < 1) return -4;
   if (!A) return -5;
   if (lda < n) return -6;
-  if (!is_pow2(N) || N < n || N > (1 << 22)) return -7;
+  if (!is_fft_len(N) || N < n || N > (1 << 22)) return -7;
   if (l < 1 || l > N) return -8;
+  if (!sketch_ok(dtype, N, l)) return -7;
   if (!d) return -9;
   if (!idx) return -10;
   if (!S) return -11;
@@ -2168,8 +2209,9 @@ int srft_sketch_h(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, i
   if (n < 1) return -4;
   if (!A) return -5;
   if (lda < n) return -6;
-  if (!is_pow2(N) || N < n || N > (1 << 22)) return -7;
+  if (!is_fft_len(N) || N < n || N > (1 << 22)) return -7;
   if (l < 1 || l > N) return -8;
+  if (!sketch_ok(dtype, N, l)) return -7;
   if (!d) return -9;
   if (!idx) return -10;
   if (!H || !H->theta || !H->perm || !H->zeta || !H->theta_t || !H->perm_t || !H->zeta_t) return -11;
@@ -2240,7 +2282,7 @@ int srft_draw(mn_handle h, int dtype, uint64_t seed, int32_t draw, int32_t sys, 
   if (dtype < 0 || dtype > 3) return -2;
   if (draw < 0) return -4;
   if (sys < 0) return -5;
-  if (!is_pow2(N) || N > (1 << 22)) return -6;
+  if (N < 1 || N > (1 << 22)) return -6;
   if (l < 1 || l > N) return -7;
   if (!d) return -8;
   if (!idx) return -9;
@@ -2320,7 +2362,7 @@ int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* 
   const bool lib_draw = d == nullptr;
   auto d_of = [&](int i) -> const void* { return lib_draw ? nullptr : d[i]; };
   auto idx_of = [&](int i) -> const int32_t* { return lib_draw ? nullptr : idx[i]; };
-  if (fused_batch_ok(batch, m, A_lo, o)) {
+  if (fused_batch_ok(dtype, batch, m, N, l, A_lo, o)) {
     std::vector<int> stv, redo;
     try {
       if (lib_draw) {

@@ -480,7 +480,7 @@ template <typename C, int B, int TPB> __host__ __device__ constexpr bool pruned_
 
 // bk.x = column group, bk.y = row within the launch, bk.gx = groups per row.
 // TPB threads hold 16 elements each: N2 = 16 TPB / B points per column.
-template <typename V, typename C, int B, int KPT, int TPB = 256>
+template <typename V, typename C, int B, int KPT, int TPB = 256, bool P2 = true>
 __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t row0,
                                                        int64_t rows, int64_t n, int N1, int G, FftPlan pl2,
                                                        const void* __restrict__ dv, const int32_t* __restrict__ idx,
@@ -498,7 +498,24 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
   constexpr bool TW_LDS = pruned_tw_lds<C, B, TPB>();
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
-  const unsigned Nm = (unsigned)N1 * (unsigned)N2 - 1u;
+  // N = N1 N2 with N2 a power of two and N1 any positive integer (P2: N a
+  // power of two).  The factor W_N^{c0 k} of a block (c0 < N1) needs
+  // (c0 k) mod N: a mask for a power of two; otherwise, with k = a N2 + k2
+  // (k2 < N2),  c0 k = N2 (c0 a) + c0 k2,  N2 ((c0 a) mod N1) < N,  c0 k2 < N,
+  // so one 32-bit remainder by N1 and one conditional subtraction.  (The two
+  // index forms are separate instantiations: selected at run time inside
+  // the block loop they cost the registers of both.)
+  const unsigned Ntot = (unsigned)N1 * (unsigned)N2, Nm = Ntot - 1u;
+  auto modn = [&](unsigned c, unsigned k) -> unsigned {
+    if constexpr (P2) {
+      return (c * k) & Nm;
+    } else {
+      const unsigned a = k >> ilog2c<N2>(), k2 = k & (unsigned)(N2 - 1);
+      unsigned r = ((c * a) % (unsigned)N1) * (unsigned)N2 + c * k2;
+      if (r >= Ntot) r -= Ntot;
+      return r;
+    }
+  };
   const int64_t i = row0 + bk.y;
   const V* row = A + i * lda;
   C* tws = sm + B * Lp;
@@ -523,7 +540,7 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
 #pragma unroll
   for (int u = 0; u < KPT; ++u) {
     const int q = tid + TPB * u;
-    kq[u] = q < l ? (unsigned)idx[order[q]] & Nm : 0u;
+    kq[u] = q < l ? (unsigned)idx[order[q]] % Ntot : 0u;
   }
   // the empty asm makes k opaque inside the block loop, so the table reads
   // that depend on it stay there (hoisted, they would hold 4 KPT registers
@@ -538,12 +555,15 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
   // outer sum and used after it; A is read once, as a stream (non-temporal:
   // it does not push the phase and twiddle tables, which every row reads,
   // out of the cache).  The phases are read when the block is formed.
+  // Columns n1 >= N1 of a last, partial block are zero (their transforms
+  // add nothing to the outer sum).
   V pa[16];
   auto load = [&](int c0) {
+    const bool col = c0 + bb < N1;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int64_t j = (int64_t)(c0 + bb) + (int64_t)N1 * (jj + r * LR);
-      pa[r] = j < n ? ld_stream(row + j) : V{};
+      pa[r] = (col && j < n) ? ld_stream(row + j) : V{};
     }
   };
   const int cbeg = bk.x * G * B;
@@ -552,10 +572,11 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
     const int c0 = cbeg + g * B;
     {
       C v[16];
+      const bool col = c0 + bb < N1;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t j = (int64_t)(c0 + bb) + (int64_t)N1 * (jj + r * LR);
-        const D dd = j < n ? dp[j] : D{};
+        const D dd = (col && j < n) ? dp[j] : D{};
         if constexpr (VT<V>::cplx) v[r] = vcmul(vconv<C>(pa[r]), vmake<C>(dd.re, dd.im));  // conj(a) d
         else v[r] = C{(R)pa[r] * (R)dd, (R)0};
       }
@@ -586,7 +607,7 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
 #pragma unroll
     for (int u = 0; u < KPT; u += 2) {
       const unsigned k0 = kept(u), k1 = kept(u + 1);
-      C w0 = tw[((unsigned)c0 * k0) & Nm], w1 = tw[((unsigned)c0 * k1) & Nm];  // W_N^{c0 k}
+      C w0 = tw[modn((unsigned)c0, k0)], w1 = tw[modn((unsigned)c0, k1)];  // W_N^{c0 k}
       const C st0 = tw[k0], st1 = tw[k1];                                       // W_N^k
       const C* zp0 = sm + lpad((int)(k0 & (unsigned)(N2 - 1)));
       const C* zp1 = sm + lpad((int)(k1 & (unsigned)(N2 - 1)));
@@ -619,8 +640,12 @@ __global__ void __launch_bounds__(TPB, TPB == 256 ? 2 : 1) k_sketch_pruned(
     const V* __restrict__ A, int64_t lda, int64_t row0, int64_t rows, int64_t n, int N1, int G, FftPlan pl2,
     const void* __restrict__ dv, const int32_t* __restrict__ idx, const int32_t* __restrict__ order, int64_t l,
     const C* __restrict__ tw, V* __restrict__ S, int64_t lds, C* __restrict__ P, typename VT<C>::real scale) {
-  k_sketch_pruned_body<V, C, B, KPT, TPB>(bk_hw(), A, lda, row0, rows, n, N1, G, pl2, dv, idx, order, l, tw, S, lds,
-                                          P, scale);
+  if ((N1 & (N1 - 1)) == 0)
+    k_sketch_pruned_body<V, C, B, KPT, TPB, true>(bk_hw(), A, lda, row0, rows, n, N1, G, pl2, dv, idx, order, l, tw, S,
+                                                  lds, P, scale);
+  else
+    k_sketch_pruned_body<V, C, B, KPT, TPB, false>(bk_hw(), A, lda, row0, rows, n, N1, G, pl2, dv, idx, order, l, tw, S,
+                                                   lds, P, scale);
 }
 
 // order[0 .. l) = a permutation of 0 .. l that groups the kept outputs by
@@ -779,7 +804,7 @@ template <typename C> static int pruned_groups(int64_t N, int64_t l, int B, int 
   const int64_t N2 = (int64_t)tpb * 16 / B;
   if (N2 > kOrderMaxN2 || N <= N2 || N % N2) return 0;
   if ((int64_t)pruned_smem<C>(B, tpb) > lds_limit()) return 0;
-  const int64_t nb = N / N2 / B;  // blocks per row
+  const int64_t nb = ceil_div(N / N2, B);  // blocks per row (the last one partial when B does not divide N1)
   if (nb < 1) return 0;
   int g = ng < 1 ? 1 : ng;
   while (g > 1 && (nb % g || g > nb)) g >>= 1;
@@ -838,7 +863,7 @@ static hipError_t sketch_pruned_impl(const SketchArgs& a, hipStream_t st) {
   const int ng = pruned_groups<C>(a.N, a.l, B, a.pruned_ng, tpb);
   if (ng < 1) return hipErrorInvalidValue;
   const int N2 = tpb * 16 / B, N1 = N / N2;
-  const int G = N1 / (B * ng);
+  const int G = (int)ceil_div(N1, B) / ng;
   const int64_t per_thread = ceil_div(a.l, tpb);
   const int kpt = per_thread <= 2 ? 2 : (per_thread <= 4 ? 4 : (per_thread <= 8 ? 8 : (per_thread <= 16 ? 16 : 32)));
   const FftPlan pl2 = make_plan(N2);
@@ -881,7 +906,11 @@ static hipError_t sketch_impl(const SketchArgs& a, hipStream_t st) {
   const V* A = reinterpret_cast<const V*>(a.A);
   V* S = reinterpret_cast<V*>(a.S);
   const int Lmax = max_lds_fft_len<C>();
-  if (N <= Lmax) {
+  const bool p2 = (N & (N - 1)) == 0;
+  // a length that is not a power of two runs only in the kept-outputs-only
+  // form (the radix plans below cover powers of two only)
+  if (!p2 && a.pruned_b <= 0) return hipErrorInvalidValue;
+  if (p2 && N <= Lmax) {
     FftPlan pl = make_plan(N);
     const int B = fft_batch<C>(N);
     const size_t sm = (size_t)B * lds_stride(N) * sizeof(C);
@@ -928,7 +957,9 @@ static hipError_t sketch_impl(const SketchArgs& a, hipStream_t st) {
 
 int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng, int tpb) {
   const bool sp = dtype == 1 || dtype == 3;
-  if (N <= (sp ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>())) return 0;  // one-workgroup transform
+  const bool p2 = N > 0 && (N & (N - 1)) == 0;
+  // a power of two that fits one workgroup's LDS takes the whole-row transform
+  if (p2 && N <= (sp ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>())) return 0;
   return sp ? pruned_groups<cf>(N, l, B, ng, tpb) : pruned_groups<cd>(N, l, B, ng, tpb);
 }
 
@@ -1055,10 +1086,18 @@ __global__ void __launch_bounds__(256, 2) kb_sketch_pruned(const BSys* __restric
   const int i = bgrid_find(grid, nsys, blockIdx.x);
   const BSys& s = sys[i];
   using R = typename VT<C>::real;
-  k_sketch_pruned_body<V, C, 16, KPT>(bgrid_local(grid[i], (int)blockIdx.x - grid[i].start),
-                                      reinterpret_cast<const V*>(s.Ab), s.ldab, 0, s.m, s.n, s.N1, s.N1 / 16, s.pl_b,
-                                      s.d, s.idx, s.order, s.l, reinterpret_cast<const C*>(s.tw),
-                                      reinterpret_cast<V*>(s.S), s.l, nullptr, (R)(1.0 / sqrt((double)s.N)));
+  const Bk bk = bgrid_local(grid[i], (int)blockIdx.x - grid[i].start);
+  const R scale = (R)(1.0 / sqrt((double)s.N));
+  if ((s.N1 & (s.N1 - 1)) == 0)
+    k_sketch_pruned_body<V, C, 16, KPT, 256, true>(bk, reinterpret_cast<const V*>(s.Ab), s.ldab, 0, s.m, s.n, s.N1,
+                                                   s.N1 / 16, s.pl_b, s.d, s.idx, s.order, s.l,
+                                                   reinterpret_cast<const C*>(s.tw), reinterpret_cast<V*>(s.S), s.l,
+                                                   nullptr, scale);
+  else
+    k_sketch_pruned_body<V, C, 16, KPT, 256, false>(bk, reinterpret_cast<const V*>(s.Ab), s.ldab, 0, s.m, s.n, s.N1,
+                                                    (s.N1 + 15) / 16, s.pl_b, s.d, s.idx, s.order, s.l,
+                                                    reinterpret_cast<const C*>(s.tw), reinterpret_cast<V*>(s.S), s.l,
+                                                    nullptr, scale);
 }
 
 __global__ void __launch_bounds__(1024) kb_sketch_order(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
@@ -1089,7 +1128,8 @@ template <typename C> void plan_sketch_t(BSys& s, BGrid& small, BGrid& cols, BGr
   pruned = BGrid{0, 0, 1, 1};
   ls = lc = lr = lp = 0;
   s.sk_kpt = 0;
-  if (N <= max_lds_fft_len<C>()) {
+  const bool p2 = (N & (N - 1)) == 0;
+  if (p2 && N <= max_lds_fft_len<C>()) {
     s.pl_a = make_plan(N);
     s.fft_ba = fft_batch<C>(N);
     s.N1 = N;
@@ -1171,7 +1211,8 @@ void b_plan_sketch(int dtype, BSys& s, BGrid& small, BGrid& cols, BGrid& rows, B
 
 int64_t b_sketch_work_elems(int dtype, int64_t m, int64_t N, int64_t l) {
   const int L = (dtype == 1 || dtype == 3) ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>();
-  if (N <= L || (l <= 2048 && sketch_pruned_groups(dtype, N, l, 16, 1) > 0)) return 0;
+  const bool p2 = (N & (N - 1)) == 0;
+  if ((p2 && N <= L) || (l <= 2048 && sketch_pruned_groups(dtype, N, l, 16, 1) > 0)) return 0;
   return m * N;
 }
 

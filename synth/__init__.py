@@ -10,6 +10,7 @@ from .gen import (  # noqa: F401
     real_gaussian,
     haar_columns,
     next_pow2,
+    next_fft_len,
     sketch_width,
     draw_srft,
     draw_hfactor,

@@ -58,6 +58,14 @@ def next_pow2(n: int) -> int:
     return 1 if n <= 1 else 1 << (n - 1).bit_length()
 
 
+def next_fft_len(n: int) -> int:
+    """A transform length N >= n that is not restricted to powers of two: the
+    power of two when n <= 512, else the smallest multiple of 256 >= n."""
+    if n <= 512:
+        return next_pow2(n)
+    return -(-n // 256) * 256
+
+
 def sketch_width(m: int, N: int, factor: int = 4) -> int:
     """l = 4m as Remarks 5.6 and the cost section advise, capped at N."""
     return int(min(factor * int(m), int(N)))

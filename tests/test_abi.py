@@ -58,7 +58,10 @@ def test_sketch_argument_errors():
     assert call(n=0) == -4
     assert call(A=None) == -5
     assert call(lda=9) == -6
-    assert call(N=12) == -7          # not a power of two
+    assert call(N=12) == -7          # neither a power of two nor N1 x 2^k with 2^k >= 256
+    assert call(n=700, lda=700, N=769) == -7
+    # N = 79 x 256: its kept-outputs-only form holds at most 2048 complex128 outputs per row
+    assert call(n=20000, lda=20000, N=20224, l=3000, lds=3000) == -7
     assert call(N=8) == -7           # N < n
     assert call(N=1 << 23) == -7     # too long
     assert call(l=0) == -8
@@ -110,6 +113,7 @@ def test_solve_argument_errors():
     assert call(eps=0.0) == -12
     assert call(eps=1.0) == -12
     assert call(N=24) == -13
+    assert call(n=20000, lda=20000, ldx=20000, N=20224, l=3000) == -13
     assert call(l=4) == -14         # l must exceed m
     assert call(l=17) == -14
     assert call(d=None) == -15      # one of d, idx without the other
@@ -133,7 +137,7 @@ def test_draw_argument_errors():
     assert lib.srft_draw(h, 4, 1, 0, 0, 16, 8, p, p) == -2
     assert lib.srft_draw(h, 0, 1, -1, 0, 16, 8, p, p) == -4
     assert lib.srft_draw(h, 0, 1, 0, -1, 16, 8, p, p) == -5
-    assert lib.srft_draw(h, 0, 1, 0, 0, 24, 8, p, p) == -6
+    assert lib.srft_draw(h, 0, 1, 0, 0, 0, 8, p, p) == -6
     assert lib.srft_draw(h, 0, 1, 0, 0, 1 << 23, 8, p, p) == -6
     assert lib.srft_draw(h, 0, 1, 0, 0, 16, 0, p, p) == -7
     assert lib.srft_draw(h, 0, 1, 0, 0, 16, 17, p, p) == -7

@@ -12,13 +12,13 @@ import oracle
 import synth
 
 
-@pytest.mark.parametrize("N", [1, 2, 8, 16, 64])
+@pytest.mark.parametrize("N", [1, 2, 8, 16, 64, 3, 12, 20, 768])
 def test_dft_unitary(N):
     F = oracle.dft_matrix(N)
     assert np.allclose(F @ F.conj().T, np.eye(N), atol=1e-13)
 
 
-@pytest.mark.parametrize("N", [2, 8, 32, 64])
+@pytest.mark.parametrize("N", [2, 8, 32, 64, 3, 12, 20, 768])
 def test_fft_matches_dense_dft(N):
     g = np.random.default_rng(N)
     X = g.standard_normal((5, N)) + 1j * g.standard_normal((5, N))
@@ -26,8 +26,8 @@ def test_fft_matches_dense_dft(N):
     assert np.allclose(oracle.fft_ortho(X, axis=1), X @ F.T, atol=1e-13)
 
 
-def test_dft_closed_forms():
-    N = 16
+@pytest.mark.parametrize("N", [16, 12, 768])
+def test_dft_closed_forms(N):
     j = np.arange(N)
     # impulse at 0 -> constant 1/sqrt(N)
     e0 = np.zeros(N, complex); e0[0] = 1
@@ -43,7 +43,7 @@ def test_dft_closed_forms():
     assert np.allclose(out, ref, atol=1e-13)
 
 
-@pytest.mark.parametrize("N", [2, 8, 32])
+@pytest.mark.parametrize("N", [2, 8, 32, 3, 12, 20])
 def test_dht_orthonormal_symmetric(N):
     H = oracle.dht_matrix(N)
     assert np.allclose(H, H.T)
@@ -67,7 +67,8 @@ def test_srft_rows_orthonormal(N, l):
     assert np.allclose(Tr @ Tr.T, np.eye(l), atol=1e-13)
 
 
-@pytest.mark.parametrize("m,n,N,l", [(3, 8, 8, 6), (4, 13, 16, 12), (5, 40, 64, 20), (1, 2, 2, 2)])
+@pytest.mark.parametrize("m,n,N,l", [(3, 8, 8, 6), (4, 13, 16, 12), (5, 40, 64, 20), (1, 2, 2, 2),
+                                     (4, 11, 12, 7), (3, 700, 768, 50)])
 def test_sketch_equals_dense_T_times_Astar(m, n, N, l):
     g = np.random.default_rng(m * n)
     A = g.standard_normal((m, n)) + 1j * g.standard_normal((m, n))
@@ -80,7 +81,7 @@ def test_sketch_equals_dense_T_times_Astar(m, n, N, l):
     assert np.allclose(S, T @ Astar_pad, atol=1e-13)
 
 
-@pytest.mark.parametrize("m,n,N,l", [(3, 8, 8, 6), (4, 13, 16, 12), (5, 40, 64, 20)])
+@pytest.mark.parametrize("m,n,N,l", [(3, 8, 8, 6), (4, 13, 16, 12), (5, 40, 64, 20), (4, 11, 12, 7)])
 def test_sketch_real_equals_dense(m, n, N, l):
     g = np.random.default_rng(m + n)
     A = g.standard_normal((m, n))
@@ -144,3 +145,20 @@ def test_lemma_3_1_least_singular_value():
         TQ = oracle.srft_matrix(N, d, idx) @ (H @ Q)
         fails += np.linalg.svd(TQ, compute_uv=False)[-1] < np.sqrt(l / (alpha * N))
     assert fails / trials <= 1.0 / beta
+
+
+@pytest.mark.parametrize("N", [12, 20, 768])
+def test_dft_four_step_identity_any_length(N):
+    """For N = N1 N2 (N1 any integer), the kept-outputs-only form's identity
+    V[k] = sum_{n1} W_N^{n1 k} Z_{n1}[k mod N2], Z_{n1} = DFT_{N2} of
+    v[n1 + N1 n2] (eq. DFT regrouped), holds for the oracle's transform."""
+    N2 = 4 if N in (12, 20) else 256
+    N1 = N // N2
+    g = np.random.default_rng(N)
+    v = g.standard_normal(N) + 1j * g.standard_normal(N)
+    V = oracle.fft_ortho(v) * np.sqrt(N)
+    Z = np.array([np.fft.fft(v[n1::N1]) for n1 in range(N1)])
+    k = np.arange(N)
+    W = np.exp(-2j * np.pi * np.outer(np.arange(N1), k) / N)
+    Vk = np.sum(W * Z[:, k % N2], axis=0)
+    assert np.allclose(Vk, V, atol=1e-10 * np.abs(V).max())
