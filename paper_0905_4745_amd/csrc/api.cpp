@@ -500,9 +500,31 @@ bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, in
   const bool cplx = is_complex(dtype);
   const int64_t W = cplx ? 16 : 8;
   void* G = ws(h, "gram_G", (size_t)(m * m * W));
-  // G = S* S: FP64 matrix-core product (plan 0) or register-tiled FP64
-  // product on the vector units (plan 1)
+  // G = S* S: FP64 matrix-core product in the block GEMM's Hermitian mode
+  // (plan 0), register-tiled FP64 product on the vector units (plan 1), or
+  // the dedicated FP64 matrix-core Gram kernel (plan 2)
   auto run = [&](int pl) {
+    if (pl == 2) {
+      // split K so that the active tiles fill whole rounds of 1024
+      // workgroups (four per CU) as nearly as possible
+      const int64_t mt = cdiv(m, herk_mf_tile()), tiles = mt * (mt + 1) / 2;
+      int best = 1;
+      double best_eff = 0.0;
+      for (int sp = 1; sp <= 8; ++sp) {
+        if (sp > 1 && l / sp < 256) break;
+        const double rounds = (double)(tiles * sp) / 1024.0;
+        const double eff = rounds / std::ceil(rounds);
+        if (eff > best_eff + 0.02) {
+          best_eff = eff;
+          best = sp;
+        }
+      }
+      const int64_t ks = rup(cdiv(l, best), 16);
+      const int splits = (int)cdiv(l, ks);
+      void* Cp = splits > 1 ? ws(h, "herk_part", (size_t)(herk_part_elems(m, splits) * W)) : nullptr;
+      ck(launch_herk_mf(dtype, S, lds, l, m, G, m, Cp, splits, ks, st));
+      return;
+    }
     if (pl == 1) {
       const int64_t tiles = std::max<int64_t>(1, cdiv(m, 128) * cdiv(m, 64) / 2);
       int64_t splits = std::min<int64_t>(std::min<int64_t>(std::max<int64_t>(cdiv(512, tiles), 1), 8), cdiv(l, 64));
@@ -524,9 +546,9 @@ bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, in
     ck(launch_gram_s(dtype, S, lds, l, m, G, m, Cp, ldc, (int)splits, ks, st));
     if (splits > 1) ck(launch_gram_fold(cplx, Cp, (int)splits, ldc, m, G, m, st));
   };
-  int pl = m > 1024 ? 1 : 0;
+  int pl = 2;
   const std::string key = plan_key("gram_s", dtype, m, l, 0);
-  if (o) pl = plan_get(h, *o, key, {pl, 1 - pl}, run);
+  if (o) pl = plan_get(h, *o, key, {2, 1, 0}, run);
   else plan_find(h, key, &pl);
   run(pl);
   int32_t* bad = (int32_t*)ws(h, "chol_bad", 16);
@@ -539,7 +561,7 @@ bool gram_factor(mn_handle h, int dtype, int64_t l, int64_t m, const void* S, in
   double* dr = (double*)ws(h, "qr_diag", (size_t)(4 + 2 * kPow) * 8);
   ck(launch_rdiag_range(cplx ? MN_C128 : MN_F64, R64, m, m, dr, st));
   ck(launch_fill0(dr + 4, 2 * kPow * 8, st));
-  if (X != nullptr) ck(launch_power_sq(cplx, R64, m, X, ldx, m, ws(h, "cond_pw", (size_t)(6 * m * W)), dr + 4, kPow, st));
+  if (X != nullptr) ck(launch_power_sq(cplx, R64, m, X, ldx, m, ws(h, "cond_pw", (size_t)(power_work_elems(m) * W)), dr + 4, kPow, st));
   ck(hipMemcpyAsync(h->host_diag, dr, (size_t)(4 + 2 * kPow) * 8, hipMemcpyDeviceToHost, st));
   ck(hipMemcpyAsync(h->host_flag, bad, 4, hipMemcpyDeviceToHost, st));
   ck(hipStreamSynchronize(st));
@@ -900,7 +922,10 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
       fa.qpart = v.qpart;
       int chunks = 1;
       fa.chunks_out = &chunks;
-      if (fused_res) {
+      if (outer == 0) {
+        // y_outer = 0: the residual is b itself (no pass over A)
+        cg_start(c, v, b, nullptr, 0, y_outer);
+      } else if (fused_res) {
         ck(launch_resid_tall(c.dtype, res_at, rldt, m, n, y_outer, res_x, res_part, kResG, qdd, h->stream));
         x_current = true;
         cg_start(c, v, b, qdd, 1, y_outer);
@@ -1834,8 +1859,11 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     for (int outer = 0; outer <= o.max_refine + 1; ++outer) {
       // r = b - A (A* y_outer) in FP64: one fused pass over FP64 data (its
       // instances for single-precision problem data with m > 256 would spill
-      // registers, so those keep the two passes A* then A)
-      if (!is_single(dtype)) {
+      // registers, so those keep the two passes A* then A); y_outer = 0 at
+      // the first step, whose residual is b itself
+      if (outer == 0) {
+        ck(launch_b_cg(cplx, L(cgs), L(cgp), 1, 0, 1, par, cg_lds, st));
+      } else if (!is_single(dtype)) {
         const BLaunch gl[4] = {L(gramR[0]), L(gramR[1]), L(gramR[2]), L(gramR[3])};
         ck(launch_b_gram_res(dtype, gl, L(gred), st));
         ck(launch_b_cg(cplx, L(cgs), L(cgp), 1, 2, 1, par, cg_lds, st));

@@ -421,70 +421,87 @@ __global__ void __launch_bounds__(256) k_pw_adj(PwPair P, int64_t m, const W* __
   if (lane == 0) g[t * m + j] = a;
 }
 
-// u_i = sum_{j >= i} T_ij g_j for one 64-row block per workgroup: lane = row,
-// the eight waves take every eighth column (each load a contiguous 64-entry
-// piece of a column), then the waves' sums are added in wave order.
-// grid (ceil(m / 64), 2), 512 threads.
+// u_i = sum_{j >= i} T_ij g_j, one 64-row block and one chunk of kPwCols
+// columns per workgroup: lane = row, the eight waves take every eighth
+// column of the chunk (each load a contiguous 64-entry piece of a column),
+// then the waves' sums are added in wave order into the chunk's partial
+// u_part[t][chunk][row] (zero for a chunk left of the block's diagonal).
+// grid (ceil(m / 64), chunks, 2), 512 threads.
+constexpr int kPwCols = 512;
+
 template <typename W>
-__global__ void __launch_bounds__(512) k_pw_fwd(PwPair P, int64_t m, const W* __restrict__ g, W* __restrict__ u) {
+__global__ void __launch_bounds__(512) k_pw_fwd(PwPair P, int64_t m, const W* __restrict__ g, W* __restrict__ upart) {
   __shared__ W part[8][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int t = blockIdx.y;
+  const int t = blockIdx.z;
   const W* T = reinterpret_cast<const W*>(P.T[t]);
   const int64_t ldt = P.ld[t];
   const W* gt = g + t * m;
   const int64_t r0 = (int64_t)blockIdx.x * 64, r = r0 + lane;
+  const int64_t jb = (int64_t)blockIdx.y * kPwCols;
+  const int64_t je = jb + kPwCols < m ? jb + kPwCols : m;
   W a0 = vzero<W>(), a1 = vzero<W>();
-  int64_t j = r0 + wv;
-  for (; j + 8 < m; j += 16) {
+  int64_t j = (jb > r0 ? jb : r0) + wv;
+  for (; j + 8 < je; j += 16) {
     if (r <= j) a0 = vfma(T[r + j * ldt], gt[j], a0);
     if (r <= j + 8) a1 = vfma(T[r + (j + 8) * ldt], gt[j + 8], a1);
   }
-  if (j < m && r <= j) a0 = vfma(T[r + j * ldt], gt[j], a0);
+  if (j < je && r <= j) a0 = vfma(T[r + j * ldt], gt[j], a0);
   part[wv][lane] = vadd(a0, a1);
   __syncthreads();
   if (wv == 0 && r < m) {
     W a = part[0][lane];
 #pragma unroll
     for (int w = 1; w < 8; ++w) a = vadd(a, part[w][lane]);
-    u[t * m + r] = a;
+    upart[((int64_t)t * gridDim.y + blockIdx.y) * m + r] = a;
   }
 }
 
-// workgroup t: out[t * stride + slot] = ||u_t|| (slot >= 0), v_t = u_t /
-// ||u_t|| when the norm is positive and finite (else v_t keeps its entries).
-// grid 2, 1024 threads.
+// workgroup t: u_t = the sum of its chunk partials (in chunk order);
+// out[t * stride + slot] = ||u_t|| (slot >= 0), v_t = u_t / ||u_t|| when the
+// norm is positive and finite (else v_t keeps its entries).  grid 2, 1024
+// threads.  With chunks = 0, u_t = upart_t itself (one vector).
 template <typename W>
-__global__ void __launch_bounds__(1024) k_pw_norm(const W* __restrict__ u, int64_t m, W* __restrict__ v,
-                                                  double* __restrict__ out, int stride, int slot) {
+__global__ void __launch_bounds__(1024) k_pw_norm(const W* __restrict__ upart, int chunks, int64_t m,
+                                                  W* __restrict__ v, double* __restrict__ out, int stride, int slot) {
   __shared__ double red[16];
   const int t = blockIdx.x;
-  const W* ut = u + t * m;
+  const int nc = chunks > 0 ? chunks : 1;
+  const W* ut = upart + (int64_t)t * nc * m;
   W* vt = v + t * m;
+  auto u_at = [&](int64_t i) {
+    W a = ut[i];
+    for (int c = 1; c < nc; ++c) a = vadd(a, ut[(int64_t)c * m + i]);
+    return a;
+  };
   double s2 = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += 1024) s2 += vabs2(ut[i]);
+  for (int64_t i = threadIdx.x; i < m; i += 1024) s2 += vabs2(u_at(i));
   const double s = sqrt(block_sum(s2, red));
   if (threadIdx.x == 0 && slot >= 0) out[t * stride + slot] = s;
   if (!(s > 0.0) || !isfinite(s)) return;
-  const double r = 1.0 / s;
-  for (int64_t i = threadIdx.x; i < m; i += 1024) vt[i] = vscale(ut[i], r);
+  const double rs = 1.0 / s;
+  for (int64_t i = threadIdx.x; i < m; i += 1024) vt[i] = vscale(u_at(i), rs);
 }
 
 template <typename W>
 hipError_t power_t(const PwPair& P, int64_t m, void* work, double* out, int steps, hipStream_t st) {
+  const int nch = (int)ceil_div(m, kPwCols);
   W* v = reinterpret_cast<W*>(work);
   W* g = v + 2 * m;
-  W* u = v + 4 * m;
+  W* up = v + 4 * m;
   hipLaunchKernelGGL((k_pw_init<W>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, m, v);
-  hipLaunchKernelGGL((k_pw_norm<W>), dim3(2), dim3(1024), 0, st, v, m, v, out, steps, -1);
+  hipLaunchKernelGGL((k_pw_norm<W>), dim3(2), dim3(1024), 0, st, v, 0, m, v, out, steps, -1);
   for (int k = 0; k < steps; ++k) {
     hipLaunchKernelGGL((k_pw_adj<W>), dim3((unsigned)ceil_div(m, 4), 2), dim3(256), 0, st, P, m, v, g);
-    hipLaunchKernelGGL((k_pw_fwd<W>), dim3((unsigned)ceil_div(m, 64), 2), dim3(512), 0, st, P, m, g, u);
-    hipLaunchKernelGGL((k_pw_norm<W>), dim3(2), dim3(1024), 0, st, u, m, v, out, steps, k);
+    hipLaunchKernelGGL((k_pw_fwd<W>), dim3((unsigned)ceil_div(m, 64), (unsigned)nch, 2), dim3(512), 0, st, P, m, g,
+                       up);
+    hipLaunchKernelGGL((k_pw_norm<W>), dim3(2), dim3(1024), 0, st, up, nch, m, v, out, steps, k);
   }
   return hipGetLastError();
 }
 }  // namespace
+
+int64_t power_work_elems(int64_t m) { return (4 + 2 * ceil_div(m, kPwCols)) * m; }
 
 hipError_t launch_power_sq(bool cplx, const void* T0, int64_t ld0, const void* T1, int64_t ld1, int64_t m, void* work,
                            double* out, int steps, hipStream_t st) {

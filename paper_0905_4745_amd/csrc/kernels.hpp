@@ -301,6 +301,11 @@ int gram_col_block(int dtype);
 int64_t herk_part_elems(int64_t m, int splits);
 hipError_t launch_herk(int dtype, const void* S, int64_t lds, int64_t l, int64_t m, void* G, int64_t ldg, void* Cp,
                        int splits, int64_t ks, hipStream_t st);
+// The same product on the FP64 matrix cores: 64 x 64 tiles of G, split K as
+// launch_herk (same partial layout, herk_part_elems).
+hipError_t launch_herk_mf(int dtype, const void* S, int64_t lds, int64_t l, int64_t m, void* G, int64_t ldg,
+                          void* Cp, int splits, int64_t ks, hipStream_t st);
+int herk_mf_tile();
 hipError_t launch_gram_s(int dtype, const void* S, int64_t lds, int64_t l, int64_t m, void* G, int64_t ldg,
                          double* Cp, int64_t ldc, int splits, int64_t ks, hipStream_t st);
 hipError_t launch_gram_fold(bool cplx, const double* Cp, int splits, int64_t ldc, int64_t m, void* G, int64_t ldg,
@@ -316,7 +321,8 @@ hipError_t launch_chol(bool cplx, void* G, int64_t ldg, int64_t m, void* R, int6
 // Power steps on T T* for two upper triangular FP64 matrices T0, T1 (ld0,
 // ld1) at once: out[t * steps + k] (k < steps) = ||T_t T_t* v_k|| with v_0 a
 // fixed unit vector and v_{k+1} the normalised product; each is a lower
-// bound of sigma_max(T_t)^2.  work: 6 m entries (wide).
+// bound of sigma_max(T_t)^2.  work: power_work_elems(m) entries (wide).
+int64_t power_work_elems(int64_t m);
 hipError_t launch_power_sq(bool cplx, const void* T0, int64_t ld0, const void* T1, int64_t ld1, int64_t m, void* work,
                            double* out, int steps, hipStream_t st);
 
