@@ -647,30 +647,39 @@ template <typename V> constexpr int colmajor_tw() {
   return 1024 / (int)sizeof(V) < 64 ? 1024 / (int)sizeof(V) : (1024 / (int)sizeof(V) > 128 ? 128 : 1024 / (int)sizeof(V));
 }
 
-// First level of the sum over workgroup partials: q8[gr * m + i] = sum of
-// qpart[g * m + i] over the gr-th eighth of g, in a fixed order.
-// grid = (ceil(m/64), 8), 256 threads (64 rows x 4 interleaved quarters).
+// q[i] = sum over the pass's G workgroup partials qpart[g * m + i], in a
+// fixed order: 16 rows per workgroup, the 16 lane groups of a row each take
+// every sixteenth g, then the group sums are added in group order.
+// grid = ceil(m / 16), 256 threads.
 template <typename U>
 __device__ __forceinline__ void k_gram_reduce_body(const Bk bk, const U* __restrict__ qpart, int G, int64_t m,
-                                                     U* __restrict__ q8, const int32_t* __restrict__ flag) {
+                                                     U* __restrict__ q, const int32_t* __restrict__ flag) {
   if (stopped(flag)) return;
-  __shared__ U red[4][64];
-  const int rr = threadIdx.x & 63, quarter = threadIdx.x >> 6;
-  const int64_t i = (int64_t)bk.x * 64 + rr;
-  const int per = (G + 7) / 8;
-  const int g0 = bk.y * per, g1 = (g0 + per) < G ? (g0 + per) : G;
-  U acc = vzero<U>();
-  if (i < m)
-    for (int g = g0 + quarter; g < g1; g += 4) acc = vadd(acc, qpart[(int64_t)g * m + i]);
-  red[quarter][rr] = acc;
+  __shared__ U red[16][16];
+  const int rr = threadIdx.x & 15, part = threadIdx.x >> 4;
+  const int64_t i = (int64_t)bk.x * 16 + rr;
+  U a0 = vzero<U>(), a1 = vzero<U>();
+  if (i < m) {
+    int g = part;
+    for (; g + 16 < G; g += 32) {
+      a0 = vadd(a0, qpart[(int64_t)g * m + i]);
+      a1 = vadd(a1, qpart[(int64_t)(g + 16) * m + i]);
+    }
+    if (g < G) a0 = vadd(a0, qpart[(int64_t)g * m + i]);
+  }
+  red[part][rr] = vadd(a0, a1);
   __syncthreads();
-  if (quarter == 0 && i < m)
-    q8[(int64_t)bk.y * m + i] = vadd(vadd(red[0][rr], red[1][rr]), vadd(red[2][rr], red[3][rr]));
+  if (part == 0 && i < m) {
+    U t = red[0][rr];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) t = vadd(t, red[k][rr]);
+    q[i] = t;
+  }
 }
 template <typename U>
 __global__ void __launch_bounds__(256) k_gram_reduce(const U* __restrict__ qpart, int G, int64_t m,
-                                                     U* __restrict__ q8, const int32_t* __restrict__ flag) {
-  k_gram_reduce_body<U>(bk_hw(), qpart, G, m, q8, flag);
+                                                     U* __restrict__ q, const int32_t* __restrict__ flag) {
+  k_gram_reduce_body<U>(bk_hw(), qpart, G, m, q, flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -796,7 +805,7 @@ static hipError_t gram_go(const GramArgs& a, hipStream_t st) {
     hipExtLaunchKernelGGL((k_gram<V, C, U, CPT, 8, 512, VEC>), dim3((unsigned)G), dim3(512), 0, st, a.ev_begin,
                           a.ev_end, 0, A, a.lda, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
   }
-  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64), 8), dim3(256), 0, st, qpart, (int)G,
+  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 16)), dim3(256), 0, st, qpart, (int)G,
                      a.m, reinterpret_cast<U*>(a.q), a.flag);
   return hipGetLastError();
 }
@@ -828,7 +837,7 @@ static hipError_t gram_cm_go(const GramArgs& a, hipStream_t st) {
   else
     hipExtLaunchKernelGGL((k_gram_cm<V, C, U, 2, 8>), dim3((unsigned)G), dim3(512), 0, st, a.ev_begin, a.ev_end, 0,
                           At, a.ldt, a.m, a.n, p, spw, nstrips, qpart, a.flag, a.interleave);
-  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64), 8), dim3(256), 0, st, qpart, (int)G,
+  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 16)), dim3(256), 0, st, qpart, (int)G,
                      a.m, reinterpret_cast<U*>(a.q), a.flag);
   return hipGetLastError();
 }
@@ -867,7 +876,7 @@ static hipError_t gram_tall_go(const GramArgs& a, hipStream_t st) {
       default: tall_launch<V, C, U, 16, 1, 2, 256>(a, G, st); break;
     }
   }
-  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 64), 8), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_gram_reduce<U>), dim3((unsigned)ceil_div(a.m, 16)), dim3(256), 0, st,
                      reinterpret_cast<const U*>(a.qpart), (int)G, a.m, reinterpret_cast<U*>(a.q), a.flag);
   return hipGetLastError();
 }
@@ -1073,7 +1082,7 @@ template <typename V> int plan_gram_t(BSys& s, BGrid& gram, BGrid& red) {
     s.cm_spw = ceil_div(s.cm_nstrips, G);
   }
   gram = BGrid{0, (int)G, 1, 1};
-  red = BGrid{0, (int)ceil_div(s.m, 64), 8, 1};
+  red = BGrid{0, (int)ceil_div(s.m, 16), 1, 1};
   // rows per thread class: 512 threads hold 64 RPT rows
   return s.m <= 64 ? 0 : s.m <= 128 ? 1 : s.m <= 256 ? 2 : 3;
 }

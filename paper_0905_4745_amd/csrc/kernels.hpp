@@ -151,7 +151,7 @@ hipError_t launch_gemv_fwd_dd(int dtype, const FwdArgs& a, void* q, hipStream_t 
 constexpr int kGramMaxRows = 512;
 constexpr int kGramTallMaxRows = 2048;
 constexpr int kGramMaxWg = 1024;  // partial sums per row (largest workgroup count)
-constexpr int kGramParts = 8;    // slices of q left for the CG kernel to add
+constexpr int kGramParts = 1;    // slices of q left for the CG kernel to add
 struct GramArgs {
   const void* A;
   int64_t lda, m, n;
