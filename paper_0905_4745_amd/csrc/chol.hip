@@ -201,7 +201,11 @@ __global__ void __launch_bounds__(256) k_chol_diag0(V* __restrict__ G, int64_t l
 // k (nbk - k) workgroups for block step k - 1 of X = R^{-1} (its inputs, R's
 // block row k - 1 and X_kk, come from the previous launch; k = nbk - 1 runs
 // only those).
-template <typename V>
+//
+// SEP: block row k of R comes from a separate launch before this one
+// (k_chol_panel), so the grid holds only the trailing tiles (and the X
+// workgroups) and each trailing tile reads R_ki, R_kj instead of forming them.
+template <typename V, bool SEP = false>
 __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G, int64_t ldg, int64_t m, int k, int nbk,
                                                    V* __restrict__ R, int64_t ldr, V* __restrict__ Yd, V* X,
                                                    int64_t ldx, int32_t* __restrict__ bad) {
@@ -211,18 +215,19 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
   __shared__ double piv[CB];
   __shared__ double rinv[CB];
   const int nrow = nbk - k - 1;
-  const int nchol = nrow + nrow * (nrow + 1) / 2;
+  const int npanel = SEP ? 0 : nrow;
+  const int nchol = npanel + nrow * (nrow + 1) / 2;
   if (bk.x >= nchol) {
     trtri_tile(bk.x - nchol, k - 1, nbk, m, R, ldr, X, ldx, TA, TB);
     return;
   }
   int bi, bj;
   int w = bk.x;
-  if (w < nrow) {
+  if (w < npanel) {
     bi = k;
     bj = k + 1 + w;
   } else {
-    w -= nrow;
+    w -= npanel;
     bi = k + 1;
     int len = nbk - bi;
     while (w >= len) {
@@ -234,8 +239,9 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
   }
   const int r = threadIdx.x % CB, cg = threadIdx.x / CB;
   const V* yd = Yd + (int64_t)k * CB * CB;
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) Y[(e % CB) + (e / CB) * LDC] = yd[e];
-  if (bi == k) {
+  if (!SEP)
+    for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) Y[(e % CB) + (e / CB) * LDC] = yd[e];
+  if (!SEP && bi == k) {
     tile_in(TA, G, ldg, m, k, bj);
     __syncthreads();
     V acc[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
@@ -259,6 +265,15 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
     const int64_t gr = (int64_t)bi * CB + r, gc = (int64_t)bj * CB + cg + 8 * u;
     gij[u] = (gr < m && gc < m) ? G[gr + gc * ldg] : vzero<V>();
   }
+  if constexpr (SEP) {
+    // TA <- R_ki^* (rows of P^* contiguous for the product), TB <- R_kj
+    for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+      const int rr = e % CB, cc = e / CB;
+      const int64_t gr = (int64_t)k * CB + rr, gci = (int64_t)bi * CB + cc, gcj = (int64_t)bj * CB + cc;
+      TA[cc + rr * LDC] = (gr < m && gci < m) ? vconj(R[gr + gci * ldr]) : vzero<V>();
+      TB[rr + cc * LDC] = (gr < m && gcj < m) ? R[gr + gcj * ldr] : vzero<V>();
+    }
+  } else {
   tile_in(TA, G, ldg, m, k, bi);
   if (bj != bi) tile_in(TB, G, ldg, m, k, bj);
   __syncthreads();
@@ -279,6 +294,7 @@ __device__ __forceinline__ void k_chol_step_body(const Bk bk, V* __restrict__ G,
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) TA[(cg + 8 * u) + r * LDC] = vconj(p[u]);
+  }
   }
   __syncthreads();
   V acc[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
@@ -307,20 +323,57 @@ __global__ void __launch_bounds__(256) k_chol_step(V* __restrict__ G, int64_t ld
 }
 
 template <typename V>
+__global__ void __launch_bounds__(256) k_chol_step_sep(V* __restrict__ G, int64_t ldg, int64_t m, int k, int nbk,
+                                                       V* __restrict__ R, int64_t ldr, V* __restrict__ Yd, V* X,
+                                                       int64_t ldx, int32_t* __restrict__ bad) {
+  k_chol_step_body<V, true>(bk_hw(), G, ldg, m, k, nbk, R, ldr, Yd, X, ldx, bad);
+}
+
+// Block row k of R: tile (k, k + 1 + w) = Y_kk G_k,k+1+w (and its mirrored
+// strictly lower tile zeroed).  grid = nbk - k - 1.
+template <typename V>
+__global__ void __launch_bounds__(256) k_chol_panel(const V* __restrict__ G, int64_t ldg, int64_t m, int k,
+                                                    V* __restrict__ R, int64_t ldr, const V* __restrict__ Yd) {
+  __shared__ V Y[CB * LDC];
+  __shared__ V TA[CB * LDC];
+  const int bj = k + 1 + (int)blockIdx.x;
+  const int r = threadIdx.x % CB, cg = threadIdx.x / CB;
+  const V* yd = Yd + (int64_t)k * CB * CB;
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) Y[(e % CB) + (e / CB) * LDC] = yd[e];
+  tile_in(TA, G, ldg, m, k, bj);
+  __syncthreads();
+  V acc[4] = {vzero<V>(), vzero<V>(), vzero<V>(), vzero<V>()};
+  tile_mm(Y, TA, acc);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t gr = (int64_t)k * CB + r, gc = (int64_t)bj * CB + cg + 8 * u;
+    if (gr < m && gc < m) R[gr + gc * ldr] = acc[u];
+    const int64_t lr = (int64_t)bj * CB + r, lc = (int64_t)k * CB + cg + 8 * u;
+    if (lr < m && lc < m) R[lr + lc * ldr] = vzero<V>();
+  }
+}
+
+// Two launches per block step: block row k of R (k_chol_panel), then the
+// trailing tiles, which read it (one 32 x 32 product each instead of three),
+// the factorisation of diagonal tile k + 1 and block step k - 1 of X.
+template <typename V>
 hipError_t chol_impl(void* G, int64_t ldg, int64_t m, void* R, int64_t ldr, void* Yd, void* X, int64_t ldx,
                      int32_t* bad, hipStream_t st) {
   const int nbk = (int)ceil_div(m, CB);
   V* Xv = reinterpret_cast<V*>(X);
-  hipLaunchKernelGGL((k_chol_diag0<V>), dim3(1), dim3(256), 0, st, reinterpret_cast<V*>(G), ldg, m,
-                     reinterpret_cast<V*>(R), ldr, reinterpret_cast<V*>(Yd), Xv, ldx, bad);
+  V* Gv = reinterpret_cast<V*>(G);
+  V* Rv = reinterpret_cast<V*>(R);
+  V* Ydv = reinterpret_cast<V*>(Yd);
+  hipLaunchKernelGGL((k_chol_diag0<V>), dim3(1), dim3(256), 0, st, Gv, ldg, m, Rv, ldr, Ydv, Xv, ldx, bad);
   for (int k = 0; k < nbk; ++k) {
     const int nrow = nbk - k - 1;
     const int ntrail = (nbk - k - 1) * (nbk - k) / 2;
     const int ntri = (X && k >= 1) ? k * (nbk - k) : 0;
-    if (nrow + ntrail + ntri == 0) continue;
-    hipLaunchKernelGGL((k_chol_step<V>), dim3((unsigned)(nrow + ntrail + ntri)), dim3(256), 0, st,
-                       reinterpret_cast<V*>(G), ldg, m, k, nbk, reinterpret_cast<V*>(R), ldr,
-                       reinterpret_cast<V*>(Yd), Xv, ldx, bad);
+    if (nrow > 0)
+      hipLaunchKernelGGL((k_chol_panel<V>), dim3((unsigned)nrow), dim3(256), 0, st, Gv, ldg, m, k, Rv, ldr, Ydv);
+    if (ntrail + ntri == 0) continue;
+    hipLaunchKernelGGL((k_chol_step_sep<V>), dim3((unsigned)(ntrail + ntri)), dim3(256), 0, st, Gv, ldg, m, k, nbk,
+                       Rv, ldr, Ydv, Xv, ldx, bad);
   }
   return hipGetLastError();
 }
