@@ -442,8 +442,10 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, in
 // intermediate nor the discarded outputs reach memory; the outer sum costs
 // l N1 = l N / N2 multiply-adds per row, so with N2 near l (the wide form)
 // the row costs O(N log N2) for the column transforms plus about 8 N flops
-// for the outer sum: O(N log l).  The factors W_N^{n1 k} of
-// one block come from one table entry and a recurrence in n1.  Thread slot
+// for the outer sum: O(N log l).  A block's share of the outer sum is
+// W_N^{c0 k} times a polynomial in W_N^k with the block's B values Z as
+// coefficients, evaluated by Horner's rule (one table entry for W_N^{c0 k},
+// one for W_N^k, one complex multiply-add per column).  Thread slot
 // q = tid + TPB u takes kept output order[q]: the order groups outputs of
 // equal k mod N2 (k_sketch_order), so the lanes of a wave read a few LDS
 // addresses (broadcast) rather than 64 scattered ones.  With one column
@@ -601,26 +603,26 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
     // Z of the block is in LDS (the last stage ends with a barrier); the
     // next block's loads fly during the outer sum
     if (g + 1 < G) load(c0 + B);
-    // two kept outputs at a time (two independent recurrences interleave;
-    // the scheduling barrier keeps the next pair's LDS reads from being
-    // hoisted into this one's registers)
+    // two kept outputs at a time (two independent chains interleave; the
+    // scheduling barrier keeps the next pair's LDS reads from being hoisted
+    // into this one's registers).  The block's share
+    //   sum_b W_N^{(c0 + b) k} Z_{c0+b} = W_N^{c0 k} sum_b (W_N^k)^b Z_{c0+b}
+    // is evaluated by Horner's rule (one complex multiply-add per column)
 #pragma unroll
     for (int u = 0; u < KPT; u += 2) {
       const unsigned k0 = kept(u), k1 = kept(u + 1);
-      C w0 = tw[modn((unsigned)c0, k0)], w1 = tw[modn((unsigned)c0, k1)];  // W_N^{c0 k}
-      const C st0 = tw[k0], st1 = tw[k1];                                       // W_N^k
+      const C w0 = tw[modn((unsigned)c0, k0)], w1 = tw[modn((unsigned)c0, k1)];  // W_N^{c0 k}
+      const C st0 = tw[k0], st1 = tw[k1];                                         // W_N^k
       const C* zp0 = sm + lpad((int)(k0 & (unsigned)(N2 - 1)));
       const C* zp1 = sm + lpad((int)(k1 & (unsigned)(N2 - 1)));
-      C a0 = acc[u], a1 = acc[u + 1];
+      C h0 = zp0[(B - 1) * Lp], h1 = zp1[(B - 1) * Lp];
 #pragma unroll
-      for (int b = 0; b < B; ++b) {
-        a0 = vfma(w0, zp0[b * Lp], a0);
-        a1 = vfma(w1, zp1[b * Lp], a1);
-        w0 = vmul(w0, st0);
-        w1 = vmul(w1, st1);
+      for (int b = B - 2; b >= 0; --b) {
+        h0 = vfma(h0, st0, zp0[b * Lp]);
+        h1 = vfma(h1, st1, zp1[b * Lp]);
       }
-      acc[u] = a0;
-      acc[u + 1] = a1;
+      acc[u] = vfma(w0, h0, acc[u]);
+      acc[u + 1] = vfma(w1, h1, acc[u + 1]);
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
