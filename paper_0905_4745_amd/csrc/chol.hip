@@ -569,23 +569,25 @@ hipError_t launch_power_sq(bool cplx, const void* T0, int64_t ld0, const void* T
 
 namespace {
 // sigma_max(T)^2 record after `steps` power steps on T T* (T upper, FP64,
-// ld ldt), the same steps as launch_power_sq, inside one workgroup of 256
-// threads: g = T* v a wave per column, u = T g a 64-row block at a time
-// (lane = row, the waves taking every fourth column).
+// ld ldt), the same steps as launch_power_sq, inside one workgroup of
+// kBPowT threads: g = T* v a wave per column, u = T g a 64-row block at a
+// time (lane = row, the waves taking every kBPowW-th column).
+constexpr int kBPowT = 1024, kBPowW = kBPowT / 64;
+
 template <typename W>
 __device__ double b_power_one(const W* __restrict__ T, int64_t ldt, int64_t m, W* v, W* g, W* u, int steps,
                               double* red, W (*part)[64]) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  for (int64_t i = t; i < m; i += 256) v[i] = pw_start<W>(i);
+  for (int64_t i = t; i < m; i += kBPowT) v[i] = pw_start<W>(i);
   __syncthreads();
   double s2 = 0.0;
-  for (int64_t i = t; i < m; i += 256) s2 += vabs2(v[i]);
+  for (int64_t i = t; i < m; i += kBPowT) s2 += vabs2(v[i]);
   const double nrm = sqrt(block_sum(s2, red));
-  for (int64_t i = t; i < m; i += 256) v[i] = vscale(v[i], 1.0 / nrm);
+  for (int64_t i = t; i < m; i += kBPowT) v[i] = vscale(v[i], 1.0 / nrm);
   double rec = 0.0;
   for (int k = 0; k < steps; ++k) {
     __syncthreads();
-    for (int64_t j = wv; j < m; j += 4) {
+    for (int64_t j = wv; j < m; j += kBPowW) {
       W a = vzero<W>();
       for (int64_t i = lane; i <= j; i += 64) a = vcfma(T[i + j * ldt], v[i], a);
       a = wave_sum(a);
@@ -597,15 +599,16 @@ __device__ double b_power_one(const W* __restrict__ T, int64_t ldt, int64_t m, W
       const int64_t r = r0 + lane;
       W a0 = vzero<W>(), a1 = vzero<W>();
       int64_t j = r0 + wv;
-      for (; j + 4 < m; j += 8) {
+      for (; j + kBPowW < m; j += 2 * kBPowW) {
         if (r <= j) a0 = vfma(T[r + j * ldt], g[j], a0);
-        if (r <= j + 4) a1 = vfma(T[r + (j + 4) * ldt], g[j + 4], a1);
+        if (r <= j + kBPowW) a1 = vfma(T[r + (j + kBPowW) * ldt], g[j + kBPowW], a1);
       }
       if (j < m && r <= j) a0 = vfma(T[r + j * ldt], g[j], a0);
       part[wv][lane] = vadd(a0, a1);
       __syncthreads();
       if (wv == 0 && r < m) {
-        const W a = vadd(vadd(part[0][lane], part[1][lane]), vadd(part[2][lane], part[3][lane]));
+        W a = part[0][lane];
+        for (int w = 1; w < kBPowW; ++w) a = vadd(a, part[w][lane]);
         u[r] = a;
         s2 += vabs2(a);
       }
@@ -613,16 +616,16 @@ __device__ double b_power_one(const W* __restrict__ T, int64_t ldt, int64_t m, W
     }
     rec = sqrt(block_sum(s2, red));
     if (!(rec > 0.0) || !isfinite(rec)) return rec;
-    for (int64_t i = t; i < m; i += 256) v[i] = vscale(u[i], 1.0 / rec);
+    for (int64_t i = t; i < m; i += kBPowT) v[i] = vscale(u[i], 1.0 / rec);
   }
   return rec;
 }
 
 template <typename W>
-__global__ void __launch_bounds__(256) kb_power(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
-                                                int nsys, int steps) {
-  __shared__ double red[4];
-  __shared__ W part[4][64];
+__global__ void __launch_bounds__(kBPowT) kb_power(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                   int nsys, int steps) {
+  __shared__ double red[kBPowW];
+  __shared__ W part[kBPowW][64];
   const int i = bgrid_find(grid, nsys, blockIdx.x);
   const BSys& s = sys[i];
   const int64_t m = s.m;
@@ -637,8 +640,10 @@ __global__ void __launch_bounds__(256) kb_power(const BSys* __restrict__ sys, co
 
 hipError_t launch_b_power(bool cplx, const BLaunch& L, int steps, hipStream_t st) {
   if (L.total == 0) return hipSuccess;
-  if (cplx) hipLaunchKernelGGL(kb_power<cd>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, steps);
-  else hipLaunchKernelGGL(kb_power<double>, dim3((unsigned)L.total), dim3(256), 0, st, L.sys, L.grid, L.nsys, steps);
+  if (cplx)
+    hipLaunchKernelGGL(kb_power<cd>, dim3((unsigned)L.total), dim3(kBPowT), 0, st, L.sys, L.grid, L.nsys, steps);
+  else
+    hipLaunchKernelGGL(kb_power<double>, dim3((unsigned)L.total), dim3(kBPowT), 0, st, L.sys, L.grid, L.nsys, steps);
   return hipGetLastError();
 }
 
