@@ -47,8 +47,8 @@ DEFAULT_PLANS = os.path.join(ROOT, "paper_0905_4745_amd", "plans", "mi355x.json"
 # plain 1 GiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the
 # kernel source it was measured on: a changed source reports null.
 MEASURED_TRAFFIC = {
-    "k_gram_cm": {"bytes": 539.14e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-                  "sha256": "6aec2ea2bd8e3631a42988db9dc8f50d8bfe0db068036f981d8e53fb59ed64fa",
+    "k_gram_cm": {"bytes": 539.15e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
+                  "sha256": "07d248ae3ff4a38391fd9babe8c18b77909efdde318cd779a4775db80548e414",
                   "plan_key": "gram/0/512/65536/0", "plan": 655616},
 }
 
@@ -79,12 +79,14 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="columns (default: the workload's)")
     ap.add_argument("--kappa", type=float, default=None, help="cond(A) (default: the workload's)")
     ap.add_argument("--eps", type=float, default=1e-10)
-    ap.add_argument("--workload", choices=("plain", "multirhs", "batched", "mixed"), default="mixed",
+    ap.add_argument("--l", type=int, default=None, help="householder: sketch rows (default 4 m)")
+    ap.add_argument("--workload", choices=("plain", "multirhs", "batched", "mixed", "householder"), default="mixed",
                     help="mixed (default): complex128 2048 x 262144 at cond 1e6 with a complex64 copy "
                          "(FP64 refinement), beside the FP64 GPU path; plain: 512 x 65536 complex128 "
                          "cond 1e3, FP64 throughout; multirhs: complex64 rows scaled by 10^U(-2,2), "
                          "64 RHS through the block path; batched: 256 uneven real systems (FP64 data + "
-                         "FP32 copies) in one batched call")
+                         "FP32 copies) in one batched call; householder: Step 2's Householder QR "
+                         "(build_preconditioner) of a random complex64 l x m sketch (default 8192 x 2048)")
     ap.add_argument("--fp64-steps", type=int, default=None,
                     help="mixed: timed solves of the FP64 GPU path (default: steps / 2, at least 2; 0 skips it)")
     ap.add_argument("--inner-digits", type=int, default=None,
@@ -145,7 +147,35 @@ def main():
         return main_batched(args)
     if args.workload == "mixed":
         return main_mixed(args)
+    if args.workload == "householder":
+        return main_householder(args)
     return main_plain(args)
+
+
+def main_householder(args):
+    """Step 2's Householder QR (the fallback factorisation) of a random complex64 sketch."""
+    import torch
+
+    from paper_0905_4745_amd import api
+
+    dev = torch.device("cuda:0")
+    m = args.m or 2048
+    l = args.l or 4 * m
+    g = torch.Generator(device=dev).manual_seed(1)
+    S = torch.randn((m, l), dtype=torch.complex64, device=dev, generator=g).t()  # column-major l x m
+    for _ in range(args.warmup):
+        api.build_preconditioner(S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        api.build_preconditioner(S)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"metric": "Householder factorisations/s", "value": 1.0 / dt, "unit": "factorisations/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+                      "data": "synthetic", "config": {"workload": f"Householder QR of a {l} x {m} complex64 sketch",
+                                                      "l": l, "m": m}}), flush=True)
 
 
 def main_plain(args):
@@ -575,8 +605,8 @@ def cpu_baseline_classical(A_dev, b_dev, m, n):
 # MEASURED_TRAFFIC: the A copy once, plus the workgroups' q partials written);
 # valid while the source and the plan are the measured ones
 MEASURED_TRAFFIC_MIXED = {
-    "k_gram_tall": {"bytes": 4312112000.0, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-                    "sha256": "13676a381cfa603c9c3c450ceddc9673be69505945e570e0c54adec64b79551d",
+    "k_gram_tall": {"bytes": 4312113357.0, "source": "paper_0905_4745_amd/csrc/gemv.hip",
+                    "sha256": "07d248ae3ff4a38391fd9babe8c18b77909efdde318cd779a4775db80548e414",
                     "plan_key": "gram/1/2048/262144/1", "plan": 524800},
 }
 

@@ -11,7 +11,7 @@
 // broadcast) and over the group's waves in wave order through LDS, rounds it
 // once to FP64 -- exactly what the two-pass form stores between its passes --
 // and adds A_rc w_c to the rows' double-double accumulators.  Each workgroup
-// leaves (hi, lo) partials of q; a fold adds them in workgroup order and
+// leaves (hi, lo) partials of q; a fold adds them in a fixed order and
 // rounds once.  The column sums are written as x = A* y when asked for.
 // Rows m .. ldt - 1 of the copy are not read.
 #include "common.hpp"
@@ -185,19 +185,33 @@ __global__ void __launch_bounds__(TPB) k_resid_tall(const V* __restrict__ At, in
   }
 }
 
-// q[i] = the workgroups' (hi, lo) partials merged in workgroup order, rounded once
+// q[i] = the workgroups' (hi, lo) partials merged in a fixed order, rounded
+// once: 16 rows per workgroup, the 16 lane groups of a row each merge every
+// sixteenth partial, then the group sums are merged in group order.
+// grid ceil(m / 16), 256 threads.
 template <typename W>
 __global__ void __launch_bounds__(256) k_resid_fold(const W* __restrict__ qh, const W* __restrict__ ql, int G,
                                                     int64_t m, W* __restrict__ q) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= m) return;
+  __shared__ dd2 red[2][16][16];
+  const int rr = threadIdx.x & 15, part = threadIdx.x >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + rr;
   dd2 re{0.0, 0.0}, im{0.0, 0.0};
-  for (int g = 0; g < G; ++g) {
-    const W h = qh[(int64_t)g * m + i], l = ql[(int64_t)g * m + i];
-    d2_merge(re, dd2{vre(h), vre(l)});
-    if constexpr (VT<W>::cplx) d2_merge(im, dd2{vim(h), vim(l)});
+  if (i < m)
+    for (int g = part; g < G; g += 16) {
+      const W h = qh[(int64_t)g * m + i], l = ql[(int64_t)g * m + i];
+      d2_merge(re, dd2{vre(h), vre(l)});
+      if constexpr (VT<W>::cplx) d2_merge(im, dd2{vim(h), vim(l)});
+    }
+  red[0][part][rr] = re;
+  red[1][part][rr] = im;
+  __syncthreads();
+  if (part == 0 && i < m) {
+    for (int k = 1; k < 16; ++k) {
+      d2_merge(re, red[0][k][rr]);
+      d2_merge(im, red[1][k][rr]);
+    }
+    q[i] = vmake<W>(d2_round(re), d2_round(im));
   }
-  q[i] = vmake<W>(d2_round(re), d2_round(im));
 }
 
 template <typename V, typename W>
@@ -217,7 +231,7 @@ static hipError_t resid_t(const void* At, int64_t ldt, int64_t m, int64_t n, con
   else
     hipLaunchKernelGGL((k_resid_tall<V, W, 8, 4, 256>), dim3((unsigned)G), dim3(256), 0, st, a, ldt, m, n, yy, xo, qh,
                        ql);
-  hipLaunchKernelGGL((k_resid_fold<W>), dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, st, qh, ql, G, m,
+  hipLaunchKernelGGL((k_resid_fold<W>), dim3((unsigned)ceil_div(m, 16)), dim3(256), 0, st, qh, ql, G, m,
                      reinterpret_cast<W*>(q));
   return hipGetLastError();
 }
