@@ -290,73 +290,105 @@ def minnorm_solve(A, b, eps: float, d, idx, N: int, A_lo=None, opts: SolveOption
     return out, info.as_dict()
 
 
+class BatchedSystems:
+    """A validated batch of independent systems for repeated batched solves.
+
+    The matrices (and optional single-precision copies), right-hand sides and
+    transform lengths are checked once and their pointer arrays built once;
+    the solution vectors are allocated once and reused (their contents are
+    overwritten by every solve).  Each solve() passes the tolerances, the
+    SRFT draws (or the library draw with opts.seed) and the options.
+    """
+
+    def __init__(self, As, bs, Ns, A_los=None):
+        batch = len(As)
+        code = _check_matrix(As[0])
+        wide = _WIDE[code]
+        dev = As[0].device
+        if len(bs) != batch or len(Ns) != batch:
+            raise ValueError("As, bs and Ns must have one entry per system")
+        if A_los is not None and len(A_los) != batch:
+            raise ValueError("A_los must have one entry per system (or be None)")
+        single = _SINGLE_OF.get(code)
+        xs = []
+        for i, A in enumerate(As):
+            if _check_matrix(A) != code:
+                raise ValueError("all systems must share one dtype")
+            if A.device != dev:
+                raise ValueError("all systems must live on one device")
+            m_i, n_i = A.shape
+            b = bs[i]
+            if (b.dtype != wide or not b.is_cuda or b.device != dev or b.dim() != 1 or b.numel() != m_i
+                    or (b.stride(0) != 1 and m_i > 1)):
+                raise ValueError(f"b[{i}] must be a contiguous device {wide} vector of {m_i} entries")
+            if A_los is not None:
+                lo = A_los[i]
+                # the library reads A_lo[i] with A[i]'s leading dimension
+                if (lo.dtype != single or lo.shape != A.shape or lo.device != dev
+                        or (lo.stride(1) != 1 and n_i > 1) or _ld(lo, 0, n_i) != _ld(A, 0, n_i)):
+                    raise ValueError(f"A_los[{i}] must be the single-precision copy of As[{i}] "
+                                     "with the same leading dimension")
+            xs.append(torch.empty(n_i, dtype=wide, device=dev))
+        I64 = C.c_int64 * batch
+        PP = C.c_void_p * batch
+        self.batch, self.code, self.device = batch, code, dev
+        self._keep = (list(As), list(bs), None if A_los is None else list(A_los))
+        self.m_list = [A.shape[0] for A in As]
+        self.N_list = [int(v) for v in Ns]
+        self.m = I64(*self.m_list)
+        self.n = I64(*[A.shape[1] for A in As])
+        self.lda = I64(*[_ld(A, 0, A.shape[1]) for A in As])
+        self.Ap = PP(*[A.data_ptr() for A in As])
+        self.Alo = PP(*[a.data_ptr() for a in A_los]) if A_los is not None else None
+        self.bp = PP(*[b.data_ptr() for b in bs])
+        self.Na = I64(*self.N_list)
+        self.xs = xs
+        self.xp = PP(*[t.data_ptr() for t in xs])
+
+    def solve(self, eps, ds=None, idxs=None, opts: SolveOptions | None = None, raise_on_status: bool = True,
+              ls=None):
+        """Solve every system; returns (xs, infos).  ds = idxs = None: the
+        library draws (opts.seed, sys = the system's index) with sketch widths
+        ls (default min(4 m_i, N_i))."""
+        batch = self.batch
+        lib_draw = ds is None and idxs is None
+        if (ds is None) != (idxs is None):
+            raise ValueError("pass both ds and idxs, or neither (library draws)")
+        if lib_draw:
+            ls = [int(v) for v in ls] if ls is not None else [min(4 * m, N) for m, N in zip(self.m_list, self.N_list)]
+            if len(ls) != batch:
+                raise ValueError("ls must have one entry per system")
+            dp = ip = None
+        else:
+            if len(ds) != batch or len(idxs) != batch:
+                raise ValueError("ds and idxs must have one entry per system")
+            dts = [_d_tensor(d, self.code, self.device) for d in ds]
+            its = [_idx_tensor(idx, self.device) for idx in idxs]
+            ls = [t.numel() for t in its]
+            PP = C.c_void_p * batch
+            dp = PP(*[t.data_ptr() for t in dts])
+            ip = PP(*[t.data_ptr() for t in its])
+        epsa = (C.c_double * batch)(*([float(eps)] * batch if isinstance(eps, (int, float)) else list(eps)))
+        la = (C.c_int64 * batch)(*ls)
+        infos = (L.MnInfo * batch)()
+        o = (opts or SolveOptions()).to_c()
+        st = L.load().minnorm_solve_batched(_handle(self.device), self.code, batch, self.m, self.n, self.Ap,
+                                            self.lda, self.Alo, self.bp, epsa, self.Na, la, dp, ip, C.byref(o),
+                                            self.xp, infos)
+        if st != 0 and raise_on_status:
+            raise MinnormError("minnorm_solve_batched", st)
+        return self.xs, [i.as_dict() for i in infos]
+
+
 def minnorm_solve_batched(As, bs, eps, ds, idxs, Ns, A_los=None, opts: SolveOptions | None = None,
                           raise_on_status: bool = True, ls=None):
     """Independent systems of uneven sizes in one call; returns (xs, infos).
 
     ds = idxs = None: the library draws every system's (d, idx) (srft_draw with
     opts.seed and sys = the system's index), sketch widths ls (default
-    min(4 m_i, N_i)).
+    min(4 m_i, N_i)).  Repeated solves of one batch: BatchedSystems.
     """
-    batch = len(As)
-    code = _check_matrix(As[0])
-    wide = _WIDE[code]
-    dev = As[0].device
-    lib_draw = ds is None and idxs is None
-    if (ds is None) != (idxs is None):
-        raise ValueError("pass both ds and idxs, or neither (library draws)")
-    if lib_draw:
-        ls = [int(v) for v in ls] if ls is not None else [min(4 * A.shape[0], int(N)) for A, N in zip(As, Ns)]
-        if len(ls) != batch:
-            raise ValueError("ls must have one entry per system")
-    if len(bs) != batch or len(Ns) != batch or (not lib_draw and (len(ds) != batch or len(idxs) != batch)):
-        raise ValueError("As, bs, ds, idxs and Ns must have one entry per system")
-    if A_los is not None and len(A_los) != batch:
-        raise ValueError("A_los must have one entry per system (or be None)")
-    xs, dts, its = [], [], []
-    for i, A in enumerate(As):
-        if _check_matrix(A) != code:
-            raise ValueError("all systems must share one dtype")
-        if A.device != dev:
-            raise ValueError("all systems must live on one device")
-        m_i, n_i = A.shape
-        b = bs[i]
-        if (b.dtype != wide or not b.is_cuda or b.device != dev or b.dim() != 1 or b.numel() != m_i
-                or (b.stride(0) != 1 and m_i > 1)):
-            raise ValueError(f"b[{i}] must be a contiguous device {wide} vector of {m_i} entries")
-        if A_los is not None:
-            lo = A_los[i]
-            # the library reads A_lo[i] with A[i]'s leading dimension
-            if (lo.dtype != _SINGLE_OF.get(code) or lo.shape != A.shape or lo.device != dev
-                    or (lo.stride(1) != 1 and n_i > 1) or _ld(lo, 0, n_i) != _ld(A, 0, n_i)):
-                raise ValueError(f"A_los[{i}] must be the single-precision copy of As[{i}] "
-                                 "with the same leading dimension")
-        xs.append(torch.empty(n_i, dtype=wide, device=dev))
-    if not lib_draw:
-        for d, idx in zip(ds, idxs):
-            dts.append(_d_tensor(d, code, dev))
-            its.append(_idx_tensor(idx, dev))
-    I64 = C.c_int64 * batch
-    PP = C.c_void_p * batch
-    m = I64(*[A.shape[0] for A in As])
-    n = I64(*[A.shape[1] for A in As])
-    lda = I64(*[_ld(A, 0, A.shape[1]) for A in As])
-    Ap = PP(*[A.data_ptr() for A in As])
-    Alo = PP(*[a.data_ptr() for a in A_los]) if A_los is not None else None
-    bp = PP(*[b.data_ptr() for b in bs])
-    epsa = (C.c_double * batch)(*([float(eps)] * batch if isinstance(eps, (int, float)) else list(eps)))
-    Na = I64(*[int(v) for v in Ns])
-    la = I64(*(ls if lib_draw else [t.numel() for t in its]))
-    dp = None if lib_draw else PP(*[t.data_ptr() for t in dts])
-    ip = None if lib_draw else PP(*[t.data_ptr() for t in its])
-    xp = PP(*[t.data_ptr() for t in xs])
-    infos = (L.MnInfo * batch)()
-    o = (opts or SolveOptions()).to_c()
-    st = L.load().minnorm_solve_batched(_handle(dev), code, batch, m, n, Ap, lda, Alo, bp, epsa, Na, la, dp, ip,
-                                        C.byref(o), xp, infos)
-    if st != 0 and raise_on_status:
-        raise MinnormError("minnorm_solve_batched", st)
-    return xs, [i.as_dict() for i in infos]
+    return BatchedSystems(As, bs, Ns, A_los).solve(eps, ds, idxs, opts, raise_on_status, ls)
 
 
 def workspace_bytes(device=None) -> int:

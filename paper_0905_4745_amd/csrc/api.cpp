@@ -434,6 +434,43 @@ void draw_srft_into(mn_handle h, bool cplx, uint64_t seed, int draw, int sys, in
   ck(hipStreamSynchronize(h->stream));
 }
 
+// The same for several systems (draw 0, sys = the system's index): every
+// system's phases are launched, all index sets are drawn into one pinned
+// buffer and copied, and the stream is synchronised once.
+void draw_srft_batch(mn_handle h, bool cplx, uint64_t seed, int batch, const int64_t* N, const int64_t* l,
+                     void* const* d, int32_t* const* idx) {
+  size_t total = 0;
+  for (int i = 0; i < batch; ++i) total += (size_t)l[i];
+  if (h->host_draw_n < total) {
+    if (h->host_draw) {
+      ck(hipStreamSynchronize(h->stream));
+      ck(hipHostFree(h->host_draw));
+      h->host_draw = nullptr;
+      h->host_draw_n = 0;
+    }
+    ck(hipHostMalloc((void**)&h->host_draw, total * sizeof(int32_t), hipHostMallocDefault));
+    h->host_draw_n = total;
+  }
+  std::vector<size_t> off((size_t)batch + 1, 0);
+  for (int i = 0; i < batch; ++i) off[i + 1] = off[i] + (size_t)l[i];
+  // the phases on the device, the index sets meanwhile on host threads (the
+  // systems are independent; nothing that throws runs while they do)
+  for (int i = 0; i < batch; ++i) ck(launch_draw_phases(cplx, seed, 0, i, N[i], d[i], h->stream));
+  const int nt = (int)std::max<unsigned>(1u, std::min<unsigned>(std::min(16u, std::thread::hardware_concurrency()),
+                                                                   (unsigned)batch));
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t)
+    pool.emplace_back([&, t]() {
+      for (int i = t; i < batch; i += nt) draw_indices(seed, 0, i, N[i], l[i], h->host_draw + off[i]);
+    });
+  for (int i = 0; i < batch; i += nt) draw_indices(seed, 0, i, N[i], l[i], h->host_draw + off[i]);
+  for (auto& th : pool) th.join();
+  for (int i = 0; i < batch; ++i)
+    ck(hipMemcpyAsync(idx[i], h->host_draw + off[i], (size_t)l[i] * sizeof(int32_t), hipMemcpyHostToDevice,
+                      h->stream));
+  ck(hipStreamSynchronize(h->stream));
+}
+
 // Redraws after a rank-deficient sketch when the library draws (max_reseed:
 // 0 = the default 2, -1 = none).
 int reseeds_of(const mn_opts& o) { return o.max_reseed == 0 ? 2 : (o.max_reseed < 0 ? 0 : o.max_reseed); }
@@ -2403,13 +2440,17 @@ int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* 
         char* ibase = (char*)ws(h, "bdraw_idx", (size_t)in);
         dv.resize(batch);
         iv.resize(batch);
+        std::vector<void*> dw((size_t)batch);
+        std::vector<int32_t*> iw((size_t)batch);
         for (int32_t i = 0; i < batch; ++i) {
-          draw_srft_into(h, is_complex(dtype), o.seed, 0, i, N[i], l[i], dbase, (int32_t*)ibase);
+          dw[i] = dbase;
+          iw[i] = (int32_t*)ibase;
           dv[i] = dbase;
           iv[i] = (const int32_t*)ibase;
           dbase += a256(N[i] * (is_complex(dtype) ? 16 : 8));
           ibase += a256(l[i] * 4);
         }
+        draw_srft_batch(h, is_complex(dtype), o.seed, batch, N, l, dw.data(), iw.data());
       }
       solve_batched_fused(h, dtype, batch, m, n, A, lda, A_lo, b, eps, N, l, lib_draw ? dv.data() : d,
                           lib_draw ? iv.data() : idx, o, x, info, stv, redo);

@@ -474,16 +474,18 @@ __global__ void __launch_bounds__(256) k_pw_adj(PwPair P, int64_t m, const W* __
   if (lane == 0) g[t * m + j] = a;
 }
 
-// u_i = sum_{j >= i} T_ij g_j, one 64-row block and one chunk of kPwCols
-// columns per workgroup: lane = row, the eight waves take every eighth
-// column of the chunk (each load a contiguous 64-entry piece of a column),
-// then the waves' sums are added in wave order into the chunk's partial
-// u_part[t][chunk][row] (zero for a chunk left of the block's diagonal).
-// grid (ceil(m / 64), chunks, 2), 512 threads.
-constexpr int kPwCols = 512;
+// u_i = sum_{j >= i} T_ij g_j, one 64-row block and one chunk of cw columns
+// per workgroup: lane = row, the eight waves take every eighth column of the
+// chunk (each load a contiguous 64-entry piece of a column), then the waves'
+// sums are added in wave order into the chunk's partial u_part[t][chunk][row]
+// (zero for a chunk left of the block's diagonal).  grid (ceil(m / 64),
+// chunks, 2), 512 threads.  The chunk width pw_cols(m) gives small m enough
+// workgroups and large m few partials.
+__host__ __device__ inline int64_t pw_cols(int64_t m) { return m <= 1024 ? 64 : (m <= 4096 ? 256 : 512); }
 
 template <typename W>
 __global__ void __launch_bounds__(512) k_pw_fwd(PwPair P, int64_t m, const W* __restrict__ g, W* __restrict__ upart) {
+  const int64_t cw = pw_cols(m);
   __shared__ W part[8][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = blockIdx.z;
@@ -491,8 +493,8 @@ __global__ void __launch_bounds__(512) k_pw_fwd(PwPair P, int64_t m, const W* __
   const int64_t ldt = P.ld[t];
   const W* gt = g + t * m;
   const int64_t r0 = (int64_t)blockIdx.x * 64, r = r0 + lane;
-  const int64_t jb = (int64_t)blockIdx.y * kPwCols;
-  const int64_t je = jb + kPwCols < m ? jb + kPwCols : m;
+  const int64_t jb = (int64_t)blockIdx.y * cw;
+  const int64_t je = jb + cw < m ? jb + cw : m;
   W a0 = vzero<W>(), a1 = vzero<W>();
   int64_t j = (jb > r0 ? jb : r0) + wv;
   for (; j + 8 < je; j += 16) {
@@ -538,7 +540,7 @@ __global__ void __launch_bounds__(1024) k_pw_norm(const W* __restrict__ upart, i
 
 template <typename W>
 hipError_t power_t(const PwPair& P, int64_t m, void* work, double* out, int steps, hipStream_t st) {
-  const int nch = (int)ceil_div(m, kPwCols);
+  const int nch = (int)ceil_div(m, pw_cols(m));
   W* v = reinterpret_cast<W*>(work);
   W* g = v + 2 * m;
   W* up = v + 4 * m;
@@ -554,7 +556,7 @@ hipError_t power_t(const PwPair& P, int64_t m, void* work, double* out, int step
 }
 }  // namespace
 
-int64_t power_work_elems(int64_t m) { return (4 + 2 * ceil_div(m, kPwCols)) * m; }
+int64_t power_work_elems(int64_t m) { return (4 + 2 * ceil_div(m, pw_cols(m))) * m; }
 
 hipError_t launch_power_sq(bool cplx, const void* T0, int64_t ld0, const void* T1, int64_t ld1, int64_t m, void* work,
                            double* out, int steps, hipStream_t st) {

@@ -449,3 +449,29 @@ def test_mixed_kappa_1e6_512x65536():
         f"cert {info['cert_rel']:.2e} rho0 {info['rho0']:.2e} rho {info['rho']:.2e} xi {info['xi']:.2e}")
     assert info["status"] == 0
     assert rel(to_np(x), p) <= 1e-10
+
+
+def test_batched_systems_reuse():
+    """A batch validated once (api.BatchedSystems) and solved repeatedly: each
+    solve equals the one-shot batched call with the same library draws (bitwise:
+    the same kernels on the same data), and every solve meets the oracle's
+    bar."""
+    import torch
+    from paper_0905_4745_amd import api
+    shapes = [(40, 2300), (64, 5000), (32, 1000), (100, 4000)]
+    systems = [synth.make_svd(m, n, 1e3, seed=80 + i)[:2] for i, (m, n) in enumerate(shapes)]
+    As = [to_dev(A) for A, _ in systems]
+    bs = [to_dev(b) for _, b in systems]
+    A_los = [A.to(torch.complex64) for A in As]
+    Ns = [synth.next_pow2(n) for _, n in shapes]
+    batch = api.BatchedSystems(As, bs, Ns, A_los)
+    for seed in (3, 4):
+        opts = api.SolveOptions(seed=seed)
+        xs, infos = batch.solve(1e-10, opts=opts)
+        xs = [x.clone() for x in xs]
+        ys, _ = api.minnorm_solve_batched(As, bs, 1e-10, None, None, Ns, A_los=A_los, opts=opts)
+        for i, (A, b) in enumerate(systems):
+            assert torch.equal(xs[i], ys[i])
+            err = rel(to_np(xs[i]), oracle.refined_minnorm(A, b))
+            say(f"  seed {seed} system {i}: status {infos[i]['status']} err {err:.1e}")
+            assert infos[i]["status"] == 0 and err <= 1e-10
