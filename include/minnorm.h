@@ -317,7 +317,8 @@ int srft_sketch_h(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, i
  * allocate: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same arguments, result and errors as srft_sketch, for
  * N <= 65536 (-7 beyond).  Its scratch (the twiddle table, the inverse
- * subsample map, the kept-output order and the four-step work area) lives in
+ * subsample map, the kept-output order with its twiddle table and the
+ * four-step work area) lives in
  * a static device array of 32 MiB that the library holds on every GPU it
  * runs on until the process ends; the array's device address is looked up
  * once per device by mn_create.  Calls that overlap on one GPU (different

@@ -336,7 +336,7 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
       a.order = a.pruned_b ? ar->order : nullptr;
     } else {
       a.work = per_row > 0 ? ws(h, "fft_y", (size_t)(chunk * per_row * ces)) : nullptr;
-      a.order = a.pruned_b ? (int32_t*)ws(h, "sk_order", (size_t)l * 4) : nullptr;
+      a.order = a.pruned_b ? (int32_t*)ws(h, "sk_order", (size_t)sketch_order_bytes(l, single)) : nullptr;
     }
     ck(launch_sketch(dtype, a, h->stream));
   };
@@ -344,12 +344,10 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
   // groups per row for 512 workgroups (two per CU).  For single-precision
   // sketches with 2048 < l <= 8192 it is a tuning candidate only: at
   // 2048 x 262144 (l = 8192) it measured no faster than the full four-step.
-  // For larger l the wide form with B = 16 (N2 = 512), groups enough for
-  // 256 workgroups: at 2048 x 262144 complex64, l = 8192, it measured 6.68
-  // ms against 9.35 ms for the full four-step (B = 8: 7.17, B = 4: 8.41; the
-  // strided column loads, 16 B-wide runs at B = 4, not the outer sum, set
-  // the pace); at 4096 x 131072, l = 16384, B = 8 measured best (8.87 ms
-  // against 9.32), a tuning candidate.
+  // For larger l the wide form with B = 8 (N2 = 1024: half the outer sum of
+  // B = 16), groups enough for 256 workgroups: at 2048 x 262144 complex64,
+  // l = 8192, it measured 4.46 ms against 4.72 ms for B = 16 and 9.35 ms
+  // for the full four-step; at 4096 x 131072, l = 16384, 6.99 ms.
   int mb = 64;
   if (!p2) {
     // N = N1 2^k: the first kept-outputs-only shape that applies, with
@@ -370,11 +368,16 @@ void run_sketch(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int
     int lg = 0;
     while ((m << lg) < 512 && lg < 10) ++lg;
     mb = 64 | (1 << 19) | (lg << 21);
-  } else if (sketch_pruned_groups(dtype, N, l, 16, 1, wide_tpb) > 0) {
-    int lg = 0;
-    while ((m << lg) < 256 && lg < 10 && sketch_pruned_groups(dtype, N, l, 16, 1 << (lg + 1), wide_tpb) == (1 << (lg + 1)))
-      ++lg;
-    mb = 64 | (1 << 19) | (lg << 21) | (1 << 25);
+  } else {
+    for (int bc : {2, 1}) {
+      if (sketch_pruned_groups(dtype, N, l, pruned_b[bc], 1, wide_tpb) < 1) continue;
+      int lg = 0;
+      while ((m << lg) < 256 && lg < 10 &&
+             sketch_pruned_groups(dtype, N, l, pruned_b[bc], 1 << (lg + 1), wide_tpb) == (1 << (lg + 1)))
+        ++lg;
+      mb = 64 | (bc << 19) | (lg << 21) | (1 << 25);
+      break;
+    }
   }
   const std::string key = plan_key("sketch_chunk_mb", dtype, m, N, 0);
   if (o) {
@@ -1608,7 +1611,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     // 16-byte vectors
     const int64_t pad_ld = (use_cm || b_aligned16(q.Ab, q.ldab, bulk)) ? 0 : rup(n[i], std::max<int64_t>(16 / be, 1));
     wbytes[i] = a256(pad_ld * mm * be) + (use_cm ? a256(rup(mm, 64) * n[i] * be) : 0) + a256(N[i] * 4) +
-                a256(l[i] * 4) + a256(l[i] * mm * be) +
+                a256(sketch_order_bytes(l[i], is_single(bulk))) + a256(l[i] * mm * be) +
                 a256(b_sketch_work_elems(bulk, mm, N[i], l[i]) * ces) +
                 2 * a256(mm * mm * W) + a256(q.ldx * q.ldx * W) + a256(chol_scratch_elems(mm) * W) +
                 6 * a256(mm * W) + a256(kGramParts * mm * W) + a256(3 * mm * W) +
@@ -1686,7 +1689,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       q.ldab = pld;
     }
     q.inv = (int32_t*)take(N[i] * 4);
-    q.order = (int32_t*)take(l[i] * 4);
+    q.order = (int32_t*)take(sketch_order_bytes(l[i], is_single(bulk)));
     q.S = take(l[i] * mm * be);
     q.Y = take(b_sketch_work_elems(bulk, mm, N[i], l[i]) * ces);
     q.G = take(mm * mm * W);
@@ -2314,13 +2317,15 @@ int srft_sketch_noalloc(mn_handle h, int dtype, int64_t m, int64_t n, const void
     return MN_HIP_ERROR;
   }
   const bool single = is_single(dtype);
-  // layout of the static array: twiddles | inverse map | flag | order | work
+  // layout of the static array: twiddles | inverse map | flag | order and
+  // kept-output table (sketch_order_bytes(l)) | work
   unsigned char* tw = base;
   int32_t* inv = (int32_t*)(base + kNoAllocTwBytes);
   int32_t* bad = (int32_t*)(base + kNoAllocTwBytes + kNoAllocIdxBytes);
   int32_t* order = (int32_t*)(base + kNoAllocTwBytes + kNoAllocIdxBytes + 256);
-  unsigned char* work = base + kNoAllocTwBytes + 2 * kNoAllocIdxBytes + 256;
-  const int64_t work_bytes = kNoAllocBytes - (kNoAllocTwBytes + 2 * kNoAllocIdxBytes + 256);
+  const int64_t order_bytes = rup(sketch_order_bytes(l, is_single(dtype)), 256);
+  unsigned char* work = (unsigned char*)order + order_bytes;
+  const int64_t work_bytes = kNoAllocBytes - (work - base);
   if (twiddle_entries(N) * (single ? 8 : 16) > kNoAllocTwBytes) return -7;
   try {
     if (noalloc_twiddle_swap(h->device, (N << 1) | (single ? 1 : 0))) {

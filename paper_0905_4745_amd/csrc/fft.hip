@@ -442,10 +442,15 @@ __global__ void __launch_bounds__(256) k_sketch_rows(const C* __restrict__ Y, in
 // intermediate nor the discarded outputs reach memory; the outer sum costs
 // l N1 = l N / N2 multiply-adds per row, so with N2 near l (the wide form)
 // the row costs O(N log N2) for the column transforms plus about 8 N flops
-// for the outer sum: O(N log l).  A block's share of the outer sum is
-// W_N^{c0 k} times a polynomial in W_N^k with the block's B values Z as
-// coefficients, evaluated by Horner's rule (one table entry for W_N^{c0 k},
-// one for W_N^k, one complex multiply-add per column).  Thread slot
+// for the outer sum: O(N log l).  The outer sum is a polynomial in W_N^k
+// with the values Z_{n1}[k mod N2] as coefficients, evaluated by Horner's
+// rule on two levels: within a block (variable W_N^k, one complex
+// multiply-add per column) and across the blocks, taken in decreasing order
+// (variable W_N^{B k}, one more per block); a column group that starts at
+// column cbeg multiplies its sum by W_N^{cbeg k} once at the end.  The two
+// variables of every kept output come from a table laid out in slot order
+// (k_sketch_steps), so each block reads them coalesced instead of gathering
+// from the twiddle table.  Thread slot
 // q = tid + TPB u takes kept output order[q]: the order groups outputs of
 // equal k mod N2 (k_sketch_order), so the lanes of a wave read a few LDS
 // addresses (broadcast) rather than 64 scattered ones.  With one column
@@ -462,6 +467,23 @@ template <typename V> __device__ __forceinline__ V ld_stream(const V* p) {
   } else {
     return __builtin_nontemporal_load(p);
   }
+}
+
+// an LDS entry as one 8-byte (complex float) or 16-byte read: with the
+// alignment stated, the constant column offsets fold into the instruction
+template <typename C> __device__ __forceinline__ C lds_c(const C* p) {
+  if constexpr (std::is_same<C, cf>::value) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    return cf{v.x, v.y};
+  } else {
+    return *p;
+  }
+}
+
+// the kept-output table (2 l entries of the compute type) that follows the
+// order's l indices in the same buffer (sketch_order_bytes)
+template <typename C> __host__ __device__ inline const C* kept_steps(const int32_t* order, int64_t l) {
+  return reinterpret_cast<const C*>(reinterpret_cast<const char*>(order) + ((4 * l + 255) & ~(int64_t)255));
 }
 
 template <typename V> struct PhaseOf { using type = typename std::conditional<VT<V>::cplx, cd, double>::type; };
@@ -482,7 +504,7 @@ template <typename C, int B, int TPB> __host__ __device__ constexpr bool pruned_
 
 // bk.x = column group, bk.y = row within the launch, bk.gx = groups per row.
 // TPB threads hold 16 elements each: N2 = 16 TPB / B points per column.
-template <typename V, typename C, int B, int KPT, int TPB = 256, bool P2 = true>
+template <typename V, typename C, int B, int KPT, int TPB = 256>
 __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __restrict__ A, int64_t lda, int64_t row0,
                                                        int64_t rows, int64_t n, int N1, int G, FftPlan pl2,
                                                        const void* __restrict__ dv, const int32_t* __restrict__ idx,
@@ -500,24 +522,8 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
   constexpr bool TW_LDS = pruned_tw_lds<C, B, TPB>();
   extern __shared__ unsigned char smem_raw[];
   C* sm = reinterpret_cast<C*>(smem_raw);
-  // N = N1 N2 with N2 a power of two and N1 any positive integer (P2: N a
-  // power of two).  The factor W_N^{c0 k} of a block (c0 < N1) needs
-  // (c0 k) mod N: a mask for a power of two; otherwise, with k = a N2 + k2
-  // (k2 < N2),  c0 k = N2 (c0 a) + c0 k2,  N2 ((c0 a) mod N1) < N,  c0 k2 < N,
-  // so one 32-bit remainder by N1 and one conditional subtraction.  (The two
-  // index forms are separate instantiations: selected at run time inside
-  // the block loop they cost the registers of both.)
-  const unsigned Ntot = (unsigned)N1 * (unsigned)N2, Nm = Ntot - 1u;
-  auto modn = [&](unsigned c, unsigned k) -> unsigned {
-    if constexpr (P2) {
-      return (c * k) & Nm;
-    } else {
-      const unsigned a = k >> ilog2c<N2>(), k2 = k & (unsigned)(N2 - 1);
-      unsigned r = ((c * a) % (unsigned)N1) * (unsigned)N2 + c * k2;
-      if (r >= Ntot) r -= Ntot;
-      return r;
-    }
-  };
+  // N = N1 N2 with N2 a power of two and N1 any positive integer
+  const uint64_t Ntot = (uint64_t)N1 * (uint64_t)N2;
   const int64_t i = row0 + bk.y;
   const V* row = A + i * lda;
   C* tws = sm + B * Lp;
@@ -533,24 +539,32 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
   // later stages: column fb, thread tl of its LR
   const int fb = tid >> lgLR, tl = tid & (LR - 1);
 
+  // kept output of slot u (slots past l compute on k = 0 and store nothing:
+  // no branch in the sum)
   C acc[KPT];
-#pragma unroll
-  for (int u = 0; u < KPT; ++u) acc[u] = vzero<C>();
-  // kept output of slot u; slots past l compute on k = 0 and store nothing
-  // (no branch in the sum)
   unsigned kq[KPT];
 #pragma unroll
   for (int u = 0; u < KPT; ++u) {
     const int q = tid + TPB * u;
-    kq[u] = q < l ? (unsigned)idx[order[q]] % Ntot : 0u;
+    kq[u] = q < l ? (unsigned)idx[order[q]] : 0u;  // idx < N (checked before the launch)
+    acc[u] = vzero<C>();
   }
-  // the empty asm makes k opaque inside the block loop, so the table reads
-  // that depend on it stay there (hoisted, they would hold 4 KPT registers
-  // through the whole loop)
+  // slot u's (W_N^k, W_N^{B k}), from the table k_sketch_order laid out in
+  // slot order (a coalesced read).  The empty asm makes k and the slot
+  // opaque inside the block loop, so the reads that depend on them stay
+  // there (hoisted, they would hold 4 KPT more registers through the loop).
+  const C* stp = kept_steps<C>(order, l);
   auto kept = [&](int u) -> unsigned {
     unsigned k = kq[u];
     asm volatile("" : "+v"(k));
     return k;
+  };
+  auto steps = [&](int u, C& st, C& sb) {
+    int q = tid + TPB * u;
+    asm volatile("" : "+v"(q));
+    q = q < l ? q : 0;
+    st = stp[2 * q];
+    sb = stp[2 * q + 1];
   };
 
   // the next block's entries of A are loaded into registers before the
@@ -568,9 +582,13 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
       pa[r] = (col && j < n) ? ld_stream(row + j) : V{};
     }
   };
+  // blocks in decreasing order: the group's sum
+  //   sum_g W_N^{(cbeg + g B) k} H_g = W_N^{cbeg k} sum_g (W_N^{B k})^g H_g
+  // (H_g = the block's share with its columns counted from c0) is a
+  // polynomial in W_N^{B k}, evaluated by Horner's rule across the blocks
   const int cbeg = bk.x * G * B;
-  load(cbeg);
-  for (int g = 0; g < G; ++g) {
+  load(cbeg + (G - 1) * B);
+  for (int g = G - 1; g >= 0; --g) {
     const int c0 = cbeg + g * B;
     {
       C v[16];
@@ -602,27 +620,29 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
     }
     // Z of the block is in LDS (the last stage ends with a barrier); the
     // next block's loads fly during the outer sum
-    if (g + 1 < G) load(c0 + B);
+    if (g > 0) load(c0 - B);
     // two kept outputs at a time (two independent chains interleave; the
     // scheduling barrier keeps the next pair's LDS reads from being hoisted
     // into this one's registers).  The block's share
-    //   sum_b W_N^{(c0 + b) k} Z_{c0+b} = W_N^{c0 k} sum_b (W_N^k)^b Z_{c0+b}
-    // is evaluated by Horner's rule (one complex multiply-add per column)
+    //   H_g = sum_b (W_N^k)^b Z_{c0+b}
+    // by Horner's rule too (one complex multiply-add per column), then
+    //   acc = acc W_N^{B k} + H_g
 #pragma unroll
     for (int u = 0; u < KPT; u += 2) {
       const unsigned k0 = kept(u), k1 = kept(u + 1);
-      const C w0 = tw[modn((unsigned)c0, k0)], w1 = tw[modn((unsigned)c0, k1)];  // W_N^{c0 k}
-      const C st0 = tw[k0], st1 = tw[k1];                                         // W_N^k
+      C st0, sb0, st1, sb1;
+      steps(u, st0, sb0);
+      steps(u + 1, st1, sb1);
       const C* zp0 = sm + lpad((int)(k0 & (unsigned)(N2 - 1)));
       const C* zp1 = sm + lpad((int)(k1 & (unsigned)(N2 - 1)));
-      C h0 = zp0[(B - 1) * Lp], h1 = zp1[(B - 1) * Lp];
+      C h0 = lds_c(zp0 + (B - 1) * Lp), h1 = lds_c(zp1 + (B - 1) * Lp);
 #pragma unroll
       for (int b = B - 2; b >= 0; --b) {
-        h0 = vfma(h0, st0, zp0[b * Lp]);
-        h1 = vfma(h1, st1, zp1[b * Lp]);
+        h0 = vfma(h0, st0, lds_c(zp0 + b * Lp));
+        h1 = vfma(h1, st1, lds_c(zp1 + b * Lp));
       }
-      acc[u] = vfma(w0, h0, acc[u]);
-      acc[u + 1] = vfma(w1, h1, acc[u + 1]);
+      acc[u] = vfma(acc[u], sb0, h0);
+      acc[u + 1] = vfma(acc[u + 1], sb1, h1);
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
@@ -632,8 +652,10 @@ __device__ __forceinline__ void k_sketch_pruned_body(const Bk bk, const V* __res
     const int q = tid + TPB * u;
     if (q < l) {
       const int64_t s = order[q];
-      if (bk.gx == 1) S[s + i * lds] = out_value<V, C>(acc[u], scale);
-      else P[((int64_t)bk.x * rows + bk.y) * l + s] = acc[u];
+      C a = acc[u];
+      if (cbeg > 0) a = vmul(a, tw[(uint64_t)cbeg * kq[u] % Ntot]);  // W_N^{cbeg k}
+      if (bk.gx == 1) S[s + i * lds] = out_value<V, C>(a, scale);
+      else P[((int64_t)bk.x * rows + bk.y) * l + s] = a;
     }
   }
 }
@@ -642,23 +664,23 @@ __global__ void __launch_bounds__(TPB, TPB == 256 ? 2 : 1) k_sketch_pruned(
     const V* __restrict__ A, int64_t lda, int64_t row0, int64_t rows, int64_t n, int N1, int G, FftPlan pl2,
     const void* __restrict__ dv, const int32_t* __restrict__ idx, const int32_t* __restrict__ order, int64_t l,
     const C* __restrict__ tw, V* __restrict__ S, int64_t lds, C* __restrict__ P, typename VT<C>::real scale) {
-  if ((N1 & (N1 - 1)) == 0)
-    k_sketch_pruned_body<V, C, B, KPT, TPB, true>(bk_hw(), A, lda, row0, rows, n, N1, G, pl2, dv, idx, order, l, tw, S,
-                                                  lds, P, scale);
-  else
-    k_sketch_pruned_body<V, C, B, KPT, TPB, false>(bk_hw(), A, lda, row0, rows, n, N1, G, pl2, dv, idx, order, l, tw, S,
-                                                   lds, P, scale);
+  k_sketch_pruned_body<V, C, B, KPT, TPB>(bk_hw(), A, lda, row0, rows, n, N1, G, pl2, dv, idx, order, l, tw, S, lds, P,
+                                          scale);
 }
 
 // order[0 .. l) = a permutation of 0 .. l that groups the kept outputs by
 // idx[s] mod N2 (counting sort on the residue; the order inside a group is
-// whatever the LDS atomics give, which changes no result).  One workgroup of
-// 1024 threads; N2 <= kOrderMaxN2 (the counts live in LDS; their exclusive
-// prefix sum runs in parallel: each thread sums a run of N2 / 1024 counts,
-// the run totals are scanned across the workgroup, then each run is filled).
+// whatever the LDS atomics give, which changes no result), and, when tw is
+// given, beside it the kept-output table in the same order: (W_N^k,
+// W_N^{B k}) with k = idx[s] (k_sketch_steps fills it over many workgroups).
+// One workgroup of 1024 threads; N2 <= kOrderMaxN2 (the counts live in LDS;
+// their exclusive prefix sum runs in parallel: each thread sums a run of
+// N2 / 1024 counts, the run totals are scanned across the workgroup, then
+// each run is filled).
 constexpr int kOrderMaxN2 = 16384;
-__device__ __forceinline__ void k_sketch_order_body(const int32_t* __restrict__ idx, int64_t l, int N2,
-                                                    int32_t* __restrict__ order) {
+template <typename C>
+__device__ __forceinline__ void k_sketch_order_body(const int32_t* __restrict__ idx, int64_t l, int N2, int64_t N,
+                                                    int B, const C* __restrict__ tw, int32_t* __restrict__ order) {
   __shared__ int cnt[kOrderMaxN2];
   __shared__ int tot[1024];
   const int tid = threadIdx.x;
@@ -684,11 +706,33 @@ __device__ __forceinline__ void k_sketch_order_body(const int32_t* __restrict__ 
     base += c;
   }
   __syncthreads();
-  for (int64_t s = tid; s < l; s += 1024) order[atomicAdd(&cnt[idx[s] & (N2 - 1)], 1)] = (int32_t)s;
+  C* steps = const_cast<C*>(kept_steps<C>(order, l));
+  for (int64_t s = tid; s < l; s += 1024) {
+    const int64_t k = idx[s];
+    const int pos = atomicAdd(&cnt[k & (N2 - 1)], 1);
+    order[pos] = (int32_t)s;
+    if (tw != nullptr) {
+      steps[2 * (int64_t)pos] = tw[k];
+      steps[2 * (int64_t)pos + 1] = tw[(int64_t)B * k % N];
+    }
+  }
 }
-__global__ void __launch_bounds__(1024) k_sketch_order(const int32_t* __restrict__ idx, int64_t l, int N2,
-                                                       int32_t* __restrict__ order) {
-  k_sketch_order_body(idx, l, N2, order);
+// the kept-output table from the order: slot q gets (W_N^k, W_N^{B k}),
+// k = idx[order[q]].  grid ceil(l / 256), 256 threads.
+template <typename C>
+__global__ void __launch_bounds__(256) k_sketch_steps(const int32_t* __restrict__ idx, int64_t l, int64_t N, int B,
+                                                      const C* __restrict__ tw, int32_t* __restrict__ order) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= l) return;
+  const int64_t k = idx[order[q]];
+  C* steps = const_cast<C*>(kept_steps<C>(order, l));
+  steps[2 * q] = tw[k];
+  steps[2 * q + 1] = tw[(int64_t)B * k % N];
+}
+template <typename C>
+__global__ void __launch_bounds__(1024) k_sketch_order(const int32_t* __restrict__ idx, int64_t l, int N2, int64_t N,
+                                                       int B, const C* __restrict__ tw, int32_t* __restrict__ order) {
+  k_sketch_order_body<C>(idx, l, N2, N, B, tw, order);
 }
 
 // S[s + i lds] = scale * sum over the ng column groups of P[g][i - row0][s]
@@ -879,7 +923,10 @@ static hipError_t sketch_pruned_impl(const SketchArgs& a, hipStream_t st) {
   // one group per row: no partial sums, every row in one launch
   const int64_t per = ng == 1 ? a.m : a.chunk_rows;
   if (per < 1 || (ng > 1 && P == nullptr) || a.order == nullptr) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sketch_order, dim3(1), dim3(1024), 0, st, a.idx, a.l, N2, a.order);
+  hipLaunchKernelGGL((k_sketch_order<C>), dim3(1), dim3(1024), 0, st, a.idx, a.l, N2, a.N, B, (const C*)nullptr,
+                     a.order);
+  hipLaunchKernelGGL((k_sketch_steps<C>), dim3((unsigned)ceil_div(a.l, 256)), dim3(256), 0, st, a.idx, a.l, a.N, B, tw,
+                     a.order);
   for (int64_t r0 = 0; r0 < a.m; r0 += per) {
     const int64_t rows = (a.m - r0) < per ? (a.m - r0) : per;
     const dim3 grid((unsigned)ng, (unsigned)rows);
@@ -964,6 +1011,8 @@ int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng, int tpb
   if (p2 && N <= (sp ? max_lds_fft_len<cf>() : max_lds_fft_len<cd>())) return 0;
   return sp ? pruned_groups<cf>(N, l, B, ng, tpb) : pruned_groups<cd>(N, l, B, ng, tpb);
 }
+
+int64_t sketch_order_bytes(int64_t l, bool single) { return ((4 * l + 255) & ~(int64_t)255) + 2 * l * (single ? 8 : 16); }
 
 int sketch_pruned_wide_tpb(int dtype) { return (dtype == 1 || dtype == 3) ? pruned_wide_tpb<cf>() : pruned_wide_tpb<cd>(); }
 
@@ -1090,23 +1139,18 @@ __global__ void __launch_bounds__(256, 2) kb_sketch_pruned(const BSys* __restric
   using R = typename VT<C>::real;
   const Bk bk = bgrid_local(grid[i], (int)blockIdx.x - grid[i].start);
   const R scale = (R)(1.0 / sqrt((double)s.N));
-  if ((s.N1 & (s.N1 - 1)) == 0)
-    k_sketch_pruned_body<V, C, 16, KPT, 256, true>(bk, reinterpret_cast<const V*>(s.Ab), s.ldab, 0, s.m, s.n, s.N1,
-                                                   s.N1 / 16, s.pl_b, s.d, s.idx, s.order, s.l,
-                                                   reinterpret_cast<const C*>(s.tw), reinterpret_cast<V*>(s.S), s.l,
-                                                   nullptr, scale);
-  else
-    k_sketch_pruned_body<V, C, 16, KPT, 256, false>(bk, reinterpret_cast<const V*>(s.Ab), s.ldab, 0, s.m, s.n, s.N1,
-                                                    (s.N1 + 15) / 16, s.pl_b, s.d, s.idx, s.order, s.l,
-                                                    reinterpret_cast<const C*>(s.tw), reinterpret_cast<V*>(s.S), s.l,
-                                                    nullptr, scale);
+  k_sketch_pruned_body<V, C, 16, KPT, 256>(bk, reinterpret_cast<const V*>(s.Ab), s.ldab, 0, s.m, s.n, s.N1,
+                                           (s.N1 + 15) / 16, s.pl_b, s.d, s.idx, s.order, s.l,
+                                           reinterpret_cast<const C*>(s.tw), reinterpret_cast<V*>(s.S), s.l, nullptr,
+                                           scale);
 }
 
+template <typename C>
 __global__ void __launch_bounds__(1024) kb_sketch_order(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
                                                         int nsys) {
   const int i = bgrid_find(grid, nsys, blockIdx.x);
   const BSys& s = sys[i];
-  k_sketch_order_body(s.idx, s.l, s.N2, s.order);
+  k_sketch_order_body<C>(s.idx, s.l, s.N2, s.N, 16, reinterpret_cast<const C*>(s.tw), s.order);
 }
 
 __global__ void kb_fill_inv(const BSys* __restrict__ sys, const BGrid* __restrict__ grid, int nsys) {
@@ -1170,7 +1214,8 @@ template <typename V, typename C>
 hipError_t b_sketch_t(const BLaunch& sm, const BLaunch& co, const BLaunch& ro, const BLaunch& ord, const BLaunch* pr,
                       size_t ls, size_t lc, size_t lr, size_t lp, hipStream_t st) {
   if (ord.total > 0) {
-    hipLaunchKernelGGL(kb_sketch_order, dim3((unsigned)ord.total), dim3(1024), 0, st, ord.sys, ord.grid, ord.nsys);
+    hipLaunchKernelGGL((kb_sketch_order<C>), dim3((unsigned)ord.total), dim3(1024), 0, st, ord.sys, ord.grid,
+                       ord.nsys);
     if (pr[0].total > 0) {
       allow_lds(kb_sketch_pruned<V, C, 2>, lp);
       hipLaunchKernelGGL((kb_sketch_pruned<V, C, 2>), dim3((unsigned)pr[0].total), dim3(256), lp, st, pr[0].sys,

@@ -45,12 +45,16 @@ struct SketchArgs {
   int pruned_b;         // > 0: kept outputs only, B = 16, 8 or 4 columns per block (N2 = 16 pruned_tpb / B)
   int pruned_ng;        // pruned: column groups per row (partial sums in work when > 1)
   int pruned_tpb;       // pruned: threads per workgroup (256, or sketch_pruned_wide_tpb: N2 = 16 tpb / B)
-  int32_t* order;       // pruned: l entries of scratch (kept outputs grouped by k mod N2)
+  int32_t* order;       // pruned: sketch_order_bytes(l) of scratch (kept outputs grouped by k mod N2, and
+                        // their table of twiddle factors)
 };
 // column groups per row the pruned four-step uses for (B, ng), 0 if it does
 // not apply to this (dtype, N, l); work then holds ng * chunk_rows * l
 // elements of the compute type
 int sketch_pruned_groups(int dtype, int64_t N, int64_t l, int B, int ng, int tpb = 256);
+// bytes of the kept-outputs-only form's order buffer: l indices, then (from
+// the next 256-byte boundary) 2 l entries of the compute type
+int64_t sketch_order_bytes(int64_t l, bool single);
 // the wide workgroup of the kept-outputs-only form (512 threads)
 int sketch_pruned_wide_tpb(int dtype);
 hipError_t launch_sketch(int dtype, const SketchArgs& a, hipStream_t st);
@@ -85,11 +89,12 @@ hipError_t launch_twiddles(bool single, int64_t N, void* out, hipStream_t st);
 // Allocation-free sketch (noalloc.hip): a static device array of
 // kNoAllocBytes per GPU, laid out as the twiddle table (kNoAllocTwBytes,
 // enough for N <= kNoAllocMaxN), the inverse subsample map and the flag of
-// idx's check, the kept-output order, then the four-step work area.
+// idx's check, the kept-output order and table (sketch_order_bytes(l)), then
+// the four-step work area.
 constexpr int64_t kNoAllocBytes = (int64_t)32 << 20;
 constexpr int64_t kNoAllocMaxN = 65536;
 constexpr int64_t kNoAllocTwBytes = (int64_t)1152 << 10;   // >= twiddle_entries(65536) x 16 bytes
-constexpr int64_t kNoAllocIdxBytes = kNoAllocMaxN * 4;      // inverse map, then the order
+constexpr int64_t kNoAllocIdxBytes = kNoAllocMaxN * 4;      // inverse map
 // device address of this device's array (set up by noalloc_init, which runs
 // with the device current); null before
 hipError_t noalloc_init(int device);
@@ -354,7 +359,7 @@ struct BSys {
   FftPlan pl_a, pl_b;
   int fft_ba, fft_bb, N1, N2;
   int sk_kpt;      // kept-outputs-only four-step: accumulators per thread (2, 4, 8), or 0
-  int32_t* order;  // l entries: kept outputs grouped by k mod N2 (kept-outputs-only form)
+  int32_t* order;  // sketch_order_bytes(l): kept outputs grouped by k mod N2 (kept-outputs-only form)
   const void* tw;  // W_N^k, k < N, compute precision
   // workspace
   int32_t* inv;    // N
