@@ -440,37 +440,55 @@ void draw_srft_into(mn_handle h, bool cplx, uint64_t seed, int draw, int sys, in
 // The same for several systems (draw 0, sys = the system's index): every
 // system's phases are launched, all index sets are drawn into one pinned
 // buffer and copied, and the stream is synchronised once.
+int64_t a256(int64_t v) { return (v + 255) / 256 * 256; }
+
+// The library's draws for systems 0 .. batch - 1 (draw 0, sys = the
+// system's index) into contiguous device areas: system i's phases at
+// dbase + doff[i] bytes, its indices at ibase + ioff[i] bytes, with
+// doff/ioff the running sums of a256(N es) and a256(4 l).  The phases take
+// one launch (its table of (N, offset) goes first, through the pinned
+// staging buffer), the index sets are drawn meanwhile on host threads and
+// leave in one copy; returns once the staging buffer is free again.
 void draw_srft_batch(mn_handle h, bool cplx, uint64_t seed, int batch, const int64_t* N, const int64_t* l,
-                     void* const* d, int32_t* const* idx) {
-  size_t total = 0;
-  for (int i = 0; i < batch; ++i) total += (size_t)l[i];
-  if (h->host_draw_n < total) {
+                     void* dbase, int32_t* ibase, int64_t* tab_dev) {
+  const int64_t es = cplx ? 16 : 8;
+  std::vector<int64_t> ioff((size_t)batch + 1, 0);
+  int64_t doff = 0, max_n = 0;
+  for (int i = 0; i < batch; ++i) ioff[i + 1] = ioff[i] + a256(l[i] * 4);
+  // staging: the table (2 batch int64), then the index area
+  const int64_t tab_bytes = a256(2 * (int64_t)batch * 8);
+  const size_t need = (size_t)(tab_bytes + ioff[batch]);
+  if (h->host_draw_n * sizeof(int32_t) < need) {
     if (h->host_draw) {
       ck(hipStreamSynchronize(h->stream));
       ck(hipHostFree(h->host_draw));
       h->host_draw = nullptr;
       h->host_draw_n = 0;
     }
-    ck(hipHostMalloc((void**)&h->host_draw, total * sizeof(int32_t), hipHostMallocDefault));
-    h->host_draw_n = total;
+    ck(hipHostMalloc((void**)&h->host_draw, need, hipHostMallocDefault));
+    h->host_draw_n = need / sizeof(int32_t);
   }
-  std::vector<size_t> off((size_t)batch + 1, 0);
-  for (int i = 0; i < batch; ++i) off[i + 1] = off[i] + (size_t)l[i];
-  // the phases on the device, the index sets meanwhile on host threads (the
-  // systems are independent; nothing that throws runs while they do)
-  for (int i = 0; i < batch; ++i) ck(launch_draw_phases(cplx, seed, 0, i, N[i], d[i], h->stream));
+  int64_t* tab = reinterpret_cast<int64_t*>(h->host_draw);
+  for (int i = 0; i < batch; ++i) {
+    tab[2 * i] = N[i];
+    tab[2 * i + 1] = doff;
+    doff += a256(N[i] * es);
+    max_n = std::max(max_n, N[i]);
+  }
+  ck(hipMemcpyAsync(tab_dev, tab, (size_t)(2 * (int64_t)batch * 8), hipMemcpyHostToDevice, h->stream));
+  for (int s0 = 0; s0 < batch; s0 += 65535)
+    ck(launch_draw_phases_batch(cplx, seed, 0, s0, std::min(batch - s0, 65535), max_n, tab_dev, dbase, h->stream));
+  char* hidx = reinterpret_cast<char*>(h->host_draw) + tab_bytes;
   const int nt = (int)std::max<unsigned>(1u, std::min<unsigned>(std::min(16u, std::thread::hardware_concurrency()),
                                                                    (unsigned)batch));
   std::vector<std::thread> pool;
   for (int t = 1; t < nt; ++t)
     pool.emplace_back([&, t]() {
-      for (int i = t; i < batch; i += nt) draw_indices(seed, 0, i, N[i], l[i], h->host_draw + off[i]);
+      for (int i = t; i < batch; i += nt) draw_indices(seed, 0, i, N[i], l[i], (int32_t*)(hidx + ioff[i]));
     });
-  for (int i = 0; i < batch; i += nt) draw_indices(seed, 0, i, N[i], l[i], h->host_draw + off[i]);
+  for (int i = 0; i < batch; i += nt) draw_indices(seed, 0, i, N[i], l[i], (int32_t*)(hidx + ioff[i]));
   for (auto& th : pool) th.join();
-  for (int i = 0; i < batch; ++i)
-    ck(hipMemcpyAsync(idx[i], h->host_draw + off[i], (size_t)l[i] * sizeof(int32_t), hipMemcpyHostToDevice,
-                      h->stream));
+  ck(hipMemcpyAsync(ibase, hidx, (size_t)ioff[batch], hipMemcpyHostToDevice, h->stream));
   ck(hipStreamSynchronize(h->stream));
 }
 
@@ -1484,7 +1502,6 @@ struct GridTable {
   }
 };
 
-int64_t a256(int64_t v) { return (v + 255) / 256 * 256; }
 
 // The fused form takes one bulk type for all systems: either no system has a
 // single-precision copy or every system has one (a mix goes to the lanes).
@@ -2443,19 +2460,18 @@ int minnorm_solve_batched(mn_handle h, int dtype, int32_t batch, const int64_t* 
         }
         char* dbase = (char*)ws(h, "bdraw_d", (size_t)dn);
         char* ibase = (char*)ws(h, "bdraw_idx", (size_t)in);
+        int64_t* tab_dev = (int64_t*)ws(h, "bdraw_tab", (size_t)(2 * (int64_t)batch * 8));
+        void* const d0 = dbase;
+        int32_t* const i0 = (int32_t*)ibase;
         dv.resize(batch);
         iv.resize(batch);
-        std::vector<void*> dw((size_t)batch);
-        std::vector<int32_t*> iw((size_t)batch);
         for (int32_t i = 0; i < batch; ++i) {
-          dw[i] = dbase;
-          iw[i] = (int32_t*)ibase;
           dv[i] = dbase;
           iv[i] = (const int32_t*)ibase;
           dbase += a256(N[i] * (is_complex(dtype) ? 16 : 8));
           ibase += a256(l[i] * 4);
         }
-        draw_srft_batch(h, is_complex(dtype), o.seed, batch, N, l, dw.data(), iw.data());
+        draw_srft_batch(h, is_complex(dtype), o.seed, batch, N, l, d0, i0, tab_dev);
       }
       solve_batched_fused(h, dtype, batch, m, n, A, lda, A_lo, b, eps, N, l, lib_draw ? dv.data() : d,
                           lib_draw ? iv.data() : idx, o, x, info, stv, redo);

@@ -22,11 +22,9 @@
 
 namespace mn {
 
+// phase j of system sys
 template <bool CPLX>
-__global__ void __launch_bounds__(256) k_draw_phases(uint64_t seed, uint32_t draw, uint32_t sys, int64_t N,
-                                                     void* __restrict__ d) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
+__device__ __forceinline__ void phase_at(uint64_t seed, int64_t j, uint32_t draw, uint32_t sys, void* __restrict__ d) {
   const U32x4 w = srft_words(seed, (uint32_t)j, draw, 0u, sys);
   if constexpr (CPLX) {
     double s, c;
@@ -37,12 +35,43 @@ __global__ void __launch_bounds__(256) k_draw_phases(uint64_t seed, uint32_t dra
   }
 }
 
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_draw_phases(uint64_t seed, uint32_t draw, uint32_t sys, int64_t N,
+                                                     void* __restrict__ d) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < N) phase_at<CPLX>(seed, j, draw, sys, d);
+}
+
+// the phases of systems sys0 .. sys0 + count - 1 in one launch: grid
+// (ceil(max N / 256), count), sys = sys0 + blockIdx.y; tab[2 sys] = N of the
+// system, tab[2 sys + 1] = byte offset of its phases from d
+template <bool CPLX>
+__global__ void __launch_bounds__(256) k_draw_phases_batch(uint64_t seed, uint32_t draw, uint32_t sys0,
+                                                           const int64_t* __restrict__ tab, char* __restrict__ d) {
+  const uint32_t sys = sys0 + blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < tab[2 * sys]) phase_at<CPLX>(seed, j, draw, sys, d + tab[2 * sys + 1]);
+}
+
 hipError_t launch_draw_phases(bool cplx, uint64_t seed, int draw, int sys, int64_t N, void* d, hipStream_t st) {
   const dim3 grid((unsigned)ceil_div(N, 256));
   if (cplx)
     hipLaunchKernelGGL((k_draw_phases<true>), grid, dim3(256), 0, st, seed, (uint32_t)draw, (uint32_t)sys, N, d);
   else
     hipLaunchKernelGGL((k_draw_phases<false>), grid, dim3(256), 0, st, seed, (uint32_t)draw, (uint32_t)sys, N, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_draw_phases_batch(bool cplx, uint64_t seed, int draw, int sys0, int count, int64_t max_n,
+                                    const int64_t* tab, void* d, hipStream_t st) {
+  if (sys0 < 0 || count < 1 || count > 65535 || max_n < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)ceil_div(max_n, 256), (unsigned)count);
+  if (cplx)
+    hipLaunchKernelGGL((k_draw_phases_batch<true>), grid, dim3(256), 0, st, seed, (uint32_t)draw, (uint32_t)sys0,
+                       tab, reinterpret_cast<char*>(d));
+  else
+    hipLaunchKernelGGL((k_draw_phases_batch<false>), grid, dim3(256), 0, st, seed, (uint32_t)draw, (uint32_t)sys0,
+                       tab, reinterpret_cast<char*>(d));
   return hipGetLastError();
 }
 

@@ -105,6 +105,11 @@ bool noalloc_twiddle_swap(int device, int64_t tag);
 // The library's own draw of D and S (draw.hip): phases (complex128 or +-1
 // float64, N entries) on the device, the l indices (increasing) on the host.
 hipError_t launch_draw_phases(bool cplx, uint64_t seed, int draw, int sys, int64_t N, void* d, hipStream_t st);
+// the phases of systems sys0 .. sys0 + count - 1 (count <= 65535; sys = the
+// system's index) in one launch: tab (device) holds (N, byte offset from d)
+// per system from system 0 on, max_n the largest N
+hipError_t launch_draw_phases_batch(bool cplx, uint64_t seed, int draw, int sys0, int count, int64_t max_n,
+                                    const int64_t* tab, void* d, hipStream_t st);
 void draw_indices(uint64_t seed, int draw, int sys, int64_t N, int64_t l, int32_t* idx);
 
 struct QrArgs {
