@@ -76,6 +76,8 @@ struct mn_handle_s {
   int32_t* host_draw = nullptr;  // pinned staging of library-drawn indices
   size_t host_draw_n = 0;
   hipStream_t cap_stream = nullptr;  // records HIP graphs of the batched iteration blocks
+  StreamFork fork{};                 // side streams of the batched passes' row classes
+  bool fork_ready = false;
 };
 
 namespace {
@@ -441,6 +443,19 @@ void draw_srft_into(mn_handle h, bool cplx, uint64_t seed, int draw, int sys, in
 // system's phases are launched, all index sets are drawn into one pinned
 // buffer and copied, and the stream is synchronised once.
 int64_t a256(int64_t v) { return (v + 255) / 256 * 256; }
+
+// the handle's fork for the batched passes, created on first use (default
+// priority, non-blocking streams; events without timing)
+const StreamFork* handle_fork(mn_handle h) {
+  if (!h->fork_ready) {
+    for (auto& sd : h->fork.side)
+      if (!sd) ck(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
+    for (auto& e : h->fork.ev)
+      if (!e) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->fork_ready = true;
+  }
+  return &h->fork;
+}
 
 // The library's draws for systems 0 .. batch - 1 (draw 0, sys = the
 // system's index) into contiguous device areas: system i's phases at
@@ -1542,6 +1557,8 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
                          const mn_opts& o, void* const* x, mn_info* info, std::vector<int>& st_out,
                          std::vector<int>& redo) {
   hipStream_t st = h->stream;
+  // the passes' rows-per-lane classes run side by side
+  const StreamFork* fork = handle_fork(h);
   const bool cplx = is_complex(dtype);
   const bool mixed = A_lo != nullptr || is_single(dtype);
   const int bulk = A_lo ? dtype + 1 : dtype;
@@ -1860,7 +1877,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
       // systems with their partial-sum reduction, as one interval
       const auto ev = s == st ? prof_pair(h, K_GRAM) : std::pair<hipEvent_t, hipEvent_t>{nullptr, nullptr};
       if (ev.first) ck(hipEventRecord(ev.first, s));
-      ck(launch_b_gram(bulk, gl, L(gred), use_cm ? (at_written ? 2 : 1) : 0, s));
+      ck(launch_b_gram(bulk, gl, L(gred), use_cm ? (at_written ? 2 : 1) : 0, s, fork));
       if (ev.second) ck(hipEventRecord(ev.second, s));
       at_written = true;
       ck(launch_b_cg(cplx, L(cgs), L(cgp), 0, 2, 0, par, cg_lds, s));
@@ -1922,7 +1939,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
         ck(launch_b_cg(cplx, L(cgs), L(cgp), 1, 0, 1, par, cg_lds, st));
       } else if (!is_single(dtype)) {
         const BLaunch gl[4] = {L(gramR[0]), L(gramR[1]), L(gramR[2]), L(gramR[3])};
-        ck(launch_b_gram_res(dtype, gl, L(gred), st));
+        ck(launch_b_gram_res(dtype, gl, L(gred), st, fork));
         ck(launch_b_cg(cplx, L(cgs), L(cgp), 1, 2, 1, par, cg_lds, st));
       } else {
         ck(launch_b_adj_wide(dtype, true, L(adjA), none, 0, 0, st));
@@ -2042,6 +2059,10 @@ int mn_destroy(mn_handle h) {
   for (auto& e : h->pool) (void)hipEventDestroy(e);
   if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  for (auto& sd : h->fork.side)
+    if (sd) (void)hipStreamDestroy(sd);
+  for (auto& e : h->fork.ev)
+    if (e) (void)hipEventDestroy(e);
   delete h;
   return 0;
 }

@@ -1154,12 +1154,41 @@ static void b_gram_one(const BLaunch& L, int mode, hipStream_t st) {
                        L.grid, L.nsys);
 }
 
+// Streams of the four rows-per-lane classes: with a fork, classes 1 .. 3
+// that have work run on its side streams, which wait for an event recorded
+// on st and are joined back into st by events of their own (under graph
+// capture this records parallel branches); without, all run on st.
+static hipError_t fork_out(const StreamFork* fk, const BLaunch* L, hipStream_t st, hipStream_t* s) {
+  for (int k = 0; k < 4; ++k) s[k] = st;
+  if (!fk) return hipSuccess;
+  hipError_t e = hipEventRecord(fk->ev[0], st);
+  for (int k = 1; k < 4 && e == hipSuccess; ++k)
+    if (L[k].total > 0) {
+      e = hipStreamWaitEvent(fk->side[k - 1], fk->ev[0], 0);
+      s[k] = fk->side[k - 1];
+    }
+  return e;
+}
+static hipError_t fork_in(const StreamFork* fk, hipStream_t st, const hipStream_t* s) {
+  hipError_t e = hipSuccess;
+  for (int k = 1; k < 4 && e == hipSuccess; ++k)
+    if (s[k] != st) {
+      e = hipEventRecord(fk->ev[k], s[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, fk->ev[k], 0);
+    }
+  return e;
+}
+
 template <typename V, typename C, typename U>
-static hipError_t b_gram_go(const BLaunch* L, const BLaunch& red, int mode, hipStream_t st) {
-  b_gram_one<V, C, U, 1>(L[0], mode, st);
-  b_gram_one<V, C, U, 2>(L[1], mode, st);
-  b_gram_one<V, C, U, 4>(L[2], mode, st);
-  b_gram_one<V, C, U, 8>(L[3], mode, st);
+static hipError_t b_gram_go(const BLaunch* L, const BLaunch& red, int mode, hipStream_t st, const StreamFork* fk) {
+  hipStream_t s[4];
+  hipError_t e = fork_out(fk, L, st, s);
+  if (e != hipSuccess) return e;
+  b_gram_one<V, C, U, 1>(L[0], mode, s[0]);
+  b_gram_one<V, C, U, 2>(L[1], mode, s[1]);
+  b_gram_one<V, C, U, 4>(L[2], mode, s[2]);
+  b_gram_one<V, C, U, 8>(L[3], mode, s[3]);
+  if ((e = hipGetLastError()) != hipSuccess || (e = fork_in(fk, st, s)) != hipSuccess) return e;
   if (red.total > 0)
     hipLaunchKernelGGL((kb_gram_reduce<U>), dim3((unsigned)red.total), dim3(256), 0, st, red.sys, red.grid,
                        red.nsys, 1);
@@ -1175,33 +1204,38 @@ static void b_res_one(const BLaunch& L, hipStream_t st) {
 }
 
 template <typename V, typename U>
-static hipError_t b_res_go(const BLaunch* L, const BLaunch& red, hipStream_t st) {
-  b_res_one<V, U, 1>(L[0], st);
-  b_res_one<V, U, 2>(L[1], st);
-  b_res_one<V, U, 4>(L[2], st);
-  b_res_one<V, U, 8>(L[3], st);
+static hipError_t b_res_go(const BLaunch* L, const BLaunch& red, hipStream_t st, const StreamFork* fk) {
+  hipStream_t s[4];
+  hipError_t e = fork_out(fk, L, st, s);
+  if (e != hipSuccess) return e;
+  b_res_one<V, U, 1>(L[0], s[0]);
+  b_res_one<V, U, 2>(L[1], s[1]);
+  b_res_one<V, U, 4>(L[2], s[2]);
+  b_res_one<V, U, 8>(L[3], s[3]);
+  if ((e = hipGetLastError()) != hipSuccess || (e = fork_in(fk, st, s)) != hipSuccess) return e;
   if (red.total > 0)
     hipLaunchKernelGGL((kb_gram_reduce<U>), dim3((unsigned)red.total), dim3(256), 0, st, red.sys, red.grid,
                        red.nsys, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_b_gram_res(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st) {
+hipError_t launch_b_gram_res(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st, const StreamFork* fk) {
   switch (dtype) {
-    case 0: return b_res_go<cd, cd>(L, red, st);
-    case 1: return b_res_go<cf, cd>(L, red, st);
-    case 2: return b_res_go<double, double>(L, red, st);
-    case 3: return b_res_go<float, double>(L, red, st);
+    case 0: return b_res_go<cd, cd>(L, red, st, fk);
+    case 1: return b_res_go<cf, cd>(L, red, st, fk);
+    case 2: return b_res_go<double, double>(L, red, st, fk);
+    case 3: return b_res_go<float, double>(L, red, st, fk);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, int mode, hipStream_t st) {
+hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, int mode, hipStream_t st,
+                         const StreamFork* fk) {
   switch (dtype) {
-    case 0: return b_gram_go<cd, cd, cd>(L, red, mode, st);
-    case 1: return b_gram_go<cf, cf, cd>(L, red, mode, st);
-    case 2: return b_gram_go<double, double, double>(L, red, mode, st);
-    case 3: return b_gram_go<float, float, double>(L, red, mode, st);
+    case 0: return b_gram_go<cd, cd, cd>(L, red, mode, st, fk);
+    case 1: return b_gram_go<cf, cf, cd>(L, red, mode, st, fk);
+    case 2: return b_gram_go<double, double, double>(L, red, mode, st, fk);
+    case 3: return b_gram_go<float, float, double>(L, red, mode, st, fk);
   }
   return hipErrorInvalidValue;
 }

@@ -427,11 +427,19 @@ hipError_t launch_b_trtri_step(bool cplx, const BLaunch& L, int k, hipStream_t s
 // launch per rows-per-thread class L[0..3], then the partial sums
 // mode 0: row-major pass over Ab; 1: the same, also writing each system's
 // column-major copy At (never skipped); 2: the pass over At
-hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, int mode, hipStream_t st);
+// side streams and events that let the rows-per-lane classes of a batched
+// pass run concurrently (fork from and join back into the calling stream)
+struct StreamFork {
+  hipStream_t side[3];
+  hipEvent_t ev[4];
+};
+hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, int mode, hipStream_t st,
+                         const StreamFork* fk = nullptr);
 // the refinement's FP64 residual product q = A (A* y_outer) as one fused pass
 // over each system's problem data A (dtype = the problem dtype); same grids
 // as launch_b_gram, strips from b_plan_gram_res (after b_plan_gram)
-hipError_t launch_b_gram_res(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st);
+hipError_t launch_b_gram_res(int dtype, const BLaunch* L, const BLaunch& red, hipStream_t st,
+                             const StreamFork* fk = nullptr);
 void b_plan_gram_res(int dtype, BSys& s);
 // FP64 passes on the problem data: w64 (or x) = A* u, u = y_outer (outer) or y;
 // fpart = A w64 in column chunks
