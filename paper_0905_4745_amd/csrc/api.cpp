@@ -78,6 +78,7 @@ struct mn_handle_s {
   hipStream_t cap_stream = nullptr;  // records HIP graphs of the batched iteration blocks
   StreamFork fork{};                 // side streams of the batched passes' row classes
   bool fork_ready = false;
+  hipEvent_t pre_ev[2] = {};         // fork and join of the early column-major copies
 };
 
 namespace {
@@ -452,6 +453,8 @@ const StreamFork* handle_fork(mn_handle h) {
       if (!sd) ck(hipStreamCreateWithFlags(&sd, hipStreamNonBlocking));
     for (auto& e : h->fork.ev)
       if (!e) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (auto& e : h->pre_ev)
+      if (!e) ck(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     h->fork_ready = true;
   }
   return &h->fork;
@@ -668,6 +671,13 @@ struct SolveCtx {
   double sigma_lo = 1.0;  // lower bound of sigma_min(A* R^{-1}) (below 1 for a Gram-route R)
   bool comp = false;  // compensated FP64 refinement passes (cond(A) u64 near eps)
   bool wide_acc = false;  // single-precision bulk accumulated in FP64 (large cond(A))
+  // column-major copies written on a side stream while Steps 1-2 ran (null
+  // when not made): the bulk matrix's for the inner passes, the problem
+  // matrix's for the compensated residuals; the solve's stream waits on
+  // pre_ev before it reads them
+  void* pre_at = nullptr;
+  void* pre_res = nullptr;
+  hipEvent_t pre_ev = nullptr;
 };
 
 void init_state(mn_handle h, PcgState* dst, const SolveCtx& c, int rule, double eps, int max_iter) {
@@ -964,11 +974,19 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
     void* res_at = nullptr;
     void* res_x = nullptr;
     void* res_part = nullptr;
+    if (c.pre_ev) {
+      // the copies written during Steps 1-2 (the compensated residual serves
+      // at any conditioning)
+      ck(hipStreamWaitEvent(h->stream, c.pre_ev, 0));
+      v.at = c.pre_at;
+      v.at_valid = true;
+      fused_res = true;
+    }
     if (fused_res) {
-      res_at = ws(h, "res_at", (size_t)(rldt * n * dtype_size(c.dtype)));
+      res_at = c.pre_res ? c.pre_res : ws(h, "res_at", (size_t)(rldt * n * dtype_size(c.dtype)));
       res_x = ws(h, "res_x", (size_t)(n * W + 64));
       res_part = ws(h, "res_part", (size_t)(resid_part_elems(m, kResG) * W));
-      ck(launch_colmajor(c.dtype, c.A, c.lda, m, n, res_at, rldt, h->stream));
+      if (!c.pre_res) ck(launch_colmajor(c.dtype, c.A, c.lda, m, n, res_at, rldt, h->stream));
       // FP64 refinement around the FP64 matrix itself: the inner passes read
       // the same column-major copy (same leading dimension, zero padding)
       if (c.Ab == c.A && c.bulk == c.dtype && m > kGramMaxRows && rldt == rup(m, gram_tall_ld_multiple())) {
@@ -1398,6 +1416,37 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   const int64_t ldxi = rinv_ld(m);
   c.X = ws(h, "Xinv", (size_t)(ldxi * ldxi * wide_size(dtype)));
   const bool block = o.block == 2 || (o.block == 0 && nrhs >= 2 && c.mixed && is_single(c.bulk));
+  // A single right-hand side on a separate single-precision bulk with m in
+  // the tall form's range: the two column-major copies its passes read are
+  // written on a side stream from here on, overlapping Steps 1-2 (compute-
+  // bound sketch, matrix-core Gram product, latency-bound Cholesky), where
+  // both fit in half the free memory
+  // every way out of this call leaves the solve's stream behind the copies
+  // (the next call may reuse or reallocate their buffers)
+  struct PreJoin {
+    mn_handle h;
+    const hipEvent_t* e;
+    ~PreJoin() {
+      if (*e) (void)hipStreamWaitEvent(h->stream, *e, 0);
+    }
+  } pre_join{h, &c.pre_ev};
+  if (c.mixed && A_lo && !block && nrhs == 1 && m > kGramMaxRows && m <= kGramTallMaxRows) {
+    const int64_t tld = rup(m, gram_tall_ld_multiple());
+    const size_t at_bytes = (size_t)(tld * n * dtype_size(c.bulk)), res_bytes = (size_t)(tld * n * dtype_size(dtype));
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)(at_bytes + res_bytes) <= 0.5 * (double)fr) {
+      const StreamFork* fk = handle_fork(h);
+      c.pre_at = ws(h, "gram_at", at_bytes);
+      c.pre_res = ws(h, "res_at", res_bytes);
+      hipStream_t side = fk->side[0];
+      ck(hipEventRecord(h->pre_ev[0], h->stream));
+      ck(hipStreamWaitEvent(side, h->pre_ev[0], 0));
+      ck(launch_colmajor(c.bulk, c.Ab, c.ldab, m, n, c.pre_at, tld, side));
+      ck(launch_colmajor(dtype, A, lda, m, n, c.pre_res, tld, side));
+      ck(hipEventRecord(h->pre_ev[1], side));
+      c.pre_ev = h->pre_ev[1];
+    }
+  }
   // Steps 1-2 for one draw of (d, idx): the caller's, or the library's own
   // (srft_draw), redrawn after a rank-deficient sketch (Remark 4.1)
   const bool lib_draw = d == nullptr;
@@ -2062,6 +2111,8 @@ int mn_destroy(mn_handle h) {
   for (auto& sd : h->fork.side)
     if (sd) (void)hipStreamDestroy(sd);
   for (auto& e : h->fork.ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : h->pre_ev)
     if (e) (void)hipEventDestroy(e);
   delete h;
   return 0;
