@@ -1418,9 +1418,9 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   const bool block = o.block == 2 || (o.block == 0 && nrhs >= 2 && c.mixed && is_single(c.bulk));
   // A single right-hand side on a separate single-precision bulk with m in
   // the tall form's range: the two column-major copies its passes read are
-  // written on a side stream from here on, overlapping Steps 1-2 (compute-
-  // bound sketch, matrix-core Gram product, latency-bound Cholesky), where
-  // both fit in half the free memory
+  // written on a side stream once the first sketch is enqueued, overlapping
+  // Step 2 (matrix-core Gram product, latency-bound Cholesky), where both
+  // fit in half the free memory
   // every way out of this call leaves the solve's stream behind the copies
   // (the next call may reuse or reallocate their buffers)
   struct PreJoin {
@@ -1430,23 +1430,25 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
       if (*e) (void)hipStreamWaitEvent(h->stream, *e, 0);
     }
   } pre_join{h, &c.pre_ev};
-  if (c.mixed && A_lo && !block && nrhs == 1 && m > kGramMaxRows && m <= kGramTallMaxRows) {
-    const int64_t tld = rup(m, gram_tall_ld_multiple());
-    const size_t at_bytes = (size_t)(tld * n * dtype_size(c.bulk)), res_bytes = (size_t)(tld * n * dtype_size(dtype));
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)(at_bytes + res_bytes) <= 0.5 * (double)fr) {
-      const StreamFork* fk = handle_fork(h);
-      c.pre_at = ws(h, "gram_at", at_bytes);
-      c.pre_res = ws(h, "res_at", res_bytes);
-      hipStream_t side = fk->side[0];
-      ck(hipEventRecord(h->pre_ev[0], h->stream));
-      ck(hipStreamWaitEvent(side, h->pre_ev[0], 0));
-      ck(launch_colmajor(c.bulk, c.Ab, c.ldab, m, n, c.pre_at, tld, side));
-      ck(launch_colmajor(dtype, A, lda, m, n, c.pre_res, tld, side));
-      ck(hipEventRecord(h->pre_ev[1], side));
-      c.pre_ev = h->pre_ev[1];
+  auto start_copies = [&]() {
+    if (c.mixed && A_lo && !block && nrhs == 1 && m > kGramMaxRows && m <= kGramTallMaxRows) {
+      const int64_t tld = rup(m, gram_tall_ld_multiple());
+      const size_t at_bytes = (size_t)(tld * n * dtype_size(c.bulk)), res_bytes = (size_t)(tld * n * dtype_size(dtype));
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)(at_bytes + res_bytes) <= 0.5 * (double)fr) {
+        const StreamFork* fk = handle_fork(h);
+        c.pre_at = ws(h, "gram_at", at_bytes);
+        c.pre_res = ws(h, "res_at", res_bytes);
+        hipStream_t side = fk->side[0];
+        ck(hipEventRecord(h->pre_ev[0], h->stream));
+        ck(hipStreamWaitEvent(side, h->pre_ev[0], 0));
+        ck(launch_colmajor(c.bulk, c.Ab, c.ldab, m, n, c.pre_at, tld, side));
+        ck(launch_colmajor(dtype, A, lda, m, n, c.pre_res, tld, side));
+        ck(hipEventRecord(h->pre_ev[1], side));
+        c.pre_ev = h->pre_ev[1];
+      }
     }
-  }
+  };
   // Steps 1-2 for one draw of (d, idx): the caller's, or the library's own
   // (srft_draw), redrawn after a rank-deficient sketch (Remark 4.1)
   const bool lib_draw = d == nullptr;
@@ -1463,6 +1465,9 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     int32_t* inv = nullptr;
     if (!prepare_idx(h, idx, l, N, &inv)) return -16;
     run_sketch(h, c.bulk, m, n, c.Ab, c.ldab, N, l, d, idx, inv, S, l, &o, nullptr, o.hfactor);
+    // (after the compute-bound sketch, which holds every CU, so that the
+    // copies share the chip with the Gram product and the Cholesky)
+    if (!c.pre_ev) start_copies();
     ev_record(h, 1);
     // Step 2's R: Cholesky of the FP64 Gram matrix when that is accurate,
     // Householder QR of S otherwise
