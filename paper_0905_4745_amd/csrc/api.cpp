@@ -1416,11 +1416,12 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
   const int64_t ldxi = rinv_ld(m);
   c.X = ws(h, "Xinv", (size_t)(ldxi * ldxi * wide_size(dtype)));
   const bool block = o.block == 2 || (o.block == 0 && nrhs >= 2 && c.mixed && is_single(c.bulk));
-  // A single right-hand side on a separate single-precision bulk with m in
-  // the tall form's range: the two column-major copies its passes read are
-  // written on a side stream once the first sketch is enqueued, overlapping
-  // Step 2 (matrix-core Gram product, latency-bound Cholesky), where both
-  // fit in half the free memory
+  // A single right-hand side of a refined solve with m in the tall form's
+  // range: the column-major copies its passes read (of a separate
+  // single-precision bulk for the inner passes, of the problem matrix for
+  // the compensated residuals) are written on a side stream once the first
+  // sketch is enqueued, overlapping Step 2 (matrix-core Gram product,
+  // latency-bound Cholesky), where they fit in half the free memory
   // every way out of this call leaves the solve's stream behind the copies
   // (the next call may reuse or reallocate their buffers)
   struct PreJoin {
@@ -1431,18 +1432,22 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     }
   } pre_join{h, &c.pre_ev};
   auto start_copies = [&]() {
-    if (c.mixed && A_lo && !block && nrhs == 1 && m > kGramMaxRows && m <= kGramTallMaxRows) {
+    // (FP64 refinement around the FP64 matrix itself: one copy serves both)
+    const bool sep = A_lo != nullptr;
+    if (c.mixed && (sep || c.bulk == dtype) && !block && nrhs == 1 && m > kGramMaxRows &&
+        m <= kGramTallMaxRows) {
       const int64_t tld = rup(m, gram_tall_ld_multiple());
-      const size_t at_bytes = (size_t)(tld * n * dtype_size(c.bulk)), res_bytes = (size_t)(tld * n * dtype_size(dtype));
+      const size_t at_bytes = sep ? (size_t)(tld * n * dtype_size(c.bulk)) : 0;
+      const size_t res_bytes = (size_t)(tld * n * dtype_size(dtype));
       size_t fr = 0, tot = 0;
       if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)(at_bytes + res_bytes) <= 0.5 * (double)fr) {
         const StreamFork* fk = handle_fork(h);
-        c.pre_at = ws(h, "gram_at", at_bytes);
         c.pre_res = ws(h, "res_at", res_bytes);
+        c.pre_at = sep ? ws(h, "gram_at", at_bytes) : c.pre_res;
         hipStream_t side = fk->side[0];
         ck(hipEventRecord(h->pre_ev[0], h->stream));
         ck(hipStreamWaitEvent(side, h->pre_ev[0], 0));
-        ck(launch_colmajor(c.bulk, c.Ab, c.ldab, m, n, c.pre_at, tld, side));
+        if (sep) ck(launch_colmajor(c.bulk, c.Ab, c.ldab, m, n, c.pre_at, tld, side));
         ck(launch_colmajor(dtype, A, lda, m, n, c.pre_res, tld, side));
         ck(hipEventRecord(h->pre_ev[1], side));
         c.pre_ev = h->pre_ev[1];

@@ -66,3 +66,32 @@ def test_every_tall_plan_meets_eps(m, n, data, tmp_path):
             assert err <= 1e-10, (code, wg)
             worst = max(worst, err)
     say(f"  worst {worst:.2e}")
+
+
+@pytest.mark.parametrize("data", ["c128", "c128+c64"])
+def test_refined_tall_solve_with_early_copies(data):
+    """A refined solve at m above 512 writes its column-major copies on a
+    side stream while Step 2 runs (one copy when the bulk is the problem
+    matrix itself, two with a separate complex64 bulk); the solve still meets
+    eps against the oracle's refined solution at cond 1e6, twice in a row on
+    one handle (the second call rewrites the copies after the first call's
+    passes)."""
+    import torch
+    from paper_0905_4745_amd import api
+    m, n = 1024, 6000
+    A, b, _ = synth.make_svd(m, n, 1e6, seed=17)
+    N = synth.next_pow2(n)
+    d, idx = synth.draw_srft(N, synth.sketch_width(m, N), seed=18)
+    p = oracle.refined_minnorm(A, b)
+    At = to_dev(A)
+    if data == "c128":
+        kw = {"opts": api.SolveOptions(refine=1)}
+    else:
+        kw = {"A_lo": At.to(torch.complex64)}
+    for rep in range(2):
+        x, info = api.minnorm_solve(At, to_dev(b), 1e-10, d, idx, N, **kw)
+        err = rel(to_np(x), p)
+        say(f"  {data} call {rep}: status {info['status']} iters {info['iters']} refine {info['refine_steps']} "
+            f"err {err:.2e}")
+        assert info["status"] == 0
+        assert err <= 1e-10
