@@ -933,6 +933,12 @@ int solve_one(const SolveCtx& c, const void* b, void* x, mn_info* info) {
   v.q = ws(h, "q", kGramParts * m * W);
   ev_record(h, 3);
   if (!c.mixed) {
+    if (c.pre_ev) {
+      // the copy written during Step 2
+      ck(hipStreamWaitEvent(h->stream, c.pre_ev, 0));
+      v.at = c.pre_at;
+      v.at_valid = true;
+    }
     init_state(h, v.st, c, c.o.stop_rule, c.eps, c.o.max_iter);
     cg_start(c, v, b, nullptr, 0, nullptr);
     cg_loop(c, v, b, c.o.max_iter);
@@ -1432,6 +1438,27 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
     }
   } pre_join{h, &c.pre_ev};
   auto start_copies = [&]() {
+    // A plain solve whose fused pass reads the column-major copy (by the
+    // stored launch plan) gets that copy the same way; its first pass then
+    // reads the copy instead of writing it.
+    int cm_plan = 0;
+    if (!c.mixed && !block && nrhs == 1 && gram_supported(c.bulk, m, c.Ab, c.ldab) &&
+        plan_find(h, plan_key("gram", c.bulk, m, n, 0), &cm_plan) && ((cm_plan >> 19) & 1)) {
+      const int64_t cld = rup(m, 64);
+      const size_t at_bytes = (size_t)(cld * n * dtype_size(c.bulk));
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess && (double)at_bytes <= 0.5 * (double)fr) {
+        const StreamFork* fk = handle_fork(h);
+        c.pre_at = ws(h, "gram_at", at_bytes);
+        hipStream_t side = fk->side[0];
+        ck(hipEventRecord(h->pre_ev[0], h->stream));
+        ck(hipStreamWaitEvent(side, h->pre_ev[0], 0));
+        ck(launch_colmajor(c.bulk, c.Ab, c.ldab, m, n, c.pre_at, cld, side));
+        ck(hipEventRecord(h->pre_ev[1], side));
+        c.pre_ev = h->pre_ev[1];
+      }
+      return;
+    }
     // (FP64 refinement around the FP64 matrix itself: one copy serves both)
     const bool sep = A_lo != nullptr;
     if (c.mixed && (sep || c.bulk == dtype) && !block && nrhs == 1 && m > kGramMaxRows &&
