@@ -1131,8 +1131,13 @@ int solve_block(const SolveCtx& c, const void* b, int64_t ldb, int kc, void* x, 
   uint16_t* a_lo = (uint16_t*)ws(h, "blk_a_lo", (size_t)(m * pl.Kp2 * 2));
   uint16_t* t_hi = (uint16_t*)ws(h, "blk_t_hi", (size_t)(n * pl.Kp1 * 2));
   uint16_t* t_lo = (uint16_t*)ws(h, "blk_t_lo", (size_t)(n * pl.Kp1 * 2));
-  ck(launch_planes(c.bulk, c.Ab, c.ldab, m, n, false, a_hi, a_lo, pl.Kp2, st));
-  ck(launch_planes(c.bulk, c.Ab, c.ldab, m, n, true, t_hi, t_lo, pl.Kp1, st));
+  if (c.pre_ev) {
+    // written on the side stream during Step 2
+    ck(hipStreamWaitEvent(st, c.pre_ev, 0));
+  } else {
+    ck(launch_planes(c.bulk, c.Ab, c.ldab, m, n, false, a_hi, a_lo, pl.Kp2, st));
+    ck(launch_planes(c.bulk, c.Ab, c.ldab, m, n, true, t_hi, t_lo, pl.Kp1, st));
+  }
   // right-operand planes (zero where the products never write)
   const size_t p_bytes = (size_t)(kc * pl.Kp1 * 2), w_bytes = (size_t)(kc * pl.Kp2 * 2);
   uint16_t* p_hi = (uint16_t*)ws(h, "blk_p_hi", p_bytes);
@@ -1457,6 +1462,24 @@ int solve_impl(mn_handle h, int dtype, int64_t m, int64_t n, const void* A, int6
         ck(hipEventRecord(h->pre_ev[1], side));
         c.pre_ev = h->pre_ev[1];
       }
+      return;
+    }
+    // The block form's BF16 planes of the bulk matrix (and of its
+    // transpose), the same way.
+    if (block && is_single(c.bulk)) {
+      const BlockPlan pl = plan_block(is_complex(dtype), m, n, (int)nrhs);
+      uint16_t* a_hi = (uint16_t*)ws(h, "blk_a_hi", (size_t)(m * pl.Kp2 * 2));
+      uint16_t* a_lo = (uint16_t*)ws(h, "blk_a_lo", (size_t)(m * pl.Kp2 * 2));
+      uint16_t* t_hi = (uint16_t*)ws(h, "blk_t_hi", (size_t)(n * pl.Kp1 * 2));
+      uint16_t* t_lo = (uint16_t*)ws(h, "blk_t_lo", (size_t)(n * pl.Kp1 * 2));
+      const StreamFork* fk = handle_fork(h);
+      hipStream_t side = fk->side[0];
+      ck(hipEventRecord(h->pre_ev[0], h->stream));
+      ck(hipStreamWaitEvent(side, h->pre_ev[0], 0));
+      ck(launch_planes(c.bulk, c.Ab, c.ldab, m, n, false, a_hi, a_lo, pl.Kp2, side));
+      ck(launch_planes(c.bulk, c.Ab, c.ldab, m, n, true, t_hi, t_lo, pl.Kp1, side));
+      ck(hipEventRecord(h->pre_ev[1], side));
+      c.pre_ev = h->pre_ev[1];
       return;
     }
     // (FP64 refinement around the FP64 matrix itself: one copy serves both)
