@@ -49,7 +49,7 @@ DEFAULT_PLANS = os.path.join(ROOT, "paper_0905_4745_amd", "plans", "mi355x.json"
 # kernel source it was measured on: a changed source reports null.
 MEASURED_TRAFFIC = {
     "k_gram_cm": {"bytes": 539.15e6, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-                  "sha256": "0d5b3629e796b0ea9ac13e3f6dc4efde0818619c385ceae217ac6e1dcf05c3f8",
+                  "sha256": "3a931e32285c866c2f0ddf45c965b8d17ea9f0bd90f5b7550d7798aaa6258207",
                   "plan_key": "gram/0/512/65536/0", "plan": 655616},
 }
 
@@ -605,7 +605,7 @@ def cpu_baseline_classical(A_dev, b_dev, m, n):
 # valid while the source and the plan are the measured ones
 MEASURED_TRAFFIC_MIXED = {
     "k_gram_tall": {"bytes": 4312113357.0, "source": "paper_0905_4745_amd/csrc/gemv.hip",
-                    "sha256": "0d5b3629e796b0ea9ac13e3f6dc4efde0818619c385ceae217ac6e1dcf05c3f8",
+                    "sha256": "3a931e32285c866c2f0ddf45c965b8d17ea9f0bd90f5b7550d7798aaa6258207",
                     "plan_key": "gram/1/2048/262144/1", "plan": 524800},
 }
 

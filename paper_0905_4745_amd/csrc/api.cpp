@@ -1677,10 +1677,10 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   std::vector<BSys> hs((size_t)batch);
   // grids
   GridTable fill, map, sk_small, sk_cols, sk_rows, sk_ord, sk_pr[3], gram_s, rdiag, invd, gramR[4], gred, adjA, adjU,
-      sum, fwdA, fwdU, cgs, cgp, vec;
+      sum, fwdA, fwdU, cgs, cgp, vec, colm;
   for (GridTable* t : {&fill, &map, &sk_small, &sk_cols, &sk_rows, &sk_ord, &sk_pr[0], &sk_pr[1], &sk_pr[2], &gram_s,
                        &rdiag, &invd, &gramR[0], &gramR[1], &gramR[2], &gramR[3], &gred, &adjA, &adjU, &sum, &fwdA,
-                       &fwdU, &cgs, &cgp, &vec})
+                       &fwdU, &cgs, &cgp, &vec, &colm})
     t->init(batch);
   int maxnbk = 0;
   size_t lds_small = 0, lds_cols = 0, lds_rows = 0, lds_pr = 0;
@@ -1753,6 +1753,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
     // (one extra pass over the bulk copy) so that the fused pass reads
     // 16-byte vectors
     const int64_t pad_ld = (use_cm || b_aligned16(q.Ab, q.ldab, bulk)) ? 0 : rup(n[i], std::max<int64_t>(16 / be, 1));
+    if (use_cm) colm.g[i] = BGrid{0, (int)cdiv(n[i], b_colmajor_tw(bulk)), (int)(rup(mm, 64) / 64), 1};
     wbytes[i] = a256(pad_ld * mm * be) + (use_cm ? a256(rup(mm, 64) * n[i] * be) : 0) + a256(N[i] * 4) +
                 a256(sketch_order_bytes(l[i], is_single(bulk))) + a256(l[i] * mm * be) +
                 a256(b_sketch_work_elems(bulk, mm, N[i], l[i]) * ces) +
@@ -1791,7 +1792,7 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   std::vector<GridTable*> all = {&fill,     &map,      &sk_small, &sk_cols,  &sk_rows,  &sk_ord, &sk_pr[0],
                                  &sk_pr[1], &sk_pr[2], &gram_s,   &rdiag,    &invd,     &gramR[0], &gramR[1],
                                  &gramR[2], &gramR[3], &gred,     &adjA,     &adjU,     &sum,    &fwdA,
-                                 &fwdU,     &cgs,      &cgp,      &vec};
+                                 &fwdU,     &cgs,      &cgp,      &vec,     &colm};
   for (auto& t : chol) all.push_back(&t);
   for (auto& t : trtri) all.push_back(&t);
   size_t nent = 0;
@@ -1903,6 +1904,25 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   const BLaunch prl[3] = {L(sk_pr[0]), L(sk_pr[1]), L(sk_pr[2])};
   ck(launch_b_sketch(bulk, L(sk_small), L(sk_cols), L(sk_rows), L(sk_ord), prl, lds_small, lds_cols, lds_rows, lds_pr,
                      st));
+  // the column-major copies on a side stream beside Step 2 (the first pass
+  // then reads them instead of writing them); every way out of this call
+  // leaves the stream behind them
+  bool pre_cm = false;
+  struct CmJoin {
+    hipStream_t st;
+    hipEvent_t e;
+    const bool* on;
+    ~CmJoin() {
+      if (*on) (void)hipStreamWaitEvent(st, e, 0);
+    }
+  } cm_join{st, h->pre_ev[1], &pre_cm};
+  if (use_cm && colm.total > 0) {
+    ck(hipEventRecord(h->pre_ev[0], st));
+    ck(hipStreamWaitEvent(fork->side[0], h->pre_ev[0], 0));
+    ck(launch_b_colmajor(bulk, L(colm), fork->side[0]));
+    ck(hipEventRecord(h->pre_ev[1], fork->side[0]));
+    pre_cm = true;
+  }
   ck(launch_b_gram_s(bulk, L(gram_s), st));
   for (int k = 0; k < maxnbk; ++k) ck(launch_b_chol_step(cplx, L(chol[k]), k - 1, st));
   ck(launch_b_rdiag(cplx, L(rdiag), st));
@@ -1966,7 +1986,8 @@ void solve_batched_fused(mn_handle h, int dtype, int batch, const int64_t* m, co
   ck(hipStreamSynchronize(st));
   const size_t cg_lds = (size_t)maxm * W;
   int par = 0;
-  bool at_written = false;
+  if (pre_cm) ck(hipStreamWaitEvent(st, h->pre_ev[1], 0));
+  bool at_written = pre_cm;
   auto all_done = [&](bool outer) {
     for (int i = 0; i < batch; ++i)
       if (!(outer ? hst_state[i].outer_done : hst_state[i].done)) return false;

@@ -611,12 +611,12 @@ __global__ void __launch_bounds__(TPB) k_gram_tall(const V* __restrict__ At, int
 // issues all its loads of a tile before storing any.  grid (ceil(n / TW),
 // ldt / 64), 256 threads.
 template <typename V>
-__global__ void __launch_bounds__(256) k_colmajor(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-                                                  V* __restrict__ At, int64_t ldt) {
+__device__ __forceinline__ void colmajor_tile(int bx, int by, const V* __restrict__ A, int64_t lda, int64_t m,
+                                              int64_t n, V* __restrict__ At, int64_t ldt) {
   constexpr int TW = 1024 / (int)sizeof(V) < 64 ? 1024 / (int)sizeof(V) : (1024 / (int)sizeof(V) > 128 ? 128 : 1024 / (int)sizeof(V));
   constexpr int PER = 64 * TW / 256;  // entries per thread
   __shared__ V tile[64][TW + 1];
-  const int64_t c0 = (int64_t)blockIdx.x * TW, r0 = (int64_t)blockIdx.y * 64;
+  const int64_t c0 = (int64_t)bx * TW, r0 = (int64_t)by * 64;
   const int tid = threadIdx.x;
   V v[PER];
 #pragma unroll
@@ -643,8 +643,24 @@ __global__ void __launch_bounds__(256) k_colmajor(const V* __restrict__ A, int64
     if (c < n) At[c * ldt + r0 + rr] = v[u];
   }
 }
+template <typename V>
+__global__ void __launch_bounds__(256) k_colmajor(const V* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                                                  V* __restrict__ At, int64_t ldt) {
+  colmajor_tile<V>((int)blockIdx.x, (int)blockIdx.y, A, lda, m, n, At, ldt);
+}
 template <typename V> constexpr int colmajor_tw() {
   return 1024 / (int)sizeof(V) < 64 ? 1024 / (int)sizeof(V) : (1024 / (int)sizeof(V) > 128 ? 128 : 1024 / (int)sizeof(V));
+}
+// every system's column-major copy At of its bulk matrix Ab (batched form):
+// the system's grid is (ceil(n / TW), ldt / 64) tiles
+template <typename V>
+__global__ void __launch_bounds__(256) kb_colmajor(const BSys* __restrict__ sys, const BGrid* __restrict__ grid,
+                                                   int nsys) {
+  const int i = bgrid_find(grid, nsys, blockIdx.x);
+  const BSys& s = sys[i];
+  const Bk bk = bgrid_local(grid[i], (int)blockIdx.x - grid[i].start);
+  colmajor_tile<V>(bk.x, bk.y, reinterpret_cast<const V*>(s.Ab), s.ldab, s.m, s.n, reinterpret_cast<V*>(s.At),
+                   s.ldt);
 }
 
 // q[i] = sum over the pass's G workgroup partials qpart[g * m + i], in a
@@ -902,6 +918,29 @@ bool gram_supported(int dtype, int64_t m, const void* A, int64_t lda) {
 }
 
 int64_t gram_tall_ld_multiple() { return 256; }
+
+int b_colmajor_tw(int dtype) {
+  switch (dtype) {
+    case 0: return colmajor_tw<cd>();
+    case 1: return colmajor_tw<cf>();
+    case 2: return colmajor_tw<double>();
+    case 3: return colmajor_tw<float>();
+  }
+  return 0;
+}
+
+hipError_t launch_b_colmajor(int dtype, const BLaunch& L, hipStream_t st) {
+  if (L.total <= 0) return hipSuccess;
+  const dim3 grid((unsigned)L.total);
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL((kb_colmajor<cd>), grid, dim3(256), 0, st, L.sys, L.grid, L.nsys); break;
+    case 1: hipLaunchKernelGGL((kb_colmajor<cf>), grid, dim3(256), 0, st, L.sys, L.grid, L.nsys); break;
+    case 2: hipLaunchKernelGGL((kb_colmajor<double>), grid, dim3(256), 0, st, L.sys, L.grid, L.nsys); break;
+    case 3: hipLaunchKernelGGL((kb_colmajor<float>), grid, dim3(256), 0, st, L.sys, L.grid, L.nsys); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_colmajor(int dtype, const void* A, int64_t lda, int64_t m, int64_t n, void* At, int64_t ldt,
                            hipStream_t st) {

@@ -435,6 +435,10 @@ struct StreamFork {
 };
 hipError_t launch_b_gram(int dtype, const BLaunch* L, const BLaunch& red, int mode, hipStream_t st,
                          const StreamFork* fk = nullptr);
+// every system's column-major copy At (ldt) of its bulk matrix Ab; the
+// system's grid is (ceil(n / b_colmajor_tw(dtype)), ldt / 64) tiles
+hipError_t launch_b_colmajor(int dtype, const BLaunch& L, hipStream_t st);
+int b_colmajor_tw(int dtype);
 // the refinement's FP64 residual product q = A (A* y_outer) as one fused pass
 // over each system's problem data A (dtype = the problem dtype); same grids
 // as launch_b_gram, strips from b_plan_gram_res (after b_plan_gram)
