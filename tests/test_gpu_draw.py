@@ -10,7 +10,9 @@ rank-deficient sketch (Remark 4.1), through the C ABI:
   after one redraw (info.retries == 1); with redraws switched off, or for a
   matrix that is not of full rank, +1 is returned (after 0, resp. 2 redraws);
 * the batched call draws every system (sys = its index) and redraws the
-  forced system alone.
+  forced system alone; its one-launch draw of all systems' phases and its
+  single copy of the index sets give bit for bit the solutions of the call
+  handed srft_draw's output.
 """
 
 import numpy as np
@@ -133,3 +135,43 @@ def test_batched_library_draws_and_redraw():
         assert infos[i]["status"] == 0
         assert infos[i]["retries"] == (1 if i == 2 else 0)
         assert err <= 1e-12
+
+
+@pytest.mark.parametrize("real", [False, True])
+def test_batched_library_draws_equal_srft_draw(real):
+    """The batched call's own draws (every system's phases in one launch, the
+    index sets staged and copied at once) are the draws srft_draw makes for
+    (seed, draw 0, sys = the system's index): the solutions of the call that
+    draws and of the call handed srft_draw's output agree bit for bit, on
+    systems of uneven m and N (powers of two and N1 2^k)."""
+    import torch
+    from paper_0905_4745_amd import api
+    rng = np.random.default_rng(31)
+    seed = 424242
+    shapes = [(24, 900), (48, 2000), (16, 700), (64, 5000), (32, 1500)]
+    As, bs, Ns = [], [], []
+    for m, n in shapes:
+        if real:
+            A, b = rng.standard_normal((m, n)), rng.standard_normal(m)
+        else:
+            A, b = synth.complex_gaussian(rng, (m, n)), synth.complex_gaussian(rng, (m,))
+        As.append(to_dev(A))
+        bs.append(to_dev(b))
+        Ns.append(synth.next_fft_len(n))
+    assert any(N & (N - 1) for N in Ns)  # some lengths are not powers of two
+    ls = [min(4 * m, N) for (m, _), N in zip(shapes, Ns)]
+    opts = api.SolveOptions(seed=seed)
+    xs_lib, inf_lib = api.minnorm_solve_batched(As, bs, 1e-12, None, None, Ns, opts=opts, ls=ls)
+    tdt = torch.float64 if real else torch.complex128
+    ds, idxs = [], []
+    for i, (N, l) in enumerate(zip(Ns, ls)):
+        d, idx = api.srft_draw(tdt, seed, 0, i, N, l)
+        ds.append(d)
+        idxs.append(idx)
+    xs_cal, inf_cal = api.minnorm_solve_batched(As, bs, 1e-12, ds, idxs, Ns, opts=opts)
+    for i in range(len(shapes)):
+        say(f"  system {i} N={Ns[i]} l={ls[i]}: status {inf_lib[i]['status']} / {inf_cal[i]['status']}, "
+            f"iters {inf_lib[i]['iters']} / {inf_cal[i]['iters']}")
+        assert inf_lib[i]["status"] == 0 and inf_cal[i]["status"] == 0
+        assert inf_lib[i]["retries"] == 0
+        assert torch.equal(xs_lib[i], xs_cal[i])
