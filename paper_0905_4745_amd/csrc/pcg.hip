@@ -298,32 +298,33 @@ __global__ void __launch_bounds__(256) k_cg_s(const W* __restrict__ X, int64_t l
 
 // ---------------------------------------------------------------------------
 // k_cg_p.  rho' = ||s||^2 (and xi, the stopping test); z = X s on this
-// workgroup's 16-row band; p = z + beta p (start: p = z, rho0 = rho').
+// workgroup's RB-row band; p = z + beta p (start: p = z, rho0 = rho').
 // With y_outer (start of an FP64 refinement step) the outer certificate is
-// tested first.  grid = ceil(m / 16), 256 threads.
-template <typename W>
+// tested first.  grid = ceil(m / RB), 256 threads (RB = 16, or 8 for large
+// m, where 16-row bands leave half the CUs without a workgroup).
+template <typename W, int RB = 16>
 __device__ __forceinline__ void k_cg_p_body(const Bk bk, const W* __restrict__ X, int64_t ldx, int64_t m, int start,
                                               const W* __restrict__ b, const W* __restrict__ y,
                                               const W* __restrict__ y_outer, const W* __restrict__ r,
                                               const W* __restrict__ s, W* __restrict__ p,
                                               PcgState* __restrict__ stp) {
-  constexpr int RB = 16;
+  constexpr int NG = 256 / RB;  // column groups
   extern __shared__ unsigned char smem_raw[];
   W* ss = reinterpret_cast<W*>(smem_raw);  // s, m entries
-  __shared__ W part[16][RB];
+  __shared__ W part[NG][RB];
   PcgState& st = *stp;
   const bool lead = bk.x == 0;
-  // z = X s on rows i0 .. i0+15: thread t takes row t%16 and every 16th
+  // z = X s on rows i0 .. i0+RB-1: thread t takes row t%RB and every NG-th
   // column.  X is zero below the diagonal inside the diagonal block, so the
   // band can be read from column i0 on; the first group of four columns per
   // thread does not depend on the iteration and is loaded first.
   const int64_t i0 = (int64_t)bk.x * RB;
-  const int rr = threadIdx.x % RB, cgrp = threadIdx.x / RB;  // 16 column groups
+  const int rr = threadIdx.x % RB, cgrp = threadIdx.x / RB;
   const int64_t i = i0 + rr;
-  const bool first = i < m && i0 + cgrp + 48 < m;
+  const bool first = i < m && i0 + cgrp + 3 * NG < m;
   W xf[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) xf[u] = first ? X[i + (i0 + cgrp + 16 * u) * ldx] : vzero<W>();
+  for (int u = 0; u < 4; ++u) xf[u] = first ? X[i + (i0 + cgrp + NG * u) * ldx] : vzero<W>();
   const int64_t ip = i0 + threadIdx.x;  // this workgroup's entries of p (threads < 16)
   const W p_old = (!start && threadIdx.x < RB && ip < m) ? p[ip] : vzero<W>();
   if (start ? (st.outer_done != 0) : (st.done != 0)) return;
@@ -414,32 +415,32 @@ __device__ __forceinline__ void k_cg_p_body(const Bk bk, const W* __restrict__ X
     int64_t j = i0 + cgrp;
     if (first) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a4[u] = vfma(xf[u], ss[j + 16 * u], a4[u]);
-      j += 64;
+      for (int u = 0; u < 4; ++u) a4[u] = vfma(xf[u], ss[j + NG * u], a4[u]);
+      j += 4 * NG;
     }
-    for (; j + 48 < m; j += 64) {
+    for (; j + 3 * NG < m; j += 4 * NG) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a4[u] = vfma(X[i + (j + 16 * u) * ldx], ss[j + 16 * u], a4[u]);
+      for (int u = 0; u < 4; ++u) a4[u] = vfma(X[i + (j + NG * u) * ldx], ss[j + NG * u], a4[u]);
     }
-    for (; j < m; j += 16) a4[0] = vfma(X[i + j * ldx], ss[j], a4[0]);
+    for (; j < m; j += NG) a4[0] = vfma(X[i + j * ldx], ss[j], a4[0]);
   }
   W acc = vadd(vadd(a4[0], a4[1]), vadd(a4[2], a4[3]));
   part[cgrp][rr] = acc;
   __syncthreads();
   if (threadIdx.x < RB && i0 + threadIdx.x < m) {
     W z = part[0][threadIdx.x];
-    for (int c = 1; c < 16; ++c) z = vadd(z, part[c][threadIdx.x]);
+    for (int c = 1; c < NG; ++c) z = vadd(z, part[c][threadIdx.x]);
     const int64_t ii = i0 + threadIdx.x;
     p[ii] = start ? z : vadd(z, vscale(p_old, beta));
   }
 }
-template <typename W>
+template <typename W, int RB = 16>
 __global__ void __launch_bounds__(256) k_cg_p(const W* __restrict__ X, int64_t ldx, int64_t m, int start,
                                               const W* __restrict__ b, const W* __restrict__ y,
                                               const W* __restrict__ y_outer, const W* __restrict__ r,
                                               const W* __restrict__ s, W* __restrict__ p,
                                               PcgState* __restrict__ stp) {
-  k_cg_p_body<W>(bk_hw(), X, ldx, m, start, b, y, y_outer, r, s, p, stp);
+  k_cg_p_body<W, RB>(bk_hw(), X, ldx, m, start, b, y, y_outer, r, s, p, stp);
 }
 
 // y_outer += y (after an inner solve).
@@ -495,17 +496,26 @@ static hipError_t cg_step_impl(const CgStep& a, hipStream_t st) {
   if (sm > 48 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_s<W>), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sm);
-  if (sm > 48 * 1024)
+  if (sm > 48 * 1024) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_p<W>), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sm);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_p<W, 8>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sm);
+  }
   hipLaunchKernelGGL((k_cg_s<W>), dim3((unsigned)ceil_div(a.m, 8)), dim3(256), sm, st, X, ldx, a.m, a.start,
                      reinterpret_cast<const W*>(a.b), reinterpret_cast<const W*>(a.parts), a.nparts,
                      reinterpret_cast<W*>(a.p), reinterpret_cast<W*>(a.y), reinterpret_cast<const W*>(a.r_in),
                      reinterpret_cast<W*>(a.r_out), reinterpret_cast<W*>(a.s), a.state);
-  hipLaunchKernelGGL((k_cg_p<W>), dim3((unsigned)ceil_div(a.m, 16)), dim3(256), sm, st, X, ldx, a.m, a.start,
-                     reinterpret_cast<const W*>(a.b), reinterpret_cast<const W*>(a.y),
-                     reinterpret_cast<const W*>(a.y_outer), reinterpret_cast<const W*>(a.r_out),
-                     reinterpret_cast<const W*>(a.s), reinterpret_cast<W*>(a.p), a.state);
+  if (a.m >= 1024)
+    hipLaunchKernelGGL((k_cg_p<W, 8>), dim3((unsigned)ceil_div(a.m, 8)), dim3(256), sm, st, X, ldx, a.m, a.start,
+                       reinterpret_cast<const W*>(a.b), reinterpret_cast<const W*>(a.y),
+                       reinterpret_cast<const W*>(a.y_outer), reinterpret_cast<const W*>(a.r_out),
+                       reinterpret_cast<const W*>(a.s), reinterpret_cast<W*>(a.p), a.state);
+  else
+    hipLaunchKernelGGL((k_cg_p<W>), dim3((unsigned)ceil_div(a.m, 16)), dim3(256), sm, st, X, ldx, a.m, a.start,
+                       reinterpret_cast<const W*>(a.b), reinterpret_cast<const W*>(a.y),
+                       reinterpret_cast<const W*>(a.y_outer), reinterpret_cast<const W*>(a.r_out),
+                       reinterpret_cast<const W*>(a.s), reinterpret_cast<W*>(a.p), a.state);
   return hipGetLastError();
 }
 
