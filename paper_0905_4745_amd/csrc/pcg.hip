@@ -156,9 +156,11 @@ __device__ inline bool stop_test(const PcgState& st, double rho, double xi) {
 
 // ---------------------------------------------------------------------------
 // k_cg_s.  start: r' = b - sum(parts) (or b), y = 0.  iter: alpha, r', y.
-// Then s_j = sum_{i<=j} conj(X_ij) r'_i for this workgroup's 8 columns.
-// grid = ceil(m / 8), 256 threads, dynamic LDS = m FP64 entries (r').
-template <typename W>
+// Then s_j = sum_{i<=j} conj(X_ij) r'_i for this workgroup's 4 CPW columns
+// (CPW = 2, or 1 for large m, where the longer columns want more waves in
+// flight).  grid = ceil(m / (4 CPW)), 256 threads, dynamic LDS = m FP64
+// entries (r').
+template <typename W, int CPW = 2>
 __device__ __forceinline__ void k_cg_s_body(const Bk bk, const W* __restrict__ X, int64_t ldx, int64_t m, int start,
                                               const W* __restrict__ b, const W* __restrict__ parts, int nparts,
                                               W* __restrict__ p, W* __restrict__ y, const W* __restrict__ r_in,
@@ -168,12 +170,12 @@ __device__ __forceinline__ void k_cg_s_body(const Bk bk, const W* __restrict__ X
   __shared__ double red[4];
   PcgState& st = *stp;
   const bool lead = bk.x == 0;
-  // s for columns c0 .. c0+7: wave w takes 2 columns, lanes run down each.
-  // Column j of X has entries 0 .. j; its first 256 entries do not depend on
-  // the iteration, so their loads are issued before anything else.
+  // s for this workgroup's columns: wave w takes CPW of them, lanes run down
+  // each.  Column j of X has entries 0 .. j; its first 256 entries do not
+  // depend on the iteration, so their loads are issued before anything else.
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t j0 = (int64_t)bk.x * 8 + 2 * wv, j1 = j0 + 1;
-  const int64_t e0 = j0 < m ? j0 + 1 : 0, e1 = j1 < m ? j1 + 1 : 0;
+  const int64_t j0 = (int64_t)bk.x * (4 * CPW) + CPW * wv, j1 = j0 + 1;
+  const int64_t e0 = j0 < m ? j0 + 1 : 0, e1 = (CPW == 2 && j1 < m) ? j1 + 1 : 0;
   const W* col0 = X + j0 * ldx;
   const W* col1 = X + j1 * ldx;
   W x0[4], x1[4];
@@ -285,15 +287,15 @@ __device__ __forceinline__ void k_cg_s_body(const Bk bk, const W* __restrict__ X
   W acc1 = wave_sum(vadd(vadd(a1[0], a1[1]), vadd(a1[2], a1[3])));
   if (lane == 0) {
     if (j0 < m) s[j0] = acc0;
-    if (j1 < m) s[j1] = acc1;
+    if (CPW == 2 && j1 < m) s[j1] = acc1;
   }
 }
-template <typename W>
+template <typename W, int CPW = 2>
 __global__ void __launch_bounds__(256) k_cg_s(const W* __restrict__ X, int64_t ldx, int64_t m, int start,
                                               const W* __restrict__ b, const W* __restrict__ parts, int nparts,
                                               W* __restrict__ p, W* __restrict__ y, const W* __restrict__ r_in,
                                               W* __restrict__ r_out, W* __restrict__ s, PcgState* __restrict__ stp) {
-  k_cg_s_body<W>(bk_hw(), X, ldx, m, start, b, parts, nparts, p, y, r_in, r_out, s, stp);
+  k_cg_s_body<W, CPW>(bk_hw(), X, ldx, m, start, b, parts, nparts, p, y, r_in, r_out, s, stp);
 }
 
 // ---------------------------------------------------------------------------
@@ -493,19 +495,28 @@ static hipError_t cg_step_impl(const CgStep& a, hipStream_t st) {
   const W* X = reinterpret_cast<const W*>(a.X);
   const int64_t ldx = rinv_ld(a.m);
   const size_t sm = (size_t)a.m * sizeof(W);
-  if (sm > 48 * 1024)
+  if (sm > 48 * 1024) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_s<W>), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sm);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_s<W, 1>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sm);
+  }
   if (sm > 48 * 1024) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_p<W>), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sm);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cg_p<W, 8>), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sm);
   }
-  hipLaunchKernelGGL((k_cg_s<W>), dim3((unsigned)ceil_div(a.m, 8)), dim3(256), sm, st, X, ldx, a.m, a.start,
-                     reinterpret_cast<const W*>(a.b), reinterpret_cast<const W*>(a.parts), a.nparts,
-                     reinterpret_cast<W*>(a.p), reinterpret_cast<W*>(a.y), reinterpret_cast<const W*>(a.r_in),
-                     reinterpret_cast<W*>(a.r_out), reinterpret_cast<W*>(a.s), a.state);
+  if (a.m >= 1024)
+    hipLaunchKernelGGL((k_cg_s<W, 1>), dim3((unsigned)ceil_div(a.m, 4)), dim3(256), sm, st, X, ldx, a.m, a.start,
+                       reinterpret_cast<const W*>(a.b), reinterpret_cast<const W*>(a.parts), a.nparts,
+                       reinterpret_cast<W*>(a.p), reinterpret_cast<W*>(a.y), reinterpret_cast<const W*>(a.r_in),
+                       reinterpret_cast<W*>(a.r_out), reinterpret_cast<W*>(a.s), a.state);
+  else
+    hipLaunchKernelGGL((k_cg_s<W>), dim3((unsigned)ceil_div(a.m, 8)), dim3(256), sm, st, X, ldx, a.m, a.start,
+                       reinterpret_cast<const W*>(a.b), reinterpret_cast<const W*>(a.parts), a.nparts,
+                       reinterpret_cast<W*>(a.p), reinterpret_cast<W*>(a.y), reinterpret_cast<const W*>(a.r_in),
+                       reinterpret_cast<W*>(a.r_out), reinterpret_cast<W*>(a.s), a.state);
   if (a.m >= 1024)
     hipLaunchKernelGGL((k_cg_p<W, 8>), dim3((unsigned)ceil_div(a.m, 8)), dim3(256), sm, st, X, ldx, a.m, a.start,
                        reinterpret_cast<const W*>(a.b), reinterpret_cast<const W*>(a.y),
